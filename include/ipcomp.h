@@ -1,0 +1,148 @@
+/*
+ * ipcomp.h -- C ABI of the IPComp hot path on MI355X (gfx950).
+ *
+ * IPComp (arXiv 2502.04093) is an interpolation-based progressive lossy
+ * compressor.  Compression predicts every point from already reconstructed
+ * coarser points, level by level and one dimension at a time (Sec. 4.1,
+ * Eq. interp-linear / Eq. interp-cubic), quantizes the residual within an
+ * absolute error bound (Sec. 4.2.2), and stores the integer codes as
+ * negabinary, prefix-XOR-coded bitplanes (Sec. 4.3-4.4).  Retrieval loads only
+ * the planes a planner selects for an error bound or a bitrate (Sec. 5) and
+ * reconstructs in one pass (Alg. 1); refinement adds planes to a resident
+ * reconstruction (Alg. 2).  The statement of the problem (Sec. 3.1.2): a user
+ * retrieves at fidelity F1 and refines to F2..Fn, and every retrieval meets its
+ * error bound.
+ *
+ * Conventions for every call:
+ *  - Device pointers are HIP device allocations on the context's device.
+ *  - Calls are ordered on the context's hipStream and return when their
+ *    results are ready (they synchronize that stream).
+ *  - A context is not thread-safe; use one per host thread.
+ *  - Errors are reported by status codes only.  On error every output pointer
+ *    is set to NULL, nothing leaks, and ipc_last_error() holds a message.
+ *  - Streams and states are owned by the library and released with their
+ *    *_free call; a stream must outlive the states made from it, and a
+ *    context must outlive the streams and states it made.
+ */
+#ifndef IPCOMP_H
+#define IPCOMP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IPC_OK = 0,
+  IPC_EINVAL = -1,       /* invalid argument */
+  IPC_ENOMEM = -2,       /* device or host allocation failed */
+  IPC_ECORRUPT = -3,     /* serialized stream fails validation */
+  IPC_EHIP = -4,         /* HIP runtime error */
+  IPC_ESTATE = -5,       /* object used with the wrong context or stream */
+  IPC_EUNSUPPORTED = -6  /* valid request outside what this build supports */
+} ipc_status;
+
+typedef enum { IPC_F32 = 0, IPC_F64 = 1 } ipc_dtype;
+typedef enum { IPC_LINEAR = 0, IPC_CUBIC = 1 } ipc_interp;
+typedef enum { IPC_TARGET_EB = 0, IPC_TARGET_BITRATE = 1 } ipc_target_kind;
+
+/* Retrieval target (Sec. 5): an absolute L-infinity error bound, or a bitrate
+ * in bits per value (the loaded bytes are at most bitrate * n / 8). */
+typedef struct {
+  int32_t kind;  /* ipc_target_kind */
+  double value;  /* > 0 */
+} ipc_target;
+
+/* Compression options; pass NULL for the defaults
+ * {IPC_CUBIC, nonprog_levels 0, default chunk shape}. */
+typedef struct {
+  int32_t interp;          /* ipc_interp */
+  int32_t nonprog_levels;  /* top levels always fully loaded (L_p of Alg. 1) */
+  uint8_t chunk_log2[3];   /* chunk extents (log2) per dimension; all 0 = default */
+  uint8_t reserved[5];
+} ipc_options;
+
+#define IPC_FLAG_CLAMPED_TO_EB 1u      /* E below the compression bound: full load */
+#define IPC_FLAG_BUDGET_BELOW_MIN 2u   /* bitrate below the fixed bytes: coarsest plan */
+#define IPC_FLAG_NOOP 4u               /* refine target already met: nothing loaded */
+#define IPC_MAX_PASSES 100
+
+/* What a retrieval or refinement did. */
+typedef struct {
+  double bound;               /* guaranteed max |x - x~| of the result */
+  uint64_t bytes_loaded;      /* stream bytes the plan uses (fixed part included) */
+  uint64_t bytes_total;       /* serialized stream size */
+  uint64_t bytes_read;        /* plane bytes read by this call */
+  uint32_t n_passes;
+  uint32_t flags;             /* IPC_FLAG_* */
+  uint8_t plan[IPC_MAX_PASSES]; /* planes discarded per pass (0 = all loaded) */
+  float t_plan_ms;            /* host planner time */
+  float t_device_ms;          /* device time of the call's kernels */
+} ipc_info;
+
+typedef struct ipc_ctx ipc_ctx;
+typedef struct ipc_stream ipc_stream;
+typedef struct ipc_state ipc_state;
+
+/* Context on HIP device `device`, issuing work on `hip_stream` (a
+ * hipStream_t; NULL = a stream the context creates and owns). */
+ipc_status ipc_ctx_create(int device, void *hip_stream, ipc_ctx **out);
+void ipc_ctx_destroy(ipc_ctx *ctx);
+/* Switch the hipStream later calls are ordered on (NULL = the owned one). */
+ipc_status ipc_ctx_set_stream(ipc_ctx *ctx, void *hip_stream);
+
+/* Compress a C-ordered field (dims[0] slowest, ndim 1..3, every dim >= 1) of
+ * float32 or float64 on the device with absolute error bound abs_eb > 0
+ * (finite).  The field is read only and must stay valid for the call.
+ * Every reconstructed value satisfies |x - x^| <= abs_eb (Sec. 4.2.2).
+ * The returned stream is device resident. */
+ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dims, int ndim,
+                        int dtype, double abs_eb, const ipc_options *opts, ipc_stream **out);
+
+/* Serialized size of a stream in bytes (the compressed size). */
+ipc_status ipc_stream_size(const ipc_stream *s, uint64_t *bytes);
+/* Write the serialized stream to host memory `dst` of `capacity` bytes. */
+ipc_status ipc_stream_to_host(ipc_ctx *ctx, const ipc_stream *s, void *dst, uint64_t capacity);
+/* Make a device-resident stream from serialized bytes (validated:
+ * IPC_ECORRUPT on any inconsistency). */
+ipc_status ipc_stream_from_host(ipc_ctx *ctx, const void *src, uint64_t bytes, ipc_stream **out);
+void ipc_stream_free(ipc_stream *s);
+
+/* Alg. 1: reconstruct from the planes the Sec. 5 planner selects for
+ * `target`.  The state holds the reconstruction and the plan; `info` may be
+ * NULL. */
+ipc_status ipc_retrieve(ipc_ctx *ctx, const ipc_stream *s, ipc_target target, ipc_state **out,
+                        ipc_info *info);
+/* Same, with an explicit plan (planes discarded per pass, n_passes entries). */
+ipc_status ipc_retrieve_plan(ipc_ctx *ctx, const ipc_stream *s, const uint8_t *plan,
+                             uint32_t n_passes, ipc_state **out, ipc_info *info);
+/* Device pointer to the state's reconstructed field (C order, the stream's
+ * dtype); valid until the next ipc_refine on the state or ipc_state_free. */
+const void *ipc_state_field(const ipc_state *st);
+/* Stream-ordered device-to-device copy of the state's field into `dst_dev`
+ * (capacity bytes, at least n * itemsize). */
+ipc_status ipc_state_copy_field(ipc_ctx *ctx, const ipc_state *st, void *dst_dev,
+                                uint64_t capacity);
+/* Number of passes of a stream (anchors + one per level and dimension). */
+ipc_status ipc_stream_passes(const ipc_stream *s, uint32_t *n_passes);
+/* Alg. 2: tighten a resident reconstruction to `target`, loading only planes
+ * not yet loaded; the result equals a fresh retrieval with the new plan bit
+ * for bit.  A target already met is a no-op (IPC_FLAG_NOOP). */
+ipc_status ipc_refine(ipc_ctx *ctx, ipc_state *st, ipc_target target, ipc_info *info);
+void ipc_state_free(ipc_state *st);
+
+/* Host-only planner on a serialized stream (no GPU needed): the plan the
+ * library would choose for `target`, optionally restricted to b <= limit[s]
+ * (refinement).  plan_out has room for the stream's pass count. */
+ipc_status ipc_plan_host(const void *stream_bytes, uint64_t nbytes, ipc_target target,
+                         const uint8_t *limit, uint8_t *plan_out, uint32_t plan_capacity,
+                         double *bound_out, uint32_t *flags_out, uint64_t *loaded_out);
+
+const char *ipc_status_string(ipc_status st);
+const char *ipc_last_error(const ipc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPCOMP_H */

@@ -342,7 +342,8 @@ def retrieve_with_plan(buf: bytes, plan, mode: str = "eb", target: Optional[floa
         passes.append(PassData(e=e, b=b))
     fld = np.zeros(ps.header.dims, dtype=ps.header.dtype)
     if target is None:
-        bound = planner.bound_of(tables, plan, tables.maxabs)
+        b0 = planner.bound_of(tables, plan, tables.maxabs)
+        bound = planner.bound_of(tables, plan, 2.0 * (tables.maxabs + b0))
     else:
         bound = planner.reported_bound(tables, plan, mode, target)
     st = State(stream=buf, parsed=ps, sched=sched, tables=tables, plan=plan.copy(),

@@ -31,7 +31,8 @@ Readings used:
   floor(term / unit) + 1 units for a non-zero term (never below the exact
   ratio), 0 for a zero term.  Ties go to the smallest number of discarded
   planes.  Byte budgets are discretised into at most 1024 units, costs rounded
-  up, so the plan never exceeds the budget.
+  up, so the plan never exceeds the budget; a budget of at least the whole
+  stream loads everything.
 * Anchors (pass 0) and the passes of the first ``nonprog_levels`` levels are
   always fully loaded.
 """
@@ -170,10 +171,9 @@ def plan_error_bound(t: PlanTables, E: float, limit=None):
             tv = term(t, s, b, r) if t.progressive[s] else 0.0
             if tv == 0.0:
                 c = 0
-            elif u > 0.0:
-                c = math.floor(tv / u) + 1
             else:
-                c = G_UNITS + 1
+                qv = tv / u if u > 0.0 else math.inf
+                c = math.floor(qv) + 1 if qv < G_UNITS else G_UNITS + 1
             costs[s, b] = c
             if c > G_UNITS:
                 continue
@@ -202,7 +202,11 @@ def plan_bitrate(t: PlanTables, bitrate: float, limit=None):
     bytes already loaded, the current plan is returned with FLAG_NOOP.
     """
     P = t.n_passes
-    budget = math.floor(bitrate * t.n_points / 8.0) - t.fixed_bytes
+    bt = bitrate * t.n_points / 8.0
+    if bt >= t.total_bytes:
+        # everything fits
+        return np.zeros(P, dtype=np.int64), 0
+    budget = math.floor(bt) - t.fixed_bytes
     if limit is not None:
         cur = np.asarray(limit, dtype=np.int64)
         if budget < loaded_bytes(t, cur) - t.fixed_bytes:

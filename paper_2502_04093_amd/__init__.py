@@ -1,0 +1,307 @@
+"""Python binding of the IPComp MI355X library (``libipcomp.so``).
+
+Thin ctypes wrappers with the names of the C ABI in ``include/ipcomp.h``;
+every step of compression, retrieval and refinement runs in the library's HIP
+kernels.  PyTorch supplies device memory (the field and output tensors) and
+the HIP stream calls are ordered on.  There is no CPU fallback: if the library
+is not built, importing the binding's entry points raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import weakref
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libipcomp.so")
+
+IPC_F32, IPC_F64 = 0, 1
+IPC_LINEAR, IPC_CUBIC = 0, 1
+IPC_TARGET_EB, IPC_TARGET_BITRATE = 0, 1
+IPC_FLAG_CLAMPED_TO_EB, IPC_FLAG_BUDGET_BELOW_MIN, IPC_FLAG_NOOP = 1, 2, 4
+IPC_MAX_PASSES = 100
+STATUS = {0: "IPC_OK", -1: "IPC_EINVAL", -2: "IPC_ENOMEM", -3: "IPC_ECORRUPT", -4: "IPC_EHIP",
+          -5: "IPC_ESTATE", -6: "IPC_EUNSUPPORTED"}
+
+c_void_p, c_int, c_uint8, c_uint32, c_uint64, c_double, c_float = (
+    ctypes.c_void_p, ctypes.c_int, ctypes.c_uint8, ctypes.c_uint32, ctypes.c_uint64,
+    ctypes.c_double, ctypes.c_float)
+
+
+class ipc_target(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("value", c_double)]
+
+
+class ipc_options(ctypes.Structure):
+    _fields_ = [("interp", ctypes.c_int32), ("nonprog_levels", ctypes.c_int32),
+                ("chunk_log2", c_uint8 * 3), ("reserved", c_uint8 * 5)]
+
+
+class ipc_info(ctypes.Structure):
+    _fields_ = [("bound", c_double), ("bytes_loaded", c_uint64), ("bytes_total", c_uint64),
+                ("bytes_read", c_uint64), ("n_passes", c_uint32), ("flags", c_uint32),
+                ("plan", c_uint8 * IPC_MAX_PASSES), ("t_plan_ms", c_float),
+                ("t_device_ms", c_float)]
+
+    def plan_list(self):
+        return [int(self.plan[i]) for i in range(self.n_passes)]
+
+
+P = ctypes.POINTER
+SIGNATURES = {
+    "ipc_ctx_create": (c_int, [c_int, c_void_p, P(c_void_p)]),
+    "ipc_ctx_destroy": (None, [c_void_p]),
+    "ipc_ctx_set_stream": (c_int, [c_void_p, c_void_p]),
+    "ipc_compress": (c_int, [c_void_p, c_void_p, P(c_uint64), c_int, c_int, c_double,
+                             P(ipc_options), P(c_void_p)]),
+    "ipc_stream_size": (c_int, [c_void_p, P(c_uint64)]),
+    "ipc_stream_to_host": (c_int, [c_void_p, c_void_p, c_void_p, c_uint64]),
+    "ipc_stream_from_host": (c_int, [c_void_p, c_void_p, c_uint64, P(c_void_p)]),
+    "ipc_stream_free": (None, [c_void_p]),
+    "ipc_stream_passes": (c_int, [c_void_p, P(c_uint32)]),
+    "ipc_retrieve": (c_int, [c_void_p, c_void_p, ipc_target, P(c_void_p), P(ipc_info)]),
+    "ipc_retrieve_plan": (c_int, [c_void_p, c_void_p, P(c_uint8), c_uint32, P(c_void_p),
+                                  P(ipc_info)]),
+    "ipc_state_field": (c_void_p, [c_void_p]),
+    "ipc_state_copy_field": (c_int, [c_void_p, c_void_p, c_void_p, c_uint64]),
+    "ipc_refine": (c_int, [c_void_p, c_void_p, ipc_target, P(ipc_info)]),
+    "ipc_state_free": (None, [c_void_p]),
+    "ipc_plan_host": (c_int, [c_void_p, c_uint64, ipc_target, P(c_uint8), P(c_uint8), c_uint32,
+                              P(c_double), P(c_uint32), P(c_uint64)]),
+    "ipc_status_string": (ctypes.c_char_p, [c_int]),
+    "ipc_last_error": (ctypes.c_char_p, [c_void_p]),
+}
+
+_lib = None
+
+
+class IpcError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        self.status = status
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+
+
+def lib():
+    """The loaded C library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libipcomp.so not built ({LIB_PATH}); run "
+                              "`python -m paper_2502_04093_amd.build` first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st: int, ctx=None):
+    if st != 0:
+        msg = lib().ipc_last_error(ctx).decode() if ctx else ""
+        raise IpcError(st, msg)
+
+
+def _target(eb: Optional[float], bitrate: Optional[float]) -> ipc_target:
+    if (eb is None) == (bitrate is None):
+        raise ValueError("give exactly one of eb= and bitrate=")
+    if eb is not None:
+        return ipc_target(IPC_TARGET_EB, float(eb))
+    return ipc_target(IPC_TARGET_BITRATE, float(bitrate))
+
+
+def plan_host(stream_bytes: bytes, eb=None, bitrate=None, limit: Optional[Sequence[int]] = None):
+    """Host-only planner: (plan, bound, flags, loaded_bytes) for a serialized stream."""
+    L = lib()
+    buf = ctypes.create_string_buffer(bytes(stream_bytes), len(stream_bytes))
+    out = (c_uint8 * IPC_MAX_PASSES)()
+    lim = (c_uint8 * IPC_MAX_PASSES)(*limit) if limit is not None else None
+    bound, flags, loaded = c_double(), c_uint32(), c_uint64()
+    st = L.ipc_plan_host(buf, len(stream_bytes), _target(eb, bitrate), lim, out, IPC_MAX_PASSES,
+                         ctypes.byref(bound), ctypes.byref(flags), ctypes.byref(loaded))
+    _check(st)
+    return list(out), bound.value, flags.value, loaded.value
+
+
+class Context:
+    """ipc_ctx on a device, ordered on torch's current HIP stream by default."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        L = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        handle = c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+        p = c_void_p()
+        _check(L.ipc_ctx_create(int(device), handle, ctypes.byref(p)))
+        self._p = p
+        self.device = device
+        self._states = weakref.WeakSet()
+        self._streams = weakref.WeakSet()
+
+    def close(self):
+        """Free every live state and stream of this context, then the context."""
+        if getattr(self, "_p", None):
+            for st in list(self._states):
+                st.free()
+            for s in list(self._streams):
+                s.free()
+            lib().ipc_ctx_destroy(self._p)
+            self._p = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._p
+
+    def compress(self, field, eb: float, interp: str = "cubic", nonprog_levels: int = 0,
+                 chunk_log2: Optional[Sequence[int]] = None) -> "Stream":
+        import torch
+        if not (field.is_cuda and field.is_contiguous()):
+            raise ValueError("field must be a contiguous device tensor")
+        if field.dtype not in (torch.float32, torch.float64):
+            raise TypeError("field must be float32 or float64")
+        dims = (c_uint64 * field.dim())(*field.shape)
+        opts = ipc_options()
+        opts.interp = IPC_CUBIC if interp == "cubic" else IPC_LINEAR
+        opts.nonprog_levels = nonprog_levels
+        if chunk_log2 is not None:
+            for j, c in enumerate(chunk_log2):
+                opts.chunk_log2[j] = c
+        out = c_void_p()
+        dt = IPC_F32 if field.dtype == torch.float32 else IPC_F64
+        _check(lib().ipc_compress(self._p, c_void_p(field.data_ptr()), dims, field.dim(), dt,
+                                  float(eb), ctypes.byref(opts), ctypes.byref(out)), self._p)
+        return Stream(self, out, tuple(field.shape), field.dtype)
+
+    def stream_from_bytes(self, data: bytes, shape=None, dtype=None) -> "Stream":
+        import numpy as np
+        import torch
+        out = c_void_p()
+        buf = ctypes.create_string_buffer(bytes(data), len(data))
+        _check(lib().ipc_stream_from_host(self._p, buf, len(data), ctypes.byref(out)), self._p)
+        if shape is None or dtype is None:
+            import struct
+            dcode, nd = data[8], data[9]
+            dims = struct.unpack("<3Q", data[16:40])[:nd]
+            shape = tuple(int(d) for d in dims)
+            dtype = torch.float32 if dcode == 0 else torch.float64
+        _ = np
+        return Stream(self, out, shape, dtype)
+
+
+class Stream:
+    """ipc_stream: a device-resident compressed field."""
+
+    def __init__(self, ctx: Context, p, shape, dtype):
+        self.ctx, self._p, self.shape, self.dtype = ctx, p, shape, dtype
+        ctx._streams.add(self)
+
+    def free(self):
+        if getattr(self, "_p", None):
+            for st in list(self.ctx._states):
+                if st.stream is self:
+                    st.free()
+            lib().ipc_stream_free(self._p)
+            self._p = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    @property
+    def nbytes(self) -> int:
+        n = c_uint64()
+        _check(lib().ipc_stream_size(self._p, ctypes.byref(n)))
+        return n.value
+
+    @property
+    def n_passes(self) -> int:
+        n = c_uint32()
+        _check(lib().ipc_stream_passes(self._p, ctypes.byref(n)))
+        return n.value
+
+    def to_bytes(self) -> bytes:
+        n = self.nbytes
+        buf = ctypes.create_string_buffer(n)
+        _check(lib().ipc_stream_to_host(self.ctx.handle, self._p, buf, n), self.ctx.handle)
+        return buf.raw
+
+    def retrieve(self, eb=None, bitrate=None) -> "State":
+        out = c_void_p()
+        info = ipc_info()
+        _check(lib().ipc_retrieve(self.ctx.handle, self._p, _target(eb, bitrate),
+                                  ctypes.byref(out), ctypes.byref(info)), self.ctx.handle)
+        return State(self, out, info)
+
+    def retrieve_plan(self, plan: Sequence[int]) -> "State":
+        out = c_void_p()
+        info = ipc_info()
+        arr = (c_uint8 * len(plan))(*plan)
+        _check(lib().ipc_retrieve_plan(self.ctx.handle, self._p, arr, len(plan),
+                                       ctypes.byref(out), ctypes.byref(info)), self.ctx.handle)
+        return State(self, out, info)
+
+
+class State:
+    """ipc_state: a resident reconstruction plus the planes it was built from."""
+
+    def __init__(self, stream: Stream, p, info: ipc_info):
+        self.stream, self._p, self.info = stream, p, info
+        stream.ctx._states.add(self)
+
+    def free(self):
+        if getattr(self, "_p", None):
+            lib().ipc_state_free(self._p)
+            self._p = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    @property
+    def plan(self):
+        return self.info.plan_list()
+
+    @property
+    def bound(self) -> float:
+        return self.info.bound
+
+    def field_ptr(self) -> int:
+        return lib().ipc_state_field(self._p)
+
+    def tensor(self):
+        """A copy of the reconstruction as a torch tensor on the device."""
+        import torch
+        t = torch.empty(self.stream.shape, dtype=self.stream.dtype,
+                        device=f"cuda:{self.stream.ctx.device}")
+        self.copy_into(t)
+        return t
+
+    def copy_into(self, t):
+        _check(lib().ipc_state_copy_field(self.stream.ctx.handle, self._p, c_void_p(t.data_ptr()),
+                                          t.numel() * t.element_size()), self.stream.ctx.handle)
+
+    def refine(self, eb=None, bitrate=None) -> ipc_info:
+        info = ipc_info()
+        _check(lib().ipc_refine(self.stream.ctx.handle, self._p, _target(eb, bitrate),
+                                ctypes.byref(info)), self.stream.ctx.handle)
+        if not info.flags & IPC_FLAG_NOOP:
+            self.info = info
+        return info
+
+
+__all__ = ["lib", "plan_host", "Context", "Stream", "State", "IpcError", "ipc_info",
+           "ipc_target", "ipc_options", "LIB_PATH"]

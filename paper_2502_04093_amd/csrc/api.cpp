@@ -1,0 +1,764 @@
+// C ABI of the IPComp library: contexts, streams, states and the three calls
+// of the paper's problem statement (compress; retrieve at a fidelity; refine to
+// a higher fidelity), plus the host-only planner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ipc_internal.h"
+#include "kernels.h"
+
+using namespace ipc;
+
+// ------------------------------------------------------------------ objects
+
+struct ipc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t owned = nullptr;
+  std::string err;
+  std::multimap<size_t, void *> cache;  // freed device blocks by size
+  size_t cached_bytes = 0;
+  // reusable workspace
+  void *ws_xh = nullptr;
+  size_t ws_xh_bytes = 0;
+  void *ws_summary = nullptr;
+  size_t ws_summary_bytes = 0;
+  void *ws_out = nullptr;
+  size_t ws_out_cap = 0;  // records
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+struct ipc_stream {
+  ipc_ctx *ctx = nullptr;
+  StreamMeta meta;
+  PlanTables tables;
+  bool packed = false;         // payload placement
+  DevBuf payload;              // u32 words
+  DevBuf masks;                // u32 per chunk
+  DevBuf chunk_off;            // u64 per chunk (packed placement only)
+  DevBuf out_gchunk, out_local, out_bits;
+  bool host_masks_valid = false;
+  std::vector<PassArgs> args;
+};
+
+struct ipc_state {
+  ipc_ctx *ctx = nullptr;
+  const ipc_stream *stream = nullptr;
+  std::vector<int> plan;
+  DevBuf field;
+  double bound = 0;
+};
+
+// ------------------------------------------------------------------ helpers
+
+namespace {
+
+struct Fail {
+  ipc_status st;
+};
+
+void set_err(ipc_ctx *ctx, const std::string &m) {
+  if (ctx) ctx->err = m;
+}
+
+void hip_check(ipc_ctx *ctx, hipError_t e, const char *what) {
+  if (e != hipSuccess) {
+    set_err(ctx, std::string(what) + ": " + hipGetErrorString(e));
+    throw Fail{e == hipErrorOutOfMemory ? IPC_ENOMEM : IPC_EHIP};
+  }
+}
+
+DevBuf dev_alloc(ipc_ctx *ctx, size_t bytes) {
+  DevBuf b;
+  b.bytes = bytes;
+  if (bytes == 0) return b;
+  auto it = ctx->cache.lower_bound(bytes);
+  if (it != ctx->cache.end() && it->first <= bytes + bytes / 2 + 4096) {
+    b.p = it->second;
+    b.bytes = it->first;
+    ctx->cached_bytes -= it->first;
+    ctx->cache.erase(it);
+    return b;
+  }
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    // release the cache and retry once
+    for (auto &kv : ctx->cache) (void)hipFree(kv.second);
+    ctx->cache.clear();
+    ctx->cached_bytes = 0;
+    (void)hipGetLastError();
+    e = hipMalloc(&b.p, bytes);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_err(ctx, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    throw Fail{IPC_ENOMEM};
+  }
+  return b;
+}
+
+void dev_free(ipc_ctx *ctx, DevBuf &b) {
+  if (b.p) {
+    if (ctx) {
+      ctx->cache.emplace(b.bytes, b.p);
+      ctx->cached_bytes += b.bytes;
+    } else {
+      (void)hipFree(b.p);
+    }
+  }
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+void *ensure_ws(ipc_ctx *ctx, void *&p, size_t &have, size_t need) {
+  if (have >= need && p) return p;
+  if (p) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(p);
+    p = nullptr;
+    have = 0;
+  }
+  hipError_t e = hipMalloc(&p, need);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_err(ctx, "workspace allocation failed");
+    throw Fail{IPC_ENOMEM};
+  }
+  have = need;
+  return p;
+}
+
+PassArgs make_args(const Schedule &s, const PassGeom &p) {
+  PassArgs a;
+  for (int j = 0; j < 3; ++j) {
+    a.dims3[j] = s.dims3[j];
+    a.ldims[j] = p.ldims[j];
+    a.tdims[j] = p.tdims[j];
+    a.ct[j] = p.ct[j];
+    a.tiles[j] = p.tiles[j];
+    a.kinds[j] = p.kinds[j];
+  }
+  a.dim3 = p.dim3;
+  a.h = p.h;
+  a.n_chunks = p.n_chunks;
+  a.chunk_base = p.chunk_base;
+  a.slot_base = p.slot_base;
+  a.wmax = uint32_t(p.wmax);
+  a.pass_index = uint32_t(p.index);
+  return a;
+}
+
+bool chunks_supported(const Schedule &s, std::string &err) {
+  for (const PassGeom &p : s.passes)
+    if (p.max_count > MAX_CHUNK_CODES) {
+      err = "chunks larger than " + std::to_string(MAX_CHUNK_CODES) + " codes are not supported";
+      return false;
+    }
+  return true;
+}
+
+template <typename F>
+ipc_status guarded(ipc_ctx *ctx, F &&f) {
+  try {
+    f();
+    return IPC_OK;
+  } catch (const Fail &e) {
+    return e.st;
+  } catch (const std::bad_alloc &) {
+    set_err(ctx, "host allocation failed");
+    return IPC_ENOMEM;
+  } catch (...) {
+    set_err(ctx, "unexpected internal error");
+    return IPC_EHIP;
+  }
+}
+
+void free_stream_bufs(ipc_stream *s) {
+  ipc_ctx *c = s->ctx;
+  dev_free(c, s->payload);
+  dev_free(c, s->masks);
+  dev_free(c, s->chunk_off);
+  dev_free(c, s->out_gchunk);
+  dev_free(c, s->out_local);
+  dev_free(c, s->out_bits);
+}
+
+void upload_outliers(ipc_ctx *ctx, ipc_stream *s) {
+  size_t n = s->meta.outliers.size();
+  if (n == 0) return;
+  std::vector<uint64_t> gch(n), bits(n);
+  std::vector<uint32_t> loc(n);
+  for (size_t i = 0; i < n; ++i) {
+    const OutlierRec &o = s->meta.outliers[i];
+    gch[i] = uint64_t(s->meta.sched.passes[o.pass].chunk_base) + o.chunk;
+    loc[i] = o.local;
+    bits[i] = o.bits;
+  }
+  s->out_gchunk = dev_alloc(ctx, 8 * n);
+  s->out_local = dev_alloc(ctx, 4 * n);
+  s->out_bits = dev_alloc(ctx, 8 * n);
+  hip_check(ctx, hipMemcpyAsync(s->out_gchunk.p, gch.data(), 8 * n, hipMemcpyHostToDevice, ctx->stream), "upload");
+  hip_check(ctx, hipMemcpyAsync(s->out_local.p, loc.data(), 4 * n, hipMemcpyHostToDevice, ctx->stream), "upload");
+  hip_check(ctx, hipMemcpyAsync(s->out_bits.p, bits.data(), 8 * n, hipMemcpyHostToDevice, ctx->stream), "upload");
+  hip_check(ctx, hipStreamSynchronize(ctx->stream), "upload");
+}
+
+void fill_info(const ipc_stream *s, const std::vector<int> &plan, double bound, uint32_t flags,
+               uint64_t read, float tplan, float tdev, ipc_info *info) {
+  if (!info) return;
+  std::memset(info, 0, sizeof(*info));
+  info->bound = bound;
+  info->bytes_loaded = uint64_t(plan_loaded(s->tables, plan));
+  info->bytes_total = s->meta.serialized_bytes;
+  info->bytes_read = read;
+  info->n_passes = uint32_t(plan.size());
+  info->flags = flags;
+  for (size_t i = 0; i < plan.size() && i < IPC_MAX_PASSES; ++i) info->plan[i] = uint8_t(plan[i]);
+  info->t_plan_ms = tplan;
+  info->t_device_ms = tdev;
+}
+
+// run passes [s0, P) of a retrieval into `field`
+void run_retrieve(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &plan, int s0,
+                  void *field) {
+  RetrieveIn in;
+  in.payload = static_cast<const uint32_t *>(s->payload.p);
+  in.masks = static_cast<const uint32_t *>(s->masks.p);
+  in.chunk_off = s->packed ? static_cast<const uint64_t *>(s->chunk_off.p) : nullptr;
+  in.out_gchunk = static_cast<const uint64_t *>(s->out_gchunk.p);
+  in.out_local = static_cast<const uint32_t *>(s->out_local.p);
+  in.out_bits = static_cast<const uint64_t *>(s->out_bits.p);
+  in.n_out = s->meta.outliers.size();
+  for (size_t i = size_t(s0); i < s->args.size(); ++i)
+    hip_check(ctx, launch_retrieve_pass(s->meta.dtype, s->meta.interp, s->args[i], field, plan[i],
+                                        in, s->meta.eb, ctx->stream),
+              "retrieve kernel launch");
+}
+
+uint64_t plane_bytes_between(const ipc_stream *s, const std::vector<int> &lo,
+                             const std::vector<int> &hi) {
+  uint64_t tot = 0;
+  for (size_t p = 0; p < lo.size(); ++p)
+    for (int k = lo[p]; k < hi[p]; ++k) tot += uint64_t(s->tables.sizes[p * 32 + k]);
+  return tot;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char *ipc_status_string(ipc_status st) {
+  switch (st) {
+    case IPC_OK: return "ok";
+    case IPC_EINVAL: return "invalid argument";
+    case IPC_ENOMEM: return "out of memory";
+    case IPC_ECORRUPT: return "corrupt stream";
+    case IPC_EHIP: return "HIP runtime error";
+    case IPC_ESTATE: return "object used with the wrong context or stream";
+    case IPC_EUNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+const char *ipc_last_error(const ipc_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+ipc_status ipc_ctx_create(int device, void *hip_stream, ipc_ctx **out) {
+  if (!out) return IPC_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return IPC_EINVAL;
+  }
+  ipc_ctx *c = new (std::nothrow) ipc_ctx();
+  if (!c) return IPC_ENOMEM;
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return IPC_EHIP;
+  }
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->owned, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return IPC_EHIP;
+    }
+    c->stream = c->owned;
+  }
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    if (c->owned) (void)hipStreamDestroy(c->owned);
+    delete c;
+    return IPC_EHIP;
+  }
+  *out = c;
+  return IPC_OK;
+}
+
+ipc_status ipc_ctx_set_stream(ipc_ctx *ctx, void *hip_stream) {
+  if (!ctx) return IPC_EINVAL;
+  (void)hipStreamSynchronize(ctx->stream);
+  if (hip_stream) {
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (!ctx->owned && hipStreamCreateWithFlags(&ctx->owned, hipStreamNonBlocking) != hipSuccess)
+      return IPC_EHIP;
+    ctx->stream = ctx->owned;
+  }
+  return IPC_OK;
+}
+
+void ipc_ctx_destroy(ipc_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto &kv : ctx->cache) (void)hipFree(kv.second);
+  if (ctx->ws_xh) (void)hipFree(ctx->ws_xh);
+  if (ctx->ws_summary) (void)hipFree(ctx->ws_summary);
+  if (ctx->ws_out) (void)hipFree(ctx->ws_out);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->owned) (void)hipStreamDestroy(ctx->owned);
+  delete ctx;
+}
+
+ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dims, int ndim,
+                        int dtype, double abs_eb, const ipc_options *opts, ipc_stream **out) {
+  if (!out) return IPC_EINVAL;
+  *out = nullptr;
+  if (!ctx) return IPC_EINVAL;
+  if (!field_dev || !dims || ndim < 1 || ndim > 3 || (dtype != IPC_F32 && dtype != IPC_F64) ||
+      !(std::isfinite(abs_eb) && abs_eb > 0)) {
+    set_err(ctx, "invalid argument to ipc_compress");
+    return IPC_EINVAL;
+  }
+  int interp = opts ? opts->interp : IPC_CUBIC;
+  if (interp != IPC_LINEAR && interp != IPC_CUBIC) {
+    set_err(ctx, "interp must be IPC_LINEAR or IPC_CUBIC");
+    return IPC_EINVAL;
+  }
+  ipc_stream *s = new (std::nothrow) ipc_stream();
+  if (!s) return IPC_ENOMEM;
+  s->ctx = ctx;
+  ipc_status st = guarded(ctx, [&] {
+    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    int64_t d64[3];
+    for (int j = 0; j < ndim; ++j) d64[j] = int64_t(dims[j]);
+    int cl[3] = {0, 0, 0};
+    if (opts)
+      for (int j = 0; j < ndim; ++j) cl[j] = opts->chunk_log2[j];
+    StreamMeta &m = s->meta;
+    std::string e;
+    if (!make_schedule(d64, ndim, cl, m.sched, e)) {
+      set_err(ctx, e);
+      throw Fail{IPC_EINVAL};
+    }
+    if (!chunks_supported(m.sched, e)) {
+      set_err(ctx, e);
+      throw Fail{IPC_EUNSUPPORTED};
+    }
+    int np = opts ? opts->nonprog_levels : 0;
+    if (np < 0 || np > m.sched.K) {
+      set_err(ctx, "nonprog_levels out of range");
+      throw Fail{IPC_EINVAL};
+    }
+    m.dtype = dtype;
+    m.interp = interp;
+    m.nonprog_levels = np;
+    m.eb = abs_eb;
+    m.qmax = dtype == IPC_F32 ? QMAX_F32 : QMAX_F64;
+    const Schedule &sc = m.sched;
+    const int P = int(sc.passes.size());
+    const size_t isz = dtype == IPC_F32 ? 4 : 8;
+    const size_t nbytes = size_t(sc.n_points) * isz;
+    for (const PassGeom &p : sc.passes) s->args.push_back(make_args(sc, p));
+
+    s->payload = dev_alloc(ctx, size_t(sc.slot_words) * 4);
+    s->masks = dev_alloc(ctx, size_t(sc.n_chunks) * 4);
+    void *xh = ensure_ws(ctx, ctx->ws_xh, ctx->ws_xh_bytes, nbytes);
+    // summary: n_out, maxabs bits, sizes [P][32] u64, errq [P][33] u32
+    size_t sum_bytes = 16 + size_t(P) * 32 * 8 + size_t(P) * 33 * 4;
+    char *summary = static_cast<char *>(ensure_ws(ctx, ctx->ws_summary, ctx->ws_summary_bytes, sum_bytes));
+    size_t cap = std::max<size_t>(4096, size_t(sc.n_points / 1024));
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      ensure_ws(ctx, ctx->ws_out, ctx->ws_out_cap, cap * sizeof(OutlierRec));
+      size_t cap_recs = ctx->ws_out_cap / sizeof(OutlierRec);
+      hip_check(ctx, hipMemsetAsync(summary, 0, sum_bytes, ctx->stream), "memset");
+      CompressOut o;
+      o.payload = static_cast<uint32_t *>(s->payload.p);
+      o.masks = static_cast<uint32_t *>(s->masks.p);
+      o.n_out = reinterpret_cast<unsigned long long *>(summary);
+      o.maxabs_bits = reinterpret_cast<unsigned long long *>(summary + 8);
+      unsigned long long *sizes = reinterpret_cast<unsigned long long *>(summary + 16);
+      o.errq = reinterpret_cast<uint32_t *>(summary + 16 + size_t(P) * 32 * 8);
+      o.out_recs = ctx->ws_out;
+      o.out_cap = cap_recs;
+      hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
+      for (int i = 0; i < P; ++i) {
+        int wb = i + 1 < P ? 1 : 0;  // the last pass is read by nobody
+        hip_check(ctx, launch_compress_pass(dtype, interp, s->args[i], field_dev, xh, wb, abs_eb, o,
+                                            ctx->stream),
+                  "compress kernel launch");
+      }
+      for (int i = 0; i < P; ++i)
+        hip_check(ctx, launch_pass_sizes(s->args[i], o.masks, sizes + size_t(i) * 32, ctx->stream),
+                  "sizes kernel launch");
+      hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
+      std::vector<char> host(sum_bytes);
+      hip_check(ctx, hipMemcpyAsync(host.data(), summary, sum_bytes, hipMemcpyDeviceToHost, ctx->stream), "copy");
+      hip_check(ctx, hipStreamSynchronize(ctx->stream), "compress");
+      uint64_t nout;
+      std::memcpy(&nout, host.data(), 8);
+      if (nout > cap_recs) {
+        cap = size_t(nout) + 1024;
+        if (attempt == 0) continue;
+        set_err(ctx, "outlier buffer overflow");
+        throw Fail{IPC_EHIP};
+      }
+      uint64_t mb;
+      std::memcpy(&mb, host.data() + 8, 8);
+      std::memcpy(&m.maxabs, &mb, 8);
+      m.errq.resize(size_t(P) * 33);
+      std::memcpy(m.errq.data(), host.data() + 16 + size_t(P) * 32 * 8, m.errq.size() * 4);
+      std::vector<uint64_t> sz(size_t(P) * 32);
+      std::memcpy(sz.data(), host.data() + 16, sz.size() * 8);
+      m.outliers.resize(nout);
+      if (nout) {
+        hip_check(ctx, hipMemcpy(m.outliers.data(), ctx->ws_out, nout * sizeof(OutlierRec), hipMemcpyDeviceToHost), "copy");
+        std::sort(m.outliers.begin(), m.outliers.end(), [](const OutlierRec &a, const OutlierRec &b) {
+          if (a.pass != b.pass) return a.pass < b.pass;
+          if (a.chunk != b.chunk) return a.chunk < b.chunk;
+          return a.local < b.local;
+        });
+      }
+      uint64_t words = 0;
+      for (uint64_t v : sz) words += v / 4;
+      m.payload_words = words;
+      m.serialized_bytes = serialized_size(m);
+      // planner tables from the device-computed plane sizes (no mask copy needed)
+      s->tables = plan_tables_from_sizes(m, sz);
+      break;
+    }
+    upload_outliers(ctx, s);
+  });
+  if (st != IPC_OK) {
+    free_stream_bufs(s);
+    delete s;
+    return st;
+  }
+  *out = s;
+  return IPC_OK;
+}
+
+ipc_status ipc_stream_size(const ipc_stream *s, uint64_t *bytes) {
+  if (!s || !bytes) return IPC_EINVAL;
+  *bytes = s->meta.serialized_bytes;
+  return IPC_OK;
+}
+
+ipc_status ipc_stream_to_host(ipc_ctx *ctx, const ipc_stream *sc, void *dst, uint64_t capacity) {
+  if (!ctx || !sc || !dst) return IPC_EINVAL;
+  if (sc->ctx != ctx) {
+    set_err(ctx, "stream belongs to another context");
+    return IPC_ESTATE;
+  }
+  ipc_stream *s = const_cast<ipc_stream *>(sc);
+  if (capacity < s->meta.serialized_bytes) {
+    set_err(ctx, "destination too small");
+    return IPC_EINVAL;
+  }
+  return guarded(ctx, [&] {
+    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    StreamMeta &m = s->meta;
+    if (!s->host_masks_valid) {
+      m.masks.resize(size_t(m.sched.n_chunks));
+      hip_check(ctx, hipMemcpyAsync(m.masks.data(), s->masks.p, m.masks.size() * 4, hipMemcpyDeviceToHost, ctx->stream), "copy");
+      hip_check(ctx, hipStreamSynchronize(ctx->stream), "copy");
+      s->host_masks_valid = true;
+    }
+    uint8_t *d = static_cast<uint8_t *>(dst);
+    write_serialized_head(m, d);
+    uint64_t poff = payload_offset(m);
+    uint64_t pbytes = m.payload_words * 4;
+    if (s->packed) {
+      hip_check(ctx, hipMemcpyAsync(d + poff, s->payload.p, pbytes, hipMemcpyDeviceToHost, ctx->stream), "copy");
+    } else {
+      std::vector<uint64_t> off;
+      packed_chunk_offsets(m, off);
+      DevBuf doff = dev_alloc(ctx, off.size() * 8);
+      DevBuf packed = dev_alloc(ctx, std::max<size_t>(4, pbytes));
+      try {
+        hip_check(ctx, hipMemcpyAsync(doff.p, off.data(), off.size() * 8, hipMemcpyHostToDevice, ctx->stream), "copy");
+        for (const PassArgs &a : s->args)
+          hip_check(ctx, launch_pack_payload(a, static_cast<const uint32_t *>(s->masks.p),
+                                             static_cast<const uint64_t *>(doff.p),
+                                             static_cast<const uint32_t *>(s->payload.p),
+                                             static_cast<uint32_t *>(packed.p), ctx->stream),
+                    "pack kernel launch");
+        hip_check(ctx, hipMemcpyAsync(d + poff, packed.p, pbytes, hipMemcpyDeviceToHost, ctx->stream), "copy");
+        hip_check(ctx, hipStreamSynchronize(ctx->stream), "copy");
+      } catch (...) {
+        dev_free(ctx, doff);
+        dev_free(ctx, packed);
+        throw;
+      }
+      dev_free(ctx, doff);
+      dev_free(ctx, packed);
+    }
+    hip_check(ctx, hipStreamSynchronize(ctx->stream), "copy");
+    std::memset(d + poff + pbytes, 0, size_t(pad8(pbytes) - pbytes));
+  });
+}
+
+ipc_status ipc_stream_from_host(ipc_ctx *ctx, const void *src, uint64_t bytes, ipc_stream **out) {
+  if (!out) return IPC_EINVAL;
+  *out = nullptr;
+  if (!ctx || !src) return IPC_EINVAL;
+  ipc_stream *s = new (std::nothrow) ipc_stream();
+  if (!s) return IPC_ENOMEM;
+  s->ctx = ctx;
+  ipc_status st = guarded(ctx, [&] {
+    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    const uint32_t *payload = nullptr;
+    std::string e;
+    if (!parse_serialized(static_cast<const uint8_t *>(src), bytes, s->meta, &payload, e)) {
+      set_err(ctx, e);
+      throw Fail{IPC_ECORRUPT};
+    }
+    if (!chunks_supported(s->meta.sched, e)) {
+      set_err(ctx, e);
+      throw Fail{IPC_EUNSUPPORTED};
+    }
+    StreamMeta &m = s->meta;
+    s->host_masks_valid = true;
+    s->packed = true;
+    for (const PassGeom &p : m.sched.passes) s->args.push_back(make_args(m.sched, p));
+    std::vector<uint64_t> off;
+    packed_chunk_offsets(m, off);
+    s->payload = dev_alloc(ctx, std::max<size_t>(4, m.payload_words * 4));
+    s->masks = dev_alloc(ctx, std::max<size_t>(4, m.masks.size() * 4));
+    s->chunk_off = dev_alloc(ctx, off.size() * 8);
+    hip_check(ctx, hipMemcpyAsync(s->payload.p, payload, m.payload_words * 4, hipMemcpyHostToDevice, ctx->stream), "upload");
+    hip_check(ctx, hipMemcpyAsync(s->masks.p, m.masks.data(), m.masks.size() * 4, hipMemcpyHostToDevice, ctx->stream), "upload");
+    hip_check(ctx, hipMemcpyAsync(s->chunk_off.p, off.data(), off.size() * 8, hipMemcpyHostToDevice, ctx->stream), "upload");
+    hip_check(ctx, hipStreamSynchronize(ctx->stream), "upload");
+    s->tables = plan_tables(m);
+    upload_outliers(ctx, s);
+  });
+  if (st != IPC_OK) {
+    free_stream_bufs(s);
+    delete s;
+    return st;
+  }
+  *out = s;
+  return IPC_OK;
+}
+
+void ipc_stream_free(ipc_stream *s) {
+  if (!s) return;
+  if (s->ctx) (void)hipStreamSynchronize(s->ctx->stream);
+  free_stream_bufs(s);
+  delete s;
+}
+
+static ipc_status retrieve_common(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &plan,
+                                  double bound, uint32_t flags, float tplan, ipc_state **out,
+                                  ipc_info *info) {
+  ipc_state *stt = new (std::nothrow) ipc_state();
+  if (!stt) return IPC_ENOMEM;
+  stt->ctx = ctx;
+  stt->stream = s;
+  stt->plan = plan;
+  stt->bound = bound;
+  ipc_status st = guarded(ctx, [&] {
+    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    size_t isz = s->meta.dtype == IPC_F32 ? 4 : 8;
+    stt->field = dev_alloc(ctx, size_t(s->meta.sched.n_points) * isz);
+    hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
+    run_retrieve(ctx, s, plan, 0, stt->field.p);
+    hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
+    hip_check(ctx, hipStreamSynchronize(ctx->stream), "retrieve");
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    std::vector<int> none(plan.size(), 32);
+    fill_info(s, plan, bound, flags, plane_bytes_between(s, plan, none), tplan, ms, info);
+  });
+  if (st != IPC_OK) {
+    dev_free(ctx, stt->field);
+    delete stt;
+    return st;
+  }
+  *out = stt;
+  return IPC_OK;
+}
+
+static bool valid_target(ipc_target t) {
+  return (t.kind == IPC_TARGET_EB || t.kind == IPC_TARGET_BITRATE) && std::isfinite(t.value) &&
+         t.value > 0;
+}
+
+ipc_status ipc_retrieve(ipc_ctx *ctx, const ipc_stream *s, ipc_target target, ipc_state **out,
+                        ipc_info *info) {
+  if (!out) return IPC_EINVAL;
+  *out = nullptr;
+  if (!ctx || !s) return IPC_EINVAL;
+  if (s->ctx != ctx) {
+    set_err(ctx, "stream belongs to another context");
+    return IPC_ESTATE;
+  }
+  if (!valid_target(target)) {
+    set_err(ctx, "target value must be finite and > 0");
+    return IPC_EINVAL;
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  PlanResult pr = plan_request(s->tables, target.kind, target.value, nullptr);
+  float tplan = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return retrieve_common(ctx, s, pr.plan, pr.bound, pr.flags, tplan, out, info);
+}
+
+ipc_status ipc_retrieve_plan(ipc_ctx *ctx, const ipc_stream *s, const uint8_t *plan,
+                             uint32_t n_passes, ipc_state **out, ipc_info *info) {
+  if (!out) return IPC_EINVAL;
+  *out = nullptr;
+  if (!ctx || !s || !plan) return IPC_EINVAL;
+  if (s->ctx != ctx) return IPC_ESTATE;
+  if (n_passes != s->args.size()) {
+    set_err(ctx, "plan has the wrong number of passes");
+    return IPC_EINVAL;
+  }
+  std::vector<int> p(n_passes);
+  for (uint32_t i = 0; i < n_passes; ++i) {
+    if (plan[i] > 32 || ((!s->tables.progressive[i]) && plan[i] != 0)) {
+      set_err(ctx, "plan entry out of range");
+      return IPC_EINVAL;
+    }
+    p[i] = plan[i];
+  }
+  double b0 = plan_bound(s->tables, p, s->tables.maxabs);
+  double bound = plan_bound(s->tables, p, 2.0 * (s->tables.maxabs + b0));
+  return retrieve_common(ctx, s, p, bound, 0, 0.0f, out, info);
+}
+
+const void *ipc_state_field(const ipc_state *st) { return st ? st->field.p : nullptr; }
+
+ipc_status ipc_state_copy_field(ipc_ctx *ctx, const ipc_state *st, void *dst_dev,
+                                uint64_t capacity) {
+  if (!ctx || !st || !dst_dev) return IPC_EINVAL;
+  if (st->ctx != ctx) return IPC_ESTATE;
+  uint64_t n = uint64_t(st->stream->meta.sched.n_points) * (st->stream->meta.dtype == IPC_F32 ? 4 : 8);
+  if (capacity < n) {
+    set_err(ctx, "destination too small");
+    return IPC_EINVAL;
+  }
+  return guarded(ctx, [&] {
+    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    hip_check(ctx, hipMemcpyAsync(dst_dev, st->field.p, n, hipMemcpyDeviceToDevice, ctx->stream), "copy");
+    hip_check(ctx, hipStreamSynchronize(ctx->stream), "copy");
+  });
+}
+
+ipc_status ipc_stream_passes(const ipc_stream *s, uint32_t *n_passes) {
+  if (!s || !n_passes) return IPC_EINVAL;
+  *n_passes = uint32_t(s->args.size());
+  return IPC_OK;
+}
+
+ipc_status ipc_refine(ipc_ctx *ctx, ipc_state *st, ipc_target target, ipc_info *info) {
+  if (!ctx || !st) return IPC_EINVAL;
+  if (st->ctx != ctx) {
+    set_err(ctx, "state belongs to another context");
+    return IPC_ESTATE;
+  }
+  if (!valid_target(target)) {
+    set_err(ctx, "target value must be finite and > 0");
+    return IPC_EINVAL;
+  }
+  const ipc_stream *s = st->stream;
+  auto t0 = std::chrono::steady_clock::now();
+  if (target.kind == IPC_TARGET_EB && target.value >= st->bound) {
+    fill_info(s, st->plan, st->bound, IPC_FLAG_NOOP, 0, 0.0f, 0.0f, info);
+    return IPC_OK;
+  }
+  PlanResult pr = plan_request(s->tables, target.kind, target.value, st->plan.data());
+  float tplan = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (pr.plan == st->plan) {
+    fill_info(s, st->plan, st->bound, pr.flags | IPC_FLAG_NOOP, 0, tplan, 0.0f, info);
+    return IPC_OK;
+  }
+  int s_min = -1;
+  for (size_t i = 0; i < pr.plan.size(); ++i)
+    if (pr.plan[i] < st->plan[i]) {
+      s_min = int(i);
+      break;
+    }
+  return guarded(ctx, [&] {
+    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
+    run_retrieve(ctx, s, pr.plan, s_min, st->field.p);
+    hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
+    hip_check(ctx, hipStreamSynchronize(ctx->stream), "refine");
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    uint64_t read = plane_bytes_between(s, pr.plan, st->plan);
+    st->plan = pr.plan;
+    st->bound = pr.bound;
+    fill_info(s, st->plan, st->bound, pr.flags, read, tplan, ms, info);
+  });
+}
+
+void ipc_state_free(ipc_state *st) {
+  if (!st) return;
+  if (st->ctx) (void)hipStreamSynchronize(st->ctx->stream);
+  dev_free(st->ctx, st->field);
+  delete st;
+}
+
+ipc_status ipc_plan_host(const void *stream_bytes, uint64_t nbytes, ipc_target target,
+                         const uint8_t *limit, uint8_t *plan_out, uint32_t plan_capacity,
+                         double *bound_out, uint32_t *flags_out, uint64_t *loaded_out) {
+  if (!stream_bytes || !plan_out) return IPC_EINVAL;
+  if (!valid_target(target)) return IPC_EINVAL;
+  try {
+    StreamMeta m;
+    const uint32_t *payload = nullptr;
+    std::string e;
+    if (!parse_serialized(static_cast<const uint8_t *>(stream_bytes), nbytes, m, &payload, e))
+      return IPC_ECORRUPT;
+    PlanTables t = plan_tables(m);
+    if (plan_capacity < uint32_t(t.P)) return IPC_EINVAL;
+    std::vector<int> lim;
+    if (limit) {
+      lim.resize(t.P);
+      for (int i = 0; i < t.P; ++i) {
+        if (limit[i] > 32) return IPC_EINVAL;
+        lim[i] = t.progressive[i] ? limit[i] : 0;
+      }
+    }
+    PlanResult pr = plan_request(t, target.kind, target.value, limit ? lim.data() : nullptr);
+    for (int i = 0; i < t.P; ++i) plan_out[i] = uint8_t(pr.plan[i]);
+    if (bound_out) *bound_out = pr.bound;
+    if (flags_out) *flags_out = pr.flags;
+    if (loaded_out) *loaded_out = uint64_t(pr.loaded);
+    return IPC_OK;
+  } catch (...) {
+    return IPC_ENOMEM;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+// Kernel launchers of the IPComp library (implemented in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ipc {
+
+// Geometry of one pass, as the kernels see it (3-D padded).
+struct PassArgs {
+  int64_t dims3[3];   // fine extents
+  int64_t ldims[3];   // level-grid extents
+  int64_t tdims[3];   // target-lattice extents
+  int64_t ct[3];      // chunk extent (target coordinates)
+  int64_t tiles[3];   // chunk grid
+  int32_t kinds[3];
+  int32_t dim3;       // pass dimension, -1 for the anchors
+  int64_t h;          // stride in fine coordinates
+  int64_t n_chunks;
+  int64_t chunk_base; // first chunk of the pass in the stream's tables
+  uint64_t slot_base; // first payload word of the pass (slot placement)
+  uint32_t wmax;      // words per plane of a full chunk
+  uint32_t pass_index;
+};
+
+// Everything a compression pass reads or writes besides the field.
+struct CompressOut {
+  uint32_t *payload;     // slot placement: chunk c at slot_base + c*32*wmax
+  uint32_t *masks;       // [n_chunks total]
+  uint32_t *errq;        // [P][33], max-reduced
+  unsigned long long *maxabs_bits;  // max |x^| over finite values, as double bits
+  unsigned long long *n_out;        // outlier counter
+  void *out_recs;        // OutlierRec array
+  unsigned long long out_cap;
+};
+
+struct RetrieveIn {
+  const uint32_t *payload;
+  const uint32_t *masks;
+  const uint64_t *chunk_off;  // packed placement: word offset per chunk (null = slot)
+  const uint64_t *out_gchunk; // outliers sorted by (global chunk, local)
+  const uint32_t *out_local;
+  const uint64_t *out_bits;
+  uint64_t n_out;
+};
+
+hipError_t launch_compress_pass(int dtype, int interp, const PassArgs &pa, const void *x, void *xh,
+                                int write_back, double eb, const CompressOut &o,
+                                hipStream_t stream);
+hipError_t launch_retrieve_pass(int dtype, int interp, const PassArgs &pa, void *field,
+                                int discard, const RetrieveIn &in, double eb, hipStream_t stream);
+// sizes[k] (bytes of plane k summed over the pass's chunks), one pass
+hipError_t launch_pass_sizes(const PassArgs &pa, const uint32_t *masks,
+                             unsigned long long *sizes, hipStream_t stream);
+// copy the stored planes of one pass from slot placement to packed placement
+hipError_t launch_pack_payload(const PassArgs &pa, const uint32_t *masks,
+                               const uint64_t *packed_off, const uint32_t *slot_payload,
+                               uint32_t *packed, hipStream_t stream);
+
+}  // namespace ipc

@@ -1,0 +1,501 @@
+// HIP kernels of the IPComp hot path for gfx950 (CDNA4, wave64).
+//
+// One workgroup handles one chunk of one pass (Sec. 4.1: a pass is one 1-D
+// interpolation sweep of a level; its targets are independent of each other,
+// all their neighbours come from earlier passes).
+//
+//  k_compress: prediction (Eq. interp-linear / interp-cubic) from the working
+//    reconstruction, quantization with the explicit error check and in-place
+//    write-back (Sec. 4.2.2), negabinary + 2-prefix-bit XOR (Sec. 4.4), exact
+//    delta-y per discarded-plane count (Thm. 1), chunk plane mask, and an
+//    in-register 32x32 bit transpose that turns 32 codes into 32 plane words
+//    (Sec. 4.3), stored at the chunk's fixed slot.
+//  k_retrieve: the inverse (Alg. 1): gather the loaded plane words, transpose
+//    back, undo the XOR code and negabinary, dequantize on top of the same
+//    prediction, and put the exactly stored outliers back.
+//
+// Arithmetic: one IEEE rounding per operation in the field's dtype through the
+// *_rn intrinsics (no contraction), round-half-even quantization, the error
+// check in double.  This is what makes the result bit-identical to a plain CPU
+// evaluation of the same formulas.
+#include "kernels.h"
+
+#include "ipc_internal.h"
+
+namespace ipc {
+namespace {
+
+constexpr uint32_t NB_A = 0xAAAAAAAAu;
+constexpr int WG = 256;
+constexpr int MAXC = int(MAX_CHUNK_CODES);
+constexpr int LDS_WORDS = MAXC + MAXC / 32;
+
+__device__ __forceinline__ int lds_idx(int j) { return j + (j >> 5); }
+
+template <typename T>
+struct FP;
+template <>
+struct FP<float> {
+  static __device__ __forceinline__ float add(float a, float b) { return __fadd_rn(a, b); }
+  static __device__ __forceinline__ float sub(float a, float b) { return __fsub_rn(a, b); }
+  static __device__ __forceinline__ float mul(float a, float b) { return __fmul_rn(a, b); }
+  static __device__ __forceinline__ float rnd(float a) { return __builtin_rintf(a); }
+  static __device__ __forceinline__ uint64_t bits(float a) { return __float_as_uint(a); }
+  static __device__ __forceinline__ float from_bits(uint64_t b) { return __uint_as_float(uint32_t(b)); }
+};
+template <>
+struct FP<double> {
+  static __device__ __forceinline__ double add(double a, double b) { return __dadd_rn(a, b); }
+  static __device__ __forceinline__ double sub(double a, double b) { return __dsub_rn(a, b); }
+  static __device__ __forceinline__ double mul(double a, double b) { return __dmul_rn(a, b); }
+  static __device__ __forceinline__ double rnd(double a) { return __builtin_rint(a); }
+  static __device__ __forceinline__ uint64_t bits(double a) { return uint64_t(__double_as_longlong(a)); }
+  static __device__ __forceinline__ double from_bits(uint64_t b) { return __longlong_as_double((long long)b); }
+};
+
+// Transpose a 32x32 bit matrix held as 32 words: afterwards bit j of a[k]
+// is what bit k of a[j] was.  Five block-swap stages (16, 8, 4, 2, 1).
+__device__ __forceinline__ void transpose32(uint32_t a[32]) {
+  uint32_t m = 0x0000FFFFu;
+#pragma unroll
+  for (int j = 16; j != 0; j >>= 1, m ^= (m << j)) {
+#pragma unroll
+    for (int k = 0; k < 32; k = ((k | j) + 1) & ~j) {
+      uint32_t t = ((a[k] >> j) ^ a[k | j]) & m;
+      a[k] ^= t << j;
+      a[k | j] ^= t;
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t xor_encode(uint32_t v) { return v ^ (v >> 1) ^ (v >> 2); }
+
+// (1 + x + x^2)^-1 = (1 + x)(1 + x^3)(1 + x^6)(1 + x^12)(1 + x^24) over GF(2)
+__device__ __forceinline__ uint32_t xor_decode(uint32_t e) {
+  uint32_t t = e ^ (e >> 1);
+  t ^= t >> 3;
+  t ^= t >> 6;
+  t ^= t >> 12;
+  t ^= t >> 24;
+  return t;
+}
+
+struct ChunkGeo {
+  int32_t e[3];
+  int64_t m0[3];
+  int32_t count;
+};
+
+__device__ __forceinline__ ChunkGeo chunk_geo(const PassArgs &a, int64_t c) {
+  ChunkGeo g;
+  int64_t t2 = c % a.tiles[2];
+  int64_t r = c / a.tiles[2];
+  int64_t t1 = r % a.tiles[1];
+  int64_t t0 = r / a.tiles[1];
+  int64_t t[3] = {t0, t1, t2};
+  int32_t cnt = 1;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    int64_t base = t[j] * a.ct[j];
+    int64_t e = a.tdims[j] - base;
+    if (e > a.ct[j]) e = a.ct[j];
+    if (e < 0) e = 0;
+    g.e[j] = int32_t(e);
+    g.m0[j] = base;
+    cnt *= int32_t(e);
+  }
+  g.count = cnt;
+  return g;
+}
+
+__device__ __forceinline__ int64_t level_coord(int64_t m, int kind) {
+  return kind == KIND_ANY ? m : (kind == KIND_ODD ? 2 * m + 1 : 2 * m);
+}
+
+// level coordinates and fine linear index of code j of a chunk
+__device__ __forceinline__ int64_t code_position(const PassArgs &a, const ChunkGeo &g, int j,
+                                                 int64_t lev[3]) {
+  int o2 = j % g.e[2];
+  int r = j / g.e[2];
+  int o1 = r % g.e[1];
+  int o0 = r / g.e[1];
+  lev[0] = level_coord(g.m0[0] + o0, a.kinds[0]);
+  lev[1] = level_coord(g.m0[1] + o1, a.kinds[1]);
+  lev[2] = level_coord(g.m0[2] + o2, a.kinds[2]);
+  return ((a.h * lev[0]) * a.dims3[1] + a.h * lev[1]) * a.dims3[2] + a.h * lev[2];
+}
+
+__device__ __forceinline__ int64_t pass_stride(const PassArgs &a) {
+  if (a.dim3 == 0) return a.h * a.dims3[1] * a.dims3[2];
+  if (a.dim3 == 1) return a.h * a.dims3[2];
+  return a.h;
+}
+
+// Prediction along the pass dimension from level neighbours -+1, -+3.
+template <typename T, int INTERP>
+__device__ __forceinline__ T predict(const T *w, int64_t idx, int64_t st, int64_t t, int64_t L) {
+  using F = FP<T>;
+  T b = w[idx - st];
+  if (t + 1 >= L) return b;
+  T c = w[idx + st];
+  if (INTERP == IPC_LINEAR) return F::mul(F::add(b, c), T(0.5));
+  bool ha = t >= 3;
+  bool he = t + 3 < L;
+  if (ha && he) {
+    T a = w[idx - 3 * st];
+    T e = w[idx + 3 * st];
+    return F::mul(F::sub(F::mul(F::add(b, c), T(9.0)), F::add(a, e)), T(0.0625));
+  }
+  if (he) {
+    T e = w[idx + 3 * st];
+    return F::mul(F::sub(F::add(F::mul(b, T(3.0)), F::mul(c, T(6.0))), e), T(0.125));
+  }
+  if (ha) {
+    T a = w[idx - 3 * st];
+    return F::mul(F::sub(F::add(F::mul(c, T(3.0)), F::mul(b, T(6.0))), a), T(0.125));
+  }
+  return F::mul(F::add(b, c), T(0.5));
+}
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    uint32_t u = __shfl_xor(v, o, 64);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+__device__ __forceinline__ unsigned long long wave_max64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long u = __shfl_xor(v, o, 64);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+
+template <typename T, int INTERP>
+__global__ __launch_bounds__(WG) void k_compress(PassArgs a, const T *__restrict__ x, T *xh,
+                                                  int write_back, double eb, T two_eb, T inv,
+                                                  T qmax, CompressOut o) {
+  using F = FP<T>;
+  __shared__ uint32_t s_v[LDS_WORDS];
+  __shared__ uint32_t s_or_e, s_or_v, s_qmax;
+  __shared__ uint32_t s_errq[33];
+  __shared__ unsigned long long s_maxabs;
+
+  const int64_t c = blockIdx.x;
+  const int tid = threadIdx.x;
+  const ChunkGeo g = chunk_geo(a, c);
+  const int count = g.count;
+  uint32_t *mask_out = o.masks + a.chunk_base + c;
+  if (count == 0) {
+    if (tid == 0) *mask_out = 0;
+    return;
+  }
+  if (tid == 0) {
+    s_or_e = 0;
+    s_or_v = 0;
+    s_qmax = 0;
+    s_maxabs = 0;
+  }
+  if (tid < 33) s_errq[tid] = 0;
+  __syncthreads();
+
+  const int64_t st = pass_stride(a);
+  const int pd = a.dim3;
+  uint32_t or_e = 0, or_v = 0, qabs = 0;
+  unsigned long long mx = 0;
+  for (int j = tid; j < count; j += WG) {
+    int64_t lev[3];
+    int64_t idx = code_position(a, g, j, lev);
+    T xv = x[idx];
+    T pred;
+    if (pd < 0)
+      pred = T(0);
+    else
+      pred = predict<T, INTERP>(xh, idx, st, lev[pd], a.ldims[pd]);
+    T diff = F::sub(xv, pred);
+    T qf = F::rnd(F::mul(diff, inv));
+    bool out = !(fabs(qf) <= qmax);
+    int32_t q = out ? 0 : int32_t(qf);
+    T xr = F::add(pred, F::mul(T(q), two_eb));
+    if (!out) out = !(fabs(__dsub_rn(double(xr), double(xv))) <= eb);
+    T xhat = xr;
+    if (out) {
+      q = 0;
+      xhat = xv;
+      unsigned long long slot = atomicAdd(o.n_out, 1ull);
+      if (slot < o.out_cap) {
+        OutlierRec *r = reinterpret_cast<OutlierRec *>(o.out_recs) + slot;
+        r->pass = a.pass_index;
+        r->chunk = uint32_t(c);
+        r->local = uint32_t(j);
+        r->pad = 0;
+        r->bits = F::bits(xv);
+      }
+    }
+    if (write_back) xh[idx] = xhat;
+    uint32_t v = (uint32_t(q) + NB_A) ^ NB_A;
+    s_v[lds_idx(j)] = v;
+    or_v |= v;
+    or_e |= xor_encode(v);
+    uint32_t aq = q < 0 ? uint32_t(-int64_t(q)) : uint32_t(q);
+    qabs = aq > qabs ? aq : qabs;
+    double ax = fabs(double(xhat));
+    if (ax <= 1.7976931348623157e308) {
+      unsigned long long bx = (unsigned long long)__double_as_longlong(ax);
+      mx = bx > mx ? bx : mx;
+    }
+  }
+  or_e = wave_or(or_e);
+  or_v = wave_or(or_v);
+  qabs = wave_max(qabs);
+  mx = wave_max64(mx);
+  if ((tid & 63) == 0) {
+    atomicOr(&s_or_e, or_e);
+    atomicOr(&s_or_v, or_v);
+    atomicMax(&s_qmax, qabs);
+    atomicMax(&s_maxabs, mx);
+  }
+  __syncthreads();
+  const uint32_t mask = s_or_e;
+  const uint32_t orv = s_or_v;
+  const int nb = orv ? 32 - __clz(orv) : 0;  // significant negabinary digits in the chunk
+
+  // delta-y: |q - q'_b| = |(w & M_b) - (A & M_b)| with w = v xor A, M_b = 2^b - 1
+  if (nb > 1) {
+    uint32_t acc[32];
+#pragma unroll
+    for (int b = 0; b < 32; ++b) acc[b] = 0;
+    for (int j = tid; j < count; j += WG) {
+      uint32_t w = s_v[lds_idx(j)] ^ NB_A;
+#pragma unroll
+      for (int b = 1; b < 32; ++b) {
+        if (b < nb) {
+          uint32_t m = (1u << b) - 1u;
+          uint32_t d = __usad(w & m, NB_A & m, 0u);
+          acc[b] = d > acc[b] ? d : acc[b];
+        }
+      }
+    }
+#pragma unroll
+    for (int b = 1; b < 32; ++b) {
+      if (b < nb) {
+        uint32_t r = wave_max(acc[b]);
+        if ((tid & 63) == 0) atomicMax(&s_errq[b], r);
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < 33 && tid > 0) {
+    uint32_t val = tid < nb ? s_errq[tid] : s_qmax;
+    uint32_t *dst = o.errq + size_t(a.pass_index) * 33 + tid;
+    if (val > *dst) atomicMax(dst, val);
+  }
+  if (tid == 0) {
+    *mask_out = mask;
+    if (s_maxabs > *o.maxabs_bits) atomicMax(o.maxabs_bits, s_maxabs);
+  }
+
+  // planes: thread per word, 32 codes -> 32 plane words
+  const int W = (count + 31) >> 5;
+  uint32_t *slot = o.payload + a.slot_base + uint64_t(c) * 32u * a.wmax;
+  for (int w = tid; w < W; w += WG) {
+    uint32_t r[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      int jj = 32 * w + j;
+      uint32_t v = jj < count ? s_v[lds_idx(jj)] : 0u;
+      r[j] = xor_encode(v);
+    }
+    transpose32(r);
+#pragma unroll
+    for (int k = 0; k < 32; ++k)
+      if ((mask >> k) & 1u) slot[size_t(31 - k) * W + w] = r[k];
+  }
+}
+
+template <typename T, int INTERP>
+__global__ __launch_bounds__(WG) void k_retrieve(PassArgs a, T *f, int discard, RetrieveIn in,
+                                                  T two_eb) {
+  using F = FP<T>;
+  __shared__ uint32_t s_v[LDS_WORDS];
+  __shared__ uint64_t s_lo, s_hi;
+  const int64_t c = blockIdx.x;
+  const int tid = threadIdx.x;
+  const ChunkGeo g = chunk_geo(a, c);
+  const int count = g.count;
+  if (count == 0) return;
+  const int64_t gc = a.chunk_base + c;
+  const uint32_t mask = in.masks[gc];
+  const uint32_t keep = discard >= 32 ? 0u : (0xFFFFFFFFu << discard);
+  const uint32_t load = mask & keep;
+  const int W = (count + 31) >> 5;
+  const bool packed = in.chunk_off != nullptr;
+  const uint64_t off = packed ? in.chunk_off[gc] : a.slot_base + uint64_t(c) * 32u * a.wmax;
+  for (int w = tid; w < W; w += WG) {
+    uint32_t r[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      uint32_t rank = packed ? uint32_t(__popc(k == 31 ? 0u : (mask >> (k + 1)))) : uint32_t(31 - k);
+      r[k] = ((load >> k) & 1u) ? in.payload[off + uint64_t(rank) * W + w] : 0u;
+    }
+    transpose32(r);
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      int jj = 32 * w + j;
+      if (jj < count) s_v[lds_idx(jj)] = xor_decode(r[j]) & keep;
+    }
+  }
+  if (tid == 0) {
+    uint64_t lo = 0, hi = in.n_out;
+    // first outlier with chunk >= gc
+    uint64_t a0 = 0, a1 = in.n_out;
+    while (a0 < a1) {
+      uint64_t m = (a0 + a1) >> 1;
+      if (in.out_gchunk[m] < uint64_t(gc)) a0 = m + 1; else a1 = m;
+    }
+    lo = a0;
+    a1 = in.n_out;
+    while (a0 < a1) {
+      uint64_t m = (a0 + a1) >> 1;
+      if (in.out_gchunk[m] <= uint64_t(gc)) a0 = m + 1; else a1 = m;
+    }
+    hi = a0;
+    s_lo = lo;
+    s_hi = hi;
+  }
+  __syncthreads();
+  const uint64_t olo = s_lo, ohi = s_hi;
+  const int64_t st = pass_stride(a);
+  const int pd = a.dim3;
+  for (int j = tid; j < count; j += WG) {
+    int64_t lev[3];
+    int64_t idx = code_position(a, g, j, lev);
+    uint32_t v = s_v[lds_idx(j)];
+    int64_t q = int64_t(v ^ NB_A) - int64_t(NB_A);
+    T pred;
+    if (pd < 0)
+      pred = T(0);
+    else
+      pred = predict<T, INTERP>(f, idx, st, lev[pd], a.ldims[pd]);
+    // float32 codes have at most 26 negabinary digits, so q fits in int32
+    T tq = sizeof(T) == 4 ? T(int32_t(q)) : T(q);
+    T val = F::add(pred, F::mul(tq, two_eb));
+    if (ohi > olo) {
+      uint64_t b0 = olo, b1 = ohi;
+      while (b0 < b1) {
+        uint64_t m = (b0 + b1) >> 1;
+        if (in.out_local[m] < uint32_t(j)) b0 = m + 1; else b1 = m;
+      }
+      if (b0 < ohi && in.out_local[b0] == uint32_t(j)) val = F::from_bits(in.out_bits[b0]);
+    }
+    f[idx] = val;
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_pass_sizes(PassArgs a, const uint32_t *masks,
+                                                    unsigned long long *sizes) {
+  __shared__ unsigned long long s_acc;
+  const int k = blockIdx.x;
+  if (threadIdx.x == 0) s_acc = 0;
+  __syncthreads();
+  unsigned long long acc = 0;
+  for (int64_t c = threadIdx.x; c < a.n_chunks; c += WG) {
+    uint32_t mk = masks[a.chunk_base + c];
+    if ((mk >> k) & 1u) {
+      ChunkGeo g = chunk_geo(a, c);
+      acc += 4ull * uint64_t((g.count + 31) >> 5);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(&s_acc, acc);
+  __syncthreads();
+  if (threadIdx.x == 0) sizes[k] = s_acc;
+}
+
+__global__ __launch_bounds__(WG) void k_pack(PassArgs a, const uint32_t *masks,
+                                              const uint64_t *packed_off,
+                                              const uint32_t *slot_payload, uint32_t *packed) {
+  const int64_t c = blockIdx.x;
+  const int64_t gc = a.chunk_base + c;
+  const uint32_t mask = masks[gc];
+  if (!mask) return;
+  const ChunkGeo g = chunk_geo(a, c);
+  const int W = (g.count + 31) >> 5;
+  const uint32_t *src = slot_payload + a.slot_base + uint64_t(c) * 32u * a.wmax;
+  uint32_t *dst = packed + packed_off[gc];
+  int rank = 0;
+  for (int k = 31; k >= 0; --k) {
+    if (!((mask >> k) & 1u)) continue;
+    for (int w = threadIdx.x; w < W; w += WG) dst[size_t(rank) * W + w] = src[size_t(31 - k) * W + w];
+    ++rank;
+  }
+}
+
+template <typename T, int INTERP>
+hipError_t launch_c(const PassArgs &pa, const void *x, void *xh, int wb, double eb,
+                    const CompressOut &o, hipStream_t s) {
+  T two_eb = T(2.0 * eb);
+  T inv = T(1.0 / (2.0 * eb));
+  T qmax = T(sizeof(T) == 4 ? QMAX_F32 : QMAX_F64);
+  if (pa.n_chunks == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_compress<T, INTERP>), dim3(uint32_t(pa.n_chunks)), dim3(WG), 0, s, pa,
+                     static_cast<const T *>(x), static_cast<T *>(xh), wb, eb, two_eb, inv, qmax, o);
+  return hipGetLastError();
+}
+
+template <typename T, int INTERP>
+hipError_t launch_r(const PassArgs &pa, void *f, int discard, const RetrieveIn &in, double eb,
+                    hipStream_t s) {
+  T two_eb = T(2.0 * eb);
+  if (pa.n_chunks == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_retrieve<T, INTERP>), dim3(uint32_t(pa.n_chunks)), dim3(WG), 0, s, pa,
+                     static_cast<T *>(f), discard, in, two_eb);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_compress_pass(int dtype, int interp, const PassArgs &pa, const void *x, void *xh,
+                                int write_back, double eb, const CompressOut &o,
+                                hipStream_t stream) {
+  if (dtype == IPC_F32)
+    return interp == IPC_LINEAR ? launch_c<float, IPC_LINEAR>(pa, x, xh, write_back, eb, o, stream)
+                                : launch_c<float, IPC_CUBIC>(pa, x, xh, write_back, eb, o, stream);
+  return interp == IPC_LINEAR ? launch_c<double, IPC_LINEAR>(pa, x, xh, write_back, eb, o, stream)
+                              : launch_c<double, IPC_CUBIC>(pa, x, xh, write_back, eb, o, stream);
+}
+
+hipError_t launch_retrieve_pass(int dtype, int interp, const PassArgs &pa, void *field,
+                                int discard, const RetrieveIn &in, double eb, hipStream_t stream) {
+  if (dtype == IPC_F32)
+    return interp == IPC_LINEAR ? launch_r<float, IPC_LINEAR>(pa, field, discard, in, eb, stream)
+                                : launch_r<float, IPC_CUBIC>(pa, field, discard, in, eb, stream);
+  return interp == IPC_LINEAR ? launch_r<double, IPC_LINEAR>(pa, field, discard, in, eb, stream)
+                              : launch_r<double, IPC_CUBIC>(pa, field, discard, in, eb, stream);
+}
+
+hipError_t launch_pass_sizes(const PassArgs &pa, const uint32_t *masks, unsigned long long *sizes,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(k_pass_sizes, dim3(32), dim3(WG), 0, stream, pa, masks, sizes);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_payload(const PassArgs &pa, const uint32_t *masks,
+                               const uint64_t *packed_off, const uint32_t *slot_payload,
+                               uint32_t *packed, hipStream_t stream) {
+  if (pa.n_chunks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack, dim3(uint32_t(pa.n_chunks)), dim3(WG), 0, stream, pa, masks,
+                     packed_off, slot_payload, packed);
+  return hipGetLastError();
+}
+
+}  // namespace ipc

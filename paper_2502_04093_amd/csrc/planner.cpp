@@ -1,0 +1,246 @@
+// Loading planner: the error bound of a partial load (Thm. 1) and the two
+// knapsack dynamic programs of Sec. 5.2 (least data for an error bound) and
+// Sec. 5.3 (least error for a byte budget).
+//
+// Readings used:
+//  * Groups are passes (one per level and dimension).  Loss delta_s of pass s
+//    reaches the final reconstruction through at most S - s later predictions,
+//    each of infinity norm p (1 linear, 1.25 cubic): A_s = p^(S - s).
+//  * delta_s(b) = errq[s][b] * T(2 eb), errq being the exact max code loss.
+//  * Rounding of a reconstruction computed in the field's dtype from truncated
+//    codes: each lossy pass s is charged T_s * r with T_s = sum_{s'>=s} A_s'
+//    and r = 14 u M (u unit roundoff, M bounds the magnitudes: maxabs + E in
+//    error-bound mode; maxabs while planning a bitrate, 2 (maxabs + B0) when
+//    reporting its bound).
+//  * Error budget in 1024 units of (E - eb); cost floor(term / unit) + 1 for a
+//    non-zero term.  Byte budget in at most 1024 units, costs rounded up.  Ties
+//    go to the smallest number of discarded planes, last pass first.
+#include "ipc_internal.h"
+
+#include <cmath>
+#include <limits>
+
+namespace ipc {
+
+static constexpr int G_UNITS = 1024;
+
+static double rounding_step(const PlanTables &t, double M) { return 14.0 * t.unit_roundoff * M; }
+
+static double term(const PlanTables &t, int s, int b, double r) {
+  double v = (double(t.errq[size_t(s) * 33 + b]) * t.two_eb) * t.amp[s];
+  if (b > 0) v = v + t.tail[s] * r;
+  return v;
+}
+
+double plan_bound(const PlanTables &t, const std::vector<int> &plan, double M) {
+  double r = rounding_step(t, M);
+  double tot = t.eb;
+  for (int s = 0; s < t.P; ++s)
+    if (t.progressive[s]) tot = tot + term(t, s, plan[s], r);
+  return tot;
+}
+
+int64_t plan_loaded(const PlanTables &t, const std::vector<int> &plan) {
+  int64_t tot = t.fixed_bytes;
+  for (int s = 0; s < t.P; ++s)
+    if (t.progressive[s])
+      for (int k = plan[s]; k < 32; ++k) tot += t.sizes[size_t(s) * 32 + k];
+  return tot;
+}
+
+static int allowed_hi(const PlanTables &t, int s, const int *limit) {
+  if (!t.progressive[s]) return 0;
+  return limit ? limit[s] : 32;
+}
+
+static PlanResult plan_eb(const PlanTables &t, double E, const int *limit) {
+  PlanResult res;
+  const int P = t.P;
+  res.plan.assign(P, 0);
+  double R = E - t.eb;
+  if (!(R >= 0.0)) {
+    res.flags = IPC_FLAG_CLAMPED_TO_EB;
+    return res;
+  }
+  double r = rounding_step(t, t.maxabs + E);
+  double u = R / G_UNITS;
+  const int64_t NEG = std::numeric_limits<int64_t>::min() / 4;
+  std::vector<int64_t> F(G_UNITS + 1, 0), nF(G_UNITS + 1);
+  std::vector<uint8_t> choice(size_t(P) * (G_UNITS + 1), 0);
+  std::vector<int> cost(size_t(P) * 33, 0);
+  for (int s = 0; s < P; ++s) {
+    std::fill(nF.begin(), nF.end(), NEG);
+    uint8_t *ch = &choice[size_t(s) * (G_UNITS + 1)];
+    int hi = allowed_hi(t, s, limit);
+    int64_t saved = 0;
+    for (int b = 0; b <= hi; ++b) {
+      if (b > 0 && t.progressive[s]) saved += t.sizes[size_t(s) * 32 + (b - 1)];
+      double tv = t.progressive[s] ? term(t, s, b, r) : 0.0;
+      int c;
+      if (tv == 0.0) {
+        c = 0;
+      } else {
+        double qv = u > 0.0 ? tv / u : std::numeric_limits<double>::infinity();
+        c = (qv < double(G_UNITS)) ? int(std::floor(qv)) + 1 : G_UNITS + 1;
+      }
+      cost[size_t(s) * 33 + b] = c;
+      if (c > G_UNITS) continue;
+      int64_t sv = t.progressive[s] ? saved : 0;
+      for (int rr = c; rr <= G_UNITS; ++rr) {
+        int64_t prev = F[rr - c];
+        if (prev == NEG) continue;
+        int64_t cand = prev + sv;
+        if (cand > nF[rr]) {
+          nF[rr] = cand;
+          ch[rr] = uint8_t(b);
+        }
+      }
+    }
+    F.swap(nF);
+  }
+  int rr = G_UNITS;
+  for (int s = P - 1; s >= 0; --s) {
+    int b = choice[size_t(s) * (G_UNITS + 1) + rr];
+    res.plan[s] = b;
+    rr -= cost[size_t(s) * 33 + b];
+  }
+  return res;
+}
+
+static PlanResult plan_br(const PlanTables &t, double bitrate, const int *limit) {
+  PlanResult res;
+  const int P = t.P;
+  res.plan.assign(P, 0);
+  double bt = bitrate * double(t.n_points) / 8.0;
+  if (bt >= double(t.total_bytes)) return res;  // everything fits
+  int64_t budget = int64_t(std::floor(bt)) - t.fixed_bytes;
+  if (limit) {
+    std::vector<int> cur(limit, limit + P);
+    if (budget < plan_loaded(t, cur) - t.fixed_bytes) {
+      res.plan = cur;
+      res.flags = IPC_FLAG_NOOP;
+      return res;
+    }
+  }
+  if (budget < 0) {
+    for (int s = 0; s < P; ++s)
+      if (t.progressive[s]) res.plan[s] = 32;
+    res.flags = IPC_FLAG_BUDGET_BELOW_MIN;
+    return res;
+  }
+  int64_t ub = std::max<int64_t>(1, (budget + G_UNITS - 1) / G_UNITS);
+  int64_t cap = budget / ub;
+  double r = rounding_step(t, t.maxabs);
+  const double INF = std::numeric_limits<double>::infinity();
+  std::vector<double> F(cap + 1, 0.0), nF(cap + 1);
+  std::vector<uint8_t> choice(size_t(P) * (cap + 1), 0);
+  std::vector<int64_t> lcs(size_t(P) * 33, 0);
+  for (int s = 0; s < P; ++s) {
+    std::fill(nF.begin(), nF.end(), INF);
+    uint8_t *ch = &choice[size_t(s) * (cap + 1)];
+    int hi = allowed_hi(t, s, limit);
+    for (int b = 0; b <= hi; ++b) {
+      int64_t lc = 0;
+      double tv = 0.0;
+      if (t.progressive[s]) {
+        int64_t load = 0;
+        for (int k = b; k < 32; ++k) load += t.sizes[size_t(s) * 32 + k];
+        lc = (load + ub - 1) / ub;
+        tv = term(t, s, b, r);
+      }
+      lcs[size_t(s) * 33 + b] = lc;
+      if (lc > cap) continue;
+      for (int64_t rr = lc; rr <= cap; ++rr) {
+        double cand = F[rr - lc] + tv;
+        if (cand < nF[rr]) {
+          nF[rr] = cand;
+          ch[rr] = uint8_t(b);
+        }
+      }
+    }
+    F.swap(nF);
+  }
+  if (!std::isfinite(F[cap])) {
+    res.plan.assign(limit, limit + P);
+    res.flags = IPC_FLAG_NOOP;
+    return res;
+  }
+  int64_t rr = cap;
+  for (int s = P - 1; s >= 0; --s) {
+    int b = choice[size_t(s) * (cap + 1) + rr];
+    res.plan[s] = b;
+    rr -= lcs[size_t(s) * 33 + b];
+  }
+  return res;
+}
+
+PlanResult plan_request(const PlanTables &t, int mode, double value, const int *limit) {
+  PlanResult res;
+  if (mode == IPC_TARGET_EB) {
+    res = plan_eb(t, value, limit);
+    if (value < t.eb)
+      res.bound = plan_bound(t, res.plan, t.maxabs);
+    else
+      res.bound = plan_bound(t, res.plan, t.maxabs + value);
+  } else {
+    res = plan_br(t, value, limit);
+    double b0 = plan_bound(t, res.plan, t.maxabs);
+    res.bound = plan_bound(t, res.plan, 2.0 * (t.maxabs + b0));
+  }
+  res.loaded = plan_loaded(t, res.plan);
+  return res;
+}
+
+PlanTables plan_tables_from_sizes(const StreamMeta &m, const std::vector<uint64_t> &sizes) {
+  PlanTables t;
+  const Schedule &s = m.sched;
+  t.P = int(s.passes.size());
+  t.errq = m.errq;
+  t.sizes.assign(sizes.begin(), sizes.end());
+  t.progressive.assign(t.P, 1);
+  t.progressive[0] = 0;
+  for (const PassGeom &p : s.passes)
+    if (p.index > 0 && p.level > s.K - m.nonprog_levels) t.progressive[p.index] = 0;
+  double pval = m.interp == IPC_LINEAR ? 1.0 : 1.25;
+  t.amp.assign(t.P, 0.0);
+  t.tail.assign(t.P, 0.0);
+  double a = 1.0, tt = 0.0;
+  for (int s2 = t.P - 1; s2 >= 1; --s2) {
+    t.amp[s2] = a;
+    tt = tt + a;
+    t.tail[s2] = tt;
+    a = a * pval;
+  }
+  if (m.dtype == IPC_F32)
+    t.two_eb = double(float(2.0 * m.eb));
+  else
+    t.two_eb = 2.0 * m.eb;
+  t.eb = m.eb;
+  t.unit_roundoff = m.dtype == IPC_F32 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
+  t.maxabs = m.maxabs;
+  t.n_points = s.n_points;
+  t.total_bytes = int64_t(m.serialized_bytes);
+  int64_t prog = 0;
+  for (int s2 = 0; s2 < t.P; ++s2)
+    if (t.progressive[s2])
+      for (int k = 0; k < 32; ++k) prog += t.sizes[size_t(s2) * 32 + k];
+  t.fixed_bytes = t.total_bytes - prog;
+  return t;
+}
+
+PlanTables plan_tables(const StreamMeta &m) {
+  const Schedule &s = m.sched;
+  std::vector<uint64_t> sizes(s.passes.size() * 32, 0);
+  for (const PassGeom &p : s.passes) {
+    for (int64_t c = 0; c < p.n_chunks; ++c) {
+      uint32_t mk = m.masks[size_t(p.chunk_base + c)];
+      if (!mk) continue;
+      uint64_t W = uint64_t((chunk_count(p, c) + 31) / 32);
+      for (int k = 0; k < 32; ++k)
+        if ((mk >> k) & 1u) sizes[size_t(p.index) * 32 + k] += 4 * W;
+    }
+  }
+  return plan_tables_from_sizes(m, sizes);
+}
+
+}  // namespace ipc

@@ -102,7 +102,8 @@ def _exhaustive_eb(t, E, limit=None):
         opts = []
         for b in planner._allowed(t, s, limit):
             tv = planner.term(t, s, b, r) if t.progressive[s] else 0.0
-            c = 0 if tv == 0.0 else (int(np.floor(tv / u)) + 1 if u > 0 else planner.G_UNITS + 1)
+            qv = tv / u if u > 0 else np.inf
+            c = 0 if tv == 0.0 else (int(np.floor(qv)) + 1 if qv < planner.G_UNITS else planner.G_UNITS + 1)
             if c > planner.G_UNITS:
                 continue
             saved = int(np.sum(t.sizes[s, :b])) if t.progressive[s] else 0
@@ -123,7 +124,10 @@ def _exhaustive_eb(t, E, limit=None):
 
 
 def _exhaustive_br(t, bitrate):
-    budget = int(np.floor(bitrate * t.n_points / 8.0)) - t.fixed_bytes
+    bt = bitrate * t.n_points / 8.0
+    if bt >= t.total_bytes:
+        return (0.0, [0] * t.n_passes)
+    budget = int(np.floor(bt)) - t.fixed_bytes
     ub = max(1, -(-budget // planner.G_UNITS))
     cap = budget // ub
     r = planner.rounding_step(t, t.maxabs)
