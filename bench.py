@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Throughput of the IPComp hot path on one MI355X.
+
+One step = one compress of the whole field plus one retrieval of it at the
+compression bound (every plane loaded), both through the C ABI, with the field
+resident in HBM.  The default workload is the 512^3 float32 Gaussian random
+field with a k^-5/3 power spectrum (turbulence-like, unit variance), cubic
+interpolation, absolute error bound 1e-4 * (max - min).
+
+Printed (one JSON line): value = input GB (10^9 bytes of float32) per second
+through compress + retrieve (n * 4 / ms_per_step), the two halves separately,
+p50/p99 host latency of a retrieval call, the roofline of the dominant kernel
+(measured with HIP events on the library's stream) and the oracle timed on a
+bounded sample of the same field on the host CPU.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--shape", type=int, nargs="+", default=[512, 512, 512])
+    ap.add_argument("--interp", choices=["linear", "cubic"], default="cubic")
+    ap.add_argument("--rel-eb", type=float, default=1e-4)
+    ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--latency-calls", type=int, default=50)
+    ap.add_argument("--cpu-sample", type=int, default=384,
+                    help="edge of the cubic sub-block the oracle compresses and retrieves")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    return ap.parse_args()
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "independent fields would shard across GPUs with no exchange, see DESIGN.md",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import fieldgen
+    import paper_2502_04093_amd as pkg
+
+    dev = "cuda:0"
+    shape = tuple(args.shape)
+    n = int(np.prod(shape))
+    print(f"[bench] generating {shape} field on {dev}", file=sys.stderr, flush=True)
+    x = fieldgen.grf_torch(shape, -5.0 / 6.0, args.seed, device=dev)
+    if args.dtype == "f64":
+        x = x.double()
+    itemsize = x.element_size()
+    rng = float(x.max().double() - x.min().double())
+    eb = args.rel_eb * rng
+    ctx = pkg.Context(0)
+
+    def step():
+        t0 = time.perf_counter()
+        s = ctx.compress(x, eb, interp=args.interp)
+        t1 = time.perf_counter()
+        st = s.retrieve(eb=eb)
+        t2 = time.perf_counter()
+        return s, st, t1 - t0, t2 - t1
+
+    # warm-up (code objects load on the first call); the last warm-up step
+    # times every launch to find the dominant kernel
+    for _ in range(max(1, args.warmup) - 1):
+        s, st, _, _ = step()
+        st.free()
+        s.free()
+    ctx.set_profiling(True, -1)
+    s = ctx.compress(x, eb, interp=args.interp)
+    c_ms = ctx.pass_times()
+    st = s.retrieve(eb=eb)
+    r_ms = ctx.pass_times()
+    P = s.n_passes
+    pinfo = [s.pass_info(i) for i in range(P)]
+    stream_bytes = s.nbytes
+    st.free()
+    s.free()
+    ctx.set_profiling(False)
+    launches = sorted({p["launch_pass"] for p in pinfo})
+    dom_op, dom_pass = max([("compress", i) for i in launches] + [("retrieve", i) for i in launches],
+                           key=lambda k: (c_ms if k[0] == "compress" else r_ms)[k[1]])
+
+    # timed region; only the dominant pass is bracketed by events
+    ctx.set_profiling(True, dom_pass)
+    torch.cuda.synchronize()
+    tc = tr = 0.0
+    dom_c = []
+    dom_r = []
+    T0 = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        s = ctx.compress(x, eb, interp=args.interp)
+        dom_c.append(ctx.pass_times()[dom_pass])
+        t1 = time.perf_counter()
+        st = s.retrieve(eb=eb)
+        dom_r.append(ctx.pass_times()[dom_pass])
+        t2 = time.perf_counter()
+        tc += t1 - t0
+        tr += t2 - t1
+        st.free()
+        s.free()
+    torch.cuda.synchronize()
+    T1 = time.perf_counter()
+    ctx.set_profiling(False)
+    ms_per_step = (T1 - T0) * 1e3 / args.steps
+    gb = n * itemsize / 1e9
+
+    # retrieval latency
+    s = ctx.compress(x, eb, interp=args.interp)
+    lat = []
+    L = args.latency_calls
+    for _ in range(L):
+        t0 = time.perf_counter()
+        st = s.retrieve(eb=eb)
+        lat.append((time.perf_counter() - t0) * 1e3)
+        st.free()
+    s.free()
+    lat.sort()
+    p50 = lat[len(lat) // 2]
+    p99 = lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)]
+
+    # roofline of the dominant kernel: algorithmic bytes per launch
+    alg_bytes, kname = launch_bytes(dom_op, dom_pass, pinfo, shape, itemsize, args.interp)
+    dom_list = dom_c if dom_op == "compress" else dom_r
+    dom_avg_ms = sum(dom_list) / len(dom_list)
+    achieved = alg_bytes / (dom_avg_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": "compress & retrieve GB/s (fp32 in) at eb=1e-4*range; p50/p99 retrieval latency",
+        "value": round(gb / (ms_per_step / 1e3), 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if itemsize == 4 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{'x'.join(map(str, shape))} {'f32' if itemsize == 4 else 'f64'} "
+                               f"Gaussian random field P(k)~k^-5/3, {args.interp}, eb={args.rel_eb:g}*range, "
+                               "compress + full retrieve",
+                   "eb_abs": eb, "stream_bytes": stream_bytes,
+                   "compression_ratio": round(n * itemsize / stream_bytes, 4),
+                   "n_passes": P},
+        "compress_GBps": round(gb / (tc / args.steps), 3),
+        "retrieve_GBps": round(gb / (tr / args.steps), 3),
+        "retrieve_latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4), "calls": L},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "kernel": kname, "alg_bytes_per_launch": int(alg_bytes),
+                     "avg_launch_ms": round(dom_avg_ms, 5)},
+        "pass_ms": {"compress": [round(v, 4) for v in c_ms], "retrieve": [round(v, 4) for v in r_ms]},
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(x, eb, args, rng)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def launch_bytes(op, launch, pinfo, shape, itemsize, interp):
+    """Algorithmic HBM bytes of one launch (each byte the launch must move once).
+
+    A launch that runs a whole level l of a 3-D field (passes along z, y, x)
+    reads the coarse grid G_l (points at stride 2^l), the planes of its three
+    passes and, for compression, the inputs at its targets; it writes the
+    level grid G_(l-1) (compression: only when a finer level follows) and, for
+    compression, the planes.  A single-pass launch moves its targets' values
+    once and its planes once.
+    """
+    group = [i for i, p in enumerate(pinfo) if p["launch_pass"] == launch]
+    planes = sum(sum(pinfo[i]["plane_bytes"]) for i in group)
+    targets = sum(pinfo[i]["n_targets"] for i in group)
+    tname = "float" if itemsize == 4 else "double"
+    if len(group) == 1:
+        return targets * itemsize + planes, f"k_{op}_pass<{tname},{interp}> pass {launch}"
+    lev = pinfo[launch]["level"]
+
+    def grid(j):
+        n = 1
+        for d in shape:
+            n *= ((d - 1) >> j) + 1
+        return n
+
+    coarse, fine = grid(lev), grid(lev - 1)
+    if op == "compress":
+        b = targets * itemsize + coarse * itemsize + planes + (fine * itemsize if lev > 1 else 0)
+    else:
+        b = coarse * itemsize + planes + fine * itemsize
+    return b, f"k_level3_{op}<{tname},{interp}> level {lev}"
+
+
+def cpu_baseline(x, eb, args, rng):
+    """The oracle (plain NumPy, one core) on a cubic corner of the same field."""
+    import numpy as np
+    from oracle import codec
+    e = min(args.cpu_sample, *x.shape) if x.dim() == 3 else None
+    sub = x[:e, :e, :e] if x.dim() == 3 else x
+    xs = np.ascontiguousarray(sub.cpu().numpy())
+    print(f"[bench] cpu baseline: oracle on {xs.shape}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    buf = codec.compress(xs, eb, interp=1 if args.interp == "cubic" else 0)
+    t1 = time.perf_counter()
+    codec.retrieve(buf, "eb", eb)
+    t2 = time.perf_counter()
+    gb = xs.nbytes / 1e9
+    return {"value": round(gb / (t2 - t0), 5), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{'x'.join(map(str, xs.shape))} corner of the same field, same eb; "
+                      f"compress {t1 - t0:.2f} s + full retrieve {t2 - t1:.2f} s",
+            "compress_GBps": round(gb / (t1 - t0), 5), "retrieve_GBps": round(gb / (t2 - t1), 5)}
+
+
+if __name__ == "__main__":
+    main()

@@ -169,3 +169,37 @@ def poly_field(shape, degrees, seed: int = 0, dtype=np.float64, max_abs: int = 1
     if np.max(np.abs(f)) > max_abs:
         raise ValueError("polynomial too large for the grid; pick smaller degrees or shape")
     return f.astype(dtype)
+
+
+def grf_torch(shape, amp_exponent: float, seed: int, device="cuda:0"):
+    """Same recipe as :func:`grf`, computed on the GPU in float32 with torch.
+
+    Used where a large field has to be drawn quickly on the device (the
+    512^3 benchmark field); the values differ from :func:`grf` in rounding and
+    random stream, not in distribution.
+    """
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    white = torch.randn(tuple(shape), generator=g, device=device, dtype=torch.float32)
+    spec = torch.fft.rfftn(white)
+    del white
+    k2 = None
+    for j, n in enumerate(shape):
+        if j == len(shape) - 1:
+            kj = torch.fft.rfftfreq(n, device=device) * n
+        else:
+            kj = torch.fft.fftfreq(n, device=device) * n
+        sh = [1] * len(shape)
+        sh[j] = kj.numel()
+        term = (kj.reshape(sh)) ** 2
+        k2 = term if k2 is None else k2 + term
+    k = torch.sqrt(k2)
+    amp = torch.where(k > 0, k.clamp_min(1e-30) ** amp_exponent, torch.zeros_like(k))
+    spec *= amp
+    del amp, k, k2
+    f = torch.fft.irfftn(spec, s=tuple(shape))
+    del spec
+    f -= f.mean()
+    f /= f.std()
+    return f.contiguous()

@@ -109,6 +109,22 @@ ipc_status ipc_stream_to_host(ipc_ctx *ctx, const ipc_stream *s, void *dst, uint
 ipc_status ipc_stream_from_host(ipc_ctx *ctx, const void *src, uint64_t bytes, ipc_stream **out);
 void ipc_stream_free(ipc_stream *s);
 
+/* Per-pass description of a stream (the planner's inputs, Sec. 5). */
+typedef struct {
+  int32_t level;              /* l (0 for the anchors) */
+  int32_t dim;                /* interpolation dimension (-1 for the anchors) */
+  uint64_t n_targets;         /* points predicted by the pass */
+  uint64_t n_chunks;
+  uint64_t plane_bytes[32];   /* stored bytes of plane k over the pass */
+  uint32_t errq[33];          /* delta-y in code units with b planes discarded */
+  uint32_t progressive;       /* 0 for passes that are always fully loaded */
+  uint32_t launch_pass;       /* pass whose timing slot records the kernel launch that
+                                 runs this pass (itself unless one launch runs the
+                                 whole level; then the level's last pass) */
+} ipc_pass_info;
+
+ipc_status ipc_stream_pass_info(const ipc_stream *s, uint32_t pass, ipc_pass_info *out);
+
 /* Alg. 1: reconstruct from the planes the Sec. 5 planner selects for
  * `target`.  The state holds the reconstruction and the plan; `info` may be
  * NULL. */
@@ -138,6 +154,16 @@ void ipc_state_free(ipc_state *st);
 ipc_status ipc_plan_host(const void *stream_bytes, uint64_t nbytes, ipc_target target,
                          const uint8_t *limit, uint8_t *plan_out, uint32_t plan_capacity,
                          double *bound_out, uint32_t *flags_out, uint64_t *loaded_out);
+
+/* Per-pass device timing (for measurement): when on, the pass kernels of
+ * later compress / retrieve / refine calls (every pass, or only pass
+ * `only_pass` when it is >= 0) are bracketed by HIP events on the context's
+ * stream; ipc_ctx_pass_times returns the last call's milliseconds per pass
+ * (n_out = the stream's pass count; 0 for passes not timed).  A launch that
+ * runs several passes is timed once, in the slot ipc_pass_info.launch_pass
+ * names; `only_pass` selects launches by that slot. */
+ipc_status ipc_ctx_set_profiling(ipc_ctx *ctx, int on, int only_pass);
+ipc_status ipc_ctx_pass_times(const ipc_ctx *ctx, float *ms, uint32_t capacity, uint32_t *n_out);
 
 const char *ipc_status_string(ipc_status st);
 const char *ipc_last_error(const ipc_ctx *ctx);

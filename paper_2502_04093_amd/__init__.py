@@ -49,6 +49,13 @@ class ipc_info(ctypes.Structure):
         return [int(self.plan[i]) for i in range(self.n_passes)]
 
 
+class ipc_pass_info(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("dim", ctypes.c_int32), ("n_targets", c_uint64),
+                ("n_chunks", c_uint64), ("plane_bytes", c_uint64 * 32), ("errq", c_uint32 * 33),
+                ("progressive", c_uint32),
+                ("launch_pass", c_uint32)]
+
+
 P = ctypes.POINTER
 SIGNATURES = {
     "ipc_ctx_create": (c_int, [c_int, c_void_p, P(c_void_p)]),
@@ -61,6 +68,7 @@ SIGNATURES = {
     "ipc_stream_from_host": (c_int, [c_void_p, c_void_p, c_uint64, P(c_void_p)]),
     "ipc_stream_free": (None, [c_void_p]),
     "ipc_stream_passes": (c_int, [c_void_p, P(c_uint32)]),
+    "ipc_stream_pass_info": (c_int, [c_void_p, c_uint32, P(ipc_pass_info)]),
     "ipc_retrieve": (c_int, [c_void_p, c_void_p, ipc_target, P(c_void_p), P(ipc_info)]),
     "ipc_retrieve_plan": (c_int, [c_void_p, c_void_p, P(c_uint8), c_uint32, P(c_void_p),
                                   P(ipc_info)]),
@@ -70,6 +78,8 @@ SIGNATURES = {
     "ipc_state_free": (None, [c_void_p]),
     "ipc_plan_host": (c_int, [c_void_p, c_uint64, ipc_target, P(c_uint8), P(c_uint8), c_uint32,
                               P(c_double), P(c_uint32), P(c_uint64)]),
+    "ipc_ctx_set_profiling": (c_int, [c_void_p, c_int, c_int]),
+    "ipc_ctx_pass_times": (c_int, [c_void_p, P(c_float), c_uint32, P(c_uint32)]),
     "ipc_status_string": (ctypes.c_char_p, [c_int]),
     "ipc_last_error": (ctypes.c_char_p, [c_void_p]),
 }
@@ -162,6 +172,17 @@ class Context:
     def handle(self):
         return self._p
 
+    def set_profiling(self, on: bool = True, only_pass: int = -1):
+        _check(lib().ipc_ctx_set_profiling(self._p, int(bool(on)), int(only_pass)), self._p)
+
+    def pass_times(self):
+        """Per-pass kernel milliseconds of the last call (profiling on)."""
+        n = c_uint32()
+        _check(lib().ipc_ctx_pass_times(self._p, None, 0, ctypes.byref(n)), self._p)
+        arr = (c_float * max(1, n.value))()
+        _check(lib().ipc_ctx_pass_times(self._p, arr, n.value, ctypes.byref(n)), self._p)
+        return [float(arr[i]) for i in range(n.value)]
+
     def compress(self, field, eb: float, interp: str = "cubic", nonprog_levels: int = 0,
                  chunk_log2: Optional[Sequence[int]] = None) -> "Stream":
         import torch
@@ -230,6 +251,14 @@ class Stream:
         n = c_uint32()
         _check(lib().ipc_stream_passes(self._p, ctypes.byref(n)))
         return n.value
+
+    def pass_info(self, i: int) -> dict:
+        pi = ipc_pass_info()
+        _check(lib().ipc_stream_pass_info(self._p, i, ctypes.byref(pi)))
+        return {"level": pi.level, "dim": pi.dim, "n_targets": pi.n_targets,
+                "n_chunks": pi.n_chunks, "plane_bytes": list(pi.plane_bytes),
+                "errq": list(pi.errq), "progressive": bool(pi.progressive),
+                "launch_pass": int(pi.launch_pass)}
 
     def to_bytes(self) -> bytes:
         n = self.nbytes

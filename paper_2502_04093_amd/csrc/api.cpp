@@ -34,7 +34,20 @@ struct ipc_ctx {
   size_t ws_summary_bytes = 0;
   void *ws_out = nullptr;
   size_t ws_out_cap = 0;  // records
+  void *ws_g[2] = {nullptr, nullptr};   // compact coarse grids (by level parity)
+  size_t ws_g_bytes[2] = {0, 0};
+  void *ws_args = nullptr;              // PassArgs of the current call
+  size_t ws_args_bytes = 0;
+  void *host_summary = nullptr;         // pinned copy of the compression summary
+  size_t host_summary_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // per-pass timing
+  bool profiling = false;
+  std::vector<hipEvent_t> pev;   // 2 per pass
+  std::vector<int> pev_pass;     // pass index of each timed pair
+  std::vector<float> pass_ms;     // per pass (0 = not run)
+  size_t prof_np = 0;
+  int prof_only = -1;
 };
 
 struct DevBuf {
@@ -142,6 +155,43 @@ void *ensure_ws(ipc_ctx *ctx, void *&p, size_t &have, size_t need) {
   return p;
 }
 
+void prof_begin(ipc_ctx *ctx, size_t n_passes) {
+  ctx->pev_pass.clear();
+  ctx->pass_ms.clear();
+  ctx->prof_np = n_passes;
+  if (!ctx->profiling) return;
+  while (ctx->pev.size() < 2 * n_passes) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      set_err(ctx, "event creation failed");
+      throw Fail{IPC_EHIP};
+    }
+    ctx->pev.push_back(e);
+  }
+}
+
+void prof_mark(ipc_ctx *ctx, int pass, bool start) {
+  if (!ctx->profiling) return;
+  if (ctx->prof_only >= 0 && pass != ctx->prof_only) return;
+  size_t k = ctx->pev_pass.size();
+  if (start) {
+    (void)hipEventRecord(ctx->pev[2 * k], ctx->stream);
+  } else {
+    (void)hipEventRecord(ctx->pev[2 * k + 1], ctx->stream);
+    ctx->pev_pass.push_back(pass);
+  }
+}
+
+// after the stream is synchronized
+void prof_end(ipc_ctx *ctx) {
+  if (!ctx->profiling) return;
+  ctx->pass_ms.assign(ctx->prof_np, 0.0f);
+  for (size_t k = 0; k < ctx->pev_pass.size(); ++k)
+    (void)hipEventElapsedTime(&ctx->pass_ms[size_t(ctx->pev_pass[k])], ctx->pev[2 * k],
+                              ctx->pev[2 * k + 1]);
+}
+
 PassArgs make_args(const Schedule &s, const PassGeom &p) {
   PassArgs a;
   for (int j = 0; j < 3; ++j) {
@@ -232,6 +282,92 @@ void fill_info(const ipc_stream *s, const std::vector<int> &plan, double bound, 
   info->t_device_ms = tdev;
 }
 
+// ---------------------------------------------------------------- fused 3-D levels
+
+Level3Args level3_args(const Schedule &s, int l);
+
+// The fused level kernels cover 3-D fields with the default chunk shape whose
+// level-1 launch fits the grid limits (their tile arithmetic is 32-bit).
+bool fused3(const Schedule &s) {
+  if (!(s.D == 3 && s.K >= 1 && s.chunk_log2[0] == 1 && s.chunk_log2[1] == 4 &&
+        s.chunk_log2[2] == 6))
+    return false;
+  for (int j = 0; j < 3; ++j)
+    if (s.dims3[j] > (int64_t(1) << 24)) return false;
+  const Level3Args A = level3_args(s, 1);
+  return A.tiles_y <= 65535 && (A.tiles_z + A.zseg - 1) / A.zseg <= 65535;
+}
+
+// points of the coarse grid G_j (fine stride 2^j)
+int64_t coarse_points(const Schedule &s, int j) {
+  int64_t n = 1;
+  for (int d = 0; d < 3; ++d) n *= ((s.dims3[d] - 1) >> j) + 1;
+  return n;
+}
+
+// fine-field strides of one step of stride h along z, y, x
+void level_strides(const Schedule &s, int64_t h, Level3Args &A) {
+  A.sZ = h * s.dims3[1] * s.dims3[2];
+  A.sY = h * s.dims3[2];
+  A.sX = int32_t(h);
+}
+
+Level3Args anchor3_args(const Schedule &s) {
+  Level3Args A;
+  std::memset(&A, 0, sizeof(A));
+  const PassGeom &p = s.passes[0];
+  for (int j = 0; j < 3; ++j) {
+    A.L[j] = int32_t(p.ldims[j]);
+    A.G[j] = int32_t(p.ldims[j]);
+  }
+  level_strides(s, p.h, A);
+  A.chunk_base[0] = p.chunk_base;
+  A.slot_base[0] = p.slot_base;
+  A.wmax[0] = uint32_t(p.wmax);
+  A.pass_index[0] = 0;
+  return A;
+}
+
+Level3Args level3_args(const Schedule &s, int l) {
+  Level3Args A;
+  std::memset(&A, 0, sizeof(A));
+  const int64_t h = int64_t(1) << (l - 1);
+  for (int j = 0; j < 3; ++j) {
+    A.L[j] = int32_t((s.dims3[j] - 1) / h + 1);
+    A.G[j] = int32_t((s.dims3[j] - 1) / (2 * h) + 1);
+  }
+  level_strides(s, h, A);
+  A.tiles_z = (A.L[0] + 1) / 2;
+  A.tiles_y = (A.L[1] + 15) / 16;
+  A.tiles_x = (A.L[2] + 63) / 64;
+  // chunk rows per workgroup: long columns amortize the coarse-plane halo,
+  // but small levels need more, shorter columns to fill the device
+  const int64_t nxy = int64_t(A.tiles_y) * A.tiles_x;
+  A.zseg = 16;
+  while (A.zseg > 2 && nxy * ((A.tiles_z + A.zseg - 1) / A.zseg) < 2048) A.zseg -= 2;
+  for (int p = 0; p < 3; ++p) {
+    const PassGeom &g = s.passes[size_t(1 + (s.K - l) * 3 + p)];
+    for (int j = 0; j < 3; ++j) {
+      A.tdims[p][j] = int32_t(g.tdims[j]);
+      A.ct[p][j] = int32_t(g.ct[j]);
+    }
+    A.chunk_base[p] = g.chunk_base;
+    A.slot_base[p] = g.slot_base;
+    A.wmax[p] = uint32_t(g.wmax);
+    A.pass_index[p] = uint32_t(g.index);
+  }
+  return A;
+}
+
+// compact coarse-grid buffers: G_j lives in ws_g[j & 1]
+void ensure_coarse(ipc_ctx *ctx, const Schedule &s, size_t isz) {
+  size_t need[2] = {0, 0};
+  for (int j = 1; j <= s.K; ++j)
+    need[j & 1] = std::max(need[j & 1], size_t(coarse_points(s, j)) * isz);
+  for (int i = 0; i < 2; ++i)
+    ensure_ws(ctx, ctx->ws_g[i], ctx->ws_g_bytes[i], std::max<size_t>(need[i], 8));
+}
+
 // run passes [s0, P) of a retrieval into `field`
 void run_retrieve(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &plan, int s0,
                   void *field) {
@@ -243,10 +379,49 @@ void run_retrieve(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &pla
   in.out_local = static_cast<const uint32_t *>(s->out_local.p);
   in.out_bits = static_cast<const uint64_t *>(s->out_bits.p);
   in.n_out = s->meta.outliers.size();
-  for (size_t i = size_t(s0); i < s->args.size(); ++i)
+  prof_begin(ctx, s->args.size());
+  const Schedule &sc = s->meta.sched;
+  if (fused3(sc)) {
+    const size_t isz = s->meta.dtype == IPC_F32 ? 4 : 8;
+    ensure_coarse(ctx, sc, isz);
+    int l_start = sc.K;
+    if (s0 <= 0) {
+      Level3Args A = anchor3_args(sc);
+      prof_mark(ctx, 0, true);
+      hip_check(ctx, launch_anchor3_retrieve(s->meta.dtype, A, ctx->ws_g[sc.K & 1], in, s->meta.eb,
+                                             ctx->stream),
+                "anchor kernel launch");
+      prof_mark(ctx, 0, false);
+    } else {
+      // refinement: restart at the level of pass s0 from the resident field
+      l_start = sc.passes[size_t(s0)].level;
+      int64_t gd[3];
+      for (int j = 0; j < 3; ++j) gd[j] = ((sc.dims3[j] - 1) >> l_start) + 1;
+      hip_check(ctx, launch_gather_coarse(s->meta.dtype, field, sc.dims3, int64_t(1) << l_start,
+                                          ctx->ws_g[l_start & 1], gd, ctx->stream),
+                "gather kernel launch");
+    }
+    for (int l = l_start; l >= 1; --l) {
+      Level3Args La = level3_args(sc, l);
+      int disc[3];
+      for (int p = 0; p < 3; ++p) disc[p] = plan[La.pass_index[p]];
+      int pc = int(La.pass_index[2]);
+      prof_mark(ctx, pc, true);
+      hip_check(ctx, launch_level3_retrieve(s->meta.dtype, s->meta.interp, La, ctx->ws_g[l & 1],
+                                            l > 1 ? ctx->ws_g[(l - 1) & 1] : field, disc, in,
+                                            s->meta.eb, ctx->stream),
+                "level kernel launch");
+      prof_mark(ctx, pc, false);
+    }
+    return;
+  }
+  for (size_t i = size_t(s0); i < s->args.size(); ++i) {
+    prof_mark(ctx, int(i), true);
     hip_check(ctx, launch_retrieve_pass(s->meta.dtype, s->meta.interp, s->args[i], field, plan[i],
                                         in, s->meta.eb, ctx->stream),
               "retrieve kernel launch");
+    prof_mark(ctx, int(i), false);
+  }
 }
 
 uint64_t plane_bytes_between(const ipc_stream *s, const std::vector<int> &lo,
@@ -277,6 +452,23 @@ const char *ipc_status_string(ipc_status st) {
 }
 
 const char *ipc_last_error(const ipc_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+ipc_status ipc_ctx_set_profiling(ipc_ctx *ctx, int on, int only_pass) {
+  if (!ctx) return IPC_EINVAL;
+  ctx->profiling = on != 0;
+  ctx->prof_only = only_pass;
+  return IPC_OK;
+}
+
+ipc_status ipc_ctx_pass_times(const ipc_ctx *ctx, float *ms, uint32_t capacity, uint32_t *n_out) {
+  if (!ctx || !n_out) return IPC_EINVAL;
+  *n_out = uint32_t(ctx->pass_ms.size());
+  if (ms) {
+    if (capacity < ctx->pass_ms.size()) return IPC_EINVAL;
+    for (size_t k = 0; k < ctx->pass_ms.size(); ++k) ms[k] = ctx->pass_ms[k];
+  }
+  return IPC_OK;
+}
 
 ipc_status ipc_ctx_create(int device, void *hip_stream, ipc_ctx **out) {
   if (!out) return IPC_EINVAL;
@@ -332,6 +524,11 @@ void ipc_ctx_destroy(ipc_ctx *ctx) {
   if (ctx->ws_xh) (void)hipFree(ctx->ws_xh);
   if (ctx->ws_summary) (void)hipFree(ctx->ws_summary);
   if (ctx->ws_out) (void)hipFree(ctx->ws_out);
+  for (int i = 0; i < 2; ++i)
+    if (ctx->ws_g[i]) (void)hipFree(ctx->ws_g[i]);
+  if (ctx->ws_args) (void)hipFree(ctx->ws_args);
+  if (ctx->host_summary) (void)hipHostFree(ctx->host_summary);
+  for (hipEvent_t e : ctx->pev) (void)hipEventDestroy(e);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->owned) (void)hipStreamDestroy(ctx->owned);
@@ -391,7 +588,17 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
 
     s->payload = dev_alloc(ctx, size_t(sc.slot_words) * 4);
     s->masks = dev_alloc(ctx, size_t(sc.n_chunks) * 4);
-    void *xh = ensure_ws(ctx, ctx->ws_xh, ctx->ws_xh_bytes, nbytes);
+    const bool fused = fused3(sc);
+    void *xh = nullptr;
+    if (fused)
+      ensure_coarse(ctx, sc, isz);
+    else
+      xh = ensure_ws(ctx, ctx->ws_xh, ctx->ws_xh_bytes, nbytes);
+    ensure_ws(ctx, ctx->ws_args, ctx->ws_args_bytes, s->args.size() * sizeof(PassArgs));
+    hip_check(ctx, hipMemcpyAsync(ctx->ws_args, s->args.data(), s->args.size() * sizeof(PassArgs),
+                                  hipMemcpyHostToDevice, ctx->stream), "upload");
+    int64_t max_chunks = 0;
+    for (const PassGeom &g : sc.passes) max_chunks = std::max(max_chunks, g.n_chunks);
     // summary: n_out, maxabs bits, sizes [P][32] u64, errq [P][33] u32
     size_t sum_bytes = 16 + size_t(P) * 32 * 8 + size_t(P) * 33 * 4;
     char *summary = static_cast<char *>(ensure_ws(ctx, ctx->ws_summary, ctx->ws_summary_bytes, sum_bytes));
@@ -410,21 +617,52 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
       o.out_recs = ctx->ws_out;
       o.out_cap = cap_recs;
       hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
-      for (int i = 0; i < P; ++i) {
-        int wb = i + 1 < P ? 1 : 0;  // the last pass is read by nobody
-        hip_check(ctx, launch_compress_pass(dtype, interp, s->args[i], field_dev, xh, wb, abs_eb, o,
-                                            ctx->stream),
-                  "compress kernel launch");
+      prof_begin(ctx, size_t(P));
+      if (fused) {
+        const int K = sc.K;
+        Level3Args A = anchor3_args(sc);
+        prof_mark(ctx, 0, true);
+        hip_check(ctx, launch_anchor3_compress(dtype, A, field_dev, ctx->ws_g[K & 1], abs_eb, o,
+                                               ctx->stream),
+                  "anchor kernel launch");
+        prof_mark(ctx, 0, false);
+        for (int l = K; l >= 1; --l) {
+          Level3Args La = level3_args(sc, l);
+          int pc = int(La.pass_index[2]);
+          prof_mark(ctx, pc, true);
+          hip_check(ctx, launch_level3_compress(dtype, interp, La, field_dev, ctx->ws_g[l & 1],
+                                                l > 1 ? ctx->ws_g[(l - 1) & 1] : nullptr, abs_eb, o,
+                                                ctx->stream),
+                    "level kernel launch");
+          prof_mark(ctx, pc, false);
+        }
+      } else {
+        for (int i = 0; i < P; ++i) {
+          int wb = i + 1 < P ? 1 : 0;  // the last pass is read by nobody
+          prof_mark(ctx, i, true);
+          hip_check(ctx, launch_compress_pass(dtype, interp, s->args[i], field_dev, xh, wb, abs_eb,
+                                              o, ctx->stream),
+                    "compress kernel launch");
+          prof_mark(ctx, i, false);
+        }
       }
-      for (int i = 0; i < P; ++i)
-        hip_check(ctx, launch_pass_sizes(s->args[i], o.masks, sizes + size_t(i) * 32, ctx->stream),
-                  "sizes kernel launch");
+      hip_check(ctx, launch_all_sizes(static_cast<const PassArgs *>(ctx->ws_args), P, max_chunks,
+                                      o.masks, sizes, ctx->stream),
+                "sizes kernel launch");
       hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
-      std::vector<char> host(sum_bytes);
-      hip_check(ctx, hipMemcpyAsync(host.data(), summary, sum_bytes, hipMemcpyDeviceToHost, ctx->stream), "copy");
+      if (ctx->host_summary_bytes < sum_bytes) {
+        if (ctx->host_summary) (void)hipHostFree(ctx->host_summary);
+        ctx->host_summary = nullptr;
+        ctx->host_summary_bytes = 0;
+        hip_check(ctx, hipHostMalloc(&ctx->host_summary, sum_bytes, hipHostMallocDefault), "pinned alloc");
+        ctx->host_summary_bytes = sum_bytes;
+      }
+      char *hostp = static_cast<char *>(ctx->host_summary);
+      hip_check(ctx, hipMemcpyAsync(hostp, summary, sum_bytes, hipMemcpyDeviceToHost, ctx->stream), "copy");
       hip_check(ctx, hipStreamSynchronize(ctx->stream), "compress");
+      prof_end(ctx);
       uint64_t nout;
-      std::memcpy(&nout, host.data(), 8);
+      std::memcpy(&nout, hostp, 8);
       if (nout > cap_recs) {
         cap = size_t(nout) + 1024;
         if (attempt == 0) continue;
@@ -432,12 +670,12 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
         throw Fail{IPC_EHIP};
       }
       uint64_t mb;
-      std::memcpy(&mb, host.data() + 8, 8);
+      std::memcpy(&mb, hostp + 8, 8);
       std::memcpy(&m.maxabs, &mb, 8);
       m.errq.resize(size_t(P) * 33);
-      std::memcpy(m.errq.data(), host.data() + 16 + size_t(P) * 32 * 8, m.errq.size() * 4);
+      std::memcpy(m.errq.data(), hostp + 16 + size_t(P) * 32 * 8, m.errq.size() * 4);
       std::vector<uint64_t> sz(size_t(P) * 32);
-      std::memcpy(sz.data(), host.data() + 16, sz.size() * 8);
+      std::memcpy(sz.data(), hostp + 16, sz.size() * 8);
       m.outliers.resize(nout);
       if (nout) {
         hip_check(ctx, hipMemcpy(m.outliers.data(), ctx->ws_out, nout * sizeof(OutlierRec), hipMemcpyDeviceToHost), "copy");
@@ -594,6 +832,7 @@ static ipc_status retrieve_common(ipc_ctx *ctx, const ipc_stream *s, const std::
     run_retrieve(ctx, s, plan, 0, stt->field.p);
     hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
     hip_check(ctx, hipStreamSynchronize(ctx->stream), "retrieve");
+    prof_end(ctx);
     float ms = 0;
     (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
     std::vector<int> none(plan.size(), 32);
@@ -673,6 +912,23 @@ ipc_status ipc_state_copy_field(ipc_ctx *ctx, const ipc_state *st, void *dst_dev
   });
 }
 
+ipc_status ipc_stream_pass_info(const ipc_stream *s, uint32_t pass, ipc_pass_info *out) {
+  if (!s || !out || pass >= s->args.size()) return IPC_EINVAL;
+  const PassGeom &g = s->meta.sched.passes[pass];
+  std::memset(out, 0, sizeof(*out));
+  out->level = g.level;
+  out->dim = g.dim;
+  out->n_targets = uint64_t(g.n_targets);
+  out->n_chunks = uint64_t(g.n_chunks);
+  for (int k = 0; k < 32; ++k) out->plane_bytes[k] = uint64_t(s->tables.sizes[size_t(pass) * 32 + k]);
+  for (int b = 0; b < 33; ++b) out->errq[b] = s->meta.errq[size_t(pass) * 33 + b];
+  out->progressive = s->tables.progressive[pass];
+  out->launch_pass = pass;
+  if (fused3(s->meta.sched) && g.level >= 1)
+    out->launch_pass = uint32_t(1 + (s->meta.sched.K - g.level) * 3 + 2);
+  return IPC_OK;
+}
+
 ipc_status ipc_stream_passes(const ipc_stream *s, uint32_t *n_passes) {
   if (!s || !n_passes) return IPC_EINVAL;
   *n_passes = uint32_t(s->args.size());
@@ -713,6 +969,7 @@ ipc_status ipc_refine(ipc_ctx *ctx, ipc_state *st, ipc_target target, ipc_info *
     run_retrieve(ctx, s, pr.plan, s_min, st->field.p);
     hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
     hip_check(ctx, hipStreamSynchronize(ctx->stream), "refine");
+    prof_end(ctx);
     float ms = 0;
     (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
     uint64_t read = plane_bytes_between(s, pr.plan, st->plan);

@@ -45,11 +45,45 @@ struct RetrieveIn {
   uint64_t n_out;
 };
 
+// A whole level of a 3-D field in one launch (chunk shape (2, 16, 64)).
+// Level-grid extents are below 2^30 (checked by the host).
+struct Level3Args {
+  int32_t L[3];          // level-grid extents (z, y, x)
+  int32_t G[3];          // coarse-grid extents ((L - 1) >> 1) + 1
+  int64_t sZ, sY;        // fine-field index strides of one level step in z and y
+  int32_t sX;            // ... and in x (the level stride h)
+  int32_t tiles_z, tiles_y, tiles_x;  // chunk grid (shared by the 3 passes)
+  int32_t zseg;          // chunk rows per workgroup (even)
+  int32_t tdims[3][3];   // target lattice of passes A, B, C
+  int32_t ct[3][3];      // chunk extents in target coordinates
+  int64_t chunk_base[3];
+  uint64_t slot_base[3];
+  uint32_t wmax[3];
+  uint32_t pass_index[3];
+};
+
+hipError_t launch_level3_compress(int dtype, int interp, const Level3Args &L, const void *x,
+                                  const void *gin, void *gout, double eb, const CompressOut &o,
+                                  hipStream_t s);
+hipError_t launch_level3_retrieve(int dtype, int interp, const Level3Args &L, const void *gin,
+                                  void *gout, const int disc[3], const RetrieveIn &in, double eb,
+                                  hipStream_t s);
+hipError_t launch_anchor3_compress(int dtype, const Level3Args &A, const void *x, void *gout,
+                                   double eb, const CompressOut &o, hipStream_t s);
+hipError_t launch_anchor3_retrieve(int dtype, const Level3Args &A, void *gout, const RetrieveIn &in,
+                                   double eb, hipStream_t s);
+// g[c] = field[step * c] over the coarse grid gd
+hipError_t launch_gather_coarse(int dtype, const void *field, const int64_t fd[3], int64_t step,
+                                void *g, const int64_t gd[3], hipStream_t s);
+
 hipError_t launch_compress_pass(int dtype, int interp, const PassArgs &pa, const void *x, void *xh,
                                 int write_back, double eb, const CompressOut &o,
                                 hipStream_t stream);
 hipError_t launch_retrieve_pass(int dtype, int interp, const PassArgs &pa, void *field,
                                 int discard, const RetrieveIn &in, double eb, hipStream_t stream);
+// sizes[p][k] for every pass at once (args_dev: the passes' PassArgs on the device)
+hipError_t launch_all_sizes(const PassArgs *args_dev, int n_passes, int64_t max_chunks,
+                            const uint32_t *masks, unsigned long long *sizes, hipStream_t stream);
 // sizes[k] (bytes of plane k summed over the pass's chunks), one pass
 hipError_t launch_pass_sizes(const PassArgs &pa, const uint32_t *masks,
                              unsigned long long *sizes, hipStream_t stream);

@@ -440,6 +440,40 @@ __global__ __launch_bounds__(WG) void k_pack(PassArgs a, const uint32_t *masks,
   }
 }
 
+// sizes[p][k] += 4 * sum over chunks c of pass p with bit k of mask_c of W_c;
+// grid (passes, splits), each workgroup covers up to 16 chunks per thread.
+__global__ __launch_bounds__(WG) void k_all_sizes(const PassArgs *args, const uint32_t *masks,
+                                                   unsigned long long *sizes) {
+  __shared__ unsigned long long s_acc[32];
+  const PassArgs a = args[blockIdx.x];
+  const int tid = threadIdx.x;
+  if (tid < 32) s_acc[tid] = 0;
+  __syncthreads();
+  const int64_t c0 = int64_t(blockIdx.y) * (16 * WG);
+  int64_t c1 = c0 + 16 * WG;
+  if (c1 > a.n_chunks) c1 = a.n_chunks;
+  uint32_t acc[32];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) acc[k] = 0;
+  for (int64_t c = c0 + tid; c < c1; c += WG) {
+    uint32_t mk = masks[a.chunk_base + c];
+    if (!mk) continue;
+    ChunkGeo g = chunk_geo(a, c);
+    uint32_t W = uint32_t((g.count + 31) >> 5);
+#pragma unroll
+    for (int k = 0; k < 32; ++k) acc[k] += ((mk >> k) & 1u) * W;
+  }
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    uint32_t v = acc[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((tid & 63) == 0 && v) atomicAdd(&s_acc[k], 4ull * v);
+  }
+  __syncthreads();
+  if (tid < 32 && s_acc[tid]) atomicAdd(&sizes[size_t(blockIdx.x) * 32 + tid], s_acc[tid]);
+}
+
 template <typename T, int INTERP>
 hipError_t launch_c(const PassArgs &pa, const void *x, void *xh, int wb, double eb,
                     const CompressOut &o, hipStream_t s) {
@@ -481,6 +515,15 @@ hipError_t launch_retrieve_pass(int dtype, int interp, const PassArgs &pa, void 
                                 : launch_r<float, IPC_CUBIC>(pa, field, discard, in, eb, stream);
   return interp == IPC_LINEAR ? launch_r<double, IPC_LINEAR>(pa, field, discard, in, eb, stream)
                               : launch_r<double, IPC_CUBIC>(pa, field, discard, in, eb, stream);
+}
+
+hipError_t launch_all_sizes(const PassArgs *args_dev, int n_passes, int64_t max_chunks,
+                            const uint32_t *masks, unsigned long long *sizes, hipStream_t stream) {
+  uint32_t splits = uint32_t((max_chunks + 16 * WG - 1) / (16 * WG));
+  if (splits == 0) splits = 1;
+  hipLaunchKernelGGL(k_all_sizes, dim3(uint32_t(n_passes), splits), dim3(WG), 0, stream, args_dev,
+                     masks, sizes);
+  return hipGetLastError();
 }
 
 hipError_t launch_pass_sizes(const PassArgs &pa, const uint32_t *masks, unsigned long long *sizes,

@@ -1,0 +1,981 @@
+// Fused per-level kernels for 3-D fields with the default chunk shape
+// (2, 16, 64) level coordinates.
+//
+// One launch runs a whole level l (Sec. 4.1: the level's three 1-D
+// interpolation passes along z, y, x) on the level grid G_{l-1}, reading the
+// coarse grid G_l from a compact array and writing G_{l-1} compactly (or, for
+// retrieval at level 1, the final field).  A workgroup owns a 16 x 64 column of
+// chunks and marches along z, two level planes (one chunk row) per step:
+//
+//   pass A (along z) at the odd plane, from a ring of 4 coarse planes,
+//   pass B (along y) at both planes, from the even rows,
+//   pass C (along x) at both planes, from the even columns.
+//
+// Passes A and B are also evaluated on a halo (even rows y0-2, y0+16, y0+18
+// and even columns x0-2, x0+64, x0+66) that neighbouring columns own; those
+// values are recomputed from the same inputs, so workgroups never wait on each
+// other.  Codes of the workgroup's own targets are buffered in LDS for two
+// steps; 112 threads then turn rows of 32 codes into plane words (or back)
+// with an in-register 32x32 bit transpose (Sec. 4.3).  Compression also
+// accumulates the delta-y maxima of Thm. 1 from the buffered codes.
+//
+// Tile-local arithmetic is 32-bit (the host limits extents to 2^24);
+// only offsets into global arrays are 64-bit.  Per target the arithmetic is
+// exactly that of the per-pass kernels (same stencils, same rounding), so
+// streams and reconstructions are bit-identical.
+#include "kernels.h"
+
+#include "ipc_internal.h"
+
+namespace ipc {
+namespace {
+
+constexpr uint32_t NB_A = 0xAAAAAAAAu;
+constexpr int WG3 = 256;
+constexpr int TY = 16, TX = 64;   // chunk extents (level coordinates) in y, x
+constexpr int NYE = 11;           // even rows y0-2 .. y0+18
+constexpr int NXE = 35;           // even columns x0-2 .. x0+66
+constexpr int NXP = 36;           // padded row length
+constexpr int CA = 256, CB = 512, CC = 1024;  // codes per full chunk of pass A, B, C
+constexpr int PADA = CA + CA / 32, PADB = CB + CB / 32, PADC = CC + CC / 32;
+constexpr int NHA = 129, NHB = 48;  // halo targets of pass A and B per step
+
+__device__ __forceinline__ int pidx(int j) { return j + (j >> 5); }
+
+template <typename T>
+struct F3;
+template <>
+struct F3<float> {
+  static __device__ __forceinline__ float add(float a, float b) { return __fadd_rn(a, b); }
+  static __device__ __forceinline__ float sub(float a, float b) { return __fsub_rn(a, b); }
+  static __device__ __forceinline__ float mul(float a, float b) { return __fmul_rn(a, b); }
+  static __device__ __forceinline__ float rnd(float a) { return __builtin_rintf(a); }
+  static __device__ __forceinline__ uint64_t bits(float a) { return __float_as_uint(a); }
+  static __device__ __forceinline__ float from_bits(uint64_t b) { return __uint_as_float(uint32_t(b)); }
+};
+template <>
+struct F3<double> {
+  static __device__ __forceinline__ double add(double a, double b) { return __dadd_rn(a, b); }
+  static __device__ __forceinline__ double sub(double a, double b) { return __dsub_rn(a, b); }
+  static __device__ __forceinline__ double mul(double a, double b) { return __dmul_rn(a, b); }
+  static __device__ __forceinline__ double rnd(double a) { return __builtin_rint(a); }
+  static __device__ __forceinline__ uint64_t bits(double a) { return uint64_t(__double_as_longlong(a)); }
+  static __device__ __forceinline__ double from_bits(uint64_t b) { return __longlong_as_double((long long)b); }
+};
+
+// Transpose a 32x32 bit matrix held as 32 words: afterwards bit j of a[k]
+// is what bit k of a[j] was.
+__device__ __forceinline__ void transpose32(uint32_t a[32]) {
+  uint32_t m = 0x0000FFFFu;
+#pragma unroll
+  for (int j = 16; j != 0; j >>= 1, m ^= (m << j)) {
+#pragma unroll
+    for (int k = 0; k < 32; k = ((k | j) + 1) & ~j) {
+      uint32_t t = ((a[k] >> j) ^ a[k | j]) & m;
+      a[k] ^= t << j;
+      a[k | j] ^= t;
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t xenc(uint32_t v) { return v ^ (v >> 1) ^ (v >> 2); }
+// (1 + x + x^2)^-1 = (1 + x)(1 + x^3)(1 + x^6)(1 + x^12)(1 + x^24) over GF(2)
+__device__ __forceinline__ uint32_t xdec(uint32_t e) {
+  uint32_t t = e ^ (e >> 1);
+  t ^= t >> 3;
+  t ^= t >> 6;
+  t ^= t >> 12;
+  t ^= t >> 24;
+  return t;
+}
+
+// One-dimensional stencil on gathered neighbours (b, c at -+1; a, e at -+3).
+template <typename T, int INTERP>
+__device__ __forceinline__ T stencil(T a, T b, T c, T e, bool hc, bool ha, bool he) {
+  using F = F3<T>;
+  if (!hc) return b;
+  if (INTERP == IPC_LINEAR) return F::mul(F::add(b, c), T(0.5));
+  if (ha && he) return F::mul(F::sub(F::mul(F::add(b, c), T(9.0)), F::add(a, e)), T(0.0625));
+  if (he) return F::mul(F::sub(F::add(F::mul(b, T(3.0)), F::mul(c, T(6.0))), e), T(0.125));
+  if (ha) return F::mul(F::sub(F::add(F::mul(c, T(3.0)), F::mul(b, T(6.0))), a), T(0.125));
+  return F::mul(F::add(b, c), T(0.5));
+}
+
+// Quantization of Sec. 4.2.2 with the explicit check; returns the code (0 for
+// an outlier) and the reconstruction.
+template <typename T>
+__device__ __forceinline__ int32_t quantize(T xv, T pred, double eb, T two_eb, T inv, T qmax,
+                                            T &xhat, bool &out) {
+  using F = F3<T>;
+  T qf = F::rnd(F::mul(F::sub(xv, pred), inv));
+  out = !(fabs(qf) <= qmax);
+  int32_t q = out ? 0 : int32_t(qf);
+  T xr = F::add(pred, F::mul(T(q), two_eb));
+  if (!out) out = !(fabs(__dsub_rn(double(xr), double(xv))) <= eb);
+  xhat = out ? xv : xr;
+  return out ? 0 : q;
+}
+
+struct Ext {
+  int ez, ey, ex, count;
+};
+
+__device__ __forceinline__ int clampi(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
+
+// extents of chunk (tz, ty, tx) of pass p (0 = A, 1 = B, 2 = C)
+__device__ __forceinline__ Ext chunk_ext(const Level3Args &L, int p, int tz, int ty, int tx) {
+  Ext c;
+  c.ez = clampi(L.tdims[p][0] - tz * L.ct[p][0], L.ct[p][0]);
+  c.ey = clampi(L.tdims[p][1] - ty * L.ct[p][1], L.ct[p][1]);
+  c.ex = clampi(L.tdims[p][2] - tx * L.ct[p][2], L.ct[p][2]);
+  c.count = c.ez * c.ey * c.ex;
+  return c;
+}
+
+__device__ __forceinline__ int64_t chunk_id(const Level3Args &L, int tz, int ty, int tx) {
+  return (int64_t(tz) * L.tiles_y + ty) * L.tiles_x + tx;
+}
+
+// first payload word of a chunk's stored planes, and a plane's rank among them
+__device__ __forceinline__ uint64_t chunk_words(const Level3Args &L, const RetrieveIn &in, int p,
+                                                int64_t cid) {
+  if (in.chunk_off) return in.chunk_off[L.chunk_base[p] + cid];
+  return L.slot_base[p] + uint64_t(cid) * 32u * L.wmax[p];
+}
+__device__ __forceinline__ uint32_t plane_rank(bool packed, uint32_t mask, int k) {
+  return packed ? uint32_t(__popc((mask >> k) >> 1)) : uint32_t(31 - k);
+}
+
+// outlier lookup: value bits of (global chunk, local) if stored
+__device__ __forceinline__ bool find_outlier(const RetrieveIn &in, uint64_t gch, uint32_t local,
+                                             uint64_t &bits) {
+  uint64_t a0 = 0, a1 = in.n_out;
+  while (a0 < a1) {
+    uint64_t m = (a0 + a1) >> 1;
+    uint64_t kg = in.out_gchunk[m];
+    bool less = kg < gch || (kg == gch && in.out_local[m] < local);
+    if (less) a0 = m + 1; else a1 = m;
+  }
+  if (a0 < in.n_out && in.out_gchunk[a0] == gch && in.out_local[a0] == local) {
+    bits = in.out_bits[a0];
+    return true;
+  }
+  return false;
+}
+
+// Halo positions of one step (owned by neighbouring workgroups):
+//   pass A: even rows {y0-2, y0+16, y0+18} x 35 even columns (105), then own
+//           even rows x columns {x0-2, x0+64, x0+66} (24)                 = 129
+//   pass B: 2 planes x 8 odd rows x columns {x0-2, x0+64, x0+66}         =  48
+__device__ __forceinline__ void halo_a(int h, int &yj, int &xi) {
+  if (h < 105) {
+    int r = h / NXE;
+    yj = r == 0 ? 0 : 8 + r;
+    xi = h - r * NXE;
+  } else {
+    int hh = h - 105;
+    int r = hh / 3;
+    yj = 1 + r;
+    int c = hh - r * 3;
+    xi = c == 0 ? 0 : 32 + c;
+  }
+}
+__device__ __forceinline__ void halo_b(int h, int &zz, int &k, int &xi) {
+  zz = h >= 24 ? 1 : 0;
+  int r = h - zz * 24;
+  k = r / 3;
+  int c = r - k * 3;
+  xi = c == 0 ? 0 : 32 + c;
+}
+// Chunk column and in-chunk offset of halo index i (0 .. per + 2) around tile
+// `tile` whose chunks hold `per` target coordinates: target coordinate
+// tile * per - 1 + i lies in the tile before (i = 0), the tile, or the next.
+__device__ __forceinline__ void halo_tile(int tile, int i, int per, int &tn, int &off) {
+  int e = tile * per - 1 + i;
+  tn = i == 0 ? tile - 1 : (i <= per ? tile : tile + 1);
+  off = e - tn * per;
+}
+
+// Code of the target at offset (oz, oy, ox) of chunk (tz, tyn, txn) of pass p:
+// every plane word is loaded independently (unrolled), then bits are gathered.
+// Planes that are not loaded read word 0 of the payload, which always exists.
+__device__ __forceinline__ uint32_t fetch_code(const Level3Args &L, const RetrieveIn &in, int p,
+                                               int tz, int tyn, int txn, int oz, int oy, int ox,
+                                               uint32_t keep) {
+  const Ext e = chunk_ext(L, p, tz, tyn, txn);
+  const uint32_t local = uint32_t((oz * e.ey + oy) * e.ex + ox);
+  const int64_t cid = chunk_id(L, tz, tyn, txn);
+  const uint32_t mask = in.masks[L.chunk_base[p] + cid];
+  const uint32_t load = mask & keep;
+  const uint32_t W = uint32_t((e.count + 31) >> 5);
+  const bool packed = in.chunk_off != nullptr;
+  const uint32_t *base = in.payload + chunk_words(L, in, p, cid) + (local >> 5);
+  const uint32_t bsel = local & 31;
+  uint32_t code = 0;
+#pragma unroll
+  for (int k = 31; k >= 0; --k) {
+    bool on = (load >> k) & 1u;
+    uint32_t w = *(on ? base + plane_rank(packed, mask, k) * W : in.payload);
+    code |= (on ? (w >> bsel) & 1u : 0u) << k;
+  }
+  return xdec(code) & keep;
+}
+
+template <typename T>
+struct Shared3 {
+  T ring[4][NYE][NXP];
+  T wa[NYE][NXP];
+  T wb[2][8][NXP];
+  T xs[2][16][TX];
+  T wc[2][16][32];
+  T xha[NYE][NXP];          // compress: inputs of pass-A halo targets
+  T xhb[2][8][4];           //           inputs of pass-B halo targets
+  uint32_t hva[NYE][NXP];   // retrieve: codes of pass-A halo targets
+  uint32_t hvb[2][8][4];    //           codes of pass-B halo targets
+  uint32_t codes[2 * PADA + 2 * PADB + 2 * PADC];
+  uint32_t cmask[3][2];
+  uint32_t eq[3][33];       // per workgroup delta-y of each pass
+};
+
+__device__ __forceinline__ int code_off(int p, int si) {
+  return p == 0 ? si * PADA : (p == 1 ? 2 * PADA + si * PADB : 2 * PADA + 2 * PADB + si * PADC);
+}
+
+// ring slot cz & 3 <- coarse plane cz (11 even rows x 35 even columns)
+template <typename T>
+__device__ __forceinline__ void load_ring_plane(const Level3Args &L, const T *gin, Shared3<T> &S,
+                                                int cz, int y0, int x0) {
+  if (cz < 0 || cz >= L.G[0]) return;
+  T(*dst)[NXP] = S.ring[cz & 3];
+  const int64_t pb = int64_t(cz) * L.G[1];
+  T v[2];
+  bool ok[2];
+  int yj[2], xi[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    int t = threadIdx.x + i * WG3;
+    yj[i] = t / NXE;
+    xi[i] = t - yj[i] * NXE;
+    int cy = (y0 >> 1) - 1 + yj[i], cx = (x0 >> 1) - 1 + xi[i];
+    ok[i] = t < NYE * NXE && unsigned(cy) < unsigned(L.G[1]) && unsigned(cx) < unsigned(L.G[2]);
+    v[i] = gin[ok[i] ? (pb + cy) * L.G[2] + cx : 0];
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+    if (threadIdx.x + i * WG3 < NYE * NXE) dst[yj[i]][xi[i]] = ok[i] ? v[i] : T(0);
+}
+
+// even-column values of plane zz at tile row yy (0 .. 15), index i + 1 for the
+// even column x0 + 2 i: the coarse plane (zz = 0, yy even), pass A (zz = 1,
+// yy even) or pass B (yy odd)
+template <typename T>
+__device__ __forceinline__ const T *even_row(Shared3<T> &S, int m, int zz, int yy) {
+  if (yy & 1) return S.wb[zz][yy >> 1];
+  return zz == 0 ? S.ring[m & 3][(yy >> 1) + 1] : S.wa[(yy >> 1) + 1];
+}
+
+// write the 2 x 16 x 64 level points of a step from LDS to a compact grid,
+// four consecutive points per thread
+template <typename T>
+__device__ __forceinline__ void write_rows(const Level3Args &L, Shared3<T> &S, T *gout, int m,
+                                           int y0, int x0) {
+  const int Lz = L.L[0], Ly = L.L[1], Lx = L.L[2];
+  const bool vec = (Lx & 3) == 0 && (reinterpret_cast<uintptr_t>(gout) & 15) == 0;
+  for (int t = threadIdx.x; t < 2 * 16 * (TX / 4); t += WG3) {
+    int zz = t >> 8, yy = (t >> 4) & 15, xq = (t & 15) * 4;
+    int z = 2 * m + zz, y = y0 + yy, x = x0 + xq;
+    if (z >= Lz || y >= Ly || x >= Lx) continue;
+    const T *ev = even_row(S, m, zz, yy);
+    T v0 = ev[(xq >> 1) + 1];
+    T v1 = S.wc[zz][yy][xq >> 1];
+    T v2 = ev[(xq >> 1) + 2];
+    T v3 = S.wc[zz][yy][(xq >> 1) + 1];
+    T *dst = gout + (int64_t(z) * Ly + y) * int64_t(Lx) + x;
+    if (vec) {
+      if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4 *>(dst) = make_float4(v0, v1, v2, v3);
+      } else {
+        reinterpret_cast<double2 *>(dst)[0] = make_double2(v0, v1);
+        reinterpret_cast<double2 *>(dst)[1] = make_double2(v2, v3);
+      }
+    } else {
+      dst[0] = v0;
+      if (x + 1 < Lx) dst[1] = v1;
+      if (x + 2 < Lx) dst[2] = v2;
+      if (x + 3 < Lx) dst[3] = v3;
+    }
+  }
+}
+
+// Per-lane delta-y accumulator of Thm. 1 in code units: d[b] = max |q - q'_b|
+// over the codes seen, q'_b the code with its b lowest negabinary digits
+// cleared.  With w = v xor A (A = 0xAAAAAAAA) the value of the low b digits is
+// (w mod 2^b) - (A mod 2^b), so |q - q'_b| = |(w mod 2^b) - (A mod 2^b)|; for
+// b at or above the code's digit count it equals |q|.  d[32] = max |q|.
+struct ErrqAcc {
+  uint32_t d[33];
+};
+
+__device__ __forceinline__ void errq_init(ErrqAcc &a) {
+#pragma unroll
+  for (int b = 0; b < 33; ++b) a.d[b] = 0u;
+}
+
+__device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) { return a > b ? a - b : b - a; }
+
+// Add codes v[j], j = lane, lane + 64, ... < count of one chunk whose codes
+// have at most nb negabinary digits: b < nb per code, b >= nb from the
+// chunk's largest |q|.
+__device__ __forceinline__ void errq_add(ErrqAcc &a, const uint32_t *v, int count, int nb, int lane) {
+  uint32_t qa = 0;
+  for (int j = lane; j < count; j += 64) {
+    uint32_t w = v[pidx(j)] ^ NB_A;
+    int32_t q = int32_t(w - NB_A);
+    uint32_t aq = uint32_t(q < 0 ? -q : q);
+    qa = aq > qa ? aq : qa;
+#pragma unroll
+    for (int b = 1; b < 32; ++b) {
+      if (b < nb) {
+        uint32_t t = absdiff(w & ((1u << b) - 1u), NB_A & ((1u << b) - 1u));
+        a.d[b] = t > a.d[b] ? t : a.d[b];
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 1; b < 33; ++b)
+    if (b >= nb) a.d[b] = qa > a.d[b] ? qa : a.d[b];
+}
+
+// role of thread tid < 112 in the encode / decode of a group of two chunk rows:
+// pass rp, chunk row rsi, plane-word column rw
+__device__ __forceinline__ void row_role(int tid, int &rp, int &rsi, int &rw) {
+  if (tid < 16) { rp = 0; rsi = tid >> 3; rw = tid & 7; }
+  else if (tid < 48) { rp = 1; rsi = (tid - 16) >> 4; rw = (tid - 16) & 15; }
+  else { rp = 2; rsi = (tid - 48) >> 5; rw = (tid - 48) & 31; }
+}
+
+// ------------------------------------------------------------------ compress
+
+template <typename T, int INTERP>
+__global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *__restrict__ x,
+                                                          const T *__restrict__ gin, T *gout,
+                                                          double eb, T two_eb, T inv, T qmax,
+                                                          CompressOut o) {
+  using F = F3<T>;
+  __shared__ Shared3<T> S;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tx = blockIdx.x, ty = blockIdx.y;
+  const int x0 = tx * TX, y0 = ty * TY;
+  const int m0 = int(blockIdx.z) * L.zseg;
+  const int m1 = m0 + L.zseg < L.tiles_z ? m0 + L.zseg : L.tiles_z;
+  const int Lz = L.L[0], Ly = L.L[1], Lx = L.L[2];
+  // offset of level point (z, y, xx) in the fine field
+  auto xin = [&](int z, int y, int xx) -> int64_t {
+    return int64_t(z) * L.sZ + int64_t(y) * L.sY + int64_t(xx) * L.sX;
+  };
+  // wave 0 accumulates delta-y of pass A, wave 1 of pass B, waves 2-3 of pass C
+  const int ep = wave == 0 ? 0 : (wave == 1 ? 1 : 2);
+  ErrqAcc acc;
+  errq_init(acc);
+  unsigned long long mx_abs = 0;
+
+  load_ring_plane(L, gin, S, m0 - 1, y0, x0);
+  load_ring_plane(L, gin, S, m0, y0, x0);
+  load_ring_plane(L, gin, S, m0 + 1, y0, x0);
+
+  auto record = [&](int p, int m, int local, T xv) {
+    unsigned long long slot = atomicAdd(o.n_out, 1ull);
+    if (slot < o.out_cap) {
+      OutlierRec *rr = reinterpret_cast<OutlierRec *>(o.out_recs) + slot;
+      rr->pass = L.pass_index[p];
+      rr->chunk = uint32_t(chunk_id(L, m, ty, tx));
+      rr->local = uint32_t(local);
+      rr->pad = 0;
+      rr->bits = F::bits(xv);
+    }
+  };
+  auto track = [&](T xhat) {
+    double ax = fabs(double(xhat));
+    if (ax <= 1.7976931348623157e308) {
+      unsigned long long bx = (unsigned long long)__double_as_longlong(ax);
+      mx_abs = bx > mx_abs ? bx : mx_abs;
+    }
+  };
+
+  for (int gm = m0; gm < m1; gm += 2) {
+    const int nsteps = (m1 - gm) >= 2 ? 2 : 1;
+    for (int si = 0; si < nsteps; ++si) {
+      const int m = gm + si;
+      const int ze = 2 * m, zo = 2 * m + 1;
+      // ---- one load phase: coarse plane m+2, the tile's inputs, the halo inputs
+      load_ring_plane(L, gin, S, m + 2, y0, x0);
+      {
+        T xv[8];
+        bool xok[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          int t = tid + i * WG3;
+          int zz = t >> 10, yy = (t >> 6) & 15, xx = t & 63;
+          int z = ze + zz, y = y0 + yy, xg = x0 + xx;
+          xok[i] = z < Lz && y < Ly && xg < Lx;
+          xv[i] = x[xok[i] ? xin(z, y, xg) : 0];
+        }
+        T hv = T(0);
+        bool hok = false;
+        int hyj = 0, hxi = 0, hzz = 0, hk = 0;
+        if (tid < NHA) {
+          halo_a(tid, hyj, hxi);
+          int y = y0 - 2 + 2 * hyj, xg = x0 - 2 + 2 * hxi;
+          hok = zo < Lz && unsigned(y) < unsigned(Ly) && unsigned(xg) < unsigned(Lx);
+          hv = x[hok ? xin(zo, y, xg) : 0];
+        } else if (tid < NHA + NHB) {
+          halo_b(tid - NHA, hzz, hk, hxi);
+          int z = ze + hzz, y = y0 + 1 + 2 * hk, xg = x0 - 2 + 2 * hxi;
+          hok = z < Lz && y < Ly && unsigned(xg) < unsigned(Lx);
+          hv = x[hok ? xin(z, y, xg) : 0];
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          int t = tid + i * WG3;
+          S.xs[t >> 10][(t >> 6) & 15][t & 63] = xok[i] ? xv[i] : T(0);
+        }
+        if (tid < NHA)
+          S.xha[hyj][hxi] = hok ? hv : T(0);
+        else if (tid < NHA + NHB)
+          S.xhb[hzz][hk][hxi & 3] = hok ? hv : T(0);
+      }
+      __syncthreads();
+      // ---- pass A (along z) at plane zo on the halo'd even grid
+      if (zo < Lz) {
+        const bool hc = zo + 1 < Lz, ha = zo >= 3, he = zo + 3 < Lz;
+        T(*rb)[NXP] = S.ring[m & 3];
+        T(*rc)[NXP] = S.ring[(m + 1) & 3];
+        T(*ra)[NXP] = S.ring[(m - 1) & 3];
+        T(*re)[NXP] = S.ring[(m + 2) & 3];
+        const Ext ce = chunk_ext(L, 0, m, ty, tx);
+        uint32_t *cb = S.codes + code_off(0, si);
+        for (int t = tid; t < NYE * NXE; t += WG3) {
+          int yj = t / NXE, xi = t - yj * NXE;
+          int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
+          if (unsigned(y) >= unsigned(Ly) || unsigned(xg) >= unsigned(Lx)) continue;
+          bool own = unsigned(yj - 1) < 8u && unsigned(xi - 1) < 32u;
+          T xv = own ? S.xs[1][y - y0][xg - x0] : S.xha[yj][xi];
+          T pred = stencil<T, INTERP>(ha ? ra[yj][xi] : T(0), rb[yj][xi], hc ? rc[yj][xi] : T(0),
+                                      he ? re[yj][xi] : T(0), hc, ha, he);
+          T xhat;
+          bool out;
+          int32_t q = quantize<T>(xv, pred, eb, two_eb, inv, qmax, xhat, out);
+          S.wa[yj][xi] = xhat;
+          if (own) {
+            int local = (yj - 1) * ce.ex + (xi - 1);
+            cb[pidx(local)] = (uint32_t(q) + NB_A) ^ NB_A;
+            if (out) record(0, m, local, xv);
+            track(xhat);
+          }
+        }
+      }
+      __syncthreads();
+      // ---- pass B (along y) at planes ze, zo; odd rows, halo'd even columns
+      {
+        const Ext ce = chunk_ext(L, 1, m, ty, tx);
+        uint32_t *cb = S.codes + code_off(1, si);
+        for (int t = tid; t < 2 * 8 * NXE; t += WG3) {
+          int zz = t >= 8 * NXE ? 1 : 0;
+          int r = t - zz * (8 * NXE);
+          int k = r / NXE, xi = r - k * NXE;
+          int z = ze + zz, y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
+          if (z >= Lz || y >= Ly || unsigned(xg) >= unsigned(Lx)) continue;
+          bool own = unsigned(xi - 1) < 32u;
+          T(*src)[NXP] = zz == 0 ? S.ring[m & 3] : S.wa;
+          const bool hc = y + 1 < Ly, ha = y >= 3, he = y + 3 < Ly;
+          T pred = stencil<T, INTERP>(ha ? src[k][xi] : T(0), src[k + 1][xi], hc ? src[k + 2][xi] : T(0),
+                                      he ? src[k + 3][xi] : T(0), hc, ha, he);
+          T xv = own ? S.xs[zz][2 * k + 1][xg - x0] : S.xhb[zz][k][xi & 3];
+          T xhat;
+          bool out;
+          int32_t q = quantize<T>(xv, pred, eb, two_eb, inv, qmax, xhat, out);
+          S.wb[zz][k][xi] = xhat;
+          if (own) {
+            int local = (zz * ce.ey + k) * ce.ex + (xi - 1);
+            cb[pidx(local)] = (uint32_t(q) + NB_A) ^ NB_A;
+            if (out) record(1, m, local, xv);
+            track(xhat);
+          }
+        }
+      }
+      __syncthreads();
+      // ---- pass C (along x) at planes ze, zo, every row of the tile
+      {
+        const Ext ce = chunk_ext(L, 2, m, ty, tx);
+        uint32_t *cb = S.codes + code_off(2, si);
+        for (int t = tid; t < 2 * 16 * 32; t += WG3) {
+          int zz = t >> 9, yy = (t >> 5) & 15, i = t & 31;
+          int z = ze + zz, y = y0 + yy, xg = x0 + 1 + 2 * i;
+          if (z >= Lz || y >= Ly || xg >= Lx) continue;
+          const T *row = even_row(S, m, zz, yy);
+          const bool hc = xg + 1 < Lx, ha = xg >= 3, he = xg + 3 < Lx;
+          T pred = stencil<T, INTERP>(ha ? row[i] : T(0), row[i + 1], hc ? row[i + 2] : T(0),
+                                      he ? row[i + 3] : T(0), hc, ha, he);
+          T xv = S.xs[zz][yy][2 * i + 1];
+          T xhat;
+          bool out;
+          int32_t q = quantize<T>(xv, pred, eb, two_eb, inv, qmax, xhat, out);
+          S.wc[zz][yy][i] = xhat;
+          int local = (zz * ce.ey + yy) * ce.ex + i;
+          cb[pidx(local)] = (uint32_t(q) + NB_A) ^ NB_A;
+          if (out) record(2, m, local, xv);
+          track(xhat);
+        }
+      }
+      __syncthreads();
+      // ---- the level's output grid (compact), read by the next finer level
+      if (gout) write_rows(L, S, gout, m, y0, x0);
+    }
+    // ---- encode the buffered chunk rows: rows of 32 codes -> plane words
+    if (tid < 6) S.cmask[tid >> 1][tid & 1] = 0;
+    __syncthreads();
+    uint32_t r[32];
+    int rp = -1, rsi = 0, rw = 0, rW = 0;
+    if (tid < 112) {
+      row_role(tid, rp, rsi, rw);
+      if (rsi >= nsteps) rp = -1;
+    }
+    if (rp >= 0) {
+      const Ext rce = chunk_ext(L, rp, gm + rsi, ty, tx);
+      rW = (rce.count + 31) >> 5;
+      if (rw >= rW) {
+        rp = -1;
+      } else {
+        const uint32_t *cb = S.codes + code_off(rp, rsi);
+        uint32_t rowor = 0;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+          int jj = 32 * rw + j;
+          uint32_t v = jj < rce.count ? cb[pidx(jj)] : 0u;
+          r[j] = xenc(v);
+          rowor |= r[j];
+        }
+        transpose32(r);
+        atomicOr(&S.cmask[rp][rsi], rowor);
+      }
+    }
+    __syncthreads();
+    if (rp >= 0) {
+      const uint32_t mask = S.cmask[rp][rsi];
+      const int64_t cid = chunk_id(L, gm + rsi, ty, tx);
+      uint32_t *slot = o.payload + L.slot_base[rp] + uint64_t(cid) * 32u * L.wmax[rp] + rw;
+#pragma unroll
+      for (int k = 0; k < 32; ++k)
+        if ((mask >> k) & 1u) slot[(31 - k) * rW] = r[k];
+      if (rw == 0) o.masks[L.chunk_base[rp] + cid] = mask;
+    }
+    if (tid < 6) {  // empty chunks of this group still get a zero mask
+      int p = tid >> 1, s2 = tid & 1;
+      if (s2 < nsteps && chunk_ext(L, p, gm + s2, ty, tx).count == 0)
+        o.masks[L.chunk_base[p] + chunk_id(L, gm + s2, ty, tx)] = 0u;
+    }
+    // ---- delta-y: each wave adds the codes of its pass
+    if (ep == 2) {
+      int s2 = wave - 2;
+      if (s2 < nsteps) {
+        uint32_t mk = S.cmask[2][s2];
+        errq_add(acc, S.codes + code_off(2, s2), chunk_ext(L, 2, gm + s2, ty, tx).count,
+                 mk ? 32 - __clz(mk) : 0, lane);
+      }
+    } else {
+      for (int s2 = 0; s2 < nsteps; ++s2) {
+        uint32_t mk = S.cmask[ep][s2];
+        errq_add(acc, S.codes + code_off(ep, s2), chunk_ext(L, ep, gm + s2, ty, tx).count,
+                 mk ? 32 - __clz(mk) : 0, lane);
+      }
+    }
+    __syncthreads();
+  }
+  // ---- workgroup totals: per-pass delta-y and max |x^|
+  if (tid < 3 * 33) (&S.eq[0][0])[tid] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int b = 1; b < 33; ++b)
+    if (acc.d[b] != 0u) atomicMax(&S.eq[ep][b], acc.d[b]);
+  {
+    unsigned long long v = mx_abs;
+#pragma unroll
+    for (int o2 = 32; o2 > 0; o2 >>= 1) {
+      unsigned long long u = __shfl_xor(v, o2, 64);
+      v = u > v ? u : v;
+    }
+    if (lane == 0 && v > *o.maxabs_bits) atomicMax(o.maxabs_bits, v);
+  }
+  __syncthreads();
+  if (tid < 3 * 33) {
+    int p = tid / 33, b = tid - p * 33;
+    uint32_t val = S.eq[p][b];
+    uint32_t *dst = o.errq + size_t(L.pass_index[p]) * 33 + b;
+    if (b > 0 && val > *dst) atomicMax(dst, val);
+  }
+}
+
+// ------------------------------------------------------------------ retrieve
+
+template <typename T, int INTERP>
+__global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *__restrict__ gin,
+                                                          T *gout, int discA, int discB, int discC,
+                                                          RetrieveIn in, T two_eb) {
+  using F = F3<T>;
+  __shared__ Shared3<T> S;
+  const int tid = threadIdx.x;
+  const int tx = blockIdx.x, ty = blockIdx.y;
+  const int x0 = tx * TX, y0 = ty * TY;
+  const int m0 = int(blockIdx.z) * L.zseg;
+  const int m1 = m0 + L.zseg < L.tiles_z ? m0 + L.zseg : L.tiles_z;
+  const int Lz = L.L[0], Ly = L.L[1], Lx = L.L[2];
+  const uint32_t keep[3] = {discA >= 32 ? 0u : (0xFFFFFFFFu << discA),
+                            discB >= 32 ? 0u : (0xFFFFFFFFu << discB),
+                            discC >= 32 ? 0u : (0xFFFFFFFFu << discC)};
+  const bool has_out = in.n_out > 0;
+  const bool packed = in.chunk_off != nullptr;
+
+  load_ring_plane(L, gin, S, m0 - 1, y0, x0);
+  load_ring_plane(L, gin, S, m0, y0, x0);
+  load_ring_plane(L, gin, S, m0 + 1, y0, x0);
+
+  // reconstruction pred + q * 2eb from the negabinary code v
+  auto value = [&](T pred, uint32_t v) -> T {
+    T tq;
+    if constexpr (sizeof(T) == 4)
+      tq = T(int32_t((v ^ NB_A) - NB_A));
+    else
+      tq = T(int64_t(v ^ NB_A) - int64_t(NB_A));
+    return F::add(pred, F::mul(tq, two_eb));
+  };
+
+  for (int gm = m0; gm < m1; gm += 2) {
+    const int nsteps = (m1 - gm) >= 2 ? 2 : 1;
+    // ---- decode the own codes of the next two chunk rows
+    if (tid < 112) {
+      int rp, rsi, rw;
+      row_role(tid, rp, rsi, rw);
+      if (rsi < nsteps) {
+        const Ext ce = chunk_ext(L, rp, gm + rsi, ty, tx);
+        const int W = (ce.count + 31) >> 5;
+        if (rw < W) {
+          const int64_t cid = chunk_id(L, gm + rsi, ty, tx);
+          const uint32_t mask = in.masks[L.chunk_base[rp] + cid];
+          const uint32_t kp = keep[rp];
+          const uint32_t load = mask & kp;
+          const uint32_t *base = in.payload + chunk_words(L, in, rp, cid) + rw;
+          uint32_t r[32];
+#pragma unroll
+          for (int k = 0; k < 32; ++k) {
+            bool on = (load >> k) & 1u;
+            uint32_t w = *(on ? base + plane_rank(packed, mask, k) * uint32_t(W) : in.payload);
+            r[k] = on ? w : 0u;
+          }
+          transpose32(r);
+          uint32_t *cb = S.codes + code_off(rp, rsi);
+#pragma unroll
+          for (int j = 0; j < 32; ++j) {
+            int jj = 32 * rw + j;
+            if (jj < ce.count) cb[pidx(jj)] = xdec(r[j]) & kp;
+          }
+        }
+      }
+    }
+    for (int si = 0; si < nsteps; ++si) {
+      const int m = gm + si;
+      const int ze = 2 * m, zo = 2 * m + 1;
+      // ---- one load phase: coarse plane m+2 and the codes of the halo targets
+      load_ring_plane(L, gin, S, m + 2, y0, x0);
+      if (tid < NHA) {
+        int yj, xi;
+        halo_a(tid, yj, xi);
+        int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
+        if (zo < Lz && unsigned(y) < unsigned(Ly) && unsigned(xg) < unsigned(Lx)) {
+          int tyn, oy, txn, ox;
+          halo_tile(ty, yj, 8, tyn, oy);
+          halo_tile(tx, xi, 32, txn, ox);
+          S.hva[yj][xi] = fetch_code(L, in, 0, m, tyn, txn, 0, oy, ox, keep[0]);
+        }
+      } else if (tid < NHA + NHB) {
+        int zz, k, xi;
+        halo_b(tid - NHA, zz, k, xi);
+        int z = ze + zz, y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
+        if (z < Lz && y < Ly && unsigned(xg) < unsigned(Lx)) {
+          int txn, ox;
+          halo_tile(tx, xi, 32, txn, ox);
+          S.hvb[zz][k][xi & 3] = fetch_code(L, in, 1, m, ty, txn, zz, k, ox, keep[1]);
+        }
+      }
+      __syncthreads();
+      // ---- pass A
+      if (zo < Lz) {
+        const bool hc = zo + 1 < Lz, ha = zo >= 3, he = zo + 3 < Lz;
+        T(*rb)[NXP] = S.ring[m & 3];
+        T(*rc)[NXP] = S.ring[(m + 1) & 3];
+        T(*ra)[NXP] = S.ring[(m - 1) & 3];
+        T(*re)[NXP] = S.ring[(m + 2) & 3];
+        const Ext ce = chunk_ext(L, 0, m, ty, tx);
+        const uint32_t *cb = S.codes + code_off(0, si);
+        for (int t = tid; t < NYE * NXE; t += WG3) {
+          int yj = t / NXE, xi = t - yj * NXE;
+          int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
+          if (unsigned(y) >= unsigned(Ly) || unsigned(xg) >= unsigned(Lx)) continue;
+          bool own = unsigned(yj - 1) < 8u && unsigned(xi - 1) < 32u;
+          uint32_t v = own ? cb[pidx((yj - 1) * ce.ex + (xi - 1))] : S.hva[yj][xi];
+          T pred = stencil<T, INTERP>(ha ? ra[yj][xi] : T(0), rb[yj][xi], hc ? rc[yj][xi] : T(0),
+                                      he ? re[yj][xi] : T(0), hc, ha, he);
+          T val = value(pred, v);
+          if (has_out) {
+            int tyn, oy, txn, ox;
+            halo_tile(ty, yj, 8, tyn, oy);
+            halo_tile(tx, xi, 32, txn, ox);
+            const Ext e = chunk_ext(L, 0, m, tyn, txn);
+            uint64_t ob;
+            if (find_outlier(in, uint64_t(L.chunk_base[0] + chunk_id(L, m, tyn, txn)),
+                             uint32_t(oy * e.ex + ox), ob))
+              val = F::from_bits(ob);
+          }
+          S.wa[yj][xi] = val;
+        }
+      }
+      __syncthreads();
+      // ---- pass B
+      {
+        const Ext ce = chunk_ext(L, 1, m, ty, tx);
+        const uint32_t *cb = S.codes + code_off(1, si);
+        for (int t = tid; t < 2 * 8 * NXE; t += WG3) {
+          int zz = t >= 8 * NXE ? 1 : 0;
+          int r = t - zz * (8 * NXE);
+          int k = r / NXE, xi = r - k * NXE;
+          int z = ze + zz, y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
+          if (z >= Lz || y >= Ly || unsigned(xg) >= unsigned(Lx)) continue;
+          bool own = unsigned(xi - 1) < 32u;
+          uint32_t v = own ? cb[pidx((zz * ce.ey + k) * ce.ex + (xi - 1))] : S.hvb[zz][k][xi & 3];
+          T(*src)[NXP] = zz == 0 ? S.ring[m & 3] : S.wa;
+          const bool hc = y + 1 < Ly, ha = y >= 3, he = y + 3 < Ly;
+          T pred = stencil<T, INTERP>(ha ? src[k][xi] : T(0), src[k + 1][xi], hc ? src[k + 2][xi] : T(0),
+                                      he ? src[k + 3][xi] : T(0), hc, ha, he);
+          T val = value(pred, v);
+          if (has_out) {
+            int txn, ox;
+            halo_tile(tx, xi, 32, txn, ox);
+            const Ext e = chunk_ext(L, 1, m, ty, txn);
+            uint64_t ob;
+            if (find_outlier(in, uint64_t(L.chunk_base[1] + chunk_id(L, m, ty, txn)),
+                             uint32_t((zz * e.ey + k) * e.ex + ox), ob))
+              val = F::from_bits(ob);
+          }
+          S.wb[zz][k][xi] = val;
+        }
+      }
+      __syncthreads();
+      // ---- pass C
+      {
+        const Ext ce = chunk_ext(L, 2, m, ty, tx);
+        const uint64_t gch = uint64_t(L.chunk_base[2] + chunk_id(L, m, ty, tx));
+        const uint32_t *cb = S.codes + code_off(2, si);
+        for (int t = tid; t < 2 * 16 * 32; t += WG3) {
+          int zz = t >> 9, yy = (t >> 5) & 15, i = t & 31;
+          int z = ze + zz, y = y0 + yy, xg = x0 + 1 + 2 * i;
+          if (z >= Lz || y >= Ly || xg >= Lx) continue;
+          const T *row = even_row(S, m, zz, yy);
+          const bool hc = xg + 1 < Lx, ha = xg >= 3, he = xg + 3 < Lx;
+          T pred = stencil<T, INTERP>(ha ? row[i] : T(0), row[i + 1], hc ? row[i + 2] : T(0),
+                                      he ? row[i + 3] : T(0), hc, ha, he);
+          uint32_t local = uint32_t((zz * ce.ey + yy) * ce.ex + i);
+          T val = value(pred, cb[pidx(int(local))]);
+          uint64_t ob;
+          if (has_out && find_outlier(in, gch, local, ob)) val = F::from_bits(ob);
+          S.wc[zz][yy][i] = val;
+        }
+      }
+      __syncthreads();
+      write_rows(L, S, gout, m, y0, x0);
+    }
+    __syncthreads();
+  }
+}
+
+// anchors of a fused compression: quantize against 0 into the compact coarse grid
+template <typename T>
+__global__ void k_anchor3_compress(Level3Args L, const T *__restrict__ x, T *gout, double eb,
+                                   T two_eb, T inv, T qmax, CompressOut o) {
+  using F = F3<T>;
+  __shared__ uint32_t sv[64];
+  __shared__ uint32_t sor;
+  const int tid = threadIdx.x;
+  const int n = L.L[0] * L.L[1] * L.L[2];  // anchor grid (<= 2 per dimension)
+  if (tid == 0) sor = 0;
+  __syncthreads();
+  unsigned long long mb = 0;
+  if (tid < n) {
+    int az = tid / (L.L[1] * L.L[2]), r = tid - az * (L.L[1] * L.L[2]);
+    int ay = r / L.L[2], ax = r - ay * L.L[2];
+    T xv = x[int64_t(az) * L.sZ + int64_t(ay) * L.sY + int64_t(ax) * L.sX];
+    T xhat;
+    bool out;
+    int32_t q = quantize<T>(xv, T(0), eb, two_eb, inv, qmax, xhat, out);
+    gout[tid] = xhat;
+    uint32_t v = (uint32_t(q) + NB_A) ^ NB_A;
+    sv[tid] = v;
+    atomicOr(&sor, xenc(v));
+    if (out) {
+      unsigned long long slot = atomicAdd(o.n_out, 1ull);
+      if (slot < o.out_cap) {
+        OutlierRec *rr = reinterpret_cast<OutlierRec *>(o.out_recs) + slot;
+        rr->pass = 0;
+        rr->chunk = 0;
+        rr->local = uint32_t(tid);
+        rr->pad = 0;
+        rr->bits = F::bits(xv);
+      }
+    }
+    double ax2 = fabs(double(xhat));
+    if (ax2 <= 1.7976931348623157e308) mb = (unsigned long long)__double_as_longlong(ax2);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t mask = sor;
+    uint32_t r[32];
+    for (int j = 0; j < 32; ++j) r[j] = j < n ? xenc(sv[j]) : 0u;
+    transpose32(r);
+    for (int k = 0; k < 32; ++k)
+      if ((mask >> k) & 1u) o.payload[L.slot_base[0] + uint64_t(31 - k)] = r[k];
+    o.masks[L.chunk_base[0]] = mask;
+    // delta-y of the anchors (always loaded; kept for completeness)
+    for (int b = 1; b <= 32; ++b) {
+      uint32_t mxv = 0;
+      for (int j = 0; j < n; ++j) {
+        uint32_t w = sv[j] ^ NB_A;
+        uint32_t mm = b == 32 ? 0xFFFFFFFFu : ((1u << b) - 1u);
+        uint32_t ab = NB_A & mm, t = w & mm;
+        uint32_t d = t >= ab ? t - ab : ab - t;
+        mxv = d > mxv ? d : mxv;
+      }
+      atomicMax(o.errq + b, mxv);
+    }
+  }
+  if (mb) atomicMax(o.maxabs_bits, mb);
+}
+
+// anchors of a fused retrieval
+template <typename T>
+__global__ void k_anchor3_retrieve(Level3Args L, T *gout, RetrieveIn in, T two_eb) {
+  using F = F3<T>;
+  const int tid = threadIdx.x;
+  const int n = L.L[0] * L.L[1] * L.L[2];
+  if (tid >= n) return;
+  const uint32_t mask = in.masks[L.chunk_base[0]];
+  const bool packed = in.chunk_off != nullptr;
+  const uint64_t base = packed ? in.chunk_off[L.chunk_base[0]] : L.slot_base[0];
+  uint32_t e = 0;
+  for (int k = 31; k >= 0; --k) {
+    if (!((mask >> k) & 1u)) continue;
+    e |= ((in.payload[base + plane_rank(packed, mask, k)] >> tid) & 1u) << k;
+  }
+  uint32_t v = xdec(e);
+  int64_t q = int64_t(v ^ NB_A) - int64_t(NB_A);
+  T tq = sizeof(T) == 4 ? T(int32_t(q)) : T(q);
+  T val = F::add(T(0), F::mul(tq, two_eb));
+  uint64_t ob;
+  if (in.n_out > 0 && find_outlier(in, uint64_t(L.chunk_base[0]), uint32_t(tid), ob)) val = F::from_bits(ob);
+  gout[tid] = val;
+}
+
+template <typename T>
+__global__ void k_gather_coarse(const T *__restrict__ field, int64_t fd1, int64_t fd2, int64_t s,
+                                T *g, int64_t g0, int64_t g1, int64_t g2) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int64_t n = g0 * g1 * g2;
+  if (i >= n) return;
+  int64_t c2 = i % g2, r = i / g2, c1 = r % g1, c0 = r / g1;
+  g[i] = field[((s * c0) * fd1 + s * c1) * fd2 + s * c2];
+}
+
+}  // namespace
+
+hipError_t launch_level3_compress(int dtype, int interp, const Level3Args &L, const void *x,
+                                  const void *gin, void *gout, double eb, const CompressOut &o,
+                                  hipStream_t s) {
+  dim3 grid(uint32_t(L.tiles_x), uint32_t(L.tiles_y), uint32_t((L.tiles_z + L.zseg - 1) / L.zseg));
+  if (dtype == IPC_F32) {
+    float two_eb = float(2.0 * eb), inv = float(1.0 / (2.0 * eb)), qm = float(QMAX_F32);
+    if (interp == IPC_LINEAR)
+      hipLaunchKernelGGL((k_level3_compress<float, IPC_LINEAR>), grid, dim3(WG3), 0, s, L,
+                         (const float *)x, (const float *)gin, (float *)gout, eb, two_eb, inv, qm, o);
+    else
+      hipLaunchKernelGGL((k_level3_compress<float, IPC_CUBIC>), grid, dim3(WG3), 0, s, L,
+                         (const float *)x, (const float *)gin, (float *)gout, eb, two_eb, inv, qm, o);
+  } else {
+    double two_eb = 2.0 * eb, inv = 1.0 / (2.0 * eb), qm = double(QMAX_F64);
+    if (interp == IPC_LINEAR)
+      hipLaunchKernelGGL((k_level3_compress<double, IPC_LINEAR>), grid, dim3(WG3), 0, s, L,
+                         (const double *)x, (const double *)gin, (double *)gout, eb, two_eb, inv, qm, o);
+    else
+      hipLaunchKernelGGL((k_level3_compress<double, IPC_CUBIC>), grid, dim3(WG3), 0, s, L,
+                         (const double *)x, (const double *)gin, (double *)gout, eb, two_eb, inv, qm, o);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_level3_retrieve(int dtype, int interp, const Level3Args &L, const void *gin,
+                                  void *gout, const int disc[3], const RetrieveIn &in, double eb,
+                                  hipStream_t s) {
+  dim3 grid(uint32_t(L.tiles_x), uint32_t(L.tiles_y), uint32_t((L.tiles_z + L.zseg - 1) / L.zseg));
+  if (dtype == IPC_F32) {
+    float two_eb = float(2.0 * eb);
+    if (interp == IPC_LINEAR)
+      hipLaunchKernelGGL((k_level3_retrieve<float, IPC_LINEAR>), grid, dim3(WG3), 0, s, L,
+                         (const float *)gin, (float *)gout, disc[0], disc[1], disc[2], in, two_eb);
+    else
+      hipLaunchKernelGGL((k_level3_retrieve<float, IPC_CUBIC>), grid, dim3(WG3), 0, s, L,
+                         (const float *)gin, (float *)gout, disc[0], disc[1], disc[2], in, two_eb);
+  } else {
+    double two_eb = 2.0 * eb;
+    if (interp == IPC_LINEAR)
+      hipLaunchKernelGGL((k_level3_retrieve<double, IPC_LINEAR>), grid, dim3(WG3), 0, s, L,
+                         (const double *)gin, (double *)gout, disc[0], disc[1], disc[2], in, two_eb);
+    else
+      hipLaunchKernelGGL((k_level3_retrieve<double, IPC_CUBIC>), grid, dim3(WG3), 0, s, L,
+                         (const double *)gin, (double *)gout, disc[0], disc[1], disc[2], in, two_eb);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_anchor3_compress(int dtype, const Level3Args &A, const void *x, void *gout,
+                                   double eb, const CompressOut &o, hipStream_t s) {
+  if (dtype == IPC_F32)
+    hipLaunchKernelGGL(k_anchor3_compress<float>, dim3(1), dim3(64), 0, s, A, (const float *)x,
+                       (float *)gout, eb, float(2.0 * eb), float(1.0 / (2.0 * eb)), float(QMAX_F32), o);
+  else
+    hipLaunchKernelGGL(k_anchor3_compress<double>, dim3(1), dim3(64), 0, s, A, (const double *)x,
+                       (double *)gout, eb, 2.0 * eb, 1.0 / (2.0 * eb), double(QMAX_F64), o);
+  return hipGetLastError();
+}
+
+hipError_t launch_anchor3_retrieve(int dtype, const Level3Args &A, void *gout, const RetrieveIn &in,
+                                   double eb, hipStream_t s) {
+  if (dtype == IPC_F32)
+    hipLaunchKernelGGL(k_anchor3_retrieve<float>, dim3(1), dim3(64), 0, s, A, (float *)gout, in,
+                       float(2.0 * eb));
+  else
+    hipLaunchKernelGGL(k_anchor3_retrieve<double>, dim3(1), dim3(64), 0, s, A, (double *)gout, in,
+                       2.0 * eb);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_coarse(int dtype, const void *field, const int64_t fd[3], int64_t step,
+                                void *g, const int64_t gd[3], hipStream_t s) {
+  int64_t n = gd[0] * gd[1] * gd[2];
+  if (n == 0) return hipSuccess;
+  dim3 grid(uint32_t((n + 255) / 256));
+  if (dtype == IPC_F32)
+    hipLaunchKernelGGL(k_gather_coarse<float>, grid, dim3(256), 0, s, (const float *)field, fd[1],
+                       fd[2], step, (float *)g, gd[0], gd[1], gd[2]);
+  else
+    hipLaunchKernelGGL(k_gather_coarse<double>, grid, dim3(256), 0, s, (const double *)field, fd[1],
+                       fd[2], step, (double *)g, gd[0], gd[1], gd[2]);
+  return hipGetLastError();
+}
+
+}  // namespace ipc

@@ -61,6 +61,12 @@ CASES = [
     ((20, 21, 70), np.float32, predict.CUBIC, 1e-5, (1, 2, 3), 0, True),
     ((40, 50, 130), np.float32, predict.CUBIC, 1e-4, None, 2, False),
     ((3, 1, 700), np.float32, predict.CUBIC, 1e-4, None, 0, False),
+    ((2, 2, 2), np.float32, predict.CUBIC, 1e-3, None, 0, False),
+    ((1, 1, 5), np.float64, predict.CUBIC, 1e-3, None, 0, False),
+    ((5, 70, 130), np.float32, predict.CUBIC, 1e-4, None, 0, True),
+    ((33, 17, 65), np.float64, predict.CUBIC, 1e-6, None, 0, True),
+    ((64, 96, 200), np.float32, predict.LINEAR, 1e-5, None, 0, False),
+    ((65, 33, 129), np.float32, predict.CUBIC, 1e-3, None, 1, True),
 ]
 
 
