@@ -63,7 +63,7 @@ struct ipc_stream {
   DevBuf payload;              // u32 words
   DevBuf masks;                // u32 per chunk
   DevBuf chunk_off;            // u64 per chunk (packed placement only)
-  DevBuf out_gchunk, out_local, out_bits;
+  DevBuf out_gchunk, out_local, out_bits, out_start;
   bool host_masks_valid = false;
   std::vector<PassArgs> args;
 };
@@ -245,6 +245,7 @@ void free_stream_bufs(ipc_stream *s) {
   dev_free(c, s->out_gchunk);
   dev_free(c, s->out_local);
   dev_free(c, s->out_bits);
+  dev_free(c, s->out_start);
 }
 
 void upload_outliers(ipc_ctx *ctx, ipc_stream *s) {
@@ -264,6 +265,11 @@ void upload_outliers(ipc_ctx *ctx, ipc_stream *s) {
   hip_check(ctx, hipMemcpyAsync(s->out_gchunk.p, gch.data(), 8 * n, hipMemcpyHostToDevice, ctx->stream), "upload");
   hip_check(ctx, hipMemcpyAsync(s->out_local.p, loc.data(), 4 * n, hipMemcpyHostToDevice, ctx->stream), "upload");
   hip_check(ctx, hipMemcpyAsync(s->out_bits.p, bits.data(), 8 * n, hipMemcpyHostToDevice, ctx->stream), "upload");
+  const uint64_t nc = uint64_t(s->meta.sched.n_chunks);
+  s->out_start = dev_alloc(ctx, 4 * (nc + 1));
+  hip_check(ctx, launch_out_start(static_cast<const uint64_t *>(s->out_gchunk.p), n, nc,
+                                  static_cast<uint32_t *>(s->out_start.p), ctx->stream),
+            "outlier index launch");
   hip_check(ctx, hipStreamSynchronize(ctx->stream), "upload");
 }
 
@@ -378,6 +384,7 @@ void run_retrieve(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &pla
   in.out_gchunk = static_cast<const uint64_t *>(s->out_gchunk.p);
   in.out_local = static_cast<const uint32_t *>(s->out_local.p);
   in.out_bits = static_cast<const uint64_t *>(s->out_bits.p);
+  in.out_start = static_cast<const uint32_t *>(s->out_start.p);
   in.n_out = s->meta.outliers.size();
   prof_begin(ctx, s->args.size());
   const Schedule &sc = s->meta.sched;

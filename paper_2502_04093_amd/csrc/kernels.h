@@ -42,6 +42,7 @@ struct RetrieveIn {
   const uint64_t *out_gchunk; // outliers sorted by (global chunk, local)
   const uint32_t *out_local;
   const uint64_t *out_bits;
+  const uint32_t *out_start;  // first outlier of each global chunk (n_chunks + 1 entries)
   uint64_t n_out;
 };
 
@@ -81,6 +82,10 @@ hipError_t launch_compress_pass(int dtype, int interp, const PassArgs &pa, const
                                 hipStream_t stream);
 hipError_t launch_retrieve_pass(int dtype, int interp, const PassArgs &pa, void *field,
                                 int discard, const RetrieveIn &in, double eb, hipStream_t stream);
+// out_start[c] = index of the first outlier whose global chunk is >= c, for
+// c = 0 .. n_chunks (outliers sorted by global chunk)
+hipError_t launch_out_start(const uint64_t *out_gchunk, uint64_t n_out, uint64_t n_chunks,
+                            uint32_t *out_start, hipStream_t stream);
 // sizes[p][k] for every pass at once (args_dev: the passes' PassArgs on the device)
 hipError_t launch_all_sizes(const PassArgs *args_dev, int n_passes, int64_t max_chunks,
                             const uint32_t *masks, unsigned long long *sizes, hipStream_t stream);

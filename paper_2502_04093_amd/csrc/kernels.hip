@@ -400,6 +400,17 @@ __global__ __launch_bounds__(WG) void k_retrieve(PassArgs a, T *f, int discard, 
   }
 }
 
+__global__ void k_out_start(const uint64_t *keys, uint64_t n, uint64_t n_chunks, uint32_t *start) {
+  uint64_t c = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c > n_chunks) return;
+  uint64_t a0 = 0, a1 = n;
+  while (a0 < a1) {
+    uint64_t m = (a0 + a1) >> 1;
+    if (keys[m] < c) a0 = m + 1; else a1 = m;
+  }
+  start[c] = uint32_t(a0);
+}
+
 __global__ __launch_bounds__(WG) void k_pass_sizes(PassArgs a, const uint32_t *masks,
                                                     unsigned long long *sizes) {
   __shared__ unsigned long long s_acc;
@@ -538,6 +549,13 @@ hipError_t launch_pack_payload(const PassArgs &pa, const uint32_t *masks,
   if (pa.n_chunks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_pack, dim3(uint32_t(pa.n_chunks)), dim3(WG), 0, stream, pa, masks,
                      packed_off, slot_payload, packed);
+  return hipGetLastError();
+}
+
+hipError_t launch_out_start(const uint64_t *out_gchunk, uint64_t n_out, uint64_t n_chunks,
+                            uint32_t *out_start, hipStream_t stream) {
+  dim3 grid(uint32_t((n_chunks + 1 + 255) / 256));
+  hipLaunchKernelGGL(k_out_start, grid, dim3(256), 0, stream, out_gchunk, n_out, n_chunks, out_start);
   return hipGetLastError();
 }
 

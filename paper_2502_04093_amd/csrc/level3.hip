@@ -146,17 +146,15 @@ __device__ __forceinline__ uint32_t plane_rank(bool packed, uint32_t mask, int k
   return packed ? uint32_t(__popc((mask >> k) >> 1)) : uint32_t(31 - k);
 }
 
-// outlier lookup: value bits of (global chunk, local) if stored
-__device__ __forceinline__ bool find_outlier(const RetrieveIn &in, uint64_t gch, uint32_t local,
-                                             uint64_t &bits) {
-  uint64_t a0 = 0, a1 = in.n_out;
+// outlier lookup inside the sorted range [a0, a1) of one chunk
+__device__ __forceinline__ bool find_outlier(const RetrieveIn &in, uint32_t a0, uint32_t a1,
+                                             uint32_t local, uint64_t &bits) {
+  const uint32_t end = a1;
   while (a0 < a1) {
-    uint64_t m = (a0 + a1) >> 1;
-    uint64_t kg = in.out_gchunk[m];
-    bool less = kg < gch || (kg == gch && in.out_local[m] < local);
-    if (less) a0 = m + 1; else a1 = m;
+    uint32_t m = (a0 + a1) >> 1;
+    if (in.out_local[m] < local) a0 = m + 1; else a1 = m;
   }
-  if (a0 < in.n_out && in.out_gchunk[a0] == gch && in.out_local[a0] == local) {
+  if (a0 < end && in.out_local[a0] == local) {
     bits = in.out_bits[a0];
     return true;
   }
@@ -234,6 +232,7 @@ struct Shared3 {
   uint32_t hvb[2][8][4];    //           codes of pass-B halo targets
   uint32_t codes[2 * PADA + 2 * PADB + 2 * PADC];
   uint32_t cmask[3][2];
+  uint32_t orng[13][2];     // retrieve: outlier ranges of the step's chunks
   uint32_t eq[3][33];       // per workgroup delta-y of each pass
 };
 
@@ -706,7 +705,24 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
           S.hvb[zz][k][xi & 3] = fetch_code(L, in, 1, m, ty, txn, zz, k, ox, keep[1]);
         }
       }
-      __syncthreads();
+      // outlier ranges of the chunks the step reads: pass A (m, ty-1..ty+1,
+      // tx-1..tx+1), pass B (m, ty, tx-1..tx+1), pass C (m, ty, tx)
+      int any_out = 0;
+      if (has_out && tid < 13) {
+        int p = tid < 9 ? 0 : (tid < 12 ? 1 : 2);
+        int tyn = tid < 9 ? ty - 1 + tid / 3 : ty;
+        int txn = tid < 9 ? tx - 1 + tid % 3 : (tid < 12 ? tx - 10 + tid : tx);
+        uint32_t a = 0, b = 0;
+        if (unsigned(tyn) < unsigned(L.tiles_y) && unsigned(txn) < unsigned(L.tiles_x)) {
+          const uint64_t g = uint64_t(L.chunk_base[p] + chunk_id(L, m, tyn, txn));
+          a = in.out_start[g];
+          b = in.out_start[g + 1];
+        }
+        S.orng[tid][0] = a;
+        S.orng[tid][1] = b;
+        any_out = b > a;
+      }
+      any_out = __builtin_amdgcn_readfirstlane(__syncthreads_or(any_out));
       // ---- pass A
       if (zo < Lz) {
         const bool hc = zo + 1 < Lz, ha = zo >= 3, he = zo + 3 < Lz;
@@ -725,15 +741,17 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
           T pred = stencil<T, INTERP>(ha ? ra[yj][xi] : T(0), rb[yj][xi], hc ? rc[yj][xi] : T(0),
                                       he ? re[yj][xi] : T(0), hc, ha, he);
           T val = value(pred, v);
-          if (has_out) {
-            int tyn, oy, txn, ox;
-            halo_tile(ty, yj, 8, tyn, oy);
-            halo_tile(tx, xi, 32, txn, ox);
-            const Ext e = chunk_ext(L, 0, m, tyn, txn);
-            uint64_t ob;
-            if (find_outlier(in, uint64_t(L.chunk_base[0] + chunk_id(L, m, tyn, txn)),
-                             uint32_t(oy * e.ex + ox), ob))
-              val = F::from_bits(ob);
+          if (any_out) {
+            const int ri = (yj == 0 ? 0 : (yj <= 8 ? 3 : 6)) + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
+            const uint32_t a0 = S.orng[ri][0], a1 = S.orng[ri][1];
+            if (a1 > a0) {
+              int tyn, oy, txn, ox;
+              halo_tile(ty, yj, 8, tyn, oy);
+              halo_tile(tx, xi, 32, txn, ox);
+              const Ext e = chunk_ext(L, 0, m, tyn, txn);
+              uint64_t ob;
+              if (find_outlier(in, a0, a1, uint32_t(oy * e.ex + ox), ob)) val = F::from_bits(ob);
+            }
           }
           S.wa[yj][xi] = val;
         }
@@ -756,14 +774,17 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
           T pred = stencil<T, INTERP>(ha ? src[k][xi] : T(0), src[k + 1][xi], hc ? src[k + 2][xi] : T(0),
                                       he ? src[k + 3][xi] : T(0), hc, ha, he);
           T val = value(pred, v);
-          if (has_out) {
-            int txn, ox;
-            halo_tile(tx, xi, 32, txn, ox);
-            const Ext e = chunk_ext(L, 1, m, ty, txn);
-            uint64_t ob;
-            if (find_outlier(in, uint64_t(L.chunk_base[1] + chunk_id(L, m, ty, txn)),
-                             uint32_t((zz * e.ey + k) * e.ex + ox), ob))
-              val = F::from_bits(ob);
+          if (any_out) {
+            const int ri = 9 + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
+            const uint32_t a0 = S.orng[ri][0], a1 = S.orng[ri][1];
+            if (a1 > a0) {
+              int txn, ox;
+              halo_tile(tx, xi, 32, txn, ox);
+              const Ext e = chunk_ext(L, 1, m, ty, txn);
+              uint64_t ob;
+              if (find_outlier(in, a0, a1, uint32_t((zz * e.ey + k) * e.ex + ox), ob))
+                val = F::from_bits(ob);
+            }
           }
           S.wb[zz][k][xi] = val;
         }
@@ -772,7 +793,7 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
       // ---- pass C
       {
         const Ext ce = chunk_ext(L, 2, m, ty, tx);
-        const uint64_t gch = uint64_t(L.chunk_base[2] + chunk_id(L, m, ty, tx));
+        const uint32_t oc0 = any_out ? S.orng[12][0] : 0u, oc1 = any_out ? S.orng[12][1] : 0u;
         const uint32_t *cb = S.codes + code_off(2, si);
         for (int t = tid; t < 2 * 16 * 32; t += WG3) {
           int zz = t >> 9, yy = (t >> 5) & 15, i = t & 31;
@@ -785,7 +806,7 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
           uint32_t local = uint32_t((zz * ce.ey + yy) * ce.ex + i);
           T val = value(pred, cb[pidx(int(local))]);
           uint64_t ob;
-          if (has_out && find_outlier(in, gch, local, ob)) val = F::from_bits(ob);
+          if (oc1 > oc0 && find_outlier(in, oc0, oc1, local, ob)) val = F::from_bits(ob);
           S.wc[zz][yy][i] = val;
         }
       }
@@ -878,7 +899,9 @@ __global__ void k_anchor3_retrieve(Level3Args L, T *gout, RetrieveIn in, T two_e
   T tq = sizeof(T) == 4 ? T(int32_t(q)) : T(q);
   T val = F::add(T(0), F::mul(tq, two_eb));
   uint64_t ob;
-  if (in.n_out > 0 && find_outlier(in, uint64_t(L.chunk_base[0]), uint32_t(tid), ob)) val = F::from_bits(ob);
+  if (in.n_out > 0 && find_outlier(in, in.out_start[L.chunk_base[0]], in.out_start[L.chunk_base[0] + 1],
+                                   uint32_t(tid), ob))
+    val = F::from_bits(ob);
   gout[tid] = val;
 }
 

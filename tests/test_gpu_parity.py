@@ -125,6 +125,36 @@ def test_partial_retrieve_and_refine_match_oracle(ctx, dtype):
     s.free()
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_dense_outliers(ctx, dtype):
+    """About 1 % unpredictable values (NaN, inf, huge) spread over a field whose
+    level grids span several chunk columns, so outliers fall inside the halos
+    that neighbouring workgroups recompute."""
+    shape = (21, 70, 200)
+    x = fieldgen.random_field(shape, seed=11, dtype=dtype)
+    rng = np.random.default_rng(5)
+    f = x.reshape(-1)
+    idx = rng.choice(f.size, size=f.size // 100, replace=False)
+    kinds = rng.integers(0, 4, size=idx.size)
+    big = dtype(3e37) if dtype == np.float32 else 3e300
+    f[idx] = np.where(kinds == 0, np.nan, np.where(kinds == 1, np.inf, np.where(kinds == 2, -big, big)))
+    eb = 1e-3
+    ref, dbg = codec.compress(x, eb, debug=True)
+    s = ctx.compress(_dev(x), eb)
+    assert s.to_bytes() == ref
+    st = s.retrieve(eb=eb)
+    assert _bytes(st.tensor()) == dbg.xhat.tobytes()
+    st.free()
+    for plan_seed in range(3):
+        draw = np.random.default_rng(plan_seed).integers(0, 12, size=s.n_passes)
+        plan = [int(b) if s.pass_info(i)["progressive"] else 0 for i, b in enumerate(draw)]
+        st = s.retrieve_plan(plan)
+        o = codec.retrieve_with_plan(ref, plan)
+        assert _bytes(st.tensor()) == o.field.tobytes()
+        st.free()
+    s.free()
+
+
 def test_oracle_stream_retrieved_on_gpu(ctx):
     """A stream the oracle wrote, loaded through the packed placement."""
     x = fieldgen.climate_2d(1, shape=(180, 360), dtype=np.float32)
