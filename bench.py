@@ -42,6 +42,9 @@ def parse_args():
                     help="edge of the cubic sub-block the oracle compresses and retrieves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="first run one plain device copy of the field (a known-size "
+                         "reference for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -68,6 +71,13 @@ def main():
     itemsize = x.element_size()
     rng = float(x.max().double() - x.min().double())
     eb = args.rel_eb * rng
+    if args.copy_reference:
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(f"[bench] copy reference: {x.numel() * itemsize} bytes read, same written",
+              file=sys.stderr, flush=True)
+        del y
     ctx = pkg.Context(0)
 
     def step():
@@ -135,11 +145,12 @@ def main():
         st.free()
     s.free()
     lat.sort()
-    p50 = lat[len(lat) // 2]
-    p99 = lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)]
+    p50 = lat[len(lat) // 2] if lat else None
+    p99 = lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)] if lat else None
 
     # roofline of the dominant kernel: algorithmic bytes per launch
     alg_bytes, kname = launch_bytes(dom_op, dom_pass, pinfo, shape, itemsize, args.interp)
+    traffic = counted_traffic(dom_op, pinfo[dom_pass]["level"], shape, itemsize, args.interp)
     dom_list = dom_c if dom_op == "compress" else dom_r
     dom_avg_ms = sum(dom_list) / len(dom_list)
     achieved = alg_bytes / (dom_avg_ms * 1e-3) / 1e9
@@ -165,9 +176,9 @@ def main():
                    "n_passes": P},
         "compress_GBps": round(gb / (tc / args.steps), 3),
         "retrieve_GBps": round(gb / (tr / args.steps), 3),
-        "retrieve_latency_ms": {"p50": round(p50, 4), "p99": round(p99, 4), "calls": L},
+        "retrieve_latency_ms": {"p50": p50 and round(p50, 4), "p99": p99 and round(p99, 4), "calls": L},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "kernel": kname, "alg_bytes_per_launch": int(alg_bytes),
                      "avg_launch_ms": round(dom_avg_ms, 5)},
         "pass_ms": {"compress": [round(v, 4) for v in c_ms], "retrieve": [round(v, 4) for v in r_ms]},
@@ -209,6 +220,31 @@ def launch_bytes(op, launch, pinfo, shape, itemsize, interp):
     else:
         b = coarse * itemsize + planes + fine * itemsize
     return b, f"k_level3_{op}<{tname},{interp}> level {lev}"
+
+
+def counted_traffic(op, level, shape, itemsize, interp):
+    """HBM bytes per launch from the committed counter summaries under profiles/
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or None when
+    no summary covers this launch or the kernel source changed since it was taken."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2502_04093_amd", "csrc", "level3.hip")
+    try:
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if not line.startswith("traffic-json: "):
+                continue
+            d = json.loads(line[len("traffic-json: "):])
+            if (d.get("source_sha256_16") == h and list(d.get("shape", [])) == list(shape)
+                    and d.get("dtype") == ("f32" if itemsize == 4 else "f64")
+                    and d.get("interp") == interp):
+                v = d.get("bytes_per_launch", {}).get(f"{op}|level {level}")
+                if v is not None:
+                    return int(v)
+    return None
 
 
 def cpu_baseline(x, eb, args, rng):
