@@ -78,6 +78,35 @@ __device__ __forceinline__ void transpose32(uint32_t a[32]) {
   }
 }
 
+// Same transpose: the 16- and 8-bit stages as byte permutes (v_perm_b32),
+// the 4-, 2- and 1-bit stages as shifted bit-field inserts.
+__device__ __forceinline__ void transpose32p(uint32_t a[32]) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const uint32_t lo = a[k], hi = a[k + 16];
+    a[k] = __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+    a[k + 16] = __builtin_amdgcn_perm(hi, lo, 0x07060302u);
+  }
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    if (k & 8) continue;
+    const uint32_t lo = a[k], hi = a[k + 8];
+    a[k] = __builtin_amdgcn_perm(hi, lo, 0x06020400u);
+    a[k + 8] = __builtin_amdgcn_perm(hi, lo, 0x07030501u);
+  }
+  uint32_t m = 0x0F0F0F0Fu;
+#pragma unroll
+  for (int j = 4; j != 0; j >>= 1, m ^= (m << j)) {
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      if (k & j) continue;
+      const uint32_t lo = a[k], hi = a[k | j];
+      a[k] = (lo & m) | ((hi << j) & ~m);
+      a[k | j] = ((lo >> j) & m) | (hi & ~m);
+    }
+  }
+}
+
 __device__ __forceinline__ uint32_t xenc(uint32_t v) { return v ^ (v >> 1) ^ (v >> 2); }
 // (1 + x + x^2)^-1 = (1 + x)(1 + x^3)(1 + x^6)(1 + x^12)(1 + x^24) over GF(2)
 __device__ __forceinline__ uint32_t xdec(uint32_t e) {
@@ -219,31 +248,64 @@ __device__ __forceinline__ uint32_t fetch_code(const Level3Args &L, const Retrie
   return xdec(code) & keep;
 }
 
+// LDS of a retrieval workgroup
 template <typename T>
 struct Shared3 {
+  T ring[4][NYE][NXP];      // coarse planes m-1 .. m+2 (even rows x even columns, halo'd)
+  T wa[NYE][NXP];           // pass A values of the step's odd plane (halo'd)
+  T wb[2][8][NXP];          // pass B values of both planes (odd rows, halo'd columns)
+  T wc[2][16][32];          // pass C values (odd columns)
+  uint32_t hva[NYE][NXP];   // codes of pass-A halo targets
+  uint32_t hvb[2][8][4];    // codes of pass-B halo targets
+  uint32_t codes[2 * PADA + 2 * PADB + 2 * PADC];
+  uint32_t orng[13][2];     // outlier ranges of the step's chunks
+};
+
+// inputs of a compression step: the tile (both planes), then the halo targets
+constexpr int XIN_HA = 2 * 16 * TX;           // pass-A halo inputs [NYE][NXP]
+constexpr int XIN_HB = XIN_HA + NYE * NXP;    // pass-B halo inputs [2][8][4]
+constexpr int XIN_N = XIN_HB + 2 * 8 * 4;
+
+// residue bits of the delta-y set (see k_level3_compress)
+constexpr int RB = 13;
+constexpr int RW = (1 << RB) / 32;            // words of one pass's residue set
+
+// LDS of a compression workgroup
+template <typename T>
+struct SharedC {
   T ring[4][NYE][NXP];
   T wa[NYE][NXP];
   T wb[2][8][NXP];
-  T xs[2][16][TX];
   T wc[2][16][32];
-  T xha[NYE][NXP];          // compress: inputs of pass-A halo targets
-  T xhb[2][8][4];           //           inputs of pass-B halo targets
-  uint32_t hva[NYE][NXP];   // retrieve: codes of pass-A halo targets
-  uint32_t hvb[2][8][4];    //           codes of pass-B halo targets
+  T xin[XIN_N];
   uint32_t codes[2 * PADA + 2 * PADB + 2 * PADC];
+  uint32_t bm[3][RW];       // residues w mod 2^13 present among each pass's codes
   uint32_t cmask[3][2];
-  uint32_t orng[13][2];     // retrieve: outlier ranges of the step's chunks
   uint32_t eq[3][33];       // per workgroup delta-y of each pass
+  uint32_t qa[3];           // largest |q| among 14-digit codes, per pass
 };
 
 __device__ __forceinline__ int code_off(int p, int si) {
   return p == 0 ? si * PADA : (p == 1 ? 2 * PADA + si * PADB : 2 * PADA + 2 * PADB + si * PADC);
 }
 
+// Tile (tx, ty) and column segment zs of this workgroup.  Consecutive
+// workgroup ids are dealt round-robin to the 8 XCDs; renumbering them so that
+// each XCD works through a contiguous run of tiles keeps neighbouring columns,
+// whose halos overlap, in the same L2.
+__device__ __forceinline__ void block_tile(const Level3Args &L, int &tx, int &ty, int &zs) {
+  const int nb = int(gridDim.x), b = int(blockIdx.x);
+  const int lin = (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+  tx = lin % L.tiles_x;
+  const int r = lin / L.tiles_x;
+  ty = r % L.tiles_y;
+  zs = r / L.tiles_y;
+}
+
 // ring slot cz & 3 <- coarse plane cz (11 even rows x 35 even columns)
-template <typename T>
-__device__ __forceinline__ void load_ring_plane(const Level3Args &L, const T *gin, Shared3<T> &S,
-                                                int cz, int y0, int x0) {
+template <typename T, typename SH>
+__device__ __forceinline__ void load_ring_plane(const Level3Args &L, const T *gin, SH &S, int cz,
+                                                int y0, int x0) {
   if (cz < 0 || cz >= L.G[0]) return;
   T(*dst)[NXP] = S.ring[cz & 3];
   const int64_t pb = int64_t(cz) * L.G[1];
@@ -267,24 +329,24 @@ __device__ __forceinline__ void load_ring_plane(const Level3Args &L, const T *gi
 // even-column values of plane zz at tile row yy (0 .. 15), index i + 1 for the
 // even column x0 + 2 i: the coarse plane (zz = 0, yy even), pass A (zz = 1,
 // yy even) or pass B (yy odd)
-template <typename T>
-__device__ __forceinline__ const T *even_row(Shared3<T> &S, int m, int zz, int yy) {
+template <typename T, typename SH>
+__device__ __forceinline__ const T *even_row(SH &S, int m, int zz, int yy) {
   if (yy & 1) return S.wb[zz][yy >> 1];
   return zz == 0 ? S.ring[m & 3][(yy >> 1) + 1] : S.wa[(yy >> 1) + 1];
 }
 
 // write the 2 x 16 x 64 level points of a step from LDS to a compact grid,
 // four consecutive points per thread
-template <typename T>
-__device__ __forceinline__ void write_rows(const Level3Args &L, Shared3<T> &S, T *gout, int m,
-                                           int y0, int x0) {
+template <typename T, typename SH>
+__device__ __forceinline__ void write_rows(const Level3Args &L, SH &S, T *gout, int m, int y0,
+                                           int x0) {
   const int Lz = L.L[0], Ly = L.L[1], Lx = L.L[2];
   const bool vec = (Lx & 3) == 0 && (reinterpret_cast<uintptr_t>(gout) & 15) == 0;
   for (int t = threadIdx.x; t < 2 * 16 * (TX / 4); t += WG3) {
     int zz = t >> 8, yy = (t >> 4) & 15, xq = (t & 15) * 4;
     int z = 2 * m + zz, y = y0 + yy, x = x0 + xq;
     if (z >= Lz || y >= Ly || x >= Lx) continue;
-    const T *ev = even_row(S, m, zz, yy);
+    const T *ev = even_row<T>(S, m, zz, yy);
     T v0 = ev[(xq >> 1) + 1];
     T v1 = S.wc[zz][yy][xq >> 1];
     T v2 = ev[(xq >> 1) + 2];
@@ -306,45 +368,6 @@ __device__ __forceinline__ void write_rows(const Level3Args &L, Shared3<T> &S, T
   }
 }
 
-// Per-lane delta-y accumulator of Thm. 1 in code units: d[b] = max |q - q'_b|
-// over the codes seen, q'_b the code with its b lowest negabinary digits
-// cleared.  With w = v xor A (A = 0xAAAAAAAA) the value of the low b digits is
-// (w mod 2^b) - (A mod 2^b), so |q - q'_b| = |(w mod 2^b) - (A mod 2^b)|; for
-// b at or above the code's digit count it equals |q|.  d[32] = max |q|.
-struct ErrqAcc {
-  uint32_t d[33];
-};
-
-__device__ __forceinline__ void errq_init(ErrqAcc &a) {
-#pragma unroll
-  for (int b = 0; b < 33; ++b) a.d[b] = 0u;
-}
-
-__device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) { return a > b ? a - b : b - a; }
-
-// Add codes v[j], j = lane, lane + 64, ... < count of one chunk whose codes
-// have at most nb negabinary digits: b < nb per code, b >= nb from the
-// chunk's largest |q|.
-__device__ __forceinline__ void errq_add(ErrqAcc &a, const uint32_t *v, int count, int nb, int lane) {
-  uint32_t qa = 0;
-  for (int j = lane; j < count; j += 64) {
-    uint32_t w = v[pidx(j)] ^ NB_A;
-    int32_t q = int32_t(w - NB_A);
-    uint32_t aq = uint32_t(q < 0 ? -q : q);
-    qa = aq > qa ? aq : qa;
-#pragma unroll
-    for (int b = 1; b < 32; ++b) {
-      if (b < nb) {
-        uint32_t t = absdiff(w & ((1u << b) - 1u), NB_A & ((1u << b) - 1u));
-        a.d[b] = t > a.d[b] ? t : a.d[b];
-      }
-    }
-  }
-#pragma unroll
-  for (int b = 1; b < 33; ++b)
-    if (b >= nb) a.d[b] = qa > a.d[b] ? qa : a.d[b];
-}
-
 // role of thread tid < 112 in the encode / decode of a group of two chunk rows:
 // pass rp, chunk row rsi, plane-word column rw
 __device__ __forceinline__ void row_role(int tid, int &rp, int &rsi, int &rw) {
@@ -353,7 +376,151 @@ __device__ __forceinline__ void row_role(int tid, int &rp, int &rsi, int &rw) {
   else { rp = 2; rsi = (tid - 48) >> 5; rw = (tid - 48) & 31; }
 }
 
+// role of thread tid < 112 in the encode of a group of two chunk rows, with
+// the rows of each chunk in one wave: wave 0 holds pass C (32 + 32 rows),
+// wave 1 pass B (16 + 16) and pass A (8 + 8)
+__device__ __forceinline__ void enc_role(int tid, int &rp, int &rsi, int &rw) {
+  if (tid < 64) { rp = 2; rsi = tid >> 5; rw = tid & 31; }
+  else if (tid < 96) { rp = 1; rsi = (tid - 64) >> 4; rw = (tid - 64) & 15; }
+  else { rp = 0; rsi = (tid - 96) >> 3; rw = (tid - 96) & 7; }
+}
+
+__device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) { return a > b ? a - b : b - a; }
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    int u = __shfl_xor(v, o, 64);
+    v = u < v ? u : v;
+  }
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    int u = __shfl_xor(v, o, 64);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+
+// Delta-y for b >= 14 over one chunk of `count` buffered codes with at most nb
+// digits, nb > 14 (see k_level3_compress): exact |q - q'_b| per code while
+// b < nb, the chunk's largest |q| from there on; into the maxima eq[14..32].
+__device__ __forceinline__ void errq_hi(uint32_t *eq, const uint32_t *v, int count, int nb, int lane) {
+  uint32_t d[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) d[i] = 0u;
+  uint32_t qa = 0;
+  for (int j = lane; j < count; j += 64) {
+    const uint32_t w = v[pidx(j)] ^ NB_A;
+    const int32_t q = int32_t(w - NB_A);
+    const uint32_t aq = uint32_t(q < 0 ? -q : q);
+    qa = aq > qa ? aq : qa;
+#pragma unroll
+    for (int b = 14; b < 32; ++b) {
+      if (b < nb) {
+        const uint32_t t = absdiff(w & ((1u << b) - 1u), NB_A & ((1u << b) - 1u));
+        d[b - 14] = t > d[b - 14] ? t : d[b - 14];
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 14; b < 33; ++b) {
+    uint32_t t = b >= nb ? (qa > d[b - 14] ? qa : d[b - 14]) : d[b - 14];
+    if (t) atomicMax(&eq[b], t);
+  }
+}
+
+// Delta-y for b <= 13 from the residue set of one pass (one wave): folding the
+// 2^13-bit set onto 2^b bits gives the smallest and largest residue w mod 2^b,
+// and |q - q'_b| is largest at one of them.  Results into eq[1..13].
+__device__ __forceinline__ void errq_fold(const uint32_t *bm, uint32_t *eq, int lane) {
+  auto emit = [&](int b, int mn, int mx) {
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    if (lane == 0 && mx >= 0) {
+      const uint32_t ab = NB_A & ((1u << b) - 1u);
+      const uint32_t d1 = uint32_t(mx) >= ab ? uint32_t(mx) - ab : 0u;
+      const uint32_t d2 = ab >= uint32_t(mn) ? ab - uint32_t(mn) : 0u;
+      eq[b] = d1 > d2 ? d1 : d2;
+    }
+  };
+  auto lo = [](uint32_t w, int base) { return w ? base + __builtin_ctz(w) : 0x7FFFFFFF; };
+  auto hi = [](uint32_t w, int base) { return w ? base + 31 - __builtin_clz(w) : -1; };
+  const uint32_t w0 = bm[lane], w1 = bm[lane + 64], w2 = bm[lane + 128], w3 = bm[lane + 192];
+  // b = 13: word j of the set holds residues 32 j .. 32 j + 31
+  {
+    int mn = min(min(lo(w0, 32 * lane), lo(w1, 32 * (lane + 64))),
+                 min(lo(w2, 32 * (lane + 128)), lo(w3, 32 * (lane + 192))));
+    int mx = max(max(hi(w0, 32 * lane), hi(w1, 32 * (lane + 64))),
+                 max(hi(w2, 32 * (lane + 128)), hi(w3, 32 * (lane + 192))));
+    emit(13, mn, mx);
+  }
+  // b = 12: words j and j + 128 fold onto word j
+  const uint32_t f0 = w0 | w2, f1 = w1 | w3;
+  emit(12, min(lo(f0, 32 * lane), lo(f1, 32 * (lane + 64))),
+       max(hi(f0, 32 * lane), hi(f1, 32 * (lane + 64))));
+  // b = 11 .. 5: word j of 2^(b-5) words held by lane j
+  uint32_t f = f0 | f1;
+  emit(11, lo(f, 32 * lane), hi(f, 32 * lane));
+#pragma unroll
+  for (int b = 10; b >= 5; --b) {
+    const int n = 1 << (b - 5);
+    const uint32_t g = __shfl_down(f, n, 64);
+    f = lane < n ? (f | g) : 0u;
+    emit(b, lo(f, 32 * lane), hi(f, 32 * lane));
+  }
+  // b = 4 .. 1 inside the word of lane 0 (every lane computes the same, lane 0 writes)
+  uint32_t g = __shfl(f, 0, 64);
+#pragma unroll
+  for (int b = 4; b >= 1; --b) {
+    const int n = 1 << b;
+    g = (g | (g >> n)) & ((1u << n) - 1u);
+    if (lane == 0 && g) {
+      const uint32_t ab = NB_A & ((1u << b) - 1u);
+      const uint32_t mn = __builtin_ctz(g), mx = 31 - __builtin_clz(g);
+      const uint32_t d1 = mx >= ab ? mx - ab : 0u;
+      const uint32_t d2 = ab >= mn ? ab - mn : 0u;
+      eq[b] = d1 > d2 ? d1 : d2;
+    }
+  }
+}
+
+template <typename T>
+struct BitsOf;
+template <>
+struct BitsOf<float> {
+  using U = uint32_t;
+  static __device__ __forceinline__ U abs_bits(float a) { return __float_as_uint(a) & 0x7FFFFFFFu; }
+  static __device__ __forceinline__ bool finite(float a) { return (__float_as_uint(a) & 0x7F800000u) != 0x7F800000u; }
+  static __device__ __forceinline__ double to_double(U b) { return double(__uint_as_float(b)); }
+};
+template <>
+struct BitsOf<double> {
+  using U = uint64_t;
+  static __device__ __forceinline__ U abs_bits(double a) {
+    return uint64_t(__double_as_longlong(a)) & 0x7FFFFFFFFFFFFFFFull;
+  }
+  static __device__ __forceinline__ bool finite(double a) {
+    return (uint64_t(__double_as_longlong(a)) & 0x7FF0000000000000ull) != 0x7FF0000000000000ull;
+  }
+  static __device__ __forceinline__ double to_double(U b) { return __longlong_as_double((long long)b); }
+};
+
 // ------------------------------------------------------------------ compress
+//
+// Delta-y of Thm. 1 in code units, errq[b] = max over a pass's codes of
+// |q - q'_b|, q'_b being q with its b lowest negabinary digits cleared.  With
+// w = q + A (mod 2^32, A = 0xAAAAAAAA; the code stored is v = w xor A) the
+// low b digits are worth (w mod 2^b) - (A mod 2^b), which is q itself once b
+// reaches the code's digit count.  The work is split by b:
+//   b <= 13: the set of residues w mod 2^13 of the workgroup's codes (one LDS
+//            OR per code); at the end, folding the set onto 2^b bits gives the
+//            extreme residues mod 2^b and so the exact maximum;
+//   b >= 14: a code within the 14-digit range [-0x2AAA, 0x1555] contributes
+//            |q| (one max per code); chunks holding longer codes are scanned
+//            exactly for b >= 14 once their codes are buffered (errq_hi).
 
 template <typename T, int INTERP>
 __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *__restrict__ x,
@@ -361,28 +528,112 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
                                                           double eb, T two_eb, T inv, T qmax,
                                                           CompressOut o) {
   using F = F3<T>;
-  __shared__ Shared3<T> S;
+  using BT = BitsOf<T>;
+  using U = typename BT::U;
+  __shared__ SharedC<T> S;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tx = blockIdx.x, ty = blockIdx.y;
+  int tx, ty, zs;
+  block_tile(L, tx, ty, zs);
   const int x0 = tx * TX, y0 = ty * TY;
-  const int m0 = int(blockIdx.z) * L.zseg;
+  const int m0 = zs * L.zseg;
   const int m1 = m0 + L.zseg < L.tiles_z ? m0 + L.zseg : L.tiles_z;
   const int Lz = L.L[0], Ly = L.L[1], Lx = L.L[2];
-  // offset of level point (z, y, xx) in the fine field
-  auto xin = [&](int z, int y, int xx) -> int64_t {
-    return int64_t(z) * L.sZ + int64_t(y) * L.sY + int64_t(xx) * L.sX;
-  };
-  // wave 0 accumulates delta-y of pass A, wave 1 of pass B, waves 2-3 of pass C
-  const int ep = wave == 0 ? 0 : (wave == 1 ? 1 : 2);
-  ErrqAcc acc;
-  errq_init(acc);
-  unsigned long long mx_abs = 0;
 
-  load_ring_plane(L, gin, S, m0 - 1, y0, x0);
-  load_ring_plane(L, gin, S, m0, y0, x0);
-  load_ring_plane(L, gin, S, m0 + 1, y0, x0);
+  for (int i = tid; i < 3 * RW; i += WG3) (&S.bm[0][0])[i] = 0u;
+  if (tid < 3 * 33) (&S.eq[0][0])[tid] = 0u;
+  if (tid < 3) S.qa[tid] = 0u;
 
-  auto record = [&](int p, int m, int local, T xv) {
+  // ---- per-thread constants
+  // tile inputs: rows ly + 4 i of both planes at column lx (xin index tid + 256 i)
+  const int lx = tid & 63, ly = tid >> 6;
+  const bool colok = x0 + lx < Lx;
+  const T *xrow = x + (int64_t(y0 + ly) * L.sY + int64_t(x0 + lx) * L.sX);
+  // the halo input this thread loads (pass A: tid < 129 at the odd plane;
+  // pass B: 129 <= tid < 177 at plane ze + hzz)
+  int hidx = -1, hzz = 1;
+  bool hxy = false;
+  const T *hptr = x;
+  if (tid < NHA) {
+    int yj, xi;
+    halo_a(tid, yj, xi);
+    const int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
+    hxy = unsigned(y) < unsigned(Ly) && unsigned(xg) < unsigned(Lx);
+    hidx = XIN_HA + yj * NXP + xi;
+    if (hxy) hptr = x + (int64_t(y) * L.sY + int64_t(xg) * L.sX);
+  } else if (tid < NHA + NHB) {
+    int zz, k, xi;
+    halo_b(tid - NHA, zz, k, xi);
+    const int y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
+    hxy = y < Ly && unsigned(xg) < unsigned(Lx);
+    hzz = zz;
+    hidx = XIN_HB + (zz * 8 + k) * 4 + (xi & 3);
+    if (hxy) hptr = x + (int64_t(y) * L.sY + int64_t(xg) * L.sX);
+  }
+  // the coarse-plane entries this thread loads: tid, tid + 256 (< 385)
+  int rj[2];
+  int64_t roff[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int t = tid + i * WG3;
+    const int yj = t / NXE, xi = t - (t / NXE) * NXE;
+    const int cy = (y0 >> 1) - 1 + yj, cx = (x0 >> 1) - 1 + xi;
+    const bool ok = t < NYE * NXE && unsigned(cy) < unsigned(L.G[1]) && unsigned(cx) < unsigned(L.G[2]);
+    rj[i] = t < NYE * NXE ? (ok ? yj * NXP + xi : -1 - (yj * NXP + xi)) : INT32_MIN;
+    roff[i] = ok ? int64_t(cy) * L.G[2] + cx : 0;
+  }
+  // pass A: targets tid, tid + 256 of the 11 x 35 halo'd grid
+  //   aI: ring / wa index (-1: outside the level), aX: input index in xin,
+  //   aL: padded code index (-1: halo target)
+  int aI[2], aX[2], aL[2];
+  {
+    const int ex = clampi(L.tdims[0][2] - tx * L.ct[0][2], L.ct[0][2]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int t = tid + j * WG3;
+      const int yj = t / NXE, xi = t - (t / NXE) * NXE;
+      const int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
+      const bool ok = t < NYE * NXE && unsigned(y) < unsigned(Ly) && unsigned(xg) < unsigned(Lx);
+      const bool own = unsigned(yj - 1) < 8u && unsigned(xi - 1) < 32u;
+      aI[j] = ok ? yj * NXP + xi : -1;
+      aX[j] = own ? 1024 + (y - y0) * TX + (xg - x0) : XIN_HA + yj * NXP + xi;
+      aL[j] = own ? pidx((yj - 1) * ex + (xi - 1)) : -1;
+    }
+  }
+  // pass B: targets tid, tid + 256, tid + 512 of the 2 x 8 x 35 grid
+  //   bI: zz << 16 | (k * NXP + xi) (-1: outside), bX, bL as for pass A,
+  //   bF: stencil flags (bit 0: c present, 1: a present, 2: e present)
+  int bI[3], bX[3], bL[3], bF[3];
+  {
+    const int ey = clampi(L.tdims[1][1] - ty * L.ct[1][1], L.ct[1][1]);
+    const int ex = clampi(L.tdims[1][2] - tx * L.ct[1][2], L.ct[1][2]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int t = tid + j * WG3;
+      const int zz = t >= 8 * NXE ? 1 : 0;
+      const int r = t - zz * (8 * NXE);
+      const int k = r / NXE, xi = r - (r / NXE) * NXE;
+      const int y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
+      const bool ok = t < 2 * 8 * NXE && y < Ly && unsigned(xg) < unsigned(Lx);
+      const bool own = unsigned(xi - 1) < 32u;
+      bI[j] = ok ? (zz << 16) | (k * NXP + xi) : -1;
+      bX[j] = own ? zz * 1024 + (2 * k + 1) * TX + (xg - x0) : XIN_HB + (zz * 8 + k) * 4 + (xi & 3);
+      bL[j] = own ? pidx((zz * ey + k) * ex + (xi - 1)) : -1;
+      bF[j] = (y + 1 < Ly ? 1 : 0) | (y >= 3 ? 2 : 0) | (y + 3 < Ly ? 4 : 0);
+    }
+  }
+  // pass C: targets tid + 256 j: plane j >> 1, row cr + 8 (j & 1), odd column ci
+  const int ci = tid & 31, cr = (tid >> 5) & 7;
+  const int cxg = x0 + 1 + 2 * ci;
+  const bool cxok = cxg < Lx;
+  const bool chc = cxg + 1 < Lx, cha = cxg >= 3, che = cxg + 3 < Lx;
+  const int cey = clampi(L.tdims[2][1] - ty * L.ct[2][1], L.ct[2][1]);
+  const int cex = clampi(L.tdims[2][2] - tx * L.ct[2][2], L.ct[2][2]);
+
+  uint32_t qaA = 0, qaB = 0, qaC = 0;
+  U mxb = 0;
+
+  auto record = [&](int p, int m, int pl, T xv) {
+    const int local = (pl / 33) * 32 + pl % 33;
     unsigned long long slot = atomicAdd(o.n_out, 1ull);
     if (slot < o.out_cap) {
       OutlierRec *rr = reinterpret_cast<OutlierRec *>(o.out_recs) + slot;
@@ -392,223 +643,246 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
       rr->pad = 0;
       rr->bits = F::bits(xv);
     }
-  };
-  auto track = [&](T xhat) {
-    double ax = fabs(double(xhat));
-    if (ax <= 1.7976931348623157e308) {
-      unsigned long long bx = (unsigned long long)__double_as_longlong(ax);
-      mx_abs = bx > mx_abs ? bx : mx_abs;
+    if (BT::finite(xv)) {
+      const U b = BT::abs_bits(xv);
+      mxb = b > mxb ? b : mxb;
     }
   };
+  // one own target: its code, its residue, its |q|
+  auto emit_code = [&](int p, uint32_t *cb, int pl, int32_t q, uint32_t &qa) {
+    const uint32_t w = uint32_t(q) + NB_A;
+    cb[pl] = w ^ NB_A;
+    atomicOr(&S.bm[p][(w >> 5) & (RW - 1)], 1u << (w & 31));
+    const uint32_t aq = uint32_t(q < 0 ? -q : q);
+    if (uint32_t(q) + 0x2AAAu <= 0x3FFFu) qa = aq > qa ? aq : qa;
+  };
+
+  // prefetched inputs of the next step
+  T xv[8], hv, rv[2];
+  auto issue = [&](int m) {
+    const int ze = 2 * m;
+    const bool z0 = ze < Lz, z1 = ze + 1 < Lz;
+    const T *xz = xrow + int64_t(ze) * L.sZ;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int zz = i >> 2, yy = ly + 4 * (i & 3);
+      const bool ok = (zz ? z1 : z0) && y0 + yy < Ly && colok;
+      const T v = *(ok ? xz + (int64_t(zz) * L.sZ + int64_t(4 * (i & 3)) * L.sY) : x);
+      xv[i] = ok ? v : T(0);
+    }
+    {
+      const bool ok = hxy && ze + hzz < Lz;
+      const T v = *(ok ? hptr + int64_t(ze + hzz) * L.sZ : x);
+      hv = ok ? v : T(0);
+    }
+    const int cz = m + 2;
+    if (cz < L.G[0]) {
+      const T *gp = gin + int64_t(cz) * L.G[1] * L.G[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const T v = gp[roff[i]];
+        rv[i] = rj[i] >= 0 ? v : T(0);
+      }
+    }
+  };
+
+  load_ring_plane(L, gin, S, m0 - 1, y0, x0);
+  load_ring_plane(L, gin, S, m0, y0, x0);
+  load_ring_plane(L, gin, S, m0 + 1, y0, x0);
+  issue(m0);
 
   for (int gm = m0; gm < m1; gm += 2) {
     const int nsteps = (m1 - gm) >= 2 ? 2 : 1;
     for (int si = 0; si < nsteps; ++si) {
       const int m = gm + si;
       const int ze = 2 * m, zo = 2 * m + 1;
-      // ---- one load phase: coarse plane m+2, the tile's inputs, the halo inputs
-      load_ring_plane(L, gin, S, m + 2, y0, x0);
-      {
-        T xv[8];
-        bool xok[8];
+      // ---- stash the prefetched inputs, then prefetch the next step's
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          int t = tid + i * WG3;
-          int zz = t >> 10, yy = (t >> 6) & 15, xx = t & 63;
-          int z = ze + zz, y = y0 + yy, xg = x0 + xx;
-          xok[i] = z < Lz && y < Ly && xg < Lx;
-          xv[i] = x[xok[i] ? xin(z, y, xg) : 0];
-        }
-        T hv = T(0);
-        bool hok = false;
-        int hyj = 0, hxi = 0, hzz = 0, hk = 0;
-        if (tid < NHA) {
-          halo_a(tid, hyj, hxi);
-          int y = y0 - 2 + 2 * hyj, xg = x0 - 2 + 2 * hxi;
-          hok = zo < Lz && unsigned(y) < unsigned(Ly) && unsigned(xg) < unsigned(Lx);
-          hv = x[hok ? xin(zo, y, xg) : 0];
-        } else if (tid < NHA + NHB) {
-          halo_b(tid - NHA, hzz, hk, hxi);
-          int z = ze + hzz, y = y0 + 1 + 2 * hk, xg = x0 - 2 + 2 * hxi;
-          hok = z < Lz && y < Ly && unsigned(xg) < unsigned(Lx);
-          hv = x[hok ? xin(z, y, xg) : 0];
-        }
+      for (int i = 0; i < 8; ++i) S.xin[tid + i * WG3] = xv[i];
+      if (hidx >= 0) S.xin[hidx] = hv;
+      if (m + 2 < L.G[0]) {
+        T *rs = &S.ring[(m + 2) & 3][0][0];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          int t = tid + i * WG3;
-          S.xs[t >> 10][(t >> 6) & 15][t & 63] = xok[i] ? xv[i] : T(0);
-        }
-        if (tid < NHA)
-          S.xha[hyj][hxi] = hok ? hv : T(0);
-        else if (tid < NHA + NHB)
-          S.xhb[hzz][hk][hxi & 3] = hok ? hv : T(0);
+        for (int i = 0; i < 2; ++i)
+          if (rj[i] != INT32_MIN) rs[rj[i] >= 0 ? rj[i] : -1 - rj[i]] = rv[i];
       }
       __syncthreads();
+      if (m + 1 < m1) issue(m + 1);
       // ---- pass A (along z) at plane zo on the halo'd even grid
       if (zo < Lz) {
         const bool hc = zo + 1 < Lz, ha = zo >= 3, he = zo + 3 < Lz;
-        T(*rb)[NXP] = S.ring[m & 3];
-        T(*rc)[NXP] = S.ring[(m + 1) & 3];
-        T(*ra)[NXP] = S.ring[(m - 1) & 3];
-        T(*re)[NXP] = S.ring[(m + 2) & 3];
-        const Ext ce = chunk_ext(L, 0, m, ty, tx);
+        const T *rb = &S.ring[m & 3][0][0];
+        const T *rc = &S.ring[(m + 1) & 3][0][0];
+        const T *ra = &S.ring[(m - 1) & 3][0][0];
+        const T *re = &S.ring[(m + 2) & 3][0][0];
         uint32_t *cb = S.codes + code_off(0, si);
-        for (int t = tid; t < NYE * NXE; t += WG3) {
-          int yj = t / NXE, xi = t - yj * NXE;
-          int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
-          if (unsigned(y) >= unsigned(Ly) || unsigned(xg) >= unsigned(Lx)) continue;
-          bool own = unsigned(yj - 1) < 8u && unsigned(xi - 1) < 32u;
-          T xv = own ? S.xs[1][y - y0][xg - x0] : S.xha[yj][xi];
-          T pred = stencil<T, INTERP>(ha ? ra[yj][xi] : T(0), rb[yj][xi], hc ? rc[yj][xi] : T(0),
-                                      he ? re[yj][xi] : T(0), hc, ha, he);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int ri = aI[j];
+          if (ri < 0) continue;
+          const T xval = S.xin[aX[j]];
+          const T pred = stencil<T, INTERP>(ha ? ra[ri] : T(0), rb[ri], hc ? rc[ri] : T(0),
+                                            he ? re[ri] : T(0), hc, ha, he);
           T xhat;
           bool out;
-          int32_t q = quantize<T>(xv, pred, eb, two_eb, inv, qmax, xhat, out);
-          S.wa[yj][xi] = xhat;
-          if (own) {
-            int local = (yj - 1) * ce.ex + (xi - 1);
-            cb[pidx(local)] = (uint32_t(q) + NB_A) ^ NB_A;
-            if (out) record(0, m, local, xv);
-            track(xhat);
+          const int32_t q = quantize<T>(xval, pred, eb, two_eb, inv, qmax, xhat, out);
+          (&S.wa[0][0])[ri] = xhat;
+          if (aL[j] >= 0) {
+            emit_code(0, cb, aL[j], q, qaA);
+            if (out) {
+              record(0, m, aL[j], xval);
+            } else {
+              const U b = BT::abs_bits(xhat);
+              mxb = b > mxb ? b : mxb;
+            }
           }
         }
       }
       __syncthreads();
       // ---- pass B (along y) at planes ze, zo; odd rows, halo'd even columns
       {
-        const Ext ce = chunk_ext(L, 1, m, ty, tx);
         uint32_t *cb = S.codes + code_off(1, si);
-        for (int t = tid; t < 2 * 8 * NXE; t += WG3) {
-          int zz = t >= 8 * NXE ? 1 : 0;
-          int r = t - zz * (8 * NXE);
-          int k = r / NXE, xi = r - k * NXE;
-          int z = ze + zz, y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
-          if (z >= Lz || y >= Ly || unsigned(xg) >= unsigned(Lx)) continue;
-          bool own = unsigned(xi - 1) < 32u;
-          T(*src)[NXP] = zz == 0 ? S.ring[m & 3] : S.wa;
-          const bool hc = y + 1 < Ly, ha = y >= 3, he = y + 3 < Ly;
-          T pred = stencil<T, INTERP>(ha ? src[k][xi] : T(0), src[k + 1][xi], hc ? src[k + 2][xi] : T(0),
-                                      he ? src[k + 3][xi] : T(0), hc, ha, he);
-          T xv = own ? S.xs[zz][2 * k + 1][xg - x0] : S.xhb[zz][k][xi & 3];
+        const bool z1 = ze + 1 < Lz;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const int bi = bI[j];
+          if (bi < 0) continue;
+          const int zz = bi >> 16, ri = bi & 0xFFFF;
+          if (zz && !z1) continue;
+          const T *src = zz == 0 ? &S.ring[m & 3][0][0] : &S.wa[0][0];
+          const bool hc = bF[j] & 1, ha = bF[j] & 2, he = bF[j] & 4;
+          const T pred = stencil<T, INTERP>(ha ? src[ri] : T(0), src[ri + NXP], hc ? src[ri + 2 * NXP] : T(0),
+                                            he ? src[ri + 3 * NXP] : T(0), hc, ha, he);
+          const T xval = S.xin[bX[j]];
           T xhat;
           bool out;
-          int32_t q = quantize<T>(xv, pred, eb, two_eb, inv, qmax, xhat, out);
-          S.wb[zz][k][xi] = xhat;
-          if (own) {
-            int local = (zz * ce.ey + k) * ce.ex + (xi - 1);
-            cb[pidx(local)] = (uint32_t(q) + NB_A) ^ NB_A;
-            if (out) record(1, m, local, xv);
-            track(xhat);
+          const int32_t q = quantize<T>(xval, pred, eb, two_eb, inv, qmax, xhat, out);
+          (&S.wb[zz][0][0])[ri] = xhat;
+          if (bL[j] >= 0) {
+            emit_code(1, cb, bL[j], q, qaB);
+            if (out) {
+              record(1, m, bL[j], xval);
+            } else {
+              const U b = BT::abs_bits(xhat);
+              mxb = b > mxb ? b : mxb;
+            }
           }
         }
       }
       __syncthreads();
       // ---- pass C (along x) at planes ze, zo, every row of the tile
       {
-        const Ext ce = chunk_ext(L, 2, m, ty, tx);
         uint32_t *cb = S.codes + code_off(2, si);
-        for (int t = tid; t < 2 * 16 * 32; t += WG3) {
-          int zz = t >> 9, yy = (t >> 5) & 15, i = t & 31;
-          int z = ze + zz, y = y0 + yy, xg = x0 + 1 + 2 * i;
-          if (z >= Lz || y >= Ly || xg >= Lx) continue;
-          const T *row = even_row(S, m, zz, yy);
-          const bool hc = xg + 1 < Lx, ha = xg >= 3, he = xg + 3 < Lx;
-          T pred = stencil<T, INTERP>(ha ? row[i] : T(0), row[i + 1], hc ? row[i + 2] : T(0),
-                                      he ? row[i + 3] : T(0), hc, ha, he);
-          T xv = S.xs[zz][yy][2 * i + 1];
+        const bool z1 = ze + 1 < Lz;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int zz = j >> 1, yy = cr + 8 * (j & 1);
+          if (!cxok || y0 + yy >= Ly || (zz && !z1)) continue;
+          const T *row = even_row<T>(S, m, zz, yy);
+          const T pred = stencil<T, INTERP>(cha ? row[ci] : T(0), row[ci + 1], chc ? row[ci + 2] : T(0),
+                                            che ? row[ci + 3] : T(0), chc, cha, che);
+          const T xval = S.xin[zz * 1024 + yy * TX + 2 * ci + 1];
           T xhat;
           bool out;
-          int32_t q = quantize<T>(xv, pred, eb, two_eb, inv, qmax, xhat, out);
-          S.wc[zz][yy][i] = xhat;
-          int local = (zz * ce.ey + yy) * ce.ex + i;
-          cb[pidx(local)] = (uint32_t(q) + NB_A) ^ NB_A;
-          if (out) record(2, m, local, xv);
-          track(xhat);
+          const int32_t q = quantize<T>(xval, pred, eb, two_eb, inv, qmax, xhat, out);
+          S.wc[zz][yy][ci] = xhat;
+          const int pl = pidx((zz * cey + yy) * cex + ci);
+          emit_code(2, cb, pl, q, qaC);
+          if (out) {
+            record(2, m, pl, xval);
+          } else {
+            const U b = BT::abs_bits(xhat);
+            mxb = b > mxb ? b : mxb;
+          }
         }
       }
       __syncthreads();
       // ---- the level's output grid (compact), read by the next finer level
       if (gout) write_rows(L, S, gout, m, y0, x0);
     }
-    // ---- encode the buffered chunk rows: rows of 32 codes -> plane words
-    if (tid < 6) S.cmask[tid >> 1][tid & 1] = 0;
-    __syncthreads();
-    uint32_t r[32];
-    int rp = -1, rsi = 0, rw = 0, rW = 0;
-    if (tid < 112) {
-      row_role(tid, rp, rsi, rw);
-      if (rsi >= nsteps) rp = -1;
-    }
-    if (rp >= 0) {
-      const Ext rce = chunk_ext(L, rp, gm + rsi, ty, tx);
-      rW = (rce.count + 31) >> 5;
-      if (rw >= rW) {
-        rp = -1;
-      } else {
-        const uint32_t *cb = S.codes + code_off(rp, rsi);
-        uint32_t rowor = 0;
+    // ---- encode the buffered chunk rows: 32 codes -> 32 plane words per thread.
+    // The rows of one chunk sit in one wave (enc_role), so the chunk's plane
+    // mask is an OR across its lanes.
+    {
+      int rp = 0, rsi = 2, rw = 0;
+      if (tid < 112) enc_role(tid, rp, rsi, rw);
+      const bool act = rsi < nsteps;
+      const Ext rce = chunk_ext(L, rp, gm + (act ? rsi : 0), ty, tx);
+      const int rW = (rce.count + 31) >> 5;
+      const bool work = act && rw < rW;
+      uint32_t r[32];
+      uint32_t rowor = 0;
+      if (work) {
+        // codes 32 rw .. 32 rw + 31 sit at padded indices 33 rw + j
+        const uint32_t *cb = S.codes + code_off(rp, rsi) + 33 * rw;
+        const int nv = rce.count - 32 * rw;
 #pragma unroll
-        for (int j = 0; j < 32; ++j) {
-          int jj = 32 * rw + j;
-          uint32_t v = jj < rce.count ? cb[pidx(jj)] : 0u;
-          r[j] = xenc(v);
-          rowor |= r[j];
-        }
-        transpose32(r);
-        atomicOr(&S.cmask[rp][rsi], rowor);
+        for (int j = 0; j < 32; ++j) r[j] = j < nv ? cb[j] : 0u;
+        transpose32p(r);
+        // planes of e = v ^ (v >> 1) ^ (v >> 2) from the planes of v
+#pragma unroll
+        for (int k = 0; k < 32; ++k)
+          r[k] = k < 30 ? (r[k] ^ r[k + 1] ^ r[k + 2]) : (k == 30 ? (r[30] ^ r[31]) : r[31]);
+#pragma unroll
+        for (int k = 31; k >= 0; --k) rowor = (rowor << 1) | (r[k] != 0u ? 1u : 0u);
+      }
+      // OR over the 8, 16 or 32 lanes of the chunk row (pass A, B, C)
+#pragma unroll
+      for (int o2 = 1; o2 < 32; o2 <<= 1) {
+        const uint32_t u = __shfl_xor(rowor, o2, 64);
+        if ((8 << rp) > o2) rowor |= u;
+      }
+      if (work) {
+        const int64_t cid = chunk_id(L, gm + rsi, ty, tx);
+        uint32_t *slot = o.payload + L.slot_base[rp] + uint64_t(cid) * 32u * L.wmax[rp] + rw;
+#pragma unroll
+        for (int k = 0; k < 32; ++k)
+          if ((rowor >> k) & 1u) slot[(31 - k) * rW] = r[k];
+      }
+      if (act && rw == 0) {
+        o.masks[L.chunk_base[rp] + chunk_id(L, gm + rsi, ty, tx)] = rowor;
+        S.cmask[rp][rsi] = rowor;
       }
     }
     __syncthreads();
-    if (rp >= 0) {
-      const uint32_t mask = S.cmask[rp][rsi];
-      const int64_t cid = chunk_id(L, gm + rsi, ty, tx);
-      uint32_t *slot = o.payload + L.slot_base[rp] + uint64_t(cid) * 32u * L.wmax[rp] + rw;
-#pragma unroll
-      for (int k = 0; k < 32; ++k)
-        if ((mask >> k) & 1u) slot[(31 - k) * rW] = r[k];
-      if (rw == 0) o.masks[L.chunk_base[rp] + cid] = mask;
-    }
-    if (tid < 6) {  // empty chunks of this group still get a zero mask
-      int p = tid >> 1, s2 = tid & 1;
-      if (s2 < nsteps && chunk_ext(L, p, gm + s2, ty, tx).count == 0)
-        o.masks[L.chunk_base[p] + chunk_id(L, gm + s2, ty, tx)] = 0u;
-    }
-    // ---- delta-y: each wave adds the codes of its pass
-    if (ep == 2) {
-      int s2 = wave - 2;
-      if (s2 < nsteps) {
-        uint32_t mk = S.cmask[2][s2];
-        errq_add(acc, S.codes + code_off(2, s2), chunk_ext(L, 2, gm + s2, ty, tx).count,
-                 mk ? 32 - __clz(mk) : 0, lane);
-      }
-    } else {
-      for (int s2 = 0; s2 < nsteps; ++s2) {
-        uint32_t mk = S.cmask[ep][s2];
-        errq_add(acc, S.codes + code_off(ep, s2), chunk_ext(L, ep, gm + s2, ty, tx).count,
-                 mk ? 32 - __clz(mk) : 0, lane);
+    // ---- delta-y for b >= 14 of chunks with codes longer than 14 digits
+    {
+      const int ep = wave == 0 ? 0 : (wave == 1 ? 1 : 2);
+      for (int s2 = (ep == 2 ? wave - 2 : 0); s2 < nsteps; s2 += (ep == 2 ? 2 : 1)) {
+        const uint32_t mk = S.cmask[ep][s2];
+        const int nb = mk ? 32 - __clz(mk) : 0;
+        if (nb > 14)
+          errq_hi(S.eq[ep], S.codes + code_off(ep, s2), chunk_ext(L, ep, gm + s2, ty, tx).count, nb, lane);
       }
     }
     __syncthreads();
   }
-  // ---- workgroup totals: per-pass delta-y and max |x^|
-  if (tid < 3 * 33) (&S.eq[0][0])[tid] = 0u;
-  __syncthreads();
-#pragma unroll
-  for (int b = 1; b < 33; ++b)
-    if (acc.d[b] != 0u) atomicMax(&S.eq[ep][b], acc.d[b]);
+  // ---- workgroup totals: per-pass |q| of 14-digit codes, max |x^|
   {
-    unsigned long long v = mx_abs;
+    uint32_t qs[3] = {qaA, qaB, qaC};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const int v = wave_max(int(qs[p]));
+      if (lane == 0 && v > 0) atomicMax(&S.qa[p], uint32_t(v));
+    }
+    U v = mxb;
 #pragma unroll
     for (int o2 = 32; o2 > 0; o2 >>= 1) {
-      unsigned long long u = __shfl_xor(v, o2, 64);
+      const U u = __shfl_xor(v, o2, 64);
       v = u > v ? u : v;
     }
-    if (lane == 0 && v > *o.maxabs_bits) atomicMax(o.maxabs_bits, v);
+    if (lane == 0 && v) {
+      const unsigned long long db = (unsigned long long)__double_as_longlong(BT::to_double(v));
+      if (db > *o.maxabs_bits) atomicMax(o.maxabs_bits, db);
+    }
   }
   __syncthreads();
+  if (wave < 3) errq_fold(S.bm[wave], S.eq[wave], lane);
+  __syncthreads();
   if (tid < 3 * 33) {
-    int p = tid / 33, b = tid - p * 33;
+    const int p = tid / 33, b = tid - p * 33;
     uint32_t val = S.eq[p][b];
+    if (b >= 14) val = S.qa[p] > val ? S.qa[p] : val;
     uint32_t *dst = o.errq + size_t(L.pass_index[p]) * 33 + b;
     if (b > 0 && val > *dst) atomicMax(dst, val);
   }
@@ -623,9 +897,10 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
   using F = F3<T>;
   __shared__ Shared3<T> S;
   const int tid = threadIdx.x;
-  const int tx = blockIdx.x, ty = blockIdx.y;
+  int tx, ty, zs;
+  block_tile(L, tx, ty, zs);
   const int x0 = tx * TX, y0 = ty * TY;
-  const int m0 = int(blockIdx.z) * L.zseg;
+  const int m0 = zs * L.zseg;
   const int m1 = m0 + L.zseg < L.tiles_z ? m0 + L.zseg : L.tiles_z;
   const int Lz = L.L[0], Ly = L.L[1], Lx = L.L[2];
   const uint32_t keep[3] = {discA >= 32 ? 0u : (0xFFFFFFFFu << discA),
@@ -799,7 +1074,7 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
           int zz = t >> 9, yy = (t >> 5) & 15, i = t & 31;
           int z = ze + zz, y = y0 + yy, xg = x0 + 1 + 2 * i;
           if (z >= Lz || y >= Ly || xg >= Lx) continue;
-          const T *row = even_row(S, m, zz, yy);
+          const T *row = even_row<T>(S, m, zz, yy);
           const bool hc = xg + 1 < Lx, ha = xg >= 3, he = xg + 3 < Lx;
           T pred = stencil<T, INTERP>(ha ? row[i] : T(0), row[i + 1], hc ? row[i + 2] : T(0),
                                       he ? row[i + 3] : T(0), hc, ha, he);
@@ -920,7 +1195,7 @@ __global__ void k_gather_coarse(const T *__restrict__ field, int64_t fd1, int64_
 hipError_t launch_level3_compress(int dtype, int interp, const Level3Args &L, const void *x,
                                   const void *gin, void *gout, double eb, const CompressOut &o,
                                   hipStream_t s) {
-  dim3 grid(uint32_t(L.tiles_x), uint32_t(L.tiles_y), uint32_t((L.tiles_z + L.zseg - 1) / L.zseg));
+  dim3 grid(uint32_t(L.tiles_x) * uint32_t(L.tiles_y) * uint32_t((L.tiles_z + L.zseg - 1) / L.zseg));
   if (dtype == IPC_F32) {
     float two_eb = float(2.0 * eb), inv = float(1.0 / (2.0 * eb)), qm = float(QMAX_F32);
     if (interp == IPC_LINEAR)
@@ -944,7 +1219,7 @@ hipError_t launch_level3_compress(int dtype, int interp, const Level3Args &L, co
 hipError_t launch_level3_retrieve(int dtype, int interp, const Level3Args &L, const void *gin,
                                   void *gout, const int disc[3], const RetrieveIn &in, double eb,
                                   hipStream_t s) {
-  dim3 grid(uint32_t(L.tiles_x), uint32_t(L.tiles_y), uint32_t((L.tiles_z + L.zseg - 1) / L.zseg));
+  dim3 grid(uint32_t(L.tiles_x) * uint32_t(L.tiles_y) * uint32_t((L.tiles_z + L.zseg - 1) / L.zseg));
   if (dtype == IPC_F32) {
     float two_eb = float(2.0 * eb);
     if (interp == IPC_LINEAR)
