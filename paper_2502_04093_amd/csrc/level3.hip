@@ -890,6 +890,37 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
 
 // ------------------------------------------------------------------ retrieve
 
+// 32 plane words (p[k] = plane k of 32 codes, absent planes 0) -> the 32
+// codes v with the digits outside `keep` cleared.  The XOR coding e = v ^
+// (v >> 1) ^ (v >> 2) is undone plane by plane from the top (v_31 = e_31,
+// v_30 = e_30 ^ v_31, v_k = e_k ^ v_k+1 ^ v_k+2), then the planes are
+// transposed back into codes.
+__device__ __forceinline__ void planes_to_codes(uint32_t p[32], uint32_t keep) {
+  p[30] ^= p[31];
+#pragma unroll
+  for (int k = 29; k >= 0; --k) p[k] ^= p[k + 1] ^ p[k + 2];
+  transpose32p(p);
+#pragma unroll
+  for (int j = 0; j < 32; ++j) p[j] &= keep;
+}
+
+// the 32 plane words of word `w` of a chunk (its stored planes that `keep`
+// selects); planes not loaded read word 0 of the payload, which always exists
+__device__ __forceinline__ void load_planes(const RetrieveIn &in, uint64_t first_word, uint32_t mask,
+                                            uint32_t keep, uint32_t W, uint32_t w, uint32_t p[32]) {
+  const bool packed = in.chunk_off != nullptr;
+  uint32_t load = mask & keep;
+  // keeps the compiler from precomputing keep & (1 << k) for every plane
+  asm volatile("" : "+v"(load));
+  const uint32_t *base = in.payload + first_word + w;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const bool on = (load >> k) & 1u;
+    const uint32_t v = *(on ? base + plane_rank(packed, mask, k) * W : in.payload);
+    p[k] = on ? v : 0u;
+  }
+}
+
 template <typename T, int INTERP>
 __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *__restrict__ gin,
                                                           T *gout, int discA, int discB, int discC,
@@ -907,11 +938,6 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
                             discB >= 32 ? 0u : (0xFFFFFFFFu << discB),
                             discC >= 32 ? 0u : (0xFFFFFFFFu << discC)};
   const bool has_out = in.n_out > 0;
-  const bool packed = in.chunk_off != nullptr;
-
-  load_ring_plane(L, gin, S, m0 - 1, y0, x0);
-  load_ring_plane(L, gin, S, m0, y0, x0);
-  load_ring_plane(L, gin, S, m0 + 1, y0, x0);
 
   // reconstruction pred + q * 2eb from the negabinary code v
   auto value = [&](T pred, uint32_t v) -> T {
@@ -922,6 +948,161 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
       tq = T(int64_t(v ^ NB_A) - int64_t(NB_A));
     return F::add(pred, F::mul(tq, two_eb));
   };
+
+  // ---- per-thread constants
+  // coarse-plane entries tid, tid + 256 (< 385) of the ring
+  int rj[2];
+  int64_t roff[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int t = tid + i * WG3;
+    const int yj = t / NXE, xi = t - (t / NXE) * NXE;
+    const int cy = (y0 >> 1) - 1 + yj, cx = (x0 >> 1) - 1 + xi;
+    const bool ok = t < NYE * NXE && unsigned(cy) < unsigned(L.G[1]) && unsigned(cx) < unsigned(L.G[2]);
+    rj[i] = t < NYE * NXE ? (ok ? yj * NXP + xi : -1 - (yj * NXP + xi)) : INT32_MIN;
+    roff[i] = ok ? int64_t(cy) * L.G[2] + cx : 0;
+  }
+  // pass A targets tid, tid + 256: ring / wa index (-1: outside), code source
+  // (>= 0: padded index in the chunk's code buffer, < 0: -1 - halo index)
+  int aI[2], aC[2];
+  {
+    const int ex = clampi(L.tdims[0][2] - tx * L.ct[0][2], L.ct[0][2]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int t = tid + j * WG3;
+      const int yj = t / NXE, xi = t - (t / NXE) * NXE;
+      const int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
+      const bool ok = t < NYE * NXE && unsigned(y) < unsigned(Ly) && unsigned(xg) < unsigned(Lx);
+      const bool own = unsigned(yj - 1) < 8u && unsigned(xi - 1) < 32u;
+      aI[j] = ok ? yj * NXP + xi : -1;
+      aC[j] = own ? pidx((yj - 1) * ex + (xi - 1)) : -1 - (yj * NXP + xi);
+    }
+  }
+  // pass B targets tid, tid + 256, tid + 512: zz << 16 | (k * NXP + xi), code
+  // source (own: padded index, halo: -1 - index into hvb), stencil flags
+  int bI[3], bC[3], bF[3];
+  {
+    const int ey = clampi(L.tdims[1][1] - ty * L.ct[1][1], L.ct[1][1]);
+    const int ex = clampi(L.tdims[1][2] - tx * L.ct[1][2], L.ct[1][2]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int t = tid + j * WG3;
+      const int zz = t >= 8 * NXE ? 1 : 0;
+      const int r = t - zz * (8 * NXE);
+      const int k = r / NXE, xi = r - (r / NXE) * NXE;
+      const int y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
+      const bool ok = t < 2 * 8 * NXE && y < Ly && unsigned(xg) < unsigned(Lx);
+      const bool own = unsigned(xi - 1) < 32u;
+      bI[j] = ok ? (zz << 16) | (k * NXP + xi) : -1;
+      bC[j] = own ? pidx((zz * ey + k) * ex + (xi - 1)) : -1 - ((zz * 8 + k) * 4 + (xi & 3));
+      bF[j] = (y + 1 < Ly ? 1 : 0) | (y >= 3 ? 2 : 0) | (y + 3 < Ly ? 4 : 0);
+    }
+  }
+  // pass C targets tid + 256 j: plane j >> 1, row cr + 8 (j & 1), odd column ci
+  const int ci = tid & 31, cr = (tid >> 5) & 7;
+  const int cxg = x0 + 1 + 2 * ci;
+  const bool cxok = cxg < Lx;
+  const bool chc = cxg + 1 < Lx, cha = cxg >= 3, che = cxg + 3 < Lx;
+  const int cey = clampi(L.tdims[2][1] - ty * L.ct[2][1], L.ct[2][1]);
+  const int cex = clampi(L.tdims[2][2] - tx * L.ct[2][2], L.ct[2][2]);
+
+  // Halo codes by plane words when every chunk column involved is 32 targets
+  // wide (one chunk row = one word): thread tid < 57 fetches one word.
+  //   0 .. 8:   pass A rows y0-2, y0+16, y0+18 in chunk columns tx-1, tx, tx+1
+  //   9 .. 24:  pass A own rows, columns tx-1 (code 31) and tx+1 (codes 0, 1)
+  //   25 .. 56: pass B rows (zz, k), columns tx-1 and tx+1
+  const int xe = L.tdims[0][2];  // even columns of the level (passes A and B)
+  const int txr = tx + 1 < L.tiles_x ? tx + 1 : L.tiles_x - 1;
+  const bool wordhalo = xe - 32 * txr >= 32;
+  int hp = -1, hdy = 0, hdx = 0, hrow = 0, hyy = 0, hsel = 0, hdst = 0;
+  if (wordhalo && tid < 57) {
+    if (tid < 9) {
+      const int r = tid / 3, c = tid - (tid / 3) * 3;
+      hp = 0;
+      hdy = r == 0 ? -1 : 1;
+      hdx = c - 1;
+      hrow = r == 0 ? 7 : r - 1;            // row inside the neighbouring chunk
+      hyy = r == 0 ? y0 - 2 : y0 + 14 + 2 * r;
+      hsel = c;                             // 0: code 31, 1: all, 2: codes 0, 1
+      hdst = (r == 0 ? 0 : 8 + r) * NXP;    // hva row
+    } else if (tid < 25) {
+      const int u = tid - 9, yj = 1 + (u >> 1), side = u & 1;
+      hp = 0;
+      hdy = 0;
+      hdx = side ? 1 : -1;
+      hrow = yj - 1;
+      hyy = y0 - 2 + 2 * yj;
+      hsel = side ? 2 : 0;
+      hdst = yj * NXP;
+    } else {
+      const int u = tid - 25, zz = u >> 4, k = (u >> 1) & 7, side = u & 1;
+      hp = 1;
+      hdy = 0;
+      hdx = side ? 1 : -1;
+      hrow = zz * 16 + k;                   // zz * ey + k with ey resolved per chunk below
+      hyy = y0 + 1 + 2 * k;
+      hsel = side ? 2 : 0;
+      hdst = -1 - ((zz * 8 + k) * 4);       // hvb row (negative: pass B)
+    }
+  }
+
+  auto halo_words = [&](int m) {
+    if (hp < 0) return;
+    const int ze = 2 * m;
+    const int tyn = ty + hdy, txn = tx + hdx;
+    int row = hrow, zz = 0;
+    if (hp == 1) {
+      zz = hrow >> 4;
+      row = hrow & 15;
+    }
+    const int zt = hp == 0 ? ze + 1 : ze + zz;
+    if (zt >= Lz || hyy < 0 || hyy >= Ly || unsigned(txn) >= unsigned(L.tiles_x)) return;
+    const Ext e = chunk_ext(L, hp, m, tyn, txn);
+    const int wd = hp == 0 ? row : zz * e.ey + row;
+    const int64_t cid = chunk_id(L, m, tyn, txn);
+    const uint32_t mask = in.masks[L.chunk_base[hp] + cid];
+    uint32_t p[32];
+    load_planes(in, chunk_words(L, in, hp, cid), mask, keep[hp], uint32_t((e.count + 31) >> 5),
+                uint32_t(wd), p);
+    planes_to_codes(p, keep[hp]);
+    if (hp == 0) {
+      uint32_t *d = &S.hva[0][0] + hdst;
+      if (hsel == 1) {
+#pragma unroll
+        for (int j = 0; j < 32; ++j) d[1 + j] = p[j];
+      } else if (hsel == 0) {
+        d[0] = p[31];
+      } else {
+        d[33] = p[0];
+        d[34] = p[1];
+      }
+    } else {
+      uint32_t *d = &S.hvb[0][0][0] + (-1 - hdst);
+      if (hsel == 0) {
+        d[0] = p[31];
+      } else {
+        d[1] = p[0];
+        d[2] = p[1];
+      }
+    }
+  };
+
+  T rv[2];
+  auto issue_ring = [&](int cz) {
+    if (cz < L.G[0]) {
+      const T *gp = gin + int64_t(cz) * L.G[1] * L.G[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const T v = gp[roff[i]];
+        rv[i] = rj[i] >= 0 ? v : T(0);
+      }
+    }
+  };
+
+  load_ring_plane(L, gin, S, m0 - 1, y0, x0);
+  load_ring_plane(L, gin, S, m0, y0, x0);
+  load_ring_plane(L, gin, S, m0 + 1, y0, x0);
+  issue_ring(m0 + 2);
 
   for (int gm = m0; gm < m1; gm += 2) {
     const int nsteps = (m1 - gm) >= 2 ? 2 : 1;
@@ -935,32 +1116,30 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
         if (rw < W) {
           const int64_t cid = chunk_id(L, gm + rsi, ty, tx);
           const uint32_t mask = in.masks[L.chunk_base[rp] + cid];
-          const uint32_t kp = keep[rp];
-          const uint32_t load = mask & kp;
-          const uint32_t *base = in.payload + chunk_words(L, in, rp, cid) + rw;
-          uint32_t r[32];
+          uint32_t p[32];
+          load_planes(in, chunk_words(L, in, rp, cid), mask, keep[rp], uint32_t(W), uint32_t(rw), p);
+          planes_to_codes(p, keep[rp]);
+          uint32_t *cb = S.codes + code_off(rp, rsi) + 33 * rw;
+          const int nv = ce.count - 32 * rw;
 #pragma unroll
-          for (int k = 0; k < 32; ++k) {
-            bool on = (load >> k) & 1u;
-            uint32_t w = *(on ? base + plane_rank(packed, mask, k) * uint32_t(W) : in.payload);
-            r[k] = on ? w : 0u;
-          }
-          transpose32(r);
-          uint32_t *cb = S.codes + code_off(rp, rsi);
-#pragma unroll
-          for (int j = 0; j < 32; ++j) {
-            int jj = 32 * rw + j;
-            if (jj < ce.count) cb[pidx(jj)] = xdec(r[j]) & kp;
-          }
+          for (int j = 0; j < 32; ++j)
+            if (j < nv) cb[j] = p[j];
         }
       }
     }
     for (int si = 0; si < nsteps; ++si) {
       const int m = gm + si;
       const int ze = 2 * m, zo = 2 * m + 1;
-      // ---- one load phase: coarse plane m+2 and the codes of the halo targets
-      load_ring_plane(L, gin, S, m + 2, y0, x0);
-      if (tid < NHA) {
+      // ---- stash the prefetched coarse plane m + 2; codes of the halo targets
+      if (m + 2 < L.G[0]) {
+        T *rs = &S.ring[(m + 2) & 3][0][0];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          if (rj[i] != INT32_MIN) rs[rj[i] >= 0 ? rj[i] : -1 - rj[i]] = rv[i];
+      }
+      if (wordhalo) {
+        halo_words(m);
+      } else if (tid < NHA) {
         int yj, xi;
         halo_a(tid, yj, xi);
         int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
@@ -983,42 +1162,43 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
       // outlier ranges of the chunks the step reads: pass A (m, ty-1..ty+1,
       // tx-1..tx+1), pass B (m, ty, tx-1..tx+1), pass C (m, ty, tx)
       int any_out = 0;
-      if (has_out && tid < 13) {
-        int p = tid < 9 ? 0 : (tid < 12 ? 1 : 2);
-        int tyn = tid < 9 ? ty - 1 + tid / 3 : ty;
-        int txn = tid < 9 ? tx - 1 + tid % 3 : (tid < 12 ? tx - 10 + tid : tx);
+      if (has_out && tid >= 64 && tid < 64 + 13) {
+        const int u = tid - 64;
+        const int p = u < 9 ? 0 : (u < 12 ? 1 : 2);
+        const int tyn = u < 9 ? ty - 1 + u / 3 : ty;
+        const int txn = u < 9 ? tx - 1 + u % 3 : (u < 12 ? tx - 10 + u : tx);
         uint32_t a = 0, b = 0;
         if (unsigned(tyn) < unsigned(L.tiles_y) && unsigned(txn) < unsigned(L.tiles_x)) {
           const uint64_t g = uint64_t(L.chunk_base[p] + chunk_id(L, m, tyn, txn));
           a = in.out_start[g];
           b = in.out_start[g + 1];
         }
-        S.orng[tid][0] = a;
-        S.orng[tid][1] = b;
+        S.orng[u][0] = a;
+        S.orng[u][1] = b;
         any_out = b > a;
       }
       any_out = __builtin_amdgcn_readfirstlane(__syncthreads_or(any_out));
+      if (m + 1 < m1) issue_ring(m + 3);
       // ---- pass A
       if (zo < Lz) {
         const bool hc = zo + 1 < Lz, ha = zo >= 3, he = zo + 3 < Lz;
-        T(*rb)[NXP] = S.ring[m & 3];
-        T(*rc)[NXP] = S.ring[(m + 1) & 3];
-        T(*ra)[NXP] = S.ring[(m - 1) & 3];
-        T(*re)[NXP] = S.ring[(m + 2) & 3];
-        const Ext ce = chunk_ext(L, 0, m, ty, tx);
+        const T *rb = &S.ring[m & 3][0][0];
+        const T *rc = &S.ring[(m + 1) & 3][0][0];
+        const T *ra = &S.ring[(m - 1) & 3][0][0];
+        const T *re = &S.ring[(m + 2) & 3][0][0];
         const uint32_t *cb = S.codes + code_off(0, si);
-        for (int t = tid; t < NYE * NXE; t += WG3) {
-          int yj = t / NXE, xi = t - yj * NXE;
-          int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
-          if (unsigned(y) >= unsigned(Ly) || unsigned(xg) >= unsigned(Lx)) continue;
-          bool own = unsigned(yj - 1) < 8u && unsigned(xi - 1) < 32u;
-          uint32_t v = own ? cb[pidx((yj - 1) * ce.ex + (xi - 1))] : S.hva[yj][xi];
-          T pred = stencil<T, INTERP>(ha ? ra[yj][xi] : T(0), rb[yj][xi], hc ? rc[yj][xi] : T(0),
-                                      he ? re[yj][xi] : T(0), hc, ha, he);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int ri = aI[j];
+          if (ri < 0) continue;
+          const uint32_t v = aC[j] >= 0 ? cb[aC[j]] : (&S.hva[0][0])[-1 - aC[j]];
+          const T pred = stencil<T, INTERP>(ha ? ra[ri] : T(0), rb[ri], hc ? rc[ri] : T(0),
+                                            he ? re[ri] : T(0), hc, ha, he);
           T val = value(pred, v);
           if (any_out) {
-            const int ri = (yj == 0 ? 0 : (yj <= 8 ? 3 : 6)) + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
-            const uint32_t a0 = S.orng[ri][0], a1 = S.orng[ri][1];
+            const int yj = ri / NXP, xi = ri - (ri / NXP) * NXP;
+            const int oi = (yj == 0 ? 0 : (yj <= 8 ? 3 : 6)) + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
+            const uint32_t a0 = S.orng[oi][0], a1 = S.orng[oi][1];
             if (a1 > a0) {
               int tyn, oy, txn, ox;
               halo_tile(ty, yj, 8, tyn, oy);
@@ -1028,30 +1208,30 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
               if (find_outlier(in, a0, a1, uint32_t(oy * e.ex + ox), ob)) val = F::from_bits(ob);
             }
           }
-          S.wa[yj][xi] = val;
+          (&S.wa[0][0])[ri] = val;
         }
       }
       __syncthreads();
       // ---- pass B
       {
-        const Ext ce = chunk_ext(L, 1, m, ty, tx);
         const uint32_t *cb = S.codes + code_off(1, si);
-        for (int t = tid; t < 2 * 8 * NXE; t += WG3) {
-          int zz = t >= 8 * NXE ? 1 : 0;
-          int r = t - zz * (8 * NXE);
-          int k = r / NXE, xi = r - k * NXE;
-          int z = ze + zz, y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
-          if (z >= Lz || y >= Ly || unsigned(xg) >= unsigned(Lx)) continue;
-          bool own = unsigned(xi - 1) < 32u;
-          uint32_t v = own ? cb[pidx((zz * ce.ey + k) * ce.ex + (xi - 1))] : S.hvb[zz][k][xi & 3];
-          T(*src)[NXP] = zz == 0 ? S.ring[m & 3] : S.wa;
-          const bool hc = y + 1 < Ly, ha = y >= 3, he = y + 3 < Ly;
-          T pred = stencil<T, INTERP>(ha ? src[k][xi] : T(0), src[k + 1][xi], hc ? src[k + 2][xi] : T(0),
-                                      he ? src[k + 3][xi] : T(0), hc, ha, he);
+        const bool z1 = ze + 1 < Lz;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const int bi = bI[j];
+          if (bi < 0) continue;
+          const int zz = bi >> 16, ri = bi & 0xFFFF;
+          if (zz && !z1) continue;
+          const uint32_t v = bC[j] >= 0 ? cb[bC[j]] : (&S.hvb[0][0][0])[-1 - bC[j]];
+          const T *src = zz == 0 ? &S.ring[m & 3][0][0] : &S.wa[0][0];
+          const bool hc = bF[j] & 1, ha = bF[j] & 2, he = bF[j] & 4;
+          const T pred = stencil<T, INTERP>(ha ? src[ri] : T(0), src[ri + NXP], hc ? src[ri + 2 * NXP] : T(0),
+                                            he ? src[ri + 3 * NXP] : T(0), hc, ha, he);
           T val = value(pred, v);
           if (any_out) {
-            const int ri = 9 + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
-            const uint32_t a0 = S.orng[ri][0], a1 = S.orng[ri][1];
+            const int k = ri / NXP, xi = ri - (ri / NXP) * NXP;
+            const int oi = 9 + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
+            const uint32_t a0 = S.orng[oi][0], a1 = S.orng[oi][1];
             if (a1 > a0) {
               int txn, ox;
               halo_tile(tx, xi, 32, txn, ox);
@@ -1061,28 +1241,27 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
                 val = F::from_bits(ob);
             }
           }
-          S.wb[zz][k][xi] = val;
+          (&S.wb[zz][0][0])[ri] = val;
         }
       }
       __syncthreads();
       // ---- pass C
       {
-        const Ext ce = chunk_ext(L, 2, m, ty, tx);
-        const uint32_t oc0 = any_out ? S.orng[12][0] : 0u, oc1 = any_out ? S.orng[12][1] : 0u;
         const uint32_t *cb = S.codes + code_off(2, si);
-        for (int t = tid; t < 2 * 16 * 32; t += WG3) {
-          int zz = t >> 9, yy = (t >> 5) & 15, i = t & 31;
-          int z = ze + zz, y = y0 + yy, xg = x0 + 1 + 2 * i;
-          if (z >= Lz || y >= Ly || xg >= Lx) continue;
+        const bool z1 = ze + 1 < Lz;
+        const uint32_t oc0 = any_out ? S.orng[12][0] : 0u, oc1 = any_out ? S.orng[12][1] : 0u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int zz = j >> 1, yy = cr + 8 * (j & 1);
+          if (!cxok || y0 + yy >= Ly || (zz && !z1)) continue;
           const T *row = even_row<T>(S, m, zz, yy);
-          const bool hc = xg + 1 < Lx, ha = xg >= 3, he = xg + 3 < Lx;
-          T pred = stencil<T, INTERP>(ha ? row[i] : T(0), row[i + 1], hc ? row[i + 2] : T(0),
-                                      he ? row[i + 3] : T(0), hc, ha, he);
-          uint32_t local = uint32_t((zz * ce.ey + yy) * ce.ex + i);
+          const T pred = stencil<T, INTERP>(cha ? row[ci] : T(0), row[ci + 1], chc ? row[ci + 2] : T(0),
+                                            che ? row[ci + 3] : T(0), chc, cha, che);
+          const uint32_t local = uint32_t((zz * cey + yy) * cex + ci);
           T val = value(pred, cb[pidx(int(local))]);
           uint64_t ob;
           if (oc1 > oc0 && find_outlier(in, oc0, oc1, local, ob)) val = F::from_bits(ob);
-          S.wc[zz][yy][i] = val;
+          S.wc[zz][yy][ci] = val;
         }
       }
       __syncthreads();
