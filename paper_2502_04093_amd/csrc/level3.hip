@@ -145,6 +145,15 @@ __device__ __forceinline__ int32_t quantize(T xv, T pred, double eb, T two_eb, T
   return out ? 0 : q;
 }
 
+// Per-pass launch arguments picked by a pass number held in a register: a
+// select chain, so no dynamically indexed read of the argument block
+template <typename V>
+__device__ __forceinline__ V sel3(int p, V a0, V a1, V a2) {
+  return p == 0 ? a0 : (p == 1 ? a1 : a2);
+}
+#define LSEL(field, p) sel3((p), L.field[0], L.field[1], L.field[2])
+#define LSEL2(field, p, j) sel3((p), L.field[0][j], L.field[1][j], L.field[2][j])
+
 struct Ext {
   int ez, ey, ex, count;
 };
@@ -154,9 +163,9 @@ __device__ __forceinline__ int clampi(int v, int hi) { return v < 0 ? 0 : (v > h
 // extents of chunk (tz, ty, tx) of pass p (0 = A, 1 = B, 2 = C)
 __device__ __forceinline__ Ext chunk_ext(const Level3Args &L, int p, int tz, int ty, int tx) {
   Ext c;
-  c.ez = clampi(L.tdims[p][0] - tz * L.ct[p][0], L.ct[p][0]);
-  c.ey = clampi(L.tdims[p][1] - ty * L.ct[p][1], L.ct[p][1]);
-  c.ex = clampi(L.tdims[p][2] - tx * L.ct[p][2], L.ct[p][2]);
+  c.ez = clampi(LSEL2(tdims, p, 0) - tz * LSEL2(ct, p, 0), LSEL2(ct, p, 0));
+  c.ey = clampi(LSEL2(tdims, p, 1) - ty * LSEL2(ct, p, 1), LSEL2(ct, p, 1));
+  c.ex = clampi(LSEL2(tdims, p, 2) - tx * LSEL2(ct, p, 2), LSEL2(ct, p, 2));
   c.count = c.ez * c.ey * c.ex;
   return c;
 }
@@ -168,8 +177,8 @@ __device__ __forceinline__ int64_t chunk_id(const Level3Args &L, int tz, int ty,
 // first payload word of a chunk's stored planes, and a plane's rank among them
 __device__ __forceinline__ uint64_t chunk_words(const Level3Args &L, const RetrieveIn &in, int p,
                                                 int64_t cid) {
-  if (in.chunk_off) return in.chunk_off[L.chunk_base[p] + cid];
-  return L.slot_base[p] + uint64_t(cid) * 32u * L.wmax[p];
+  if (in.chunk_off) return in.chunk_off[LSEL(chunk_base, p) + cid];
+  return LSEL(slot_base, p) + uint64_t(cid) * 32u * LSEL(wmax, p);
 }
 __device__ __forceinline__ uint32_t plane_rank(bool packed, uint32_t mask, int k) {
   return packed ? uint32_t(__popc((mask >> k) >> 1)) : uint32_t(31 - k);
@@ -232,7 +241,7 @@ __device__ __forceinline__ uint32_t fetch_code(const Level3Args &L, const Retrie
   const Ext e = chunk_ext(L, p, tz, tyn, txn);
   const uint32_t local = uint32_t((oz * e.ey + oy) * e.ex + ox);
   const int64_t cid = chunk_id(L, tz, tyn, txn);
-  const uint32_t mask = in.masks[L.chunk_base[p] + cid];
+  const uint32_t mask = in.masks[LSEL(chunk_base, p) + cid];
   const uint32_t load = mask & keep;
   const uint32_t W = uint32_t((e.count + 31) >> 5);
   const bool packed = in.chunk_off != nullptr;
@@ -257,7 +266,7 @@ struct Shared3 {
   T wc[2][16][32];          // pass C values (odd columns)
   uint32_t hva[NYE][NXP];   // codes of pass-A halo targets
   uint32_t hvb[2][8][4];    // codes of pass-B halo targets
-  uint32_t codes[2 * PADA + 2 * PADB + 2 * PADC];
+  uint32_t codes[PADA + PADB + PADC];
   uint32_t orng[13][2];     // outlier ranges of the step's chunks
 };
 
@@ -284,6 +293,9 @@ struct SharedC {
   uint32_t eq[3][33];       // per workgroup delta-y of each pass
   uint32_t qa[3];           // largest |q| among 14-digit codes, per pass
 };
+
+// code buffers of one step (retrieval): pass A, B, C
+__device__ __forceinline__ int code_off1(int p) { return p == 0 ? 0 : (p == 1 ? PADA : PADA + PADB); }
 
 __device__ __forceinline__ int code_off(int p, int si) {
   return p == 0 ? si * PADA : (p == 1 ? 2 * PADA + si * PADB : 2 * PADA + 2 * PADB + si * PADC);
@@ -637,7 +649,7 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
     unsigned long long slot = atomicAdd(o.n_out, 1ull);
     if (slot < o.out_cap) {
       OutlierRec *rr = reinterpret_cast<OutlierRec *>(o.out_recs) + slot;
-      rr->pass = L.pass_index[p];
+      rr->pass = LSEL(pass_index, p);
       rr->chunk = uint32_t(chunk_id(L, m, ty, tx));
       rr->local = uint32_t(local);
       rr->pad = 0;
@@ -663,26 +675,23 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
     const int ze = 2 * m;
     const bool z0 = ze < Lz, z1 = ze + 1 < Lz;
     const T *xz = xrow + int64_t(ze) * L.sZ;
+    // values at positions outside the level are loaded from x[0] and never
+    // read by a stencil, so they are not cleared (no wait right after a load)
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int zz = i >> 2, yy = ly + 4 * (i & 3);
       const bool ok = (zz ? z1 : z0) && y0 + yy < Ly && colok;
-      const T v = *(ok ? xz + (int64_t(zz) * L.sZ + int64_t(4 * (i & 3)) * L.sY) : x);
-      xv[i] = ok ? v : T(0);
+      xv[i] = *(ok ? xz + (int64_t(zz) * L.sZ + int64_t(4 * (i & 3)) * L.sY) : x);
     }
     {
       const bool ok = hxy && ze + hzz < Lz;
-      const T v = *(ok ? hptr + int64_t(ze + hzz) * L.sZ : x);
-      hv = ok ? v : T(0);
+      hv = *(ok ? hptr + int64_t(ze + hzz) * L.sZ : x);
     }
     const int cz = m + 2;
     if (cz < L.G[0]) {
       const T *gp = gin + int64_t(cz) * L.G[1] * L.G[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const T v = gp[roff[i]];
-        rv[i] = rj[i] >= 0 ? v : T(0);
-      }
+      for (int i = 0; i < 2; ++i) rv[i] = gp[roff[i]];
     }
   };
 
@@ -834,13 +843,13 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
       }
       if (work) {
         const int64_t cid = chunk_id(L, gm + rsi, ty, tx);
-        uint32_t *slot = o.payload + L.slot_base[rp] + uint64_t(cid) * 32u * L.wmax[rp] + rw;
+        uint32_t *slot = o.payload + LSEL(slot_base, rp) + uint64_t(cid) * 32u * LSEL(wmax, rp) + rw;
 #pragma unroll
         for (int k = 0; k < 32; ++k)
           if ((rowor >> k) & 1u) slot[(31 - k) * rW] = r[k];
       }
       if (act && rw == 0) {
-        o.masks[L.chunk_base[rp] + chunk_id(L, gm + rsi, ty, tx)] = rowor;
+        o.masks[LSEL(chunk_base, rp) + chunk_id(L, gm + rsi, ty, tx)] = rowor;
         S.cmask[rp][rsi] = rowor;
       }
     }
@@ -883,7 +892,7 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
     const int p = tid / 33, b = tid - p * 33;
     uint32_t val = S.eq[p][b];
     if (b >= 14) val = S.qa[p] > val ? S.qa[p] : val;
-    uint32_t *dst = o.errq + size_t(L.pass_index[p]) * 33 + b;
+    uint32_t *dst = o.errq + size_t(LSEL(pass_index, p)) * 33 + b;
     if (b > 0 && val > *dst) atomicMax(dst, val);
   }
 }
@@ -927,17 +936,22 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
                                                           RetrieveIn in, T two_eb) {
   using F = F3<T>;
   __shared__ Shared3<T> S;
-  const int tid = threadIdx.x;
+  const int tid0 = threadIdx.x;
   int tx, ty, zs;
   block_tile(L, tx, ty, zs);
   const int x0 = tx * TX, y0 = ty * TY;
   const int m0 = zs * L.zseg;
   const int m1 = m0 + L.zseg < L.tiles_z ? m0 + L.zseg : L.tiles_z;
   const int Lz = L.L[0], Ly = L.L[1], Lx = L.L[2];
-  const uint32_t keep[3] = {discA >= 32 ? 0u : (0xFFFFFFFFu << discA),
-                            discB >= 32 ? 0u : (0xFFFFFFFFu << discB),
-                            discC >= 32 ? 0u : (0xFFFFFFFFu << discC)};
+  const uint32_t keepA = discA >= 32 ? 0u : (0xFFFFFFFFu << discA);
+  const uint32_t keepB = discB >= 32 ? 0u : (0xFFFFFFFFu << discB);
+  const uint32_t keepC = discC >= 32 ? 0u : (0xFFFFFFFFu << discC);
   const bool has_out = in.n_out > 0;
+  const bool packed = in.chunk_off != nullptr;
+  // halo codes by plane words when every chunk column involved is 32 targets
+  // wide (one chunk row = one word)
+  const int txr = tx + 1 < L.tiles_x ? tx + 1 : L.tiles_x - 1;
+  const bool wordhalo = L.tdims[0][2] - 32 * txr >= 32;
 
   // reconstruction pred + q * 2eb from the negabinary code v
   auto value = [&](T pred, uint32_t v) -> T {
@@ -949,324 +963,309 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
     return F::add(pred, F::mul(tq, two_eb));
   };
 
-  // ---- per-thread constants
-  // coarse-plane entries tid, tid + 256 (< 385) of the ring
-  int rj[2];
-  int64_t roff[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int t = tid + i * WG3;
-    const int yj = t / NXE, xi = t - (t / NXE) * NXE;
-    const int cy = (y0 >> 1) - 1 + yj, cx = (x0 >> 1) - 1 + xi;
-    const bool ok = t < NYE * NXE && unsigned(cy) < unsigned(L.G[1]) && unsigned(cx) < unsigned(L.G[2]);
-    rj[i] = t < NYE * NXE ? (ok ? yj * NXP + xi : -1 - (yj * NXP + xi)) : INT32_MIN;
-    roff[i] = ok ? int64_t(cy) * L.G[2] + cx : 0;
-  }
-  // pass A targets tid, tid + 256: ring / wa index (-1: outside), code source
-  // (>= 0: padded index in the chunk's code buffer, < 0: -1 - halo index)
-  int aI[2], aC[2];
-  {
-    const int ex = clampi(L.tdims[0][2] - tx * L.ct[0][2], L.ct[0][2]);
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int t = tid + j * WG3;
-      const int yj = t / NXE, xi = t - (t / NXE) * NXE;
-      const int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
-      const bool ok = t < NYE * NXE && unsigned(y) < unsigned(Ly) && unsigned(xg) < unsigned(Lx);
-      const bool own = unsigned(yj - 1) < 8u && unsigned(xi - 1) < 32u;
-      aI[j] = ok ? yj * NXP + xi : -1;
-      aC[j] = own ? pidx((yj - 1) * ex + (xi - 1)) : -1 - (yj * NXP + xi);
-    }
-  }
-  // pass B targets tid, tid + 256, tid + 512: zz << 16 | (k * NXP + xi), code
-  // source (own: padded index, halo: -1 - index into hvb), stencil flags
-  int bI[3], bC[3], bF[3];
-  {
-    const int ey = clampi(L.tdims[1][1] - ty * L.ct[1][1], L.ct[1][1]);
-    const int ex = clampi(L.tdims[1][2] - tx * L.ct[1][2], L.ct[1][2]);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const int t = tid + j * WG3;
-      const int zz = t >= 8 * NXE ? 1 : 0;
-      const int r = t - zz * (8 * NXE);
-      const int k = r / NXE, xi = r - (r / NXE) * NXE;
-      const int y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
-      const bool ok = t < 2 * 8 * NXE && y < Ly && unsigned(xg) < unsigned(Lx);
-      const bool own = unsigned(xi - 1) < 32u;
-      bI[j] = ok ? (zz << 16) | (k * NXP + xi) : -1;
-      bC[j] = own ? pidx((zz * ey + k) * ex + (xi - 1)) : -1 - ((zz * 8 + k) * 4 + (xi & 3));
-      bF[j] = (y + 1 < Ly ? 1 : 0) | (y >= 3 ? 2 : 0) | (y + 3 < Ly ? 4 : 0);
-    }
-  }
-  // pass C targets tid + 256 j: plane j >> 1, row cr + 8 (j & 1), odd column ci
-  const int ci = tid & 31, cr = (tid >> 5) & 7;
-  const int cxg = x0 + 1 + 2 * ci;
-  const bool cxok = cxg < Lx;
-  const bool chc = cxg + 1 < Lx, cha = cxg >= 3, che = cxg + 3 < Lx;
-  const int cey = clampi(L.tdims[2][1] - ty * L.ct[2][1], L.ct[2][1]);
-  const int cex = clampi(L.tdims[2][2] - tx * L.ct[2][2], L.ct[2][2]);
-
-  // Halo codes by plane words when every chunk column involved is 32 targets
-  // wide (one chunk row = one word): thread tid < 57 fetches one word.
-  //   0 .. 8:   pass A rows y0-2, y0+16, y0+18 in chunk columns tx-1, tx, tx+1
-  //   9 .. 24:  pass A own rows, columns tx-1 (code 31) and tx+1 (codes 0, 1)
-  //   25 .. 56: pass B rows (zz, k), columns tx-1 and tx+1
-  const int xe = L.tdims[0][2];  // even columns of the level (passes A and B)
-  const int txr = tx + 1 < L.tiles_x ? tx + 1 : L.tiles_x - 1;
-  const bool wordhalo = xe - 32 * txr >= 32;
-  int hp = -1, hdy = 0, hdx = 0, hrow = 0, hyy = 0, hsel = 0, hdst = 0;
-  if (wordhalo && tid < 57) {
-    if (tid < 9) {
-      const int r = tid / 3, c = tid - (tid / 3) * 3;
-      hp = 0;
-      hdy = r == 0 ? -1 : 1;
-      hdx = c - 1;
-      hrow = r == 0 ? 7 : r - 1;            // row inside the neighbouring chunk
-      hyy = r == 0 ? y0 - 2 : y0 + 14 + 2 * r;
-      hsel = c;                             // 0: code 31, 1: all, 2: codes 0, 1
-      hdst = (r == 0 ? 0 : 8 + r) * NXP;    // hva row
-    } else if (tid < 25) {
-      const int u = tid - 9, yj = 1 + (u >> 1), side = u & 1;
-      hp = 0;
-      hdy = 0;
-      hdx = side ? 1 : -1;
-      hrow = yj - 1;
-      hyy = y0 - 2 + 2 * yj;
-      hsel = side ? 2 : 0;
-      hdst = yj * NXP;
-    } else {
-      const int u = tid - 25, zz = u >> 4, k = (u >> 1) & 7, side = u & 1;
-      hp = 1;
-      hdy = 0;
-      hdx = side ? 1 : -1;
-      hrow = zz * 16 + k;                   // zz * ey + k with ey resolved per chunk below
-      hyy = y0 + 1 + 2 * k;
-      hsel = side ? 2 : 0;
-      hdst = -1 - ((zz * 8 + k) * 4);       // hvb row (negative: pass B)
-    }
-  }
-
-  auto halo_words = [&](int m) {
-    if (hp < 0) return;
-    const int ze = 2 * m;
-    const int tyn = ty + hdy, txn = tx + hdx;
-    int row = hrow, zz = 0;
-    if (hp == 1) {
-      zz = hrow >> 4;
-      row = hrow & 15;
-    }
-    const int zt = hp == 0 ? ze + 1 : ze + zz;
-    if (zt >= Lz || hyy < 0 || hyy >= Ly || unsigned(txn) >= unsigned(L.tiles_x)) return;
-    const Ext e = chunk_ext(L, hp, m, tyn, txn);
-    const int wd = hp == 0 ? row : zz * e.ey + row;
-    const int64_t cid = chunk_id(L, m, tyn, txn);
-    const uint32_t mask = in.masks[L.chunk_base[hp] + cid];
-    uint32_t p[32];
-    load_planes(in, chunk_words(L, in, hp, cid), mask, keep[hp], uint32_t((e.count + 31) >> 5),
-                uint32_t(wd), p);
-    planes_to_codes(p, keep[hp]);
-    if (hp == 0) {
-      uint32_t *d = &S.hva[0][0] + hdst;
-      if (hsel == 1) {
-#pragma unroll
-        for (int j = 0; j < 32; ++j) d[1 + j] = p[j];
-      } else if (hsel == 0) {
-        d[0] = p[31];
+  // The plane word this thread fetches each step (role from its thread index):
+  //   tid < 56:        word of the workgroup's own chunks (A: 8, B: 16, C: 32)
+  //   64 <= tid < 121: a halo word (plane-word halo only)
+  //     u 0 .. 8:   pass A rows y0-2, y0+16, y0+18 in chunk columns tx-1, tx, tx+1
+  //     u 9 .. 24:  pass A own rows, chunk columns tx-1 (code 31) and tx+1 (codes 0, 1)
+  //     u 25 .. 56: pass B rows (zz, k), chunk columns tx-1 and tx+1
+  struct Role {
+    int p, dy, dx, zz, row, y, sel, dst;  // sel: 0 code 31, 1 all 32, 2 codes 0 and 1, 3 own words
+  };
+  auto role_of = [&](int t) {
+    Role r{-1, 0, 0, 0, 0, 0, 0, 0};
+    if (t < 56) {
+      r.p = t < 8 ? 0 : (t < 24 ? 1 : 2);
+      r.row = t < 8 ? t : (t < 24 ? t - 8 : t - 24);
+      r.y = y0;
+      r.sel = 3;
+    } else if (wordhalo && t >= 64 && t < 121) {
+      const int u = t - 64;
+      if (u < 9) {
+        const int q = u / 3, c = u - (u / 3) * 3;
+        r.p = 0;
+        r.dy = q == 0 ? -1 : 1;
+        r.dx = c - 1;
+        r.row = q == 0 ? 7 : q - 1;
+        r.y = q == 0 ? y0 - 2 : y0 + 14 + 2 * q;
+        r.sel = c;
+        r.dst = (q == 0 ? 0 : 8 + q) * NXP;
+      } else if (u < 25) {
+        const int v = u - 9, yj = 1 + (v >> 1), side = v & 1;
+        r.p = 0;
+        r.dx = side ? 1 : -1;
+        r.row = yj - 1;
+        r.y = y0 - 2 + 2 * yj;
+        r.sel = side ? 2 : 0;
+        r.dst = yj * NXP;
       } else {
-        d[33] = p[0];
-        d[34] = p[1];
+        const int v = u - 25, zz = v >> 4, k = (v >> 1) & 7, side = v & 1;
+        r.p = 1;
+        r.dx = side ? 1 : -1;
+        r.zz = zz;
+        r.row = k;
+        r.y = y0 + 1 + 2 * k;
+        r.sel = side ? 2 : 0;
+        r.dst = (zz * 8 + k) * 4;
       }
-    } else {
-      uint32_t *d = &S.hvb[0][0][0] + (-1 - hdst);
-      if (hsel == 0) {
-        d[0] = p[31];
-      } else {
-        d[1] = p[0];
-        d[2] = p[1];
-      }
+    }
+    return r;
+  };
+  // whether the role's word exists at chunk row m, its chunk id and word index
+  auto role_word = [&](const Role &r, int m, int64_t &cid, int &wd, Ext &e) -> bool {
+    if (r.p < 0 || m >= m1) return false;
+    const int tyn = ty + r.dy, txn = tx + r.dx;
+    if (unsigned(tyn) >= unsigned(L.tiles_y) || unsigned(txn) >= unsigned(L.tiles_x)) return false;
+    e = chunk_ext(L, r.p, m, tyn, txn);
+    cid = chunk_id(L, m, tyn, txn);
+    if (r.sel == 3) {
+      wd = r.row;
+      return wd < ((e.count + 31) >> 5);
+    }
+    if (r.y < 0 || r.y >= Ly) return false;
+    if (r.p == 0 && 2 * m + 1 >= Lz) return false;
+    if (r.p == 1 && 2 * m + r.zz >= Lz) return false;
+    wd = r.p == 0 ? r.row : r.zz * e.ey + r.row;
+    return true;
+  };
+  // prefetched mask and first payload word of the next step's chunk
+  uint32_t pmask = 0;
+  uint64_t pword = 0;
+  auto prefetch_word = [&](const Role &r, int m) {
+    int64_t cid;
+    int wd;
+    Ext e;
+    if (role_word(r, m, cid, wd, e)) {
+      const uint64_t g = uint64_t(LSEL(chunk_base, r.p) + cid);
+      pmask = in.masks[g];
+      pword = packed ? in.chunk_off[g] : LSEL(slot_base, r.p) + uint64_t(cid) * 32u * LSEL(wmax, r.p);
     }
   };
 
+  // coarse-plane entries tid, tid + 256 (< 385) of the ring, prefetched a step ahead
   T rv[2];
-  auto issue_ring = [&](int cz) {
+  auto ring_slot = [&](int i, int t, int &li) -> int64_t {
+    const int e = t + i * WG3;
+    const int yj = e / NXE, xi = e - (e / NXE) * NXE;
+    const int cy = (y0 >> 1) - 1 + yj, cx = (x0 >> 1) - 1 + xi;
+    const bool ok = e < NYE * NXE && unsigned(cy) < unsigned(L.G[1]) && unsigned(cx) < unsigned(L.G[2]);
+    li = e < NYE * NXE ? yj * NXP + xi : -1;
+    return ok ? int64_t(cy) * L.G[2] + cx : 0;
+  };
+  auto issue_ring = [&](int cz, int t) {
     if (cz < L.G[0]) {
       const T *gp = gin + int64_t(cz) * L.G[1] * L.G[2];
+      int li;
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const T v = gp[roff[i]];
-        rv[i] = rj[i] >= 0 ? v : T(0);
-      }
+      for (int i = 0; i < 2; ++i) rv[i] = gp[ring_slot(i, t, li)];
     }
   };
 
   load_ring_plane(L, gin, S, m0 - 1, y0, x0);
   load_ring_plane(L, gin, S, m0, y0, x0);
   load_ring_plane(L, gin, S, m0 + 1, y0, x0);
-  issue_ring(m0 + 2);
+  issue_ring(m0 + 2, tid0);
+  prefetch_word(role_of(tid0), m0);
 
-  for (int gm = m0; gm < m1; gm += 2) {
-    const int nsteps = (m1 - gm) >= 2 ? 2 : 1;
-    // ---- decode the own codes of the next two chunk rows
-    if (tid < 112) {
-      int rp, rsi, rw;
-      row_role(tid, rp, rsi, rw);
-      if (rsi < nsteps) {
-        const Ext ce = chunk_ext(L, rp, gm + rsi, ty, tx);
-        const int W = (ce.count + 31) >> 5;
-        if (rw < W) {
-          const int64_t cid = chunk_id(L, gm + rsi, ty, tx);
-          const uint32_t mask = in.masks[L.chunk_base[rp] + cid];
-          uint32_t p[32];
-          load_planes(in, chunk_words(L, in, rp, cid), mask, keep[rp], uint32_t(W), uint32_t(rw), p);
-          planes_to_codes(p, keep[rp]);
-          uint32_t *cb = S.codes + code_off(rp, rsi) + 33 * rw;
-          const int nv = ce.count - 32 * rw;
+  for (int m = m0; m < m1; ++m) {
+    // a fresh copy of the thread index each step: values derived from it are
+    // recomputed here instead of being held in registers across the loop
+    int tid = tid0;
+    asm volatile("" : "+v"(tid));
+    const int ze = 2 * m, zo = 2 * m + 1;
+    // ---- stash the coarse plane m + 2
+    if (m + 2 < L.G[0]) {
+      T *rs = &S.ring[(m + 2) & 3][0][0];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        int li;
+        ring_slot(i, tid, li);
+        if (li >= 0) rs[li] = rv[i];
+      }
+    }
+    // ---- this step's plane words: own chunks and halo
+    {
+      const Role r = role_of(tid);
+      int64_t cid;
+      int wd;
+      Ext e;
+      const bool ok = role_word(r, m, cid, wd, e);
+      const uint32_t mask = pmask;
+      const uint64_t first = pword;
+      if (m + 1 < m1) prefetch_word(r, m + 1);
+      if (ok) {
+        const uint32_t keep = sel3(r.p, keepA, keepB, keepC);
+        uint32_t p[32];
+        load_planes(in, first, mask, keep, uint32_t((e.count + 31) >> 5), uint32_t(wd), p);
+        planes_to_codes(p, keep);
+        if (r.sel == 3) {
+          uint32_t *cb = S.codes + code_off1(r.p) + 33 * wd;
+          const int nv = e.count - 32 * wd;
 #pragma unroll
           for (int j = 0; j < 32; ++j)
             if (j < nv) cb[j] = p[j];
+        } else if (r.p == 0) {
+          uint32_t *d = &S.hva[0][0] + r.dst;
+          if (r.sel == 1) {
+#pragma unroll
+            for (int j = 0; j < 32; ++j) d[1 + j] = p[j];
+          } else if (r.sel == 0) {
+            d[0] = p[31];
+          } else {
+            d[33] = p[0];
+            d[34] = p[1];
+          }
+        } else {
+          uint32_t *d = &S.hvb[0][0][0] + r.dst;
+          if (r.sel == 0) {
+            d[0] = p[31];
+          } else {
+            d[1] = p[0];
+            d[2] = p[1];
+          }
         }
       }
     }
-    for (int si = 0; si < nsteps; ++si) {
-      const int m = gm + si;
-      const int ze = 2 * m, zo = 2 * m + 1;
-      // ---- stash the prefetched coarse plane m + 2; codes of the halo targets
-      if (m + 2 < L.G[0]) {
-        T *rs = &S.ring[(m + 2) & 3][0][0];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-          if (rj[i] != INT32_MIN) rs[rj[i] >= 0 ? rj[i] : -1 - rj[i]] = rv[i];
+    // ---- halo codes one at a time where chunk rows are not single words
+    if (!wordhalo && tid >= 64 && tid < 64 + NHA) {
+      int yj, xi;
+      halo_a(tid - 64, yj, xi);
+      int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
+      if (zo < Lz && unsigned(y) < unsigned(Ly) && unsigned(xg) < unsigned(Lx)) {
+        int tyn, oy, txn, ox;
+        halo_tile(ty, yj, 8, tyn, oy);
+        halo_tile(tx, xi, 32, txn, ox);
+        S.hva[yj][xi] = fetch_code(L, in, 0, m, tyn, txn, 0, oy, ox, keepA);
       }
-      if (wordhalo) {
-        halo_words(m);
-      } else if (tid < NHA) {
-        int yj, xi;
-        halo_a(tid, yj, xi);
-        int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
-        if (zo < Lz && unsigned(y) < unsigned(Ly) && unsigned(xg) < unsigned(Lx)) {
-          int tyn, oy, txn, ox;
-          halo_tile(ty, yj, 8, tyn, oy);
-          halo_tile(tx, xi, 32, txn, ox);
-          S.hva[yj][xi] = fetch_code(L, in, 0, m, tyn, txn, 0, oy, ox, keep[0]);
-        }
-      } else if (tid < NHA + NHB) {
-        int zz, k, xi;
-        halo_b(tid - NHA, zz, k, xi);
-        int z = ze + zz, y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
-        if (z < Lz && y < Ly && unsigned(xg) < unsigned(Lx)) {
-          int txn, ox;
-          halo_tile(tx, xi, 32, txn, ox);
-          S.hvb[zz][k][xi & 3] = fetch_code(L, in, 1, m, ty, txn, zz, k, ox, keep[1]);
-        }
+    } else if (!wordhalo && tid >= 64 + NHA && tid < 64 + NHA + NHB) {
+      int zz, k, xi;
+      halo_b(tid - 64 - NHA, zz, k, xi);
+      int z = ze + zz, y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
+      if (z < Lz && y < Ly && unsigned(xg) < unsigned(Lx)) {
+        int txn, ox;
+        halo_tile(tx, xi, 32, txn, ox);
+        S.hvb[zz][k][xi & 3] = fetch_code(L, in, 1, m, ty, txn, zz, k, ox, keepB);
       }
-      // outlier ranges of the chunks the step reads: pass A (m, ty-1..ty+1,
-      // tx-1..tx+1), pass B (m, ty, tx-1..tx+1), pass C (m, ty, tx)
-      int any_out = 0;
-      if (has_out && tid >= 64 && tid < 64 + 13) {
-        const int u = tid - 64;
-        const int p = u < 9 ? 0 : (u < 12 ? 1 : 2);
-        const int tyn = u < 9 ? ty - 1 + u / 3 : ty;
-        const int txn = u < 9 ? tx - 1 + u % 3 : (u < 12 ? tx - 10 + u : tx);
-        uint32_t a = 0, b = 0;
-        if (unsigned(tyn) < unsigned(L.tiles_y) && unsigned(txn) < unsigned(L.tiles_x)) {
-          const uint64_t g = uint64_t(L.chunk_base[p] + chunk_id(L, m, tyn, txn));
-          a = in.out_start[g];
-          b = in.out_start[g + 1];
-        }
-        S.orng[u][0] = a;
-        S.orng[u][1] = b;
-        any_out = b > a;
-      }
-      any_out = __builtin_amdgcn_readfirstlane(__syncthreads_or(any_out));
-      if (m + 1 < m1) issue_ring(m + 3);
-      // ---- pass A
-      if (zo < Lz) {
-        const bool hc = zo + 1 < Lz, ha = zo >= 3, he = zo + 3 < Lz;
-        const T *rb = &S.ring[m & 3][0][0];
-        const T *rc = &S.ring[(m + 1) & 3][0][0];
-        const T *ra = &S.ring[(m - 1) & 3][0][0];
-        const T *re = &S.ring[(m + 2) & 3][0][0];
-        const uint32_t *cb = S.codes + code_off(0, si);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int ri = aI[j];
-          if (ri < 0) continue;
-          const uint32_t v = aC[j] >= 0 ? cb[aC[j]] : (&S.hva[0][0])[-1 - aC[j]];
-          const T pred = stencil<T, INTERP>(ha ? ra[ri] : T(0), rb[ri], hc ? rc[ri] : T(0),
-                                            he ? re[ri] : T(0), hc, ha, he);
-          T val = value(pred, v);
-          if (any_out) {
-            const int yj = ri / NXP, xi = ri - (ri / NXP) * NXP;
-            const int oi = (yj == 0 ? 0 : (yj <= 8 ? 3 : 6)) + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
-            const uint32_t a0 = S.orng[oi][0], a1 = S.orng[oi][1];
-            if (a1 > a0) {
-              int tyn, oy, txn, ox;
-              halo_tile(ty, yj, 8, tyn, oy);
-              halo_tile(tx, xi, 32, txn, ox);
-              const Ext e = chunk_ext(L, 0, m, tyn, txn);
-              uint64_t ob;
-              if (find_outlier(in, a0, a1, uint32_t(oy * e.ex + ox), ob)) val = F::from_bits(ob);
-            }
-          }
-          (&S.wa[0][0])[ri] = val;
-        }
-      }
-      __syncthreads();
-      // ---- pass B
-      {
-        const uint32_t *cb = S.codes + code_off(1, si);
-        const bool z1 = ze + 1 < Lz;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          const int bi = bI[j];
-          if (bi < 0) continue;
-          const int zz = bi >> 16, ri = bi & 0xFFFF;
-          if (zz && !z1) continue;
-          const uint32_t v = bC[j] >= 0 ? cb[bC[j]] : (&S.hvb[0][0][0])[-1 - bC[j]];
-          const T *src = zz == 0 ? &S.ring[m & 3][0][0] : &S.wa[0][0];
-          const bool hc = bF[j] & 1, ha = bF[j] & 2, he = bF[j] & 4;
-          const T pred = stencil<T, INTERP>(ha ? src[ri] : T(0), src[ri + NXP], hc ? src[ri + 2 * NXP] : T(0),
-                                            he ? src[ri + 3 * NXP] : T(0), hc, ha, he);
-          T val = value(pred, v);
-          if (any_out) {
-            const int k = ri / NXP, xi = ri - (ri / NXP) * NXP;
-            const int oi = 9 + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
-            const uint32_t a0 = S.orng[oi][0], a1 = S.orng[oi][1];
-            if (a1 > a0) {
-              int txn, ox;
-              halo_tile(tx, xi, 32, txn, ox);
-              const Ext e = chunk_ext(L, 1, m, ty, txn);
-              uint64_t ob;
-              if (find_outlier(in, a0, a1, uint32_t((zz * e.ey + k) * e.ex + ox), ob))
-                val = F::from_bits(ob);
-            }
-          }
-          (&S.wb[zz][0][0])[ri] = val;
-        }
-      }
-      __syncthreads();
-      // ---- pass C
-      {
-        const uint32_t *cb = S.codes + code_off(2, si);
-        const bool z1 = ze + 1 < Lz;
-        const uint32_t oc0 = any_out ? S.orng[12][0] : 0u, oc1 = any_out ? S.orng[12][1] : 0u;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int zz = j >> 1, yy = cr + 8 * (j & 1);
-          if (!cxok || y0 + yy >= Ly || (zz && !z1)) continue;
-          const T *row = even_row<T>(S, m, zz, yy);
-          const T pred = stencil<T, INTERP>(cha ? row[ci] : T(0), row[ci + 1], chc ? row[ci + 2] : T(0),
-                                            che ? row[ci + 3] : T(0), chc, cha, che);
-          const uint32_t local = uint32_t((zz * cey + yy) * cex + ci);
-          T val = value(pred, cb[pidx(int(local))]);
-          uint64_t ob;
-          if (oc1 > oc0 && find_outlier(in, oc0, oc1, local, ob)) val = F::from_bits(ob);
-          S.wc[zz][yy][ci] = val;
-        }
-      }
-      __syncthreads();
-      write_rows(L, S, gout, m, y0, x0);
     }
+    // outlier ranges of the chunks the step reads: pass A (m, ty-1..ty+1,
+    // tx-1..tx+1), pass B (m, ty, tx-1..tx+1), pass C (m, ty, tx)
+    int any_out = 0;
+    if (has_out && tid >= 241 && tid < 254) {
+      const int u = tid - 241;
+      const int p = u < 9 ? 0 : (u < 12 ? 1 : 2);
+      const int tyn = u < 9 ? ty - 1 + u / 3 : ty;
+      const int txn = u < 9 ? tx - 1 + u % 3 : (u < 12 ? tx - 10 + u : tx);
+      uint32_t a = 0, b = 0;
+      if (unsigned(tyn) < unsigned(L.tiles_y) && unsigned(txn) < unsigned(L.tiles_x)) {
+        const uint64_t g = uint64_t(LSEL(chunk_base, p) + chunk_id(L, m, tyn, txn));
+        a = in.out_start[g];
+        b = in.out_start[g + 1];
+      }
+      S.orng[u][0] = a;
+      S.orng[u][1] = b;
+      any_out = b > a;
+    }
+    any_out = __builtin_amdgcn_readfirstlane(__syncthreads_or(any_out));
+    if (m + 1 < m1) issue_ring(m + 3, tid);
+    // ---- pass A: 11 x 35 halo'd even grid of the odd plane
+    if (zo < Lz) {
+      const bool hc = zo + 1 < Lz, ha = zo >= 3, he = zo + 3 < Lz;
+      const T *rb = &S.ring[m & 3][0][0];
+      const T *rc = &S.ring[(m + 1) & 3][0][0];
+      const T *ra = &S.ring[(m - 1) & 3][0][0];
+      const T *re = &S.ring[(m + 2) & 3][0][0];
+      const uint32_t *cb = S.codes + code_off1(0);
+      const int ex = clampi(L.tdims[0][2] - tx * L.ct[0][2], L.ct[0][2]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int t = tid + j * WG3;
+        const int yj = t / NXE, xi = t - (t / NXE) * NXE;
+        const int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
+        if (t >= NYE * NXE || unsigned(y) >= unsigned(Ly) || unsigned(xg) >= unsigned(Lx)) continue;
+        const int ri = yj * NXP + xi;
+        const bool own = unsigned(yj - 1) < 8u && unsigned(xi - 1) < 32u;
+        const uint32_t v = own ? cb[pidx((yj - 1) * ex + (xi - 1))] : (&S.hva[0][0])[ri];
+        const T pred = stencil<T, INTERP>(ha ? ra[ri] : T(0), rb[ri], hc ? rc[ri] : T(0),
+                                          he ? re[ri] : T(0), hc, ha, he);
+        T val = value(pred, v);
+        if (any_out) {
+          const int oi = (yj == 0 ? 0 : (yj <= 8 ? 3 : 6)) + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
+          const uint32_t a0 = S.orng[oi][0], a1 = S.orng[oi][1];
+          if (a1 > a0) {
+            int tyn, oy, txn, ox;
+            halo_tile(ty, yj, 8, tyn, oy);
+            halo_tile(tx, xi, 32, txn, ox);
+            const Ext e = chunk_ext(L, 0, m, tyn, txn);
+            uint64_t ob;
+            if (find_outlier(in, a0, a1, uint32_t(oy * e.ex + ox), ob)) val = F::from_bits(ob);
+          }
+        }
+        (&S.wa[0][0])[ri] = val;
+      }
+    }
+    __syncthreads();
+    // ---- pass B: 2 planes x 8 odd rows x 35 halo'd even columns
+    {
+      const uint32_t *cb = S.codes + code_off1(1);
+      const int ey = clampi(L.tdims[1][1] - ty * L.ct[1][1], L.ct[1][1]);
+      const int ex = clampi(L.tdims[1][2] - tx * L.ct[1][2], L.ct[1][2]);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int t = tid + j * WG3;
+        const int zz = t >= 8 * NXE ? 1 : 0;
+        const int r = t - zz * (8 * NXE);
+        const int k = r / NXE, xi = r - (r / NXE) * NXE;
+        const int y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
+        if (t >= 2 * 8 * NXE || ze + zz >= Lz || y >= Ly || unsigned(xg) >= unsigned(Lx)) continue;
+        const bool own = unsigned(xi - 1) < 32u;
+        const uint32_t v = own ? cb[pidx((zz * ey + k) * ex + (xi - 1))] : S.hvb[zz][k][xi & 3];
+        const T *src = zz == 0 ? S.ring[m & 3][0] : S.wa[0];
+        const int ri = k * NXP + xi;
+        const bool hc = y + 1 < Ly, ha = y >= 3, he = y + 3 < Ly;
+        const T pred = stencil<T, INTERP>(ha ? src[ri] : T(0), src[ri + NXP], hc ? src[ri + 2 * NXP] : T(0),
+                                          he ? src[ri + 3 * NXP] : T(0), hc, ha, he);
+        T val = value(pred, v);
+        if (any_out) {
+          const int oi = 9 + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
+          const uint32_t a0 = S.orng[oi][0], a1 = S.orng[oi][1];
+          if (a1 > a0) {
+            int txn, ox;
+            halo_tile(tx, xi, 32, txn, ox);
+            const Ext e = chunk_ext(L, 1, m, ty, txn);
+            uint64_t ob;
+            if (find_outlier(in, a0, a1, uint32_t((zz * e.ey + k) * e.ex + ox), ob)) val = F::from_bits(ob);
+          }
+        }
+        S.wb[zz][k][xi] = val;
+      }
+    }
+    __syncthreads();
+    // ---- pass C: 2 planes x 16 rows x 32 odd columns
+    {
+      const uint32_t *cb = S.codes + code_off1(2);
+      const int ci = tid & 31, cr = (tid >> 5) & 7;
+      const int cxg = x0 + 1 + 2 * ci;
+      const bool chc = cxg + 1 < Lx, cha = cxg >= 3, che = cxg + 3 < Lx;
+      const int cey = clampi(L.tdims[2][1] - ty * L.ct[2][1], L.ct[2][1]);
+      const int cex = clampi(L.tdims[2][2] - tx * L.ct[2][2], L.ct[2][2]);
+      const uint32_t oc0 = any_out ? S.orng[12][0] : 0u, oc1 = any_out ? S.orng[12][1] : 0u;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int zz = j >> 1, yy = cr + 8 * (j & 1);
+        if (cxg >= Lx || y0 + yy >= Ly || ze + zz >= Lz) continue;
+        const T *row = even_row<T>(S, m, zz, yy);
+        const T pred = stencil<T, INTERP>(cha ? row[ci] : T(0), row[ci + 1], chc ? row[ci + 2] : T(0),
+                                          che ? row[ci + 3] : T(0), chc, cha, che);
+        const uint32_t local = uint32_t((zz * cey + yy) * cex + ci);
+        T val = value(pred, cb[pidx(int(local))]);
+        uint64_t ob;
+        if (oc1 > oc0 && find_outlier(in, oc0, oc1, local, ob)) val = F::from_bits(ob);
+        S.wc[zz][yy][ci] = val;
+      }
+    }
+    __syncthreads();
+    write_rows(L, S, gout, m, y0, x0);
+    // the next step's word fetch rewrites the code buffers pass C read above
     __syncthreads();
   }
 }
