@@ -287,9 +287,8 @@ struct SharedC {
   T wb[2][8][NXP];
   T wc[2][16][32];
   T xin[XIN_N];
-  uint32_t codes[2 * PADA + 2 * PADB + 2 * PADC];
+  uint32_t codes[PADA + PADB + PADC];
   uint32_t bm[3][RW];       // residues w mod 2^13 present among each pass's codes
-  uint32_t cmask[3][2];
   uint32_t eq[3][33];       // per workgroup delta-y of each pass
   uint32_t qa[3];           // largest |q| among 14-digit codes, per pass
 };
@@ -297,9 +296,6 @@ struct SharedC {
 // code buffers of one step (retrieval): pass A, B, C
 __device__ __forceinline__ int code_off1(int p) { return p == 0 ? 0 : (p == 1 ? PADA : PADA + PADB); }
 
-__device__ __forceinline__ int code_off(int p, int si) {
-  return p == 0 ? si * PADA : (p == 1 ? 2 * PADA + si * PADB : 2 * PADA + 2 * PADB + si * PADC);
-}
 
 // Tile (tx, ty) and column segment zs of this workgroup.  Consecutive
 // workgroup ids are dealt round-robin to the 8 XCDs; renumbering them so that
@@ -378,23 +374,6 @@ __device__ __forceinline__ void write_rows(const Level3Args &L, SH &S, T *gout, 
       if (x + 3 < Lx) dst[3] = v3;
     }
   }
-}
-
-// role of thread tid < 112 in the encode / decode of a group of two chunk rows:
-// pass rp, chunk row rsi, plane-word column rw
-__device__ __forceinline__ void row_role(int tid, int &rp, int &rsi, int &rw) {
-  if (tid < 16) { rp = 0; rsi = tid >> 3; rw = tid & 7; }
-  else if (tid < 48) { rp = 1; rsi = (tid - 16) >> 4; rw = (tid - 16) & 15; }
-  else { rp = 2; rsi = (tid - 48) >> 5; rw = (tid - 48) & 31; }
-}
-
-// role of thread tid < 112 in the encode of a group of two chunk rows, with
-// the rows of each chunk in one wave: wave 0 holds pass C (32 + 32 rows),
-// wave 1 pass B (16 + 16) and pass A (8 + 8)
-__device__ __forceinline__ void enc_role(int tid, int &rp, int &rsi, int &rw) {
-  if (tid < 64) { rp = 2; rsi = tid >> 5; rw = tid & 31; }
-  else if (tid < 96) { rp = 1; rsi = (tid - 64) >> 4; rw = (tid - 64) & 15; }
-  else { rp = 0; rsi = (tid - 96) >> 3; rw = (tid - 96) & 7; }
 }
 
 __device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) { return a > b ? a - b : b - a; }
@@ -543,7 +522,7 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
   using BT = BitsOf<T>;
   using U = typename BT::U;
   __shared__ SharedC<T> S;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid0 = threadIdx.x;
   int tx, ty, zs;
   block_tile(L, tx, ty, zs);
   const int x0 = tx * TX, y0 = ty * TY;
@@ -551,101 +530,14 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
   const int m1 = m0 + L.zseg < L.tiles_z ? m0 + L.zseg : L.tiles_z;
   const int Lz = L.L[0], Ly = L.L[1], Lx = L.L[2];
 
-  for (int i = tid; i < 3 * RW; i += WG3) (&S.bm[0][0])[i] = 0u;
-  if (tid < 3 * 33) (&S.eq[0][0])[tid] = 0u;
-  if (tid < 3) S.qa[tid] = 0u;
-
-  // ---- per-thread constants
-  // tile inputs: rows ly + 4 i of both planes at column lx (xin index tid + 256 i)
-  const int lx = tid & 63, ly = tid >> 6;
-  const bool colok = x0 + lx < Lx;
-  const T *xrow = x + (int64_t(y0 + ly) * L.sY + int64_t(x0 + lx) * L.sX);
-  // the halo input this thread loads (pass A: tid < 129 at the odd plane;
-  // pass B: 129 <= tid < 177 at plane ze + hzz)
-  int hidx = -1, hzz = 1;
-  bool hxy = false;
-  const T *hptr = x;
-  if (tid < NHA) {
-    int yj, xi;
-    halo_a(tid, yj, xi);
-    const int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
-    hxy = unsigned(y) < unsigned(Ly) && unsigned(xg) < unsigned(Lx);
-    hidx = XIN_HA + yj * NXP + xi;
-    if (hxy) hptr = x + (int64_t(y) * L.sY + int64_t(xg) * L.sX);
-  } else if (tid < NHA + NHB) {
-    int zz, k, xi;
-    halo_b(tid - NHA, zz, k, xi);
-    const int y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
-    hxy = y < Ly && unsigned(xg) < unsigned(Lx);
-    hzz = zz;
-    hidx = XIN_HB + (zz * 8 + k) * 4 + (xi & 3);
-    if (hxy) hptr = x + (int64_t(y) * L.sY + int64_t(xg) * L.sX);
-  }
-  // the coarse-plane entries this thread loads: tid, tid + 256 (< 385)
-  int rj[2];
-  int64_t roff[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int t = tid + i * WG3;
-    const int yj = t / NXE, xi = t - (t / NXE) * NXE;
-    const int cy = (y0 >> 1) - 1 + yj, cx = (x0 >> 1) - 1 + xi;
-    const bool ok = t < NYE * NXE && unsigned(cy) < unsigned(L.G[1]) && unsigned(cx) < unsigned(L.G[2]);
-    rj[i] = t < NYE * NXE ? (ok ? yj * NXP + xi : -1 - (yj * NXP + xi)) : INT32_MIN;
-    roff[i] = ok ? int64_t(cy) * L.G[2] + cx : 0;
-  }
-  // pass A: targets tid, tid + 256 of the 11 x 35 halo'd grid
-  //   aI: ring / wa index (-1: outside the level), aX: input index in xin,
-  //   aL: padded code index (-1: halo target)
-  int aI[2], aX[2], aL[2];
-  {
-    const int ex = clampi(L.tdims[0][2] - tx * L.ct[0][2], L.ct[0][2]);
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int t = tid + j * WG3;
-      const int yj = t / NXE, xi = t - (t / NXE) * NXE;
-      const int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
-      const bool ok = t < NYE * NXE && unsigned(y) < unsigned(Ly) && unsigned(xg) < unsigned(Lx);
-      const bool own = unsigned(yj - 1) < 8u && unsigned(xi - 1) < 32u;
-      aI[j] = ok ? yj * NXP + xi : -1;
-      aX[j] = own ? 1024 + (y - y0) * TX + (xg - x0) : XIN_HA + yj * NXP + xi;
-      aL[j] = own ? pidx((yj - 1) * ex + (xi - 1)) : -1;
-    }
-  }
-  // pass B: targets tid, tid + 256, tid + 512 of the 2 x 8 x 35 grid
-  //   bI: zz << 16 | (k * NXP + xi) (-1: outside), bX, bL as for pass A,
-  //   bF: stencil flags (bit 0: c present, 1: a present, 2: e present)
-  int bI[3], bX[3], bL[3], bF[3];
-  {
-    const int ey = clampi(L.tdims[1][1] - ty * L.ct[1][1], L.ct[1][1]);
-    const int ex = clampi(L.tdims[1][2] - tx * L.ct[1][2], L.ct[1][2]);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const int t = tid + j * WG3;
-      const int zz = t >= 8 * NXE ? 1 : 0;
-      const int r = t - zz * (8 * NXE);
-      const int k = r / NXE, xi = r - (r / NXE) * NXE;
-      const int y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
-      const bool ok = t < 2 * 8 * NXE && y < Ly && unsigned(xg) < unsigned(Lx);
-      const bool own = unsigned(xi - 1) < 32u;
-      bI[j] = ok ? (zz << 16) | (k * NXP + xi) : -1;
-      bX[j] = own ? zz * 1024 + (2 * k + 1) * TX + (xg - x0) : XIN_HB + (zz * 8 + k) * 4 + (xi & 3);
-      bL[j] = own ? pidx((zz * ey + k) * ex + (xi - 1)) : -1;
-      bF[j] = (y + 1 < Ly ? 1 : 0) | (y >= 3 ? 2 : 0) | (y + 3 < Ly ? 4 : 0);
-    }
-  }
-  // pass C: targets tid + 256 j: plane j >> 1, row cr + 8 (j & 1), odd column ci
-  const int ci = tid & 31, cr = (tid >> 5) & 7;
-  const int cxg = x0 + 1 + 2 * ci;
-  const bool cxok = cxg < Lx;
-  const bool chc = cxg + 1 < Lx, cha = cxg >= 3, che = cxg + 3 < Lx;
-  const int cey = clampi(L.tdims[2][1] - ty * L.ct[2][1], L.ct[2][1]);
-  const int cex = clampi(L.tdims[2][2] - tx * L.ct[2][2], L.ct[2][2]);
+  for (int i = tid0; i < 3 * RW; i += WG3) (&S.bm[0][0])[i] = 0u;
+  if (tid0 < 3 * 33) (&S.eq[0][0])[tid0] = 0u;
+  if (tid0 < 3) S.qa[tid0] = 0u;
 
   uint32_t qaA = 0, qaB = 0, qaC = 0;
   U mxb = 0;
 
-  auto record = [&](int p, int m, int pl, T xv) {
-    const int local = (pl / 33) * 32 + pl % 33;
+  auto record = [&](int p, int m, int local, T xv) {
     unsigned long long slot = atomicAdd(o.n_out, 1ull);
     if (slot < o.out_cap) {
       OutlierRec *rr = reinterpret_cast<OutlierRec *>(o.out_recs) + slot;
@@ -660,170 +552,212 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
       mxb = b > mxb ? b : mxb;
     }
   };
-  // one own target: its code, its residue, its |q|
-  auto emit_code = [&](int p, uint32_t *cb, int pl, int32_t q, uint32_t &qa) {
+  // one own target: code, residue, |q|, and the outlier record or max |x^|
+  auto own_target = [&](int p, uint32_t *cb, int local, int32_t q, bool out, T xval, T xhat,
+                        uint32_t &qa, int m) {
     const uint32_t w = uint32_t(q) + NB_A;
-    cb[pl] = w ^ NB_A;
+    cb[pidx(local)] = w ^ NB_A;
     atomicOr(&S.bm[p][(w >> 5) & (RW - 1)], 1u << (w & 31));
     const uint32_t aq = uint32_t(q < 0 ? -q : q);
     if (uint32_t(q) + 0x2AAAu <= 0x3FFFu) qa = aq > qa ? aq : qa;
+    if (out) {
+      record(p, m, local, xval);
+    } else {
+      const U b = BT::abs_bits(xhat);
+      mxb = b > mxb ? b : mxb;
+    }
   };
 
-  // prefetched inputs of the next step
+  // inputs of a step, prefetched one step ahead:
+  //   xv[i]: tile row ly + 4 (i & 3) of plane ze + (i >> 2) at column lx (xin tid + 256 i)
+  //   hv:    the halo input of this thread (pass A: tid < 129, pass B: 129 .. 176)
+  //   rv[i]: coarse-plane entry tid + 256 i (< 385) of plane m + 2
+  // Values at positions outside the level are loaded from x[0] and never read
+  // by a stencil, so they are not cleared.
   T xv[8], hv, rv[2];
-  auto issue = [&](int m) {
+  auto halo_of = [&](int t, int &hidx, int &hzz, int &y, int &xg) -> bool {
+    if (t < NHA) {
+      int yj, xi;
+      halo_a(t, yj, xi);
+      y = y0 - 2 + 2 * yj;
+      xg = x0 - 2 + 2 * xi;
+      hzz = 1;
+      hidx = XIN_HA + yj * NXP + xi;
+      return unsigned(y) < unsigned(Ly) && unsigned(xg) < unsigned(Lx);
+    }
+    if (t < NHA + NHB) {
+      int zz, k, xi;
+      halo_b(t - NHA, zz, k, xi);
+      y = y0 + 1 + 2 * k;
+      xg = x0 - 2 + 2 * xi;
+      hzz = zz;
+      hidx = XIN_HB + (zz * 8 + k) * 4 + (xi & 3);
+      return y < Ly && unsigned(xg) < unsigned(Lx);
+    }
+    hidx = -1;
+    return false;
+  };
+  auto ring_slot = [&](int i, int t, int &li) -> int64_t {
+    const int e = t + i * WG3;
+    const int yj = e / NXE, xi = e - (e / NXE) * NXE;
+    const int cy = (y0 >> 1) - 1 + yj, cx = (x0 >> 1) - 1 + xi;
+    const bool ok = e < NYE * NXE && unsigned(cy) < unsigned(L.G[1]) && unsigned(cx) < unsigned(L.G[2]);
+    li = e < NYE * NXE ? yj * NXP + xi : -1;
+    return ok ? int64_t(cy) * L.G[2] + cx : 0;
+  };
+  auto issue = [&](int m, int t) {
     const int ze = 2 * m;
-    const bool z0 = ze < Lz, z1 = ze + 1 < Lz;
-    const T *xz = xrow + int64_t(ze) * L.sZ;
-    // values at positions outside the level are loaded from x[0] and never
-    // read by a stencil, so they are not cleared (no wait right after a load)
+    const int lx = t & 63, ly = t >> 6;
+    const bool colok = x0 + lx < Lx;
+    const T *xz = x + (int64_t(ze) * L.sZ + int64_t(y0 + ly) * L.sY + int64_t(x0 + lx) * L.sX);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int zz = i >> 2, yy = ly + 4 * (i & 3);
-      const bool ok = (zz ? z1 : z0) && y0 + yy < Ly && colok;
+      const bool ok = ze + zz < Lz && y0 + yy < Ly && colok;
       xv[i] = *(ok ? xz + (int64_t(zz) * L.sZ + int64_t(4 * (i & 3)) * L.sY) : x);
     }
     {
-      const bool ok = hxy && ze + hzz < Lz;
-      hv = *(ok ? hptr + int64_t(ze + hzz) * L.sZ : x);
+      int hidx, hzz, y, xg;
+      const bool ok = halo_of(t, hidx, hzz, y, xg) && ze + hzz < Lz;
+      hv = *(ok ? x + (int64_t(ze + hzz) * L.sZ + int64_t(y) * L.sY + int64_t(xg) * L.sX) : x);
     }
     const int cz = m + 2;
     if (cz < L.G[0]) {
       const T *gp = gin + int64_t(cz) * L.G[1] * L.G[2];
+      int li;
 #pragma unroll
-      for (int i = 0; i < 2; ++i) rv[i] = gp[roff[i]];
+      for (int i = 0; i < 2; ++i) rv[i] = gp[ring_slot(i, t, li)];
     }
   };
 
   load_ring_plane(L, gin, S, m0 - 1, y0, x0);
   load_ring_plane(L, gin, S, m0, y0, x0);
   load_ring_plane(L, gin, S, m0 + 1, y0, x0);
-  issue(m0);
+  issue(m0, tid0);
 
-  for (int gm = m0; gm < m1; gm += 2) {
-    const int nsteps = (m1 - gm) >= 2 ? 2 : 1;
-    for (int si = 0; si < nsteps; ++si) {
-      const int m = gm + si;
-      const int ze = 2 * m, zo = 2 * m + 1;
-      // ---- stash the prefetched inputs, then prefetch the next step's
+  for (int m = m0; m < m1; ++m) {
+    // a fresh copy of the thread index each step: values derived from it are
+    // recomputed here instead of being held in registers across the loop
+    int tid = tid0;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63;
+    const int ze = 2 * m, zo = 2 * m + 1;
+    // ---- stash the prefetched inputs, then prefetch the next step's
 #pragma unroll
-      for (int i = 0; i < 8; ++i) S.xin[tid + i * WG3] = xv[i];
-      if (hidx >= 0) S.xin[hidx] = hv;
-      if (m + 2 < L.G[0]) {
-        T *rs = &S.ring[(m + 2) & 3][0][0];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-          if (rj[i] != INT32_MIN) rs[rj[i] >= 0 ? rj[i] : -1 - rj[i]] = rv[i];
-      }
-      __syncthreads();
-      if (m + 1 < m1) issue(m + 1);
-      // ---- pass A (along z) at plane zo on the halo'd even grid
-      if (zo < Lz) {
-        const bool hc = zo + 1 < Lz, ha = zo >= 3, he = zo + 3 < Lz;
-        const T *rb = &S.ring[m & 3][0][0];
-        const T *rc = &S.ring[(m + 1) & 3][0][0];
-        const T *ra = &S.ring[(m - 1) & 3][0][0];
-        const T *re = &S.ring[(m + 2) & 3][0][0];
-        uint32_t *cb = S.codes + code_off(0, si);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int ri = aI[j];
-          if (ri < 0) continue;
-          const T xval = S.xin[aX[j]];
-          const T pred = stencil<T, INTERP>(ha ? ra[ri] : T(0), rb[ri], hc ? rc[ri] : T(0),
-                                            he ? re[ri] : T(0), hc, ha, he);
-          T xhat;
-          bool out;
-          const int32_t q = quantize<T>(xval, pred, eb, two_eb, inv, qmax, xhat, out);
-          (&S.wa[0][0])[ri] = xhat;
-          if (aL[j] >= 0) {
-            emit_code(0, cb, aL[j], q, qaA);
-            if (out) {
-              record(0, m, aL[j], xval);
-            } else {
-              const U b = BT::abs_bits(xhat);
-              mxb = b > mxb ? b : mxb;
-            }
-          }
-        }
-      }
-      __syncthreads();
-      // ---- pass B (along y) at planes ze, zo; odd rows, halo'd even columns
-      {
-        uint32_t *cb = S.codes + code_off(1, si);
-        const bool z1 = ze + 1 < Lz;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          const int bi = bI[j];
-          if (bi < 0) continue;
-          const int zz = bi >> 16, ri = bi & 0xFFFF;
-          if (zz && !z1) continue;
-          const T *src = zz == 0 ? &S.ring[m & 3][0][0] : &S.wa[0][0];
-          const bool hc = bF[j] & 1, ha = bF[j] & 2, he = bF[j] & 4;
-          const T pred = stencil<T, INTERP>(ha ? src[ri] : T(0), src[ri + NXP], hc ? src[ri + 2 * NXP] : T(0),
-                                            he ? src[ri + 3 * NXP] : T(0), hc, ha, he);
-          const T xval = S.xin[bX[j]];
-          T xhat;
-          bool out;
-          const int32_t q = quantize<T>(xval, pred, eb, two_eb, inv, qmax, xhat, out);
-          (&S.wb[zz][0][0])[ri] = xhat;
-          if (bL[j] >= 0) {
-            emit_code(1, cb, bL[j], q, qaB);
-            if (out) {
-              record(1, m, bL[j], xval);
-            } else {
-              const U b = BT::abs_bits(xhat);
-              mxb = b > mxb ? b : mxb;
-            }
-          }
-        }
-      }
-      __syncthreads();
-      // ---- pass C (along x) at planes ze, zo, every row of the tile
-      {
-        uint32_t *cb = S.codes + code_off(2, si);
-        const bool z1 = ze + 1 < Lz;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int zz = j >> 1, yy = cr + 8 * (j & 1);
-          if (!cxok || y0 + yy >= Ly || (zz && !z1)) continue;
-          const T *row = even_row<T>(S, m, zz, yy);
-          const T pred = stencil<T, INTERP>(cha ? row[ci] : T(0), row[ci + 1], chc ? row[ci + 2] : T(0),
-                                            che ? row[ci + 3] : T(0), chc, cha, che);
-          const T xval = S.xin[zz * 1024 + yy * TX + 2 * ci + 1];
-          T xhat;
-          bool out;
-          const int32_t q = quantize<T>(xval, pred, eb, two_eb, inv, qmax, xhat, out);
-          S.wc[zz][yy][ci] = xhat;
-          const int pl = pidx((zz * cey + yy) * cex + ci);
-          emit_code(2, cb, pl, q, qaC);
-          if (out) {
-            record(2, m, pl, xval);
-          } else {
-            const U b = BT::abs_bits(xhat);
-            mxb = b > mxb ? b : mxb;
-          }
-        }
-      }
-      __syncthreads();
-      // ---- the level's output grid (compact), read by the next finer level
-      if (gout) write_rows(L, S, gout, m, y0, x0);
-    }
-    // ---- encode the buffered chunk rows: 32 codes -> 32 plane words per thread.
-    // The rows of one chunk sit in one wave (enc_role), so the chunk's plane
-    // mask is an OR across its lanes.
+    for (int i = 0; i < 8; ++i) S.xin[tid + i * WG3] = xv[i];
     {
-      int rp = 0, rsi = 2, rw = 0;
-      if (tid < 112) enc_role(tid, rp, rsi, rw);
-      const bool act = rsi < nsteps;
-      const Ext rce = chunk_ext(L, rp, gm + (act ? rsi : 0), ty, tx);
+      int hidx, hzz, y, xg;
+      halo_of(tid, hidx, hzz, y, xg);
+      if (hidx >= 0) S.xin[hidx] = hv;
+    }
+    if (m + 2 < L.G[0]) {
+      T *rs = &S.ring[(m + 2) & 3][0][0];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        int li;
+        ring_slot(i, tid, li);
+        if (li >= 0) rs[li] = rv[i];
+      }
+    }
+    __syncthreads();
+    if (m + 1 < m1) issue(m + 1, tid);
+    // ---- pass A (along z) at plane zo on the 11 x 35 halo'd even grid
+    if (zo < Lz) {
+      const bool hc = zo + 1 < Lz, ha = zo >= 3, he = zo + 3 < Lz;
+      const T *rb = &S.ring[m & 3][0][0];
+      const T *rc = &S.ring[(m + 1) & 3][0][0];
+      const T *ra = &S.ring[(m - 1) & 3][0][0];
+      const T *re = &S.ring[(m + 2) & 3][0][0];
+      uint32_t *cb = S.codes + code_off1(0);
+      const int ex = clampi(L.tdims[0][2] - tx * L.ct[0][2], L.ct[0][2]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int t = tid + j * WG3;
+        const int yj = t / NXE, xi = t - (t / NXE) * NXE;
+        const int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
+        if (t >= NYE * NXE || unsigned(y) >= unsigned(Ly) || unsigned(xg) >= unsigned(Lx)) continue;
+        const int ri = yj * NXP + xi;
+        const bool own = unsigned(yj - 1) < 8u && unsigned(xi - 1) < 32u;
+        const T xval = S.xin[own ? 1024 + (y - y0) * TX + (xg - x0) : XIN_HA + ri];
+        const T pred = stencil<T, INTERP>(ha ? ra[ri] : T(0), rb[ri], hc ? rc[ri] : T(0),
+                                          he ? re[ri] : T(0), hc, ha, he);
+        T xhat;
+        bool out;
+        const int32_t q = quantize<T>(xval, pred, eb, two_eb, inv, qmax, xhat, out);
+        (&S.wa[0][0])[ri] = xhat;
+        if (own) own_target(0, cb, (yj - 1) * ex + (xi - 1), q, out, xval, xhat, qaA, m);
+      }
+    }
+    __syncthreads();
+    // ---- pass B (along y) at planes ze, zo; 8 odd rows x 35 halo'd even columns
+    {
+      uint32_t *cb = S.codes + code_off1(1);
+      const int ey = clampi(L.tdims[1][1] - ty * L.ct[1][1], L.ct[1][1]);
+      const int ex = clampi(L.tdims[1][2] - tx * L.ct[1][2], L.ct[1][2]);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int t = tid + j * WG3;
+        const int zz = t >= 8 * NXE ? 1 : 0;
+        const int r = t - zz * (8 * NXE);
+        const int k = r / NXE, xi = r - (r / NXE) * NXE;
+        const int y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
+        if (t >= 2 * 8 * NXE || ze + zz >= Lz || y >= Ly || unsigned(xg) >= unsigned(Lx)) continue;
+        const bool own = unsigned(xi - 1) < 32u;
+        const T *src = zz == 0 ? S.ring[m & 3][0] : S.wa[0];
+        const int ri = k * NXP + xi;
+        const bool hc = y + 1 < Ly, ha = y >= 3, he = y + 3 < Ly;
+        const T pred = stencil<T, INTERP>(ha ? src[ri] : T(0), src[ri + NXP], hc ? src[ri + 2 * NXP] : T(0),
+                                          he ? src[ri + 3 * NXP] : T(0), hc, ha, he);
+        const T xval = S.xin[own ? zz * 1024 + (2 * k + 1) * TX + (xg - x0) : XIN_HB + (zz * 8 + k) * 4 + (xi & 3)];
+        T xhat;
+        bool out;
+        const int32_t q = quantize<T>(xval, pred, eb, two_eb, inv, qmax, xhat, out);
+        S.wb[zz][k][xi] = xhat;
+        if (own) own_target(1, cb, (zz * ey + k) * ex + (xi - 1), q, out, xval, xhat, qaB, m);
+      }
+    }
+    __syncthreads();
+    // ---- pass C (along x) at planes ze, zo: 16 rows x 32 odd columns
+    {
+      uint32_t *cb = S.codes + code_off1(2);
+      const int ci = tid & 31, cr = (tid >> 5) & 7;
+      const int cxg = x0 + 1 + 2 * ci;
+      const bool chc = cxg + 1 < Lx, cha = cxg >= 3, che = cxg + 3 < Lx;
+      const int cey = clampi(L.tdims[2][1] - ty * L.ct[2][1], L.ct[2][1]);
+      const int cex = clampi(L.tdims[2][2] - tx * L.ct[2][2], L.ct[2][2]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int zz = j >> 1, yy = cr + 8 * (j & 1);
+        if (cxg >= Lx || y0 + yy >= Ly || ze + zz >= Lz) continue;
+        const T *row = even_row<T>(S, m, zz, yy);
+        const T pred = stencil<T, INTERP>(cha ? row[ci] : T(0), row[ci + 1], chc ? row[ci + 2] : T(0),
+                                          che ? row[ci + 3] : T(0), chc, cha, che);
+        const T xval = S.xin[zz * 1024 + yy * TX + 2 * ci + 1];
+        T xhat;
+        bool out;
+        const int32_t q = quantize<T>(xval, pred, eb, two_eb, inv, qmax, xhat, out);
+        S.wc[zz][yy][ci] = xhat;
+        own_target(2, cb, (zz * cey + yy) * cex + ci, q, out, xval, xhat, qaC, m);
+      }
+    }
+    __syncthreads();
+    // ---- the level's output grid (compact), read by the next finer level
+    if (gout) write_rows(L, S, gout, m, y0, x0);
+    // ---- wave 0 encodes the step's chunks: 32 codes -> 32 plane words per
+    // lane (pass C: lanes 0-31, B: 32-47, A: 48-55), chunk masks by OR
+    // across each chunk's lanes.  The next step's first barrier orders these
+    // reads of the code buffers before they are rewritten.
+    if (tid < 64) {
+      const int rp = lane < 32 ? 2 : (lane < 48 ? 1 : 0);
+      const int rw = lane < 32 ? lane : (lane < 48 ? lane - 32 : lane - 48);
+      const Ext rce = chunk_ext(L, rp, m, ty, tx);
       const int rW = (rce.count + 31) >> 5;
-      const bool work = act && rw < rW;
+      const bool work = lane < 56 && rw < rW;
       uint32_t r[32];
       uint32_t rowor = 0;
       if (work) {
         // codes 32 rw .. 32 rw + 31 sit at padded indices 33 rw + j
-        const uint32_t *cb = S.codes + code_off(rp, rsi) + 33 * rw;
+        const uint32_t *cb = S.codes + code_off1(rp) + 33 * rw;
         const int nv = rce.count - 32 * rw;
 #pragma unroll
         for (int j = 0; j < 32; ++j) r[j] = j < nv ? cb[j] : 0u;
@@ -835,39 +769,32 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
 #pragma unroll
         for (int k = 31; k >= 0; --k) rowor = (rowor << 1) | (r[k] != 0u ? 1u : 0u);
       }
-      // OR over the 8, 16 or 32 lanes of the chunk row (pass A, B, C)
 #pragma unroll
       for (int o2 = 1; o2 < 32; o2 <<= 1) {
         const uint32_t u = __shfl_xor(rowor, o2, 64);
         if ((8 << rp) > o2) rowor |= u;
       }
+      const int64_t cid = chunk_id(L, m, ty, tx);
       if (work) {
-        const int64_t cid = chunk_id(L, gm + rsi, ty, tx);
         uint32_t *slot = o.payload + LSEL(slot_base, rp) + uint64_t(cid) * 32u * LSEL(wmax, rp) + rw;
 #pragma unroll
         for (int k = 0; k < 32; ++k)
           if ((rowor >> k) & 1u) slot[(31 - k) * rW] = r[k];
       }
-      if (act && rw == 0) {
-        o.masks[LSEL(chunk_base, rp) + chunk_id(L, gm + rsi, ty, tx)] = rowor;
-        S.cmask[rp][rsi] = rowor;
-      }
-    }
-    __syncthreads();
-    // ---- delta-y for b >= 14 of chunks with codes longer than 14 digits
-    {
-      const int ep = wave == 0 ? 0 : (wave == 1 ? 1 : 2);
-      for (int s2 = (ep == 2 ? wave - 2 : 0); s2 < nsteps; s2 += (ep == 2 ? 2 : 1)) {
-        const uint32_t mk = S.cmask[ep][s2];
-        const int nb = mk ? 32 - __clz(mk) : 0;
+      if (lane < 56 && rw == 0) o.masks[LSEL(chunk_base, rp) + cid] = rowor;
+      // delta-y for b >= 14 of chunks holding codes longer than 14 digits
+      const uint32_t mk[3] = {__shfl(rowor, 48, 64), __shfl(rowor, 32, 64), __shfl(rowor, 0, 64)};
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const int nb = mk[p] ? 32 - __clz(mk[p]) : 0;
         if (nb > 14)
-          errq_hi(S.eq[ep], S.codes + code_off(ep, s2), chunk_ext(L, ep, gm + s2, ty, tx).count, nb, lane);
+          errq_hi(S.eq[p], S.codes + code_off1(p), chunk_ext(L, p, m, ty, tx).count, nb, lane);
       }
     }
-    __syncthreads();
   }
   // ---- workgroup totals: per-pass |q| of 14-digit codes, max |x^|
   {
+    const int lane = tid0 & 63, wave = tid0 >> 6;
     uint32_t qs[3] = {qaA, qaB, qaC};
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
@@ -884,20 +811,18 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
       const unsigned long long db = (unsigned long long)__double_as_longlong(BT::to_double(v));
       if (db > *o.maxabs_bits) atomicMax(o.maxabs_bits, db);
     }
+    __syncthreads();
+    if (wave < 3) errq_fold(S.bm[wave], S.eq[wave], lane);
+    __syncthreads();
   }
-  __syncthreads();
-  if (wave < 3) errq_fold(S.bm[wave], S.eq[wave], lane);
-  __syncthreads();
-  if (tid < 3 * 33) {
-    const int p = tid / 33, b = tid - p * 33;
+  if (tid0 < 3 * 33) {
+    const int p = tid0 / 33, b = tid0 - p * 33;
     uint32_t val = S.eq[p][b];
     if (b >= 14) val = S.qa[p] > val ? S.qa[p] : val;
     uint32_t *dst = o.errq + size_t(LSEL(pass_index, p)) * 33 + b;
     if (b > 0 && val > *dst) atomicMax(dst, val);
   }
 }
-
-// ------------------------------------------------------------------ retrieve
 
 // 32 plane words (p[k] = plane k of 32 codes, absent planes 0) -> the 32
 // codes v with the digits outside `keep` cleared.  The XOR coding e = v ^
