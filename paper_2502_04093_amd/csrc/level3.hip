@@ -118,16 +118,25 @@ __device__ __forceinline__ uint32_t xdec(uint32_t e) {
   return t;
 }
 
-// One-dimensional stencil on gathered neighbours (b, c at -+1; a, e at -+3).
+// One-dimensional stencil on gathered neighbours (b, c at -+1; a, e at -+3);
+// hc, ha, he say which of c, a, e exist.  Every lane evaluates the full cubic
+// form; the boundary forms are evaluated only when some lane of the wave needs
+// one, and then chosen by select (the neighbours of a missing point may hold
+// anything: they are never selected).
 template <typename T, int INTERP>
 __device__ __forceinline__ T stencil(T a, T b, T c, T e, bool hc, bool ha, bool he) {
   using F = F3<T>;
-  if (!hc) return b;
-  if (INTERP == IPC_LINEAR) return F::mul(F::add(b, c), T(0.5));
-  if (ha && he) return F::mul(F::sub(F::mul(F::add(b, c), T(9.0)), F::add(a, e)), T(0.0625));
-  if (he) return F::mul(F::sub(F::add(F::mul(b, T(3.0)), F::mul(c, T(6.0))), e), T(0.125));
-  if (ha) return F::mul(F::sub(F::add(F::mul(c, T(3.0)), F::mul(b, T(6.0))), a), T(0.125));
-  return F::mul(F::add(b, c), T(0.5));
+  if (INTERP == IPC_LINEAR) return hc ? F::mul(F::add(b, c), T(0.5)) : b;
+  const bool full = hc && ha && he;
+  T r = F::mul(F::sub(F::mul(F::add(b, c), T(9.0)), F::add(a, e)), T(0.0625));
+  if (__builtin_amdgcn_ballot_w64(!full)) {
+    const T lin = F::mul(F::add(b, c), T(0.5));
+    const T qr = F::mul(F::sub(F::add(F::mul(b, T(3.0)), F::mul(c, T(6.0))), e), T(0.125));
+    const T ql = F::mul(F::sub(F::add(F::mul(c, T(3.0)), F::mul(b, T(6.0))), a), T(0.125));
+    const T g = !hc ? b : (he ? qr : (ha ? ql : lin));
+    r = full ? r : g;
+  }
+  return r;
 }
 
 // Quantization of Sec. 4.2.2 with the explicit check; returns the code (0 for
@@ -679,8 +688,7 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
         const int ri = yj * NXP + xi;
         const bool own = unsigned(yj - 1) < 8u && unsigned(xi - 1) < 32u;
         const T xval = S.xin[own ? 1024 + (y - y0) * TX + (xg - x0) : XIN_HA + ri];
-        const T pred = stencil<T, INTERP>(ha ? ra[ri] : T(0), rb[ri], hc ? rc[ri] : T(0),
-                                          he ? re[ri] : T(0), hc, ha, he);
+        const T pred = stencil<T, INTERP>(ra[ri], rb[ri], rc[ri], re[ri], hc, ha, he);
         T xhat;
         bool out;
         const int32_t q = quantize<T>(xval, pred, eb, two_eb, inv, qmax, xhat, out);
@@ -706,8 +714,7 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
         const T *src = zz == 0 ? S.ring[m & 3][0] : S.wa[0];
         const int ri = k * NXP + xi;
         const bool hc = y + 1 < Ly, ha = y >= 3, he = y + 3 < Ly;
-        const T pred = stencil<T, INTERP>(ha ? src[ri] : T(0), src[ri + NXP], hc ? src[ri + 2 * NXP] : T(0),
-                                          he ? src[ri + 3 * NXP] : T(0), hc, ha, he);
+        const T pred = stencil<T, INTERP>(src[ri], src[ri + NXP], src[ri + 2 * NXP], src[ri + 3 * NXP], hc, ha, he);
         const T xval = S.xin[own ? zz * 1024 + (2 * k + 1) * TX + (xg - x0) : XIN_HB + (zz * 8 + k) * 4 + (xi & 3)];
         T xhat;
         bool out;
@@ -730,8 +737,7 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
         const int zz = j >> 1, yy = cr + 8 * (j & 1);
         if (cxg >= Lx || y0 + yy >= Ly || ze + zz >= Lz) continue;
         const T *row = even_row<T>(S, m, zz, yy);
-        const T pred = stencil<T, INTERP>(cha ? row[ci] : T(0), row[ci + 1], chc ? row[ci + 2] : T(0),
-                                          che ? row[ci + 3] : T(0), chc, cha, che);
+        const T pred = stencil<T, INTERP>(row[ci], row[ci + 1], row[ci + 2], row[ci + 3], chc, cha, che);
         const T xval = S.xin[zz * 1024 + yy * TX + 2 * ci + 1];
         T xhat;
         bool out;
@@ -1110,8 +1116,7 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
         const int ri = yj * NXP + xi;
         const bool own = unsigned(yj - 1) < 8u && unsigned(xi - 1) < 32u;
         const uint32_t v = own ? cb[pidx((yj - 1) * ex + (xi - 1))] : (&S.hva[0][0])[ri];
-        const T pred = stencil<T, INTERP>(ha ? ra[ri] : T(0), rb[ri], hc ? rc[ri] : T(0),
-                                          he ? re[ri] : T(0), hc, ha, he);
+        const T pred = stencil<T, INTERP>(ra[ri], rb[ri], rc[ri], re[ri], hc, ha, he);
         T val = value(pred, v);
         if (any_out) {
           const int oi = (yj == 0 ? 0 : (yj <= 8 ? 3 : 6)) + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
@@ -1147,8 +1152,7 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
         const T *src = zz == 0 ? S.ring[m & 3][0] : S.wa[0];
         const int ri = k * NXP + xi;
         const bool hc = y + 1 < Ly, ha = y >= 3, he = y + 3 < Ly;
-        const T pred = stencil<T, INTERP>(ha ? src[ri] : T(0), src[ri + NXP], hc ? src[ri + 2 * NXP] : T(0),
-                                          he ? src[ri + 3 * NXP] : T(0), hc, ha, he);
+        const T pred = stencil<T, INTERP>(src[ri], src[ri + NXP], src[ri + 2 * NXP], src[ri + 3 * NXP], hc, ha, he);
         T val = value(pred, v);
         if (any_out) {
           const int oi = 9 + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
@@ -1179,8 +1183,7 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
         const int zz = j >> 1, yy = cr + 8 * (j & 1);
         if (cxg >= Lx || y0 + yy >= Ly || ze + zz >= Lz) continue;
         const T *row = even_row<T>(S, m, zz, yy);
-        const T pred = stencil<T, INTERP>(cha ? row[ci] : T(0), row[ci + 1], chc ? row[ci + 2] : T(0),
-                                          che ? row[ci + 3] : T(0), chc, cha, che);
+        const T pred = stencil<T, INTERP>(row[ci], row[ci + 1], row[ci + 2], row[ci + 3], chc, cha, che);
         const uint32_t local = uint32_t((zz * cey + yy) * cex + ci);
         T val = value(pred, cb[pidx(int(local))]);
         uint64_t ob;
