@@ -670,57 +670,78 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
     }
     __syncthreads();
     if (m + 1 < m1) issue(m + 1, tid);
-    // ---- pass A (along z) at plane zo on the 11 x 35 halo'd even grid
+    // ---- pass A (along z) at plane zo: the 8 x 32 own targets (one per
+    // thread), then the 129 halo targets of the 11 x 35 even grid
     if (zo < Lz) {
       const bool hc = zo + 1 < Lz, ha = zo >= 3, he = zo + 3 < Lz;
       const T *rb = &S.ring[m & 3][0][0];
       const T *rc = &S.ring[(m + 1) & 3][0][0];
       const T *ra = &S.ring[(m - 1) & 3][0][0];
       const T *re = &S.ring[(m + 2) & 3][0][0];
-      uint32_t *cb = S.codes + code_off1(0);
-      const int ex = clampi(L.tdims[0][2] - tx * L.ct[0][2], L.ct[0][2]);
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int t = tid + j * WG3;
-        const int yj = t / NXE, xi = t - (t / NXE) * NXE;
+      {
+        const int r = tid >> 5, c = tid & 31;
+        if (y0 + 2 * r < Ly && x0 + 2 * c < Lx) {
+          const int ri = (r + 1) * NXP + c + 1;
+          const T xval = S.xin[1024 + r * 2 * TX + 2 * c];
+          const T pred = stencil<T, INTERP>(ra[ri], rb[ri], rc[ri], re[ri], hc, ha, he);
+          T xhat;
+          bool out;
+          const int32_t q = quantize<T>(xval, pred, eb, two_eb, inv, qmax, xhat, out);
+          (&S.wa[0][0])[ri] = xhat;
+          const int ex = clampi(L.tdims[0][2] - tx * L.ct[0][2], L.ct[0][2]);
+          own_target(0, S.codes + code_off1(0), r * ex + c, q, out, xval, xhat, qaA, m);
+        }
+      }
+      if (tid < NHA) {
+        int yj, xi;
+        halo_a(tid, yj, xi);
         const int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
-        if (t >= NYE * NXE || unsigned(y) >= unsigned(Ly) || unsigned(xg) >= unsigned(Lx)) continue;
-        const int ri = yj * NXP + xi;
-        const bool own = unsigned(yj - 1) < 8u && unsigned(xi - 1) < 32u;
-        const T xval = S.xin[own ? 1024 + (y - y0) * TX + (xg - x0) : XIN_HA + ri];
-        const T pred = stencil<T, INTERP>(ra[ri], rb[ri], rc[ri], re[ri], hc, ha, he);
-        T xhat;
-        bool out;
-        const int32_t q = quantize<T>(xval, pred, eb, two_eb, inv, qmax, xhat, out);
-        (&S.wa[0][0])[ri] = xhat;
-        if (own) own_target(0, cb, (yj - 1) * ex + (xi - 1), q, out, xval, xhat, qaA, m);
+        if (unsigned(y) < unsigned(Ly) && unsigned(xg) < unsigned(Lx)) {
+          const int ri = yj * NXP + xi;
+          const T pred = stencil<T, INTERP>(ra[ri], rb[ri], rc[ri], re[ri], hc, ha, he);
+          T xhat;
+          bool out;
+          quantize<T>(S.xin[XIN_HA + ri], pred, eb, two_eb, inv, qmax, xhat, out);
+          (&S.wa[0][0])[ri] = xhat;
+        }
       }
     }
     __syncthreads();
-    // ---- pass B (along y) at planes ze, zo; 8 odd rows x 35 halo'd even columns
+    // ---- pass B (along y) at planes ze, zo: 2 x 8 x 32 own targets (two per
+    // thread), then the 48 halo targets at columns x0-2, x0+64, x0+66
     {
-      uint32_t *cb = S.codes + code_off1(1);
       const int ey = clampi(L.tdims[1][1] - ty * L.ct[1][1], L.ct[1][1]);
       const int ex = clampi(L.tdims[1][2] - tx * L.ct[1][2], L.ct[1][2]);
+      const int k = tid >> 5, c = tid & 31;
+      const int y = y0 + 1 + 2 * k;
+      const bool hc = y + 1 < Ly, ha = y >= 3, he = y + 3 < Ly;
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const int t = tid + j * WG3;
-        const int zz = t >= 8 * NXE ? 1 : 0;
-        const int r = t - zz * (8 * NXE);
-        const int k = r / NXE, xi = r - (r / NXE) * NXE;
-        const int y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
-        if (t >= 2 * 8 * NXE || ze + zz >= Lz || y >= Ly || unsigned(xg) >= unsigned(Lx)) continue;
-        const bool own = unsigned(xi - 1) < 32u;
+      for (int zz = 0; zz < 2; ++zz) {
+        if (ze + zz >= Lz || y >= Ly || x0 + 2 * c >= Lx) continue;
         const T *src = zz == 0 ? S.ring[m & 3][0] : S.wa[0];
-        const int ri = k * NXP + xi;
-        const bool hc = y + 1 < Ly, ha = y >= 3, he = y + 3 < Ly;
+        const int ri = k * NXP + c + 1;
         const T pred = stencil<T, INTERP>(src[ri], src[ri + NXP], src[ri + 2 * NXP], src[ri + 3 * NXP], hc, ha, he);
-        const T xval = S.xin[own ? zz * 1024 + (2 * k + 1) * TX + (xg - x0) : XIN_HB + (zz * 8 + k) * 4 + (xi & 3)];
+        const T xval = S.xin[zz * 1024 + (2 * k + 1) * TX + 2 * c];
         T xhat;
         bool out;
         const int32_t q = quantize<T>(xval, pred, eb, two_eb, inv, qmax, xhat, out);
-        S.wb[zz][k][xi] = xhat;
-        if (own) own_target(1, cb, (zz * ey + k) * ex + (xi - 1), q, out, xval, xhat, qaB, m);
+        S.wb[zz][k][c + 1] = xhat;
+        own_target(1, S.codes + code_off1(1), (zz * ey + k) * ex + c, q, out, xval, xhat, qaB, m);
+      }
+      if (tid < NHB) {
+        int zz, kh, xi;
+        halo_b(tid, zz, kh, xi);
+        const int yh = y0 + 1 + 2 * kh, xg = x0 - 2 + 2 * xi;
+        if (ze + zz < Lz && yh < Ly && unsigned(xg) < unsigned(Lx)) {
+          const T *src = zz == 0 ? S.ring[m & 3][0] : S.wa[0];
+          const int ri = kh * NXP + xi;
+          const bool hch = yh + 1 < Ly, hah = yh >= 3, heh = yh + 3 < Ly;
+          const T pred = stencil<T, INTERP>(src[ri], src[ri + NXP], src[ri + 2 * NXP], src[ri + 3 * NXP], hch, hah, heh);
+          T xhat;
+          bool out;
+          quantize<T>(S.xin[XIN_HB + (zz * 8 + kh) * 4 + (xi & 3)], pred, eb, two_eb, inv, qmax, xhat, out);
+          S.wb[zz][kh][xi] = xhat;
+        }
       }
     }
     __syncthreads();
@@ -1098,74 +1119,101 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
     }
     any_out = __builtin_amdgcn_readfirstlane(__syncthreads_or(any_out));
     if (m + 1 < m1) issue_ring(m + 3, tid);
-    // ---- pass A: 11 x 35 halo'd even grid of the odd plane
+    // ---- pass A at plane zo: the 8 x 32 own targets (one per thread), then
+    // the 129 halo targets of the 11 x 35 even grid
     if (zo < Lz) {
       const bool hc = zo + 1 < Lz, ha = zo >= 3, he = zo + 3 < Lz;
       const T *rb = &S.ring[m & 3][0][0];
       const T *rc = &S.ring[(m + 1) & 3][0][0];
       const T *ra = &S.ring[(m - 1) & 3][0][0];
       const T *re = &S.ring[(m + 2) & 3][0][0];
-      const uint32_t *cb = S.codes + code_off1(0);
-      const int ex = clampi(L.tdims[0][2] - tx * L.ct[0][2], L.ct[0][2]);
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int t = tid + j * WG3;
-        const int yj = t / NXE, xi = t - (t / NXE) * NXE;
-        const int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
-        if (t >= NYE * NXE || unsigned(y) >= unsigned(Ly) || unsigned(xg) >= unsigned(Lx)) continue;
-        const int ri = yj * NXP + xi;
-        const bool own = unsigned(yj - 1) < 8u && unsigned(xi - 1) < 32u;
-        const uint32_t v = own ? cb[pidx((yj - 1) * ex + (xi - 1))] : (&S.hva[0][0])[ri];
-        const T pred = stencil<T, INTERP>(ra[ri], rb[ri], rc[ri], re[ri], hc, ha, he);
-        T val = value(pred, v);
-        if (any_out) {
-          const int oi = (yj == 0 ? 0 : (yj <= 8 ? 3 : 6)) + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
-          const uint32_t a0 = S.orng[oi][0], a1 = S.orng[oi][1];
-          if (a1 > a0) {
-            int tyn, oy, txn, ox;
-            halo_tile(ty, yj, 8, tyn, oy);
-            halo_tile(tx, xi, 32, txn, ox);
-            const Ext e = chunk_ext(L, 0, m, tyn, txn);
+      {
+        const int r = tid >> 5, c = tid & 31;
+        if (y0 + 2 * r < Ly && x0 + 2 * c < Lx) {
+          const int ri = (r + 1) * NXP + c + 1;
+          const int ex = clampi(L.tdims[0][2] - tx * L.ct[0][2], L.ct[0][2]);
+          const uint32_t local = uint32_t(r * ex + c);
+          const T pred = stencil<T, INTERP>(ra[ri], rb[ri], rc[ri], re[ri], hc, ha, he);
+          T val = value(pred, S.codes[code_off1(0) + pidx(int(local))]);
+          if (any_out) {
+            const uint32_t a0 = S.orng[4][0], a1 = S.orng[4][1];
             uint64_t ob;
-            if (find_outlier(in, a0, a1, uint32_t(oy * e.ex + ox), ob)) val = F::from_bits(ob);
+            if (a1 > a0 && find_outlier(in, a0, a1, local, ob)) val = F::from_bits(ob);
           }
+          (&S.wa[0][0])[ri] = val;
         }
-        (&S.wa[0][0])[ri] = val;
+      }
+      if (tid < NHA) {
+        int yj, xi;
+        halo_a(tid, yj, xi);
+        const int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
+        if (unsigned(y) < unsigned(Ly) && unsigned(xg) < unsigned(Lx)) {
+          const int ri = yj * NXP + xi;
+          const T pred = stencil<T, INTERP>(ra[ri], rb[ri], rc[ri], re[ri], hc, ha, he);
+          T val = value(pred, (&S.hva[0][0])[ri]);
+          if (any_out) {
+            const int oi = (yj == 0 ? 0 : (yj <= 8 ? 3 : 6)) + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
+            const uint32_t a0 = S.orng[oi][0], a1 = S.orng[oi][1];
+            if (a1 > a0) {
+              int tyn, oy, txn, ox;
+              halo_tile(ty, yj, 8, tyn, oy);
+              halo_tile(tx, xi, 32, txn, ox);
+              const Ext e = chunk_ext(L, 0, m, tyn, txn);
+              uint64_t ob;
+              if (find_outlier(in, a0, a1, uint32_t(oy * e.ex + ox), ob)) val = F::from_bits(ob);
+            }
+          }
+          (&S.wa[0][0])[ri] = val;
+        }
       }
     }
     __syncthreads();
-    // ---- pass B: 2 planes x 8 odd rows x 35 halo'd even columns
+    // ---- pass B at planes ze, zo: 2 x 8 x 32 own targets (two per thread),
+    // then the 48 halo targets at columns x0-2, x0+64, x0+66
     {
-      const uint32_t *cb = S.codes + code_off1(1);
       const int ey = clampi(L.tdims[1][1] - ty * L.ct[1][1], L.ct[1][1]);
       const int ex = clampi(L.tdims[1][2] - tx * L.ct[1][2], L.ct[1][2]);
+      const int k = tid >> 5, c = tid & 31;
+      const int y = y0 + 1 + 2 * k;
+      const bool hc = y + 1 < Ly, ha = y >= 3, he = y + 3 < Ly;
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const int t = tid + j * WG3;
-        const int zz = t >= 8 * NXE ? 1 : 0;
-        const int r = t - zz * (8 * NXE);
-        const int k = r / NXE, xi = r - (r / NXE) * NXE;
-        const int y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
-        if (t >= 2 * 8 * NXE || ze + zz >= Lz || y >= Ly || unsigned(xg) >= unsigned(Lx)) continue;
-        const bool own = unsigned(xi - 1) < 32u;
-        const uint32_t v = own ? cb[pidx((zz * ey + k) * ex + (xi - 1))] : S.hvb[zz][k][xi & 3];
+      for (int zz = 0; zz < 2; ++zz) {
+        if (ze + zz >= Lz || y >= Ly || x0 + 2 * c >= Lx) continue;
         const T *src = zz == 0 ? S.ring[m & 3][0] : S.wa[0];
-        const int ri = k * NXP + xi;
-        const bool hc = y + 1 < Ly, ha = y >= 3, he = y + 3 < Ly;
+        const int ri = k * NXP + c + 1;
+        const uint32_t local = uint32_t((zz * ey + k) * ex + c);
         const T pred = stencil<T, INTERP>(src[ri], src[ri + NXP], src[ri + 2 * NXP], src[ri + 3 * NXP], hc, ha, he);
-        T val = value(pred, v);
+        T val = value(pred, S.codes[code_off1(1) + pidx(int(local))]);
         if (any_out) {
-          const int oi = 9 + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
-          const uint32_t a0 = S.orng[oi][0], a1 = S.orng[oi][1];
-          if (a1 > a0) {
-            int txn, ox;
-            halo_tile(tx, xi, 32, txn, ox);
-            const Ext e = chunk_ext(L, 1, m, ty, txn);
-            uint64_t ob;
-            if (find_outlier(in, a0, a1, uint32_t((zz * e.ey + k) * e.ex + ox), ob)) val = F::from_bits(ob);
-          }
+          const uint32_t a0 = S.orng[10][0], a1 = S.orng[10][1];
+          uint64_t ob;
+          if (a1 > a0 && find_outlier(in, a0, a1, local, ob)) val = F::from_bits(ob);
         }
-        S.wb[zz][k][xi] = val;
+        S.wb[zz][k][c + 1] = val;
+      }
+      if (tid < NHB) {
+        int zz, kh, xi;
+        halo_b(tid, zz, kh, xi);
+        const int yh = y0 + 1 + 2 * kh, xg = x0 - 2 + 2 * xi;
+        if (ze + zz < Lz && yh < Ly && unsigned(xg) < unsigned(Lx)) {
+          const T *src = zz == 0 ? S.ring[m & 3][0] : S.wa[0];
+          const int ri = kh * NXP + xi;
+          const bool hch = yh + 1 < Ly, hah = yh >= 3, heh = yh + 3 < Ly;
+          const T pred = stencil<T, INTERP>(src[ri], src[ri + NXP], src[ri + 2 * NXP], src[ri + 3 * NXP], hch, hah, heh);
+          T val = value(pred, S.hvb[zz][kh][xi & 3]);
+          if (any_out) {
+            const int oi = 9 + (xi == 0 ? 0 : 2);
+            const uint32_t a0 = S.orng[oi][0], a1 = S.orng[oi][1];
+            if (a1 > a0) {
+              int txn, ox;
+              halo_tile(tx, xi, 32, txn, ox);
+              const Ext e = chunk_ext(L, 1, m, ty, txn);
+              uint64_t ob;
+              if (find_outlier(in, a0, a1, uint32_t((zz * e.ey + kh) * e.ex + ox), ob)) val = F::from_bits(ob);
+            }
+          }
+          S.wb[zz][kh][xi] = val;
+        }
       }
     }
     __syncthreads();
