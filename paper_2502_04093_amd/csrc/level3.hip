@@ -525,12 +525,17 @@ struct BitsOf<double> {
 template <typename T, int INTERP>
 __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *__restrict__ x,
                                                           const T *__restrict__ gin, T *gout,
-                                                          double eb, T two_eb, T inv, T qmax,
-                                                          CompressOut o) {
+                                                          double eb_arg, T two_eb_arg, T inv_arg,
+                                                          T qmax_arg, CompressOut o) {
   using F = F3<T>;
   using BT = BitsOf<T>;
   using U = typename BT::U;
   __shared__ SharedC<T> S;
+  // the quantizer's constants, held in vector registers: as scalars they are
+  // spilled and re-read with a lane read at every use
+  double eb = eb_arg;
+  T two_eb = two_eb_arg, inv = inv_arg, qmax = qmax_arg;
+  asm volatile("" : "+v"(eb), "+v"(two_eb), "+v"(inv), "+v"(qmax));
   const int tid0 = threadIdx.x;
   int tx, ty, zs;
   block_tile(L, tx, ty, zs);
@@ -885,9 +890,11 @@ __device__ __forceinline__ void load_planes(const RetrieveIn &in, uint64_t first
 template <typename T, int INTERP>
 __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *__restrict__ gin,
                                                           T *gout, int discA, int discB, int discC,
-                                                          RetrieveIn in, T two_eb) {
+                                                          RetrieveIn in, T two_eb_arg) {
   using F = F3<T>;
   __shared__ Shared3<T> S;
+  T two_eb = two_eb_arg;  // in a vector register (see k_level3_compress)
+  asm volatile("" : "+v"(two_eb));
   const int tid0 = threadIdx.x;
   int tx, ty, zs;
   block_tile(L, tx, ty, zs);
