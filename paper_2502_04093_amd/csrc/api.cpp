@@ -298,6 +298,8 @@ bool fused3(const Schedule &s) {
   if (!(s.D == 3 && s.K >= 1 && s.chunk_log2[0] == 1 && s.chunk_log2[1] == 4 &&
         s.chunk_log2[2] == 6))
     return false;
+  // 32-bit element offsets inside the kernels' two-plane slabs
+  if (s.n_points >= (int64_t(1) << 31)) return false;
   for (int j = 0; j < 3; ++j)
     if (s.dims3[j] > (int64_t(1) << 24)) return false;
   const Level3Args A = level3_args(s, 1);

@@ -78,6 +78,15 @@ __device__ __forceinline__ void transpose32(uint32_t a[32]) {
   }
 }
 
+// (m & a) | (~m & b) as one v_bfi_b32; written as an instruction so the
+// transposes below keep one temporary per word pair instead of the
+// and/shift/or sequences the scheduler would interleave
+__device__ __forceinline__ uint32_t bfi(uint32_t m, uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "s"(m), "v"(a), "v"(b));
+  return r;
+}
+
 // Same transpose: the 16- and 8-bit stages as byte permutes (v_perm_b32),
 // the 4-, 2- and 1-bit stages as shifted bit-field inserts.
 __device__ __forceinline__ void transpose32p(uint32_t a[32]) {
@@ -101,8 +110,8 @@ __device__ __forceinline__ void transpose32p(uint32_t a[32]) {
     for (int k = 0; k < 32; ++k) {
       if (k & j) continue;
       const uint32_t lo = a[k], hi = a[k | j];
-      a[k] = (lo & m) | ((hi << j) & ~m);
-      a[k | j] = ((lo >> j) & m) | (hi & ~m);
+      a[k] = bfi(m, lo, hi << j);
+      a[k | j] = bfi(m, lo >> j, hi);
     }
   }
 }
@@ -582,72 +591,78 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
     }
   };
 
-  // inputs of a step, prefetched one step ahead:
+  // Inputs of a step, prefetched one step ahead (element offsets within the
+  // two fine planes of the step fit 32 bits; the host checks 2 sZ < 2^31):
   //   xv[i]: tile row ly + 4 (i & 3) of plane ze + (i >> 2) at column lx (xin tid + 256 i)
   //   hv:    the halo input of this thread (pass A: tid < 129, pass B: 129 .. 176)
   //   rv[i]: coarse-plane entry tid + 256 i (< 385) of plane m + 2
-  // Values at positions outside the level are loaded from x[0] and never read
-  // by a stencil, so they are not cleared.
+  // Values at positions outside the level are loaded from the slab's first
+  // element and never read by a stencil, so they are not cleared.
   T xv[8], hv, rv[2];
-  auto halo_of = [&](int t, int &hidx, int &hzz, int &y, int &xg) -> bool {
-    if (t < NHA) {
-      int yj, xi;
-      halo_a(t, yj, xi);
-      y = y0 - 2 + 2 * yj;
-      xg = x0 - 2 + 2 * xi;
-      hzz = 1;
-      hidx = XIN_HA + yj * NXP + xi;
-      return unsigned(y) < unsigned(Ly) && unsigned(xg) < unsigned(Lx);
-    }
-    if (t < NHA + NHB) {
-      int zz, k, xi;
-      halo_b(t - NHA, zz, k, xi);
-      y = y0 + 1 + 2 * k;
-      xg = x0 - 2 + 2 * xi;
-      hzz = zz;
-      hidx = XIN_HB + (zz * 8 + k) * 4 + (xi & 3);
-      return y < Ly && unsigned(xg) < unsigned(Lx);
-    }
-    hidx = -1;
-    return false;
-  };
-  auto ring_slot = [&](int i, int t, int &li) -> int64_t {
-    const int e = t + i * WG3;
+  const int lx = tid0 & 63, ly = tid0 >> 6;
+  const bool colok = x0 + lx < Lx;
+  const uint32_t xo0 = uint32_t(int64_t(y0 + ly) * L.sY + int64_t(x0 + lx) * L.sX);
+  const uint32_t sZ32 = uint32_t(L.sZ), sY4 = uint32_t(4 * L.sY);
+  int hidx = -1, hzz = 0;
+  bool hxy = false;
+  uint32_t ho = 0;
+  if (tid0 < NHA) {
+    int yj, xi;
+    halo_a(tid0, yj, xi);
+    const int y = y0 - 2 + 2 * yj, xg = x0 - 2 + 2 * xi;
+    hzz = 1;
+    hidx = XIN_HA + yj * NXP + xi;
+    hxy = unsigned(y) < unsigned(Ly) && unsigned(xg) < unsigned(Lx);
+    if (hxy) ho = uint32_t(L.sZ + int64_t(y) * L.sY + int64_t(xg) * L.sX);
+  } else if (tid0 < NHA + NHB) {
+    int zz, k, xi;
+    halo_b(tid0 - NHA, zz, k, xi);
+    const int y = y0 + 1 + 2 * k, xg = x0 - 2 + 2 * xi;
+    hzz = zz;
+    hidx = XIN_HB + (zz * 8 + k) * 4 + (xi & 3);
+    hxy = y < Ly && unsigned(xg) < unsigned(Lx);
+    if (hxy) ho = uint32_t(int64_t(zz) * L.sZ + int64_t(y) * L.sY + int64_t(xg) * L.sX);
+  }
+  int li[2];
+  uint32_t ro[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int e = tid0 + i * WG3;
     const int yj = e / NXE, xi = e - (e / NXE) * NXE;
     const int cy = (y0 >> 1) - 1 + yj, cx = (x0 >> 1) - 1 + xi;
     const bool ok = e < NYE * NXE && unsigned(cy) < unsigned(L.G[1]) && unsigned(cx) < unsigned(L.G[2]);
-    li = e < NYE * NXE ? yj * NXP + xi : -1;
-    return ok ? int64_t(cy) * L.G[2] + cx : 0;
-  };
-  auto issue = [&](int m, int t) {
+    li[i] = e < NYE * NXE ? yj * NXP + xi : -1;
+    ro[i] = ok ? uint32_t(cy * L.G[2] + cx) : 0u;
+  }
+  auto issue = [&](int m) {
     const int ze = 2 * m;
-    const int lx = t & 63, ly = t >> 6;
-    const bool colok = x0 + lx < Lx;
-    const T *xz = x + (int64_t(ze) * L.sZ + int64_t(y0 + ly) * L.sY + int64_t(x0 + lx) * L.sX);
+    const T *xs = x + int64_t(ze) * L.sZ;
+    // offsets recomputed at each call rather than held across the loop
+    uint32_t xo = xo0;
+    asm volatile("" : "+v"(xo));
+    if (y0 + TY <= Ly && x0 + TX <= Lx && ze + 1 < Lz) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int zz = i >> 2, yy = ly + 4 * (i & 3);
-      const bool ok = ze + zz < Lz && y0 + yy < Ly && colok;
-      xv[i] = *(ok ? xz + (int64_t(zz) * L.sZ + int64_t(4 * (i & 3)) * L.sY) : x);
+      for (int i = 0; i < 8; ++i) xv[i] = xs[xo + (i >> 2) * sZ32 + (i & 3) * sY4];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const bool ok = ze + (i >> 2) < Lz && y0 + ly + 4 * (i & 3) < Ly && colok;
+        xv[i] = xs[ok ? xo + (i >> 2) * sZ32 + (i & 3) * sY4 : 0u];
+      }
     }
-    {
-      int hidx, hzz, y, xg;
-      const bool ok = halo_of(t, hidx, hzz, y, xg) && ze + hzz < Lz;
-      hv = *(ok ? x + (int64_t(ze + hzz) * L.sZ + int64_t(y) * L.sY + int64_t(xg) * L.sX) : x);
-    }
+    hv = xs[hxy && ze + hzz < Lz ? ho : 0u];
     const int cz = m + 2;
     if (cz < L.G[0]) {
       const T *gp = gin + int64_t(cz) * L.G[1] * L.G[2];
-      int li;
 #pragma unroll
-      for (int i = 0; i < 2; ++i) rv[i] = gp[ring_slot(i, t, li)];
+      for (int i = 0; i < 2; ++i) rv[i] = gp[ro[i]];
     }
   };
 
   load_ring_plane(L, gin, S, m0 - 1, y0, x0);
   load_ring_plane(L, gin, S, m0, y0, x0);
   load_ring_plane(L, gin, S, m0 + 1, y0, x0);
-  issue(m0, tid0);
+  issue(m0);
 
   for (int m = m0; m < m1; ++m) {
     // a fresh copy of the thread index each step: values derived from it are
@@ -659,22 +674,15 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
     // ---- stash the prefetched inputs, then prefetch the next step's
 #pragma unroll
     for (int i = 0; i < 8; ++i) S.xin[tid + i * WG3] = xv[i];
-    {
-      int hidx, hzz, y, xg;
-      halo_of(tid, hidx, hzz, y, xg);
-      if (hidx >= 0) S.xin[hidx] = hv;
-    }
+    if (hidx >= 0) S.xin[hidx] = hv;
     if (m + 2 < L.G[0]) {
       T *rs = &S.ring[(m + 2) & 3][0][0];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        int li;
-        ring_slot(i, tid, li);
-        if (li >= 0) rs[li] = rv[i];
-      }
+      for (int i = 0; i < 2; ++i)
+        if (li[i] >= 0) rs[li[i]] = rv[i];
     }
     __syncthreads();
-    if (m + 1 < m1) issue(m + 1, tid);
+    if (m + 1 < m1) issue(m + 1);
     // ---- pass A (along z) at plane zo: the 8 x 32 own targets (one per
     // thread), then the 129 halo targets of the 11 x 35 even grid
     if (zo < Lz) {
