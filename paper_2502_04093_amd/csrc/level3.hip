@@ -1011,27 +1011,29 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
 
   // coarse-plane entries tid, tid + 256 (< 385) of the ring, prefetched a step ahead
   T rv[2];
-  auto ring_slot = [&](int i, int t, int &li) -> int64_t {
-    const int e = t + i * WG3;
+  int li[2];
+  uint32_t ro[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int e = tid0 + i * WG3;
     const int yj = e / NXE, xi = e - (e / NXE) * NXE;
     const int cy = (y0 >> 1) - 1 + yj, cx = (x0 >> 1) - 1 + xi;
     const bool ok = e < NYE * NXE && unsigned(cy) < unsigned(L.G[1]) && unsigned(cx) < unsigned(L.G[2]);
-    li = e < NYE * NXE ? yj * NXP + xi : -1;
-    return ok ? int64_t(cy) * L.G[2] + cx : 0;
-  };
-  auto issue_ring = [&](int cz, int t) {
+    li[i] = e < NYE * NXE ? yj * NXP + xi : -1;
+    ro[i] = ok ? uint32_t(cy * L.G[2] + cx) : 0u;
+  }
+  auto issue_ring = [&](int cz) {
     if (cz < L.G[0]) {
       const T *gp = gin + int64_t(cz) * L.G[1] * L.G[2];
-      int li;
 #pragma unroll
-      for (int i = 0; i < 2; ++i) rv[i] = gp[ring_slot(i, t, li)];
+      for (int i = 0; i < 2; ++i) rv[i] = gp[ro[i]];
     }
   };
 
   load_ring_plane(L, gin, S, m0 - 1, y0, x0);
   load_ring_plane(L, gin, S, m0, y0, x0);
   load_ring_plane(L, gin, S, m0 + 1, y0, x0);
-  issue_ring(m0 + 2, tid0);
+  issue_ring(m0 + 2);
   prefetch_word(role_of(tid0), m0);
 
   for (int m = m0; m < m1; ++m) {
@@ -1044,11 +1046,8 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
     if (m + 2 < L.G[0]) {
       T *rs = &S.ring[(m + 2) & 3][0][0];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        int li;
-        ring_slot(i, tid, li);
-        if (li >= 0) rs[li] = rv[i];
-      }
+      for (int i = 0; i < 2; ++i)
+        if (li[i] >= 0) rs[li[i]] = rv[i];
     }
     // ---- this step's plane words: own chunks and halo
     {
@@ -1133,7 +1132,7 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
       any_out = b > a;
     }
     any_out = __builtin_amdgcn_readfirstlane(__syncthreads_or(any_out));
-    if (m + 1 < m1) issue_ring(m + 3, tid);
+    if (m + 1 < m1) issue_ring(m + 3);
     // ---- pass A at plane zo: the 8 x 32 own targets (one per thread), then
     // the 129 halo targets of the 11 x 35 even grid
     if (zo < Lz) {
