@@ -414,30 +414,30 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 // Delta-y for b >= 14 over one chunk of `count` buffered codes with at most nb
-// digits, nb > 14 (see k_level3_compress): exact |q - q'_b| per code while
-// b < nb, the chunk's largest |q| from there on; into the maxima eq[14..32].
+// digits, nb > 14 (see k_level3_compress), by one wave: exact |q - q'_b| per
+// code while b < nb, the chunk's largest |q| from there on; into the maxima
+// eq[14..32].  One b at a time keeps the register footprint small.
 __device__ __forceinline__ void errq_hi(uint32_t *eq, const uint32_t *v, int count, int nb, int lane) {
-  uint32_t d[19];
-#pragma unroll
-  for (int i = 0; i < 19; ++i) d[i] = 0u;
   uint32_t qa = 0;
   for (int j = lane; j < count; j += 64) {
-    const uint32_t w = v[pidx(j)] ^ NB_A;
-    const int32_t q = int32_t(w - NB_A);
+    const int32_t q = int32_t((v[pidx(j)] ^ NB_A) - NB_A);
     const uint32_t aq = uint32_t(q < 0 ? -q : q);
     qa = aq > qa ? aq : qa;
-#pragma unroll
-    for (int b = 14; b < 32; ++b) {
-      if (b < nb) {
-        const uint32_t t = absdiff(w & ((1u << b) - 1u), NB_A & ((1u << b) - 1u));
-        d[b - 14] = t > d[b - 14] ? t : d[b - 14];
-      }
-    }
   }
-#pragma unroll
+  qa = uint32_t(wave_max(int(qa)));
+#pragma unroll 1
   for (int b = 14; b < 33; ++b) {
-    uint32_t t = b >= nb ? (qa > d[b - 14] ? qa : d[b - 14]) : d[b - 14];
-    if (t) atomicMax(&eq[b], t);
+    uint32_t d = qa;
+    if (b < nb) {
+      const uint32_t mb = (1u << b) - 1u, ab = NB_A & mb;
+      d = 0;
+      for (int j = lane; j < count; j += 64) {
+        const uint32_t t = absdiff((v[pidx(j)] ^ NB_A) & mb, ab);
+        d = t > d ? t : d;
+      }
+      d = uint32_t(wave_max(int(d)));
+    }
+    if (lane == 0 && d) atomicMax(&eq[b], d);
   }
 }
 
@@ -802,10 +802,14 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
 #pragma unroll
         for (int j = 0; j < 32; ++j) r[j] = j < nv ? cb[j] : 0u;
         transpose32p(r);
-        // planes of e = v ^ (v >> 1) ^ (v >> 2) from the planes of v
+        // planes of e = v ^ (v >> 1) ^ (v >> 2) from the planes of v; each
+        // plane is materialized before it is tested (the scheduler would
+        // otherwise keep pairwise partial XORs alive for the tests)
 #pragma unroll
-        for (int k = 0; k < 32; ++k)
+        for (int k = 0; k < 32; ++k) {
           r[k] = k < 30 ? (r[k] ^ r[k + 1] ^ r[k + 2]) : (k == 30 ? (r[30] ^ r[31]) : r[31]);
+          asm volatile("" : "+v"(r[k]));
+        }
 #pragma unroll
         for (int k = 31; k >= 0; --k) rowor = (rowor << 1) | (r[k] != 0u ? 1u : 0u);
       }
