@@ -275,6 +275,9 @@ __device__ __forceinline__ uint32_t fetch_code(const Level3Args &L, const Retrie
   return xdec(code) & keep;
 }
 
+// outliers of one chunk kept in LDS for a step (more are looked up in HBM)
+constexpr int OCAP = 8;
+
 // LDS of a retrieval workgroup
 template <typename T>
 struct Shared3 {
@@ -286,6 +289,8 @@ struct Shared3 {
   uint32_t hvb[2][8][4];    // codes of pass-B halo targets
   uint32_t codes[PADA + PADB + PADC];
   uint32_t orng[13][2];     // outlier ranges of the step's chunks
+  uint32_t oloc[13][OCAP];  // their entries, when a chunk holds at most OCAP
+  uint64_t obits[13][OCAP];
 };
 
 // inputs of a compression step: the tile (both planes), then the halo targets
@@ -934,6 +939,20 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
     return F::add(pred, F::mul(tq, two_eb));
   };
 
+  // exact value of an outlier among the step's chunk oi, if `local` is one
+  auto lookup = [&](int oi, uint32_t local, T &val) {
+    const uint32_t a0 = S.orng[oi][0], a1 = S.orng[oi][1];
+    if (a1 > a0) {
+      if (a1 - a0 <= uint32_t(OCAP)) {
+        for (uint32_t j = 0; j < a1 - a0; ++j)
+          if (S.oloc[oi][j] == local) val = F::from_bits(S.obits[oi][j]);
+      } else {
+        uint64_t ob;
+        if (find_outlier(in, a0, a1, local, ob)) val = F::from_bits(ob);
+      }
+    }
+  };
+
   // The plane word this thread fetches each step (role from its thread index):
   //   tid < 56:        word of the workgroup's own chunks (A: 8, B: 16, C: 32)
   //   64 <= tid < 121: a halo word (plane-word halo only)
@@ -1133,6 +1152,11 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
       }
       S.orng[u][0] = a;
       S.orng[u][1] = b;
+      if (b - a <= uint32_t(OCAP))
+        for (uint32_t j = 0; j < b - a; ++j) {
+          S.oloc[u][j] = in.out_local[a + j];
+          S.obits[u][j] = in.out_bits[a + j];
+        }
       any_out = b > a;
     }
     any_out = __builtin_amdgcn_readfirstlane(__syncthreads_or(any_out));
@@ -1153,11 +1177,7 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
           const uint32_t local = uint32_t(r * ex + c);
           const T pred = stencil<T, INTERP>(ra[ri], rb[ri], rc[ri], re[ri], hc, ha, he);
           T val = value(pred, S.codes[code_off1(0) + pidx(int(local))]);
-          if (any_out) {
-            const uint32_t a0 = S.orng[4][0], a1 = S.orng[4][1];
-            uint64_t ob;
-            if (a1 > a0 && find_outlier(in, a0, a1, local, ob)) val = F::from_bits(ob);
-          }
+          if (any_out) lookup(4, local, val);
           (&S.wa[0][0])[ri] = val;
         }
       }
@@ -1171,14 +1191,12 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
           T val = value(pred, (&S.hva[0][0])[ri]);
           if (any_out) {
             const int oi = (yj == 0 ? 0 : (yj <= 8 ? 3 : 6)) + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
-            const uint32_t a0 = S.orng[oi][0], a1 = S.orng[oi][1];
-            if (a1 > a0) {
+            if (S.orng[oi][1] > S.orng[oi][0]) {
               int tyn, oy, txn, ox;
               halo_tile(ty, yj, 8, tyn, oy);
               halo_tile(tx, xi, 32, txn, ox);
               const Ext e = chunk_ext(L, 0, m, tyn, txn);
-              uint64_t ob;
-              if (find_outlier(in, a0, a1, uint32_t(oy * e.ex + ox), ob)) val = F::from_bits(ob);
+              lookup(oi, uint32_t(oy * e.ex + ox), val);
             }
           }
           (&S.wa[0][0])[ri] = val;
@@ -1202,11 +1220,7 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
         const uint32_t local = uint32_t((zz * ey + k) * ex + c);
         const T pred = stencil<T, INTERP>(src[ri], src[ri + NXP], src[ri + 2 * NXP], src[ri + 3 * NXP], hc, ha, he);
         T val = value(pred, S.codes[code_off1(1) + pidx(int(local))]);
-        if (any_out) {
-          const uint32_t a0 = S.orng[10][0], a1 = S.orng[10][1];
-          uint64_t ob;
-          if (a1 > a0 && find_outlier(in, a0, a1, local, ob)) val = F::from_bits(ob);
-        }
+        if (any_out) lookup(10, local, val);
         S.wb[zz][k][c + 1] = val;
       }
       if (tid < NHB) {
@@ -1221,13 +1235,11 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
           T val = value(pred, S.hvb[zz][kh][xi & 3]);
           if (any_out) {
             const int oi = 9 + (xi == 0 ? 0 : 2);
-            const uint32_t a0 = S.orng[oi][0], a1 = S.orng[oi][1];
-            if (a1 > a0) {
+            if (S.orng[oi][1] > S.orng[oi][0]) {
               int txn, ox;
               halo_tile(tx, xi, 32, txn, ox);
               const Ext e = chunk_ext(L, 1, m, ty, txn);
-              uint64_t ob;
-              if (find_outlier(in, a0, a1, uint32_t((zz * e.ey + kh) * e.ex + ox), ob)) val = F::from_bits(ob);
+              lookup(oi, uint32_t((zz * e.ey + kh) * e.ex + ox), val);
             }
           }
           S.wb[zz][kh][xi] = val;
@@ -1243,7 +1255,6 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
       const bool chc = cxg + 1 < Lx, cha = cxg >= 3, che = cxg + 3 < Lx;
       const int cey = clampi(L.tdims[2][1] - ty * L.ct[2][1], L.ct[2][1]);
       const int cex = clampi(L.tdims[2][2] - tx * L.ct[2][2], L.ct[2][2]);
-      const uint32_t oc0 = any_out ? S.orng[12][0] : 0u, oc1 = any_out ? S.orng[12][1] : 0u;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int zz = j >> 1, yy = cr + 8 * (j & 1);
@@ -1252,8 +1263,7 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
         const T pred = stencil<T, INTERP>(row[ci], row[ci + 1], row[ci + 2], row[ci + 3], chc, cha, che);
         const uint32_t local = uint32_t((zz * cey + yy) * cex + ci);
         T val = value(pred, cb[pidx(int(local))]);
-        uint64_t ob;
-        if (oc1 > oc0 && find_outlier(in, oc0, oc1, local, ob)) val = F::from_bits(ob);
+        if (any_out) lookup(12, local, val);
         S.wc[zz][yy][ci] = val;
       }
     }
