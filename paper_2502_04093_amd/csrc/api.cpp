@@ -38,6 +38,8 @@ struct ipc_ctx {
   size_t ws_g_bytes[2] = {0, 0};
   void *ws_args = nullptr;              // PassArgs of the current call
   size_t ws_args_bytes = 0;
+  void *ws_cnt = nullptr;               // outlier index scratch: per-chunk counts, block sums
+  size_t ws_cnt_bytes = 0;
   void *host_summary = nullptr;         // pinned copy of the compression summary
   size_t host_summary_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -65,6 +67,7 @@ struct ipc_stream {
   DevBuf chunk_off;            // u64 per chunk (packed placement only)
   DevBuf out_gchunk, out_local, out_bits, out_start;
   bool host_masks_valid = false;
+  bool host_outliers_valid = true;  // meta.outliers holds the records (else only on the device)
   std::vector<PassArgs> args;
 };
 
@@ -250,6 +253,8 @@ void free_stream_bufs(ipc_stream *s) {
 
 void upload_outliers(ipc_ctx *ctx, ipc_stream *s) {
   size_t n = s->meta.outliers.size();
+  s->meta.n_outliers = n;
+  s->host_outliers_valid = true;
   if (n == 0) return;
   std::vector<uint64_t> gch(n), bits(n);
   std::vector<uint32_t> loc(n);
@@ -271,6 +276,34 @@ void upload_outliers(ipc_ctx *ctx, ipc_stream *s) {
                                   static_cast<uint32_t *>(s->out_start.p), ctx->stream),
             "outlier index launch");
   hip_check(ctx, hipStreamSynchronize(ctx->stream), "upload");
+}
+
+// the device-sorted outlier records into meta.outliers (pass, chunk, local, bits)
+void fetch_outliers(ipc_ctx *ctx, ipc_stream *s) {
+  StreamMeta &m = s->meta;
+  const size_t n = size_t(m.n_outliers);
+  std::vector<uint64_t> gch(n), bits(n);
+  std::vector<uint32_t> loc(n);
+  if (n) {
+    hip_check(ctx, hipMemcpyAsync(gch.data(), s->out_gchunk.p, 8 * n, hipMemcpyDeviceToHost, ctx->stream), "copy");
+    hip_check(ctx, hipMemcpyAsync(loc.data(), s->out_local.p, 4 * n, hipMemcpyDeviceToHost, ctx->stream), "copy");
+    hip_check(ctx, hipMemcpyAsync(bits.data(), s->out_bits.p, 8 * n, hipMemcpyDeviceToHost, ctx->stream), "copy");
+    hip_check(ctx, hipStreamSynchronize(ctx->stream), "copy");
+  }
+  m.outliers.resize(n);
+  const std::vector<PassGeom> &ps = m.sched.passes;
+  size_t p = 0;
+  for (size_t i = 0; i < n; ++i) {
+    // records are sorted by global chunk, so the pass index only moves forward
+    while (p + 1 < ps.size() && uint64_t(ps[p + 1].chunk_base) <= gch[i]) ++p;
+    OutlierRec &o = m.outliers[i];
+    o.pass = uint32_t(p);
+    o.chunk = uint32_t(gch[i] - uint64_t(ps[p].chunk_base));
+    o.local = loc[i];
+    o.pad = 0;
+    o.bits = bits[i];
+  }
+  s->host_outliers_valid = true;
 }
 
 void fill_info(const ipc_stream *s, const std::vector<int> &plan, double bound, uint32_t flags,
@@ -387,7 +420,7 @@ void run_retrieve(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &pla
   in.out_local = static_cast<const uint32_t *>(s->out_local.p);
   in.out_bits = static_cast<const uint64_t *>(s->out_bits.p);
   in.out_start = static_cast<const uint32_t *>(s->out_start.p);
-  in.n_out = s->meta.outliers.size();
+  in.n_out = s->meta.n_outliers;
   prof_begin(ctx, s->args.size());
   const Schedule &sc = s->meta.sched;
   if (fused3(sc)) {
@@ -533,6 +566,7 @@ void ipc_ctx_destroy(ipc_ctx *ctx) {
   if (ctx->ws_xh) (void)hipFree(ctx->ws_xh);
   if (ctx->ws_summary) (void)hipFree(ctx->ws_summary);
   if (ctx->ws_out) (void)hipFree(ctx->ws_out);
+  if (ctx->ws_cnt) (void)hipFree(ctx->ws_cnt);
   for (int i = 0; i < 2; ++i)
     if (ctx->ws_g[i]) (void)hipFree(ctx->ws_g[i]);
   if (ctx->ws_args) (void)hipFree(ctx->ws_args);
@@ -658,6 +692,29 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
       hip_check(ctx, launch_all_sizes(static_cast<const PassArgs *>(ctx->ws_args), P, max_chunks,
                                       o.masks, sizes, ctx->stream),
                 "sizes kernel launch");
+      // the outlier index, sorted on the device (records stay there until a
+      // serialization asks for them)
+      {
+        const uint64_t nc = uint64_t(sc.n_chunks);
+        dev_free(ctx, s->out_gchunk);
+        dev_free(ctx, s->out_local);
+        dev_free(ctx, s->out_bits);
+        dev_free(ctx, s->out_start);
+        s->out_gchunk = dev_alloc(ctx, 8 * cap_recs);
+        s->out_local = dev_alloc(ctx, 4 * cap_recs);
+        s->out_bits = dev_alloc(ctx, 8 * cap_recs);
+        s->out_start = dev_alloc(ctx, 4 * (nc + 1));
+        const size_t nb = (nc + 1 + 1023) / 1024;
+        uint32_t *cnt = static_cast<uint32_t *>(
+            ensure_ws(ctx, ctx->ws_cnt, ctx->ws_cnt_bytes, 4 * (nc + 1) + 4 * (nb + 1)));
+        hip_check(ctx, launch_outlier_index(static_cast<const OutlierRec *>(o.out_recs), o.n_out,
+                                            cap_recs, static_cast<const PassArgs *>(ctx->ws_args),
+                                            nc, static_cast<uint32_t *>(s->out_start.p), cnt,
+                                            cnt + (nc + 1), static_cast<uint64_t *>(s->out_gchunk.p),
+                                            static_cast<uint32_t *>(s->out_local.p),
+                                            static_cast<uint64_t *>(s->out_bits.p), ctx->stream),
+                  "outlier index launch");
+      }
       hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
       if (ctx->host_summary_bytes < sum_bytes) {
         if (ctx->host_summary) (void)hipHostFree(ctx->host_summary);
@@ -685,15 +742,9 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
       std::memcpy(m.errq.data(), hostp + 16 + size_t(P) * 32 * 8, m.errq.size() * 4);
       std::vector<uint64_t> sz(size_t(P) * 32);
       std::memcpy(sz.data(), hostp + 16, sz.size() * 8);
-      m.outliers.resize(nout);
-      if (nout) {
-        hip_check(ctx, hipMemcpy(m.outliers.data(), ctx->ws_out, nout * sizeof(OutlierRec), hipMemcpyDeviceToHost), "copy");
-        std::sort(m.outliers.begin(), m.outliers.end(), [](const OutlierRec &a, const OutlierRec &b) {
-          if (a.pass != b.pass) return a.pass < b.pass;
-          if (a.chunk != b.chunk) return a.chunk < b.chunk;
-          return a.local < b.local;
-        });
-      }
+      m.outliers.clear();
+      m.n_outliers = nout;
+      s->host_outliers_valid = nout == 0;
       uint64_t words = 0;
       for (uint64_t v : sz) words += v / 4;
       m.payload_words = words;
@@ -702,7 +753,6 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
       s->tables = plan_tables_from_sizes(m, sz);
       break;
     }
-    upload_outliers(ctx, s);
   });
   if (st != IPC_OK) {
     free_stream_bufs(s);
@@ -739,6 +789,7 @@ ipc_status ipc_stream_to_host(ipc_ctx *ctx, const ipc_stream *sc, void *dst, uin
       hip_check(ctx, hipStreamSynchronize(ctx->stream), "copy");
       s->host_masks_valid = true;
     }
+    if (!s->host_outliers_valid) fetch_outliers(ctx, s);
     uint8_t *d = static_cast<uint8_t *>(dst);
     write_serialized_head(m, d);
     uint64_t poff = payload_offset(m);

@@ -106,7 +106,8 @@ struct StreamMeta {
   Schedule sched;
   std::vector<uint32_t> errq;       // [P][33]
   std::vector<uint32_t> masks;      // [n_chunks]
-  std::vector<OutlierRec> outliers; // sorted by (pass, chunk, local)
+  std::vector<OutlierRec> outliers; // sorted by (pass, chunk, local); may be left on the device
+  uint64_t n_outliers = 0;
   uint64_t payload_words = 0;       // packed payload size
   uint64_t serialized_bytes = 0;
 };

@@ -7,6 +7,8 @@
 
 namespace ipc {
 
+struct OutlierRec;
+
 // Geometry of one pass, as the kernels see it (3-D padded).
 struct PassArgs {
   int64_t dims3[3];   // fine extents
@@ -82,6 +84,14 @@ hipError_t launch_compress_pass(int dtype, int interp, const PassArgs &pa, const
                                 hipStream_t stream);
 hipError_t launch_retrieve_pass(int dtype, int interp, const PassArgs &pa, void *field,
                                 int discard, const RetrieveIn &in, double eb, hipStream_t stream);
+// Outlier index built on the device from the compression kernels' records
+// (any order, count *n_out, at most cap used): gchunk/local/bits sorted by
+// (global chunk, local) and start[c] = first record of chunk c (n_chunks + 1
+// entries).  cnt: n_chunks + 1 words of scratch; bsum: (n_chunks + 1024) / 1024.
+hipError_t launch_outlier_index(const OutlierRec *recs, const unsigned long long *n_out,
+                                uint64_t cap, const PassArgs *args, uint64_t n_chunks,
+                                uint32_t *start, uint32_t *cnt, uint32_t *bsum, uint64_t *gchunk,
+                                uint32_t *local, uint64_t *bits, hipStream_t stream);
 // out_start[c] = index of the first outlier whose global chunk is >= c, for
 // c = 0 .. n_chunks (outliers sorted by global chunk)
 hipError_t launch_out_start(const uint64_t *out_gchunk, uint64_t n_out, uint64_t n_chunks,

@@ -20,6 +20,8 @@
 // evaluation of the same formulas.
 #include "kernels.h"
 
+#include <algorithm>
+
 #include "ipc_internal.h"
 
 namespace ipc {
@@ -400,6 +402,105 @@ __global__ __launch_bounds__(WG) void k_retrieve(PassArgs a, T *f, int discard, 
   }
 }
 
+// ---- device-side outlier index: records (pass, chunk, local, bits) in any
+// order -> arrays sorted by (global chunk, local) and the first record of
+// every chunk.  Counting sort by chunk, then an insertion sort of each
+// chunk's few records by local index.
+
+__device__ __forceinline__ uint64_t rec_chunk(const PassArgs *args, const OutlierRec &r) {
+  return uint64_t(args[r.pass].chunk_base) + r.chunk;
+}
+
+__global__ void k_out_hist(const OutlierRec *recs, const unsigned long long *n_out, uint64_t cap,
+                           const PassArgs *args, uint32_t *cnt) {
+  const uint64_t n = *n_out < cap ? *n_out : cap;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += uint64_t(gridDim.x) * blockDim.x)
+    atomicAdd(&cnt[rec_chunk(args, recs[i])], 1u);
+}
+
+// exclusive scan of v[0 .. n) in blocks of 1024; block totals to bsum
+__global__ __launch_bounds__(1024) void k_scan_block(uint32_t *v, uint64_t n, uint32_t *bsum) {
+  __shared__ uint32_t s[1024];
+  const uint64_t i = uint64_t(blockIdx.x) * 1024 + threadIdx.x;
+  const uint32_t x = i < n ? v[i] : 0u;
+  s[threadIdx.x] = x;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint32_t t = threadIdx.x >= unsigned(o) ? s[threadIdx.x - o] : 0u;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  if (i < n) v[i] = s[threadIdx.x] - x;
+  if (threadIdx.x == 1023) bsum[blockIdx.x] = s[1023];
+}
+
+// exclusive scan of the nb block totals (one workgroup, serial over 1024-blocks)
+__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *bsum, uint64_t nb) {
+  __shared__ uint32_t s[1024];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (uint64_t b0 = 0; b0 < nb; b0 += 1024) {
+    const uint64_t i = b0 + threadIdx.x;
+    const uint32_t x = i < nb ? bsum[i] : 0u;
+    s[threadIdx.x] = x;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const uint32_t t = threadIdx.x >= unsigned(o) ? s[threadIdx.x - o] : 0u;
+      __syncthreads();
+      s[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < nb) bsum[i] = carry + s[threadIdx.x] - x;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += s[1023];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_add(uint32_t *v, uint64_t n, const uint32_t *bsum) {
+  const uint64_t i = uint64_t(blockIdx.x) * 1024 + threadIdx.x;
+  if (i < n) v[i] += bsum[blockIdx.x];
+}
+
+// cnt holds the per-chunk counts; counting down gives every record its slot
+__global__ void k_out_scatter(const OutlierRec *recs, const unsigned long long *n_out, uint64_t cap,
+                              const PassArgs *args, const uint32_t *start, uint32_t *cnt,
+                              uint64_t *gchunk, uint32_t *local, uint64_t *bits) {
+  const uint64_t n = *n_out < cap ? *n_out : cap;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += uint64_t(gridDim.x) * blockDim.x) {
+    const OutlierRec r = recs[i];
+    const uint64_t g = rec_chunk(args, r);
+    const uint32_t pos = start[g] + atomicSub(&cnt[g], 1u) - 1u;
+    gchunk[pos] = g;
+    local[pos] = r.local;
+    bits[pos] = r.bits;
+  }
+}
+
+__global__ void k_out_sort_chunks(const uint32_t *start, uint64_t n_chunks, uint32_t *local,
+                                  uint64_t *bits) {
+  for (uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < n_chunks;
+       g += uint64_t(gridDim.x) * blockDim.x) {
+    const uint32_t a = start[g], b = start[g + 1];
+    for (uint32_t i = a + 1; i < b; ++i) {
+      const uint32_t l = local[i];
+      const uint64_t v = bits[i];
+      uint32_t j = i;
+      while (j > a && local[j - 1] > l) {
+        local[j] = local[j - 1];
+        bits[j] = bits[j - 1];
+        --j;
+      }
+      local[j] = l;
+      bits[j] = v;
+    }
+  }
+}
+
 __global__ void k_out_start(const uint64_t *keys, uint64_t n, uint64_t n_chunks, uint32_t *start) {
   uint64_t c = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c > n_chunks) return;
@@ -556,6 +657,30 @@ hipError_t launch_out_start(const uint64_t *out_gchunk, uint64_t n_out, uint64_t
                             uint32_t *out_start, hipStream_t stream) {
   dim3 grid(uint32_t((n_chunks + 1 + 255) / 256));
   hipLaunchKernelGGL(k_out_start, grid, dim3(256), 0, stream, out_gchunk, n_out, n_chunks, out_start);
+  return hipGetLastError();
+}
+
+hipError_t launch_outlier_index(const OutlierRec *recs, const unsigned long long *n_out,
+                                uint64_t cap, const PassArgs *args, uint64_t n_chunks,
+                                uint32_t *start, uint32_t *cnt, uint32_t *bsum, uint64_t *gchunk,
+                                uint32_t *local, uint64_t *bits, hipStream_t stream) {
+  // start[] doubles as the histogram (n_chunks + 1 entries, the last one 0)
+  hipError_t e = hipMemsetAsync(start, 0, (n_chunks + 1) * 4, stream);
+  if (e != hipSuccess) return e;
+  const uint32_t rg = uint32_t(std::min<uint64_t>((cap + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_out_hist, dim3(rg), dim3(256), 0, stream, recs, n_out, cap, args, start);
+  e = hipMemcpyAsync(cnt, start, (n_chunks + 1) * 4, hipMemcpyDeviceToDevice, stream);
+  if (e != hipSuccess) return e;
+  const uint64_t n = n_chunks + 1, nb = (n + 1023) / 1024;
+  hipLaunchKernelGGL(k_scan_block, dim3(uint32_t(nb)), dim3(1024), 0, stream, start, n, bsum);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, stream, bsum, nb);
+  hipLaunchKernelGGL(k_scan_add, dim3(uint32_t(nb)), dim3(1024), 0, stream, start, n,
+                     (const uint32_t *)bsum);
+  hipLaunchKernelGGL(k_out_scatter, dim3(rg), dim3(256), 0, stream, recs, n_out, cap, args,
+                     (const uint32_t *)start, cnt, gchunk, local, bits);
+  const uint32_t cg = uint32_t(std::min<uint64_t>((n_chunks + 255) / 256, 8192));
+  hipLaunchKernelGGL(k_out_sort_chunks, dim3(cg), dim3(256), 0, stream, (const uint32_t *)start,
+                     n_chunks, local, bits);
   return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ static int itemsize(int dtype) { return dtype == IPC_F32 ? 4 : 8; }
 
 static void section_sizes(const StreamMeta &m, uint64_t sz[6]) {
   uint64_t P = m.sched.passes.size();
-  uint64_t nout = m.outliers.size();
+  uint64_t nout = m.n_outliers;
   sz[0] = HEADER_SIZE;
   sz[1] = pad8(4 * 33 * P);
   sz[2] = pad8(4 * uint64_t(m.sched.n_chunks));
@@ -93,7 +93,7 @@ void write_serialized_head(const StreamMeta &m, uint8_t *dst) {
   h[59] = 0;
   put32(h + 60, uint32_t(s.passes.size()));
   put64(h + 64, uint64_t(s.n_chunks));
-  put64(h + 72, uint64_t(m.outliers.size()));
+  put64(h + 72, m.n_outliers);
   put64(h + 80, m.payload_words);
   putd(h + 88, m.maxabs);
   uint8_t *p = dst + sz[0];
@@ -185,6 +185,7 @@ bool parse_serialized(const uint8_t *buf, uint64_t n, StreamMeta &m, const uint3
     }
   m.payload_words = pw;
   m.outliers.resize(nout);
+  m.n_outliers = nout;
   uint64_t sz[6];
   section_sizes(m, sz);
   if (sz[0] + sz[1] + sz[2] + sz[3] + sz[4] + sz[5] != n) {
