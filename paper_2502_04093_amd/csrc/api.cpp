@@ -22,6 +22,7 @@ using namespace ipc;
 
 struct ipc_ctx {
   int device = 0;
+  int n_cu = 256;                       // compute units of the device
   hipStream_t stream = nullptr;
   hipStream_t owned = nullptr;
   std::string err;
@@ -40,6 +41,8 @@ struct ipc_ctx {
   size_t ws_args_bytes = 0;
   void *ws_cnt = nullptr;               // outlier index scratch: per-chunk counts, block sums
   size_t ws_cnt_bytes = 0;
+  void *ws_rows = nullptr;              // fused-level compression: per-workgroup rows
+  size_t ws_rows_bytes = 0;
   void *host_summary = nullptr;         // pinned copy of the compression summary
   size_t host_summary_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -323,7 +326,7 @@ void fill_info(const ipc_stream *s, const std::vector<int> &plan, double bound, 
 
 // ---------------------------------------------------------------- fused 3-D levels
 
-Level3Args level3_args(const Schedule &s, int l);
+Level3Args level3_args(const Schedule &s, int l, int64_t fill = 1024);
 
 // The fused level kernels cover 3-D fields with the default chunk shape whose
 // level-1 launch fits the grid limits (their tile arithmetic is 32-bit).
@@ -369,7 +372,8 @@ Level3Args anchor3_args(const Schedule &s) {
   return A;
 }
 
-Level3Args level3_args(const Schedule &s, int l) {
+// `fill`: workgroups that make one full round of the device
+Level3Args level3_args(const Schedule &s, int l, int64_t fill) {
   Level3Args A;
   std::memset(&A, 0, sizeof(A));
   const int64_t h = int64_t(1) << (l - 1);
@@ -381,11 +385,12 @@ Level3Args level3_args(const Schedule &s, int l) {
   A.tiles_z = (A.L[0] + 1) / 2;
   A.tiles_y = (A.L[1] + 15) / 16;
   A.tiles_x = (A.L[2] + 63) / 64;
-  // chunk rows per workgroup: long columns amortize the coarse-plane halo,
-  // but small levels need more, shorter columns to fill the device
+  // chunk rows per workgroup: long columns amortize the coarse-plane halo and
+  // the workgroup's set-up, so the longest (up to 16) that still fills the
+  // device; small levels get single-step columns
   const int64_t nxy = int64_t(A.tiles_y) * A.tiles_x;
   A.zseg = 16;
-  while (A.zseg > 2 && nxy * ((A.tiles_z + A.zseg - 1) / A.zseg) < 2048) A.zseg -= 2;
+  while (A.zseg > 1 && nxy * ((A.tiles_z + A.zseg - 1) / A.zseg) < fill) A.zseg >>= 1;
   for (int p = 0; p < 3; ++p) {
     const PassGeom &g = s.passes[size_t(1 + (s.K - l) * 3 + p)];
     for (int j = 0; j < 3; ++j) {
@@ -398,6 +403,20 @@ Level3Args level3_args(const Schedule &s, int l) {
     A.pass_index[p] = uint32_t(g.index);
   }
   return A;
+}
+
+// resident workgroups per compute unit assumed when sizing the fused level
+// launches (occupancy of the compression and retrieval kernels)
+#ifndef IPC_WG_PER_CU_C
+#define IPC_WG_PER_CU_C 4
+#endif
+#ifndef IPC_WG_PER_CU_R
+#define IPC_WG_PER_CU_R 4
+#endif
+
+// workgroups of a fused level launch (its 1-D grid)
+int64_t level3_wgs(const Level3Args &A) {
+  return int64_t(A.tiles_x) * A.tiles_y * ((A.tiles_z + A.zseg - 1) / A.zseg);
 }
 
 // compact coarse-grid buffers: G_j lives in ws_g[j & 1]
@@ -444,7 +463,7 @@ void run_retrieve(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &pla
                 "gather kernel launch");
     }
     for (int l = l_start; l >= 1; --l) {
-      Level3Args La = level3_args(sc, l);
+      Level3Args La = level3_args(sc, l, IPC_WG_PER_CU_R * int64_t(ctx->n_cu));
       int disc[3];
       for (int p = 0; p < 3; ++p) disc[p] = plan[La.pass_index[p]];
       int pc = int(La.pass_index[2]);
@@ -527,6 +546,10 @@ ipc_status ipc_ctx_create(int device, void *hip_stream, ipc_ctx **out) {
     delete c;
     return IPC_EHIP;
   }
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+    c->n_cu = ncu;
+  (void)hipGetLastError();
   if (hip_stream) {
     c->stream = static_cast<hipStream_t>(hip_stream);
   } else {
@@ -567,6 +590,7 @@ void ipc_ctx_destroy(ipc_ctx *ctx) {
   if (ctx->ws_summary) (void)hipFree(ctx->ws_summary);
   if (ctx->ws_out) (void)hipFree(ctx->ws_out);
   if (ctx->ws_cnt) (void)hipFree(ctx->ws_cnt);
+  if (ctx->ws_rows) (void)hipFree(ctx->ws_rows);
   for (int i = 0; i < 2; ++i)
     if (ctx->ws_g[i]) (void)hipFree(ctx->ws_g[i]);
   if (ctx->ws_args) (void)hipFree(ctx->ws_args);
@@ -659,18 +683,40 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
       o.errq = reinterpret_cast<uint32_t *>(summary + 16 + size_t(P) * 32 * 8);
       o.out_recs = ctx->ws_out;
       o.out_cap = cap_recs;
+      o.wg_rows = nullptr;
       hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
       prof_begin(ctx, size_t(P));
       if (fused) {
         const int K = sc.K;
+        // level launches and their workgroup rows
+        std::vector<Level3Args> las;
+        LevelRows lr;
+        std::memset(&lr, 0, sizeof(lr));
+        uint32_t rows = 0;
+        for (int l = K; l >= 1; --l) {
+          Level3Args La = level3_args(sc, l, IPC_WG_PER_CU_C * int64_t(ctx->n_cu));
+          La.row_base = rows;
+          if (lr.n >= MAX_LEVEL_LAUNCHES) {
+            set_err(ctx, "too many levels for the fused kernels");
+            throw Fail{IPC_EUNSUPPORTED};
+          }
+          lr.row_base[lr.n] = rows;
+          lr.n_rows[lr.n] = uint32_t(level3_wgs(La));
+          for (int p = 0; p < 3; ++p) lr.pass_index[lr.n][p] = La.pass_index[p];
+          rows += lr.n_rows[lr.n];
+          ++lr.n;
+          las.push_back(La);
+        }
+        o.wg_rows = static_cast<uint32_t *>(
+            ensure_ws(ctx, ctx->ws_rows, ctx->ws_rows_bytes, size_t(rows) * WG_ROW * 4));
         Level3Args A = anchor3_args(sc);
         prof_mark(ctx, 0, true);
         hip_check(ctx, launch_anchor3_compress(dtype, A, field_dev, ctx->ws_g[K & 1], abs_eb, o,
                                                ctx->stream),
                   "anchor kernel launch");
         prof_mark(ctx, 0, false);
-        for (int l = K; l >= 1; --l) {
-          Level3Args La = level3_args(sc, l);
+        for (const Level3Args &La : las) {
+          const int l = int(sc.passes[La.pass_index[2]].level);
           int pc = int(La.pass_index[2]);
           prof_mark(ctx, pc, true);
           hip_check(ctx, launch_level3_compress(dtype, interp, La, field_dev, ctx->ws_g[l & 1],
@@ -679,6 +725,8 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
                     "level kernel launch");
           prof_mark(ctx, pc, false);
         }
+        hip_check(ctx, launch_rows_reduce(lr, o.wg_rows, o.errq, o.maxabs_bits, ctx->stream),
+                  "row reduction launch");
       } else {
         for (int i = 0; i < P; ++i) {
           int wb = i + 1 < P ? 1 : 0;  // the last pass is read by nobody
@@ -692,29 +740,6 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
       hip_check(ctx, launch_all_sizes(static_cast<const PassArgs *>(ctx->ws_args), P, max_chunks,
                                       o.masks, sizes, ctx->stream),
                 "sizes kernel launch");
-      // the outlier index, sorted on the device (records stay there until a
-      // serialization asks for them)
-      {
-        const uint64_t nc = uint64_t(sc.n_chunks);
-        dev_free(ctx, s->out_gchunk);
-        dev_free(ctx, s->out_local);
-        dev_free(ctx, s->out_bits);
-        dev_free(ctx, s->out_start);
-        s->out_gchunk = dev_alloc(ctx, 8 * cap_recs);
-        s->out_local = dev_alloc(ctx, 4 * cap_recs);
-        s->out_bits = dev_alloc(ctx, 8 * cap_recs);
-        s->out_start = dev_alloc(ctx, 4 * (nc + 1));
-        const size_t nb = (nc + 1 + 1023) / 1024;
-        uint32_t *cnt = static_cast<uint32_t *>(
-            ensure_ws(ctx, ctx->ws_cnt, ctx->ws_cnt_bytes, 4 * (nc + 1) + 4 * (nb + 1)));
-        hip_check(ctx, launch_outlier_index(static_cast<const OutlierRec *>(o.out_recs), o.n_out,
-                                            cap_recs, static_cast<const PassArgs *>(ctx->ws_args),
-                                            nc, static_cast<uint32_t *>(s->out_start.p), cnt,
-                                            cnt + (nc + 1), static_cast<uint64_t *>(s->out_gchunk.p),
-                                            static_cast<uint32_t *>(s->out_local.p),
-                                            static_cast<uint64_t *>(s->out_bits.p), ctx->stream),
-                  "outlier index launch");
-      }
       hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
       if (ctx->host_summary_bytes < sum_bytes) {
         if (ctx->host_summary) (void)hipHostFree(ctx->host_summary);
@@ -745,6 +770,26 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
       m.outliers.clear();
       m.n_outliers = nout;
       s->host_outliers_valid = nout == 0;
+      // the outlier index, sorted on the device (records stay there until a
+      // serialization asks for them); stream-ordered before any later use
+      if (nout > 0) {
+        const uint64_t nc = uint64_t(sc.n_chunks);
+        s->out_gchunk = dev_alloc(ctx, 8 * nout);
+        s->out_local = dev_alloc(ctx, 4 * nout);
+        s->out_bits = dev_alloc(ctx, 8 * nout);
+        s->out_start = dev_alloc(ctx, 4 * (nc + 1));
+        const size_t nb = (nc + 1 + 1023) / 1024;
+        uint32_t *cnt = static_cast<uint32_t *>(
+            ensure_ws(ctx, ctx->ws_cnt, ctx->ws_cnt_bytes, 4 * (nc + 1) + 4 * (nb + 1)));
+        hip_check(ctx, launch_outlier_index(static_cast<const OutlierRec *>(ctx->ws_out),
+                                            reinterpret_cast<const unsigned long long *>(summary),
+                                            nout, static_cast<const PassArgs *>(ctx->ws_args), nc,
+                                            static_cast<uint32_t *>(s->out_start.p), cnt,
+                                            cnt + (nc + 1), static_cast<uint64_t *>(s->out_gchunk.p),
+                                            static_cast<uint32_t *>(s->out_local.p),
+                                            static_cast<uint64_t *>(s->out_bits.p), ctx->stream),
+                  "outlier index launch");
+      }
       uint64_t words = 0;
       for (uint64_t v : sz) words += v / 4;
       m.payload_words = words;

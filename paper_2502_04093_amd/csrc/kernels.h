@@ -35,7 +35,26 @@ struct CompressOut {
   unsigned long long *n_out;        // outlier counter
   void *out_recs;        // OutlierRec array
   unsigned long long out_cap;
+  uint32_t *wg_rows;     // fused levels: one row of WG_ROW words per workgroup (see below)
 };
+
+// Row of a fused-level compression workgroup: its delta-y maxima errq[p][b]
+// (3 passes x 33, b = 0 unused) and its largest finite |x^| as double bits
+// (words 99, 100: low, high).  Rows are reduced after the level launches, so
+// no two workgroups update one word.
+constexpr int WG_ROW = 104;
+
+// the fused level launches of one compression, for the row reduction
+constexpr int MAX_LEVEL_LAUNCHES = 32;
+struct LevelRows {
+  int32_t n;                                  // launches
+  uint32_t row_base[MAX_LEVEL_LAUNCHES];      // first row of each launch
+  uint32_t n_rows[MAX_LEVEL_LAUNCHES];        // its workgroups
+  uint32_t pass_index[MAX_LEVEL_LAUNCHES][3]; // its passes A, B, C
+};
+// errq[pass][b] and maxabs_bits <- max over the rows of every launch
+hipError_t launch_rows_reduce(const LevelRows &lr, const uint32_t *rows, uint32_t *errq,
+                              unsigned long long *maxabs_bits, hipStream_t stream);
 
 struct RetrieveIn {
   const uint32_t *payload;
@@ -63,6 +82,7 @@ struct Level3Args {
   uint64_t slot_base[3];
   uint32_t wmax[3];
   uint32_t pass_index[3];
+  uint32_t row_base;     // compression: row of the launch's first workgroup in wg_rows
 };
 
 hipError_t launch_level3_compress(int dtype, int interp, const Level3Args &L, const void *x,

@@ -553,16 +553,18 @@ __global__ __launch_bounds__(WG) void k_pack(PassArgs a, const uint32_t *masks,
 }
 
 // sizes[p][k] += 4 * sum over chunks c of pass p with bit k of mask_c of W_c;
-// grid (passes, splits), each workgroup covers up to 16 chunks per thread.
+// grid (passes, splits), one chunk per thread (the mask loads all in flight).
+constexpr int SIZES_CPT = 1;
 __global__ __launch_bounds__(WG) void k_all_sizes(const PassArgs *args, const uint32_t *masks,
                                                    unsigned long long *sizes) {
   __shared__ unsigned long long s_acc[32];
   const PassArgs a = args[blockIdx.x];
   const int tid = threadIdx.x;
+  const int64_t c0 = int64_t(blockIdx.y) * (SIZES_CPT * WG);
+  if (c0 >= a.n_chunks) return;  // uniform: before any barrier
   if (tid < 32) s_acc[tid] = 0;
   __syncthreads();
-  const int64_t c0 = int64_t(blockIdx.y) * (16 * WG);
-  int64_t c1 = c0 + 16 * WG;
+  int64_t c1 = c0 + SIZES_CPT * WG;
   if (c1 > a.n_chunks) c1 = a.n_chunks;
   uint32_t acc[32];
 #pragma unroll
@@ -631,7 +633,7 @@ hipError_t launch_retrieve_pass(int dtype, int interp, const PassArgs &pa, void 
 
 hipError_t launch_all_sizes(const PassArgs *args_dev, int n_passes, int64_t max_chunks,
                             const uint32_t *masks, unsigned long long *sizes, hipStream_t stream) {
-  uint32_t splits = uint32_t((max_chunks + 16 * WG - 1) / (16 * WG));
+  uint32_t splits = uint32_t((max_chunks + SIZES_CPT * WG - 1) / (SIZES_CPT * WG));
   if (splits == 0) splits = 1;
   hipLaunchKernelGGL(k_all_sizes, dim3(uint32_t(n_passes), splits), dim3(WG), 0, stream, args_dev,
                      masks, sizes);

@@ -314,6 +314,7 @@ struct SharedC {
   uint32_t bm[3][RW];       // residues w mod 2^13 present among each pass's codes
   uint32_t eq[3][33];       // per workgroup delta-y of each pass
   uint32_t qa[3];           // largest |q| among 14-digit codes, per pass
+  unsigned long long mxab;  // bits of the workgroup's largest finite |x^| (as a double)
 };
 
 // code buffers of one step (retrieval): pass A, B, C
@@ -333,28 +334,31 @@ __device__ __forceinline__ void block_tile(const Level3Args &L, int &tx, int &ty
   zs = r / L.tiles_y;
 }
 
-// ring slot cz & 3 <- coarse plane cz (11 even rows x 35 even columns)
+// ring slots of the coarse planes m0 - 1 .. m0 + 1 (11 even rows x 35 even
+// columns each; entry li[i] of a slot from offset ro[i] of its plane), every
+// load issued before the first store.  Entries outside the coarse grid read
+// the plane's first element and are never selected by a stencil.
 template <typename T, typename SH>
-__device__ __forceinline__ void load_ring_plane(const Level3Args &L, const T *gin, SH &S, int cz,
-                                                int y0, int x0) {
-  if (cz < 0 || cz >= L.G[0]) return;
-  T(*dst)[NXP] = S.ring[cz & 3];
-  const int64_t pb = int64_t(cz) * L.G[1];
-  T v[2];
-  bool ok[2];
-  int yj[2], xi[2];
+__device__ __forceinline__ void load_ring(const Level3Args &L, const T *gin, SH &S, int m0,
+                                          const int li[2], const uint32_t ro[2]) {
+  const int64_t ps = int64_t(L.G[1]) * L.G[2];
+  T v[3][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    int t = threadIdx.x + i * WG3;
-    yj[i] = t / NXE;
-    xi[i] = t - yj[i] * NXE;
-    int cy = (y0 >> 1) - 1 + yj[i], cx = (x0 >> 1) - 1 + xi[i];
-    ok[i] = t < NYE * NXE && unsigned(cy) < unsigned(L.G[1]) && unsigned(cx) < unsigned(L.G[2]);
-    v[i] = gin[ok[i] ? (pb + cy) * L.G[2] + cx : 0];
+  for (int j = 0; j < 3; ++j) {
+    const int cz = m0 - 1 + j;
+    const T *gp = gin + (cz >= 0 && cz < L.G[0] ? int64_t(cz) * ps : 0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) v[j][i] = gp[ro[i]];
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-    if (threadIdx.x + i * WG3 < NYE * NXE) dst[yj[i]][xi[i]] = ok[i] ? v[i] : T(0);
+  for (int j = 0; j < 3; ++j) {
+    const int cz = m0 - 1 + j;
+    if (cz < 0 || cz >= L.G[0]) continue;
+    T *dst = &S.ring[cz & 3][0][0];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      if (li[i] >= 0) dst[li[i]] = v[j][i];
+  }
 }
 
 // even-column values of plane zz at tile row yy (0 .. 15), index i + 1 for the
@@ -561,6 +565,7 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
   for (int i = tid0; i < 3 * RW; i += WG3) (&S.bm[0][0])[i] = 0u;
   if (tid0 < 3 * 33) (&S.eq[0][0])[tid0] = 0u;
   if (tid0 < 3) S.qa[tid0] = 0u;
+  if (tid0 == 0) S.mxab = 0ull;
 
   uint32_t qaA = 0, qaB = 0, qaC = 0;
   U mxb = 0;
@@ -664,9 +669,7 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
     }
   };
 
-  load_ring_plane(L, gin, S, m0 - 1, y0, x0);
-  load_ring_plane(L, gin, S, m0, y0, x0);
-  load_ring_plane(L, gin, S, m0 + 1, y0, x0);
+  load_ring(L, gin, S, m0, li, ro);
   issue(m0);
 
   for (int m = m0; m < m1; ++m) {
@@ -841,7 +844,8 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
       }
     }
   }
-  // ---- workgroup totals: per-pass |q| of 14-digit codes, max |x^|
+  // ---- workgroup totals: per-pass |q| of 14-digit codes, max |x^|, then
+  // the workgroup's row (reduced over the launch's workgroups afterwards)
   {
     const int lane = tid0 & 63, wave = tid0 >> 6;
     uint32_t qs[3] = {qaA, qaB, qaC};
@@ -856,20 +860,21 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
       const U u = __shfl_xor(v, o2, 64);
       v = u > v ? u : v;
     }
-    if (lane == 0 && v) {
-      const unsigned long long db = (unsigned long long)__double_as_longlong(BT::to_double(v));
-      if (db > *o.maxabs_bits) atomicMax(o.maxabs_bits, db);
-    }
+    if (lane == 0 && v)
+      atomicMax(&S.mxab, (unsigned long long)__double_as_longlong(BT::to_double(v)));
     __syncthreads();
     if (wave < 3) errq_fold(S.bm[wave], S.eq[wave], lane);
     __syncthreads();
   }
+  uint32_t *row = o.wg_rows + size_t(L.row_base + blockIdx.x) * WG_ROW;
   if (tid0 < 3 * 33) {
     const int p = tid0 / 33, b = tid0 - p * 33;
-    uint32_t val = S.eq[p][b];
+    uint32_t val = b > 0 ? S.eq[p][b] : 0u;
     if (b >= 14) val = S.qa[p] > val ? S.qa[p] : val;
-    uint32_t *dst = o.errq + size_t(LSEL(pass_index, p)) * 33 + b;
-    if (b > 0 && val > *dst) atomicMax(dst, val);
+    row[tid0] = val;
+  } else if (tid0 < 3 * 33 + 2) {
+    const unsigned long long mx = S.mxab;
+    row[tid0] = tid0 == 3 * 33 ? uint32_t(mx) : uint32_t(mx >> 32);
   }
 }
 
@@ -1053,9 +1058,7 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
     }
   };
 
-  load_ring_plane(L, gin, S, m0 - 1, y0, x0);
-  load_ring_plane(L, gin, S, m0, y0, x0);
-  load_ring_plane(L, gin, S, m0 + 1, y0, x0);
+  load_ring(L, gin, S, m0, li, ro);
   issue_ring(m0 + 2);
   prefetch_word(role_of(tid0), m0);
 
@@ -1372,7 +1375,58 @@ __global__ void k_gather_coarse(const T *__restrict__ field, int64_t fd1, int64_
   g[i] = field[((s * c0) * fd1 + s * c1) * fd2 + s * c2];
 }
 
+// errq and max |x^| of a compression from the fused-level rows: grid
+// (launch, pass, split), each workgroup reduces up to RR_ROWS rows of one
+// launch for one pass (thread t: b = t % 33 over rows t / 33, + 7, ...), then
+// one atomic per value.
+constexpr int RR_ROWS = 512;
+__global__ __launch_bounds__(256) void k_rows_reduce(LevelRows lr, const uint32_t *rows, uint32_t *errq,
+                                                     unsigned long long *maxabs_bits) {
+  __shared__ uint32_t s_max[33];
+  __shared__ unsigned long long s_mx;
+  const int li = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
+  const uint32_t r0 = blockIdx.z * RR_ROWS;
+  const uint32_t n = lr.n_rows[li];
+  if (r0 >= n) return;  // uniform: before any barrier
+  const uint32_t r1 = n - r0 < uint32_t(RR_ROWS) ? n : r0 + RR_ROWS;
+  if (tid < 33) s_max[tid] = 0u;
+  if (tid == 0) s_mx = 0ull;
+  __syncthreads();
+  const uint32_t *base = rows + size_t(lr.row_base[li]) * WG_ROW;
+  if (tid < 7 * 33) {
+    const int b = tid % 33;
+    uint32_t m = 0;
+    for (uint32_t r = r0 + tid / 33; r < r1; r += 7) {
+      const uint32_t v = base[size_t(r) * WG_ROW + p * 33 + b];
+      m = v > m ? v : m;
+    }
+    if (m) atomicMax(&s_max[b], m);
+  }
+  if (p == 0) {
+    unsigned long long m = 0;
+    for (uint32_t r = r0 + tid; r < r1; r += 256) {
+      const uint32_t *w = base + size_t(r) * WG_ROW + 99;
+      const unsigned long long v = (unsigned long long)w[0] | ((unsigned long long)w[1] << 32);
+      m = v > m ? v : m;
+    }
+    if (m) atomicMax(&s_mx, m);
+  }
+  __syncthreads();
+  if (tid > 0 && tid < 33 && s_max[tid]) atomicMax(errq + size_t(lr.pass_index[li][p]) * 33 + tid, s_max[tid]);
+  if (p == 0 && tid == 0 && s_mx) atomicMax(maxabs_bits, s_mx);
+}
+
 }  // namespace
+
+hipError_t launch_rows_reduce(const LevelRows &lr, const uint32_t *rows, uint32_t *errq,
+                              unsigned long long *maxabs_bits, hipStream_t stream) {
+  uint32_t most = 0;
+  for (int i = 0; i < lr.n; ++i) most = lr.n_rows[i] > most ? lr.n_rows[i] : most;
+  if (lr.n == 0 || most == 0) return hipSuccess;
+  dim3 grid(uint32_t(lr.n), 3, (most + RR_ROWS - 1) / RR_ROWS);
+  hipLaunchKernelGGL(k_rows_reduce, grid, dim3(256), 0, stream, lr, rows, errq, maxabs_bits);
+  return hipGetLastError();
+}
 
 hipError_t launch_level3_compress(int dtype, int interp, const Level3Args &L, const void *x,
                                   const void *gin, void *gout, double eb, const CompressOut &o,
