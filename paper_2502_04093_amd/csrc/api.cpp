@@ -39,6 +39,8 @@ struct ipc_ctx {
   size_t ws_g_bytes[2] = {0, 0};
   void *ws_args = nullptr;              // PassArgs of the current call
   size_t ws_args_bytes = 0;
+  std::vector<PassArgs> args_host;      // what ws_args holds ...
+  void *args_dev_at = nullptr;          // ... while it is this allocation
   void *ws_cnt = nullptr;               // outlier index scratch: per-chunk counts, block sums
   size_t ws_cnt_bytes = 0;
   void *ws_rows = nullptr;              // fused-level compression: per-workgroup rows
@@ -200,6 +202,7 @@ void prof_end(ipc_ctx *ctx) {
 
 PassArgs make_args(const Schedule &s, const PassGeom &p) {
   PassArgs a;
+  std::memset(&a, 0, sizeof(a));
   for (int j = 0; j < 3; ++j) {
     a.dims3[j] = s.dims3[j];
     a.ldims[j] = p.ldims[j];
@@ -661,9 +664,20 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
       ensure_coarse(ctx, sc, isz);
     else
       xh = ensure_ws(ctx, ctx->ws_xh, ctx->ws_xh_bytes, nbytes);
-    ensure_ws(ctx, ctx->ws_args, ctx->ws_args_bytes, s->args.size() * sizeof(PassArgs));
-    hip_check(ctx, hipMemcpyAsync(ctx->ws_args, s->args.data(), s->args.size() * sizeof(PassArgs),
-                                  hipMemcpyHostToDevice, ctx->stream), "upload");
+    {
+      const size_t had = ctx->ws_args_bytes;
+      ensure_ws(ctx, ctx->ws_args, ctx->ws_args_bytes, s->args.size() * sizeof(PassArgs));
+      if (ctx->ws_args_bytes != had) ctx->args_host.clear();  // a fresh allocation
+    }
+    // the pass table on the device: uploaded when it differs from the last one
+    const size_t args_bytes = s->args.size() * sizeof(PassArgs);
+    if (ctx->ws_args != ctx->args_dev_at || ctx->args_host.size() != s->args.size() ||
+        std::memcmp(ctx->args_host.data(), s->args.data(), args_bytes) != 0) {
+      hip_check(ctx, hipMemcpyAsync(ctx->ws_args, s->args.data(), args_bytes, hipMemcpyHostToDevice,
+                                    ctx->stream), "upload");
+      ctx->args_host = s->args;
+      ctx->args_dev_at = ctx->ws_args;
+    }
     int64_t max_chunks = 0;
     for (const PassGeom &g : sc.passes) max_chunks = std::max(max_chunks, g.n_chunks);
     // summary: n_out, maxabs bits, sizes [P][32] u64, errq [P][33] u32
@@ -674,16 +688,17 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
       ensure_ws(ctx, ctx->ws_out, ctx->ws_out_cap, cap * sizeof(OutlierRec));
       size_t cap_recs = ctx->ws_out_cap / sizeof(OutlierRec);
       hip_check(ctx, hipMemsetAsync(summary, 0, sum_bytes, ctx->stream), "memset");
+      unsigned long long *sizes = reinterpret_cast<unsigned long long *>(summary + 16);
       CompressOut o;
       o.payload = static_cast<uint32_t *>(s->payload.p);
       o.masks = static_cast<uint32_t *>(s->masks.p);
       o.n_out = reinterpret_cast<unsigned long long *>(summary);
       o.maxabs_bits = reinterpret_cast<unsigned long long *>(summary + 8);
-      unsigned long long *sizes = reinterpret_cast<unsigned long long *>(summary + 16);
       o.errq = reinterpret_cast<uint32_t *>(summary + 16 + size_t(P) * 32 * 8);
       o.out_recs = ctx->ws_out;
       o.out_cap = cap_recs;
       o.wg_rows = nullptr;
+      o.sizes = sizes;
       hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
       prof_begin(ctx, size_t(P));
       if (fused) {
@@ -725,7 +740,7 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
                     "level kernel launch");
           prof_mark(ctx, pc, false);
         }
-        hip_check(ctx, launch_rows_reduce(lr, o.wg_rows, o.errq, o.maxabs_bits, ctx->stream),
+        hip_check(ctx, launch_rows_reduce(lr, o.wg_rows, o.errq, o.maxabs_bits, sizes, ctx->stream),
                   "row reduction launch");
       } else {
         for (int i = 0; i < P; ++i) {
@@ -737,9 +752,33 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
           prof_mark(ctx, i, false);
         }
       }
-      hip_check(ctx, launch_all_sizes(static_cast<const PassArgs *>(ctx->ws_args), P, max_chunks,
-                                      o.masks, sizes, ctx->stream),
-                "sizes kernel launch");
+      if (!fused)
+        hip_check(ctx, launch_all_sizes(static_cast<const PassArgs *>(ctx->ws_args), P, max_chunks,
+                                        o.masks, sizes, ctx->stream),
+                  "sizes kernel launch");
+      // the outlier index, sorted on the device (records stay there until a
+      // serialization asks for them), enqueued behind the level launches
+      {
+        const uint64_t nc = uint64_t(sc.n_chunks);
+        dev_free(ctx, s->out_gchunk);
+        dev_free(ctx, s->out_local);
+        dev_free(ctx, s->out_bits);
+        dev_free(ctx, s->out_start);
+        s->out_gchunk = dev_alloc(ctx, 8 * cap_recs);
+        s->out_local = dev_alloc(ctx, 4 * cap_recs);
+        s->out_bits = dev_alloc(ctx, 8 * cap_recs);
+        s->out_start = dev_alloc(ctx, 4 * (nc + 1));
+        const size_t nb = (nc + 1 + 1023) / 1024;
+        uint32_t *cnt = static_cast<uint32_t *>(
+            ensure_ws(ctx, ctx->ws_cnt, ctx->ws_cnt_bytes, 4 * (nc + 1) + 4 * (nb + 1)));
+        hip_check(ctx, launch_outlier_index(static_cast<const OutlierRec *>(o.out_recs), o.n_out,
+                                            cap_recs, static_cast<const PassArgs *>(ctx->ws_args),
+                                            nc, static_cast<uint32_t *>(s->out_start.p), cnt,
+                                            cnt + (nc + 1), static_cast<uint64_t *>(s->out_gchunk.p),
+                                            static_cast<uint32_t *>(s->out_local.p),
+                                            static_cast<uint64_t *>(s->out_bits.p), ctx->stream),
+                  "outlier index launch");
+      }
       hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
       if (ctx->host_summary_bytes < sum_bytes) {
         if (ctx->host_summary) (void)hipHostFree(ctx->host_summary);
@@ -770,26 +809,6 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
       m.outliers.clear();
       m.n_outliers = nout;
       s->host_outliers_valid = nout == 0;
-      // the outlier index, sorted on the device (records stay there until a
-      // serialization asks for them); stream-ordered before any later use
-      if (nout > 0) {
-        const uint64_t nc = uint64_t(sc.n_chunks);
-        s->out_gchunk = dev_alloc(ctx, 8 * nout);
-        s->out_local = dev_alloc(ctx, 4 * nout);
-        s->out_bits = dev_alloc(ctx, 8 * nout);
-        s->out_start = dev_alloc(ctx, 4 * (nc + 1));
-        const size_t nb = (nc + 1 + 1023) / 1024;
-        uint32_t *cnt = static_cast<uint32_t *>(
-            ensure_ws(ctx, ctx->ws_cnt, ctx->ws_cnt_bytes, 4 * (nc + 1) + 4 * (nb + 1)));
-        hip_check(ctx, launch_outlier_index(static_cast<const OutlierRec *>(ctx->ws_out),
-                                            reinterpret_cast<const unsigned long long *>(summary),
-                                            nout, static_cast<const PassArgs *>(ctx->ws_args), nc,
-                                            static_cast<uint32_t *>(s->out_start.p), cnt,
-                                            cnt + (nc + 1), static_cast<uint64_t *>(s->out_gchunk.p),
-                                            static_cast<uint32_t *>(s->out_local.p),
-                                            static_cast<uint64_t *>(s->out_bits.p), ctx->stream),
-                  "outlier index launch");
-      }
       uint64_t words = 0;
       for (uint64_t v : sz) words += v / 4;
       m.payload_words = words;

@@ -36,13 +36,16 @@ struct CompressOut {
   void *out_recs;        // OutlierRec array
   unsigned long long out_cap;
   uint32_t *wg_rows;     // fused levels: one row of WG_ROW words per workgroup (see below)
+  unsigned long long *sizes;  // [P][32] stored bytes per plane (fused path: anchors and rows)
 };
 
-// Row of a fused-level compression workgroup: its delta-y maxima errq[p][b]
-// (3 passes x 33, b = 0 unused) and its largest finite |x^| as double bits
-// (words 99, 100: low, high).  Rows are reduced after the level launches, so
-// no two workgroups update one word.
-constexpr int WG_ROW = 104;
+// Row of a fused-level compression workgroup, reduced after the level
+// launches so that no two workgroups update one word:
+//   words 0 .. 98:   delta-y maxima errq[p][b] (3 passes x 33, b = 0 unused)
+//   words 99, 100:   its largest finite |x^| as double bits (low, high)
+//   words 104 .. :   payload words stored per plane, [p][k] (3 x 32)
+constexpr int ROW_SIZES = 104;
+constexpr int WG_ROW = ROW_SIZES + 96;
 
 // the fused level launches of one compression, for the row reduction
 constexpr int MAX_LEVEL_LAUNCHES = 32;
@@ -52,9 +55,11 @@ struct LevelRows {
   uint32_t n_rows[MAX_LEVEL_LAUNCHES];        // its workgroups
   uint32_t pass_index[MAX_LEVEL_LAUNCHES][3]; // its passes A, B, C
 };
-// errq[pass][b] and maxabs_bits <- max over the rows of every launch
+// errq[pass][b] and maxabs_bits <- max over the rows of every launch;
+// sizes[pass][k] += 4 x the rows' plane words
 hipError_t launch_rows_reduce(const LevelRows &lr, const uint32_t *rows, uint32_t *errq,
-                              unsigned long long *maxabs_bits, hipStream_t stream);
+                              unsigned long long *maxabs_bits, unsigned long long *sizes,
+                              hipStream_t stream);
 
 struct RetrieveIn {
   const uint32_t *payload;

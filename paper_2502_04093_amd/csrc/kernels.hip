@@ -419,11 +419,14 @@ __global__ void k_out_hist(const OutlierRec *recs, const unsigned long long *n_o
     atomicAdd(&cnt[rec_chunk(args, recs[i])], 1u);
 }
 
-// exclusive scan of v[0 .. n) in blocks of 1024; block totals to bsum
-__global__ __launch_bounds__(1024) void k_scan_block(uint32_t *v, uint64_t n, uint32_t *bsum) {
+// exclusive scan of v[0 .. n) in blocks of 1024 (the counts also copied to
+// cnt); block totals to bsum
+__global__ __launch_bounds__(1024) void k_scan_block(uint32_t *v, uint64_t n, uint32_t *cnt,
+                                                     uint32_t *bsum) {
   __shared__ uint32_t s[1024];
   const uint64_t i = uint64_t(blockIdx.x) * 1024 + threadIdx.x;
   const uint32_t x = i < n ? v[i] : 0u;
+  if (i < n) cnt[i] = x;
   s[threadIdx.x] = x;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
@@ -436,33 +439,20 @@ __global__ __launch_bounds__(1024) void k_scan_block(uint32_t *v, uint64_t n, ui
   if (threadIdx.x == 1023) bsum[blockIdx.x] = s[1023];
 }
 
-// exclusive scan of the nb block totals (one workgroup, serial over 1024-blocks)
-__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *bsum, uint64_t nb) {
+// adds to block b the sum of the totals of blocks 0 .. b-1 (each workgroup
+// sums them itself)
+__global__ __launch_bounds__(1024) void k_scan_add(uint32_t *v, uint64_t n, const uint32_t *bsum) {
   __shared__ uint32_t s[1024];
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
+  uint32_t t = 0;
+  for (uint32_t j = threadIdx.x; j < blockIdx.x; j += 1024) t += bsum[j];
+  s[threadIdx.x] = t;
   __syncthreads();
-  for (uint64_t b0 = 0; b0 < nb; b0 += 1024) {
-    const uint64_t i = b0 + threadIdx.x;
-    const uint32_t x = i < nb ? bsum[i] : 0u;
-    s[threadIdx.x] = x;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const uint32_t t = threadIdx.x >= unsigned(o) ? s[threadIdx.x - o] : 0u;
-      __syncthreads();
-      s[threadIdx.x] += t;
-      __syncthreads();
-    }
-    if (i < nb) bsum[i] = carry + s[threadIdx.x] - x;
-    __syncthreads();
-    if (threadIdx.x == 1023) carry += s[1023];
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < unsigned(o)) s[threadIdx.x] += s[threadIdx.x + o];
     __syncthreads();
   }
-}
-
-__global__ __launch_bounds__(1024) void k_scan_add(uint32_t *v, uint64_t n, const uint32_t *bsum) {
   const uint64_t i = uint64_t(blockIdx.x) * 1024 + threadIdx.x;
-  if (i < n) v[i] += bsum[blockIdx.x];
+  if (i < n) v[i] += s[0];
 }
 
 // cnt holds the per-chunk counts; counting down gives every record its slot
@@ -671,11 +661,8 @@ hipError_t launch_outlier_index(const OutlierRec *recs, const unsigned long long
   if (e != hipSuccess) return e;
   const uint32_t rg = uint32_t(std::min<uint64_t>((cap + 255) / 256, 4096));
   hipLaunchKernelGGL(k_out_hist, dim3(rg), dim3(256), 0, stream, recs, n_out, cap, args, start);
-  e = hipMemcpyAsync(cnt, start, (n_chunks + 1) * 4, hipMemcpyDeviceToDevice, stream);
-  if (e != hipSuccess) return e;
   const uint64_t n = n_chunks + 1, nb = (n + 1023) / 1024;
-  hipLaunchKernelGGL(k_scan_block, dim3(uint32_t(nb)), dim3(1024), 0, stream, start, n, bsum);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, stream, bsum, nb);
+  hipLaunchKernelGGL(k_scan_block, dim3(uint32_t(nb)), dim3(1024), 0, stream, start, n, cnt, bsum);
   hipLaunchKernelGGL(k_scan_add, dim3(uint32_t(nb)), dim3(1024), 0, stream, start, n,
                      (const uint32_t *)bsum);
   hipLaunchKernelGGL(k_out_scatter, dim3(rg), dim3(256), 0, stream, recs, n_out, cap, args,

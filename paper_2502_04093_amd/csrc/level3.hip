@@ -569,6 +569,10 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
 
   uint32_t qaA = 0, qaB = 0, qaC = 0;
   U mxb = 0;
+  // payload words stored per plane, accumulated by the encoding wave: lane j
+  // holds plane j & 31 of pass C (j < 32) or B (j >= 32) in szCB, of pass A
+  // (j < 32) in szA
+  uint32_t szCB = 0, szA = 0;
 
   auto record = [&](int p, int m, int local, T xv) {
     unsigned long long slot = atomicAdd(o.n_out, 1ull);
@@ -836,6 +840,13 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
       if (lane < 56 && rw == 0) o.masks[LSEL(chunk_base, rp) + cid] = rowor;
       // delta-y for b >= 14 of chunks holding codes longer than 14 digits
       const uint32_t mk[3] = {__shfl(rowor, 48, 64), __shfl(rowor, 32, 64), __shfl(rowor, 0, 64)};
+      {
+        const int k = lane & 31;
+        const int wA = __shfl(rW, 48, 64), wB = __shfl(rW, 32, 64), wC = __shfl(rW, 0, 64);
+        const uint32_t mcb = lane < 32 ? mk[2] : mk[1];
+        szCB += ((mcb >> k) & 1u) ? uint32_t(lane < 32 ? wC : wB) : 0u;
+        szA += ((mk[0] >> k) & 1u) ? uint32_t(wA) : 0u;
+      }
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
         const int nb = mk[p] ? 32 - __clz(mk[p]) : 0;
@@ -875,6 +886,10 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
   } else if (tid0 < 3 * 33 + 2) {
     const unsigned long long mx = S.mxab;
     row[tid0] = tid0 == 3 * 33 ? uint32_t(mx) : uint32_t(mx >> 32);
+  }
+  if (tid0 < 64) {
+    row[ROW_SIZES + (tid0 < 32 ? 64 + tid0 : tid0)] = szCB;
+    if (tid0 < 32) row[ROW_SIZES + tid0] = szA;
   }
 }
 
@@ -1315,26 +1330,29 @@ __global__ void k_anchor3_compress(Level3Args L, const T *__restrict__ x, T *gou
     if (ax2 <= 1.7976931348623157e308) mb = (unsigned long long)__double_as_longlong(ax2);
   }
   __syncthreads();
+  const uint32_t mask = sor;
   if (tid == 0) {
-    uint32_t mask = sor;
     uint32_t r[32];
     for (int j = 0; j < 32; ++j) r[j] = j < n ? xenc(sv[j]) : 0u;
     transpose32(r);
     for (int k = 0; k < 32; ++k)
       if ((mask >> k) & 1u) o.payload[L.slot_base[0] + uint64_t(31 - k)] = r[k];
     o.masks[L.chunk_base[0]] = mask;
-    // delta-y of the anchors (always loaded; kept for completeness)
-    for (int b = 1; b <= 32; ++b) {
-      uint32_t mxv = 0;
-      for (int j = 0; j < n; ++j) {
-        uint32_t w = sv[j] ^ NB_A;
-        uint32_t mm = b == 32 ? 0xFFFFFFFFu : ((1u << b) - 1u);
-        uint32_t ab = NB_A & mm, t = w & mm;
-        uint32_t d = t >= ab ? t - ab : ab - t;
-        mxv = d > mxv ? d : mxv;
-      }
-      atomicMax(o.errq + b, mxv);
+  }
+  // plane sizes of the anchor chunk (one word per plane) and its delta-y
+  // (always loaded; kept for completeness), one b per thread
+  if (tid < 32 && ((mask >> tid) & 1u)) o.sizes[tid] = 4ull;
+  if (tid < 32) {
+    const int b = tid + 1;
+    const uint32_t mm = b == 32 ? 0xFFFFFFFFu : ((1u << b) - 1u);
+    const uint32_t ab = NB_A & mm;
+    uint32_t mxv = 0;
+    for (int j = 0; j < n; ++j) {
+      const uint32_t t = (sv[j] ^ NB_A) & mm;
+      const uint32_t d = t >= ab ? t - ab : ab - t;
+      mxv = d > mxv ? d : mxv;
     }
+    atomicMax(o.errq + b, mxv);
   }
   if (mb) atomicMax(o.maxabs_bits, mb);
 }
@@ -1375,56 +1393,77 @@ __global__ void k_gather_coarse(const T *__restrict__ field, int64_t fd1, int64_
   g[i] = field[((s * c0) * fd1 + s * c1) * fd2 + s * c2];
 }
 
-// errq and max |x^| of a compression from the fused-level rows: grid
-// (launch, pass, split), each workgroup reduces up to RR_ROWS rows of one
-// launch for one pass (thread t: b = t % 33 over rows t / 33, + 7, ...), then
-// one atomic per value.
-constexpr int RR_ROWS = 512;
+// errq, max |x^| and plane sizes of a compression from the fused-level rows:
+// grid (launch, pass, split), each workgroup reduces RR_ROWS rows of one
+// launch for one pass with every load of a thread issued together, then one
+// atomic per value.
+constexpr int RR_ROWS = 64;
 __global__ __launch_bounds__(256) void k_rows_reduce(LevelRows lr, const uint32_t *rows, uint32_t *errq,
-                                                     unsigned long long *maxabs_bits) {
+                                                     unsigned long long *maxabs_bits,
+                                                     unsigned long long *sizes) {
   __shared__ uint32_t s_max[33];
+  __shared__ uint32_t s_sz[32];
   __shared__ unsigned long long s_mx;
   const int li = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
   const uint32_t r0 = blockIdx.z * RR_ROWS;
   const uint32_t n = lr.n_rows[li];
   if (r0 >= n) return;  // uniform: before any barrier
-  const uint32_t r1 = n - r0 < uint32_t(RR_ROWS) ? n : r0 + RR_ROWS;
+  const uint32_t nr = n - r0 < uint32_t(RR_ROWS) ? n - r0 : uint32_t(RR_ROWS);
   if (tid < 33) s_max[tid] = 0u;
+  if (tid < 32) s_sz[tid] = 0u;
   if (tid == 0) s_mx = 0ull;
   __syncthreads();
-  const uint32_t *base = rows + size_t(lr.row_base[li]) * WG_ROW;
+  const uint32_t *base = rows + (size_t(lr.row_base[li]) + r0) * WG_ROW;
+  // delta-y: thread t takes b = t % 33 of rows t / 33, + 7, ...
   if (tid < 7 * 33) {
-    const int b = tid % 33;
-    uint32_t m = 0;
-    for (uint32_t r = r0 + tid / 33; r < r1; r += 7) {
-      const uint32_t v = base[size_t(r) * WG_ROW + p * 33 + b];
-      m = v > m ? v : m;
+    const int b = tid % 33, r = tid / 33;
+    uint32_t v[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) {
+      const uint32_t rr = uint32_t(r + 7 * j);
+      v[j] = rr < nr ? base[size_t(rr) * WG_ROW + p * 33 + b] : 0u;
     }
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < 10; ++j) m = v[j] > m ? v[j] : m;
     if (m) atomicMax(&s_max[b], m);
   }
-  if (p == 0) {
-    unsigned long long m = 0;
-    for (uint32_t r = r0 + tid; r < r1; r += 256) {
-      const uint32_t *w = base + size_t(r) * WG_ROW + 99;
-      const unsigned long long v = (unsigned long long)w[0] | ((unsigned long long)w[1] << 32);
-      m = v > m ? v : m;
+  // plane words: thread t takes plane t & 31 of rows t >> 5, + 8, ...
+  {
+    const int k = tid & 31, r = tid >> 5;
+    uint32_t v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t rr = uint32_t(r + 8 * j);
+      v[j] = rr < nr ? base[size_t(rr) * WG_ROW + ROW_SIZES + p * 32 + k] : 0u;
     }
-    if (m) atomicMax(&s_mx, m);
+    uint32_t t = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) t += v[j];
+    if (t) atomicAdd(&s_sz[k], t);
+  }
+  if (p == 0 && uint32_t(tid) < nr) {
+    const uint32_t *w = base + size_t(tid) * WG_ROW + 99;
+    const unsigned long long v = (unsigned long long)w[0] | ((unsigned long long)w[1] << 32);
+    if (v) atomicMax(&s_mx, v);
   }
   __syncthreads();
-  if (tid > 0 && tid < 33 && s_max[tid]) atomicMax(errq + size_t(lr.pass_index[li][p]) * 33 + tid, s_max[tid]);
+  const size_t pi = lr.pass_index[li][p];
+  if (tid > 0 && tid < 33 && s_max[tid]) atomicMax(errq + pi * 33 + tid, s_max[tid]);
+  if (tid < 32 && s_sz[tid]) atomicAdd(sizes + pi * 32 + tid, 4ull * s_sz[tid]);
   if (p == 0 && tid == 0 && s_mx) atomicMax(maxabs_bits, s_mx);
 }
 
 }  // namespace
 
 hipError_t launch_rows_reduce(const LevelRows &lr, const uint32_t *rows, uint32_t *errq,
-                              unsigned long long *maxabs_bits, hipStream_t stream) {
+                              unsigned long long *maxabs_bits, unsigned long long *sizes,
+                              hipStream_t stream) {
   uint32_t most = 0;
   for (int i = 0; i < lr.n; ++i) most = lr.n_rows[i] > most ? lr.n_rows[i] : most;
   if (lr.n == 0 || most == 0) return hipSuccess;
   dim3 grid(uint32_t(lr.n), 3, (most + RR_ROWS - 1) / RR_ROWS);
-  hipLaunchKernelGGL(k_rows_reduce, grid, dim3(256), 0, stream, lr, rows, errq, maxabs_bits);
+  hipLaunchKernelGGL(k_rows_reduce, grid, dim3(256), 0, stream, lr, rows, errq, maxabs_bits, sizes);
   return hipGetLastError();
 }
 
