@@ -23,6 +23,8 @@
 // only offsets into global arrays are 64-bit.  Per target the arithmetic is
 // exactly that of the per-pass kernels (same stencils, same rounding), so
 // streams and reconstructions are bit-identical.
+#include <type_traits>
+
 #include "kernels.h"
 
 #include "ipc_internal.h"
@@ -108,6 +110,31 @@ __device__ __forceinline__ void transpose32p(uint32_t a[32]) {
   for (int j = 4; j != 0; j >>= 1, m ^= (m << j)) {
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
+      if (k & j) continue;
+      const uint32_t lo = a[k], hi = a[k | j];
+      a[k] = bfi(m, lo, hi << j);
+      a[k | j] = bfi(m, lo >> j, hi);
+    }
+  }
+}
+
+// The 16x16 bit transposes of the low and of the high halves of 16 words at
+// once (the 8-, 4-, 2- and 1-bit stages above).  With 32 codes below 2^16,
+// word k = code k | code k+16 << 16 turns into word k = plane k of the 32
+// codes, and back: a 32x32 transpose whose zero half is never touched.
+__device__ __forceinline__ void transpose16x2(uint32_t a[16]) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (k & 8) continue;
+    const uint32_t lo = a[k], hi = a[k + 8];
+    a[k] = __builtin_amdgcn_perm(hi, lo, 0x06020400u);
+    a[k + 8] = __builtin_amdgcn_perm(hi, lo, 0x07030501u);
+  }
+  uint32_t m = 0x0F0F0F0Fu;
+#pragma unroll
+  for (int j = 4; j != 0; j >>= 1, m ^= (m << j)) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
       if (k & j) continue;
       const uint32_t lo = a[k], hi = a[k | j];
       a[k] = bfi(m, lo, hi << j);
@@ -802,56 +829,76 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
     if (tid < 64) {
       const int rp = lane < 32 ? 2 : (lane < 48 ? 1 : 0);
       const int rw = lane < 32 ? lane : (lane < 48 ? lane - 32 : lane - 48);
-      const Ext rce = chunk_ext(L, rp, m, ty, tx);
-      const int rW = (rce.count + 31) >> 5;
+      // code counts of the step's chunk of each pass (uniform), this lane's
+      const int cA = chunk_ext(L, 0, m, ty, tx).count, cB = chunk_ext(L, 1, m, ty, tx).count,
+                cC = chunk_ext(L, 2, m, ty, tx).count;
+      const int cnt = rp == 2 ? cC : (rp == 1 ? cB : cA);
+      const int rW = (cnt + 31) >> 5;
       const bool work = lane < 56 && rw < rW;
+      // codes 32 rw .. 32 rw + 31 sit at padded indices 33 rw + j
+      const uint32_t *cb = S.codes + code_off1(rp) + 33 * rw;
+      const int nv = work ? cnt - 32 * rw : 0;
       uint32_t r[32];
-      uint32_t rowor = 0;
-      if (work) {
-        // codes 32 rw .. 32 rw + 31 sit at padded indices 33 rw + j
-        const uint32_t *cb = S.codes + code_off1(rp) + 33 * rw;
-        const int nv = rce.count - 32 * rw;
 #pragma unroll
-        for (int j = 0; j < 32; ++j) r[j] = j < nv ? cb[j] : 0u;
-        transpose32p(r);
-        // planes of e = v ^ (v >> 1) ^ (v >> 2) from the planes of v; each
-        // plane is materialized before it is tested (the scheduler would
-        // otherwise keep pairwise partial XORs alive for the tests)
+      for (int j = 0; j < 32; ++j) r[j] = j < nv ? cb[j] : 0u;
+      uint32_t orv = 0;
 #pragma unroll
-        for (int k = 0; k < 32; ++k) {
-          r[k] = k < 30 ? (r[k] ^ r[k + 1] ^ r[k + 2]) : (k == 30 ? (r[30] ^ r[31]) : r[31]);
+      for (int j = 0; j < 32; ++j) orv |= r[j];
+      const int64_t cid = chunk_id(L, m, ty, tx);
+      // planes 0 .. NP-1 of v in r -> planes of e = v ^ (v >> 1) ^ (v >> 2)
+      // (each materialized before it is tested: the scheduler would otherwise
+      // keep pairwise partial XORs alive), the chunk masks from one ballot per
+      // plane (pass C is lanes 0-31, B 32-47, A 48-55), the stores
+      uint32_t mA = 0, mB = 0, mC = 0;
+      auto finish = [&](auto npc) {
+        constexpr int NP = decltype(npc)::value;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+          r[k] = k + 2 < NP ? (r[k] ^ r[k + 1] ^ r[k + 2]) : (k + 1 < NP ? (r[k] ^ r[k + 1]) : r[k]);
           asm volatile("" : "+v"(r[k]));
         }
 #pragma unroll
-        for (int k = 31; k >= 0; --k) rowor = (rowor << 1) | (r[k] != 0u ? 1u : 0u);
-      }
+        for (int k = 0; k < NP; ++k) {
+          const uint64_t b = __builtin_amdgcn_ballot_w64(r[k] != 0u);
+          mC |= uint32_t(uint32_t(b) != 0u) << k;
+          mB |= uint32_t((uint32_t(b >> 32) & 0xFFFFu) != 0u) << k;
+          mA |= uint32_t((uint32_t(b >> 48) & 0xFFu) != 0u) << k;
+        }
+        const uint32_t ro = rp == 2 ? mC : (rp == 1 ? mB : mA);
+        if (work) {
+          uint32_t *slot = o.payload + LSEL(slot_base, rp) + uint64_t(cid) * 32u * LSEL(wmax, rp) + rw;
 #pragma unroll
-      for (int o2 = 1; o2 < 32; o2 <<= 1) {
-        const uint32_t u = __shfl_xor(rowor, o2, 64);
-        if ((8 << rp) > o2) rowor |= u;
-      }
-      const int64_t cid = chunk_id(L, m, ty, tx);
-      if (work) {
-        uint32_t *slot = o.payload + LSEL(slot_base, rp) + uint64_t(cid) * 32u * LSEL(wmax, rp) + rw;
+          for (int k = 0; k < NP; ++k)
+            if ((ro >> k) & 1u) slot[(31 - k) * rW] = r[k];
+        }
+      };
+      // every code of the wave below 2^16: planes 16 .. 31 are zero, and a
+      // pair of 16x16 transposes gives planes 0 .. 15
+      if (__builtin_amdgcn_ballot_w64(orv > 0xFFFFu) == 0) {
 #pragma unroll
-        for (int k = 0; k < 32; ++k)
-          if ((rowor >> k) & 1u) slot[(31 - k) * rW] = r[k];
+        for (int k = 0; k < 16; ++k) r[k] = __builtin_amdgcn_perm(r[k + 16], r[k], 0x05040100u);
+        transpose16x2(r);
+        finish(std::integral_constant<int, 16>{});
+      } else {
+        transpose32p(r);
+        finish(std::integral_constant<int, 32>{});
       }
+      const uint32_t rowor = rp == 2 ? mC : (rp == 1 ? mB : mA);
       if (lane < 56 && rw == 0) o.masks[LSEL(chunk_base, rp) + cid] = rowor;
-      // delta-y for b >= 14 of chunks holding codes longer than 14 digits
-      const uint32_t mk[3] = {__shfl(rowor, 48, 64), __shfl(rowor, 32, 64), __shfl(rowor, 0, 64)};
       {
         const int k = lane & 31;
-        const int wA = __shfl(rW, 48, 64), wB = __shfl(rW, 32, 64), wC = __shfl(rW, 0, 64);
-        const uint32_t mcb = lane < 32 ? mk[2] : mk[1];
-        szCB += ((mcb >> k) & 1u) ? uint32_t(lane < 32 ? wC : wB) : 0u;
-        szA += ((mk[0] >> k) & 1u) ? uint32_t(wA) : 0u;
+        const uint32_t wA = uint32_t(cA + 31) >> 5, wB = uint32_t(cB + 31) >> 5, wC = uint32_t(cC + 31) >> 5;
+        const uint32_t mcb = lane < 32 ? mC : mB;
+        szCB += ((mcb >> k) & 1u) ? (lane < 32 ? wC : wB) : 0u;
+        szA += ((mA >> k) & 1u) ? wA : 0u;
       }
+      // delta-y for b >= 14 of chunks holding codes longer than 14 digits
+      const uint32_t mk[3] = {mA, mB, mC};
+      const int ck[3] = {cA, cB, cC};
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
         const int nb = mk[p] ? 32 - __clz(mk[p]) : 0;
-        if (nb > 14)
-          errq_hi(S.eq[p], S.codes + code_off1(p), chunk_ext(L, p, m, ty, tx).count, nb, lane);
+        if (nb > 14) errq_hi(S.eq[p], S.codes + code_off1(p), ck[p], nb, lane);
       }
     }
   }
@@ -907,8 +954,27 @@ __device__ __forceinline__ void planes_to_codes(uint32_t p[32], uint32_t keep) {
   for (int j = 0; j < 32; ++j) p[j] &= keep;
 }
 
-// the 32 plane words of word `w` of a chunk (its stored planes that `keep`
-// selects); planes not loaded read word 0 of the payload, which always exists
+// Planes 0 .. 15 only (every loaded plane below 16): the XOR coding undone
+// on 16 planes, a pair of 16x16 transposes, then the halves split into codes
+// j and j + 16.
+__device__ __forceinline__ void planes_to_codes16(uint32_t p[32], uint32_t keep) {
+  p[14] ^= p[15];
+#pragma unroll
+  for (int k = 13; k >= 0; --k) p[k] ^= p[k + 1] ^ p[k + 2];
+  transpose16x2(p);
+  const uint32_t kw = (keep & 0xFFFFu) | (keep << 16);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const uint32_t w = p[j] & kw;
+    p[j] = w & 0xFFFFu;
+    p[j + 16] = w >> 16;
+  }
+}
+
+// the NP lowest plane words of word `w` of a chunk (its stored planes that
+// `keep` selects); planes not loaded read word 0 of the payload, which always
+// exists
+template <int NP>
 __device__ __forceinline__ void load_planes(const RetrieveIn &in, uint64_t first_word, uint32_t mask,
                                             uint32_t keep, uint32_t W, uint32_t w, uint32_t p[32]) {
   const bool packed = in.chunk_off != nullptr;
@@ -917,7 +983,7 @@ __device__ __forceinline__ void load_planes(const RetrieveIn &in, uint64_t first
   asm volatile("" : "+v"(load));
   const uint32_t *base = in.payload + first_word + w;
 #pragma unroll
-  for (int k = 0; k < 32; ++k) {
+  for (int k = 0; k < NP; ++k) {
     const bool on = (load >> k) & 1u;
     const uint32_t v = *(on ? base + plane_rank(packed, mask, k) * W : in.payload);
     p[k] = on ? v : 0u;
@@ -1103,8 +1169,16 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
       if (ok) {
         const uint32_t keep = sel3(r.p, keepA, keepB, keepC);
         uint32_t p[32];
-        load_planes(in, first, mask, keep, uint32_t((e.count + 31) >> 5), uint32_t(wd), p);
-        planes_to_codes(p, keep);
+        // every loaded plane of the wave below 16: half the planes, half
+        // the transposes
+        const bool narrow = __builtin_amdgcn_ballot_w64(((mask & keep) >> 16) != 0u) == 0;
+        if (narrow) {
+          load_planes<16>(in, first, mask, keep, uint32_t((e.count + 31) >> 5), uint32_t(wd), p);
+          planes_to_codes16(p, keep);
+        } else {
+          load_planes<32>(in, first, mask, keep, uint32_t((e.count + 31) >> 5), uint32_t(wd), p);
+          planes_to_codes(p, keep);
+        }
         if (r.sel == 3) {
           uint32_t *cb = S.codes + code_off1(r.p) + 33 * wd;
           const int nv = e.count - 32 * wd;
