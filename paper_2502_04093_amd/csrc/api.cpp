@@ -22,6 +22,7 @@ using namespace ipc;
 
 struct ipc_ctx {
   int device = 0;
+  void *dev_zero = nullptr;             // 256 zero bytes on the device
   int n_cu = 256;                       // compute units of the device
   hipStream_t stream = nullptr;
   hipStream_t owned = nullptr;
@@ -443,6 +444,7 @@ void run_retrieve(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &pla
   in.out_bits = static_cast<const uint64_t *>(s->out_bits.p);
   in.out_start = static_cast<const uint32_t *>(s->out_start.p);
   in.n_out = s->meta.n_outliers;
+  in.zero = static_cast<const uint32_t *>(ctx->dev_zero);
   prof_begin(ctx, s->args.size());
   const Schedule &sc = s->meta.sched;
   if (fused3(sc)) {
@@ -562,7 +564,12 @@ ipc_status ipc_ctx_create(int device, void *hip_stream, ipc_ctx **out) {
     }
     c->stream = c->owned;
   }
-  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+      hipMalloc(&c->dev_zero, 256) != hipSuccess || hipMemset(c->dev_zero, 0, 256) != hipSuccess) {
+    (void)hipGetLastError();
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->dev_zero) (void)hipFree(c->dev_zero);
     if (c->owned) (void)hipStreamDestroy(c->owned);
     delete c;
     return IPC_EHIP;
@@ -594,6 +601,7 @@ void ipc_ctx_destroy(ipc_ctx *ctx) {
   if (ctx->ws_out) (void)hipFree(ctx->ws_out);
   if (ctx->ws_cnt) (void)hipFree(ctx->ws_cnt);
   if (ctx->ws_rows) (void)hipFree(ctx->ws_rows);
+  if (ctx->dev_zero) (void)hipFree(ctx->dev_zero);
   for (int i = 0; i < 2; ++i)
     if (ctx->ws_g[i]) (void)hipFree(ctx->ws_g[i]);
   if (ctx->ws_args) (void)hipFree(ctx->ws_args);

@@ -70,6 +70,7 @@ struct RetrieveIn {
   const uint64_t *out_bits;
   const uint32_t *out_start;  // first outlier of each global chunk (n_chunks + 1 entries)
   uint64_t n_out;
+  const uint32_t *zero;       // a device word holding 0 (read for planes not loaded)
 };
 
 // A whole level of a 3-D field in one launch (chunk shape (2, 16, 64)).

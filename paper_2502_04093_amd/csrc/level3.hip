@@ -839,11 +839,19 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
       const uint32_t *cb = S.codes + code_off1(rp) + 33 * rw;
       const int nv = work ? cnt - 32 * rw : 0;
       uint32_t r[32];
+      if (cA == CA && cB == CB && cC == CC) {
+        // every chunk full: lanes 0-55 all hold 32 codes (lanes 56-63 read
+        // codes of the step that no mask, store or test below looks at)
 #pragma unroll
-      for (int j = 0; j < 32; ++j) r[j] = j < nv ? cb[j] : 0u;
+        for (int j = 0; j < 32; ++j) r[j] = cb[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < 32; ++j) r[j] = j < nv ? cb[j] : 0u;
+      }
       uint32_t orv = 0;
 #pragma unroll
       for (int j = 0; j < 32; ++j) orv |= r[j];
+      orv = lane < 56 ? orv : 0u;
       const int64_t cid = chunk_id(L, m, ty, tx);
       // planes 0 .. NP-1 of v in r -> planes of e = v ^ (v >> 1) ^ (v >> 2)
       // (each materialized before it is tested: the scheduler would otherwise
@@ -864,12 +872,18 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
           mB |= uint32_t((uint32_t(b >> 32) & 0xFFFFu) != 0u) << k;
           mA |= uint32_t((uint32_t(b >> 48) & 0xFFu) != 0u) << k;
         }
-        const uint32_t ro = rp == 2 ? mC : (rp == 1 ? mB : mA);
+        // planes up to the highest one any of the three chunks keeps; a
+        // plane some chunk does not keep is written as zeros into its slot,
+        // which no reader looks at
+        const uint32_t top = 32u - uint32_t(__clz(mA | mB | mC));
         if (work) {
-          uint32_t *slot = o.payload + LSEL(slot_base, rp) + uint64_t(cid) * 32u * LSEL(wmax, rp) + rw;
+          uint32_t *q = o.payload + LSEL(slot_base, rp) + uint64_t(cid) * 32u * LSEL(wmax, rp) + rw +
+                        31u * uint32_t(rW);
 #pragma unroll
-          for (int k = 0; k < NP; ++k)
-            if ((ro >> k) & 1u) slot[(31 - k) * rW] = r[k];
+          for (int k = 0; k < NP; ++k) {
+            if (uint32_t(k) < top) *q = r[k];
+            q -= rW;
+          }
         }
       };
       // every code of the wave below 2^16: planes 16 .. 31 are zero, and a
@@ -972,8 +986,8 @@ __device__ __forceinline__ void planes_to_codes16(uint32_t p[32], uint32_t keep)
 }
 
 // the NP lowest plane words of word `w` of a chunk (its stored planes that
-// `keep` selects); planes not loaded read word 0 of the payload, which always
-// exists
+// `keep` selects; planes not loaded read the zero word).  Plane offsets are
+// below 2^10 words: 24-bit multiplies.
 template <int NP>
 __device__ __forceinline__ void load_planes(const RetrieveIn &in, uint64_t first_word, uint32_t mask,
                                             uint32_t keep, uint32_t W, uint32_t w, uint32_t p[32]) {
@@ -985,8 +999,7 @@ __device__ __forceinline__ void load_planes(const RetrieveIn &in, uint64_t first
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
     const bool on = (load >> k) & 1u;
-    const uint32_t v = *(on ? base + plane_rank(packed, mask, k) * W : in.payload);
-    p[k] = on ? v : 0u;
+    p[k] = *(on ? base + __umul24(plane_rank(packed, mask, k), W) : in.zero);
   }
 }
 
@@ -1180,11 +1193,12 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
           planes_to_codes(p, keep);
         }
         if (r.sel == 3) {
+          // all 32 slots of the word, also past the chunk's last code: the
+          // pass's buffer holds 33 slots per word of a full chunk, and only
+          // slots of real targets are read
           uint32_t *cb = S.codes + code_off1(r.p) + 33 * wd;
-          const int nv = e.count - 32 * wd;
 #pragma unroll
-          for (int j = 0; j < 32; ++j)
-            if (j < nv) cb[j] = p[j];
+          for (int j = 0; j < 32; ++j) cb[j] = p[j];
         } else if (r.p == 0) {
           uint32_t *d = &S.hva[0][0] + r.dst;
           if (r.sel == 1) {
