@@ -432,22 +432,50 @@ __device__ __forceinline__ void write_rows(const Level3Args &L, SH &S, T *gout, 
 
 __device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) { return a > b ? a - b : b - a; }
 
+// Full-wave reductions (every lane active): within each row of 16 lanes by
+// DPP lane swaps (quad permutes, then half-row and row mirrors; order does not
+// matter for min / max), then the four row results through lane reads.  The
+// result is uniform.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, 0xF, 0xF, false));
+}
+template <typename Op>
+__device__ __forceinline__ uint32_t wave_reduce(uint32_t v, Op op) {
+  v = op(v, dpp<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+  v = op(v, dpp<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+  v = op(v, dpp<0x141>(v));  // row_half_mirror
+  v = op(v, dpp<0x140>(v));  // row_mirror
+  const uint32_t r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+  const uint32_t r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+  return op(op(r0, r1), op(r2, r3));
+}
 __device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    int u = __shfl_xor(v, o, 64);
-    v = u < v ? u : v;
-  }
-  return v;
+  return int(wave_reduce(uint32_t(v), [](uint32_t a, uint32_t b) { return int(a) < int(b) ? a : b; }));
 }
 __device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    int u = __shfl_xor(v, o, 64);
-    v = u > v ? u : v;
-  }
-  return v;
+  return int(wave_reduce(uint32_t(v), [](uint32_t a, uint32_t b) { return int(a) > int(b) ? a : b; }));
 }
+__device__ __forceinline__ uint64_t wave_max_bits(uint64_t v) {
+  auto mx = [](uint64_t a, uint64_t b) { return a > b ? a : b; };
+  auto sw = [](uint64_t x, auto ctrl) {
+    constexpr int C = decltype(ctrl)::value;
+    return uint64_t(dpp<C>(uint32_t(x))) | (uint64_t(dpp<C>(uint32_t(x >> 32))) << 32);
+  };
+  v = mx(v, sw(v, std::integral_constant<int, 0xB1>{}));
+  v = mx(v, sw(v, std::integral_constant<int, 0x4E>{}));
+  v = mx(v, sw(v, std::integral_constant<int, 0x141>{}));
+  v = mx(v, sw(v, std::integral_constant<int, 0x140>{}));
+  uint64_t r = 0;
+#pragma unroll
+  for (int l = 0; l < 64; l += 16) {
+    const uint64_t x = uint64_t(uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v)), l))) |
+                       (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v >> 32)), l))) << 32);
+    r = mx(r, x);
+  }
+  return r;
+}
+__device__ __forceinline__ uint32_t wave_max_bits(uint32_t v) { return uint32_t(wave_max(int(v))); }
 
 // Delta-y for b >= 14 over one chunk of `count` buffered codes with at most nb
 // digits, nb > 14 (see k_level3_compress), by one wave: exact |q - q'_b| per
@@ -926,12 +954,7 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
       const int v = wave_max(int(qs[p]));
       if (lane == 0 && v > 0) atomicMax(&S.qa[p], uint32_t(v));
     }
-    U v = mxb;
-#pragma unroll
-    for (int o2 = 32; o2 > 0; o2 >>= 1) {
-      const U u = __shfl_xor(v, o2, 64);
-      v = u > v ? u : v;
-    }
+    const U v = U(wave_max_bits(mxb));
     if (lane == 0 && v)
       atomicMax(&S.mxab, (unsigned long long)__double_as_longlong(BT::to_double(v)));
     __syncthreads();
