@@ -1,0 +1,129 @@
+"""GPU parity at the sizes where the fused level kernels run multi-step
+columns (several chunk rows per workgroup, the coarse-plane ring, prefetch of
+the next step), and on streams the oracle wrote (packed payload placement)
+(gpu).
+
+Byte-exact against the oracle up to 33.5 M points; the 512^3 benchmark field
+itself is checked through properties that hold at any size (the oracle needs
+minutes there): the error bound of every retrieval, refinement equal to a fresh
+retrieval, determinism.
+"""
+
+import numpy as np
+import pytest
+
+import fieldgen
+from oracle import codec
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2502_04093_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pkg.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def _bytes(t):
+    return t.detach().cpu().numpy().tobytes()
+
+
+# (shape, dtype, seed, relative eb, special values): level-1 columns of 16
+# (512 x 256 x 256), 8 with a ragged last segment (300 x 200 x 260) and 4 in
+# float64 (200 x 130 x 260)
+MULTI = [
+    ((512, 256, 256), np.float32, 3, 1e-4, False),
+    ((300, 200, 260), np.float32, 4, 1e-4, True),
+    ((200, 130, 260), np.float64, 5, 1e-6, True),
+]
+
+
+@pytest.mark.parametrize("case", MULTI, ids=lambda c: f"{'x'.join(map(str, c[0]))}-{np.dtype(c[1]).name}")
+def test_multistep_columns_match_oracle(ctx, case):
+    shape, dt, seed, rel, special = case
+    x = fieldgen.grf(shape, -5.0 / 6.0, seed=seed, dtype=dt)
+    if special:
+        f = x.reshape(-1)
+        f[12345] = np.nan
+        f[f.size // 3] = np.inf
+        f[f.size // 2 + 7] = dt(3e37) if dt == np.float32 else 3e300
+    r = fieldgen.value_range(np.nan_to_num(x, posinf=0, neginf=0))
+    eb = rel * r
+    print(f"case {shape} {np.dtype(dt).name} eb={eb}", flush=True)
+    ref, dbg = codec.compress(x, eb, debug=True)
+    s = ctx.compress(_dev(x), eb)
+    assert s.to_bytes() == ref
+    st = s.retrieve(eb=eb)
+    assert _bytes(st.tensor()) == dbg.xhat.tobytes()
+    st.free()
+    st = s.retrieve(eb=1e2 * eb)
+    o = codec.retrieve(ref, "eb", 1e2 * eb)
+    assert st.plan == list(o.plan)
+    assert _bytes(st.tensor()) == o.field.tobytes()
+    st.free()
+    s.free()
+
+
+@pytest.mark.parametrize("rel", [1e-3, 1e-7])
+def test_oracle_stream_fused_packed_placement(ctx, rel):
+    """A 3-D stream the oracle wrote, retrieved by the fused kernels from the
+    packed placement; at 1e-7 * range the codes pass 2^16 (the full-width
+    plane transposes), at 1e-3 they stay below it."""
+    x = fieldgen.random_field((40, 70, 200), seed=21, dtype=np.float32)
+    eb = rel * fieldgen.value_range(x)
+    ref = codec.compress(x, eb)
+    s = ctx.stream_from_bytes(ref)
+    assert s.to_bytes() == ref
+    for plan_seed in range(4):
+        draw = np.random.default_rng(100 + plan_seed).integers(0, 20, size=s.n_passes)
+        plan = [int(b) if s.pass_info(i)["progressive"] else 0 for i, b in enumerate(draw)]
+        if plan_seed == 0:
+            plan = [0] * s.n_passes
+        st = s.retrieve_plan(plan)
+        o = codec.retrieve_with_plan(ref, plan)
+        assert _bytes(st.tensor()) == o.field.tobytes()
+        st.free()
+    for br in (1.0, 4.0):
+        st = s.retrieve(bitrate=br)
+        o = codec.retrieve(ref, "bitrate", br)
+        assert st.plan == list(o.plan)
+        assert _bytes(st.tensor()) == o.field.tobytes()
+        st.free()
+    s.free()
+
+
+def test_benchmark_field_properties(ctx):
+    """The 512^3 float32 field of the benchmark, compressed at 1e-4 * range in
+    the benchmark's launch configuration."""
+    x = fieldgen.grf_torch((512, 512, 512), -5.0 / 6.0, 0)
+    r = float(x.max().double() - x.min().double())
+    eb = 1e-4 * r
+    s = ctx.compress(x, eb)
+    a = s.to_bytes()
+    s2 = ctx.compress(x, eb)
+    assert s2.to_bytes() == a
+    s2.free()
+    xd = x.double()
+    for rel in (1e-4, 1e-3, 1e-2):
+        st = s.retrieve(eb=rel * r)
+        err = float((st.tensor().double() - xd).abs().max())
+        assert err <= st.bound <= rel * r * (1 + 1e-12)
+        st.free()
+    st = s.retrieve(eb=1e-2 * r)
+    st.refine(eb=1e-3 * r)
+    fresh = s.retrieve(eb=1e-3 * r)
+    assert st.plan == fresh.plan
+    assert torch.equal(st.tensor(), fresh.tensor())
+    fresh.free()
+    st.free()
+    s.free()
