@@ -43,6 +43,8 @@ constexpr int PADA = CA + CA / 32, PADB = CB + CB / 32, PADC = CC + CC / 32;
 constexpr int NHA = 129, NHB = 48;  // halo targets of pass A and B per step
 
 __device__ __forceinline__ int pidx(int j) { return j + (j >> 5); }
+// a * b + c for small non-negative operands (tile-local indices, below 2^24)
+__device__ __forceinline__ int mad24(int a, int b, int c) { return int(__umul24(uint32_t(a), uint32_t(b))) + c; }
 
 template <typename T>
 struct F3;
@@ -398,22 +400,30 @@ __device__ __forceinline__ const T *even_row(SH &S, int m, int zz, int yy) {
 }
 
 // write the 2 x 16 x 64 level points of a step from LDS to a compact grid,
-// four consecutive points per thread
+// four consecutive points per thread and plane (thread t: row (t >> 4) & 15,
+// columns 4 (t & 15) ..+3).  Level-grid indices fit 32 bits (the host limits
+// fields to 2^31 points); interior tiles skip the bounds tests.
 template <typename T, typename SH>
 __device__ __forceinline__ void write_rows(const Level3Args &L, SH &S, T *gout, int m, int y0,
                                            int x0) {
   const int Lz = L.L[0], Ly = L.L[1], Lx = L.L[2];
+  const int t = threadIdx.x;
+  const int yy = (t >> 4) & 15, xq = (t & 15) * 4;
+  const int y = y0 + yy, x = x0 + xq;
   const bool vec = (Lx & 3) == 0 && (reinterpret_cast<uintptr_t>(gout) & 15) == 0;
-  for (int t = threadIdx.x; t < 2 * 16 * (TX / 4); t += WG3) {
-    int zz = t >> 8, yy = (t >> 4) & 15, xq = (t & 15) * 4;
-    int z = 2 * m + zz, y = y0 + yy, x = x0 + xq;
-    if (z >= Lz || y >= Ly || x >= Lx) continue;
+  const bool interior = vec && 2 * m + 1 < Lz && y0 + TY <= Ly && x0 + TX <= Lx;
+  const uint32_t plane = uint32_t(Ly) * uint32_t(Lx);
+  const uint32_t row = uint32_t(mad24(y, Lx, x));
+#pragma unroll
+  for (int zz = 0; zz < 2; ++zz) {
+    const int z = 2 * m + zz;
+    if (!interior && (z >= Lz || y >= Ly || x >= Lx)) continue;
     const T *ev = even_row<T>(S, m, zz, yy);
-    T v0 = ev[(xq >> 1) + 1];
-    T v1 = S.wc[zz][yy][xq >> 1];
-    T v2 = ev[(xq >> 1) + 2];
-    T v3 = S.wc[zz][yy][(xq >> 1) + 1];
-    T *dst = gout + (int64_t(z) * Ly + y) * int64_t(Lx) + x;
+    const T v0 = ev[(xq >> 1) + 1];
+    const T v1 = S.wc[zz][yy][xq >> 1];
+    const T v2 = ev[(xq >> 1) + 2];
+    const T v3 = S.wc[zz][yy][(xq >> 1) + 1];
+    T *dst = gout + (uint32_t(z) * plane + row);
     if (vec) {
       if constexpr (sizeof(T) == 4) {
         *reinterpret_cast<float4 *>(dst) = make_float4(v0, v1, v2, v3);
@@ -769,7 +779,7 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
           const int32_t q = quantize<T>(xval, pred, eb, two_eb, inv, qmax, xhat, out);
           (&S.wa[0][0])[ri] = xhat;
           const int ex = clampi(L.tdims[0][2] - tx * L.ct[0][2], L.ct[0][2]);
-          own_target(0, S.codes + code_off1(0), r * ex + c, q, out, xval, xhat, qaA, m);
+          own_target(0, S.codes + code_off1(0), mad24(r, ex, c), q, out, xval, xhat, qaA, m);
         }
       }
       if (tid < NHA) {
@@ -806,7 +816,7 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
         bool out;
         const int32_t q = quantize<T>(xval, pred, eb, two_eb, inv, qmax, xhat, out);
         S.wb[zz][k][c + 1] = xhat;
-        own_target(1, S.codes + code_off1(1), (zz * ey + k) * ex + c, q, out, xval, xhat, qaB, m);
+        own_target(1, S.codes + code_off1(1), mad24(mad24(zz, ey, k), ex, c), q, out, xval, xhat, qaB, m);
       }
       if (tid < NHB) {
         int zz, kh, xi;
@@ -844,7 +854,7 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
         bool out;
         const int32_t q = quantize<T>(xval, pred, eb, two_eb, inv, qmax, xhat, out);
         S.wc[zz][yy][ci] = xhat;
-        own_target(2, cb, (zz * cey + yy) * cex + ci, q, out, xval, xhat, qaC, m);
+        own_target(2, cb, mad24(mad24(zz, cey, yy), cex, ci), q, out, xval, xhat, qaC, m);
       }
     }
     __syncthreads();
@@ -1303,7 +1313,7 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
         if (y0 + 2 * r < Ly && x0 + 2 * c < Lx) {
           const int ri = (r + 1) * NXP + c + 1;
           const int ex = clampi(L.tdims[0][2] - tx * L.ct[0][2], L.ct[0][2]);
-          const uint32_t local = uint32_t(r * ex + c);
+          const uint32_t local = uint32_t(mad24(r, ex, c));
           const T pred = stencil<T, INTERP>(ra[ri], rb[ri], rc[ri], re[ri], hc, ha, he);
           T val = value(pred, S.codes[code_off1(0) + pidx(int(local))]);
           if (any_out) lookup(4, local, val);
@@ -1346,7 +1356,7 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
         if (ze + zz >= Lz || y >= Ly || x0 + 2 * c >= Lx) continue;
         const T *src = zz == 0 ? S.ring[m & 3][0] : S.wa[0];
         const int ri = k * NXP + c + 1;
-        const uint32_t local = uint32_t((zz * ey + k) * ex + c);
+        const uint32_t local = uint32_t(mad24(mad24(zz, ey, k), ex, c));
         const T pred = stencil<T, INTERP>(src[ri], src[ri + NXP], src[ri + 2 * NXP], src[ri + 3 * NXP], hc, ha, he);
         T val = value(pred, S.codes[code_off1(1) + pidx(int(local))]);
         if (any_out) lookup(10, local, val);
@@ -1390,7 +1400,7 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
         if (cxg >= Lx || y0 + yy >= Ly || ze + zz >= Lz) continue;
         const T *row = even_row<T>(S, m, zz, yy);
         const T pred = stencil<T, INTERP>(row[ci], row[ci + 1], row[ci + 2], row[ci + 3], chc, cha, che);
-        const uint32_t local = uint32_t((zz * cey + yy) * cex + ci);
+        const uint32_t local = uint32_t(mad24(mad24(zz, cey, yy), cex, ci));
         T val = value(pred, cb[pidx(int(local))]);
         if (any_out) lookup(12, local, val);
         S.wc[zz][yy][ci] = val;
