@@ -148,6 +148,25 @@ ipc_status ipc_stream_passes(const ipc_stream *s, uint32_t *n_passes);
 ipc_status ipc_refine(ipc_ctx *ctx, ipc_state *st, ipc_target target, ipc_info *info);
 void ipc_state_free(ipc_state *st);
 
+/* Batches (beyond the paper, which compresses one field at a time): n fields
+ * or streams in one call.  Fields of 3-D shape with the default chunk shape
+ * share one kernel launch per level (a work list of every field's column
+ * segments; a field with fewer levels joins from its top level on), which
+ * keeps the device full where single small levels would not.  Results are
+ * bit-identical to n separate calls, which is also what other shapes get.
+ *
+ * ipc_compress_batch: fields_dev[i] with dims[i * ndim ..] and abs_eb[i],
+ *   one dtype and one ipc_options for all; out[0..n) receives n streams
+ *   (all NULL on error).
+ * ipc_retrieve_batch: streams[i] to targets[i]; out[0..n) receives n
+ *   states, info (NULL or n entries) their descriptions; t_device_ms is the
+ *   batch's device time. */
+ipc_status ipc_compress_batch(ipc_ctx *ctx, uint32_t n, const void *const *fields_dev,
+                              const uint64_t *dims, int ndim, int dtype, const double *abs_eb,
+                              const ipc_options *opts, ipc_stream **out);
+ipc_status ipc_retrieve_batch(ipc_ctx *ctx, uint32_t n, const ipc_stream *const *streams,
+                              const ipc_target *targets, ipc_state **out, ipc_info *info);
+
 /* Host-only planner on a serialized stream (no GPU needed): the plan the
  * library would choose for `target`, optionally restricted to b <= limit[s]
  * (refinement).  plan_out has room for the stream's pass count. */

@@ -78,6 +78,10 @@ SIGNATURES = {
     "ipc_state_free": (None, [c_void_p]),
     "ipc_plan_host": (c_int, [c_void_p, c_uint64, ipc_target, P(c_uint8), P(c_uint8), c_uint32,
                               P(c_double), P(c_uint32), P(c_uint64)]),
+    "ipc_compress_batch": (c_int, [c_void_p, c_uint32, P(c_void_p), P(c_uint64), c_int, c_int,
+                                   P(c_double), P(ipc_options), P(c_void_p)]),
+    "ipc_retrieve_batch": (c_int, [c_void_p, c_uint32, P(c_void_p), P(ipc_target), P(c_void_p),
+                                   P(ipc_info)]),
     "ipc_ctx_set_profiling": (c_int, [c_void_p, c_int, c_int]),
     "ipc_ctx_pass_times": (c_int, [c_void_p, P(c_float), c_uint32, P(c_uint32)]),
     "ipc_status_string": (ctypes.c_char_p, [c_int]),
@@ -202,6 +206,49 @@ class Context:
         _check(lib().ipc_compress(self._p, c_void_p(field.data_ptr()), dims, field.dim(), dt,
                                   float(eb), ctypes.byref(opts), ctypes.byref(out)), self._p)
         return Stream(self, out, tuple(field.shape), field.dtype)
+
+    def compress_batch(self, fields, ebs, interp: str = "cubic", nonprog_levels: int = 0):
+        """Compress several device tensors of one dtype and rank in one call
+        (3-D fields share one launch per level); returns a list of Streams."""
+        import torch
+        n = len(fields)
+        if n == 0 or len(ebs) != n:
+            raise ValueError("give one error bound per field")
+        nd = fields[0].dim()
+        dt = fields[0].dtype
+        for f in fields:
+            if not (f.is_cuda and f.is_contiguous()):
+                raise ValueError("fields must be contiguous device tensors")
+            if f.dim() != nd or f.dtype != dt:
+                raise ValueError("fields of one batch share dtype and rank")
+        if dt not in (torch.float32, torch.float64):
+            raise TypeError("fields must be float32 or float64")
+        ptrs = (c_void_p * n)(*[f.data_ptr() for f in fields])
+        dims = (c_uint64 * (n * nd))(*[d for f in fields for d in f.shape])
+        eba = (c_double * n)(*[float(e) for e in ebs])
+        opts = ipc_options()
+        opts.interp = IPC_CUBIC if interp == "cubic" else IPC_LINEAR
+        opts.nonprog_levels = nonprog_levels
+        out = (c_void_p * n)()
+        _check(lib().ipc_compress_batch(self._p, n, ptrs, dims, nd,
+                                        IPC_F32 if dt == torch.float32 else IPC_F64, eba,
+                                        ctypes.byref(opts), out), self._p)
+        return [Stream(self, c_void_p(out[i]), tuple(fields[i].shape), dt) for i in range(n)]
+
+    def retrieve_batch(self, streams, eb=None, bitrate=None):
+        """Retrieve several streams of this context in one call (eb= or
+        bitrate=: one value, or one per stream); returns a list of States."""
+        n = len(streams)
+        vals = eb if eb is not None else bitrate
+        if not isinstance(vals, (list, tuple)):
+            vals = [vals] * n
+        tg = (ipc_target * n)(*[_target(v if eb is not None else None,
+                                        v if bitrate is not None else None) for v in vals])
+        ptrs = (c_void_p * n)(*[s._p.value if isinstance(s._p, c_void_p) else s._p for s in streams])
+        out = (c_void_p * n)()
+        infos = (ipc_info * n)()
+        _check(lib().ipc_retrieve_batch(self._p, n, ptrs, tg, out, infos), self._p)
+        return [State(streams[i], c_void_p(out[i]), infos[i]) for i in range(n)]
 
     def stream_from_bytes(self, data: bytes, shape=None, dtype=None) -> "Stream":
         import numpy as np

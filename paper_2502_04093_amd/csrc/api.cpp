@@ -498,6 +498,315 @@ uint64_t plane_bytes_between(const ipc_stream *s, const std::vector<int> &lo,
   return tot;
 }
 
+// Schedule, metadata, pass table and device buffers of a new stream
+void setup_stream(ipc_ctx *ctx, ipc_stream *s, const uint64_t *dims, int ndim, int dtype, int interp,
+                  double abs_eb, const ipc_options *opts) {
+  int64_t d64[3];
+  for (int j = 0; j < ndim; ++j) d64[j] = int64_t(dims[j]);
+  int cl[3] = {0, 0, 0};
+  if (opts)
+    for (int j = 0; j < ndim; ++j) cl[j] = opts->chunk_log2[j];
+  StreamMeta &m = s->meta;
+  std::string e;
+  if (!make_schedule(d64, ndim, cl, m.sched, e)) {
+    set_err(ctx, e);
+    throw Fail{IPC_EINVAL};
+  }
+  if (!chunks_supported(m.sched, e)) {
+    set_err(ctx, e);
+    throw Fail{IPC_EUNSUPPORTED};
+  }
+  int np = opts ? opts->nonprog_levels : 0;
+  if (np < 0 || np > m.sched.K) {
+    set_err(ctx, "nonprog_levels out of range");
+    throw Fail{IPC_EINVAL};
+  }
+  m.dtype = dtype;
+  m.interp = interp;
+  m.nonprog_levels = np;
+  m.eb = abs_eb;
+  m.qmax = dtype == IPC_F32 ? QMAX_F32 : QMAX_F64;
+  const Schedule &sc = m.sched;
+  for (const PassGeom &p : sc.passes) s->args.push_back(make_args(sc, p));
+  s->payload = dev_alloc(ctx, size_t(sc.slot_words) * 4);
+  s->masks = dev_alloc(ctx, size_t(sc.n_chunks) * 4);
+}
+
+// Metadata of a compressed stream from its summary block: n_out, maxabs bits,
+// sizes [P][32] u64, errq [P][33] u32
+void finish_stream(ipc_stream *s, const char *hostp, uint64_t nout) {
+  StreamMeta &m = s->meta;
+  const int P = int(m.sched.passes.size());
+  uint64_t mb;
+  std::memcpy(&mb, hostp + 8, 8);
+  std::memcpy(&m.maxabs, &mb, 8);
+  m.errq.resize(size_t(P) * 33);
+  std::memcpy(m.errq.data(), hostp + 16 + size_t(P) * 32 * 8, m.errq.size() * 4);
+  std::vector<uint64_t> sz(size_t(P) * 32);
+  std::memcpy(sz.data(), hostp + 16, sz.size() * 8);
+  m.outliers.clear();
+  m.n_outliers = nout;
+  s->host_outliers_valid = nout == 0;
+  uint64_t words = 0;
+  for (uint64_t v : sz) words += v / 4;
+  m.payload_words = words;
+  m.serialized_bytes = serialized_size(m);
+  // planner tables from the device-computed plane sizes (no mask copy needed)
+  s->tables = plan_tables_from_sizes(m, sz);
+}
+
+size_t summary_bytes(int P) { return 16 + size_t(P) * 32 * 8 + size_t(P) * 33 * 4; }
+
+
+// ---------------------------------------------------------------- batches
+
+// Whether a field of these dims would take the fused 3-D path
+bool fused_dims(const uint64_t *dims, int ndim, const ipc_options *opts) {
+  if (ndim != 3) return false;
+  if (opts)
+    for (int j = 0; j < 3; ++j)
+      if (opts->chunk_log2[j] != 0) return false;
+  int64_t d64[3] = {int64_t(dims[0]), int64_t(dims[1]), int64_t(dims[2])};
+  int cl[3] = {0, 0, 0};
+  Schedule sc;
+  std::string e;
+  return make_schedule(d64, 3, cl, sc, e) && fused3(sc);
+}
+
+// Compression of n fused 3-D fields with one launch per level over all of
+// them (the levels of a field with fewer levels are skipped).  Each field
+// keeps its own summary, outlier records, coarse grids and rows.  Fields
+// whose outliers overflow their record capacity are flagged in `redo`.
+template <typename T>
+void compress_batch_fused(ipc_ctx *ctx, std::vector<ipc_stream *> &ss,
+                          const void *const *fields, const double *ebs, std::vector<char> &redo) {
+  const int n = int(ss.size());
+  const int dtype = ss[0]->meta.dtype, interp = ss[0]->meta.interp;
+  const size_t isz = sizeof(T);
+  // per-field summary blocks and record ranges
+  std::vector<size_t> sum_off(n + 1, 0), rec_off(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    const Schedule &sc = ss[i]->meta.sched;
+    sum_off[i + 1] = sum_off[i] + ((summary_bytes(int(sc.passes.size())) + 255) & ~size_t(255));
+    rec_off[i + 1] = rec_off[i] + std::max<size_t>(4096, size_t(sc.n_points / 1024));
+  }
+  char *summary = static_cast<char *>(ensure_ws(ctx, ctx->ws_summary, ctx->ws_summary_bytes, sum_off[n]));
+  ensure_ws(ctx, ctx->ws_out, ctx->ws_out_cap, rec_off[n] * sizeof(OutlierRec));
+  hip_check(ctx, hipMemsetAsync(summary, 0, sum_off[n], ctx->stream), "memset");
+  // pass tables of all fields (the outlier index reads them)
+  std::vector<PassArgs> args;
+  std::vector<size_t> args_off(n);
+  for (int i = 0; i < n; ++i) {
+    args_off[i] = args.size();
+    args.insert(args.end(), ss[i]->args.begin(), ss[i]->args.end());
+  }
+  DevBuf args_dev = dev_alloc(ctx, args.size() * sizeof(PassArgs));
+  hip_check(ctx, hipMemcpyAsync(args_dev.p, args.data(), args.size() * sizeof(PassArgs),
+                                hipMemcpyHostToDevice, ctx->stream), "upload");
+  // coarse grids, two per field
+  std::vector<DevBuf> g(2 * n);
+  std::vector<CompressOut> o(n);
+  int Kmax = 0;
+  for (int i = 0; i < n; ++i) {
+    const Schedule &sc = ss[i]->meta.sched;
+    Kmax = std::max(Kmax, sc.K);
+    size_t need[2] = {8, 8};
+    for (int j = 1; j <= sc.K; ++j)
+      need[j & 1] = std::max(need[j & 1], size_t(coarse_points(sc, j)) * isz);
+    g[2 * i] = dev_alloc(ctx, need[0]);
+    g[2 * i + 1] = dev_alloc(ctx, need[1]);
+    char *sm = summary + sum_off[i];
+    const int P = int(sc.passes.size());
+    o[i].payload = static_cast<uint32_t *>(ss[i]->payload.p);
+    o[i].masks = static_cast<uint32_t *>(ss[i]->masks.p);
+    o[i].n_out = reinterpret_cast<unsigned long long *>(sm);
+    o[i].maxabs_bits = reinterpret_cast<unsigned long long *>(sm + 8);
+    o[i].sizes = reinterpret_cast<unsigned long long *>(sm + 16);
+    o[i].errq = reinterpret_cast<uint32_t *>(sm + 16 + size_t(P) * 32 * 8);
+    o[i].out_recs = static_cast<OutlierRec *>(ctx->ws_out) + rec_off[i];
+    o[i].out_cap = rec_off[i + 1] - rec_off[i];
+  }
+  // the work lists of the level launches and every field's rows
+  std::vector<BatchC<T>> ent;
+  struct Launch { size_t off; int nf; uint32_t items; };
+  std::vector<Launch> launches;
+  std::vector<LevelRows> lr(n);
+  for (LevelRows &r : lr) std::memset(&r, 0, sizeof(r));
+  uint32_t rows = 0;
+  const int64_t fill = IPC_WG_PER_CU_C * int64_t(ctx->n_cu);
+  for (int l = Kmax; l >= 1; --l) {
+    Launch ln{ent.size(), 0, 0};
+    for (int i = 0; i < n; ++i) {
+      const Schedule &sc = ss[i]->meta.sched;
+      if (l > sc.K) continue;
+      Level3Args La = level3_args(sc, l, fill);
+      La.row_base = rows;
+      const uint32_t items = uint32_t(level3_wgs(La));
+      LevelRows &r = lr[i];
+      if (r.n >= MAX_LEVEL_LAUNCHES) {
+        set_err(ctx, "too many levels for the fused kernels");
+        throw Fail{IPC_EUNSUPPORTED};
+      }
+      r.row_base[r.n] = rows;
+      r.n_rows[r.n] = items;
+      for (int p = 0; p < 3; ++p) r.pass_index[r.n][p] = La.pass_index[p];
+      ++r.n;
+      rows += items;
+      BatchC<T> e;
+      std::memset(&e, 0, sizeof(e));
+      e.L = La;
+      e.x = static_cast<const T *>(fields[i]);
+      e.gin = static_cast<const T *>(g[2 * i + (l & 1)].p);
+      e.gout = l > 1 ? static_cast<T *>(g[2 * i + ((l - 1) & 1)].p) : nullptr;
+      e.o = o[i];
+      e.eb = ebs[i];
+      e.two_eb = T(2.0 * ebs[i]);
+      e.inv = T(1.0 / (2.0 * ebs[i]));
+      e.qmax = T(sizeof(T) == 4 ? QMAX_F32 : QMAX_F64);
+      e.item0 = ln.items;
+      ent.push_back(e);
+      ++ln.nf;
+      ln.items += items;
+    }
+    launches.push_back(ln);
+  }
+  uint32_t *rows_p = static_cast<uint32_t *>(
+      ensure_ws(ctx, ctx->ws_rows, ctx->ws_rows_bytes, size_t(rows) * WG_ROW * 4));
+  for (BatchC<T> &e : ent) e.o.wg_rows = rows_p;
+  for (int i = 0; i < n; ++i) o[i].wg_rows = rows_p;
+  DevBuf ent_dev = dev_alloc(ctx, ent.size() * sizeof(BatchC<T>));
+  hip_check(ctx, hipMemcpyAsync(ent_dev.p, ent.data(), ent.size() * sizeof(BatchC<T>),
+                                hipMemcpyHostToDevice, ctx->stream), "upload");
+  for (int i = 0; i < n; ++i) {
+    const Schedule &sc = ss[i]->meta.sched;
+    hip_check(ctx, launch_anchor3_compress(dtype, anchor3_args(sc), fields[i], g[2 * i + (sc.K & 1)].p,
+                                           ebs[i], o[i], ctx->stream),
+              "anchor kernel launch");
+  }
+  for (const Launch &ln : launches)
+    hip_check(ctx, launch_level3_compress_batch(dtype, interp, static_cast<BatchC<T> *>(ent_dev.p) + ln.off,
+                                                ln.nf, ln.items, ctx->stream),
+              "level kernel launch");
+  for (int i = 0; i < n; ++i) {
+    ipc_stream *s = ss[i];
+    hip_check(ctx, launch_rows_reduce(lr[i], rows_p, o[i].errq, o[i].maxabs_bits, o[i].sizes, ctx->stream),
+              "row reduction launch");
+    const uint64_t nc = uint64_t(s->meta.sched.n_chunks);
+    const size_t cap = size_t(o[i].out_cap);
+    s->out_gchunk = dev_alloc(ctx, 8 * cap);
+    s->out_local = dev_alloc(ctx, 4 * cap);
+    s->out_bits = dev_alloc(ctx, 8 * cap);
+    s->out_start = dev_alloc(ctx, 4 * (nc + 1));
+    const size_t nb = (nc + 1 + 1023) / 1024;
+    uint32_t *cnt = static_cast<uint32_t *>(
+        ensure_ws(ctx, ctx->ws_cnt, ctx->ws_cnt_bytes, 4 * (nc + 1) + 4 * (nb + 1)));
+    hip_check(ctx, launch_outlier_index(static_cast<const OutlierRec *>(o[i].out_recs), o[i].n_out, cap,
+                                        static_cast<const PassArgs *>(args_dev.p) + args_off[i], nc,
+                                        static_cast<uint32_t *>(s->out_start.p), cnt, cnt + (nc + 1),
+                                        static_cast<uint64_t *>(s->out_gchunk.p),
+                                        static_cast<uint32_t *>(s->out_local.p),
+                                        static_cast<uint64_t *>(s->out_bits.p), ctx->stream),
+              "outlier index launch");
+  }
+  if (ctx->host_summary_bytes < sum_off[n]) {
+    if (ctx->host_summary) (void)hipHostFree(ctx->host_summary);
+    ctx->host_summary = nullptr;
+    ctx->host_summary_bytes = 0;
+    hip_check(ctx, hipHostMalloc(&ctx->host_summary, sum_off[n], hipHostMallocDefault), "pinned alloc");
+    ctx->host_summary_bytes = sum_off[n];
+  }
+  char *hostp = static_cast<char *>(ctx->host_summary);
+  hip_check(ctx, hipMemcpyAsync(hostp, summary, sum_off[n], hipMemcpyDeviceToHost, ctx->stream), "copy");
+  hip_check(ctx, hipStreamSynchronize(ctx->stream), "compress");
+  for (int i = 0; i < n; ++i) {
+    uint64_t nout;
+    std::memcpy(&nout, hostp + sum_off[i], 8);
+    if (nout > o[i].out_cap) {
+      redo[i] = 1;
+      continue;
+    }
+    finish_stream(ss[i], hostp + sum_off[i], nout);
+  }
+  dev_free(ctx, ent_dev);
+  dev_free(ctx, args_dev);
+  for (DevBuf &b : g) dev_free(ctx, b);
+}
+
+// Retrieval of n fused 3-D streams (same dtype and interpolation) with one
+// launch per level over all of them; plans given, fields allocated by the
+// caller of this helper.
+template <typename T>
+void retrieve_batch_fused(ipc_ctx *ctx, const std::vector<const ipc_stream *> &ss,
+                          const std::vector<std::vector<int>> &plans, const std::vector<void *> &out) {
+  const int n = int(ss.size());
+  const int dtype = ss[0]->meta.dtype, interp = ss[0]->meta.interp;
+  const size_t isz = sizeof(T);
+  std::vector<DevBuf> g(2 * n);
+  std::vector<RetrieveIn> in(n);
+  int Kmax = 0;
+  for (int i = 0; i < n; ++i) {
+    const ipc_stream *s = ss[i];
+    const Schedule &sc = s->meta.sched;
+    Kmax = std::max(Kmax, sc.K);
+    size_t need[2] = {8, 8};
+    for (int j = 1; j <= sc.K; ++j)
+      need[j & 1] = std::max(need[j & 1], size_t(coarse_points(sc, j)) * isz);
+    g[2 * i] = dev_alloc(ctx, need[0]);
+    g[2 * i + 1] = dev_alloc(ctx, need[1]);
+    RetrieveIn &r = in[i];
+    r.payload = static_cast<const uint32_t *>(s->payload.p);
+    r.masks = static_cast<const uint32_t *>(s->masks.p);
+    r.chunk_off = s->packed ? static_cast<const uint64_t *>(s->chunk_off.p) : nullptr;
+    r.out_gchunk = static_cast<const uint64_t *>(s->out_gchunk.p);
+    r.out_local = static_cast<const uint32_t *>(s->out_local.p);
+    r.out_bits = static_cast<const uint64_t *>(s->out_bits.p);
+    r.out_start = static_cast<const uint32_t *>(s->out_start.p);
+    r.n_out = s->meta.n_outliers;
+    r.zero = static_cast<const uint32_t *>(ctx->dev_zero);
+  }
+  std::vector<BatchR<T>> ent;
+  struct Launch { size_t off; int nf; uint32_t items; };
+  std::vector<Launch> launches;
+  const int64_t fill = IPC_WG_PER_CU_R * int64_t(ctx->n_cu);
+  for (int l = Kmax; l >= 1; --l) {
+    Launch ln{ent.size(), 0, 0};
+    for (int i = 0; i < n; ++i) {
+      const Schedule &sc = ss[i]->meta.sched;
+      if (l > sc.K) continue;
+      Level3Args La = level3_args(sc, l, fill);
+      BatchR<T> e;
+      std::memset(&e, 0, sizeof(e));
+      e.L = La;
+      e.gin = static_cast<const T *>(g[2 * i + (l & 1)].p);
+      e.gout = l > 1 ? static_cast<T *>(g[2 * i + ((l - 1) & 1)].p) : static_cast<T *>(out[i]);
+      e.in = in[i];
+      for (int p = 0; p < 3; ++p) e.disc[p] = plans[i][La.pass_index[p]];
+      e.two_eb = T(2.0 * ss[i]->meta.eb);
+      e.item0 = ln.items;
+      ent.push_back(e);
+      ++ln.nf;
+      ln.items += uint32_t(level3_wgs(La));
+    }
+    launches.push_back(ln);
+  }
+  DevBuf ent_dev = dev_alloc(ctx, ent.size() * sizeof(BatchR<T>));
+  hip_check(ctx, hipMemcpyAsync(ent_dev.p, ent.data(), ent.size() * sizeof(BatchR<T>),
+                                hipMemcpyHostToDevice, ctx->stream), "upload");
+  for (int i = 0; i < n; ++i) {
+    const Schedule &sc = ss[i]->meta.sched;
+    hip_check(ctx, launch_anchor3_retrieve(dtype, anchor3_args(sc), g[2 * i + (sc.K & 1)].p, in[i],
+                                           ss[i]->meta.eb, ctx->stream),
+              "anchor kernel launch");
+  }
+  for (const Launch &ln : launches)
+    hip_check(ctx, launch_level3_retrieve_batch(dtype, interp, static_cast<BatchR<T> *>(ent_dev.p) + ln.off,
+                                                ln.nf, ln.items, ctx->stream),
+              "level kernel launch");
+  hip_check(ctx, hipStreamSynchronize(ctx->stream), "retrieve");
+  dev_free(ctx, ent_dev);
+  for (DevBuf &b : g) dev_free(ctx, b);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
@@ -633,39 +942,12 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
   s->ctx = ctx;
   ipc_status st = guarded(ctx, [&] {
     hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
-    int64_t d64[3];
-    for (int j = 0; j < ndim; ++j) d64[j] = int64_t(dims[j]);
-    int cl[3] = {0, 0, 0};
-    if (opts)
-      for (int j = 0; j < ndim; ++j) cl[j] = opts->chunk_log2[j];
+    setup_stream(ctx, s, dims, ndim, dtype, interp, abs_eb, opts);
     StreamMeta &m = s->meta;
-    std::string e;
-    if (!make_schedule(d64, ndim, cl, m.sched, e)) {
-      set_err(ctx, e);
-      throw Fail{IPC_EINVAL};
-    }
-    if (!chunks_supported(m.sched, e)) {
-      set_err(ctx, e);
-      throw Fail{IPC_EUNSUPPORTED};
-    }
-    int np = opts ? opts->nonprog_levels : 0;
-    if (np < 0 || np > m.sched.K) {
-      set_err(ctx, "nonprog_levels out of range");
-      throw Fail{IPC_EINVAL};
-    }
-    m.dtype = dtype;
-    m.interp = interp;
-    m.nonprog_levels = np;
-    m.eb = abs_eb;
-    m.qmax = dtype == IPC_F32 ? QMAX_F32 : QMAX_F64;
     const Schedule &sc = m.sched;
     const int P = int(sc.passes.size());
     const size_t isz = dtype == IPC_F32 ? 4 : 8;
     const size_t nbytes = size_t(sc.n_points) * isz;
-    for (const PassGeom &p : sc.passes) s->args.push_back(make_args(sc, p));
-
-    s->payload = dev_alloc(ctx, size_t(sc.slot_words) * 4);
-    s->masks = dev_alloc(ctx, size_t(sc.n_chunks) * 4);
     const bool fused = fused3(sc);
     void *xh = nullptr;
     if (fused)
@@ -689,7 +971,7 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
     int64_t max_chunks = 0;
     for (const PassGeom &g : sc.passes) max_chunks = std::max(max_chunks, g.n_chunks);
     // summary: n_out, maxabs bits, sizes [P][32] u64, errq [P][33] u32
-    size_t sum_bytes = 16 + size_t(P) * 32 * 8 + size_t(P) * 33 * 4;
+    size_t sum_bytes = summary_bytes(P);
     char *summary = static_cast<char *>(ensure_ws(ctx, ctx->ws_summary, ctx->ws_summary_bytes, sum_bytes));
     size_t cap = std::max<size_t>(4096, size_t(sc.n_points / 1024));
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -807,22 +1089,7 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
         set_err(ctx, "outlier buffer overflow");
         throw Fail{IPC_EHIP};
       }
-      uint64_t mb;
-      std::memcpy(&mb, hostp + 8, 8);
-      std::memcpy(&m.maxabs, &mb, 8);
-      m.errq.resize(size_t(P) * 33);
-      std::memcpy(m.errq.data(), hostp + 16 + size_t(P) * 32 * 8, m.errq.size() * 4);
-      std::vector<uint64_t> sz(size_t(P) * 32);
-      std::memcpy(sz.data(), hostp + 16, sz.size() * 8);
-      m.outliers.clear();
-      m.n_outliers = nout;
-      s->host_outliers_valid = nout == 0;
-      uint64_t words = 0;
-      for (uint64_t v : sz) words += v / 4;
-      m.payload_words = words;
-      m.serialized_bytes = serialized_size(m);
-      // planner tables from the device-computed plane sizes (no mask copy needed)
-      s->tables = plan_tables_from_sizes(m, sz);
+      finish_stream(s, hostp, nout);
       break;
     }
   });
@@ -1148,6 +1415,166 @@ ipc_status ipc_plan_host(const void *stream_bytes, uint64_t nbytes, ipc_target t
   } catch (...) {
     return IPC_ENOMEM;
   }
+}
+
+ipc_status ipc_compress_batch(ipc_ctx *ctx, uint32_t n, const void *const *fields_dev,
+                              const uint64_t *dims, int ndim, int dtype, const double *abs_eb,
+                              const ipc_options *opts, ipc_stream **out) {
+  if (!out) return IPC_EINVAL;
+  for (uint32_t i = 0; i < n; ++i) out[i] = nullptr;
+  if (!ctx || n == 0 || !fields_dev || !dims || !abs_eb) return IPC_EINVAL;
+  if (ndim < 1 || ndim > 3 || (dtype != IPC_F32 && dtype != IPC_F64)) {
+    set_err(ctx, "invalid argument to ipc_compress_batch");
+    return IPC_EINVAL;
+  }
+  int interp = opts ? opts->interp : IPC_CUBIC;
+  bool fused = n > 1 && (interp == IPC_LINEAR || interp == IPC_CUBIC);
+  for (uint32_t i = 0; i < n; ++i) {
+    if (!fields_dev[i] || !(std::isfinite(abs_eb[i]) && abs_eb[i] > 0)) {
+      set_err(ctx, "invalid field or error bound in ipc_compress_batch");
+      return IPC_EINVAL;
+    }
+    fused = fused && fused_dims(dims + size_t(i) * ndim, ndim, opts);
+  }
+  auto undo = [&](uint32_t upto) {
+    for (uint32_t j = 0; j < upto; ++j) {
+      ipc_stream_free(out[j]);
+      out[j] = nullptr;
+    }
+  };
+  if (!fused) {
+    // one call per field (other dimensionalities, chunk shapes, or one field)
+    for (uint32_t i = 0; i < n; ++i) {
+      ipc_status st = ipc_compress(ctx, fields_dev[i], dims + size_t(i) * ndim, ndim, dtype, abs_eb[i],
+                                   opts, &out[i]);
+      if (st != IPC_OK) {
+        undo(i);
+        return st;
+      }
+    }
+    return IPC_OK;
+  }
+  std::vector<ipc_stream *> ss(n, nullptr);
+  std::vector<char> redo(n, 0);
+  ipc_status st = guarded(ctx, [&] {
+    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    for (uint32_t i = 0; i < n; ++i) {
+      ss[i] = new ipc_stream();
+      ss[i]->ctx = ctx;
+      setup_stream(ctx, ss[i], dims + size_t(i) * 3, 3, dtype, interp, abs_eb[i], opts);
+    }
+    if (dtype == IPC_F32)
+      compress_batch_fused<float>(ctx, ss, fields_dev, abs_eb, redo);
+    else
+      compress_batch_fused<double>(ctx, ss, fields_dev, abs_eb, redo);
+  });
+  if (st != IPC_OK) {
+    for (ipc_stream *s : ss)
+      if (s) {
+        free_stream_bufs(s);
+        delete s;
+      }
+    return st;
+  }
+  for (uint32_t i = 0; i < n; ++i) out[i] = ss[i];
+  // fields whose outliers overflowed the batch's record capacity: again alone
+  for (uint32_t i = 0; i < n; ++i) {
+    if (!redo[i]) continue;
+    ipc_stream_free(out[i]);
+    out[i] = nullptr;
+    ipc_status st2 = ipc_compress(ctx, fields_dev[i], dims + size_t(i) * 3, 3, dtype, abs_eb[i], opts,
+                                  &out[i]);
+    if (st2 != IPC_OK) {
+      undo(n);
+      return st2;
+    }
+  }
+  return IPC_OK;
+}
+
+ipc_status ipc_retrieve_batch(ipc_ctx *ctx, uint32_t n, const ipc_stream *const *streams,
+                              const ipc_target *targets, ipc_state **out, ipc_info *info) {
+  if (!out) return IPC_EINVAL;
+  for (uint32_t i = 0; i < n; ++i) out[i] = nullptr;
+  if (!ctx || n == 0 || !streams || !targets) return IPC_EINVAL;
+  bool fused = n > 1;
+  for (uint32_t i = 0; i < n; ++i) {
+    const ipc_stream *s = streams[i];
+    if (!s) return IPC_EINVAL;
+    if (s->ctx != ctx) {
+      set_err(ctx, "stream belongs to another context");
+      return IPC_ESTATE;
+    }
+    if (!valid_target(targets[i])) {
+      set_err(ctx, "target value must be finite and > 0");
+      return IPC_EINVAL;
+    }
+    fused = fused && fused3(s->meta.sched) && s->meta.dtype == streams[0]->meta.dtype &&
+            s->meta.interp == streams[0]->meta.interp;
+  }
+  if (!fused) {
+    for (uint32_t i = 0; i < n; ++i) {
+      ipc_status st = ipc_retrieve(ctx, streams[i], targets[i], &out[i], info ? info + i : nullptr);
+      if (st != IPC_OK) {
+        for (uint32_t j = 0; j < i; ++j) {
+          ipc_state_free(out[j]);
+          out[j] = nullptr;
+        }
+        return st;
+      }
+    }
+    return IPC_OK;
+  }
+  std::vector<const ipc_stream *> ss(streams, streams + n);
+  std::vector<PlanResult> prs(n);
+  std::vector<float> tplan(n);
+  std::vector<std::vector<int>> plans(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    auto t0 = std::chrono::steady_clock::now();
+    prs[i] = plan_request(ss[i]->tables, targets[i].kind, targets[i].value, nullptr);
+    tplan[i] = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    plans[i] = prs[i].plan;
+  }
+  std::vector<ipc_state *> sts(n, nullptr);
+  ipc_status st = guarded(ctx, [&] {
+    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    std::vector<void *> fields(n);
+    for (uint32_t i = 0; i < n; ++i) {
+      sts[i] = new ipc_state();
+      sts[i]->ctx = ctx;
+      sts[i]->stream = ss[i];
+      sts[i]->plan = plans[i];
+      sts[i]->bound = prs[i].bound;
+      const size_t isz = ss[i]->meta.dtype == IPC_F32 ? 4 : 8;
+      sts[i]->field = dev_alloc(ctx, size_t(ss[i]->meta.sched.n_points) * isz);
+      fields[i] = sts[i]->field.p;
+    }
+    hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
+    if (ss[0]->meta.dtype == IPC_F32)
+      retrieve_batch_fused<float>(ctx, ss, plans, fields);
+    else
+      retrieve_batch_fused<double>(ctx, ss, plans, fields);
+    hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
+    hip_check(ctx, hipEventSynchronize(ctx->ev1), "retrieve");
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    if (info)
+      for (uint32_t i = 0; i < n; ++i) {
+        std::vector<int> none(plans[i].size(), 32);
+        fill_info(ss[i], plans[i], prs[i].bound, prs[i].flags, plane_bytes_between(ss[i], plans[i], none),
+                  tplan[i], ms, info + i);
+      }
+  });
+  if (st != IPC_OK) {
+    for (ipc_state *t : sts)
+      if (t) {
+        dev_free(ctx, t->field);
+        delete t;
+      }
+    return st;
+  }
+  for (uint32_t i = 0; i < n; ++i) out[i] = sts[i];
+  return IPC_OK;
 }
 
 }  // extern "C"

@@ -91,6 +91,39 @@ struct Level3Args {
   uint32_t row_base;     // compression: row of the launch's first workgroup in wg_rows
 };
 
+// One field of a batched level launch (compression): its level, buffers,
+// outputs and quantizer constants; item0 = its first work item (column
+// segment) in the launch, fields in increasing item0.
+template <typename T>
+struct BatchC {
+  Level3Args L;
+  const T *x;
+  const T *gin;
+  T *gout;
+  CompressOut o;
+  double eb;
+  T two_eb, inv, qmax;
+  uint32_t item0;
+};
+// ... and retrieval (disc: planes discarded per pass A, B, C)
+template <typename T>
+struct BatchR {
+  Level3Args L;
+  const T *gin;
+  T *gout;
+  RetrieveIn in;
+  int32_t disc[3];
+  T two_eb;
+  uint32_t item0;
+};
+// Batched level launches over a work list: one workgroup per column segment
+// of the nf fields in `batch_dev` (device array of BatchC<T> / BatchR<T>,
+// n_items segments in all).
+hipError_t launch_level3_compress_batch(int dtype, int interp, const void *batch_dev, int nf,
+                                        uint32_t n_items, hipStream_t s);
+hipError_t launch_level3_retrieve_batch(int dtype, int interp, const void *batch_dev, int nf,
+                                        uint32_t n_items, hipStream_t s);
+
 hipError_t launch_level3_compress(int dtype, int interp, const Level3Args &L, const void *x,
                                   const void *gin, void *gout, double eb, const CompressOut &o,
                                   hipStream_t s);

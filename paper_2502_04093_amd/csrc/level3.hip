@@ -605,23 +605,24 @@ struct BitsOf<double> {
 //            |q| (one max per code); chunks holding longer codes are scanned
 //            exactly for b >= 14 once their codes are buffered (errq_hi).
 
+// One column segment (tile tx, ty, chunk rows zs * zseg ..) of a level:
+// the body of the level launch and of the batched launch.  `row` is the
+// workgroup-row index of the segment.
 template <typename T, int INTERP>
-__global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *__restrict__ x,
-                                                          const T *__restrict__ gin, T *gout,
-                                                          double eb_arg, T two_eb_arg, T inv_arg,
-                                                          T qmax_arg, CompressOut o) {
+__device__ __forceinline__ void level3_compress_body(const Level3Args &L, const T *__restrict__ x,
+                                                     const T *__restrict__ gin, T *gout,
+                                                     double eb_arg, T two_eb_arg, T inv_arg,
+                                                     T qmax_arg, const CompressOut &o, int tx, int ty,
+                                                     int zs, uint32_t row_index, SharedC<T> &S) {
   using F = F3<T>;
   using BT = BitsOf<T>;
   using U = typename BT::U;
-  __shared__ SharedC<T> S;
   // the quantizer's constants, held in vector registers: as scalars they are
   // spilled and re-read with a lane read at every use
   double eb = eb_arg;
   T two_eb = two_eb_arg, inv = inv_arg, qmax = qmax_arg;
   asm volatile("" : "+v"(eb), "+v"(two_eb), "+v"(inv), "+v"(qmax));
   const int tid0 = threadIdx.x;
-  int tx, ty, zs;
-  block_tile(L, tx, ty, zs);
   const int x0 = tx * TX, y0 = ty * TY;
   const int m0 = zs * L.zseg;
   const int m1 = m0 + L.zseg < L.tiles_z ? m0 + L.zseg : L.tiles_z;
@@ -971,7 +972,7 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
     if (wave < 3) errq_fold(S.bm[wave], S.eq[wave], lane);
     __syncthreads();
   }
-  uint32_t *row = o.wg_rows + size_t(L.row_base + blockIdx.x) * WG_ROW;
+  uint32_t *row = o.wg_rows + size_t(row_index) * WG_ROW;
   if (tid0 < 3 * 33) {
     const int p = tid0 / 33, b = tid0 - p * 33;
     uint32_t val = b > 0 ? S.eq[p][b] : 0u;
@@ -985,6 +986,58 @@ __global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *
     row[ROW_SIZES + (tid0 < 32 ? 64 + tid0 : tid0)] = szCB;
     if (tid0 < 32) row[ROW_SIZES + tid0] = szA;
   }
+}
+
+template <typename T, int INTERP>
+__global__ __launch_bounds__(WG3) void k_level3_compress(Level3Args L, const T *__restrict__ x,
+                                                          const T *__restrict__ gin, T *gout,
+                                                          double eb, T two_eb, T inv, T qmax,
+                                                          CompressOut o) {
+  __shared__ SharedC<T> S;
+  int tx, ty, zs;
+  block_tile(L, tx, ty, zs);
+  level3_compress_body<T, INTERP>(L, x, gin, gout, eb, two_eb, inv, qmax, o, tx, ty, zs,
+                                  L.row_base + blockIdx.x, S);
+}
+
+// Column segment `it` of a level launch, in plain order (tx fastest)
+__device__ __forceinline__ void item_tile(const Level3Args &L, uint32_t it, int &tx, int &ty, int &zs) {
+  tx = int(it % uint32_t(L.tiles_x));
+  const uint32_t r = it / uint32_t(L.tiles_x);
+  ty = int(r % uint32_t(L.tiles_y));
+  zs = int(r / uint32_t(L.tiles_y));
+}
+
+// Work item of this workgroup in a work-list launch: consecutive workgroup
+// ids are dealt round-robin to the 8 XCDs, so (as in block_tile) each XCD
+// takes a contiguous run of items, whose halos overlap, in its own L2
+__device__ __forceinline__ uint32_t work_item() {
+  const uint32_t nb = gridDim.x, b = blockIdx.x;
+  return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+}
+
+// the field of work item `it` (fields in item order, a short uniform scan)
+template <typename B>
+__device__ __forceinline__ int item_field(const B *__restrict__ bf, int nf, uint32_t it) {
+  int f = 0;
+  while (f + 1 < nf && bf[f + 1].item0 <= it) ++f;
+  return f;
+}
+
+// Batched compression of one level of several fields: one workgroup per
+// column segment of the work list (the fields' segments in order).  The
+// fields' launch arguments are read from memory.
+template <typename T, int INTERP>
+__global__ __launch_bounds__(WG3, 4) void k_level3_compress_batch(const BatchC<T> *__restrict__ bf,
+                                                                   int nf) {
+  __shared__ SharedC<T> S;
+  const uint32_t it = work_item();
+  const BatchC<T> &b = bf[item_field(bf, nf, it)];
+  const uint32_t li = it - b.item0;
+  int tx, ty, zs;
+  item_tile(b.L, li, tx, ty, zs);
+  level3_compress_body<T, INTERP>(b.L, b.x, b.gin, b.gout, b.eb, b.two_eb, b.inv, b.qmax, b.o, tx,
+                                  ty, zs, b.L.row_base + li, S);
 }
 
 // 32 plane words (p[k] = plane k of 32 codes, absent planes 0) -> the 32
@@ -1037,16 +1090,14 @@ __device__ __forceinline__ void load_planes(const RetrieveIn &in, uint64_t first
 }
 
 template <typename T, int INTERP>
-__global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *__restrict__ gin,
-                                                          T *gout, int discA, int discB, int discC,
-                                                          RetrieveIn in, T two_eb_arg) {
+__device__ __forceinline__ void level3_retrieve_body(const Level3Args &L, const T *__restrict__ gin,
+                                                     T *gout, int discA, int discB, int discC,
+                                                     const RetrieveIn &in, T two_eb_arg, int tx,
+                                                     int ty, int zs, Shared3<T> &S) {
   using F = F3<T>;
-  __shared__ Shared3<T> S;
-  T two_eb = two_eb_arg;  // in a vector register (see k_level3_compress)
+  T two_eb = two_eb_arg;  // in a vector register (see level3_compress_body)
   asm volatile("" : "+v"(two_eb));
   const int tid0 = threadIdx.x;
-  int tx, ty, zs;
-  block_tile(L, tx, ty, zs);
   const int x0 = tx * TX, y0 = ty * TY;
   const int m0 = zs * L.zseg;
   const int m1 = m0 + L.zseg < L.tiles_z ? m0 + L.zseg : L.tiles_z;
@@ -1413,6 +1464,30 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
   }
 }
 
+template <typename T, int INTERP>
+__global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *__restrict__ gin,
+                                                          T *gout, int discA, int discB, int discC,
+                                                          RetrieveIn in, T two_eb) {
+  __shared__ Shared3<T> S;
+  int tx, ty, zs;
+  block_tile(L, tx, ty, zs);
+  level3_retrieve_body<T, INTERP>(L, gin, gout, discA, discB, discC, in, two_eb, tx, ty, zs, S);
+}
+
+// Batched retrieval of one level of several fields (work list, as
+// k_level3_compress_batch)
+template <typename T, int INTERP>
+__global__ __launch_bounds__(WG3, 5) void k_level3_retrieve_batch(const BatchR<T> *__restrict__ bf,
+                                                                   int nf) {
+  __shared__ Shared3<T> S;
+  const uint32_t it = work_item();
+  const BatchR<T> &b = bf[item_field(bf, nf, it)];
+  int tx, ty, zs;
+  item_tile(b.L, it - b.item0, tx, ty, zs);
+  level3_retrieve_body<T, INTERP>(b.L, b.gin, b.gout, b.disc[0], b.disc[1], b.disc[2], b.in,
+                                  b.two_eb, tx, ty, zs, S);
+}
+
 // anchors of a fused compression: quantize against 0 into the compact coarse grid
 template <typename T>
 __global__ void k_anchor3_compress(Level3Args L, const T *__restrict__ x, T *gout, double eb,
@@ -1585,6 +1660,54 @@ hipError_t launch_rows_reduce(const LevelRows &lr, const uint32_t *rows, uint32_
   if (lr.n == 0 || most == 0) return hipSuccess;
   dim3 grid(uint32_t(lr.n), 3, (most + RR_ROWS - 1) / RR_ROWS);
   hipLaunchKernelGGL(k_rows_reduce, grid, dim3(256), 0, stream, lr, rows, errq, maxabs_bits, sizes);
+  return hipGetLastError();
+}
+
+hipError_t launch_level3_compress_batch(int dtype, int interp, const void *batch_dev, int nf,
+                                        uint32_t n_items, hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  const dim3 grid(n_items);
+  if (dtype == IPC_F32) {
+    const BatchC<float> *b = static_cast<const BatchC<float> *>(batch_dev);
+    if (interp == IPC_LINEAR)
+      hipLaunchKernelGGL((k_level3_compress_batch<float, IPC_LINEAR>), grid, dim3(WG3), 0, s, b,
+                         nf);
+    else
+      hipLaunchKernelGGL((k_level3_compress_batch<float, IPC_CUBIC>), grid, dim3(WG3), 0, s, b,
+                         nf);
+  } else {
+    const BatchC<double> *b = static_cast<const BatchC<double> *>(batch_dev);
+    if (interp == IPC_LINEAR)
+      hipLaunchKernelGGL((k_level3_compress_batch<double, IPC_LINEAR>), grid, dim3(WG3), 0, s,
+                         b, nf);
+    else
+      hipLaunchKernelGGL((k_level3_compress_batch<double, IPC_CUBIC>), grid, dim3(WG3), 0, s,
+                         b, nf);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_level3_retrieve_batch(int dtype, int interp, const void *batch_dev, int nf,
+                                        uint32_t n_items, hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  const dim3 grid(n_items);
+  if (dtype == IPC_F32) {
+    const BatchR<float> *b = static_cast<const BatchR<float> *>(batch_dev);
+    if (interp == IPC_LINEAR)
+      hipLaunchKernelGGL((k_level3_retrieve_batch<float, IPC_LINEAR>), grid, dim3(WG3), 0, s, b,
+                         nf);
+    else
+      hipLaunchKernelGGL((k_level3_retrieve_batch<float, IPC_CUBIC>), grid, dim3(WG3), 0, s, b,
+                         nf);
+  } else {
+    const BatchR<double> *b = static_cast<const BatchR<double> *>(batch_dev);
+    if (interp == IPC_LINEAR)
+      hipLaunchKernelGGL((k_level3_retrieve_batch<double, IPC_LINEAR>), grid, dim3(WG3), 0, s,
+                         b, nf);
+    else
+      hipLaunchKernelGGL((k_level3_retrieve_batch<double, IPC_CUBIC>), grid, dim3(WG3), 0, s,
+                         b, nf);
+  }
   return hipGetLastError();
 }
 
