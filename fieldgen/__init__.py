@@ -203,3 +203,10 @@ def grf_torch(shape, amp_exponent: float, seed: int, device="cuda:0"):
     f -= f.mean()
     f /= f.std()
     return f.contiguous()
+
+
+def lognormal_torch(shape=(256, 384, 384), seed: int = 0, device="cuda:0"):
+    """:func:`lognormal` drawn on the GPU (float64 result) from :func:`grf_torch`."""
+    import torch
+    g = grf_torch(shape, -1.0, seed, device=device).to(torch.float64)
+    return torch.exp(1.5 * g)

@@ -167,6 +167,20 @@ ipc_status ipc_compress_batch(ipc_ctx *ctx, uint32_t n, const void *const *field
 ipc_status ipc_retrieve_batch(ipc_ctx *ctx, uint32_t n, const ipc_stream *const *streams,
                               const ipc_target *targets, ipc_state **out, ipc_info *info);
 
+/* Autotuner (beyond the paper): compresses and fully retrieves the given
+ * representative field once per candidate column length (chunk rows per
+ * workgroup of the fused 3-D level launches: 16, 8, 4, 2, 1; every level at
+ * once, twice) and keeps, per level and direction, the fastest launch for
+ * this (shape, dtype, interpolation) in the context; later calls on that
+ * shape, batched ones included, use the choices.  Outputs never depend on
+ * the column length.  zseg_c / zseg_r (NULL, or `capacity` entries indexed
+ * by level; 0 = no fused launch) receive the choices.  IPC_EUNSUPPORTED for
+ * shapes without fused launches.  ipc_autotune_clear forgets every choice. */
+ipc_status ipc_autotune(ipc_ctx *ctx, const void *field_dev, const uint64_t *dims, int ndim,
+                        int dtype, double abs_eb, const ipc_options *opts, int32_t *zseg_c,
+                        int32_t *zseg_r, uint32_t capacity);
+ipc_status ipc_autotune_clear(ipc_ctx *ctx);
+
 /* Host-only planner on a serialized stream (no GPU needed): the plan the
  * library would choose for `target`, optionally restricted to b <= limit[s]
  * (refinement).  plan_out has room for the stream's pass count. */

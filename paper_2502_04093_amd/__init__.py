@@ -82,6 +82,9 @@ SIGNATURES = {
                                    P(c_double), P(ipc_options), P(c_void_p)]),
     "ipc_retrieve_batch": (c_int, [c_void_p, c_uint32, P(c_void_p), P(ipc_target), P(c_void_p),
                                    P(ipc_info)]),
+    "ipc_autotune": (c_int, [c_void_p, c_void_p, P(c_uint64), c_int, c_int, c_double,
+                             P(ipc_options), P(ctypes.c_int32), P(ctypes.c_int32), c_uint32]),
+    "ipc_autotune_clear": (c_int, [c_void_p]),
     "ipc_ctx_set_profiling": (c_int, [c_void_p, c_int, c_int]),
     "ipc_ctx_pass_times": (c_int, [c_void_p, P(c_float), c_uint32, P(c_uint32)]),
     "ipc_status_string": (ctypes.c_char_p, [c_int]),
@@ -206,6 +209,26 @@ class Context:
         _check(lib().ipc_compress(self._p, c_void_p(field.data_ptr()), dims, field.dim(), dt,
                                   float(eb), ctypes.byref(opts), ctypes.byref(out)), self._p)
         return Stream(self, out, tuple(field.shape), field.dtype)
+
+    def autotune(self, field, eb: float, interp: str = "cubic"):
+        """Tune the fused launches for this field's shape, dtype and
+        interpolation; returns the chosen column lengths per level
+        (compression, retrieval; index = level)."""
+        import torch
+        if not (field.is_cuda and field.is_contiguous()):
+            raise ValueError("field must be a contiguous device tensor")
+        dims = (c_uint64 * field.dim())(*field.shape)
+        opts = ipc_options()
+        opts.interp = IPC_CUBIC if interp == "cubic" else IPC_LINEAR
+        zc = (ctypes.c_int32 * 32)()
+        zr = (ctypes.c_int32 * 32)()
+        dt = IPC_F32 if field.dtype == torch.float32 else IPC_F64
+        _check(lib().ipc_autotune(self._p, c_void_p(field.data_ptr()), dims, field.dim(), dt,
+                                  float(eb), ctypes.byref(opts), zc, zr, 32), self._p)
+        return list(zc), list(zr)
+
+    def autotune_clear(self):
+        _check(lib().ipc_autotune_clear(self._p), self._p)
 
     def compress_batch(self, fields, ebs, interp: str = "cubic", nonprog_levels: int = 0):
         """Compress several device tensors of one dtype and rank in one call

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <new>
 #include <string>
 #include <vector>
@@ -20,8 +21,24 @@ using namespace ipc;
 
 // ------------------------------------------------------------------ objects
 
+// Tuned column lengths (chunk rows per workgroup) of the fused level
+// launches, per field shape, dtype and interpolation; 0 = the default rule
+struct TuneKey {
+  int64_t d[3];
+  int dtype, interp;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(d[0], d[1], d[2], dtype, interp) < std::tie(o.d[0], o.d[1], o.d[2], o.dtype, o.interp);
+  }
+};
+struct TuneVal {
+  int32_t zseg_c[32];  // compression, by level
+  int32_t zseg_r[32];  // retrieval, by level
+};
+
 struct ipc_ctx {
   int device = 0;
+  std::map<TuneKey, TuneVal> tuned;     // autotuner results
+  int forced_zseg = 0;                  // while tuning: every level uses this
   void *dev_zero = nullptr;             // 256 zero bytes on the device
   int n_cu = 256;                       // compute units of the device
   hipStream_t stream = nullptr;
@@ -423,6 +440,20 @@ int64_t level3_wgs(const Level3Args &A) {
   return int64_t(A.tiles_x) * A.tiles_y * ((A.tiles_z + A.zseg - 1) / A.zseg);
 }
 
+// Arguments of the fused launch of level l of a stream, with the column
+// length the autotuner chose for this shape (or the one being tried)
+Level3Args level_args(const ipc_ctx *ctx, const StreamMeta &m, int l, bool compress) {
+  Level3Args La = level3_args(m.sched, l, (compress ? IPC_WG_PER_CU_C : IPC_WG_PER_CU_R) * int64_t(ctx->n_cu));
+  int z = ctx->forced_zseg;
+  if (z == 0 && !ctx->tuned.empty() && l < 32) {
+    TuneKey k{{m.sched.dims3[0], m.sched.dims3[1], m.sched.dims3[2]}, m.dtype, m.interp};
+    auto it = ctx->tuned.find(k);
+    if (it != ctx->tuned.end()) z = compress ? it->second.zseg_c[l] : it->second.zseg_r[l];
+  }
+  if (z > 0) La.zseg = z;
+  return La;
+}
+
 // compact coarse-grid buffers: G_j lives in ws_g[j & 1]
 void ensure_coarse(ipc_ctx *ctx, const Schedule &s, size_t isz) {
   size_t need[2] = {0, 0};
@@ -468,7 +499,7 @@ void run_retrieve(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &pla
                 "gather kernel launch");
     }
     for (int l = l_start; l >= 1; --l) {
-      Level3Args La = level3_args(sc, l, IPC_WG_PER_CU_R * int64_t(ctx->n_cu));
+      Level3Args La = level_args(ctx, s->meta, l, false);
       int disc[3];
       for (int p = 0; p < 3; ++p) disc[p] = plan[La.pass_index[p]];
       int pc = int(La.pass_index[2]);
@@ -633,13 +664,12 @@ void compress_batch_fused(ipc_ctx *ctx, std::vector<ipc_stream *> &ss,
   std::vector<LevelRows> lr(n);
   for (LevelRows &r : lr) std::memset(&r, 0, sizeof(r));
   uint32_t rows = 0;
-  const int64_t fill = IPC_WG_PER_CU_C * int64_t(ctx->n_cu);
   for (int l = Kmax; l >= 1; --l) {
     Launch ln{ent.size(), 0, 0};
     for (int i = 0; i < n; ++i) {
       const Schedule &sc = ss[i]->meta.sched;
       if (l > sc.K) continue;
-      Level3Args La = level3_args(sc, l, fill);
+      Level3Args La = level_args(ctx, ss[i]->meta, l, true);
       La.row_base = rows;
       const uint32_t items = uint32_t(level3_wgs(La));
       LevelRows &r = lr[i];
@@ -767,13 +797,12 @@ void retrieve_batch_fused(ipc_ctx *ctx, const std::vector<const ipc_stream *> &s
   std::vector<BatchR<T>> ent;
   struct Launch { size_t off; int nf; uint32_t items; };
   std::vector<Launch> launches;
-  const int64_t fill = IPC_WG_PER_CU_R * int64_t(ctx->n_cu);
   for (int l = Kmax; l >= 1; --l) {
     Launch ln{ent.size(), 0, 0};
     for (int i = 0; i < n; ++i) {
       const Schedule &sc = ss[i]->meta.sched;
       if (l > sc.K) continue;
-      Level3Args La = level3_args(sc, l, fill);
+      Level3Args La = level_args(ctx, ss[i]->meta, l, false);
       BatchR<T> e;
       std::memset(&e, 0, sizeof(e));
       e.L = La;
@@ -999,7 +1028,7 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
         std::memset(&lr, 0, sizeof(lr));
         uint32_t rows = 0;
         for (int l = K; l >= 1; --l) {
-          Level3Args La = level3_args(sc, l, IPC_WG_PER_CU_C * int64_t(ctx->n_cu));
+          Level3Args La = level_args(ctx, m, l, true);
           La.row_base = rows;
           if (lr.n >= MAX_LEVEL_LAUNCHES) {
             set_err(ctx, "too many levels for the fused kernels");
@@ -1574,6 +1603,86 @@ ipc_status ipc_retrieve_batch(ipc_ctx *ctx, uint32_t n, const ipc_stream *const 
     return st;
   }
   for (uint32_t i = 0; i < n; ++i) out[i] = sts[i];
+  return IPC_OK;
+}
+
+ipc_status ipc_autotune(ipc_ctx *ctx, const void *field_dev, const uint64_t *dims, int ndim,
+                        int dtype, double abs_eb, const ipc_options *opts, int32_t *zseg_c,
+                        int32_t *zseg_r, uint32_t capacity) {
+  if (!ctx || !field_dev || !dims) return IPC_EINVAL;
+  if (!fused_dims(dims, ndim, opts)) {
+    set_err(ctx, "no tunable launches for this shape (3-D fields with the default chunks only)");
+    return IPC_EUNSUPPORTED;
+  }
+  const bool prof = ctx->profiling;
+  const int only = ctx->prof_only;
+  ctx->profiling = true;
+  ctx->prof_only = -1;
+  const int cand[5] = {16, 8, 4, 2, 1};
+  float best_c[32], best_r[32];
+  int32_t zc[32], zr[32];
+  for (int l = 0; l < 32; ++l) {
+    best_c[l] = best_r[l] = 1e30f;
+    zc[l] = zr[l] = 0;
+  }
+  ipc_status st = IPC_OK;
+  int K = 0;
+  // every candidate column length for every level at once, twice; the
+  // fastest launch of each level wins (results do not depend on it)
+  for (int rep = 0; rep < 2 && st == IPC_OK; ++rep)
+    for (int c : cand) {
+      ctx->forced_zseg = c;
+      ipc_stream *s = nullptr;
+      st = ipc_compress(ctx, field_dev, dims, ndim, dtype, abs_eb, opts, &s);
+      if (st != IPC_OK) break;
+      const Schedule &sc = s->meta.sched;
+      K = sc.K;
+      std::vector<float> tc = ctx->pass_ms;
+      ipc_state *rs = nullptr;
+      ipc_target t;
+      t.kind = IPC_TARGET_EB;
+      t.value = abs_eb;
+      st = ipc_retrieve(ctx, s, t, &rs, nullptr);
+      if (st != IPC_OK) {
+        ipc_stream_free(s);
+        break;
+      }
+      std::vector<float> tr = ctx->pass_ms;
+      for (int l = 1; l <= sc.K && l < 32; ++l) {
+        const size_t slot = size_t(1 + (sc.K - l) * 3 + 2);
+        if (slot < tc.size() && tc[slot] > 0 && tc[slot] < best_c[l]) {
+          best_c[l] = tc[slot];
+          zc[l] = c;
+        }
+        if (slot < tr.size() && tr[slot] > 0 && tr[slot] < best_r[l]) {
+          best_r[l] = tr[slot];
+          zr[l] = c;
+        }
+      }
+      ipc_state_free(rs);
+      ipc_stream_free(s);
+    }
+  ctx->forced_zseg = 0;
+  ctx->profiling = prof;
+  ctx->prof_only = only;
+  if (st != IPC_OK) return st;
+  int64_t d64[3] = {1, 1, 1};
+  for (int j = 0; j < ndim; ++j) d64[3 - ndim + j] = int64_t(dims[j]);
+  TuneKey k{{d64[0], d64[1], d64[2]}, dtype, opts ? opts->interp : IPC_CUBIC};
+  TuneVal v;
+  std::memcpy(v.zseg_c, zc, sizeof(zc));
+  std::memcpy(v.zseg_r, zr, sizeof(zr));
+  ctx->tuned[k] = v;
+  for (uint32_t l = 0; l < capacity && l < 32; ++l) {
+    if (zseg_c) zseg_c[l] = int(l) <= K ? zc[l] : 0;
+    if (zseg_r) zseg_r[l] = int(l) <= K ? zr[l] : 0;
+  }
+  return IPC_OK;
+}
+
+ipc_status ipc_autotune_clear(ipc_ctx *ctx) {
+  if (!ctx) return IPC_EINVAL;
+  ctx->tuned.clear();
   return IPC_OK;
 }
 

@@ -114,3 +114,40 @@ def test_batch_argument_errors(ctx):
         ctx.compress_batch([x, x], [1e-3])
     with pytest.raises(pkg.IpcError):
         ctx.compress_batch([x, x], [1e-3, -1.0])
+
+
+def test_autotune_keeps_results(ctx):
+    """Tuned column lengths change launch shapes only: streams and
+    reconstructions stay byte-identical, single and batched."""
+    x = fieldgen.grf((130, 100, 260), -5.0 / 6.0, seed=12, dtype=np.float32)
+    y = fieldgen.grf((130, 100, 260), -5.0 / 6.0, seed=13, dtype=np.float32)
+    eb = 1e-4 * fieldgen.value_range(x)
+    d, dy = _dev(x), _dev(y)
+    ctx.autotune_clear()
+    s0 = ctx.compress(d, eb)
+    a = s0.to_bytes()
+    st0 = s0.retrieve(eb=10 * eb)
+    f0 = _bytes(st0.tensor())
+    zc, zr = ctx.autotune(d, eb)
+    levels = [l for l in range(1, 32) if zc[l]]
+    assert levels == list(range(1, len(levels) + 1)) and len(levels) >= 7
+    assert all(zc[l] in (1, 2, 4, 8, 16) and zr[l] in (1, 2, 4, 8, 16) for l in levels)
+    assert zc[0] == 0 and zr[0] == 0
+    s1 = ctx.compress(d, eb)
+    assert s1.to_bytes() == a
+    st1 = s1.retrieve(eb=10 * eb)
+    assert _bytes(st1.tensor()) == f0
+    bs = ctx.compress_batch([d, dy], [eb, eb])
+    assert bs[0].to_bytes() == a
+    ref_y = codec.compress(y, eb)
+    assert bs[1].to_bytes() == ref_y
+    sts = ctx.retrieve_batch(bs, eb=[10 * eb, 10 * eb])
+    assert _bytes(sts[0].tensor()) == f0
+    assert _bytes(sts[1].tensor()) == codec.retrieve(ref_y, "eb", 10 * eb).field.tobytes()
+    for t in sts + [st0, st1]:
+        t.free()
+    for s in bs + [s0, s1]:
+        s.free()
+    ctx.autotune_clear()
+    with pytest.raises(pkg.IpcError):
+        ctx.autotune(_dev(np.zeros((40, 50), dtype=np.float32)), 1e-3)
