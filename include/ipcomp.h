@@ -167,6 +167,66 @@ ipc_status ipc_compress_batch(ipc_ctx *ctx, uint32_t n, const void *const *field
 ipc_status ipc_retrieve_batch(ipc_ctx *ctx, uint32_t n, const ipc_stream *const *streams,
                               const ipc_target *targets, ipc_state **out, ipc_info *info);
 
+/* One request of a served batch: a retrieval of `stream` (refine = 0; the
+ * new state is returned in `state`, which must be NULL on entry) or a
+ * refinement of the resident `state` (refine = 1, `stream` ignored), both to
+ * `target`.  status and info are outputs. */
+typedef struct {
+  const ipc_stream *stream;
+  ipc_state *state;
+  ipc_target target;
+  int32_t refine;
+  int32_t status;
+  ipc_info info;
+} ipc_request;
+
+/* A mixed batch of retrievals and refinements (Alg. 1 and Alg. 2 for many
+ * requests at once): requests on 3-D streams with the default chunks (of the
+ * first such request's dtype and interpolation) share one launch per level,
+ * a refinement joining at the level of its first changed pass; the others
+ * run one at a time.  Each result equals the same request served alone.
+ * Returns IPC_OK when every request was attempted; per-request outcomes are
+ * in req[i].status. */
+ipc_status ipc_serve_batch(ipc_ctx *ctx, uint32_t n, ipc_request *req);
+
+/* Device bytes of the field a stream reconstructs / a state holds. */
+ipc_status ipc_stream_field_bytes(const ipc_stream *s, uint64_t *bytes);
+ipc_status ipc_state_field_bytes(const ipc_state *st, uint64_t *bytes);
+
+/* Serving loop (beyond the paper): streams and reconstructions stay
+ * resident; requests are submitted from any host thread and served by one
+ * worker thread in continuous batches (ipc_serve_batch), admitted in arrival
+ * order as their device memory fits `budget_bytes` (a new state's field plus
+ * the transient coarse grids; a large request does not hold back smaller
+ * ones behind it), at most `max_batch` (0 = 64) per batch.
+ *  - ipc_server_submit: a retrieval of `stream` (refine_state NULL) or a
+ *    refinement of `refine_state`; IPC_ENOMEM if it can never fit.
+ *  - ipc_server_wait: blocks (timeout_ms < 0: no limit; IPC_ESTATE on time
+ *    out) until the request is served; returns its status, the state (new
+ *    for retrievals, owned by the caller from then on), its info and its
+ *    latency from submission to completion.
+ *  - ipc_server_release: frees a state the server made (asynchronously; its
+ *    memory returns to the budget).
+ *  - ipc_server_lock / unlock: exclusive use of the context between batches
+ *    (the worker holds it while a batch runs); any other call on the
+ *    context while the server exists must be made under it.
+ *  - ipc_server_destroy: serves what fits, fails the rest, joins the worker.
+ * A refinement and a retrieval of the same state must not be outstanding at
+ * once. */
+typedef struct ipc_server ipc_server;
+ipc_status ipc_server_create(ipc_ctx *ctx, uint64_t budget_bytes, uint32_t max_batch,
+                             ipc_server **out);
+ipc_status ipc_server_submit(ipc_server *srv, const ipc_stream *stream, ipc_state *refine_state,
+                             ipc_target target, uint64_t *ticket);
+ipc_status ipc_server_wait(ipc_server *srv, uint64_t ticket, int64_t timeout_ms, ipc_state **state,
+                           ipc_info *info, double *latency_ms);
+ipc_status ipc_server_release(ipc_server *srv, ipc_state *st);
+ipc_status ipc_server_lock(ipc_server *srv);
+ipc_status ipc_server_unlock(ipc_server *srv);
+ipc_status ipc_server_stats(ipc_server *srv, uint64_t *used, uint64_t *peak, uint64_t *batches,
+                            uint64_t *served);
+void ipc_server_destroy(ipc_server *srv);
+
 /* Autotuner (beyond the paper): compresses and fully retrieves the given
  * representative field once per candidate column length (chunk rows per
  * workgroup of the fused 3-D level launches: 16, 8, 4, 2, 1; every level at

@@ -56,6 +56,11 @@ class ipc_pass_info(ctypes.Structure):
                 ("launch_pass", c_uint32)]
 
 
+class ipc_request(ctypes.Structure):
+    _fields_ = [("stream", c_void_p), ("state", c_void_p), ("target", ipc_target),
+                ("refine", ctypes.c_int32), ("status", ctypes.c_int32), ("info", ipc_info)]
+
+
 P = ctypes.POINTER
 SIGNATURES = {
     "ipc_ctx_create": (c_int, [c_int, c_void_p, P(c_void_p)]),
@@ -85,6 +90,18 @@ SIGNATURES = {
     "ipc_autotune": (c_int, [c_void_p, c_void_p, P(c_uint64), c_int, c_int, c_double,
                              P(ipc_options), P(ctypes.c_int32), P(ctypes.c_int32), c_uint32]),
     "ipc_autotune_clear": (c_int, [c_void_p]),
+    "ipc_serve_batch": (c_int, [c_void_p, c_uint32, P(ipc_request)]),
+    "ipc_stream_field_bytes": (c_int, [c_void_p, P(c_uint64)]),
+    "ipc_state_field_bytes": (c_int, [c_void_p, P(c_uint64)]),
+    "ipc_server_create": (c_int, [c_void_p, c_uint64, c_uint32, P(c_void_p)]),
+    "ipc_server_submit": (c_int, [c_void_p, c_void_p, c_void_p, ipc_target, P(c_uint64)]),
+    "ipc_server_wait": (c_int, [c_void_p, c_uint64, ctypes.c_int64, P(c_void_p), P(ipc_info),
+                                P(c_double)]),
+    "ipc_server_release": (c_int, [c_void_p, c_void_p]),
+    "ipc_server_lock": (c_int, [c_void_p]),
+    "ipc_server_unlock": (c_int, [c_void_p]),
+    "ipc_server_stats": (c_int, [c_void_p, P(c_uint64), P(c_uint64), P(c_uint64), P(c_uint64)]),
+    "ipc_server_destroy": (None, [c_void_p]),
     "ipc_ctx_set_profiling": (c_int, [c_void_p, c_int, c_int]),
     "ipc_ctx_pass_times": (c_int, [c_void_p, P(c_float), c_uint32, P(c_uint32)]),
     "ipc_status_string": (ctypes.c_char_p, [c_int]),
@@ -273,6 +290,29 @@ class Context:
         _check(lib().ipc_retrieve_batch(self._p, n, ptrs, tg, out, infos), self._p)
         return [State(streams[i], c_void_p(out[i]), infos[i]) for i in range(n)]
 
+    def serve_batch(self, requests):
+        """One mixed batch: requests are (Stream, None, target) retrievals or
+        (None, State, target) refinements, target a dict like {"eb": 1e-3} or
+        {"bitrate": 2.0}; returns per request (State, info, status)."""
+        n = len(requests)
+        arr = (ipc_request * n)()
+        for k, (stream, state, tg) in enumerate(requests):
+            arr[k].stream = stream._p if stream is not None else None
+            arr[k].state = state._p if state is not None else None
+            arr[k].refine = 1 if state is not None else 0
+            arr[k].target = _target(tg.get("eb"), tg.get("bitrate"))
+        _check(lib().ipc_serve_batch(self._p, n, arr), self._p)
+        out = []
+        for k, (stream, state, tg) in enumerate(requests):
+            r = arr[k]
+            if state is not None:
+                state.info = r.info
+                out.append((state, r.info, r.status))
+            else:
+                st = State(stream, c_void_p(r.state), r.info) if r.status == 0 and r.state else None
+                out.append((st, r.info, r.status))
+        return out
+
     def stream_from_bytes(self, data: bytes, shape=None, dtype=None) -> "Stream":
         import numpy as np
         import torch
@@ -404,3 +444,96 @@ class State:
 
 __all__ = ["lib", "plan_host", "Context", "Stream", "State", "IpcError", "ipc_info",
            "ipc_target", "ipc_options", "LIB_PATH"]
+
+
+class Server:
+    """ipc_server: resident streams, requests admitted by a device-memory
+    budget and served in continuous batches by a native worker thread.
+
+    While a server exists, use its context only through it (``locked()``
+    around any other call on the context)."""
+
+    def __init__(self, ctx: Context, budget_bytes: int, max_batch: int = 64):
+        p = c_void_p()
+        _check(lib().ipc_server_create(ctx.handle, int(budget_bytes), int(max_batch), ctypes.byref(p)),
+               ctx.handle)
+        self._p = p
+        self.ctx = ctx
+
+    def submit(self, stream: "Stream" = None, state: "State" = None, eb=None, bitrate=None) -> int:
+        """Queue a retrieval of `stream` or a refinement of `state`; returns a ticket."""
+        t = c_uint64()
+        st = lib().ipc_server_submit(self._p, stream._p if stream is not None else None,
+                                     state._p if state is not None else None,
+                                     _target(eb, bitrate), ctypes.byref(t))
+        if st != 0:
+            raise IpcError(st, "submit refused")
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1, stream: "Stream" = None, state: "State" = None):
+        """(State, info, latency_ms) of a served request (the refined State
+        itself for refinements; a new ServedState for retrievals)."""
+        out = c_void_p()
+        info = ipc_info()
+        lat = c_double()
+        st = lib().ipc_server_wait(self._p, int(ticket), int(timeout_ms), ctypes.byref(out),
+                                   ctypes.byref(info), ctypes.byref(lat))
+        if st != 0:
+            raise IpcError(st, "request failed" if st != -5 else "not finished")
+        if state is not None:
+            state.info = info
+            return state, info, lat.value
+        return ServedState(self, stream, out, info), info, lat.value
+
+    def release(self, state: "State"):
+        if getattr(state, "_p", None):
+            _check(lib().ipc_server_release(self._p, state._p))
+            state._p = None
+
+    def locked(self):
+        srv = self
+
+        class _Lock:
+            def __enter__(self):
+                _check(lib().ipc_server_lock(srv._p))
+
+            def __exit__(self, *a):
+                _check(lib().ipc_server_unlock(srv._p))
+        return _Lock()
+
+    def stats(self) -> dict:
+        v = [c_uint64() for _ in range(4)]
+        _check(lib().ipc_server_stats(self._p, *[ctypes.byref(x) for x in v]))
+        return {"used": v[0].value, "peak": v[1].value, "batches": v[2].value, "served": v[3].value}
+
+    def close(self):
+        if getattr(self, "_p", None):
+            lib().ipc_server_destroy(self._p)
+            self._p = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ServedState(State):
+    """A State made by a Server: freed through it, copied under its lock."""
+
+    def __init__(self, server: Server, stream: "Stream", p, info: ipc_info):
+        self.server = server
+        self.stream, self._p, self.info = stream, p, info
+
+    def free(self):
+        if getattr(self, "_p", None):
+            self.server.release(self)
+
+    def copy_into(self, t):
+        with self.server.locked():
+            State.copy_into(self, t)
+
+    def refine(self, eb=None, bitrate=None):
+        tk = self.server.submit(state=self, eb=eb, bitrate=bitrate)
+        _, info, _ = self.server.wait(tk, state=self)
+        return info

@@ -11,7 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libipcomp.so")
-SOURCES = ["api.cpp", "schedule.cpp", "planner.cpp", "stream_format.cpp", "kernels.hip", "level3.hip"]
+SOURCES = ["api.cpp", "server.cpp", "schedule.cpp", "planner.cpp", "stream_format.cpp", "kernels.hip",
+           "level3.hip"]
 ARCH = "gfx950"
 
 

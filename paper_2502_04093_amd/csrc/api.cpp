@@ -767,7 +767,8 @@ void compress_batch_fused(ipc_ctx *ctx, std::vector<ipc_stream *> &ss,
 // caller of this helper.
 template <typename T>
 void retrieve_batch_fused(ipc_ctx *ctx, const std::vector<const ipc_stream *> &ss,
-                          const std::vector<std::vector<int>> &plans, const std::vector<void *> &out) {
+                          const std::vector<std::vector<int>> &plans, const std::vector<void *> &out,
+                          const std::vector<int> &l_start) {
   const int n = int(ss.size());
   const int dtype = ss[0]->meta.dtype, interp = ss[0]->meta.interp;
   const size_t isz = sizeof(T);
@@ -800,8 +801,7 @@ void retrieve_batch_fused(ipc_ctx *ctx, const std::vector<const ipc_stream *> &s
   for (int l = Kmax; l >= 1; --l) {
     Launch ln{ent.size(), 0, 0};
     for (int i = 0; i < n; ++i) {
-      const Schedule &sc = ss[i]->meta.sched;
-      if (l > sc.K) continue;
+      if (l > l_start[i]) continue;
       Level3Args La = level_args(ctx, ss[i]->meta, l, false);
       BatchR<T> e;
       std::memset(&e, 0, sizeof(e));
@@ -823,9 +823,19 @@ void retrieve_batch_fused(ipc_ctx *ctx, const std::vector<const ipc_stream *> &s
                                 hipMemcpyHostToDevice, ctx->stream), "upload");
   for (int i = 0; i < n; ++i) {
     const Schedule &sc = ss[i]->meta.sched;
-    hip_check(ctx, launch_anchor3_retrieve(dtype, anchor3_args(sc), g[2 * i + (sc.K & 1)].p, in[i],
-                                           ss[i]->meta.eb, ctx->stream),
-              "anchor kernel launch");
+    const int ls = l_start[i];
+    if (ls >= sc.K) {
+      hip_check(ctx, launch_anchor3_retrieve(dtype, anchor3_args(sc), g[2 * i + (sc.K & 1)].p, in[i],
+                                             ss[i]->meta.eb, ctx->stream),
+                "anchor kernel launch");
+    } else {
+      // refinement: the coarse grid of its first level from the resident field
+      int64_t gd[3];
+      for (int j = 0; j < 3; ++j) gd[j] = ((sc.dims3[j] - 1) >> ls) + 1;
+      hip_check(ctx, launch_gather_coarse(ss[i]->meta.dtype, out[i], sc.dims3, int64_t(1) << ls,
+                                          g[2 * i + (ls & 1)].p, gd, ctx->stream),
+                "gather kernel launch");
+    }
   }
   for (const Launch &ln : launches)
     hip_check(ctx, launch_level3_retrieve_batch(dtype, interp, static_cast<BatchR<T> *>(ent_dev.p) + ln.off,
@@ -1324,6 +1334,17 @@ ipc_status ipc_retrieve_plan(ipc_ctx *ctx, const ipc_stream *s, const uint8_t *p
 
 const void *ipc_state_field(const ipc_state *st) { return st ? st->field.p : nullptr; }
 
+ipc_status ipc_stream_field_bytes(const ipc_stream *s, uint64_t *bytes) {
+  if (!s || !bytes) return IPC_EINVAL;
+  *bytes = uint64_t(s->meta.sched.n_points) * (s->meta.dtype == IPC_F32 ? 4u : 8u);
+  return IPC_OK;
+}
+
+ipc_status ipc_state_field_bytes(const ipc_state *st, uint64_t *bytes) {
+  if (!st || !bytes) return IPC_EINVAL;
+  return ipc_stream_field_bytes(st->stream, bytes);
+}
+
 ipc_status ipc_state_copy_field(ipc_ctx *ctx, const ipc_state *st, void *dst_dev,
                                 uint64_t capacity) {
   if (!ctx || !st || !dst_dev) return IPC_EINVAL;
@@ -1579,10 +1600,12 @@ ipc_status ipc_retrieve_batch(ipc_ctx *ctx, uint32_t n, const ipc_stream *const 
       fields[i] = sts[i]->field.p;
     }
     hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
+    std::vector<int> ls(n);
+    for (uint32_t i = 0; i < n; ++i) ls[i] = ss[i]->meta.sched.K;
     if (ss[0]->meta.dtype == IPC_F32)
-      retrieve_batch_fused<float>(ctx, ss, plans, fields);
+      retrieve_batch_fused<float>(ctx, ss, plans, fields, ls);
     else
-      retrieve_batch_fused<double>(ctx, ss, plans, fields);
+      retrieve_batch_fused<double>(ctx, ss, plans, fields, ls);
     hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
     hip_check(ctx, hipEventSynchronize(ctx->ev1), "retrieve");
     float ms = 0;
@@ -1683,6 +1706,152 @@ ipc_status ipc_autotune(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
 ipc_status ipc_autotune_clear(ipc_ctx *ctx) {
   if (!ctx) return IPC_EINVAL;
   ctx->tuned.clear();
+  return IPC_OK;
+}
+
+ipc_status ipc_serve_batch(ipc_ctx *ctx, uint32_t n, ipc_request *req) {
+  if (!ctx || (n && !req)) return IPC_EINVAL;
+  // plan every request; refinements that need nothing finish here
+  struct Job {
+    uint32_t r;
+    const ipc_stream *s;
+    ipc_state *st;
+    PlanResult pr;
+    int l_start;
+    float tplan;
+    uint64_t read;
+  };
+  std::vector<Job> jobs;
+  std::vector<const ipc_state *> seen;
+  for (uint32_t i = 0; i < n; ++i) {
+    ipc_request &q = req[i];
+    q.status = IPC_OK;
+    std::memset(&q.info, 0, sizeof(q.info));
+    if (q.refine && q.state) {
+      if (std::find(seen.begin(), seen.end(), q.state) != seen.end()) {
+        q.status = IPC_EINVAL;  // one request per state and batch
+        continue;
+      }
+      seen.push_back(q.state);
+    }
+    const ipc_stream *s = q.refine ? (q.state ? q.state->stream : nullptr) : q.stream;
+    if (!s || !valid_target(q.target) || (q.refine && q.state->ctx != ctx) || (!q.refine && q.state)) {
+      q.status = IPC_EINVAL;
+      continue;
+    }
+    if (s->ctx != ctx) {
+      q.status = IPC_ESTATE;
+      continue;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    Job j{i, s, q.refine ? q.state : nullptr, PlanResult(), s->meta.sched.K, 0.0f, 0};
+    if (q.refine) {
+      ipc_state *st = q.state;
+      if (q.target.kind == IPC_TARGET_EB && q.target.value >= st->bound) {
+        fill_info(s, st->plan, st->bound, IPC_FLAG_NOOP, 0, 0.0f, 0.0f, &q.info);
+        continue;
+      }
+      j.pr = plan_request(s->tables, q.target.kind, q.target.value, st->plan.data());
+      j.tplan = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      if (j.pr.plan == st->plan) {
+        fill_info(s, st->plan, st->bound, j.pr.flags | IPC_FLAG_NOOP, 0, j.tplan, 0.0f, &q.info);
+        continue;
+      }
+      int s_min = 0;
+      while (s_min < int(j.pr.plan.size()) && j.pr.plan[s_min] >= st->plan[s_min]) ++s_min;
+      j.read = plane_bytes_between(s, j.pr.plan, st->plan);
+      j.l_start = s->meta.sched.passes[size_t(s_min)].level;
+      if (s_min == 0) j.l_start = s->meta.sched.K;
+    } else {
+      j.pr = plan_request(s->tables, q.target.kind, q.target.value, nullptr);
+      j.tplan = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      std::vector<int> none(j.pr.plan.size(), 32);
+      j.read = plane_bytes_between(s, j.pr.plan, none);
+    }
+    jobs.push_back(j);
+  }
+  if (jobs.empty()) return IPC_OK;
+  // fused 3-D jobs of one dtype / interpolation share the level launches;
+  // the others run one at a time
+  const ipc_stream *s0 = nullptr;
+  std::vector<size_t> fused_idx, other_idx;
+  for (size_t k = 0; k < jobs.size(); ++k) {
+    const ipc_stream *s = jobs[k].s;
+    const bool f = fused3(s->meta.sched) && (!s0 || (s->meta.dtype == s0->meta.dtype && s->meta.interp == s0->meta.interp));
+    if (f) {
+      if (!s0) s0 = s;
+      fused_idx.push_back(k);
+    } else {
+      other_idx.push_back(k);
+    }
+  }
+  ipc_status st = guarded(ctx, [&] {
+    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    std::vector<const ipc_stream *> ss;
+    std::vector<std::vector<int>> plans;
+    std::vector<void *> fields;
+    std::vector<int> ls;
+    std::vector<ipc_state *> fresh(jobs.size(), nullptr);
+    for (size_t k : fused_idx) {
+      Job &j = jobs[k];
+      void *f;
+      if (j.st) {
+        f = j.st->field.p;
+      } else {
+        ipc_state *t = new ipc_state();
+        t->ctx = ctx;
+        t->stream = j.s;
+        const size_t isz = j.s->meta.dtype == IPC_F32 ? 4 : 8;
+        try {
+          t->field = dev_alloc(ctx, size_t(j.s->meta.sched.n_points) * isz);
+        } catch (...) {
+          delete t;
+          throw;
+        }
+        fresh[k] = t;
+        f = t->field.p;
+      }
+      ss.push_back(j.s);
+      plans.push_back(j.pr.plan);
+      fields.push_back(f);
+      ls.push_back(j.l_start);
+    }
+    hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
+    if (!ss.empty()) {
+      if (ss[0]->meta.dtype == IPC_F32)
+        retrieve_batch_fused<float>(ctx, ss, plans, fields, ls);
+      else
+        retrieve_batch_fused<double>(ctx, ss, plans, fields, ls);
+    }
+    hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
+    hip_check(ctx, hipEventSynchronize(ctx->ev1), "serve");
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    for (size_t k : fused_idx) {
+      Job &j = jobs[k];
+      ipc_request &q = req[j.r];
+      ipc_state *t = j.st ? j.st : fresh[k];
+      t->plan = j.pr.plan;
+      t->bound = j.pr.bound;
+      if (!j.st) q.state = t;
+      fill_info(j.s, t->plan, t->bound, j.pr.flags, j.read, j.tplan, ms, &q.info);
+    }
+  });
+  if (st != IPC_OK) {
+    for (size_t k : fused_idx) req[jobs[k].r].status = st;
+    return st;
+  }
+  for (size_t k : other_idx) {
+    Job &j = jobs[k];
+    ipc_request &q = req[j.r];
+    if (j.st) {
+      q.status = ipc_refine(ctx, j.st, q.target, &q.info);
+    } else {
+      ipc_state *t = nullptr;
+      q.status = retrieve_common(ctx, j.s, j.pr.plan, j.pr.bound, j.pr.flags, j.tplan, &t, &q.info);
+      if (q.status == IPC_OK) q.state = t;
+    }
+  }
   return IPC_OK;
 }
 

@@ -1028,7 +1028,7 @@ __device__ __forceinline__ int item_field(const B *__restrict__ bf, int nf, uint
 // column segment of the work list (the fields' segments in order).  The
 // fields' launch arguments are read from memory.
 template <typename T, int INTERP>
-__global__ __launch_bounds__(WG3, 4) void k_level3_compress_batch(const BatchC<T> *__restrict__ bf,
+__global__ __launch_bounds__(WG3, sizeof(T) == 4 ? 4 : 2) void k_level3_compress_batch(const BatchC<T> *__restrict__ bf,
                                                                    int nf) {
   __shared__ SharedC<T> S;
   const uint32_t it = work_item();
@@ -1477,7 +1477,7 @@ __global__ __launch_bounds__(WG3) void k_level3_retrieve(Level3Args L, const T *
 // Batched retrieval of one level of several fields (work list, as
 // k_level3_compress_batch)
 template <typename T, int INTERP>
-__global__ __launch_bounds__(WG3, 5) void k_level3_retrieve_batch(const BatchR<T> *__restrict__ bf,
+__global__ __launch_bounds__(WG3, sizeof(T) == 4 ? 5 : 4) void k_level3_retrieve_batch(const BatchR<T> *__restrict__ bf,
                                                                    int nf) {
   __shared__ Shared3<T> S;
   const uint32_t it = work_item();

@@ -1,0 +1,153 @@
+"""Serving loop (gpu): requests of different fields, sizes and targets
+arrive from a client thread while earlier ones run; each result must equal
+the same request served alone (a fresh retrieval with the final plan, which
+single-field tests tie to the oracle), and admission must respect the
+device-memory budget."""
+
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import fieldgen
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2502_04093_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pkg.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def _bytes(t):
+    return t.detach().cpu().numpy().tobytes()
+
+
+def _streams(ctx):
+    shapes = [(33, 40, 70), (64, 64, 64), (17, 130, 66), (96, 80, 100), (40, 200)]
+    out = []
+    for i, sh in enumerate(shapes):
+        x = fieldgen.grf(sh, -5.0 / 6.0, seed=60 + i, dtype=np.float32)
+        r = fieldgen.value_range(x)
+        out.append((ctx.compress(_dev(x), 1e-6 * r), r))
+    return out
+
+
+def test_mixed_requests_match_single_service(ctx):
+    streams = _streams(ctx)
+    srv = pkg.Server(ctx, budget_bytes=64 << 20, max_batch=16)
+    rng = np.random.default_rng(0)
+
+    def submit_retrieve(i):
+        s, r = streams[i]
+        if rng.random() < 0.5:
+            return srv.submit(stream=s, eb=float(r * 10 ** rng.uniform(-6, -2)))
+        return srv.submit(stream=s, bitrate=float(rng.uniform(0.5, 8)))
+
+    # phase 1: retrievals submitted by a client thread while earlier ones run
+    first = []
+
+    def client1():
+        for _ in range(30):
+            i = int(rng.integers(len(streams)))
+            first.append((i, submit_retrieve(i)))
+            time.sleep(float(rng.exponential(0.0005)))
+
+    th = threading.Thread(target=client1)
+    th.start()
+    th.join()
+    states = []
+    for i, tk in first:
+        got, info, lat = srv.wait(tk, stream=streams[i][0])
+        assert lat >= 0
+        states.append((i, got))
+    # phase 2: refinements of live states (each state once) mixed with new
+    # retrievals
+    second = []
+    for k in range(30):
+        if k % 3 == 0:
+            i, st = states[k // 3]
+            second.append((i, srv.submit(state=st, eb=max(st.bound * 0.1, 1e-12)), st))
+        else:
+            i = int(rng.integers(len(streams)))
+            second.append((i, submit_retrieve(i), None))
+    for i, tk, st in second:
+        got, info, lat = srv.wait(tk, stream=streams[i][0], state=st)
+        if st is None:
+            states.append((i, got))
+    for i, st in states:
+        s, _ = streams[i]
+        with srv.locked():
+            alone = s.retrieve_plan(st.plan)
+            a = _bytes(alone.tensor())
+            alone.free()
+        assert _bytes(st.tensor()) == a
+    stats = srv.stats()
+    assert stats["served"] == 60
+    assert stats["peak"] <= 64 << 20
+    assert stats["batches"] < 60  # requests shared batches
+    for _, st in states:
+        st.free()
+    srv.close()
+    for s, _ in streams:
+        s.free()
+
+
+def test_admission_waits_for_memory(ctx):
+    x = fieldgen.grf((64, 128, 128), -5.0 / 6.0, seed=70, dtype=np.float32)
+    r = fieldgen.value_range(x)
+    s = ctx.compress(_dev(x), 1e-5 * r)
+    field = x.nbytes
+    need = field + field // 8 + field // 64 + (1 << 20)
+    budget = need + field // 2  # one request at a time, not a second state beside a first
+    srv = pkg.Server(ctx, budget_bytes=budget)
+    t1 = srv.submit(stream=s, eb=1e-3 * r)
+    st1, _, _ = srv.wait(t1, stream=s)
+    t2 = srv.submit(stream=s, eb=1e-4 * r)
+    with pytest.raises(pkg.IpcError):
+        srv.wait(t2, timeout_ms=300, stream=s)  # blocked by the budget
+    st1.free()  # returns its field to the budget
+    st2, _, _ = srv.wait(t2, stream=s)
+    assert srv.stats()["peak"] <= budget
+    st2.free()
+    srv.close()
+    small = pkg.Server(ctx, budget_bytes=field // 2)
+    with pytest.raises(pkg.IpcError):
+        small.submit(stream=s, eb=1e-4 * r)  # can never fit
+    small.close()
+    s.free()
+
+
+def test_serve_batch_mixed(ctx):
+    """ipc_serve_batch directly: retrievals and refinements in one batch
+    (refinements joining at their first changed level), a duplicate state
+    refused, each result equal to the request served alone."""
+    streams = _streams(ctx)
+    s0, r0 = streams[0]
+    s1, r1 = streams[3]
+    a = s0.retrieve(eb=1e-2 * r0)
+    b = s1.retrieve(bitrate=1.0)
+    out = ctx.serve_batch([(s1, None, {"eb": 1e-4 * r1}), (None, a, {"eb": 1e-5 * r0}),
+                           (None, b, {"bitrate": 4.0}), (None, b, {"bitrate": 6.0}),
+                           (streams[4][0], None, {"eb": 1e-3 * streams[4][1]})])
+    assert [o[2] for o in out] == [0, 0, 0, -1, 0]
+    for (st, info, status), s in zip([out[0], out[1], out[2], out[4]], [s1, s0, s1, streams[4][0]]):
+        alone = s.retrieve_plan(st.plan)
+        assert _bytes(st.tensor()) == _bytes(alone.tensor())
+        alone.free()
+    for st in (out[0][0], out[4][0], a, b):
+        st.free()
+    for s, _ in streams:
+        s.free()
