@@ -42,10 +42,15 @@ def parse_args():
                     help="edge of the cubic sub-block the oracle compresses and retrieves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", choices=["c2", "c4-batch"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c4-batch", "c5-serve"], default="c2",
                     help="c2: the headline line (one field); c4-batch: --fields float64 "
                          "256x384x384 log-normal fields through the batched calls, beside "
-                         "the same fields one call at a time")
+                         "the same fields one call at a time; c5-serve: a Poisson request "
+                         "mix over --fields resident fields through the serving loop, beside "
+                         "the same trace served one request at a time")
+    ap.add_argument("--requests", type=int, default=600)
+    ap.add_argument("--rate", type=float, default=2000.0, help="c5-serve arrivals per second")
+    ap.add_argument("--budget-gib", type=float, default=32.0, help="c5-serve device-memory budget")
     ap.add_argument("--fields", type=int, default=8)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default column lengths (no ipc_autotune before timing)")
@@ -70,6 +75,8 @@ def main():
 
     if args.workload == "c4-batch":
         return batch_main(args)
+    if args.workload == "c5-serve":
+        return serve_main(args)
     dev = "cuda:0"
     shape = tuple(args.shape)
     n = int(np.prod(shape))
@@ -262,6 +269,159 @@ def batch_main(args):
         "batch_speedup": round(tp / tb, 4),
     }
     print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def serve_main(args):
+    """Serving mix: resident float32 fields of sizes U{64^3, 128^3, 256^3,
+    512^3, 1800x3600} (each a rolled, scaled and shifted copy of one of 4 base
+    fields per size class), compressed at 1e-6 * range.  Requests arrive as a
+    Poisson process; each picks a field; 30 % refine the state of an earlier
+    retrieval of that field to a tighter target, the rest are retrievals with an
+    error bound (log-uniform 1e-6..1e-2 * range) or a bitrate (0.5..8 bits per
+    value), half each.  Served through ipc_server (continuous batching, device
+    memory budget), then the same trace one request at a time in arrival order.
+    Latency = completion - arrival."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import fieldgen
+    import paper_2502_04093_amd as pkg
+
+    rng = np.random.default_rng(5)
+    classes = [(64, 64, 64), (128, 128, 128), (256, 256, 256), (512, 512, 512), (1800, 3600)]
+    nf = args.fields if args.fields != 8 else 40
+    print(f"[bench] generating and compressing {nf} resident fields", file=sys.stderr, flush=True)
+    ctx = pkg.Context(0)
+    bases = {}
+    streams, ranges, sizes = [], [], []
+    for i in range(nf):
+        c = int(rng.integers(len(classes)))
+        shape = classes[c]
+        key = (c, i % 4)
+        if key not in bases:
+            amp = -5.0 / 6.0 if len(shape) == 3 else -1.5
+            bases[key] = fieldgen.grf_torch(shape, amp, seed=100 * c + i % 4)
+        shifts = tuple(int(rng.integers(n)) for n in shape)
+        x = torch.roll(bases[key], shifts, dims=tuple(range(len(shape)))) * float(rng.uniform(0.5, 2)) \
+            + float(rng.uniform(-1, 1))
+        r = float(x.max().double() - x.min().double())
+        streams.append(ctx.compress(x.contiguous(), 1e-6 * r))
+        ranges.append(r)
+        sizes.append(x.numel() * 4)
+        del x
+    bases.clear()
+    torch.cuda.empty_cache()
+    # the trace: (arrival s, field, kind, value, refine_of)
+    R = args.requests
+    t = np.cumsum(rng.exponential(1.0 / args.rate, size=R))
+    trace, last_ret = [], {}
+    for k in range(R):
+        f = int(rng.integers(nf))
+        if f in last_ret and rng.random() < 0.3 and t[k] - t[last_ret[f]] > 0.002:
+            j = last_ret.pop(f)
+            trace.append((t[k], f, "refine", None, j))
+            continue
+        if rng.random() < 0.5:
+            trace.append((t[k], f, "eb", ranges[f] * 10 ** rng.uniform(-6, -2), None))
+        else:
+            trace.append((t[k], f, "bitrate", float(rng.uniform(0.5, 8)), None))
+        last_ret[f] = k
+    # tighter refinement targets: a tenth of the retrieved bound (fixed below)
+    uses = {}
+    for k, (_, _, kind, _, j) in enumerate(trace):
+        if kind == "refine":
+            uses[j] = k
+
+    def pct(v, q):
+        v = sorted(v)
+        return v[min(len(v) - 1, int(np.ceil(q * len(v))) - 1)]
+
+    # served
+    srv = pkg.Server(ctx, budget_bytes=int(args.budget_gib * (1 << 30)), max_batch=64)
+    tickets = [None] * R
+    states = [None] * R
+    done_ev = [threading.Event() for _ in range(R)]
+    lat = [0.0] * R
+    t_done = [0.0] * R
+
+    def waiter():
+        for k in range(R):
+            while tickets[k] is None:
+                time.sleep(0.0001)
+            kind, j = trace[k][2], trace[k][4]
+            st, info, ms = srv.wait(tickets[k], stream=streams[trace[k][1]],
+                                    state=states[j] if kind == "refine" else None)
+            t_done[k] = time.perf_counter()
+            lat[k] = ms
+            if kind == "refine":
+                srv.release(st)
+            elif k in uses:
+                states[k] = st
+            else:
+                srv.release(st)
+            done_ev[k].set()
+
+    wt = threading.Thread(target=waiter)
+    wt.start()
+    T0 = time.perf_counter()
+    for k, (ta, f, kind, val, j) in enumerate(trace):
+        d = T0 + ta - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        if kind == "refine":
+            done_ev[j].wait()
+            tickets[k] = srv.submit(state=states[j], eb=states[j].bound * 0.1)
+        else:
+            tickets[k] = srv.submit(stream=streams[f], **{kind: val})
+    wt.join()
+    T1 = max(t_done)
+    stats = srv.stats()
+    srv.close()
+    served = {"requests_per_s": round(R / (T1 - T0), 2), "p50_ms": round(pct(lat, 0.5), 4),
+              "p99_ms": round(pct(lat, 0.99), 4), "batches": stats["batches"],
+              "peak_budget_GiB": round(stats["peak"] / (1 << 30), 3)}
+    # plain: one request at a time, in arrival order
+    pstates = [None] * R
+    plat = []
+    T0 = time.perf_counter()
+    for k, (ta, f, kind, val, j) in enumerate(trace):
+        arr = T0 + ta
+        d = arr - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        if kind == "refine":
+            st = pstates[j]
+            st.refine(eb=st.bound * 0.1)
+            st.free()
+            pstates[j] = None
+        else:
+            st = streams[f].retrieve(**{kind: val})
+            torch.cuda.synchronize()
+            if k in uses:
+                pstates[k] = st
+            else:
+                st.free()
+        plat.append((time.perf_counter() - arr) * 1e3)
+    T1 = time.perf_counter()
+    plain = {"requests_per_s": round(R / (T1 - T0), 2), "p50_ms": round(pct(plat, 0.5), 4),
+             "p99_ms": round(pct(plat, 0.99), 4)}
+    out = {
+        "metric": "serving requests/s and p50/p99 latency (C5-like mix)",
+        "value": served["requests_per_s"], "unit": "requests/s", "n_gpus": 1, "steps": R,
+        "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{nf} resident f32 fields U{{64^3,128^3,256^3,512^3,1800x3600}}, "
+                               f"eb=1e-6*range; {R} Poisson requests at {args.rate:g}/s, 30 % "
+                               "refines; budget " + f"{args.budget_gib:g} GiB"},
+        "served": served, "plain": plain,
+        "speedup_requests_per_s": round(served["requests_per_s"] / plain["requests_per_s"], 4),
+    }
+    print(json.dumps(out), flush=True)
+    for s in streams:
+        s.free()
     ctx.close()
 
 

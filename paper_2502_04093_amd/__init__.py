@@ -306,7 +306,8 @@ class Context:
         for k, (stream, state, tg) in enumerate(requests):
             r = arr[k]
             if state is not None:
-                state.info = r.info
+                if r.status == 0:
+                    state.info = r.info
                 out.append((state, r.info, r.status))
             else:
                 st = State(stream, c_void_p(r.state), r.info) if r.status == 0 and r.state else None
