@@ -54,6 +54,9 @@ def parse_args():
     ap.add_argument("--fields", type=int, default=8)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default column lengths (no ipc_autotune before timing)")
+    ap.add_argument("--column-rows", default=None,
+                    help="install these column lengths instead of tuning: "
+                         "'c=16,8,1,...;r=8,2,1,...' (by level from 1)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="first run one plain device copy of the field (a known-size "
                          "reference for hardware byte counters)")
@@ -96,10 +99,17 @@ def main():
         del y
     ctx = pkg.Context(0)
     tuned = None
-    if not args.no_autotune:
+    if args.column_rows:
+        parts = dict(p.split("=") for p in args.column_rows.split(";"))
+        zc = [0] + [int(v) for v in parts["c"].split(",")]
+        zr = [0] + [int(v) for v in parts["r"].split(",")]
+        ctx.autotune_set(shape, x.dtype, zc, zr, interp=args.interp)
+        tuned = {"compress": zc[1:], "retrieve": zr[1:]}
+    elif not args.no_autotune:
         zc, zr = ctx.autotune(x, eb, interp=args.interp)
         tuned = {"compress": [v for v in zc if v], "retrieve": [v for v in zr if v]}
-        print(f"[bench] autotuned column lengths by level 1..: {tuned}", file=sys.stderr, flush=True)
+    if tuned:
+        print(f"[bench] column lengths by level 1..: {tuned}", file=sys.stderr, flush=True)
 
     def step():
         t0 = time.perf_counter()
@@ -203,7 +213,7 @@ def main():
                      "kernel": kname, "alg_bytes_per_launch": int(alg_bytes),
                      "avg_launch_ms": round(dom_avg_ms, 5)},
         "pass_ms": {"compress": [round(v, 4) for v in c_ms], "retrieve": [round(v, 4) for v in r_ms]},
-        "launch": {"column_rows_by_level": tuned, "autotuned": tuned is not None},
+        "launch": {"column_rows_by_level": tuned, "autotuned": tuned is not None and not args.column_rows},
     }
 
     if not args.no_cpu_baseline:

@@ -240,6 +240,10 @@ ipc_status ipc_autotune(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
                         int dtype, double abs_eb, const ipc_options *opts, int32_t *zseg_c,
                         int32_t *zseg_r, uint32_t capacity);
 ipc_status ipc_autotune_clear(ipc_ctx *ctx);
+/* Install column lengths chosen earlier (e.g. by ipc_autotune in another
+ * process): n entries per direction indexed by level, 0 = default rule. */
+ipc_status ipc_autotune_set(ipc_ctx *ctx, const uint64_t *dims, int ndim, int dtype, int interp,
+                            const int32_t *zseg_c, const int32_t *zseg_r, uint32_t n);
 
 /* Host-only planner on a serialized stream (no GPU needed): the plan the
  * library would choose for `target`, optionally restricted to b <= limit[s]

@@ -90,6 +90,8 @@ SIGNATURES = {
     "ipc_autotune": (c_int, [c_void_p, c_void_p, P(c_uint64), c_int, c_int, c_double,
                              P(ipc_options), P(ctypes.c_int32), P(ctypes.c_int32), c_uint32]),
     "ipc_autotune_clear": (c_int, [c_void_p]),
+    "ipc_autotune_set": (c_int, [c_void_p, P(c_uint64), c_int, c_int, c_int, P(ctypes.c_int32),
+                                 P(ctypes.c_int32), c_uint32]),
     "ipc_serve_batch": (c_int, [c_void_p, c_uint32, P(ipc_request)]),
     "ipc_stream_field_bytes": (c_int, [c_void_p, P(c_uint64)]),
     "ipc_state_field_bytes": (c_int, [c_void_p, P(c_uint64)]),
@@ -243,6 +245,19 @@ class Context:
         _check(lib().ipc_autotune(self._p, c_void_p(field.data_ptr()), dims, field.dim(), dt,
                                   float(eb), ctypes.byref(opts), zc, zr, 32), self._p)
         return list(zc), list(zr)
+
+    def autotune_set(self, shape, dtype, zseg_c, zseg_r, interp: str = "cubic"):
+        """Install column lengths (lists indexed by level, 0 = default) for a
+        shape and torch dtype."""
+        import torch
+        n = max(len(zseg_c), len(zseg_r))
+        zc = (ctypes.c_int32 * n)(*(list(zseg_c) + [0] * (n - len(zseg_c))))
+        zr = (ctypes.c_int32 * n)(*(list(zseg_r) + [0] * (n - len(zseg_r))))
+        dims = (c_uint64 * len(shape))(*shape)
+        _check(lib().ipc_autotune_set(self._p, dims, len(shape),
+                                      IPC_F32 if dtype == torch.float32 else IPC_F64,
+                                      IPC_CUBIC if interp == "cubic" else IPC_LINEAR, zc, zr, n),
+               self._p)
 
     def autotune_clear(self):
         _check(lib().ipc_autotune_clear(self._p), self._p)

@@ -1703,6 +1703,22 @@ ipc_status ipc_autotune(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
   return IPC_OK;
 }
 
+ipc_status ipc_autotune_set(ipc_ctx *ctx, const uint64_t *dims, int ndim, int dtype, int interp,
+                            const int32_t *zseg_c, const int32_t *zseg_r, uint32_t n) {
+  if (!ctx || !dims || ndim < 1 || ndim > 3 || !zseg_c || !zseg_r) return IPC_EINVAL;
+  TuneVal v;
+  std::memset(&v, 0, sizeof(v));
+  for (uint32_t l = 0; l < n && l < 32; ++l) {
+    if (zseg_c[l] < 0 || zseg_c[l] > 1024 || zseg_r[l] < 0 || zseg_r[l] > 1024) return IPC_EINVAL;
+    v.zseg_c[l] = zseg_c[l];
+    v.zseg_r[l] = zseg_r[l];
+  }
+  int64_t d64[3] = {1, 1, 1};
+  for (int j = 0; j < ndim; ++j) d64[3 - ndim + j] = int64_t(dims[j]);
+  ctx->tuned[TuneKey{{d64[0], d64[1], d64[2]}, dtype, interp}] = v;
+  return IPC_OK;
+}
+
 ipc_status ipc_autotune_clear(ipc_ctx *ctx) {
   if (!ctx) return IPC_EINVAL;
   ctx->tuned.clear();
