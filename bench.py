@@ -106,8 +106,11 @@ def main():
         ctx.autotune_set(shape, x.dtype, zc, zr, interp=args.interp)
         tuned = {"compress": zc[1:], "retrieve": zr[1:]}
     elif not args.no_autotune:
-        zc, zr = ctx.autotune(x, eb, interp=args.interp)
-        tuned = {"compress": [v for v in zc if v], "retrieve": [v for v in zr if v]}
+        try:
+            zc, zr = ctx.autotune(x, eb, interp=args.interp)
+            tuned = {"compress": [v for v in zc if v], "retrieve": [v for v in zr if v]}
+        except pkg.IpcError:  # no fused launches to tune for this shape
+            tuned = None
     if tuned:
         print(f"[bench] column lengths by level 1..: {tuned}", file=sys.stderr, flush=True)
 
