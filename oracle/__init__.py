@@ -16,7 +16,10 @@ What it computes (IPComp, arXiv 2502.04093):
 * ``coding``    -- negabinary (Sec. 4.4.2), the two-prefix-bit XOR predictive
   bitplane code (Sec. 4.4.1), bitplane packing (Sec. 4.3, Fig. "overwrite") and
   the truncation-loss table delta-y (Thm. 1).
-* ``stream``    -- the serialized container of independently loadable blocks.
+* ``stream``    -- the serialized container of independently loadable blocks,
+  raw or with every block entropy coded.
+* ``entropy``   -- the entropy stage that stands in for the paper's lossless
+  compressor (zstd, Sec. 6 setup): an adaptive binary range coder per block.
 * ``planner``   -- the Thm. 1 bound (per-pass reading) and the two knapsack
   dynamic programs of Sec. 5.2 (error-bound mode) and Sec. 5.3 (bitrate mode).
 * ``codec``     -- compress, retrieve (Alg. 1) and refine (Alg. 2, recompute
@@ -30,7 +33,7 @@ with it bit for bit; NumPy never contracts.
 Parity pins (what ties this oracle to something other than itself) live in
 ``tests/test_oracle_*.py``.  Every function here has at least one pin; none is
 "parity unpinned".  Compression ratio and bitrate-mode plans versus the paper's
-own numbers are unpinned (the paper's lossless stage and datasets are absent).
+own numbers are unpinned (the paper's zstd stage and datasets are absent).
 """
 
-from . import schedule, predict, coding, stream, planner, codec  # noqa: F401
+from . import schedule, predict, coding, entropy, stream, planner, codec  # noqa: F401

@@ -223,10 +223,12 @@ class State:
 
 
 def _chunk_word_offsets(ps: ParsedStream, sched: Schedule):
-    """Per pass: (first chunk index, word offset of every chunk's data)."""
+    """Per pass: (first chunk index, word offset of every chunk's data in the
+    raw payload, index of every chunk's first stored block)."""
     out = []
     c0 = 0
     off = 0
+    blk = 0
     for p in sched.passes:
         n = p.n_chunks
         m = ps.masks[c0:c0 + n]
@@ -234,16 +236,19 @@ def _chunk_word_offsets(ps: ParsedStream, sched: Schedule):
         pc = np.array([bin(int(v)).count("1") for v in m], dtype=np.int64)
         sizes = pc * W
         starts = off + np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
-        out.append((c0, starts))
+        bstarts = blk + np.concatenate([[0], np.cumsum(pc)[:-1]]).astype(np.int64)
+        out.append((c0, starts, bstarts))
         off += int(sizes.sum())
+        blk += int(pc.sum())
         c0 += n
     return out
 
 
-def _load_planes(ps: ParsedStream, p, c0, starts, b_lo: int, b_hi: int):
+def _load_planes(ps: ParsedStream, p, c0, starts, b_lo: int, b_hi: int, bstarts=None):
     """XOR-coded codes of the pass built from planes k with b_lo <= k < b_hi.
 
-    Returns (e in stream order, payload bytes read).
+    Returns (e in stream order, payload bytes read); a block of an
+    entropy-coded stream counts the bytes it occupies there.
     """
     counts = p.chunk_counts
     e = np.zeros(int(counts.sum()), dtype=np.uint32)
@@ -257,13 +262,15 @@ def _load_planes(ps: ParsedStream, p, c0, starts, b_lo: int, b_hi: int):
         mask = int(ps.masks[c0 + ci])
         planes = np.zeros((32, W), dtype=np.uint32)
         w = int(starts[ci])
+        blk = int(bstarts[ci]) if bstarts is not None else 0
         for k in range(31, -1, -1):
             if not (mask >> k) & 1:
                 continue
             if b_lo <= k < b_hi:
                 planes[k] = ps.payload[w:w + W]
-                nread += 4 * W
+                nread += 4 * (W if ps.block_words is None else int(ps.block_words[blk]))
             w += W
+            blk += 1
         e[pos:pos + n] = coding.unpack_planes(planes, n)
         pos += n
     return e, nread
@@ -335,9 +342,9 @@ def retrieve_with_plan(buf: bytes, plan, mode: str = "eb", target: Optional[floa
     passes = []
     nread = 0
     for p in sched.passes:
-        c0, starts = offs[p.index]
+        c0, starts, bstarts = offs[p.index]
         b = int(plan[p.index])
-        e, nb = _load_planes(ps, p, c0, starts, b, 32)
+        e, nb = _load_planes(ps, p, c0, starts, b, 32, bstarts)
         nread += nb
         passes.append(PassData(e=e, b=b))
     fld = np.zeros(ps.header.dims, dtype=ps.header.dtype)
@@ -377,8 +384,8 @@ def refine(state: State, mode: str, value: float) -> State:
     for p in state.sched.passes:
         b_new, b_old = int(plan[p.index]), int(state.plan[p.index])
         if b_new < b_old:
-            c0, starts = offs[p.index]
-            e_new, nb = _load_planes(state.parsed, p, c0, starts, b_new, b_old)
+            c0, starts, bstarts = offs[p.index]
+            e_new, nb = _load_planes(state.parsed, p, c0, starts, b_new, b_old, bstarts)
             nread += nb
             state.passes[p.index].e = state.passes[p.index].e | e_new
             state.passes[p.index].b = b_new

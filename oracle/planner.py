@@ -45,7 +45,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .schedule import make_schedule
-from .stream import ParsedStream, section_sizes
+from .stream import ParsedStream
 
 G_UNITS = 1024
 FLAG_CLAMPED_TO_EB = 1
@@ -79,13 +79,22 @@ def tables_from_stream(ps: ParsedStream) -> PlanTables:
     P = h.n_passes
     sizes = np.zeros((P, 32), dtype=np.int64)
     c0 = 0
+    blk = 0
     for p in sched.passes:
         n = p.n_chunks
         m = ps.masks[c0:c0 + n].astype(np.uint64)
-        W = (-(-p.chunk_counts // 32)).astype(np.int64)
-        for k in range(32):
-            bit = ((m >> np.uint64(k)) & np.uint64(1)).astype(np.int64)
-            sizes[p.index, k] = int(np.sum(bit * W)) * 4
+        if ps.block_words is None:
+            W = (-(-p.chunk_counts // 32)).astype(np.int64)
+            for k in range(32):
+                bit = ((m >> np.uint64(k)) & np.uint64(1)).astype(np.int64)
+                sizes[p.index, k] = int(np.sum(bit * W)) * 4
+        else:
+            # entropy-coded blocks: every plane costs the words it occupies
+            for mk in m:
+                for k in range(31, -1, -1):
+                    if (int(mk) >> k) & 1:
+                        sizes[p.index, k] += 4 * int(ps.block_words[blk])
+                        blk += 1
         c0 += n
     prog = np.ones(P, dtype=bool)
     prog[0] = False
@@ -271,6 +280,5 @@ def reported_bound(t: PlanTables, plan, mode: str, target: float) -> float:
 
 
 def fixed_section_bytes(ps: ParsedStream) -> int:
-    h = ps.header
-    s = section_sizes(h.n_passes, h.n_chunks, h.n_outliers, h.dtype.itemsize, h.payload_words)
-    return sum(s[:5])
+    """Bytes before the payload (with the block lengths of a coded stream)."""
+    return ps.payload_offset
