@@ -109,6 +109,25 @@ ipc_status ipc_stream_to_host(ipc_ctx *ctx, const ipc_stream *s, void *dst, uint
 ipc_status ipc_stream_from_host(ipc_ctx *ctx, const void *src, uint64_t bytes, ipc_stream **out);
 void ipc_stream_free(ipc_stream *s);
 
+/* Entropy stage for the stored bitplane blocks (stands in for the paper's
+ * general-purpose lossless compressor, Sec. 6 setup).  Codes every stored
+ * block -- one bitplane of one chunk -- on the device with an adaptive binary
+ * range coder, one block per thread; a block is kept raw when its code is not
+ * shorter.  Afterwards:
+ *   - ipc_stream_size / ipc_stream_to_host give the coded serialized form
+ *     (header byte 11 = 1, a byte per block with its stored words, then the
+ *     stored blocks);
+ *   - the planner charges every plane the bytes its blocks occupy in that
+ *     form, so bitrate targets and ipc_info.bytes_loaded / bytes_read count
+ *     coded bytes;
+ *   - retrieval and refinement read the resident raw planes, unchanged.
+ * A stream already coded is left as it is.  ipc_stream_from_host accepts both
+ * forms and decodes a coded one on the device.  The coded payload stays on the
+ * device beside the raw planes (at most the size of the raw payload). */
+ipc_status ipc_stream_entropy_code(ipc_ctx *ctx, ipc_stream *s);
+/* 0 raw blocks, 1 entropy-coded blocks */
+ipc_status ipc_stream_coding(const ipc_stream *s, int *coding);
+
 /* Per-pass description of a stream (the planner's inputs, Sec. 5). */
 typedef struct {
   int32_t level;              /* l (0 for the anchors) */

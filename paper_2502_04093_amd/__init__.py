@@ -72,6 +72,8 @@ SIGNATURES = {
     "ipc_stream_to_host": (c_int, [c_void_p, c_void_p, c_void_p, c_uint64]),
     "ipc_stream_from_host": (c_int, [c_void_p, c_void_p, c_uint64, P(c_void_p)]),
     "ipc_stream_free": (None, [c_void_p]),
+    "ipc_stream_entropy_code": (c_int, [c_void_p, c_void_p]),
+    "ipc_stream_coding": (c_int, [c_void_p, P(c_int)]),
     "ipc_stream_passes": (c_int, [c_void_p, P(c_uint32)]),
     "ipc_stream_pass_info": (c_int, [c_void_p, c_uint32, P(ipc_pass_info)]),
     "ipc_retrieve": (c_int, [c_void_p, c_void_p, ipc_target, P(c_void_p), P(ipc_info)]),
@@ -385,6 +387,18 @@ class Stream:
                 "n_chunks": pi.n_chunks, "plane_bytes": list(pi.plane_bytes),
                 "errq": list(pi.errq), "progressive": bool(pi.progressive),
                 "launch_pass": int(pi.launch_pass)}
+
+    def entropy_code(self) -> "Stream":
+        """ipc_stream_entropy_code: entropy-code the stored blocks on the
+        device; serialization and the planner then use the coded form."""
+        _check(lib().ipc_stream_entropy_code(self.ctx.handle, self._p), self.ctx.handle)
+        return self
+
+    @property
+    def coding(self) -> int:
+        c = c_int()
+        _check(lib().ipc_stream_coding(self._p, ctypes.byref(c)))
+        return c.value
 
     def to_bytes(self) -> bytes:
         n = self.nbytes

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libipcomp.so")
 SOURCES = ["api.cpp", "server.cpp", "schedule.cpp", "planner.cpp", "stream_format.cpp", "kernels.hip",
-           "level3.hip"]
+           "level3.hip", "entropy.hip"]
 ARCH = "gfx950"
 
 

@@ -88,6 +88,7 @@ struct ipc_stream {
   DevBuf payload;              // u32 words
   DevBuf masks;                // u32 per chunk
   DevBuf chunk_off;            // u64 per chunk (packed placement only)
+  DevBuf coded;                // entropy-coded payload (meta.coding == 1)
   DevBuf out_gchunk, out_local, out_bits, out_start;
   bool host_masks_valid = false;
   bool host_outliers_valid = true;  // meta.outliers holds the records (else only on the device)
@@ -269,6 +270,7 @@ void free_stream_bufs(ipc_stream *s) {
   dev_free(c, s->payload);
   dev_free(c, s->masks);
   dev_free(c, s->chunk_off);
+  dev_free(c, s->coded);
   dev_free(c, s->out_gchunk);
   dev_free(c, s->out_local);
   dev_free(c, s->out_bits);
@@ -303,6 +305,34 @@ void upload_outliers(ipc_ctx *ctx, ipc_stream *s) {
 }
 
 // the device-sorted outlier records into meta.outliers (pass, chunk, local, bits)
+// Stored blocks in payload order (chunks in order, planes 31 down to 0): raw
+// offset in the packed placement and, for a coded stream, offset of the
+// stored form
+std::vector<EcBlock> stream_blocks(const StreamMeta &m) {
+  std::vector<EcBlock> out;
+  out.reserve(size_t(n_blocks(m)));
+  uint64_t raw = 0, coded = 0;
+  for (const PassGeom &p : m.sched.passes)
+    for (int64_t c = 0; c < p.n_chunks; ++c) {
+      const uint32_t mk = m.masks[size_t(p.chunk_base + c)];
+      if (!mk) continue;
+      const uint32_t cnt = uint32_t(chunk_count(p, c));
+      const uint64_t W = (cnt + 31) / 32;
+      for (int k = 31; k >= 0; --k) {
+        if (!((mk >> k) & 1u)) continue;
+        EcBlock b;
+        b.raw_off = raw;
+        b.coded_off = coded;
+        b.count = cnt;
+        b.pad = 0;
+        raw += W;
+        if (m.coding) coded += m.block_words[out.size()];
+        out.push_back(b);
+      }
+    }
+  return out;
+}
+
 void fetch_outliers(ipc_ctx *ctx, ipc_stream *s) {
   StreamMeta &m = s->meta;
   const size_t n = size_t(m.n_outliers);
@@ -846,6 +876,39 @@ void retrieve_batch_fused(ipc_ctx *ctx, const std::vector<const ipc_stream *> &s
   for (DevBuf &b : g) dev_free(ctx, b);
 }
 
+// host copy of the chunk masks
+void ensure_host_masks(ipc_ctx *ctx, ipc_stream *s) {
+  if (s->host_masks_valid) return;
+  StreamMeta &m = s->meta;
+  m.masks.resize(size_t(m.sched.n_chunks));
+  hip_check(ctx, hipMemcpyAsync(m.masks.data(), s->masks.p, m.masks.size() * 4, hipMemcpyDeviceToHost,
+                                ctx->stream), "copy");
+  hip_check(ctx, hipStreamSynchronize(ctx->stream), "copy");
+  s->host_masks_valid = true;
+}
+
+// The raw payload in packed placement on the device: the stream's own buffer,
+// or `tmp` filled from the slot placement (host masks must be valid)
+const uint32_t *packed_payload(ipc_ctx *ctx, ipc_stream *s, DevBuf &tmp, DevBuf &tmp_off) {
+  if (s->packed) return static_cast<const uint32_t *>(s->payload.p);
+  const StreamMeta &m = s->meta;
+  std::vector<uint64_t> off;
+  packed_chunk_offsets(m, off);
+  tmp_off = dev_alloc(ctx, off.size() * 8);
+  tmp = dev_alloc(ctx, std::max<size_t>(4, m.payload_words * 4));
+  hip_check(ctx, hipMemcpyAsync(tmp_off.p, off.data(), off.size() * 8, hipMemcpyHostToDevice, ctx->stream),
+            "copy");
+  for (const PassArgs &a : s->args)
+    hip_check(ctx, launch_pack_payload(a, static_cast<const uint32_t *>(s->masks.p),
+                                       static_cast<const uint64_t *>(tmp_off.p),
+                                       static_cast<const uint32_t *>(s->payload.p),
+                                       static_cast<uint32_t *>(tmp.p), ctx->stream),
+              "pack kernel launch");
+  // the offsets must outlive the launches: the caller synchronizes before
+  // freeing them
+  return static_cast<const uint32_t *>(tmp.p);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
@@ -1161,45 +1224,97 @@ ipc_status ipc_stream_to_host(ipc_ctx *ctx, const ipc_stream *sc, void *dst, uin
   return guarded(ctx, [&] {
     hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     StreamMeta &m = s->meta;
-    if (!s->host_masks_valid) {
-      m.masks.resize(size_t(m.sched.n_chunks));
-      hip_check(ctx, hipMemcpyAsync(m.masks.data(), s->masks.p, m.masks.size() * 4, hipMemcpyDeviceToHost, ctx->stream), "copy");
-      hip_check(ctx, hipStreamSynchronize(ctx->stream), "copy");
-      s->host_masks_valid = true;
-    }
+    ensure_host_masks(ctx, s);
     if (!s->host_outliers_valid) fetch_outliers(ctx, s);
     uint8_t *d = static_cast<uint8_t *>(dst);
     write_serialized_head(m, d);
-    uint64_t poff = payload_offset(m);
-    uint64_t pbytes = m.payload_words * 4;
-    if (s->packed) {
-      hip_check(ctx, hipMemcpyAsync(d + poff, s->payload.p, pbytes, hipMemcpyDeviceToHost, ctx->stream), "copy");
-    } else {
-      std::vector<uint64_t> off;
-      packed_chunk_offsets(m, off);
-      DevBuf doff = dev_alloc(ctx, off.size() * 8);
-      DevBuf packed = dev_alloc(ctx, std::max<size_t>(4, pbytes));
-      try {
-        hip_check(ctx, hipMemcpyAsync(doff.p, off.data(), off.size() * 8, hipMemcpyHostToDevice, ctx->stream), "copy");
-        for (const PassArgs &a : s->args)
-          hip_check(ctx, launch_pack_payload(a, static_cast<const uint32_t *>(s->masks.p),
-                                             static_cast<const uint64_t *>(doff.p),
-                                             static_cast<const uint32_t *>(s->payload.p),
-                                             static_cast<uint32_t *>(packed.p), ctx->stream),
-                    "pack kernel launch");
-        hip_check(ctx, hipMemcpyAsync(d + poff, packed.p, pbytes, hipMemcpyDeviceToHost, ctx->stream), "copy");
-        hip_check(ctx, hipStreamSynchronize(ctx->stream), "copy");
-      } catch (...) {
-        dev_free(ctx, doff);
-        dev_free(ctx, packed);
-        throw;
-      }
-      dev_free(ctx, doff);
-      dev_free(ctx, packed);
+    const uint64_t poff = payload_offset(m);
+    const uint64_t pbytes = (m.coding ? m.coded_words : m.payload_words) * 4;
+    DevBuf tmp, tmp_off;
+    try {
+      const void *src = m.coding ? s->coded.p : packed_payload(ctx, s, tmp, tmp_off);
+      if (pbytes)
+        hip_check(ctx, hipMemcpyAsync(d + poff, src, pbytes, hipMemcpyDeviceToHost, ctx->stream), "copy");
+      hip_check(ctx, hipStreamSynchronize(ctx->stream), "copy");
+    } catch (...) {
+      dev_free(ctx, tmp);
+      dev_free(ctx, tmp_off);
+      throw;
     }
-    hip_check(ctx, hipStreamSynchronize(ctx->stream), "copy");
+    dev_free(ctx, tmp);
+    dev_free(ctx, tmp_off);
     std::memset(d + poff + pbytes, 0, size_t(pad8(pbytes) - pbytes));
   });
+}
+
+ipc_status ipc_stream_entropy_code(ipc_ctx *ctx, ipc_stream *s) {
+  if (!ctx || !s) return IPC_EINVAL;
+  if (s->ctx != ctx) {
+    set_err(ctx, "stream belongs to another context");
+    return IPC_ESTATE;
+  }
+  if (s->meta.coding) return IPC_OK;
+  return guarded(ctx, [&] {
+    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    StreamMeta &m = s->meta;
+    ensure_host_masks(ctx, s);
+    std::vector<EcBlock> blk = stream_blocks(m);
+    const uint64_t nb = blk.size();
+    DevBuf tmp, tmp_off, dblk, scratch, dwords, coded;
+    auto release = [&] {
+      for (DevBuf *b : {&tmp, &tmp_off, &dblk, &scratch, &dwords}) dev_free(ctx, *b);
+    };
+    try {
+      const uint32_t *raw = packed_payload(ctx, s, tmp, tmp_off);
+      dblk = dev_alloc(ctx, std::max<size_t>(sizeof(EcBlock), nb * sizeof(EcBlock)));
+      scratch = dev_alloc(ctx, std::max<size_t>(4, m.payload_words * 4));
+      dwords = dev_alloc(ctx, std::max<size_t>(1, nb));
+      if (nb)
+        hip_check(ctx, hipMemcpyAsync(dblk.p, blk.data(), nb * sizeof(EcBlock), hipMemcpyHostToDevice,
+                                      ctx->stream), "upload");
+      hip_check(ctx, launch_ec_encode(static_cast<const EcBlock *>(dblk.p), nb, raw,
+                                      static_cast<uint32_t *>(scratch.p), static_cast<uint8_t *>(dwords.p),
+                                      ctx->stream), "entropy encode launch");
+      std::vector<uint8_t> words(nb);
+      if (nb)
+        hip_check(ctx, hipMemcpyAsync(words.data(), dwords.p, nb, hipMemcpyDeviceToHost, ctx->stream),
+                  "copy");
+      hip_check(ctx, hipStreamSynchronize(ctx->stream), "entropy encode");
+      uint64_t tot = 0;
+      for (uint64_t i = 0; i < nb; ++i) {
+        blk[i].coded_off = tot;
+        tot += words[i];
+      }
+      coded = dev_alloc(ctx, std::max<size_t>(4, tot * 4));
+      if (nb)
+        hip_check(ctx, hipMemcpyAsync(dblk.p, blk.data(), nb * sizeof(EcBlock), hipMemcpyHostToDevice,
+                                      ctx->stream), "upload");
+      hip_check(ctx, launch_ec_gather(static_cast<const EcBlock *>(dblk.p), nb,
+                                      static_cast<const uint8_t *>(dwords.p),
+                                      static_cast<const uint32_t *>(scratch.p),
+                                      static_cast<uint32_t *>(coded.p), ctx->stream),
+                "entropy gather launch");
+      hip_check(ctx, hipStreamSynchronize(ctx->stream), "entropy gather");
+      m.block_words = std::move(words);
+      m.coded_words = tot;
+      m.coding = 1;
+      m.serialized_bytes = serialized_size(m);
+      s->coded = coded;
+      coded = DevBuf();
+      s->tables = plan_tables(m);
+    } catch (...) {
+      release();
+      dev_free(ctx, coded);
+      throw;
+    }
+    release();
+  });
+}
+
+ipc_status ipc_stream_coding(const ipc_stream *s, int *coding) {
+  if (!s || !coding) return IPC_EINVAL;
+  *coding = s->meta.coding;
+  return IPC_OK;
 }
 
 ipc_status ipc_stream_from_host(ipc_ctx *ctx, const void *src, uint64_t bytes, ipc_stream **out) {
@@ -1230,7 +1345,40 @@ ipc_status ipc_stream_from_host(ipc_ctx *ctx, const void *src, uint64_t bytes, i
     s->payload = dev_alloc(ctx, std::max<size_t>(4, m.payload_words * 4));
     s->masks = dev_alloc(ctx, std::max<size_t>(4, m.masks.size() * 4));
     s->chunk_off = dev_alloc(ctx, off.size() * 8);
-    hip_check(ctx, hipMemcpyAsync(s->payload.p, payload, m.payload_words * 4, hipMemcpyHostToDevice, ctx->stream), "upload");
+    if (m.coding) {
+      // stored blocks to the device, decoded there into the packed placement
+      std::vector<EcBlock> blk = stream_blocks(m);
+      const uint64_t nb = blk.size();
+      s->coded = dev_alloc(ctx, std::max<size_t>(4, m.coded_words * 4));
+      DevBuf dblk = dev_alloc(ctx, std::max<size_t>(sizeof(EcBlock), nb * sizeof(EcBlock)));
+      DevBuf dwords = dev_alloc(ctx, std::max<size_t>(1, nb));
+      try {
+        if (m.coded_words)
+          hip_check(ctx, hipMemcpyAsync(s->coded.p, payload, m.coded_words * 4, hipMemcpyHostToDevice,
+                                        ctx->stream), "upload");
+        if (nb) {
+          hip_check(ctx, hipMemcpyAsync(dblk.p, blk.data(), nb * sizeof(EcBlock), hipMemcpyHostToDevice,
+                                        ctx->stream), "upload");
+          hip_check(ctx, hipMemcpyAsync(dwords.p, m.block_words.data(), nb, hipMemcpyHostToDevice,
+                                        ctx->stream), "upload");
+        }
+        hip_check(ctx, launch_ec_decode(static_cast<const EcBlock *>(dblk.p), nb,
+                                        static_cast<const uint8_t *>(dwords.p),
+                                        static_cast<const uint32_t *>(s->coded.p),
+                                        static_cast<uint32_t *>(s->payload.p), ctx->stream),
+                  "entropy decode launch");
+        hip_check(ctx, hipStreamSynchronize(ctx->stream), "entropy decode");
+      } catch (...) {
+        dev_free(ctx, dblk);
+        dev_free(ctx, dwords);
+        throw;
+      }
+      dev_free(ctx, dblk);
+      dev_free(ctx, dwords);
+    } else if (m.payload_words) {
+      hip_check(ctx, hipMemcpyAsync(s->payload.p, payload, m.payload_words * 4, hipMemcpyHostToDevice,
+                                    ctx->stream), "upload");
+    }
     hip_check(ctx, hipMemcpyAsync(s->masks.p, m.masks.data(), m.masks.size() * 4, hipMemcpyHostToDevice, ctx->stream), "upload");
     hip_check(ctx, hipMemcpyAsync(s->chunk_off.p, off.data(), off.size() * 8, hipMemcpyHostToDevice, ctx->stream), "upload");
     hip_check(ctx, hipStreamSynchronize(ctx->stream), "upload");

@@ -1,0 +1,237 @@
+// Entropy stage for stored bitplane blocks (the stand-in for the paper's
+// general-purpose lossless compressor, Sec. 6 setup): every block -- one stored
+// plane of one chunk -- is coded on its own by an adaptive binary range coder,
+// one block per thread, so retrieval still reads only the blocks of its plan.
+//
+// Coder: range coding (Martin, 1979) of the block's bits in code order with a
+// 12-bit probability of a zero that moves 1/16 of the way toward every coded
+// bit.  bound = (range >> 12) * p0; a zero keeps [low, low + bound), a one
+// [low + bound, low + range); range is renormalized by bytes below 2^24.
+// Output bytes are final when written: the encoder holds the last byte that a
+// carry could still reach plus the run of 0xFF bytes behind it and releases
+// them once the carry is decided.  The end is the shortest byte run inside the
+// final interval, and trailing zero bytes are dropped (the decoder reads zeros
+// past the end).  A block is stored coded only when that takes fewer words
+// than the raw plane, else raw.
+#include "kernels.h"
+
+namespace ipc {
+namespace {
+
+constexpr int EC_WG = 128;
+constexpr uint32_t PROB_ONE = 4096;
+constexpr uint32_t TOP = 1u << 24;
+
+// bytes of one block's code, packed little-endian into words of dst (at most
+// cap words kept; only a code shorter than cap is ever used)
+struct ByteSink {
+  uint32_t *dst;
+  uint32_t cap;
+  uint32_t n = 0;       // bytes emitted
+  uint32_t last_nz = 0; // bytes up to the last nonzero one
+  uint32_t acc = 0;
+  bool skip = true;     // the encoder's leading virtual zero byte
+
+  __device__ ByteSink(uint32_t *d, uint32_t c) : dst(d), cap(c) {}
+  __device__ __forceinline__ void put(uint32_t b) {
+    if (skip) {
+      skip = false;
+      return;
+    }
+    acc |= b << (8 * (n & 3));
+    if (b) last_nz = n + 1;
+    ++n;
+    if ((n & 3) == 0) {
+      if ((n >> 2) <= cap) dst[(n >> 2) - 1] = acc;
+      acc = 0;
+    }
+  }
+  __device__ __forceinline__ void flush_word() {
+    if ((n & 3) && (n >> 2) < cap) dst[n >> 2] = acc;
+  }
+};
+
+struct Encoder {
+  uint64_t low = 0;       // 32 bits plus the carry bit (low + range < 2^33)
+  uint32_t range = 0xFFFFFFFFu;
+  uint32_t cache = 0;     // last byte a carry can still change; at first a
+                          // virtual zero byte ahead of the code (never carried
+                          // into: the coded value stays below 1)
+  uint32_t pending = 0;   // 0xFF bytes behind it
+
+  // moves the top byte of low out (a renormalization step); a carry left in
+  // bit 32 by the bits since the last step reaches the held bytes first
+  __device__ __forceinline__ void shift(ByteSink &out) {
+    const uint32_t top = uint32_t(low >> 24) & 0xFFu;
+    const uint32_t carry = uint32_t(low >> 32);
+    if (top != 0xFFu || carry) {
+      // the held bytes are decided
+      out.put((cache + carry) & 0xFFu);
+      for (; pending; --pending) out.put((0xFFu + carry) & 0xFFu);
+      cache = top;
+    } else {
+      ++pending;  // a 0xFF that a later carry would turn into 0x00
+    }
+    low = (low & 0x00FFFFFFull) << 8;
+  }
+
+  __device__ __forceinline__ void bit(uint32_t b, uint32_t &p0, ByteSink &out) {
+    const uint32_t bound = (range >> 12) * p0;
+    if (b) {
+      low += bound;
+      range -= bound;
+      p0 -= p0 >> 4;
+    } else {
+      range = bound;
+      p0 += (PROB_ONE - p0) >> 4;
+    }
+    while (range < TOP) {
+      shift(out);
+      range <<= 8;
+    }
+  }
+
+  // the shortest byte run (then zeros) inside [low, low + range): zero bytes
+  // when the value 0 (or the carry alone) lies inside, else one byte
+  __device__ __forceinline__ void finish(ByteSink &out) {
+    uint64_t v;
+    const uint64_t hi = low + uint64_t(range);
+    const uint64_t v0 = (low & 0xFFFFFFFFull) == 0 ? low : ((low >> 32) + 1) << 32;
+    if (v0 < hi)
+      v = v0;
+    else
+      v = ((low + 0xFFFFFFull) >> 24) << 24;
+    low = v;
+    for (int i = 0; i < 5; ++i) shift(out);
+  }
+};
+
+// one thread per block
+__global__ __launch_bounds__(EC_WG) void k_ec_encode(const EcBlock *__restrict__ blk, uint64_t n,
+                                                     const uint32_t *__restrict__ raw,
+                                                     uint32_t *__restrict__ scratch,
+                                                     uint8_t *__restrict__ words) {
+  const uint64_t i = uint64_t(blockIdx.x) * EC_WG + threadIdx.x;
+  if (i >= n) return;
+  const EcBlock b = blk[i];
+  const uint32_t count = b.count;
+  const uint32_t W = (count + 31) >> 5;
+  const uint32_t *src = raw + b.raw_off;
+  uint32_t *dst = scratch + b.raw_off;
+  ByteSink out(dst, W);
+  Encoder enc;
+  uint32_t p0 = PROB_ONE / 2;
+  for (uint32_t w = 0; w < W; ++w) {
+    const uint32_t word = src[w];
+    const uint32_t nb = count - 32 * w < 32 ? count - 32 * w : 32;
+    for (uint32_t j = 0; j < nb; ++j) enc.bit((word >> j) & 1u, p0, out);
+  }
+  enc.finish(out);
+  out.flush_word();
+  const uint32_t used = (out.last_nz + 3) >> 2;
+  if (used < W) {
+    words[i] = uint8_t(used);
+  } else {
+    for (uint32_t w = 0; w < W; ++w) dst[w] = src[w];
+    words[i] = uint8_t(W);
+  }
+}
+
+// one wave per block: stored words from the scratch slot to their place in
+// the coded payload
+__global__ __launch_bounds__(256) void k_ec_gather(const EcBlock *__restrict__ blk, uint64_t n,
+                                                   const uint8_t *__restrict__ words,
+                                                   const uint32_t *__restrict__ scratch,
+                                                   uint32_t *__restrict__ coded) {
+  const uint64_t i = uint64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const int lane = threadIdx.x & 63;
+  const EcBlock b = blk[i];
+  const uint32_t nw = words[i];
+  for (uint32_t w = lane; w < nw; w += 64) coded[b.coded_off + w] = scratch[b.raw_off + w];
+}
+
+// one thread per block: the raw plane (W words) back at raw_off
+__global__ __launch_bounds__(EC_WG) void k_ec_decode(const EcBlock *__restrict__ blk, uint64_t n,
+                                                     const uint8_t *__restrict__ words,
+                                                     const uint32_t *__restrict__ coded,
+                                                     uint32_t *__restrict__ raw) {
+  const uint64_t i = uint64_t(blockIdx.x) * EC_WG + threadIdx.x;
+  if (i >= n) return;
+  const EcBlock b = blk[i];
+  const uint32_t count = b.count;
+  const uint32_t W = (count + 31) >> 5;
+  const uint32_t nw = words[i];
+  const uint32_t *src = coded + b.coded_off;
+  uint32_t *dst = raw + b.raw_off;
+  if (nw >= W) {
+    for (uint32_t w = 0; w < W; ++w) dst[w] = src[w];
+    return;
+  }
+  const uint32_t nbytes = 4 * nw;
+  uint32_t pos = 0;      // next byte to read
+  uint32_t cur = 0;      // the word holding byte pos
+  auto next_byte = [&]() -> uint32_t {
+    if (pos >= nbytes) {
+      ++pos;
+      return 0u;
+    }
+    if ((pos & 3) == 0) cur = src[pos >> 2];
+    const uint32_t v = (cur >> (8 * (pos & 3))) & 0xFFu;
+    ++pos;
+    return v;
+  };
+  uint32_t code = 0;
+  for (int k = 0; k < 4; ++k) code = (code << 8) | next_byte();
+  uint32_t range = 0xFFFFFFFFu;
+  uint32_t p0 = PROB_ONE / 2;
+  for (uint32_t w = 0; w < W; ++w) {
+    const uint32_t nb = count - 32 * w < 32 ? count - 32 * w : 32;
+    uint32_t word = 0;
+    for (uint32_t j = 0; j < nb; ++j) {
+      const uint32_t bound = (range >> 12) * p0;
+      if (code < bound) {
+        range = bound;
+        p0 += (PROB_ONE - p0) >> 4;
+      } else {
+        code -= bound;
+        range -= bound;
+        p0 -= p0 >> 4;
+        word |= 1u << j;
+      }
+      while (range < TOP) {
+        code = (code << 8) | next_byte();
+        range <<= 8;
+      }
+    }
+    dst[w] = word;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_ec_encode(const EcBlock *blk, uint64_t n, const uint32_t *raw, uint32_t *scratch,
+                            uint8_t *words, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ec_encode, dim3(uint32_t((n + EC_WG - 1) / EC_WG)), dim3(EC_WG), 0, s, blk,
+                     n, raw, scratch, words);
+  return hipGetLastError();
+}
+
+hipError_t launch_ec_gather(const EcBlock *blk, uint64_t n, const uint8_t *words,
+                            const uint32_t *scratch, uint32_t *coded, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ec_gather, dim3(uint32_t((n + 3) / 4)), dim3(256), 0, s, blk, n, words,
+                     scratch, coded);
+  return hipGetLastError();
+}
+
+hipError_t launch_ec_decode(const EcBlock *blk, uint64_t n, const uint8_t *words,
+                            const uint32_t *coded, uint32_t *raw, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ec_decode, dim3(uint32_t((n + EC_WG - 1) / EC_WG)), dim3(EC_WG), 0, s, blk,
+                     n, words, coded, raw);
+  return hipGetLastError();
+}
+
+}  // namespace ipc

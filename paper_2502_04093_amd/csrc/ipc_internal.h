@@ -108,8 +108,14 @@ struct StreamMeta {
   std::vector<uint32_t> masks;      // [n_chunks]
   std::vector<OutlierRec> outliers; // sorted by (pass, chunk, local); may be left on the device
   uint64_t n_outliers = 0;
-  uint64_t payload_words = 0;       // packed payload size
+  uint64_t payload_words = 0;       // packed raw payload size
   uint64_t serialized_bytes = 0;
+  // entropy stage: 0 raw blocks, 1 every stored block entropy coded (then the
+  // serialized form holds the stored words of every block and coded_words
+  // payload words)
+  int coding = 0;
+  std::vector<uint8_t> block_words;  // [n_blocks], payload order
+  uint64_t coded_words = 0;
 };
 
 inline uint64_t pad8(uint64_t n) { return (n + 7) & ~uint64_t(7); }
@@ -122,5 +128,7 @@ bool parse_serialized(const uint8_t *buf, uint64_t n, StreamMeta &m, const uint3
                       std::string &err);
 void write_serialized_head(const StreamMeta &m, uint8_t *dst);  // everything before payload
 uint64_t payload_offset(const StreamMeta &m);
+// stored blocks (chunk planes) of a stream: sum of the mask popcounts
+uint64_t n_blocks(const StreamMeta &m);
 
 }  // namespace ipc

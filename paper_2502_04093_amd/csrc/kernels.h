@@ -166,4 +166,23 @@ hipError_t launch_pack_payload(const PassArgs &pa, const uint32_t *masks,
                                const uint64_t *packed_off, const uint32_t *slot_payload,
                                uint32_t *packed, hipStream_t stream);
 
+// ---- entropy stage (entropy.hip): one stored plane block of one chunk
+struct EcBlock {
+  uint64_t raw_off;    // first word of the raw plane (W = ceil(count / 32) words)
+  uint64_t coded_off;  // first word of its stored form in the coded payload
+  uint32_t count;      // codes of the chunk (bits of the block)
+  uint32_t pad;
+};
+// codes every block of raw into its scratch slot (scratch + raw_off, W words:
+// the code when shorter than W words, else the raw plane) and its stored word
+// count into words[i]
+hipError_t launch_ec_encode(const EcBlock *blk, uint64_t n, const uint32_t *raw, uint32_t *scratch,
+                            uint8_t *words, hipStream_t s);
+// words[i] stored words of every block from its scratch slot to coded_off
+hipError_t launch_ec_gather(const EcBlock *blk, uint64_t n, const uint8_t *words,
+                            const uint32_t *scratch, uint32_t *coded, hipStream_t s);
+// the raw plane of every block back from its stored form
+hipError_t launch_ec_decode(const EcBlock *blk, uint64_t n, const uint8_t *words,
+                            const uint32_t *coded, uint32_t *raw, hipStream_t s);
+
 }  // namespace ipc

@@ -228,16 +228,22 @@ PlanTables plan_tables_from_sizes(const StreamMeta &m, const std::vector<uint64_
   return t;
 }
 
+// plane sizes from the chunk masks; an entropy-coded stream charges every
+// block the words it stores
 PlanTables plan_tables(const StreamMeta &m) {
   const Schedule &s = m.sched;
   std::vector<uint64_t> sizes(s.passes.size() * 32, 0);
+  size_t blk = 0;
   for (const PassGeom &p : s.passes) {
     for (int64_t c = 0; c < p.n_chunks; ++c) {
       uint32_t mk = m.masks[size_t(p.chunk_base + c)];
       if (!mk) continue;
       uint64_t W = uint64_t((chunk_count(p, c) + 31) / 32);
-      for (int k = 0; k < 32; ++k)
-        if ((mk >> k) & 1u) sizes[size_t(p.index) * 32 + k] += 4 * W;
+      for (int k = 31; k >= 0; --k)
+        if ((mk >> k) & 1u) {
+          sizes[size_t(p.index) * 32 + k] += 4 * (m.coding ? uint64_t(m.block_words[blk]) : W);
+          ++blk;
+        }
     }
   }
   return plan_tables_from_sizes(m, sizes);

@@ -6,7 +6,10 @@
 // endian, every section zero-padded to 8 bytes):
 //   header (128 B) | errq [P][33] u32 | masks [n_chunks] u32 |
 //   outlier keys [n][3] u32 (pass, chunk, local) | outlier values [n] T |
-//   payload u32 (per pass, per chunk, stored planes from 31 down to 0).
+//   [entropy-coded streams: stored words of every block, u8] |
+//   payload u32 (per pass, per chunk, stored planes from 31 down to 0; each
+//   block raw, or entropy coded when that is shorter).
+// Header byte 11 holds the coding (0 raw, 1 entropy coded).
 #include "ipc_internal.h"
 
 #include <cmath>
@@ -35,7 +38,8 @@ static double getd(const uint8_t *p) {
 
 static int itemsize(int dtype) { return dtype == IPC_F32 ? 4 : 8; }
 
-static void section_sizes(const StreamMeta &m, uint64_t sz[6]) {
+// header, errq, masks, outlier keys, outlier values, block words, payload
+static void section_sizes(const StreamMeta &m, uint64_t sz[7]) {
   uint64_t P = m.sched.passes.size();
   uint64_t nout = m.n_outliers;
   sz[0] = HEADER_SIZE;
@@ -43,19 +47,26 @@ static void section_sizes(const StreamMeta &m, uint64_t sz[6]) {
   sz[2] = pad8(4 * uint64_t(m.sched.n_chunks));
   sz[3] = pad8(12 * nout);
   sz[4] = pad8(uint64_t(itemsize(m.dtype)) * nout);
-  sz[5] = pad8(4 * m.payload_words);
+  sz[5] = m.coding ? pad8(m.block_words.size()) : 0;
+  sz[6] = pad8(4 * (m.coding ? m.coded_words : m.payload_words));
 }
 
 uint64_t serialized_size(const StreamMeta &m) {
-  uint64_t sz[6];
+  uint64_t sz[7];
+  section_sizes(m, sz);
+  return sz[0] + sz[1] + sz[2] + sz[3] + sz[4] + sz[5] + sz[6];
+}
+
+uint64_t payload_offset(const StreamMeta &m) {
+  uint64_t sz[7];
   section_sizes(m, sz);
   return sz[0] + sz[1] + sz[2] + sz[3] + sz[4] + sz[5];
 }
 
-uint64_t payload_offset(const StreamMeta &m) {
-  uint64_t sz[6];
-  section_sizes(m, sz);
-  return sz[0] + sz[1] + sz[2] + sz[3] + sz[4];
+uint64_t n_blocks(const StreamMeta &m) {
+  uint64_t n = 0;
+  for (uint32_t mk : m.masks) n += uint64_t(__builtin_popcount(mk));
+  return n;
 }
 
 void packed_chunk_offsets(const StreamMeta &m, std::vector<uint64_t> &off) {
@@ -73,9 +84,9 @@ void packed_chunk_offsets(const StreamMeta &m, std::vector<uint64_t> &off) {
 }
 
 void write_serialized_head(const StreamMeta &m, uint8_t *dst) {
-  uint64_t sz[6];
+  uint64_t sz[7];
   section_sizes(m, sz);
-  std::memset(dst, 0, size_t(sz[0] + sz[1] + sz[2] + sz[3] + sz[4]));
+  std::memset(dst, 0, size_t(sz[0] + sz[1] + sz[2] + sz[3] + sz[4] + sz[5]));
   const Schedule &s = m.sched;
   uint8_t *h = dst;
   put32(h + 0, MAGIC);
@@ -83,7 +94,7 @@ void write_serialized_head(const StreamMeta &m, uint8_t *dst) {
   h[8] = uint8_t(m.dtype);
   h[9] = uint8_t(s.D);
   h[10] = uint8_t(m.interp);
-  h[11] = 0;
+  h[11] = uint8_t(m.coding);
   put32(h + 12, uint32_t(m.nonprog_levels));
   for (int j = 0; j < 3; ++j) put64(h + 16 + 8 * j, j < s.D ? uint64_t(s.dims[j]) : 1);
   putd(h + 40, m.eb);
@@ -94,7 +105,7 @@ void write_serialized_head(const StreamMeta &m, uint8_t *dst) {
   put32(h + 60, uint32_t(s.passes.size()));
   put64(h + 64, uint64_t(s.n_chunks));
   put64(h + 72, m.n_outliers);
-  put64(h + 80, m.payload_words);
+  put64(h + 80, m.coding ? m.coded_words : m.payload_words);
   putd(h + 88, m.maxabs);
   uint8_t *p = dst + sz[0];
   std::memcpy(p, m.errq.data(), 4 * m.errq.size());
@@ -114,6 +125,8 @@ void write_serialized_head(const StreamMeta &m, uint8_t *dst) {
     else
       put64(p + 8 * i, m.outliers[i].bits);
   }
+  p += sz[4];
+  if (m.coding) std::memcpy(p, m.block_words.data(), m.block_words.size());
 }
 
 bool parse_serialized(const uint8_t *buf, uint64_t n, StreamMeta &m, const uint32_t **payload,
@@ -130,9 +143,10 @@ bool parse_serialized(const uint8_t *buf, uint64_t n, StreamMeta &m, const uint3
   m.dtype = buf[8];
   int D = buf[9];
   m.interp = buf[10];
+  m.coding = buf[11];
   if ((m.dtype != IPC_F32 && m.dtype != IPC_F64) || D < 1 || D > 3 ||
-      (m.interp != IPC_LINEAR && m.interp != IPC_CUBIC) || buf[11] != 0) {
-    err = "bad dtype, ndim or interpolation field";
+      (m.interp != IPC_LINEAR && m.interp != IPC_CUBIC) || m.coding > 1) {
+    err = "bad dtype, ndim, interpolation or coding field";
     return false;
   }
   m.nonprog_levels = int(get32(buf + 12));
@@ -184,14 +198,26 @@ bool parse_serialized(const uint8_t *buf, uint64_t n, StreamMeta &m, const uint3
       return false;
     }
   m.payload_words = pw;
-  m.outliers.resize(nout);
+  m.coded_words = m.coding ? pw : 0;
   m.n_outliers = nout;
-  uint64_t sz[6];
+  uint64_t sz[7];
   section_sizes(m, sz);
-  if (sz[0] + sz[1] + sz[2] + sz[3] + sz[4] + sz[5] != n) {
+  if (sz[0] + sz[1] + sz[2] > n) {
+    err = "stream shorter than its tables";
+    return false;
+  }
+  if (m.coding) {
+    // the block-length section's size follows from the masks
+    m.masks.resize(nch);
+    std::memcpy(m.masks.data(), buf + sz[0] + sz[1], 4 * nch);
+    m.block_words.assign(size_t(n_blocks(m)), 0);
+    section_sizes(m, sz);
+  }
+  if (sz[0] + sz[1] + sz[2] + sz[3] + sz[4] + sz[5] + sz[6] != n) {
     err = "stream size does not match its header";
     return false;
   }
+  m.outliers.resize(nout);
   const uint8_t *p = buf + sz[0];
   m.errq.resize(33 * P);
   std::memcpy(m.errq.data(), p, 4 * m.errq.size());
@@ -214,8 +240,18 @@ bool parse_serialized(const uint8_t *buf, uint64_t n, StreamMeta &m, const uint3
   int is = itemsize(m.dtype);
   for (uint64_t i = 0; i < nout; ++i) m.outliers[i].bits = is == 4 ? get32(p + 4 * i) : get64(p + 8 * i);
   p += sz[4];
-  // masks and payload size
-  uint64_t words = 0;
+  if (m.coding) {
+    std::memcpy(m.block_words.data(), p, m.block_words.size());
+    for (uint64_t i = m.block_words.size(); i < sz[5]; ++i)
+      if (p[i]) {
+        err = "nonzero padding";
+        return false;
+      }
+    p += sz[5];
+  }
+  // masks and payload size; a coded block stores at most its raw words
+  uint64_t words = 0, stored = 0;
+  size_t blk = 0;
   for (const PassGeom &g : m.sched.passes) {
     for (int64_t c = 0; c < g.n_chunks; ++c) {
       uint32_t mk = m.masks[size_t(g.chunk_base + c)];
@@ -224,13 +260,23 @@ bool parse_serialized(const uint8_t *buf, uint64_t n, StreamMeta &m, const uint3
         err = "empty chunk with stored planes";
         return false;
       }
-      words += uint64_t(__builtin_popcount(mk)) * uint64_t((cnt + 31) / 32);
+      const uint64_t W = uint64_t((cnt + 31) / 32);
+      words += uint64_t(__builtin_popcount(mk)) * W;
+      if (m.coding)
+        for (int k = 0; k < __builtin_popcount(mk); ++k, ++blk) {
+          if (m.block_words[blk] > W) {
+            err = "block longer than its raw plane";
+            return false;
+          }
+          stored += m.block_words[blk];
+        }
     }
   }
-  if (words != pw) {
+  if (m.coding ? stored != pw : words != pw) {
     err = "payload size does not match the chunk masks";
     return false;
   }
+  m.payload_words = words;
   // outlier keys: in range and strictly increasing
   for (uint64_t i = 0; i < nout; ++i) {
     const OutlierRec &o = m.outliers[i];
@@ -254,7 +300,7 @@ bool parse_serialized(const uint8_t *buf, uint64_t n, StreamMeta &m, const uint3
     }
   }
   // padding bytes must be zero
-  for (uint64_t i = 4 * pw; i < sz[5]; ++i)
+  for (uint64_t i = 4 * pw; i < sz[6]; ++i)
     if (p[i]) {
       err = "nonzero padding";
       return false;

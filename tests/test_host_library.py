@@ -15,6 +15,7 @@ import pytest
 
 import fieldgen
 from oracle import codec, planner, predict
+from oracle.stream import entropy_code_stream, parse_stream
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ipcomp.h")
@@ -64,6 +65,8 @@ def _streams():
         x.reshape(-1)[5] = np.nan
         eb = rel * fieldgen.value_range(np.nan_to_num(x))
         STREAMS.append(codec.compress(x, eb, interp=interp, nonprog_levels=npl))
+    # the same streams with entropy-coded blocks (plane sizes = coded words)
+    STREAMS.extend([entropy_code_stream(b) for b in STREAMS])
     return STREAMS
 
 
@@ -130,6 +133,24 @@ def test_parser_rejects_corruption():
     bad.append(bytes(b))                                    # a chunk mask inconsistent with the payload
     b = bytearray(buf); b[128 + 33 * 4 * 2:128 + 33 * 4 * 2 + 4] = struct.pack("<I", 5)
     bad.append(bytes(b))                                    # delta-y with nothing discarded != 0
+    for bb in bad:
+        with pytest.raises(pkg.IpcError) as ei:
+            pkg.plan_host(bb, eb=1.0)
+        assert ei.value.status == -3
+
+
+def test_parser_rejects_corrupt_coded_streams():
+    _lib_or_skip()
+    raw = _streams()[0]
+    buf = entropy_code_stream(raw)
+    pkg.plan_host(buf, eb=1.0)
+    ps = parse_stream(buf)
+    boff = ps.payload_offset - ((ps.block_words.size + 7) & ~7)
+    bad = []
+    b = bytearray(buf); b[11] = 2; bad.append(bytes(b))                 # coding field
+    b = bytearray(buf); b[boff] = 255; bad.append(bytes(b))             # block longer than raw
+    b = bytearray(buf); b[11] = 0; bad.append(bytes(b))                 # coded body read as raw
+    b = bytearray(raw); b[11] = 1; bad.append(bytes(b))                 # raw body read as coded
     for bb in bad:
         with pytest.raises(pkg.IpcError) as ei:
             pkg.plan_host(bb, eb=1.0)
