@@ -42,12 +42,15 @@ def parse_args():
                     help="edge of the cubic sub-block the oracle compresses and retrieves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", choices=["c2", "c4-batch", "c5-serve"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c4-batch", "c5-serve", "entropy"], default="c2",
                     help="c2: the headline line (one field); c4-batch: --fields float64 "
                          "256x384x384 log-normal fields through the batched calls, beside "
                          "the same fields one call at a time; c5-serve: a Poisson request "
                          "mix over --fields resident fields through the serving loop, beside "
-                         "the same trace served one request at a time")
+                         "the same trace served one request at a time; entropy: the entropy "
+                         "stage on the 512^3 field (compression ratio, coder times) and on "
+                         "--fields 1800x3600 climate fields (bitrate retrievals planned on "
+                         "raw and on coded plane sizes)")
     ap.add_argument("--requests", type=int, default=600)
     ap.add_argument("--rate", type=float, default=2000.0, help="c5-serve arrivals per second")
     ap.add_argument("--budget-gib", type=float, default=32.0, help="c5-serve device-memory budget")
@@ -80,6 +83,8 @@ def main():
         return batch_main(args)
     if args.workload == "c5-serve":
         return serve_main(args)
+    if args.workload == "entropy":
+        return entropy_main(args)
     dev = "cuda:0"
     shape = tuple(args.shape)
     n = int(np.prod(shape))
@@ -280,6 +285,112 @@ def batch_main(args):
                                "eb=1e-5*range each, batched compress + full retrieve"},
         "plain_GBps": round(gb / tp, 3), "plain_ms_per_step": round(tp * 1e3, 4),
         "batch_speedup": round(tp / tb, 4),
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def entropy_main(args):
+    """Entropy stage.  (1) The 512^3 float32 field at --rel-eb * range:
+    serialized size raw and entropy coded, device time of the coding call
+    (codes every block, gathers the coded payload) and of loading the coded
+    bytes (upload + decode) beside loading the raw bytes.  (2) --fields
+    1800x3600 float32 climate fields (odd ones 30 % masked) at 1e-3 * range:
+    compression ratios, and retrievals at 1, 2 and 4 bits per value planned on
+    raw plane sizes and on coded ones (max error, PSNR)."""
+    import numpy as np
+    import torch
+
+    import fieldgen
+    import paper_2502_04093_amd as pkg
+
+    ctx = pkg.Context(0)
+    shape = tuple(args.shape)
+    print(f"[bench] generating {shape} field", file=sys.stderr, flush=True)
+    x = fieldgen.grf_torch(shape, -5.0 / 6.0, args.seed)
+    rng = float(x.max().double() - x.min().double())
+    eb = args.rel_eb * rng
+
+    def sync_time(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    t_code, t_load_raw, t_load_coded = [], [], []
+    raw_b = coded_b = None
+    for it in range(args.warmup + args.steps):
+        s = ctx.compress(x, eb)
+        if raw_b is None:
+            raw_b = s.to_bytes()
+        _, tc = sync_time(s.entropy_code)
+        if coded_b is None:
+            coded_b = s.to_bytes()
+        s.free()
+        s1, tr = sync_time(lambda: ctx.stream_from_bytes(raw_b))
+        s2, td = sync_time(lambda: ctx.stream_from_bytes(coded_b))
+        s1.free()
+        s2.free()
+        if it >= args.warmup:
+            t_code.append(tc)
+            t_load_raw.append(tr)
+            t_load_coded.append(td)
+        print(f"[bench] entropy step {it}: code {tc * 1e3:.2f} ms, load raw {tr * 1e3:.2f} ms, "
+              f"load coded {td * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    nbytes = x.numel() * 4
+    med = lambda v: float(np.median(v))
+    big = {
+        "shape": list(shape), "rel_eb": args.rel_eb,
+        "raw_stream_bytes": len(raw_b), "coded_stream_bytes": len(coded_b),
+        "cr_raw": round(nbytes / len(raw_b), 4), "cr_coded": round(nbytes / len(coded_b), 4),
+        "code_ms": round(med(t_code) * 1e3, 3),
+        "code_GBps_of_field": round(nbytes / med(t_code) / 1e9, 2),
+        "load_raw_ms": round(med(t_load_raw) * 1e3, 3),
+        "load_coded_ms": round(med(t_load_coded) * 1e3, 3),
+    }
+    del x
+    torch.cuda.empty_cache()
+
+    climate = []
+    for f in range(args.fields):
+        xf = fieldgen.climate_2d(f)
+        xd = torch.from_numpy(xf).to("cuda:0")
+        e = 1e-3 * fieldgen.value_range(xf)
+        r = fieldgen.value_range(xf)
+        s_raw = ctx.compress(xd, e)
+        s_cod = ctx.compress(xd, e).entropy_code()
+        row = {"field": f, "masked": bool(f % 2), "cr_raw": round(xf.nbytes / s_raw.nbytes, 3),
+               "cr_coded": round(xf.nbytes / s_cod.nbytes, 3)}
+        xd64 = xd.double()
+        for br in (1.0, 2.0, 4.0):
+            for tag, s in (("raw", s_raw), ("coded", s_cod)):
+                st = s.retrieve(bitrate=br)
+                err = (st.tensor().double() - xd64)
+                mx = float(err.abs().max())
+                mse = float((err * err).mean())
+                psnr = 20 * math.log10(r) - 10 * math.log10(mse) if mse > 0 else float("inf")
+                row[f"br{br:g}_{tag}_maxerr"] = mx
+                row[f"br{br:g}_{tag}_psnr"] = round(psnr, 2)
+                st.free()
+        s_raw.free()
+        s_cod.free()
+        climate.append(row)
+        print(f"[bench] climate field {f}: {row}", file=sys.stderr, flush=True)
+    mean = lambda k: round(float(np.mean([c[k] for c in climate])), 3)
+    summary = {"cr_raw": mean("cr_raw"), "cr_coded": mean("cr_coded")}
+    for br in ("1", "2", "4"):
+        for tag in ("raw", "coded"):
+            summary[f"br{br}_{tag}_psnr"] = mean(f"br{br}_{tag}_psnr")
+    out = {
+        "metric": "entropy-coded compression ratio, 512^3 f32 GRF, eb=1e-4*range",
+        "value": big["cr_coded"], "unit": "x", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": big["code_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"entropy stage: {'x'.join(map(str, shape))} f32 GRF k^-5/3 at "
+                               f"eb={args.rel_eb:g}*range; {args.fields} x 1800x3600 f32 climate "
+                               "fields at eb=1e-3*range, bitrate 1/2/4"},
+        "field512": big, "climate_mean": summary, "climate": climate,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
