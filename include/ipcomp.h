@@ -46,11 +46,16 @@ typedef enum {
 typedef enum { IPC_F32 = 0, IPC_F64 = 1 } ipc_dtype;
 typedef enum { IPC_LINEAR = 0, IPC_CUBIC = 1 } ipc_interp;
 typedef enum { IPC_TARGET_EB = 0, IPC_TARGET_BITRATE = 1 } ipc_target_kind;
+/* Or-ed into ipc_target.kind: plan with the paper's plane groups per level
+ * (Sec. 4.3: every pass of a level discards the same number of planes) instead
+ * of per pass.  The bound reported is the same per-pass bound (Thm. 1 read per
+ * pass); only the set of plans the planner chooses from is smaller. */
+#define IPC_TARGET_LEVEL_GROUPS 0x100
 
 /* Retrieval target (Sec. 5): an absolute L-infinity error bound, or a bitrate
  * in bits per value (the loaded bytes are at most bitrate * n / 8). */
 typedef struct {
-  int32_t kind;  /* ipc_target_kind */
+  int32_t kind;  /* ipc_target_kind, optionally | IPC_TARGET_LEVEL_GROUPS */
   double value;  /* > 0 */
 } ipc_target;
 

@@ -324,11 +324,11 @@ def open_stream(buf: bytes):
     return ps, sched, tables
 
 
-def make_plan(tables, mode: str, value: float, limit=None):
+def make_plan(tables, mode: str, value: float, limit=None, level_groups: bool = False):
     if mode == "eb":
-        plan, flags = planner.plan_error_bound(tables, value, limit)
+        plan, flags = planner.plan_error_bound(tables, value, limit, level_groups)
     elif mode == "bitrate":
-        plan, flags = planner.plan_bitrate(tables, value, limit)
+        plan, flags = planner.plan_bitrate(tables, value, limit, level_groups)
     else:
         raise ValueError("mode must be 'eb' or 'bitrate'")
     return plan, flags
@@ -359,21 +359,23 @@ def retrieve_with_plan(buf: bytes, plan, mode: str = "eb", target: Optional[floa
     return st
 
 
-def retrieve(buf: bytes, mode: str = "eb", value: float = 0.0) -> State:
-    """Alg. 1 with the plan chosen by the Sec. 5 planner for (mode, value)."""
+def retrieve(buf: bytes, mode: str = "eb", value: float = 0.0,
+             level_groups: bool = False) -> State:
+    """Alg. 1 with the plan chosen by the Sec. 5 planner for (mode, value);
+    ``level_groups`` plans with one discarded-plane count per level."""
     _, _, tables = open_stream(buf)
-    plan, flags = make_plan(tables, mode, value)
+    plan, flags = make_plan(tables, mode, value, level_groups=level_groups)
     return retrieve_with_plan(buf, plan, mode, value, flags)
 
 
-def refine(state: State, mode: str, value: float) -> State:
+def refine(state: State, mode: str, value: float, level_groups: bool = False) -> State:
     """Alg. 2 (recompute form): load only new planes, recompute from s_min."""
     tables = state.tables
     if mode == "eb" and value >= state.bound:
         state.flags = planner.FLAG_NOOP
         state.bytes_read = 0
         return state
-    plan, flags = make_plan(tables, mode, value, limit=state.plan)
+    plan, flags = make_plan(tables, mode, value, limit=state.plan, level_groups=level_groups)
     if np.array_equal(plan, state.plan):
         state.flags = flags | planner.FLAG_NOOP
         state.bytes_read = 0

@@ -35,6 +35,14 @@ Readings used:
   stream loads everything.
 * Anchors (pass 0) and the passes of the first ``nonprog_levels`` levels are
   always fully loaded.
+
+Variant (the paper's own grouping, Sec. 4.3): with ``level_groups`` every pass
+of a level discards the same number of planes, so the dynamic programs choose
+one b per level.  The bound of such a plan is still the per-pass bound above
+(the per-level factor of Thm. 1 is not an upper bound in D > 1); a level's
+term and bytes are the sums over its passes.  Its plans are a subset of the
+per-pass ones, so up to the discretization of the budget it loads at least as
+much for the same bound.
 """
 
 from __future__ import annotations
@@ -71,6 +79,7 @@ class PlanTables:
     n_points: int
     total_bytes: int
     fixed_bytes: int
+    levels: np.ndarray = None   # [P] level of every pass (pass 0: the anchors)
 
 
 def tables_from_stream(ps: ParsedStream) -> PlanTables:
@@ -118,7 +127,8 @@ def tables_from_stream(ps: ParsedStream) -> PlanTables:
                       unit_roundoff=UNIT_ROUNDOFF[h.dtype.itemsize],
                       maxabs=float(h.maxabs),
                       n_points=int(np.prod(h.dims, dtype=np.int64)),
-                      total_bytes=ps.total_bytes, fixed_bytes=ps.total_bytes - prog_bytes)
+                      total_bytes=ps.total_bytes, fixed_bytes=ps.total_bytes - prog_bytes,
+                      levels=np.array([p.level for p in sched.passes], dtype=np.int64))
 
 
 def rounding_step(t: PlanTables, M: float) -> float:
@@ -150,14 +160,45 @@ def loaded_bytes(t: PlanTables, plan) -> int:
     return tot
 
 
-def _allowed(t: PlanTables, s: int, limit) -> range:
-    if not t.progressive[s]:
+def plan_groups(t: PlanTables, level_groups: bool = False):
+    """Passes that share one discarded-plane count, in stream order: every
+    pass alone, or (level_groups) the anchors alone and then one group per
+    level."""
+    if not level_groups:
+        return [[s] for s in range(t.n_passes)]
+    groups = [[0]]
+    for s in range(1, t.n_passes):
+        if len(groups) > 1 and t.levels[groups[-1][0]] == t.levels[s]:
+            groups[-1].append(s)
+        else:
+            groups.append([s])
+    return groups
+
+
+def _allowed(t: PlanTables, g, limit) -> range:
+    """Choices of b for a group (a list of passes) or a single pass."""
+    if isinstance(g, (int, np.integer)):
+        g = [int(g)]
+    if not t.progressive[g[0]]:
         return range(0, 1)
-    hi = 32 if limit is None else int(limit[s])
+    hi = 32 if limit is None else min(int(limit[s]) for s in g)
     return range(0, hi + 1)
 
 
-def plan_error_bound(t: PlanTables, E: float, limit=None):
+def _group_term(t: PlanTables, g, b: int, r: float) -> float:
+    v = 0.0
+    for s in g:
+        if t.progressive[s]:
+            v = v + term(t, s, b, r)
+    return v
+
+
+def _group_bytes(t: PlanTables, g, lo: int, hi: int) -> int:
+    """Bytes of planes lo <= k < hi over the group's progressive passes."""
+    return int(sum(int(np.sum(t.sizes[s, lo:hi])) for s in g if t.progressive[s]))
+
+
+def plan_error_bound(t: PlanTables, E: float, limit=None, level_groups: bool = False):
     """Sec. 5.2: most bytes left unloaded subject to bound <= E.
 
     ``limit`` (refine) caps b per pass at the planes not yet loaded.
@@ -170,23 +211,25 @@ def plan_error_bound(t: PlanTables, E: float, limit=None):
     r = rounding_step(t, t.maxabs + E)
     u = R / G_UNITS
     NEG = np.iinfo(np.int64).min // 4
+    groups = plan_groups(t, level_groups)
+    NG = len(groups)
     F = np.zeros(G_UNITS + 1, dtype=np.int64)        # F_0[r] = 0
-    choices = np.zeros((P, G_UNITS + 1), dtype=np.int64)
-    costs = np.zeros((P, 33), dtype=np.int64)
-    for s in range(P):
+    choices = np.zeros((NG, G_UNITS + 1), dtype=np.int64)
+    costs = np.zeros((NG, 33), dtype=np.int64)
+    for gi, g in enumerate(groups):
         newF = np.full(G_UNITS + 1, NEG, dtype=np.int64)
         ch = np.zeros(G_UNITS + 1, dtype=np.int64)
-        for b in _allowed(t, s, limit):
-            tv = term(t, s, b, r) if t.progressive[s] else 0.0
+        for b in _allowed(t, g, limit):
+            tv = _group_term(t, g, b, r)
             if tv == 0.0:
                 c = 0
             else:
                 qv = tv / u if u > 0.0 else math.inf
                 c = math.floor(qv) + 1 if qv < G_UNITS else G_UNITS + 1
-            costs[s, b] = c
+            costs[gi, b] = c
             if c > G_UNITS:
                 continue
-            saved = int(np.sum(t.sizes[s, :b])) if t.progressive[s] else 0
+            saved = _group_bytes(t, g, 0, b)
             prev = F[:G_UNITS + 1 - c]
             cand = np.full(G_UNITS + 1, NEG, dtype=np.int64)
             cand[c:] = np.where(prev == NEG, NEG, prev + saved)
@@ -194,17 +237,17 @@ def plan_error_bound(t: PlanTables, E: float, limit=None):
             newF = np.where(better, cand, newF)
             ch = np.where(better, b, ch)
         F = newF
-        choices[s] = ch
+        choices[gi] = ch
     plan = np.zeros(P, dtype=np.int64)
     rr = G_UNITS
-    for s in range(P - 1, -1, -1):
-        b = int(choices[s, rr])
-        plan[s] = b
-        rr -= int(costs[s, b])
+    for gi in range(NG - 1, -1, -1):
+        b = int(choices[gi, rr])
+        plan[groups[gi]] = b
+        rr -= int(costs[gi, b])
     return plan, 0
 
 
-def plan_bitrate(t: PlanTables, bitrate: float, limit=None):
+def plan_bitrate(t: PlanTables, bitrate: float, limit=None, level_groups: bool = False):
     """Sec. 5.3: least bound subject to loaded bytes <= bitrate * n / 8.
 
     Returns (plan, flags).  With ``limit`` (refine) and a budget below the
@@ -230,19 +273,18 @@ def plan_bitrate(t: PlanTables, bitrate: float, limit=None):
     cap = budget // ub
     r = rounding_step(t, t.maxabs)
     INF = math.inf
+    groups = plan_groups(t, level_groups)
+    NG = len(groups)
     F = np.zeros(cap + 1, dtype=np.float64)          # F_0[r] = 0
-    choices = np.zeros((P, cap + 1), dtype=np.int64)
-    lcs = np.zeros((P, 33), dtype=np.int64)
-    for s in range(P):
+    choices = np.zeros((NG, cap + 1), dtype=np.int64)
+    lcs = np.zeros((NG, 33), dtype=np.int64)
+    for gi, g in enumerate(groups):
         newF = np.full(cap + 1, INF, dtype=np.float64)
         ch = np.zeros(cap + 1, dtype=np.int64)
-        for b in _allowed(t, s, limit):
-            if t.progressive[s]:
-                lc = -(-int(np.sum(t.sizes[s, b:])) // ub)
-                tv = term(t, s, b, r)
-            else:
-                lc, tv = 0, 0.0
-            lcs[s, b] = lc
+        for b in _allowed(t, g, limit):
+            lc = -(-_group_bytes(t, g, b, 32) // ub)
+            tv = _group_term(t, g, b, r)
+            lcs[gi, b] = lc
             if lc > cap:
                 continue
             cand = np.full(cap + 1, INF, dtype=np.float64)
@@ -251,16 +293,16 @@ def plan_bitrate(t: PlanTables, bitrate: float, limit=None):
             newF = np.where(better, cand, newF)
             ch = np.where(better, b, ch)
         F = newF
-        choices[s] = ch
+        choices[gi] = ch
     if not math.isfinite(F[cap]):
         # only reachable with a limit: nothing fits, keep what is loaded
         return np.asarray(limit, dtype=np.int64).copy(), FLAG_NOOP
     plan = np.zeros(P, dtype=np.int64)
     rr = cap
-    for s in range(P - 1, -1, -1):
-        b = int(choices[s, rr])
-        plan[s] = b
-        rr -= int(lcs[s, b])
+    for gi in range(NG - 1, -1, -1):
+        b = int(choices[gi, rr])
+        plan[groups[gi]] = b
+        rr -= int(lcs[gi, b])
     return plan, 0
 
 

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libipcomp.so")
 IPC_F32, IPC_F64 = 0, 1
 IPC_LINEAR, IPC_CUBIC = 0, 1
 IPC_TARGET_EB, IPC_TARGET_BITRATE = 0, 1
+IPC_TARGET_LEVEL_GROUPS = 0x100
 IPC_FLAG_CLAMPED_TO_EB, IPC_FLAG_BUDGET_BELOW_MIN, IPC_FLAG_NOOP = 1, 2, 4
 IPC_MAX_PASSES = 100
 STATUS = {0: "IPC_OK", -1: "IPC_EINVAL", -2: "IPC_ENOMEM", -3: "IPC_ECORRUPT", -4: "IPC_EHIP",
@@ -143,22 +144,27 @@ def _check(st: int, ctx=None):
         raise IpcError(st, msg)
 
 
-def _target(eb: Optional[float], bitrate: Optional[float]) -> ipc_target:
+def _target(eb: Optional[float], bitrate: Optional[float], level_groups: bool = False) -> ipc_target:
+    """Error-bound or bitrate target; level_groups plans with one discarded-
+    plane count per level (IPC_TARGET_LEVEL_GROUPS)."""
     if (eb is None) == (bitrate is None):
         raise ValueError("give exactly one of eb= and bitrate=")
+    flag = IPC_TARGET_LEVEL_GROUPS if level_groups else 0
     if eb is not None:
-        return ipc_target(IPC_TARGET_EB, float(eb))
-    return ipc_target(IPC_TARGET_BITRATE, float(bitrate))
+        return ipc_target(IPC_TARGET_EB | flag, float(eb))
+    return ipc_target(IPC_TARGET_BITRATE | flag, float(bitrate))
 
 
-def plan_host(stream_bytes: bytes, eb=None, bitrate=None, limit: Optional[Sequence[int]] = None):
+def plan_host(stream_bytes: bytes, eb=None, bitrate=None, limit: Optional[Sequence[int]] = None,
+              level_groups: bool = False):
     """Host-only planner: (plan, bound, flags, loaded_bytes) for a serialized stream."""
     L = lib()
     buf = ctypes.create_string_buffer(bytes(stream_bytes), len(stream_bytes))
     out = (c_uint8 * IPC_MAX_PASSES)()
     lim = (c_uint8 * IPC_MAX_PASSES)(*limit) if limit is not None else None
     bound, flags, loaded = c_double(), c_uint32(), c_uint64()
-    st = L.ipc_plan_host(buf, len(stream_bytes), _target(eb, bitrate), lim, out, IPC_MAX_PASSES,
+    st = L.ipc_plan_host(buf, len(stream_bytes), _target(eb, bitrate, level_groups), lim, out,
+                         IPC_MAX_PASSES,
                          ctypes.byref(bound), ctypes.byref(flags), ctypes.byref(loaded))
     _check(st)
     return list(out), bound.value, flags.value, loaded.value
@@ -406,10 +412,10 @@ class Stream:
         _check(lib().ipc_stream_to_host(self.ctx.handle, self._p, buf, n), self.ctx.handle)
         return buf.raw
 
-    def retrieve(self, eb=None, bitrate=None) -> "State":
+    def retrieve(self, eb=None, bitrate=None, level_groups: bool = False) -> "State":
         out = c_void_p()
         info = ipc_info()
-        _check(lib().ipc_retrieve(self.ctx.handle, self._p, _target(eb, bitrate),
+        _check(lib().ipc_retrieve(self.ctx.handle, self._p, _target(eb, bitrate, level_groups),
                                   ctypes.byref(out), ctypes.byref(info)), self.ctx.handle)
         return State(self, out, info)
 
@@ -463,9 +469,9 @@ class State:
         _check(lib().ipc_state_copy_field(self.stream.ctx.handle, self._p, c_void_p(t.data_ptr()),
                                           t.numel() * t.element_size()), self.stream.ctx.handle)
 
-    def refine(self, eb=None, bitrate=None) -> ipc_info:
+    def refine(self, eb=None, bitrate=None, level_groups: bool = False) -> ipc_info:
         info = ipc_info()
-        _check(lib().ipc_refine(self.stream.ctx.handle, self._p, _target(eb, bitrate),
+        _check(lib().ipc_refine(self.stream.ctx.handle, self._p, _target(eb, bitrate, level_groups),
                                 ctypes.byref(info)), self.stream.ctx.handle)
         if not info.flags & IPC_FLAG_NOOP:
             self.info = info

@@ -1434,7 +1434,8 @@ static ipc_status retrieve_common(ipc_ctx *ctx, const ipc_stream *s, const std::
 }
 
 static bool valid_target(ipc_target t) {
-  return (t.kind == IPC_TARGET_EB || t.kind == IPC_TARGET_BITRATE) && std::isfinite(t.value) &&
+  const int base = t.kind & ~IPC_TARGET_LEVEL_GROUPS;
+  return (base == IPC_TARGET_EB || base == IPC_TARGET_BITRATE) && std::isfinite(t.value) &&
          t.value > 0;
 }
 
@@ -1544,7 +1545,7 @@ ipc_status ipc_refine(ipc_ctx *ctx, ipc_state *st, ipc_target target, ipc_info *
   }
   const ipc_stream *s = st->stream;
   auto t0 = std::chrono::steady_clock::now();
-  if (target.kind == IPC_TARGET_EB && target.value >= st->bound) {
+  if ((target.kind & ~IPC_TARGET_LEVEL_GROUPS) == IPC_TARGET_EB && target.value >= st->bound) {
     fill_info(s, st->plan, st->bound, IPC_FLAG_NOOP, 0, 0.0f, 0.0f, info);
     return IPC_OK;
   }
@@ -1911,7 +1912,7 @@ ipc_status ipc_serve_batch(ipc_ctx *ctx, uint32_t n, ipc_request *req) {
     Job j{i, s, q.refine ? q.state : nullptr, PlanResult(), s->meta.sched.K, 0.0f, 0};
     if (q.refine) {
       ipc_state *st = q.state;
-      if (q.target.kind == IPC_TARGET_EB && q.target.value >= st->bound) {
+      if ((q.target.kind & ~IPC_TARGET_LEVEL_GROUPS) == IPC_TARGET_EB && q.target.value >= st->bound) {
         fill_info(s, st->plan, st->bound, IPC_FLAG_NOOP, 0, 0.0f, 0.0f, &q.info);
         continue;
       }

@@ -68,6 +68,7 @@ struct PlanTables {
   double two_eb = 0, eb = 0, unit_roundoff = 0, maxabs = 0;
   int64_t n_points = 0;
   int64_t total_bytes = 0, fixed_bytes = 0;
+  std::vector<int> level;          // [P] level of every pass (0: the anchors)
 };
 
 struct PlanResult {
@@ -77,7 +78,9 @@ struct PlanResult {
   int64_t loaded = 0;
 };
 
-// mode 0 = error bound, 1 = bitrate; limit may be null
+// mode 0 = error bound, 1 = bitrate, optionally or-ed with
+// IPC_TARGET_LEVEL_GROUPS (one discarded-plane count per level); limit may be
+// null
 PlanResult plan_request(const PlanTables &t, int mode, double value, const int *limit);
 double plan_bound(const PlanTables &t, const std::vector<int> &plan, double M);
 int64_t plan_loaded(const PlanTables &t, const std::vector<int> &plan);

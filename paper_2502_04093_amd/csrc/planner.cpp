@@ -15,6 +15,10 @@
 //  * Error budget in 1024 units of (E - eb); cost floor(term / unit) + 1 for a
 //    non-zero term.  Byte budget in at most 1024 units, costs rounded up.  Ties
 //    go to the smallest number of discarded planes, last pass first.
+//  * Variant (the paper's grouping, Sec. 4.3): with IPC_TARGET_LEVEL_GROUPS
+//    every pass of a level discards the same number of planes; the programs
+//    then choose one b per level, a level's term and bytes being the sums over
+//    its passes.  The bound stays the per-pass one above.
 #include "ipc_internal.h"
 
 #include <cmath>
@@ -48,12 +52,44 @@ int64_t plan_loaded(const PlanTables &t, const std::vector<int> &plan) {
   return tot;
 }
 
-static int allowed_hi(const PlanTables &t, int s, const int *limit) {
-  if (!t.progressive[s]) return 0;
-  return limit ? limit[s] : 32;
+// passes sharing one choice, in stream order: each pass alone, or the
+// anchors alone and then one group per level
+static std::vector<std::vector<int>> plan_groups(const PlanTables &t, bool per_level) {
+  std::vector<std::vector<int>> g;
+  for (int s = 0; s < t.P; ++s) {
+    if (per_level && s > 1 && t.level[s] == t.level[s - 1])
+      g.back().push_back(s);
+    else
+      g.push_back({s});
+  }
+  return g;
 }
 
-static PlanResult plan_eb(const PlanTables &t, double E, const int *limit) {
+static int allowed_hi(const PlanTables &t, const std::vector<int> &g, const int *limit) {
+  if (!t.progressive[g[0]]) return 0;
+  int hi = 32;
+  if (limit)
+    for (int s : g) hi = std::min(hi, limit[s]);
+  return hi;
+}
+
+static double group_term(const PlanTables &t, const std::vector<int> &g, int b, double r) {
+  double v = 0.0;
+  for (int s : g)
+    if (t.progressive[s]) v = v + term(t, s, b, r);
+  return v;
+}
+
+// bytes of planes lo <= k < hi over the group's progressive passes
+static int64_t group_bytes(const PlanTables &t, const std::vector<int> &g, int lo, int hi) {
+  int64_t v = 0;
+  for (int s : g)
+    if (t.progressive[s])
+      for (int k = lo; k < hi; ++k) v += t.sizes[size_t(s) * 32 + k];
+  return v;
+}
+
+static PlanResult plan_eb(const PlanTables &t, double E, const int *limit, bool per_level) {
   PlanResult res;
   const int P = t.P;
   res.plan.assign(P, 0);
@@ -65,17 +101,20 @@ static PlanResult plan_eb(const PlanTables &t, double E, const int *limit) {
   double r = rounding_step(t, t.maxabs + E);
   double u = R / G_UNITS;
   const int64_t NEG = std::numeric_limits<int64_t>::min() / 4;
+  const std::vector<std::vector<int>> groups = plan_groups(t, per_level);
+  const int NG = int(groups.size());
   std::vector<int64_t> F(G_UNITS + 1, 0), nF(G_UNITS + 1);
-  std::vector<uint8_t> choice(size_t(P) * (G_UNITS + 1), 0);
-  std::vector<int> cost(size_t(P) * 33, 0);
-  for (int s = 0; s < P; ++s) {
+  std::vector<uint8_t> choice(size_t(NG) * (G_UNITS + 1), 0);
+  std::vector<int> cost(size_t(NG) * 33, 0);
+  for (int gi = 0; gi < NG; ++gi) {
+    const std::vector<int> &g = groups[gi];
     std::fill(nF.begin(), nF.end(), NEG);
-    uint8_t *ch = &choice[size_t(s) * (G_UNITS + 1)];
-    int hi = allowed_hi(t, s, limit);
+    uint8_t *ch = &choice[size_t(gi) * (G_UNITS + 1)];
+    int hi = allowed_hi(t, g, limit);
     int64_t saved = 0;
     for (int b = 0; b <= hi; ++b) {
-      if (b > 0 && t.progressive[s]) saved += t.sizes[size_t(s) * 32 + (b - 1)];
-      double tv = t.progressive[s] ? term(t, s, b, r) : 0.0;
+      if (b > 0) saved += group_bytes(t, g, b - 1, b);
+      double tv = group_term(t, g, b, r);
       int c;
       if (tv == 0.0) {
         c = 0;
@@ -83,13 +122,12 @@ static PlanResult plan_eb(const PlanTables &t, double E, const int *limit) {
         double qv = u > 0.0 ? tv / u : std::numeric_limits<double>::infinity();
         c = (qv < double(G_UNITS)) ? int(std::floor(qv)) + 1 : G_UNITS + 1;
       }
-      cost[size_t(s) * 33 + b] = c;
+      cost[size_t(gi) * 33 + b] = c;
       if (c > G_UNITS) continue;
-      int64_t sv = t.progressive[s] ? saved : 0;
       for (int rr = c; rr <= G_UNITS; ++rr) {
         int64_t prev = F[rr - c];
         if (prev == NEG) continue;
-        int64_t cand = prev + sv;
+        int64_t cand = prev + saved;
         if (cand > nF[rr]) {
           nF[rr] = cand;
           ch[rr] = uint8_t(b);
@@ -99,15 +137,15 @@ static PlanResult plan_eb(const PlanTables &t, double E, const int *limit) {
     F.swap(nF);
   }
   int rr = G_UNITS;
-  for (int s = P - 1; s >= 0; --s) {
-    int b = choice[size_t(s) * (G_UNITS + 1) + rr];
-    res.plan[s] = b;
-    rr -= cost[size_t(s) * 33 + b];
+  for (int gi = NG - 1; gi >= 0; --gi) {
+    int b = choice[size_t(gi) * (G_UNITS + 1) + rr];
+    for (int s : groups[gi]) res.plan[s] = b;
+    rr -= cost[size_t(gi) * 33 + b];
   }
   return res;
 }
 
-static PlanResult plan_br(const PlanTables &t, double bitrate, const int *limit) {
+static PlanResult plan_br(const PlanTables &t, double bitrate, const int *limit, bool per_level) {
   PlanResult res;
   const int P = t.P;
   res.plan.assign(P, 0);
@@ -132,23 +170,20 @@ static PlanResult plan_br(const PlanTables &t, double bitrate, const int *limit)
   int64_t cap = budget / ub;
   double r = rounding_step(t, t.maxabs);
   const double INF = std::numeric_limits<double>::infinity();
+  const std::vector<std::vector<int>> groups = plan_groups(t, per_level);
+  const int NG = int(groups.size());
   std::vector<double> F(cap + 1, 0.0), nF(cap + 1);
-  std::vector<uint8_t> choice(size_t(P) * (cap + 1), 0);
-  std::vector<int64_t> lcs(size_t(P) * 33, 0);
-  for (int s = 0; s < P; ++s) {
+  std::vector<uint8_t> choice(size_t(NG) * (cap + 1), 0);
+  std::vector<int64_t> lcs(size_t(NG) * 33, 0);
+  for (int gi = 0; gi < NG; ++gi) {
+    const std::vector<int> &g = groups[gi];
     std::fill(nF.begin(), nF.end(), INF);
-    uint8_t *ch = &choice[size_t(s) * (cap + 1)];
-    int hi = allowed_hi(t, s, limit);
+    uint8_t *ch = &choice[size_t(gi) * (cap + 1)];
+    int hi = allowed_hi(t, g, limit);
     for (int b = 0; b <= hi; ++b) {
-      int64_t lc = 0;
-      double tv = 0.0;
-      if (t.progressive[s]) {
-        int64_t load = 0;
-        for (int k = b; k < 32; ++k) load += t.sizes[size_t(s) * 32 + k];
-        lc = (load + ub - 1) / ub;
-        tv = term(t, s, b, r);
-      }
-      lcs[size_t(s) * 33 + b] = lc;
+      const int64_t lc = (group_bytes(t, g, b, 32) + ub - 1) / ub;
+      const double tv = group_term(t, g, b, r);
+      lcs[size_t(gi) * 33 + b] = lc;
       if (lc > cap) continue;
       for (int64_t rr = lc; rr <= cap; ++rr) {
         double cand = F[rr - lc] + tv;
@@ -166,24 +201,26 @@ static PlanResult plan_br(const PlanTables &t, double bitrate, const int *limit)
     return res;
   }
   int64_t rr = cap;
-  for (int s = P - 1; s >= 0; --s) {
-    int b = choice[size_t(s) * (cap + 1) + rr];
-    res.plan[s] = b;
-    rr -= lcs[size_t(s) * 33 + b];
+  for (int gi = NG - 1; gi >= 0; --gi) {
+    int b = choice[size_t(gi) * (cap + 1) + rr];
+    for (int s : groups[gi]) res.plan[s] = b;
+    rr -= lcs[size_t(gi) * 33 + b];
   }
   return res;
 }
 
 PlanResult plan_request(const PlanTables &t, int mode, double value, const int *limit) {
   PlanResult res;
+  const bool per_level = (mode & IPC_TARGET_LEVEL_GROUPS) != 0;
+  mode &= ~IPC_TARGET_LEVEL_GROUPS;
   if (mode == IPC_TARGET_EB) {
-    res = plan_eb(t, value, limit);
+    res = plan_eb(t, value, limit, per_level);
     if (value < t.eb)
       res.bound = plan_bound(t, res.plan, t.maxabs);
     else
       res.bound = plan_bound(t, res.plan, t.maxabs + value);
   } else {
-    res = plan_br(t, value, limit);
+    res = plan_br(t, value, limit, per_level);
     double b0 = plan_bound(t, res.plan, t.maxabs);
     res.bound = plan_bound(t, res.plan, 2.0 * (t.maxabs + b0));
   }
@@ -225,6 +262,8 @@ PlanTables plan_tables_from_sizes(const StreamMeta &m, const std::vector<uint64_
     if (t.progressive[s2])
       for (int k = 0; k < 32; ++k) prog += t.sizes[size_t(s2) * 32 + k];
   t.fixed_bytes = t.total_bytes - prog;
+  t.level.assign(t.P, 0);
+  for (const PassGeom &p : s.passes) t.level[p.index] = p.level;
   return t;
 }
 

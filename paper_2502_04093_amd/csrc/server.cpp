@@ -209,7 +209,8 @@ ipc_status ipc_server_create(ipc_ctx *ctx, uint64_t budget_bytes, uint32_t max_b
 ipc_status ipc_server_submit(ipc_server *srv, const ipc_stream *stream, ipc_state *refine_state,
                              ipc_target target, uint64_t *ticket) {
   if (!srv || !ticket || (!stream && !refine_state)) return IPC_EINVAL;
-  if (!(target.kind == IPC_TARGET_EB || target.kind == IPC_TARGET_BITRATE) || !(target.value > 0))
+  const int base = target.kind & ~IPC_TARGET_LEVEL_GROUPS;
+  if (!(base == IPC_TARGET_EB || base == IPC_TARGET_BITRATE) || !(target.value > 0))
     return IPC_EINVAL;
   Pending p{};
   p.refine = refine_state != nullptr;

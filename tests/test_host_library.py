@@ -6,6 +6,7 @@
 * Its stream parser accepts every oracle stream and rejects corrupted ones.
 """
 
+import ctypes
 import os
 import re
 import struct
@@ -164,3 +165,44 @@ def test_parser_rejects_bad_targets():
         with pytest.raises(pkg.IpcError) as ei:
             pkg.plan_host(buf, eb=v)
         assert ei.value.status == -1
+
+
+def test_level_group_planner_matches_oracle():
+    """The paper's per-level plane groups (IPC_TARGET_LEVEL_GROUPS): the C++
+    planner equals the oracle's, raw and entropy-coded streams, with and
+    without a refine limit."""
+    _lib_or_skip()
+    rng = np.random.default_rng(4)
+    for buf in _streams():
+        _, _, t = codec.open_stream(buf)
+        scale = max(t.maxabs, 1e-12)
+        for rel in (1e-5, 1e-3, 1e-1, 1.0):
+            E = rel * scale
+            plan, flags = codec.make_plan(t, "eb", E, level_groups=True)
+            cplan, cb, cf, cl = pkg.plan_host(buf, eb=E, level_groups=True)
+            assert cplan[:t.n_passes] == list(plan)
+            assert cb == planner.reported_bound(t, plan, "eb", E) and cf == flags
+            assert cl == planner.loaded_bytes(t, plan)
+        for br in (0.5, 2.0, 8.0):
+            plan, flags = codec.make_plan(t, "bitrate", br, level_groups=True)
+            cplan, cb, cf, cl = pkg.plan_host(buf, bitrate=br, level_groups=True)
+            assert cplan[:t.n_passes] == list(plan)
+            assert cb == planner.reported_bound(t, plan, "bitrate", br) and cf == flags
+        for _ in range(4):
+            limit = rng.integers(0, 33, t.n_passes)
+            limit[~t.progressive] = 0
+            E = float(rng.uniform(0.01, 1.0)) * scale
+            plan, flags = codec.make_plan(t, "eb", E, np.asarray(limit), level_groups=True)
+            cplan, cb, cf, cl = pkg.plan_host(buf, eb=E, limit=list(limit), level_groups=True)
+            assert cplan[:t.n_passes] == list(plan)
+
+
+def test_target_flags_validated():
+    _lib_or_skip()
+    buf = _streams()[0]
+    L = pkg.lib()
+    out = (ctypes.c_uint8 * pkg.IPC_MAX_PASSES)()
+    for kind in (0x200, 0x101 | 0x400, 7):
+        st = L.ipc_plan_host(buf, len(buf), pkg.ipc_target(kind, 1.0), None, out, pkg.IPC_MAX_PASSES,
+                             None, None, None)
+        assert st == -1
