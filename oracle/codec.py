@@ -14,8 +14,9 @@ The retrieval reads only the stream.
 Refinement (Alg. 2, recompute form): merge the newly loaded planes into the
 codes already held and recompute every pass from the first one whose codes
 changed; coarser values are reused.  The result is bit-identical to a fresh
-retrieval with the same plan.  (The paper's additive-Delta form agrees only up
-to rounding and is not used.)
+retrieval with the same plan.  The paper's additive form (a difference field
+predicted from itself and added to the current reconstruction) is the variant
+``refine_additive``; it agrees with a fresh retrieval only up to rounding.
 """
 
 from __future__ import annotations
@@ -402,9 +403,89 @@ def refine(state: State, mode: str, value: float, level_groups: bool = False) ->
     return state
 
 
+def _add_delta_from(state: State, s_min: int, old_plan):
+    """Additive form of Alg. 2: the difference field Delta is predicted pass
+    by pass from Delta itself (interpolation is linear) plus the dequantized
+    code difference of the pass, outliers contributing nothing; then
+    x_new = x_old + Delta wherever Delta is not zero."""
+    ps, sched = state.parsed, state.sched
+    h = ps.header
+    dt = h.dtype
+    two_eb, _ = predict.quant_constants(dt, h.eb)
+    keys = ps.out_keys
+    delta = np.zeros_like(state.field)
+    for p in sched.passes:
+        if p.index < s_min:
+            continue
+        assert p.index > 0, "the anchors are always fully loaded"
+        pdat = state.passes[p.index]
+        mn = coding.keep_mask(int(state.plan[p.index]))
+        mo = coding.keep_mask(int(old_plan[p.index]))
+        qn = coding.from_negabinary(coding.xor_decode(pdat.e & mn) & mn)
+        qo = coding.from_negabinary(coding.xor_decode(pdat.e & mo) & mo)
+        dq = np.zeros(p.n_targets, dtype=np.int64)
+        if p.n_targets:
+            dq[canonical_order(p)] = qn - qo
+        dq = dq.reshape(p.tdims)
+        with np.errstate(all="ignore"):
+            pred = _pass_prediction(delta, p, h.interp)
+            vals = pred + dq.astype(dt) * two_eb
+        sel = np.nonzero(keys[:, 0] == p.index)[0] if keys.size else np.zeros(0, np.int64)
+        if sel.size:
+            order = canonical_order(p)
+            cstart = np.concatenate([[0], np.cumsum(p.chunk_counts)[:-1]]).astype(np.int64)
+            pos = cstart[keys[sel, 1].astype(np.int64)] + keys[sel, 2].astype(np.int64)
+            flat = vals.reshape(-1).copy()
+            flat[order[pos]] = 0
+            vals = flat.reshape(vals.shape)
+        _store_pass(delta, p, vals)
+    nz = delta != 0
+    with np.errstate(all="ignore"):
+        state.field[nz] = state.field[nz] + delta[nz]
+
+
+def refine_additive(state: State, mode: str, value: float, level_groups: bool = False) -> State:
+    """Alg. 2 in the paper's additive form (a variant): plan and load the new
+    planes as :func:`refine` does, then add the difference field to the
+    current reconstruction instead of recomputing it.  The result agrees with
+    a fresh retrieval only up to rounding; its bound is
+    :func:`planner.additive_bound`."""
+    tables = state.tables
+    if mode == "eb" and value >= state.bound:
+        state.flags = planner.FLAG_NOOP
+        state.bytes_read = 0
+        return state
+    plan, flags = make_plan(tables, mode, value, limit=state.plan, level_groups=level_groups)
+    if np.array_equal(plan, state.plan):
+        state.flags = flags | planner.FLAG_NOOP
+        state.bytes_read = 0
+        return state
+    old_plan = state.plan.copy()
+    offs = _chunk_word_offsets(state.parsed, state.sched)
+    s_min = None
+    nread = 0
+    for p in state.sched.passes:
+        b_new, b_old = int(plan[p.index]), int(old_plan[p.index])
+        if b_new < b_old:
+            c0, starts, bstarts = offs[p.index]
+            e_new, nb = _load_planes(state.parsed, p, c0, starts, b_new, b_old, bstarts)
+            nread += nb
+            state.passes[p.index].e = state.passes[p.index].e | e_new
+            state.passes[p.index].b = b_new
+            if s_min is None:
+                s_min = p.index
+    state.plan = plan.copy()
+    state.bound = planner.additive_bound(tables, plan, old_plan, mode, value)
+    state.bytes_read = nread
+    state.flags = flags
+    if s_min is not None:
+        _add_delta_from(state, s_min, old_plan)
+    return state
+
+
 def stream_dtype(buf: bytes):
     return parse_stream(buf).header.dtype
 
 
-__all__ = ["compress", "retrieve", "retrieve_with_plan", "refine", "open_stream",
+__all__ = ["compress", "retrieve", "retrieve_with_plan", "refine", "refine_additive", "open_stream",
            "make_plan", "State", "DTYPES"]

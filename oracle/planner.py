@@ -321,6 +321,39 @@ def reported_bound(t: PlanTables, plan, mode: str, target: float) -> float:
     return bound_of(t, plan, 2.0 * (t.maxabs + b0))
 
 
+def reported_magnitude(t: PlanTables, plan, mode: str, target: float) -> float:
+    """The magnitude bound M that reported_bound uses."""
+    if mode == "eb":
+        return t.maxabs if target < t.eb else t.maxabs + target
+    return 2.0 * (t.maxabs + bound_of(t, plan, t.maxabs))
+
+
+def additive_bound(t: PlanTables, plan, old_plan, mode: str, target: float) -> float:
+    """Bound reported by the additive form of Alg. 2 (x_new = x_old + Delta).
+
+    Reading: the reported bound of the new plan plus what the additive form
+    rounds where a fresh reconstruction does not -- the old reconstruction's
+    own rounding (the rounding terms T_s r of the old plan's lossy passes), the
+    rounding of the difference field (charged as if every progressive pass
+    were lossy: T_s1 r, s1 the first progressive pass) and the final addition
+    (u M).
+    """
+    M = reported_magnitude(t, plan, mode, target)
+    r = rounding_step(t, M)
+    a = reported_bound(t, plan, mode, target)
+    first = None
+    for s in range(t.n_passes):
+        if not t.progressive[s]:
+            continue
+        if first is None:
+            first = s
+        if int(old_plan[s]) > 0:
+            a = a + t.tail[s] * r
+    if first is not None:
+        a = a + t.tail[first] * r
+    return a + t.unit_roundoff * M
+
+
 def fixed_section_bytes(ps: ParsedStream) -> int:
     """Bytes before the payload (with the block lengths of a coded stream)."""
     return ps.payload_offset

@@ -108,3 +108,68 @@ def test_level_groups_cost_at_least_per_pass():
             assert len(set(int(pl[s]) for s in g)) == 1
         assert planner.bound_of(t, pl, t.maxabs + E) <= E
         assert planner.loaded_bytes(t, pl) >= 0.97 * planner.loaded_bytes(t, pp)
+
+
+# ---------------------------------------------------------------------------
+# Alg. 2 in its additive form
+
+
+@pytest.mark.parametrize("interp", [predict.LINEAR, predict.CUBIC])
+@pytest.mark.parametrize("shape", [(17, 33, 20), (65, 90), (700,)])
+def test_additive_refine_exact_on_dyadic_data(interp, shape):
+    """Integer data, eb = 1/2 (2 eb = 1), float64: every prediction, code and
+    reconstruction is a short dyadic fraction, so all arithmetic is exact and
+    the additive form must equal a fresh reconstruction bit for bit (any
+    dropped or misplaced term of the difference field breaks this)."""
+    rng = np.random.default_rng(len(shape) * 7 + interp)
+    x = np.cumsum(rng.integers(-40, 41, size=shape), axis=-1).astype(np.float64)
+    buf = codec.compress(x, 0.5, interp=interp)
+    _, _, t = codec.open_stream(buf)
+    plan = np.where(t.progressive, 20, 0)
+    st = codec.retrieve_with_plan(buf, plan)
+    for b in (14, 9, 5, 2, 0):
+        target = np.where(t.progressive, np.minimum(plan, b), 0)
+        # refine to an explicit plan through the error-bound planner's limit
+        E = planner.bound_of(t, target, t.maxabs + 1e9)
+        st = codec.refine_additive(st, "eb", E)
+        fresh = codec.retrieve_with_plan(buf, st.plan)
+        assert st.field.tobytes() == fresh.field.tobytes()
+        plan = st.plan
+
+
+@pytest.mark.parametrize("dt,rel", [(np.float32, 1e-6), (np.float64, 1e-10)])
+def test_additive_refine_within_its_bound(dt, rel):
+    x = fieldgen.grf((24, 40, 64), -5.0 / 6.0, seed=9, dtype=dt)
+    r = fieldgen.value_range(x)
+    buf = codec.compress(x, rel * r)
+    st = codec.retrieve(buf, "eb", 1e-2 * r)
+    total = st.bytes_read
+    for e in (1e-3, 1e-4, 1e-5, rel):
+        prev = st.bound
+        st = codec.refine_additive(st, "eb", e * r)
+        total += st.bytes_read
+        fresh = codec.retrieve_with_plan(buf, st.plan, "eb", e * r)
+        err = float(np.max(np.abs(st.field.astype(np.float64) - x)))
+        assert err <= st.bound
+        # the additive form differs from the fresh one by rounding only
+        gap = float(np.max(np.abs(st.field.astype(np.float64) - fresh.field)))
+        assert gap <= st.bound - fresh.bound
+        assert st.bound >= fresh.bound and (st.bound < prev or st.flags)
+    assert total == codec.retrieve_with_plan(buf, st.plan).bytes_read
+
+
+def test_additive_refine_noop_and_outliers():
+    """Outliers (NaN, inf, huge) keep their exact values through additive
+    refinements; a target already met loads nothing."""
+    x = fieldgen.random_field((30, 41), seed=4, dtype=np.float32)
+    r = fieldgen.value_range(x)
+    f = x.reshape(-1)
+    f[10], f[500], f[900] = np.nan, np.inf, 3e37
+    buf = codec.compress(x, 1e-6 * r)
+    st = codec.retrieve(buf, "eb", 1e-2 * r)
+    st = codec.refine_additive(st, "eb", 1e-5 * r)
+    g = st.field.reshape(-1)
+    assert np.isnan(g[10]) and g[500] == np.inf and g[900] == np.float32(3e37)
+    b = st.bound
+    st = codec.refine_additive(st, "eb", 2 * b)
+    assert st.flags & planner.FLAG_NOOP and st.bytes_read == 0 and st.bound == b
