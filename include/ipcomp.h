@@ -172,6 +172,18 @@ ipc_status ipc_stream_passes(const ipc_stream *s, uint32_t *n_passes);
 ipc_status ipc_refine(ipc_ctx *ctx, ipc_state *st, ipc_target target, ipc_info *info);
 void ipc_state_free(ipc_state *st);
 
+/* Refinement in the paper's additive form (Alg. 2, a variant of ipc_refine):
+ * plans and reads the new planes as ipc_refine does, then predicts a
+ * difference field from itself pass by pass (interpolation is linear) with
+ * the code differences of the newly loaded planes, outliers adding nothing,
+ * and adds it to the current reconstruction wherever it is not zero.  The
+ * result agrees with a fresh retrieval only up to rounding; the reported bound
+ * adds a rounding allowance to the plan's bound (the old reconstruction's
+ * rounding terms, the difference field's, and u M for the addition).  Runs
+ * the one-pass-per-launch kernels for every shape.  Uses a context working
+ * buffer of the field's size. */
+ipc_status ipc_refine_additive(ipc_ctx *ctx, ipc_state *st, ipc_target target, ipc_info *info);
+
 /* Batches (beyond the paper, which compresses one field at a time): n fields
  * or streams in one call.  Fields of 3-D shape with the default chunk shape
  * share one kernel launch per level (a work list of every field's column

@@ -74,6 +74,7 @@ SIGNATURES = {
     "ipc_stream_from_host": (c_int, [c_void_p, c_void_p, c_uint64, P(c_void_p)]),
     "ipc_stream_free": (None, [c_void_p]),
     "ipc_stream_entropy_code": (c_int, [c_void_p, c_void_p]),
+    "ipc_refine_additive": (c_int, [c_void_p, c_void_p, ipc_target, P(ipc_info)]),
     "ipc_stream_coding": (c_int, [c_void_p, P(c_int)]),
     "ipc_stream_passes": (c_int, [c_void_p, P(c_uint32)]),
     "ipc_stream_pass_info": (c_int, [c_void_p, c_uint32, P(ipc_pass_info)]),
@@ -473,6 +474,16 @@ class State:
         info = ipc_info()
         _check(lib().ipc_refine(self.stream.ctx.handle, self._p, _target(eb, bitrate, level_groups),
                                 ctypes.byref(info)), self.stream.ctx.handle)
+        if not info.flags & IPC_FLAG_NOOP:
+            self.info = info
+        return info
+
+    def refine_additive(self, eb=None, bitrate=None, level_groups: bool = False) -> ipc_info:
+        """ipc_refine_additive: the paper's additive form of Alg. 2."""
+        info = ipc_info()
+        _check(lib().ipc_refine_additive(self.stream.ctx.handle, self._p,
+                                         _target(eb, bitrate, level_groups), ctypes.byref(info)),
+               self.stream.ctx.handle)
         if not info.flags & IPC_FLAG_NOOP:
             self.info = info
         return info

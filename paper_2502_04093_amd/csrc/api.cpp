@@ -493,9 +493,8 @@ void ensure_coarse(ipc_ctx *ctx, const Schedule &s, size_t isz) {
     ensure_ws(ctx, ctx->ws_g[i], ctx->ws_g_bytes[i], std::max<size_t>(need[i], 8));
 }
 
-// run passes [s0, P) of a retrieval into `field`
-void run_retrieve(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &plan, int s0,
-                  void *field) {
+// what the retrieval kernels read of a stream
+RetrieveIn retrieve_in(ipc_ctx *ctx, const ipc_stream *s) {
   RetrieveIn in;
   in.payload = static_cast<const uint32_t *>(s->payload.p);
   in.masks = static_cast<const uint32_t *>(s->masks.p);
@@ -506,6 +505,13 @@ void run_retrieve(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &pla
   in.out_start = static_cast<const uint32_t *>(s->out_start.p);
   in.n_out = s->meta.n_outliers;
   in.zero = static_cast<const uint32_t *>(ctx->dev_zero);
+  return in;
+}
+
+// run passes [s0, P) of a retrieval into `field`
+void run_retrieve(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &plan, int s0,
+                  void *field) {
+  const RetrieveIn in = retrieve_in(ctx, s);
   prof_begin(ctx, s->args.size());
   const Schedule &sc = s->meta.sched;
   if (fused3(sc)) {
@@ -1573,6 +1579,61 @@ ipc_status ipc_refine(ipc_ctx *ctx, ipc_state *st, ipc_target target, ipc_info *
     uint64_t read = plane_bytes_between(s, pr.plan, st->plan);
     st->plan = pr.plan;
     st->bound = pr.bound;
+    fill_info(s, st->plan, st->bound, pr.flags, read, tplan, ms, info);
+  });
+}
+
+ipc_status ipc_refine_additive(ipc_ctx *ctx, ipc_state *st, ipc_target target, ipc_info *info) {
+  if (!ctx || !st) return IPC_EINVAL;
+  if (st->ctx != ctx) {
+    set_err(ctx, "state belongs to another context");
+    return IPC_ESTATE;
+  }
+  if (!valid_target(target)) {
+    set_err(ctx, "target value must be finite and > 0");
+    return IPC_EINVAL;
+  }
+  const ipc_stream *s = st->stream;
+  auto t0 = std::chrono::steady_clock::now();
+  if ((target.kind & ~IPC_TARGET_LEVEL_GROUPS) == IPC_TARGET_EB && target.value >= st->bound) {
+    fill_info(s, st->plan, st->bound, IPC_FLAG_NOOP, 0, 0.0f, 0.0f, info);
+    return IPC_OK;
+  }
+  PlanResult pr = plan_request(s->tables, target.kind, target.value, st->plan.data());
+  float tplan = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (pr.plan == st->plan) {
+    fill_info(s, st->plan, st->bound, pr.flags | IPC_FLAG_NOOP, 0, tplan, 0.0f, info);
+    return IPC_OK;
+  }
+  int s_min = -1;
+  for (size_t i = 0; i < pr.plan.size(); ++i)
+    if (pr.plan[i] < st->plan[i]) {
+      s_min = int(i);
+      break;
+    }
+  return guarded(ctx, [&] {
+    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    const size_t isz = s->meta.dtype == IPC_F32 ? 4 : 8;
+    const uint64_t n = uint64_t(s->meta.sched.n_points);
+    // the difference field lives in the per-pass working buffer
+    void *delta = ensure_ws(ctx, ctx->ws_xh, ctx->ws_xh_bytes, size_t(n) * isz);
+    const RetrieveIn in = retrieve_in(ctx, s);
+    hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
+    hip_check(ctx, hipMemsetAsync(delta, 0, size_t(n) * isz, ctx->stream), "memset");
+    for (size_t i = size_t(s_min); i < s->args.size(); ++i)
+      hip_check(ctx, launch_retrieve_pass(s->meta.dtype, s->meta.interp, s->args[i], delta, pr.plan[i],
+                                          in, s->meta.eb, ctx->stream, st->plan[i]),
+                "additive pass launch");
+    hip_check(ctx, launch_add_delta(s->meta.dtype, st->field.p, delta, n, ctx->stream), "add launch");
+    hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
+    hip_check(ctx, hipStreamSynchronize(ctx->stream), "refine");
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    uint64_t read = plane_bytes_between(s, pr.plan, st->plan);
+    const double bound = plan_additive_bound(s->tables, pr.plan, st->plan, target.kind, target.value,
+                                             pr.bound);
+    st->plan = pr.plan;
+    st->bound = bound;
     fill_info(s, st->plan, st->bound, pr.flags, read, tplan, ms, info);
   });
 }

@@ -84,6 +84,10 @@ struct PlanResult {
 PlanResult plan_request(const PlanTables &t, int mode, double value, const int *limit);
 double plan_bound(const PlanTables &t, const std::vector<int> &plan, double M);
 int64_t plan_loaded(const PlanTables &t, const std::vector<int> &plan);
+// bound of the additive form of Alg. 2 after refining old_plan to plan
+// (`reported` = plan_request's bound for plan)
+double plan_additive_bound(const PlanTables &t, const std::vector<int> &plan,
+                           const std::vector<int> &old_plan, int mode, double value, double reported);
 
 // ---------------------------------------------------------------- format
 constexpr uint32_t MAGIC = 0x4D435049u;  // "IPCM"

@@ -141,8 +141,15 @@ hipError_t launch_gather_coarse(int dtype, const void *field, const int64_t fd[3
 hipError_t launch_compress_pass(int dtype, int interp, const PassArgs &pa, const void *x, void *xh,
                                 int write_back, double eb, const CompressOut &o,
                                 hipStream_t stream);
+// discard_old >= 0: the additive form of Alg. 2 (field is the difference
+// field; codes are the differences of the truncations at discard and
+// discard_old planes; outliers add zero)
 hipError_t launch_retrieve_pass(int dtype, int interp, const PassArgs &pa, void *field,
-                                int discard, const RetrieveIn &in, double eb, hipStream_t stream);
+                                int discard, const RetrieveIn &in, double eb, hipStream_t stream,
+                                int discard_old = -1);
+// field[i] += delta[i] wherever delta[i] != 0
+hipError_t launch_add_delta(int dtype, void *field, const void *delta, uint64_t n,
+                            hipStream_t stream);
 // Outlier index built on the device from the compression kernels' records
 // (any order, count *n_out, at most cap used): gchunk/local/bits sorted by
 // (global chunk, local) and start[c] = first record of chunk c (n_chunks + 1

@@ -323,9 +323,12 @@ __global__ __launch_bounds__(WG) void k_compress(PassArgs a, const T *__restrict
   }
 }
 
+// discard_old >= 0 selects the additive form of Alg. 2: f is the difference
+// field, the code is the difference between the codes truncated at `discard`
+// and at `discard_old` planes, and outliers contribute zero.
 template <typename T, int INTERP>
 __global__ __launch_bounds__(WG) void k_retrieve(PassArgs a, T *f, int discard, RetrieveIn in,
-                                                  T two_eb) {
+                                                  T two_eb, int discard_old) {
   using F = FP<T>;
   __shared__ uint32_t s_v[LDS_WORDS];
   __shared__ uint64_t s_lo, s_hi;
@@ -377,6 +380,8 @@ __global__ __launch_bounds__(WG) void k_retrieve(PassArgs a, T *f, int discard, 
   const uint64_t olo = s_lo, ohi = s_hi;
   const int64_t st = pass_stride(a);
   const int pd = a.dim3;
+  const bool additive = discard_old >= 0;
+  const uint32_t keep_old = discard_old >= 32 || discard_old < 0 ? 0u : (0xFFFFFFFFu << discard_old);
   for (int j = tid; j < count; j += WG) {
     int64_t lev[3];
     int64_t idx = code_position(a, g, j, lev);
@@ -387,8 +392,15 @@ __global__ __launch_bounds__(WG) void k_retrieve(PassArgs a, T *f, int discard, 
       pred = T(0);
     else
       pred = predict<T, INTERP>(f, idx, st, lev[pd], a.ldims[pd]);
-    // float32 codes have at most 26 negabinary digits, so q fits in int32
-    T tq = sizeof(T) == 4 ? T(int32_t(q)) : T(q);
+    T tq;
+    if (additive) {
+      // the planes above discard_old, as the previous plan held them
+      const uint32_t vo = xor_decode(xor_encode(v) & keep_old) & keep_old;
+      tq = T(q - (int64_t(vo ^ NB_A) - int64_t(NB_A)));
+    } else {
+      // float32 codes have at most 26 negabinary digits, so q fits in int32
+      tq = sizeof(T) == 4 ? T(int32_t(q)) : T(q);
+    }
     T val = F::add(pred, F::mul(tq, two_eb));
     if (ohi > olo) {
       uint64_t b0 = olo, b1 = ohi;
@@ -396,9 +408,20 @@ __global__ __launch_bounds__(WG) void k_retrieve(PassArgs a, T *f, int discard, 
         uint64_t m = (b0 + b1) >> 1;
         if (in.out_local[m] < uint32_t(j)) b0 = m + 1; else b1 = m;
       }
-      if (b0 < ohi && in.out_local[b0] == uint32_t(j)) val = F::from_bits(in.out_bits[b0]);
+      if (b0 < ohi && in.out_local[b0] == uint32_t(j))
+        val = additive ? T(0) : F::from_bits(in.out_bits[b0]);
     }
     f[idx] = val;
+  }
+}
+
+// x_new = x_old + delta wherever delta is not zero (additive form of Alg. 2)
+template <typename T>
+__global__ __launch_bounds__(WG) void k_add_delta(T *f, const T *__restrict__ d, uint64_t n) {
+  using F = FP<T>;
+  for (uint64_t i = uint64_t(blockIdx.x) * WG + threadIdx.x; i < n; i += uint64_t(gridDim.x) * WG) {
+    const T dv = d[i];
+    if (dv != T(0)) f[i] = F::add(f[i], dv);
   }
 }
 
@@ -592,11 +615,11 @@ hipError_t launch_c(const PassArgs &pa, const void *x, void *xh, int wb, double 
 
 template <typename T, int INTERP>
 hipError_t launch_r(const PassArgs &pa, void *f, int discard, const RetrieveIn &in, double eb,
-                    hipStream_t s) {
+                    hipStream_t s, int discard_old) {
   T two_eb = T(2.0 * eb);
   if (pa.n_chunks == 0) return hipSuccess;
   hipLaunchKernelGGL((k_retrieve<T, INTERP>), dim3(uint32_t(pa.n_chunks)), dim3(WG), 0, s, pa,
-                     static_cast<T *>(f), discard, in, two_eb);
+                     static_cast<T *>(f), discard, in, two_eb, discard_old);
   return hipGetLastError();
 }
 
@@ -613,12 +636,28 @@ hipError_t launch_compress_pass(int dtype, int interp, const PassArgs &pa, const
 }
 
 hipError_t launch_retrieve_pass(int dtype, int interp, const PassArgs &pa, void *field,
-                                int discard, const RetrieveIn &in, double eb, hipStream_t stream) {
+                                int discard, const RetrieveIn &in, double eb, hipStream_t stream,
+                                int discard_old) {
+  const int d = discard, o = discard_old;
   if (dtype == IPC_F32)
-    return interp == IPC_LINEAR ? launch_r<float, IPC_LINEAR>(pa, field, discard, in, eb, stream)
-                                : launch_r<float, IPC_CUBIC>(pa, field, discard, in, eb, stream);
-  return interp == IPC_LINEAR ? launch_r<double, IPC_LINEAR>(pa, field, discard, in, eb, stream)
-                              : launch_r<double, IPC_CUBIC>(pa, field, discard, in, eb, stream);
+    return interp == IPC_LINEAR ? launch_r<float, IPC_LINEAR>(pa, field, d, in, eb, stream, o)
+                                : launch_r<float, IPC_CUBIC>(pa, field, d, in, eb, stream, o);
+  return interp == IPC_LINEAR ? launch_r<double, IPC_LINEAR>(pa, field, d, in, eb, stream, o)
+                              : launch_r<double, IPC_CUBIC>(pa, field, d, in, eb, stream, o);
+}
+
+hipError_t launch_add_delta(int dtype, void *field, const void *delta, uint64_t n,
+                            hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  const uint64_t want = (n + WG - 1) / WG;
+  const uint32_t grid = uint32_t(want < 65536 ? want : 65536);
+  if (dtype == IPC_F32)
+    hipLaunchKernelGGL(k_add_delta<float>, dim3(grid), dim3(WG), 0, stream,
+                       static_cast<float *>(field), static_cast<const float *>(delta), n);
+  else
+    hipLaunchKernelGGL(k_add_delta<double>, dim3(grid), dim3(WG), 0, stream,
+                       static_cast<double *>(field), static_cast<const double *>(delta), n);
+  return hipGetLastError();
 }
 
 hipError_t launch_all_sizes(const PassArgs *args_dev, int n_passes, int64_t max_chunks,

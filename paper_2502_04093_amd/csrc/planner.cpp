@@ -288,4 +288,30 @@ PlanTables plan_tables(const StreamMeta &m) {
   return plan_tables_from_sizes(m, sizes);
 }
 
+// Bound of the additive form of Alg. 2 (x_new = x_old + Delta): the reported
+// bound of the new plan plus the rounding the additive form does where a fresh
+// reconstruction does not -- the old reconstruction's own rounding (T_s r for
+// the old plan's lossy passes), the difference field's (T_s1 r, s1 the first
+// progressive pass, as if every pass were lossy) and the final addition (u M),
+// with M the magnitude bound of the reported bound.
+double plan_additive_bound(const PlanTables &t, const std::vector<int> &plan,
+                           const std::vector<int> &old_plan, int mode, double value, double reported) {
+  mode &= ~IPC_TARGET_LEVEL_GROUPS;
+  double M;
+  if (mode == IPC_TARGET_EB)
+    M = value < t.eb ? t.maxabs : t.maxabs + value;
+  else
+    M = 2.0 * (t.maxabs + plan_bound(t, plan, t.maxabs));
+  const double r = rounding_step(t, M);
+  double a = reported;
+  int first = -1;
+  for (int s = 0; s < t.P; ++s) {
+    if (!t.progressive[s]) continue;
+    if (first < 0) first = s;
+    if (old_plan[s] > 0) a = a + t.tail[s] * r;
+  }
+  if (first >= 0) a = a + t.tail[first] * r;
+  return a + t.unit_roundoff * M;
+}
+
 }  // namespace ipc
