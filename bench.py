@@ -42,7 +42,8 @@ def parse_args():
                     help="edge of the cubic sub-block the oracle compresses and retrieves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", choices=["c2", "c4-batch", "c5-serve", "entropy"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c4-batch", "c5-serve", "entropy", "variants"],
+                    default="c2",
                     help="c2: the headline line (one field); c4-batch: --fields float64 "
                          "256x384x384 log-normal fields through the batched calls, beside "
                          "the same fields one call at a time; c5-serve: a Poisson request "
@@ -50,7 +51,9 @@ def parse_args():
                          "the same trace served one request at a time; entropy: the entropy "
                          "stage on the 512^3 field (compression ratio, coder times) and on "
                          "--fields 1800x3600 climate fields (bitrate retrievals planned on "
-                         "raw and on coded plane sizes)")
+                         "raw and on coded plane sizes); variants: the paper's per-level "
+                         "plane groups against per-pass groups, and its additive refinement "
+                         "against the recompute form, on the 512^3 field")
     ap.add_argument("--requests", type=int, default=600)
     ap.add_argument("--rate", type=float, default=2000.0, help="c5-serve arrivals per second")
     ap.add_argument("--budget-gib", type=float, default=32.0, help="c5-serve device-memory budget")
@@ -85,6 +88,8 @@ def main():
         return serve_main(args)
     if args.workload == "entropy":
         return entropy_main(args)
+    if args.workload == "variants":
+        return variants_main(args)
     dev = "cuda:0"
     shape = tuple(args.shape)
     n = int(np.prod(shape))
@@ -391,6 +396,82 @@ def entropy_main(args):
                                f"eb={args.rel_eb:g}*range; {args.fields} x 1800x3600 f32 climate "
                                "fields at eb=1e-3*range, bitrate 1/2/4"},
         "field512": big, "climate_mean": summary, "climate": climate,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def variants_main(args):
+    """The paper's variants on the 512^3 float32 field compressed at 1e-6 *
+    range.  (1) Plane groups: bytes loaded and bound for error-bound targets
+    1e-2 .. 1e-5 * range, and bound and max error for bitrates 1, 2, 4, with
+    per-pass groups and with the paper's per-level groups.  (2) The
+    progressive run 1e-2 -> 1e-3 -> 1e-4 -> 1e-5 -> 1e-6 * range refined in
+    the recompute form and in the additive form: device time per step, bound,
+    max error and the largest difference between the two reconstructions."""
+    import numpy as np
+    import torch
+
+    import fieldgen
+    import paper_2502_04093_amd as pkg
+
+    ctx = pkg.Context(0)
+    shape = tuple(args.shape)
+    print(f"[bench] generating {shape} field", file=sys.stderr, flush=True)
+    x = fieldgen.grf_torch(shape, -5.0 / 6.0, args.seed)
+    xd = x.double()
+    r = float(x.max().double() - x.min().double())
+    s = ctx.compress(x, 1e-6 * r)
+    groups = []
+    for rel in (1e-2, 1e-3, 1e-4, 1e-5):
+        row = {"target": f"eb={rel:g}*range"}
+        for tag, lg in (("pass", False), ("level", True)):
+            st = s.retrieve(eb=rel * r, level_groups=lg)
+            row[f"{tag}_loaded_bytes"] = int(st.info.bytes_loaded)
+            row[f"{tag}_bound"] = st.info.bound
+            st.free()
+        groups.append(row)
+        print(f"[bench] groups {row}", file=sys.stderr, flush=True)
+    for br in (1.0, 2.0, 4.0):
+        row = {"target": f"bitrate={br:g}"}
+        for tag, lg in (("pass", False), ("level", True)):
+            st = s.retrieve(bitrate=br, level_groups=lg)
+            row[f"{tag}_bound"] = st.info.bound
+            row[f"{tag}_maxerr"] = float((st.tensor().double() - xd).abs().max())
+            st.free()
+        groups.append(row)
+        print(f"[bench] groups {row}", file=sys.stderr, flush=True)
+
+    refine = []
+    a = s.retrieve(eb=1e-2 * r)
+    b = s.retrieve(eb=1e-2 * r)
+    for rel in (1e-3, 1e-4, 1e-5, 1e-6):
+        ia = a.refine(eb=rel * r)
+        ib = b.refine_additive(eb=rel * r)
+        ta, tb = a.tensor().double(), b.tensor().double()
+        row = {"target": f"eb={rel:g}*range",
+               "recompute_ms": round(ia.t_device_ms, 3), "additive_ms": round(ib.t_device_ms, 3),
+               "recompute_bound": ia.bound, "additive_bound": ib.bound,
+               "recompute_maxerr": float((ta - xd).abs().max()),
+               "additive_maxerr": float((tb - xd).abs().max()),
+               "max_abs_difference": float((ta - tb).abs().max()),
+               "bytes_read": int(ib.bytes_read)}
+        refine.append(row)
+        print(f"[bench] refine {row}", file=sys.stderr, flush=True)
+        del ta, tb
+    a.free()
+    b.free()
+    s.free()
+    out = {
+        "metric": "paper variants on 512^3 f32 GRF compressed at eb=1e-6*range",
+        "value": round(sum(r_["additive_ms"] for r_ in refine), 3), "unit": "ms (additive refine steps)",
+        "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(sum(r_["recompute_ms"] for r_ in refine), 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "per-pass vs per-level plane groups; recompute vs additive "
+                               "refinement 1e-2 -> 1e-6 * range"},
+        "plane_groups": groups, "refinement": refine,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
