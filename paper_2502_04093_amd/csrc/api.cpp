@@ -882,6 +882,197 @@ void retrieve_batch_fused(ipc_ctx *ctx, const std::vector<const ipc_stream *> &s
   for (DevBuf &b : g) dev_free(ctx, b);
 }
 
+// Compression of n fields on the one-pass-per-launch path (2-D, 1-D, other
+// chunk shapes) with one launch per pass index over all of them: step i
+// holds pass i of every field that has one.  Each field keeps its own
+// working reconstruction, summary and outlier records.  Fields whose outliers
+// overflow their record capacity are flagged in `redo`.
+template <typename T>
+void compress_batch_passes(ipc_ctx *ctx, std::vector<ipc_stream *> &ss, const void *const *fields,
+                           const double *ebs, std::vector<char> &redo) {
+  const int n = int(ss.size());
+  const int dtype = ss[0]->meta.dtype, interp = ss[0]->meta.interp;
+  std::vector<size_t> sum_off(n + 1, 0), rec_off(n + 1, 0), args_off(n);
+  int Pmax = 0;
+  std::vector<PassArgs> args;
+  for (int i = 0; i < n; ++i) {
+    const Schedule &sc = ss[i]->meta.sched;
+    const int P = int(sc.passes.size());
+    Pmax = std::max(Pmax, P);
+    sum_off[i + 1] = sum_off[i] + ((summary_bytes(P) + 255) & ~size_t(255));
+    rec_off[i + 1] = rec_off[i] + std::max<size_t>(4096, size_t(sc.n_points / 1024));
+    args_off[i] = args.size();
+    args.insert(args.end(), ss[i]->args.begin(), ss[i]->args.end());
+  }
+  char *summary = static_cast<char *>(ensure_ws(ctx, ctx->ws_summary, ctx->ws_summary_bytes, sum_off[n]));
+  ensure_ws(ctx, ctx->ws_out, ctx->ws_out_cap, rec_off[n] * sizeof(OutlierRec));
+  hip_check(ctx, hipMemsetAsync(summary, 0, sum_off[n], ctx->stream), "memset");
+  std::vector<DevBuf> xh(n);
+  DevBuf args_dev, ent_dev;
+  auto release = [&] {
+    for (DevBuf &b : xh) dev_free(ctx, b);
+    dev_free(ctx, args_dev);
+    dev_free(ctx, ent_dev);
+  };
+  try {
+    args_dev = dev_alloc(ctx, args.size() * sizeof(PassArgs));
+    hip_check(ctx, hipMemcpyAsync(args_dev.p, args.data(), args.size() * sizeof(PassArgs),
+                                  hipMemcpyHostToDevice, ctx->stream), "upload");
+    std::vector<CompressOut> o(n);
+    for (int i = 0; i < n; ++i) {
+      const Schedule &sc = ss[i]->meta.sched;
+      xh[i] = dev_alloc(ctx, std::max<size_t>(8, size_t(sc.n_points) * sizeof(T)));
+      char *sm = summary + sum_off[i];
+      const int P = int(sc.passes.size());
+      std::memset(&o[i], 0, sizeof(CompressOut));
+      o[i].payload = static_cast<uint32_t *>(ss[i]->payload.p);
+      o[i].masks = static_cast<uint32_t *>(ss[i]->masks.p);
+      o[i].n_out = reinterpret_cast<unsigned long long *>(sm);
+      o[i].maxabs_bits = reinterpret_cast<unsigned long long *>(sm + 8);
+      o[i].sizes = reinterpret_cast<unsigned long long *>(sm + 16);
+      o[i].errq = reinterpret_cast<uint32_t *>(sm + 16 + size_t(P) * 32 * 8);
+      o[i].out_recs = static_cast<OutlierRec *>(ctx->ws_out) + rec_off[i];
+      o[i].out_cap = rec_off[i + 1] - rec_off[i];
+      o[i].wg_rows = nullptr;
+    }
+    // the work list of every step
+    std::vector<PassBatchC<T>> ent;
+    struct Launch { size_t off; int nf; uint32_t items; };
+    std::vector<Launch> launches;
+    for (int step = 0; step < Pmax; ++step) {
+      Launch ln{ent.size(), 0, 0};
+      for (int i = 0; i < n; ++i) {
+        const int P = int(ss[i]->args.size());
+        if (step >= P || ss[i]->args[size_t(step)].n_chunks == 0) continue;
+        PassBatchC<T> e;
+        std::memset(&e, 0, sizeof(e));
+        e.a = ss[i]->args[size_t(step)];
+        e.x = static_cast<const T *>(fields[i]);
+        e.xh = static_cast<T *>(xh[i].p);
+        e.o = o[i];
+        e.eb = ebs[i];
+        e.two_eb = T(2.0 * ebs[i]);
+        e.inv = T(1.0 / (2.0 * ebs[i]));
+        e.qmax = T(sizeof(T) == 4 ? QMAX_F32 : QMAX_F64);
+        e.write_back = step + 1 < P ? 1 : 0;
+        e.item0 = ln.items;
+        ent.push_back(e);
+        ++ln.nf;
+        ln.items += uint32_t(e.a.n_chunks);
+      }
+      if (ln.nf) launches.push_back(ln);
+    }
+    ent_dev = dev_alloc(ctx, std::max<size_t>(1, ent.size()) * sizeof(PassBatchC<T>));
+    hip_check(ctx, hipMemcpyAsync(ent_dev.p, ent.data(), ent.size() * sizeof(PassBatchC<T>),
+                                  hipMemcpyHostToDevice, ctx->stream), "upload");
+    for (const Launch &ln : launches)
+      hip_check(ctx, launch_compress_pass_batch(dtype, interp,
+                                                static_cast<PassBatchC<T> *>(ent_dev.p) + ln.off, ln.nf,
+                                                ln.items, ctx->stream),
+                "pass kernel launch");
+    for (int i = 0; i < n; ++i) {
+      ipc_stream *s = ss[i];
+      const Schedule &sc = s->meta.sched;
+      int64_t max_chunks = 0;
+      for (const PassGeom &g : sc.passes) max_chunks = std::max(max_chunks, g.n_chunks);
+      const PassArgs *ad = static_cast<const PassArgs *>(args_dev.p) + args_off[i];
+      hip_check(ctx, launch_all_sizes(ad, int(sc.passes.size()), max_chunks, o[i].masks, o[i].sizes,
+                                      ctx->stream),
+                "sizes kernel launch");
+      const uint64_t nc = uint64_t(sc.n_chunks);
+      const size_t cap = size_t(o[i].out_cap);
+      s->out_gchunk = dev_alloc(ctx, 8 * cap);
+      s->out_local = dev_alloc(ctx, 4 * cap);
+      s->out_bits = dev_alloc(ctx, 8 * cap);
+      s->out_start = dev_alloc(ctx, 4 * (nc + 1));
+      const size_t nb = (nc + 1 + 1023) / 1024;
+      uint32_t *cnt = static_cast<uint32_t *>(
+          ensure_ws(ctx, ctx->ws_cnt, ctx->ws_cnt_bytes, 4 * (nc + 1) + 4 * (nb + 1)));
+      hip_check(ctx, launch_outlier_index(static_cast<const OutlierRec *>(o[i].out_recs), o[i].n_out, cap,
+                                          ad, nc, static_cast<uint32_t *>(s->out_start.p), cnt,
+                                          cnt + (nc + 1), static_cast<uint64_t *>(s->out_gchunk.p),
+                                          static_cast<uint32_t *>(s->out_local.p),
+                                          static_cast<uint64_t *>(s->out_bits.p), ctx->stream),
+                "outlier index launch");
+    }
+    if (ctx->host_summary_bytes < sum_off[n]) {
+      if (ctx->host_summary) (void)hipHostFree(ctx->host_summary);
+      ctx->host_summary = nullptr;
+      ctx->host_summary_bytes = 0;
+      hip_check(ctx, hipHostMalloc(&ctx->host_summary, sum_off[n], hipHostMallocDefault), "pinned alloc");
+      ctx->host_summary_bytes = sum_off[n];
+    }
+    char *hostp = static_cast<char *>(ctx->host_summary);
+    hip_check(ctx, hipMemcpyAsync(hostp, summary, sum_off[n], hipMemcpyDeviceToHost, ctx->stream), "copy");
+    hip_check(ctx, hipStreamSynchronize(ctx->stream), "compress");
+    for (int i = 0; i < n; ++i) {
+      uint64_t nout;
+      std::memcpy(&nout, hostp + sum_off[i], 8);
+      if (nout > o[i].out_cap) {
+        redo[i] = 1;
+        continue;
+      }
+      finish_stream(ss[i], hostp + sum_off[i], nout);
+    }
+  } catch (...) {
+    (void)hipStreamSynchronize(ctx->stream);
+    release();
+    throw;
+  }
+  release();
+}
+
+// Retrieval of n streams on the one-pass-per-launch path: one launch per pass
+// index over all of them, each stream from its own first pass `start[i]`
+// (0, or the first changed pass of a refinement that recomputes in place).
+template <typename T>
+void retrieve_batch_passes(ipc_ctx *ctx, const std::vector<const ipc_stream *> &ss,
+                           const std::vector<std::vector<int>> &plans, const std::vector<void *> &fields,
+                           const std::vector<int> &start) {
+  const int n = int(ss.size());
+  const int dtype = ss[0]->meta.dtype, interp = ss[0]->meta.interp;
+  int Pmax = 0;
+  for (const ipc_stream *s : ss) Pmax = std::max(Pmax, int(s->args.size()));
+  std::vector<PassBatchR<T>> ent;
+  struct Launch { size_t off; int nf; uint32_t items; };
+  std::vector<Launch> launches;
+  for (int step = 0; step < Pmax; ++step) {
+    Launch ln{ent.size(), 0, 0};
+    for (int i = 0; i < n; ++i) {
+      const ipc_stream *s = ss[i];
+      if (step < start[i] || step >= int(s->args.size()) || s->args[size_t(step)].n_chunks == 0) continue;
+      PassBatchR<T> e;
+      std::memset(&e, 0, sizeof(e));
+      e.a = s->args[size_t(step)];
+      e.f = static_cast<T *>(fields[i]);
+      e.in = retrieve_in(ctx, s);
+      e.two_eb = T(2.0 * s->meta.eb);
+      e.discard = plans[i][size_t(step)];
+      e.item0 = ln.items;
+      ent.push_back(e);
+      ++ln.nf;
+      ln.items += uint32_t(e.a.n_chunks);
+    }
+    if (ln.nf) launches.push_back(ln);
+  }
+  DevBuf ent_dev = dev_alloc(ctx, std::max<size_t>(1, ent.size()) * sizeof(PassBatchR<T>));
+  try {
+    hip_check(ctx, hipMemcpyAsync(ent_dev.p, ent.data(), ent.size() * sizeof(PassBatchR<T>),
+                                  hipMemcpyHostToDevice, ctx->stream), "upload");
+    for (const Launch &ln : launches)
+      hip_check(ctx, launch_retrieve_pass_batch(dtype, interp,
+                                                static_cast<PassBatchR<T> *>(ent_dev.p) + ln.off, ln.nf,
+                                                ln.items, ctx->stream),
+                "pass kernel launch");
+    hip_check(ctx, hipStreamSynchronize(ctx->stream), "retrieve");
+  } catch (...) {
+    (void)hipStreamSynchronize(ctx->stream);
+    dev_free(ctx, ent_dev);
+    throw;
+  }
+  dev_free(ctx, ent_dev);
+}
+
 // host copy of the chunk masks
 void ensure_host_masks(ipc_ctx *ctx, ipc_stream *s) {
   if (s->host_masks_valid) return;
@@ -1688,13 +1879,17 @@ ipc_status ipc_compress_batch(ipc_ctx *ctx, uint32_t n, const void *const *field
     return IPC_EINVAL;
   }
   int interp = opts ? opts->interp : IPC_CUBIC;
+  // all fields on the fused 3-D path, or all on the one-pass-per-launch path
   bool fused = n > 1 && (interp == IPC_LINEAR || interp == IPC_CUBIC);
+  bool passes = fused;
   for (uint32_t i = 0; i < n; ++i) {
     if (!fields_dev[i] || !(std::isfinite(abs_eb[i]) && abs_eb[i] > 0)) {
       set_err(ctx, "invalid field or error bound in ipc_compress_batch");
       return IPC_EINVAL;
     }
-    fused = fused && fused_dims(dims + size_t(i) * ndim, ndim, opts);
+    const bool f = fused_dims(dims + size_t(i) * ndim, ndim, opts);
+    fused = fused && f;
+    passes = passes && !f;
   }
   auto undo = [&](uint32_t upto) {
     for (uint32_t j = 0; j < upto; ++j) {
@@ -1702,8 +1897,8 @@ ipc_status ipc_compress_batch(ipc_ctx *ctx, uint32_t n, const void *const *field
       out[j] = nullptr;
     }
   };
-  if (!fused) {
-    // one call per field (other dimensionalities, chunk shapes, or one field)
+  if (!fused && !passes) {
+    // one call per field (a mix of paths, or one field)
     for (uint32_t i = 0; i < n; ++i) {
       ipc_status st = ipc_compress(ctx, fields_dev[i], dims + size_t(i) * ndim, ndim, dtype, abs_eb[i],
                                    opts, &out[i]);
@@ -1721,12 +1916,19 @@ ipc_status ipc_compress_batch(ipc_ctx *ctx, uint32_t n, const void *const *field
     for (uint32_t i = 0; i < n; ++i) {
       ss[i] = new ipc_stream();
       ss[i]->ctx = ctx;
-      setup_stream(ctx, ss[i], dims + size_t(i) * 3, 3, dtype, interp, abs_eb[i], opts);
+      setup_stream(ctx, ss[i], dims + size_t(i) * ndim, ndim, dtype, interp, abs_eb[i], opts);
     }
-    if (dtype == IPC_F32)
-      compress_batch_fused<float>(ctx, ss, fields_dev, abs_eb, redo);
-    else
-      compress_batch_fused<double>(ctx, ss, fields_dev, abs_eb, redo);
+    if (fused) {
+      if (dtype == IPC_F32)
+        compress_batch_fused<float>(ctx, ss, fields_dev, abs_eb, redo);
+      else
+        compress_batch_fused<double>(ctx, ss, fields_dev, abs_eb, redo);
+    } else {
+      if (dtype == IPC_F32)
+        compress_batch_passes<float>(ctx, ss, fields_dev, abs_eb, redo);
+      else
+        compress_batch_passes<double>(ctx, ss, fields_dev, abs_eb, redo);
+    }
   });
   if (st != IPC_OK) {
     for (ipc_stream *s : ss)
@@ -1742,8 +1944,8 @@ ipc_status ipc_compress_batch(ipc_ctx *ctx, uint32_t n, const void *const *field
     if (!redo[i]) continue;
     ipc_stream_free(out[i]);
     out[i] = nullptr;
-    ipc_status st2 = ipc_compress(ctx, fields_dev[i], dims + size_t(i) * 3, 3, dtype, abs_eb[i], opts,
-                                  &out[i]);
+    ipc_status st2 = ipc_compress(ctx, fields_dev[i], dims + size_t(i) * ndim, ndim, dtype, abs_eb[i],
+                                  opts, &out[i]);
     if (st2 != IPC_OK) {
       undo(n);
       return st2;
@@ -1757,7 +1959,9 @@ ipc_status ipc_retrieve_batch(ipc_ctx *ctx, uint32_t n, const ipc_stream *const 
   if (!out) return IPC_EINVAL;
   for (uint32_t i = 0; i < n; ++i) out[i] = nullptr;
   if (!ctx || n == 0 || !streams || !targets) return IPC_EINVAL;
-  bool fused = n > 1;
+  // all streams on the fused 3-D path, or all on the one-pass-per-launch
+  // path, with one dtype and interpolation
+  bool fused = n > 1, passes = n > 1;
   for (uint32_t i = 0; i < n; ++i) {
     const ipc_stream *s = streams[i];
     if (!s) return IPC_EINVAL;
@@ -1769,10 +1973,12 @@ ipc_status ipc_retrieve_batch(ipc_ctx *ctx, uint32_t n, const ipc_stream *const 
       set_err(ctx, "target value must be finite and > 0");
       return IPC_EINVAL;
     }
-    fused = fused && fused3(s->meta.sched) && s->meta.dtype == streams[0]->meta.dtype &&
-            s->meta.interp == streams[0]->meta.interp;
+    const bool same = s->meta.dtype == streams[0]->meta.dtype && s->meta.interp == streams[0]->meta.interp;
+    const bool f = fused3(s->meta.sched);
+    fused = fused && f && same;
+    passes = passes && !f && same;
   }
-  if (!fused) {
+  if (!fused && !passes) {
     for (uint32_t i = 0; i < n; ++i) {
       ipc_status st = ipc_retrieve(ctx, streams[i], targets[i], &out[i], info ? info + i : nullptr);
       if (st != IPC_OK) {
@@ -1810,12 +2016,20 @@ ipc_status ipc_retrieve_batch(ipc_ctx *ctx, uint32_t n, const ipc_stream *const 
       fields[i] = sts[i]->field.p;
     }
     hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
-    std::vector<int> ls(n);
-    for (uint32_t i = 0; i < n; ++i) ls[i] = ss[i]->meta.sched.K;
-    if (ss[0]->meta.dtype == IPC_F32)
-      retrieve_batch_fused<float>(ctx, ss, plans, fields, ls);
-    else
-      retrieve_batch_fused<double>(ctx, ss, plans, fields, ls);
+    if (fused) {
+      std::vector<int> ls(n);
+      for (uint32_t i = 0; i < n; ++i) ls[i] = ss[i]->meta.sched.K;
+      if (ss[0]->meta.dtype == IPC_F32)
+        retrieve_batch_fused<float>(ctx, ss, plans, fields, ls);
+      else
+        retrieve_batch_fused<double>(ctx, ss, plans, fields, ls);
+    } else {
+      std::vector<int> start(n, 0);
+      if (ss[0]->meta.dtype == IPC_F32)
+        retrieve_batch_passes<float>(ctx, ss, plans, fields, start);
+      else
+        retrieve_batch_passes<double>(ctx, ss, plans, fields, start);
+    }
     hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
     hip_check(ctx, hipEventSynchronize(ctx->ev1), "retrieve");
     float ms = 0;
@@ -1946,6 +2160,7 @@ ipc_status ipc_serve_batch(ipc_ctx *ctx, uint32_t n, ipc_request *req) {
     int l_start;
     float tplan;
     uint64_t read;
+    int s_min;  // first pass to recompute (0 for a new retrieval)
   };
   std::vector<Job> jobs;
   std::vector<const ipc_state *> seen;
@@ -1970,7 +2185,7 @@ ipc_status ipc_serve_batch(ipc_ctx *ctx, uint32_t n, ipc_request *req) {
       continue;
     }
     auto t0 = std::chrono::steady_clock::now();
-    Job j{i, s, q.refine ? q.state : nullptr, PlanResult(), s->meta.sched.K, 0.0f, 0};
+    Job j{i, s, q.refine ? q.state : nullptr, PlanResult(), s->meta.sched.K, 0.0f, 0, 0};
     if (q.refine) {
       ipc_state *st = q.state;
       if ((q.target.kind & ~IPC_TARGET_LEVEL_GROUPS) == IPC_TARGET_EB && q.target.value >= st->bound) {
@@ -1986,6 +2201,7 @@ ipc_status ipc_serve_batch(ipc_ctx *ctx, uint32_t n, ipc_request *req) {
       int s_min = 0;
       while (s_min < int(j.pr.plan.size()) && j.pr.plan[s_min] >= st->plan[s_min]) ++s_min;
       j.read = plane_bytes_between(s, j.pr.plan, st->plan);
+      j.s_min = s_min;
       j.l_start = s->meta.sched.passes[size_t(s_min)].level;
       if (s_min == 0) j.l_start = s->meta.sched.K;
     } else {
@@ -1997,27 +2213,35 @@ ipc_status ipc_serve_batch(ipc_ctx *ctx, uint32_t n, ipc_request *req) {
     jobs.push_back(j);
   }
   if (jobs.empty()) return IPC_OK;
-  // fused 3-D jobs of one dtype / interpolation share the level launches;
-  // the others run one at a time
-  const ipc_stream *s0 = nullptr;
-  std::vector<size_t> fused_idx, other_idx;
+  // fused 3-D jobs of one dtype / interpolation share the level launches,
+  // jobs on the one-pass-per-launch path of one dtype / interpolation share
+  // the pass launches; the others run one at a time
+  const ipc_stream *s0 = nullptr, *p0 = nullptr;
+  std::vector<size_t> fused_idx, pass_idx, other_idx;
+  auto same = [](const ipc_stream *a, const ipc_stream *b) {
+    return a->meta.dtype == b->meta.dtype && a->meta.interp == b->meta.interp;
+  };
   for (size_t k = 0; k < jobs.size(); ++k) {
     const ipc_stream *s = jobs[k].s;
-    const bool f = fused3(s->meta.sched) && (!s0 || (s->meta.dtype == s0->meta.dtype && s->meta.interp == s0->meta.interp));
-    if (f) {
+    if (fused3(s->meta.sched)) {
       if (!s0) s0 = s;
-      fused_idx.push_back(k);
+      (same(s, s0) ? fused_idx : other_idx).push_back(k);
     } else {
-      other_idx.push_back(k);
+      if (!p0) p0 = s;
+      (same(s, p0) ? pass_idx : other_idx).push_back(k);
     }
   }
+  std::vector<ipc_state *> fresh(jobs.size(), nullptr);  // new states of this call
   ipc_status st = guarded(ctx, [&] {
     hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     std::vector<const ipc_stream *> ss;
     std::vector<std::vector<int>> plans;
     std::vector<void *> fields;
     std::vector<int> ls;
-    std::vector<ipc_state *> fresh(jobs.size(), nullptr);
+    std::vector<const ipc_stream *> ps;
+    std::vector<std::vector<int>> pplans;
+    std::vector<void *> pfields;
+    std::vector<int> pstart;
     for (size_t k : fused_idx) {
       Job &j = jobs[k];
       void *f;
@@ -2042,6 +2266,30 @@ ipc_status ipc_serve_batch(ipc_ctx *ctx, uint32_t n, ipc_request *req) {
       fields.push_back(f);
       ls.push_back(j.l_start);
     }
+    for (size_t k : pass_idx) {
+      Job &j = jobs[k];
+      void *f;
+      if (j.st) {
+        f = j.st->field.p;
+      } else {
+        ipc_state *t = new ipc_state();
+        t->ctx = ctx;
+        t->stream = j.s;
+        const size_t isz = j.s->meta.dtype == IPC_F32 ? 4 : 8;
+        try {
+          t->field = dev_alloc(ctx, size_t(j.s->meta.sched.n_points) * isz);
+        } catch (...) {
+          delete t;
+          throw;
+        }
+        fresh[k] = t;
+        f = t->field.p;
+      }
+      ps.push_back(j.s);
+      pplans.push_back(j.pr.plan);
+      pfields.push_back(f);
+      pstart.push_back(j.s_min);
+    }
     hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
     if (!ss.empty()) {
       if (ss[0]->meta.dtype == IPC_F32)
@@ -2049,22 +2297,38 @@ ipc_status ipc_serve_batch(ipc_ctx *ctx, uint32_t n, ipc_request *req) {
       else
         retrieve_batch_fused<double>(ctx, ss, plans, fields, ls);
     }
+    if (!ps.empty()) {
+      if (ps[0]->meta.dtype == IPC_F32)
+        retrieve_batch_passes<float>(ctx, ps, pplans, pfields, pstart);
+      else
+        retrieve_batch_passes<double>(ctx, ps, pplans, pfields, pstart);
+    }
     hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
     hip_check(ctx, hipEventSynchronize(ctx->ev1), "serve");
     float ms = 0;
     (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
-    for (size_t k : fused_idx) {
-      Job &j = jobs[k];
-      ipc_request &q = req[j.r];
-      ipc_state *t = j.st ? j.st : fresh[k];
-      t->plan = j.pr.plan;
-      t->bound = j.pr.bound;
-      if (!j.st) q.state = t;
-      fill_info(j.s, t->plan, t->bound, j.pr.flags, j.read, j.tplan, ms, &q.info);
-    }
+    for (const std::vector<size_t> *idx : {&fused_idx, &pass_idx})
+      for (size_t k : *idx) {
+        Job &j = jobs[k];
+        ipc_request &q = req[j.r];
+        ipc_state *t = j.st ? j.st : fresh[k];
+        t->plan = j.pr.plan;
+        t->bound = j.pr.bound;
+        if (!j.st) q.state = t;
+        fill_info(j.s, t->plan, t->bound, j.pr.flags, j.read, j.tplan, ms, &q.info);
+      }
   });
   if (st != IPC_OK) {
-    for (size_t k : fused_idx) req[jobs[k].r].status = st;
+    for (const std::vector<size_t> *idx : {&fused_idx, &pass_idx})
+      for (size_t k : *idx) {
+        req[jobs[k].r].status = st;
+        req[jobs[k].r].state = jobs[k].st;
+      }
+    for (ipc_state *t : fresh)
+      if (t) {
+        dev_free(ctx, t->field);
+        delete t;
+      }
     return st;
   }
   for (size_t k : other_idx) {

@@ -147,6 +147,34 @@ hipError_t launch_compress_pass(int dtype, int interp, const PassArgs &pa, const
 hipError_t launch_retrieve_pass(int dtype, int interp, const PassArgs &pa, void *field,
                                 int discard, const RetrieveIn &in, double eb, hipStream_t stream,
                                 int discard_old = -1);
+// Batched passes (one step of several fields in one launch): the arguments
+// of one field's pass and the first work item of its chunks.
+template <typename T>
+struct PassBatchC {
+  PassArgs a;
+  const T *x;
+  T *xh;
+  CompressOut o;
+  double eb;
+  T two_eb, inv, qmax;
+  int32_t write_back;
+  uint32_t item0;
+};
+template <typename T>
+struct PassBatchR {
+  PassArgs a;
+  T *f;
+  RetrieveIn in;
+  T two_eb;
+  int32_t discard;
+  uint32_t item0;
+};
+// one workgroup per chunk of the nf fields' passes in `batch_dev` (device
+// array of PassBatchC<T> / PassBatchR<T>, n_items chunks in all)
+hipError_t launch_compress_pass_batch(int dtype, int interp, const void *batch_dev, int nf,
+                                      uint32_t n_items, hipStream_t stream);
+hipError_t launch_retrieve_pass_batch(int dtype, int interp, const void *batch_dev, int nf,
+                                      uint32_t n_items, hipStream_t stream);
 // field[i] += delta[i] wherever delta[i] != 0
 hipError_t launch_add_delta(int dtype, void *field, const void *delta, uint64_t n,
                             hipStream_t stream);

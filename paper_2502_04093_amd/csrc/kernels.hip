@@ -181,17 +181,18 @@ __device__ __forceinline__ unsigned long long wave_max64(unsigned long long v) {
   return v;
 }
 
+// Chunk c of one pass (the workgroup's share of a k_compress launch).
 template <typename T, int INTERP>
-__global__ __launch_bounds__(WG) void k_compress(PassArgs a, const T *__restrict__ x, T *xh,
-                                                  int write_back, double eb, T two_eb, T inv,
-                                                  T qmax, CompressOut o) {
+__device__ __forceinline__ void compress_chunk(const PassArgs &a, const int64_t c,
+                                               const T *__restrict__ x, T *xh, int write_back,
+                                               double eb, T two_eb, T inv, T qmax,
+                                               const CompressOut &o) {
   using F = FP<T>;
   __shared__ uint32_t s_v[LDS_WORDS];
   __shared__ uint32_t s_or_e, s_or_v, s_qmax;
   __shared__ uint32_t s_errq[33];
   __shared__ unsigned long long s_maxabs;
 
-  const int64_t c = blockIdx.x;
   const int tid = threadIdx.x;
   const ChunkGeo g = chunk_geo(a, c);
   const int count = g.count;
@@ -323,16 +324,23 @@ __global__ __launch_bounds__(WG) void k_compress(PassArgs a, const T *__restrict
   }
 }
 
+template <typename T, int INTERP>
+__global__ __launch_bounds__(WG) void k_compress(PassArgs a, const T *__restrict__ x, T *xh,
+                                                  int write_back, double eb, T two_eb, T inv,
+                                                  T qmax, CompressOut o) {
+  compress_chunk<T, INTERP>(a, int64_t(blockIdx.x), x, xh, write_back, eb, two_eb, inv, qmax, o);
+}
+
 // discard_old >= 0 selects the additive form of Alg. 2: f is the difference
 // field, the code is the difference between the codes truncated at `discard`
 // and at `discard_old` planes, and outliers contribute zero.
 template <typename T, int INTERP>
-__global__ __launch_bounds__(WG) void k_retrieve(PassArgs a, T *f, int discard, RetrieveIn in,
-                                                  T two_eb, int discard_old) {
+__device__ __forceinline__ void retrieve_chunk(const PassArgs &a, const int64_t c, T *f,
+                                               int discard, const RetrieveIn &in, T two_eb,
+                                               int discard_old) {
   using F = FP<T>;
   __shared__ uint32_t s_v[LDS_WORDS];
   __shared__ uint64_t s_lo, s_hi;
-  const int64_t c = blockIdx.x;
   const int tid = threadIdx.x;
   const ChunkGeo g = chunk_geo(a, c);
   const int count = g.count;
@@ -413,6 +421,37 @@ __global__ __launch_bounds__(WG) void k_retrieve(PassArgs a, T *f, int discard, 
     }
     f[idx] = val;
   }
+}
+
+template <typename T, int INTERP>
+__global__ __launch_bounds__(WG) void k_retrieve(PassArgs a, T *f, int discard, RetrieveIn in,
+                                                  T two_eb, int discard_old) {
+  retrieve_chunk<T, INTERP>(a, int64_t(blockIdx.x), f, discard, in, two_eb, discard_old);
+}
+
+// Batched passes: step i of several fields in one launch, one workgroup per
+// chunk of the work list (the fields' chunks in order); each workgroup finds
+// its field by a uniform scan and reads that field's arguments from memory.
+template <typename B>
+__device__ __forceinline__ int pass_item_field(const B *__restrict__ bf, int nf, uint32_t it) {
+  int f = 0;
+  while (f + 1 < nf && bf[f + 1].item0 <= it) ++f;
+  return f;
+}
+
+template <typename T, int INTERP>
+__global__ __launch_bounds__(WG) void k_compress_batch(const PassBatchC<T> *__restrict__ bf, int nf) {
+  const uint32_t it = blockIdx.x;
+  const PassBatchC<T> &b = bf[pass_item_field(bf, nf, it)];
+  compress_chunk<T, INTERP>(b.a, int64_t(it - b.item0), b.x, b.xh, b.write_back, b.eb, b.two_eb,
+                            b.inv, b.qmax, b.o);
+}
+
+template <typename T, int INTERP>
+__global__ __launch_bounds__(WG) void k_retrieve_batch(const PassBatchR<T> *__restrict__ bf, int nf) {
+  const uint32_t it = blockIdx.x;
+  const PassBatchR<T> &b = bf[pass_item_field(bf, nf, it)];
+  retrieve_chunk<T, INTERP>(b.a, int64_t(it - b.item0), b.f, b.discard, b.in, b.two_eb, -1);
 }
 
 // x_new = x_old + delta wherever delta is not zero (additive form of Alg. 2)
@@ -644,6 +683,44 @@ hipError_t launch_retrieve_pass(int dtype, int interp, const PassArgs &pa, void 
                                 : launch_r<float, IPC_CUBIC>(pa, field, d, in, eb, stream, o);
   return interp == IPC_LINEAR ? launch_r<double, IPC_LINEAR>(pa, field, d, in, eb, stream, o)
                               : launch_r<double, IPC_CUBIC>(pa, field, d, in, eb, stream, o);
+}
+
+hipError_t launch_compress_pass_batch(int dtype, int interp, const void *batch_dev, int nf,
+                                      uint32_t n_items, hipStream_t stream) {
+  if (n_items == 0) return hipSuccess;
+  if (dtype == IPC_F32) {
+    auto *b = static_cast<const PassBatchC<float> *>(batch_dev);
+    if (interp == IPC_LINEAR)
+      hipLaunchKernelGGL((k_compress_batch<float, IPC_LINEAR>), dim3(n_items), dim3(WG), 0, stream, b, nf);
+    else
+      hipLaunchKernelGGL((k_compress_batch<float, IPC_CUBIC>), dim3(n_items), dim3(WG), 0, stream, b, nf);
+  } else {
+    auto *b = static_cast<const PassBatchC<double> *>(batch_dev);
+    if (interp == IPC_LINEAR)
+      hipLaunchKernelGGL((k_compress_batch<double, IPC_LINEAR>), dim3(n_items), dim3(WG), 0, stream, b, nf);
+    else
+      hipLaunchKernelGGL((k_compress_batch<double, IPC_CUBIC>), dim3(n_items), dim3(WG), 0, stream, b, nf);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_retrieve_pass_batch(int dtype, int interp, const void *batch_dev, int nf,
+                                      uint32_t n_items, hipStream_t stream) {
+  if (n_items == 0) return hipSuccess;
+  if (dtype == IPC_F32) {
+    auto *b = static_cast<const PassBatchR<float> *>(batch_dev);
+    if (interp == IPC_LINEAR)
+      hipLaunchKernelGGL((k_retrieve_batch<float, IPC_LINEAR>), dim3(n_items), dim3(WG), 0, stream, b, nf);
+    else
+      hipLaunchKernelGGL((k_retrieve_batch<float, IPC_CUBIC>), dim3(n_items), dim3(WG), 0, stream, b, nf);
+  } else {
+    auto *b = static_cast<const PassBatchR<double> *>(batch_dev);
+    if (interp == IPC_LINEAR)
+      hipLaunchKernelGGL((k_retrieve_batch<double, IPC_LINEAR>), dim3(n_items), dim3(WG), 0, stream, b, nf);
+    else
+      hipLaunchKernelGGL((k_retrieve_batch<double, IPC_CUBIC>), dim3(n_items), dim3(WG), 0, stream, b, nf);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_add_delta(int dtype, void *field, const void *delta, uint64_t n,

@@ -85,7 +85,7 @@ def test_batch_equals_single_calls(ctx, dtype, rel):
 
 def test_batch_outlier_overflow_and_fallback(ctx):
     """A field whose outliers exceed the batch's record share is compressed
-    again alone; 2-D fields take one call per field."""
+    again alone; a batch of 2-D fields shares the pass launches."""
     rng = np.random.default_rng(3)
     a = fieldgen.random_field((40, 64, 128), seed=7, dtype=np.float32)
     f = a.reshape(-1)
@@ -151,3 +151,69 @@ def test_autotune_keeps_results(ctx):
     ctx.autotune_clear()
     with pytest.raises(pkg.IpcError):
         ctx.autotune(_dev(np.zeros((40, 50), dtype=np.float32)), 1e-3)
+
+
+@pytest.mark.parametrize("dtype,rel", [(np.float32, 1e-4), (np.float64, 1e-7)])
+def test_pass_batch_equals_single_calls(ctx, dtype, rel):
+    """2-D fields of uneven shapes (different pass counts, ragged chunks) and
+    1-D fields through the one-pass-per-launch batch: streams, retrievals
+    and refinements equal the same field alone and the oracle."""
+    for shapes in ([(300, 500), (47, 1000), (9, 17), (1800, 700)], [(20000,), (333,), (5,)]):
+        xs = [fieldgen.random_field(sh, seed=60 + i, dtype=dtype) for i, sh in enumerate(shapes)]
+        ebs = [rel * fieldgen.value_range(x) for x in xs]
+        devs = [_dev(x) for x in xs]
+        batch = ctx.compress_batch(devs, ebs)
+        singles = [ctx.compress(d, e) for d, e in zip(devs, ebs)]
+        for i, (b, one) in enumerate(zip(batch, singles)):
+            bb = b.to_bytes()
+            assert bb == one.to_bytes(), f"field {i} {shapes[i]}"
+            if xs[i].size < 200_000:
+                assert bb == codec.compress(xs[i], ebs[i]), f"field {i} vs oracle"
+        for kind, vals in (("eb", [30 * e for e in ebs]), ("bitrate", [1.0, 3.0, 6.0, 9.0][:len(xs)])):
+            got = ctx.retrieve_batch(batch, **{kind: vals})
+            for i, st in enumerate(got):
+                one = singles[i].retrieve(**{kind: vals[i]})
+                assert st.plan == one.plan
+                assert _bytes(st.tensor()) == _bytes(one.tensor()), f"field {i} {kind}"
+                one.free()
+                st.free()
+        # served together: new retrievals and refinements joining at their
+        # first changed pass
+        base = [b.retrieve(eb=1e3 * e) for b, e in zip(batch, ebs)]
+        reqs = [(None, base[0], {"eb": ebs[0]}), (batch[1], None, {"bitrate": 4.0}),
+                (None, base[2], {"eb": 10 * ebs[2]})]
+        out = ctx.serve_batch(reqs)
+        assert [o[2] for o in out] == [0, 0, 0]
+        for (st, info, status), s in zip(out, [singles[0], singles[1], singles[2]]):
+            alone = s.retrieve_plan(st.plan)
+            assert _bytes(st.tensor()) == _bytes(alone.tensor())
+            alone.free()
+        out[1][0].free()
+        for st in base:
+            st.free()
+        for b, one in zip(batch, singles):
+            b.free()
+            one.free()
+
+
+def test_climate_batch_full_size(ctx):
+    """Four full 1800 x 3600 climate fields (two 30 % masked) compressed and
+    retrieved at 1, 2 and 4 bits per value in batches: equal to single calls."""
+    xs = [fieldgen.climate_2d(i) for i in range(4)]
+    ebs = [1e-3 * fieldgen.value_range(x) for x in xs]
+    devs = [_dev(x) for x in xs]
+    batch = ctx.compress_batch(devs, ebs)
+    for d, e, b in zip(devs, ebs, batch):
+        one = ctx.compress(d, e)
+        assert b.to_bytes() == one.to_bytes()
+        one.free()
+    for br in (1.0, 2.0, 4.0):
+        got = ctx.retrieve_batch(batch, bitrate=[br] * 4)
+        for b, st in zip(batch, got):
+            one = b.retrieve(bitrate=br)
+            assert st.plan == one.plan
+            assert _bytes(st.tensor()) == _bytes(one.tensor())
+            one.free()
+            st.free()
+    for b in batch:
+        b.free()
