@@ -114,16 +114,42 @@ __device__ __forceinline__ int64_t level_coord(int64_t m, int kind) {
   return kind == KIND_ANY ? m : (kind == KIND_ODD ? 2 * m + 1 : 2 * m);
 }
 
-// level coordinates and fine linear index of code j of a chunk
-__device__ __forceinline__ int64_t code_position(const PassArgs &a, const ChunkGeo &g, int j,
-                                                 int64_t lev[3]) {
-  int o2 = j % g.e[2];
-  int r = j / g.e[2];
-  int o1 = r % g.e[1];
-  int o0 = r / g.e[1];
-  lev[0] = level_coord(g.m0[0] + o0, a.kinds[0]);
-  lev[1] = level_coord(g.m0[1] + o1, a.kinds[1]);
-  lev[2] = level_coord(g.m0[2] + o2, a.kinds[2]);
+// Codes j = j0, j0 + WG, ... of a chunk walked in order: the chunk-local
+// coordinates (o0, o1, o2) advance by WG in mixed radix (e0, e1, e2) with one
+// carry per digit, instead of a division per code.
+struct CodeWalk {
+  int o0, o1, o2;     // chunk-local coordinates of the current code
+  int s0, s1, s2;     // WG in mixed radix
+  int e1, e2;
+  __device__ __forceinline__ CodeWalk(const ChunkGeo &g, int j0) {
+    e1 = g.e[1];
+    e2 = g.e[2];
+    o2 = j0 % e2;
+    const int r = j0 / e2;
+    o1 = r % e1;
+    o0 = r / e1;
+    s2 = WG % e2;
+    const int t = WG / e2;
+    s1 = t % e1;
+    s0 = t / e1;
+  }
+  __device__ __forceinline__ void next() {
+    o2 += s2;
+    int c = o2 >= e2;
+    o2 -= c ? e2 : 0;
+    o1 += s1 + c;
+    c = o1 >= e1;
+    o1 -= c ? e1 : 0;
+    o0 += s0 + c;
+  }
+};
+
+// level coordinates and fine linear index of the walk's current code
+__device__ __forceinline__ int64_t walk_position(const PassArgs &a, const ChunkGeo &g,
+                                                 const CodeWalk &w, int64_t lev[3]) {
+  lev[0] = level_coord(g.m0[0] + w.o0, a.kinds[0]);
+  lev[1] = level_coord(g.m0[1] + w.o1, a.kinds[1]);
+  lev[2] = level_coord(g.m0[2] + w.o2, a.kinds[2]);
   return ((a.h * lev[0]) * a.dims3[1] + a.h * lev[1]) * a.dims3[2] + a.h * lev[2];
 }
 
@@ -214,9 +240,10 @@ __device__ __forceinline__ void compress_chunk(const PassArgs &a, const int64_t 
   const int pd = a.dim3;
   uint32_t or_e = 0, or_v = 0, qabs = 0;
   unsigned long long mx = 0;
-  for (int j = tid; j < count; j += WG) {
+  CodeWalk cw(g, tid);
+  for (int j = tid; j < count; j += WG, cw.next()) {
     int64_t lev[3];
-    int64_t idx = code_position(a, g, j, lev);
+    int64_t idx = walk_position(a, g, cw, lev);
     T xv = x[idx];
     T pred;
     if (pd < 0)
@@ -352,12 +379,14 @@ __device__ __forceinline__ void retrieve_chunk(const PassArgs &a, const int64_t 
   const int W = (count + 31) >> 5;
   const bool packed = in.chunk_off != nullptr;
   const uint64_t off = packed ? in.chunk_off[gc] : a.slot_base + uint64_t(c) * 32u * a.wmax;
+  // the chunk's words from one uniform base with 32-bit offsets
+  const uint32_t *cbase = in.payload + off;
   for (int w = tid; w < W; w += WG) {
     uint32_t r[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
       uint32_t rank = packed ? uint32_t(__popc(k == 31 ? 0u : (mask >> (k + 1)))) : uint32_t(31 - k);
-      r[k] = ((load >> k) & 1u) ? in.payload[off + uint64_t(rank) * W + w] : 0u;
+      r[k] = ((load >> k) & 1u) ? cbase[rank * uint32_t(W) + uint32_t(w)] : 0u;
     }
     transpose32(r);
 #pragma unroll
@@ -390,9 +419,10 @@ __device__ __forceinline__ void retrieve_chunk(const PassArgs &a, const int64_t 
   const int pd = a.dim3;
   const bool additive = discard_old >= 0;
   const uint32_t keep_old = discard_old >= 32 || discard_old < 0 ? 0u : (0xFFFFFFFFu << discard_old);
-  for (int j = tid; j < count; j += WG) {
+  CodeWalk cw(g, tid);
+  for (int j = tid; j < count; j += WG, cw.next()) {
     int64_t lev[3];
-    int64_t idx = code_position(a, g, j, lev);
+    int64_t idx = walk_position(a, g, cw, lev);
     uint32_t v = s_v[lds_idx(j)];
     int64_t q = int64_t(v ^ NB_A) - int64_t(NB_A);
     T pred;
@@ -442,7 +472,8 @@ __device__ __forceinline__ int pass_item_field(const B *__restrict__ bf, int nf,
 template <typename T, int INTERP>
 __global__ __launch_bounds__(WG) void k_compress_batch(const PassBatchC<T> *__restrict__ bf, int nf) {
   const uint32_t it = blockIdx.x;
-  const PassBatchC<T> &b = bf[pass_item_field(bf, nf, it)];
+  // uniform field index: the arguments are read with scalar loads
+  const PassBatchC<T> &b = bf[__builtin_amdgcn_readfirstlane(pass_item_field(bf, nf, it))];
   compress_chunk<T, INTERP>(b.a, int64_t(it - b.item0), b.x, b.xh, b.write_back, b.eb, b.two_eb,
                             b.inv, b.qmax, b.o);
 }
@@ -450,7 +481,7 @@ __global__ __launch_bounds__(WG) void k_compress_batch(const PassBatchC<T> *__re
 template <typename T, int INTERP>
 __global__ __launch_bounds__(WG) void k_retrieve_batch(const PassBatchR<T> *__restrict__ bf, int nf) {
   const uint32_t it = blockIdx.x;
-  const PassBatchR<T> &b = bf[pass_item_field(bf, nf, it)];
+  const PassBatchR<T> &b = bf[__builtin_amdgcn_readfirstlane(pass_item_field(bf, nf, it))];
   retrieve_chunk<T, INTERP>(b.a, int64_t(it - b.item0), b.f, b.discard, b.in, b.two_eb, -1);
 }
 
