@@ -8,10 +8,13 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ipc_internal.h"
@@ -110,6 +113,46 @@ namespace {
 struct Fail {
   ipc_status st;
 };
+
+// fn(i) for i in [0, n) on up to 16 host threads (planning several requests:
+// each plan reads only its stream's tables).  The first exception any call
+// throws is rethrown after all threads have joined.
+template <typename Fn>
+void parallel_for(size_t n, Fn fn) {
+  const size_t hw = std::max<size_t>(1, std::min<size_t>(16, std::thread::hardware_concurrency()));
+  const size_t nt = std::min(n, hw);
+  if (nt <= 1 || n < 4) {
+    for (size_t i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::exception_ptr err;
+  std::mutex err_mu;
+  std::vector<std::thread> th;
+  th.reserve(nt - 1);
+  auto work = [&](size_t t, size_t stride) {
+    for (size_t i = t; i < n; i += stride) {
+      try {
+        fn(i);
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(err_mu);
+        if (!err) err = std::current_exception();
+      }
+    }
+  };
+  size_t started = 0;  // threads 1 .. started run their share
+  try {
+    for (size_t t = 1; t < nt; ++t) {
+      th.emplace_back(work, t, nt);
+      started = t;
+    }
+  } catch (...) {
+  }
+  // this thread: share 0 and the shares of threads that could not start
+  for (size_t t = 0; t < nt; ++t)
+    if (t == 0 || t > started) work(t, nt);
+  for (std::thread &x : th) x.join();
+  if (err) std::rethrow_exception(err);
+}
 
 void set_err(ipc_ctx *ctx, const std::string &m) {
   if (ctx) ctx->err = m;
@@ -1995,12 +2038,12 @@ ipc_status ipc_retrieve_batch(ipc_ctx *ctx, uint32_t n, const ipc_stream *const 
   std::vector<PlanResult> prs(n);
   std::vector<float> tplan(n);
   std::vector<std::vector<int>> plans(n);
-  for (uint32_t i = 0; i < n; ++i) {
+  parallel_for(n, [&](size_t i) {
     auto t0 = std::chrono::steady_clock::now();
     prs[i] = plan_request(ss[i]->tables, targets[i].kind, targets[i].value, nullptr);
     tplan[i] = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     plans[i] = prs[i].plan;
-  }
+  });
   std::vector<ipc_state *> sts(n, nullptr);
   ipc_status st = guarded(ctx, [&] {
     hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
@@ -2162,7 +2205,7 @@ ipc_status ipc_serve_batch(ipc_ctx *ctx, uint32_t n, ipc_request *req) {
     uint64_t read;
     int s_min;  // first pass to recompute (0 for a new retrieval)
   };
-  std::vector<Job> jobs;
+  std::vector<Job> cand;  // requests that need a plan, in order
   std::vector<const ipc_state *> seen;
   for (uint32_t i = 0; i < n; ++i) {
     ipc_request &q = req[i];
@@ -2184,16 +2227,36 @@ ipc_status ipc_serve_batch(ipc_ctx *ctx, uint32_t n, ipc_request *req) {
       q.status = IPC_ESTATE;
       continue;
     }
-    auto t0 = std::chrono::steady_clock::now();
-    Job j{i, s, q.refine ? q.state : nullptr, PlanResult(), s->meta.sched.K, 0.0f, 0, 0};
-    if (q.refine) {
-      ipc_state *st = q.state;
-      if ((q.target.kind & ~IPC_TARGET_LEVEL_GROUPS) == IPC_TARGET_EB && q.target.value >= st->bound) {
-        fill_info(s, st->plan, st->bound, IPC_FLAG_NOOP, 0, 0.0f, 0.0f, &q.info);
-        continue;
-      }
-      j.pr = plan_request(s->tables, q.target.kind, q.target.value, st->plan.data());
+    if (q.refine && (q.target.kind & ~IPC_TARGET_LEVEL_GROUPS) == IPC_TARGET_EB &&
+        q.target.value >= q.state->bound) {
+      fill_info(s, q.state->plan, q.state->bound, IPC_FLAG_NOOP, 0, 0.0f, 0.0f, &q.info);
+      continue;
+    }
+    cand.push_back(Job{i, s, q.refine ? q.state : nullptr, PlanResult(), s->meta.sched.K, 0.0f, 0, 0});
+  }
+  // the plans, on several host threads
+  ipc_status pst = IPC_OK;
+  try {
+    parallel_for(cand.size(), [&](size_t k) {
+      Job &j = cand[k];
+      const ipc_request &q = req[j.r];
+      auto t0 = std::chrono::steady_clock::now();
+      j.pr = plan_request(j.s->tables, q.target.kind, q.target.value, j.st ? j.st->plan.data() : nullptr);
       j.tplan = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    });
+  } catch (...) {
+    pst = IPC_ENOMEM;
+  }
+  if (pst != IPC_OK) {
+    for (Job &j : cand) req[j.r].status = pst;
+    return pst;
+  }
+  std::vector<Job> jobs;
+  for (Job &j : cand) {
+    ipc_request &q = req[j.r];
+    const ipc_stream *s = j.s;
+    if (j.st) {
+      ipc_state *st = j.st;
       if (j.pr.plan == st->plan) {
         fill_info(s, st->plan, st->bound, j.pr.flags | IPC_FLAG_NOOP, 0, j.tplan, 0.0f, &q.info);
         continue;
@@ -2205,8 +2268,6 @@ ipc_status ipc_serve_batch(ipc_ctx *ctx, uint32_t n, ipc_request *req) {
       j.l_start = s->meta.sched.passes[size_t(s_min)].level;
       if (s_min == 0) j.l_start = s->meta.sched.K;
     } else {
-      j.pr = plan_request(s->tables, q.target.kind, q.target.value, nullptr);
-      j.tplan = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
       std::vector<int> none(j.pr.plan.size(), 32);
       j.read = plane_bytes_between(s, j.pr.plan, none);
     }

@@ -31,6 +31,7 @@ constexpr uint32_t NB_A = 0xAAAAAAAAu;
 constexpr int WG = 256;
 constexpr int MAXC = int(MAX_CHUNK_CODES);
 constexpr int LDS_WORDS = MAXC + MAXC / 32;
+constexpr int PU = 4;  // codes per thread whose loads are issued together
 
 __device__ __forceinline__ int lds_idx(int j) { return j + (j >> 5); }
 
@@ -241,46 +242,61 @@ __device__ __forceinline__ void compress_chunk(const PassArgs &a, const int64_t 
   uint32_t or_e = 0, or_v = 0, qabs = 0;
   unsigned long long mx = 0;
   CodeWalk cw(g, tid);
-  for (int j = tid; j < count; j += WG, cw.next()) {
-    int64_t lev[3];
-    int64_t idx = walk_position(a, g, cw, lev);
-    T xv = x[idx];
-    T pred;
-    if (pd < 0)
-      pred = T(0);
-    else
-      pred = predict<T, INTERP>(xh, idx, st, lev[pd], a.ldims[pd]);
-    T diff = F::sub(xv, pred);
-    T qf = F::rnd(F::mul(diff, inv));
-    bool out = !(fabs(qf) <= qmax);
-    int32_t q = out ? 0 : int32_t(qf);
-    T xr = F::add(pred, F::mul(T(q), two_eb));
-    if (!out) out = !(fabs(__dsub_rn(double(xr), double(xv))) <= eb);
-    T xhat = xr;
-    if (out) {
-      q = 0;
-      xhat = xv;
-      unsigned long long slot = atomicAdd(o.n_out, 1ull);
-      if (slot < o.out_cap) {
-        OutlierRec *r = reinterpret_cast<OutlierRec *>(o.out_recs) + slot;
-        r->pass = a.pass_index;
-        r->chunk = uint32_t(c);
-        r->local = uint32_t(j);
-        r->pad = 0;
-        r->bits = F::bits(xv);
+  // PU codes per thread at a time: their loads first, then their stores (the
+  // targets of a pass are never neighbours within it, so no load here reads
+  // what a store of the group writes; the compiler cannot know that)
+  for (int j0 = tid; j0 < count; j0 += PU * WG) {
+    int64_t idxu[PU];
+    T xvu[PU], predu[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      if (j0 + u * WG < count) {
+        int64_t lev[3];
+        idxu[u] = walk_position(a, g, cw, lev);
+        xvu[u] = x[idxu[u]];
+        predu[u] = pd < 0 ? T(0) : predict<T, INTERP>(xh, idxu[u], st, lev[pd], a.ldims[pd]);
       }
+      cw.next();
     }
-    if (write_back) xh[idx] = xhat;
-    uint32_t v = (uint32_t(q) + NB_A) ^ NB_A;
-    s_v[lds_idx(j)] = v;
-    or_v |= v;
-    or_e |= xor_encode(v);
-    uint32_t aq = q < 0 ? uint32_t(-int64_t(q)) : uint32_t(q);
-    qabs = aq > qabs ? aq : qabs;
-    double ax = fabs(double(xhat));
-    if (ax <= 1.7976931348623157e308) {
-      unsigned long long bx = (unsigned long long)__double_as_longlong(ax);
-      mx = bx > mx ? bx : mx;
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int j = j0 + u * WG;
+      if (j >= count) break;
+      const int64_t idx = idxu[u];
+      const T xv = xvu[u];
+      const T pred = predu[u];
+      T diff = F::sub(xv, pred);
+      T qf = F::rnd(F::mul(diff, inv));
+      bool out = !(fabs(qf) <= qmax);
+      int32_t q = out ? 0 : int32_t(qf);
+      T xr = F::add(pred, F::mul(T(q), two_eb));
+      if (!out) out = !(fabs(__dsub_rn(double(xr), double(xv))) <= eb);
+      T xhat = xr;
+      if (out) {
+        q = 0;
+        xhat = xv;
+        unsigned long long slot = atomicAdd(o.n_out, 1ull);
+        if (slot < o.out_cap) {
+          OutlierRec *r = reinterpret_cast<OutlierRec *>(o.out_recs) + slot;
+          r->pass = a.pass_index;
+          r->chunk = uint32_t(c);
+          r->local = uint32_t(j);
+          r->pad = 0;
+          r->bits = F::bits(xv);
+        }
+      }
+      if (write_back) xh[idx] = xhat;
+      uint32_t v = (uint32_t(q) + NB_A) ^ NB_A;
+      s_v[lds_idx(j)] = v;
+      or_v |= v;
+      or_e |= xor_encode(v);
+      uint32_t aq = q < 0 ? uint32_t(-int64_t(q)) : uint32_t(q);
+      qabs = aq > qabs ? aq : qabs;
+      double ax = fabs(double(xhat));
+      if (ax <= 1.7976931348623157e308) {
+        unsigned long long bx = (unsigned long long)__double_as_longlong(ax);
+        mx = bx > mx ? bx : mx;
+      }
     }
   }
   or_e = wave_or(or_e);
@@ -420,36 +436,49 @@ __device__ __forceinline__ void retrieve_chunk(const PassArgs &a, const int64_t 
   const bool additive = discard_old >= 0;
   const uint32_t keep_old = discard_old >= 32 || discard_old < 0 ? 0u : (0xFFFFFFFFu << discard_old);
   CodeWalk cw(g, tid);
-  for (int j = tid; j < count; j += WG, cw.next()) {
-    int64_t lev[3];
-    int64_t idx = walk_position(a, g, cw, lev);
-    uint32_t v = s_v[lds_idx(j)];
-    int64_t q = int64_t(v ^ NB_A) - int64_t(NB_A);
-    T pred;
-    if (pd < 0)
-      pred = T(0);
-    else
-      pred = predict<T, INTERP>(f, idx, st, lev[pd], a.ldims[pd]);
-    T tq;
-    if (additive) {
-      // the planes above discard_old, as the previous plan held them
-      const uint32_t vo = xor_decode(xor_encode(v) & keep_old) & keep_old;
-      tq = T(q - (int64_t(vo ^ NB_A) - int64_t(NB_A)));
-    } else {
-      // float32 codes have at most 26 negabinary digits, so q fits in int32
-      tq = sizeof(T) == 4 ? T(int32_t(q)) : T(q);
-    }
-    T val = F::add(pred, F::mul(tq, two_eb));
-    if (ohi > olo) {
-      uint64_t b0 = olo, b1 = ohi;
-      while (b0 < b1) {
-        uint64_t m = (b0 + b1) >> 1;
-        if (in.out_local[m] < uint32_t(j)) b0 = m + 1; else b1 = m;
+  // PU codes per thread at a time: their loads first, then their stores (see
+  // compress_chunk)
+  for (int j0 = tid; j0 < count; j0 += PU * WG) {
+    int64_t idxu[PU];
+    T predu[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      if (j0 + u * WG < count) {
+        int64_t lev[3];
+        idxu[u] = walk_position(a, g, cw, lev);
+        predu[u] = pd < 0 ? T(0) : predict<T, INTERP>(f, idxu[u], st, lev[pd], a.ldims[pd]);
       }
-      if (b0 < ohi && in.out_local[b0] == uint32_t(j))
-        val = additive ? T(0) : F::from_bits(in.out_bits[b0]);
+      cw.next();
     }
-    f[idx] = val;
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int j = j0 + u * WG;
+      if (j >= count) break;
+      const int64_t idx = idxu[u];
+      uint32_t v = s_v[lds_idx(j)];
+      int64_t q = int64_t(v ^ NB_A) - int64_t(NB_A);
+      const T pred = predu[u];
+      T tq;
+      if (additive) {
+        // the planes above discard_old, as the previous plan held them
+        const uint32_t vo = xor_decode(xor_encode(v) & keep_old) & keep_old;
+        tq = T(q - (int64_t(vo ^ NB_A) - int64_t(NB_A)));
+      } else {
+        // float32 codes have at most 26 negabinary digits, so q fits in int32
+        tq = sizeof(T) == 4 ? T(int32_t(q)) : T(q);
+      }
+      T val = F::add(pred, F::mul(tq, two_eb));
+      if (ohi > olo) {
+        uint64_t b0 = olo, b1 = ohi;
+        while (b0 < b1) {
+          uint64_t m = (b0 + b1) >> 1;
+          if (in.out_local[m] < uint32_t(j)) b0 = m + 1; else b1 = m;
+        }
+        if (b0 < ohi && in.out_local[b0] == uint32_t(j))
+          val = additive ? T(0) : F::from_bits(in.out_bits[b0]);
+      }
+      f[idx] = val;
+    }
   }
 }
 

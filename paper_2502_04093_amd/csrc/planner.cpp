@@ -111,7 +111,8 @@ static PlanResult plan_eb(const PlanTables &t, double E, const int *limit, bool 
     std::fill(nF.begin(), nF.end(), NEG);
     uint8_t *ch = &choice[size_t(gi) * (G_UNITS + 1)];
     int hi = allowed_hi(t, g, limit);
-    int64_t saved = 0;
+    int64_t saved = 0, prev_saved = -1;
+    int prev_c = -1;
     for (int b = 0; b <= hi; ++b) {
       if (b > 0) saved += group_bytes(t, g, b - 1, b);
       double tv = group_term(t, g, b, r);
@@ -124,6 +125,11 @@ static PlanResult plan_eb(const PlanTables &t, double E, const int *limit, bool 
       }
       cost[size_t(gi) * 33 + b] = c;
       if (c > G_UNITS) continue;
+      // the same (cost, saved bytes) as the choice before: it can only tie
+      // with it, and ties go to the smaller b
+      if (c == prev_c && saved == prev_saved) continue;
+      prev_c = c;
+      prev_saved = saved;
       for (int rr = c; rr <= G_UNITS; ++rr) {
         int64_t prev = F[rr - c];
         if (prev == NEG) continue;
@@ -180,11 +186,18 @@ static PlanResult plan_br(const PlanTables &t, double bitrate, const int *limit,
     std::fill(nF.begin(), nF.end(), INF);
     uint8_t *ch = &choice[size_t(gi) * (cap + 1)];
     int hi = allowed_hi(t, g, limit);
+    int64_t prev_lc = -1;
+    double prev_tv = -1.0;
     for (int b = 0; b <= hi; ++b) {
       const int64_t lc = (group_bytes(t, g, b, 32) + ub - 1) / ub;
       const double tv = group_term(t, g, b, r);
       lcs[size_t(gi) * 33 + b] = lc;
       if (lc > cap) continue;
+      // the same (bytes, term) as the choice before: it can only tie with
+      // it, and ties go to the smaller b
+      if (lc == prev_lc && tv == prev_tv) continue;
+      prev_lc = lc;
+      prev_tv = tv;
       for (int64_t rr = lc; rr <= cap; ++rr) {
         double cand = F[rr - lc] + tv;
         if (cand < nF[rr]) {
