@@ -194,6 +194,16 @@ def main():
         lat.append((time.perf_counter() - t0) * 1e3)
         st.free()
     s.free()
+    # quality of the full retrieval (outside the timed region)
+    s = ctx.compress(x, eb, interp=args.interp)
+    st = s.retrieve(eb=eb)
+    err = st.tensor().double() - x.double()
+    max_err = float(err.abs().max())
+    mse = float((err * err).mean())
+    psnr = 20 * math.log10(rng) - 10 * math.log10(mse) if mse > 0 else float("inf")
+    del err
+    st.free()
+    s.free()
     lat.sort()
     p50 = lat[len(lat) // 2] if lat else None
     p99 = lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)] if lat else None
@@ -227,6 +237,7 @@ def main():
         "compress_GBps": round(gb / (tc / args.steps), 3),
         "retrieve_GBps": round(gb / (tr / args.steps), 3),
         "retrieve_latency_ms": {"p50": p50 and round(p50, 4), "p99": p99 and round(p99, 4), "calls": L},
+        "quality": {"max_abs_err": max_err, "within_eb": max_err <= eb, "psnr_db": round(psnr, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "kernel": kname, "alg_bytes_per_launch": int(alg_bytes),
@@ -236,7 +247,7 @@ def main():
     }
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(x, eb, args, rng)
+        out["cpu_baseline"], out["parity"] = cpu_baseline(x, eb, args, ctx)
     print(json.dumps(out), flush=True)
     ctx.close()
 
@@ -752,24 +763,40 @@ def counted_traffic(op, level, shape, itemsize, interp):
     return None
 
 
-def cpu_baseline(x, eb, args, rng):
-    """The oracle (plain NumPy, one core) on a cubic corner of the same field."""
+def cpu_baseline(x, eb, args, ctx):
+    """The oracle (plain NumPy, one core) on a cubic corner of the same field,
+    and the parity of the GPU path on that corner: its stream and full
+    retrieval compared byte for byte with the oracle's."""
+    import hashlib
+
     import numpy as np
     from oracle import codec
     e = min(args.cpu_sample, *x.shape) if x.dim() == 3 else None
     sub = x[:e, :e, :e] if x.dim() == 3 else x
     xs = np.ascontiguousarray(sub.cpu().numpy())
     print(f"[bench] cpu baseline: oracle on {xs.shape}", file=sys.stderr, flush=True)
+    interp = 1 if args.interp == "cubic" else 0
     t0 = time.perf_counter()
-    buf = codec.compress(xs, eb, interp=1 if args.interp == "cubic" else 0)
+    buf = codec.compress(xs, eb, interp=interp)
     t1 = time.perf_counter()
-    codec.retrieve(buf, "eb", eb)
+    ref = codec.retrieve(buf, "eb", eb)
     t2 = time.perf_counter()
     gb = xs.nbytes / 1e9
-    return {"value": round(gb / (t2 - t0), 5), "unit": "GB/s", "cores": 1, "kind": "oracle",
+    base = {"value": round(gb / (t2 - t0), 5), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"{'x'.join(map(str, xs.shape))} corner of the same field, same eb; "
                       f"compress {t1 - t0:.2f} s + full retrieve {t2 - t1:.2f} s",
             "compress_GBps": round(gb / (t1 - t0), 5), "retrieve_GBps": round(gb / (t2 - t1), 5)}
+    s = ctx.compress(sub.contiguous(), eb, interp=args.interp)
+    got = s.to_bytes()
+    st = s.retrieve(eb=eb)
+    fld = st.tensor().cpu().numpy().tobytes()
+    st.free()
+    s.free()
+    parity = {"sample": f"{'x'.join(map(str, xs.shape))} corner",
+              "stream_sha256": hashlib.sha256(got).hexdigest()[:16],
+              "stream_equal_oracle": got == buf,
+              "retrieval_equal_oracle": fld == ref.field.tobytes()}
+    return base, parity
 
 
 if __name__ == "__main__":
