@@ -348,32 +348,38 @@ void upload_outliers(ipc_ctx *ctx, ipc_stream *s) {
 }
 
 // the device-sorted outlier records into meta.outliers (pass, chunk, local, bits)
-// Stored blocks in payload order (chunks in order, planes 31 down to 0): raw
-// offset in the packed placement and, for a coded stream, offset of the
-// stored form
-std::vector<EcBlock> stream_blocks(const StreamMeta &m) {
-  std::vector<EcBlock> out;
-  out.reserve(size_t(n_blocks(m)));
-  uint64_t raw = 0, coded = 0;
+// Descriptors of the stored blocks (payload order: chunks in order, planes
+// 31 down to 0) built on the device into `blk` from three per-chunk tables
+// made here: first block, raw word offset in the packed placement, codes.
+// Coded offsets are filled separately (launch_ec_offsets).  `tabs` holds the
+// uploaded tables until the caller synchronizes.
+void device_blocks(ipc_ctx *ctx, const StreamMeta &m, DevBuf &blk, DevBuf &tabs) {
+  const size_t nc = size_t(m.sched.n_chunks);
+  std::vector<uint64_t> craw;
+  packed_chunk_offsets(m, craw);  // nc + 1 entries
+  std::vector<uint32_t> cblk(nc + 1), ccount(nc + 1, 0);
+  uint32_t nb = 0;
   for (const PassGeom &p : m.sched.passes)
     for (int64_t c = 0; c < p.n_chunks; ++c) {
-      const uint32_t mk = m.masks[size_t(p.chunk_base + c)];
-      if (!mk) continue;
-      const uint32_t cnt = uint32_t(chunk_count(p, c));
-      const uint64_t W = (cnt + 31) / 32;
-      for (int k = 31; k >= 0; --k) {
-        if (!((mk >> k) & 1u)) continue;
-        EcBlock b;
-        b.raw_off = raw;
-        b.coded_off = coded;
-        b.count = cnt;
-        b.pad = 0;
-        raw += W;
-        if (m.coding) coded += m.block_words[out.size()];
-        out.push_back(b);
-      }
+      const size_t g = size_t(p.chunk_base + c);
+      cblk[g] = nb;
+      ccount[g] = uint32_t(chunk_count(p, c));
+      nb += uint32_t(__builtin_popcount(m.masks[g]));
     }
-  return out;
+  cblk[nc] = nb;
+  const size_t b_raw = craw.size() * 8, b_blk = cblk.size() * 4, b_cnt = ccount.size() * 4;
+  tabs = dev_alloc(ctx, b_raw + b_blk + b_cnt);
+  char *t = static_cast<char *>(tabs.p);
+  hip_check(ctx, hipMemcpyAsync(t, craw.data(), b_raw, hipMemcpyHostToDevice, ctx->stream), "upload");
+  hip_check(ctx, hipMemcpyAsync(t + b_raw, cblk.data(), b_blk, hipMemcpyHostToDevice, ctx->stream), "upload");
+  hip_check(ctx, hipMemcpyAsync(t + b_raw + b_blk, ccount.data(), b_cnt, hipMemcpyHostToDevice, ctx->stream),
+            "upload");
+  blk = dev_alloc(ctx, std::max<size_t>(sizeof(EcBlock), size_t(nb) * sizeof(EcBlock)));
+  hip_check(ctx, launch_ec_blocks(reinterpret_cast<const uint32_t *>(t + b_raw),
+                                  reinterpret_cast<const uint64_t *>(t),
+                                  reinterpret_cast<const uint32_t *>(t + b_raw + b_blk), nc,
+                                  static_cast<EcBlock *>(blk.p), ctx->stream),
+            "block table launch");
 }
 
 void fetch_outliers(ipc_ctx *ctx, ipc_stream *s) {
@@ -1498,40 +1504,31 @@ ipc_status ipc_stream_entropy_code(ipc_ctx *ctx, ipc_stream *s) {
     hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
     StreamMeta &m = s->meta;
     ensure_host_masks(ctx, s);
-    std::vector<EcBlock> blk = stream_blocks(m);
-    const uint64_t nb = blk.size();
-    DevBuf tmp, tmp_off, dblk, scratch, dwords, coded;
+    const uint64_t nb = n_blocks(m);
+    DevBuf tmp, tmp_off, dblk, tabs, scratch, dwords, dtot, coded;
     auto release = [&] {
-      for (DevBuf *b : {&tmp, &tmp_off, &dblk, &scratch, &dwords}) dev_free(ctx, *b);
+      for (DevBuf *b : {&tmp, &tmp_off, &dblk, &tabs, &scratch, &dwords, &dtot}) dev_free(ctx, *b);
     };
     try {
+      device_blocks(ctx, m, dblk, tabs);
       const uint32_t *raw = packed_payload(ctx, s, tmp, tmp_off);
-      dblk = dev_alloc(ctx, std::max<size_t>(sizeof(EcBlock), nb * sizeof(EcBlock)));
       scratch = dev_alloc(ctx, std::max<size_t>(4, m.payload_words * 4));
       dwords = dev_alloc(ctx, std::max<size_t>(1, nb));
-      if (nb)
-        hip_check(ctx, hipMemcpyAsync(dblk.p, blk.data(), nb * sizeof(EcBlock), hipMemcpyHostToDevice,
-                                      ctx->stream), "upload");
-      hip_check(ctx, launch_ec_encode(static_cast<const EcBlock *>(dblk.p), nb, raw,
-                                      static_cast<uint32_t *>(scratch.p), static_cast<uint8_t *>(dwords.p),
-                                      ctx->stream), "entropy encode launch");
+      dtot = dev_alloc(ctx, std::max<size_t>(8, (nb + 1023) / 1024 * 8));
+      EcBlock *blk = static_cast<EcBlock *>(dblk.p);
+      uint8_t *words_d = static_cast<uint8_t *>(dwords.p);
+      hip_check(ctx, launch_ec_encode(blk, nb, raw, static_cast<uint32_t *>(scratch.p), words_d, ctx->stream),
+                "entropy encode launch");
+      hip_check(ctx, launch_ec_offsets(words_d, nb, blk, static_cast<uint64_t *>(dtot.p), ctx->stream),
+                "entropy offsets launch");
       std::vector<uint8_t> words(nb);
       if (nb)
-        hip_check(ctx, hipMemcpyAsync(words.data(), dwords.p, nb, hipMemcpyDeviceToHost, ctx->stream),
-                  "copy");
+        hip_check(ctx, hipMemcpyAsync(words.data(), words_d, nb, hipMemcpyDeviceToHost, ctx->stream), "copy");
       hip_check(ctx, hipStreamSynchronize(ctx->stream), "entropy encode");
       uint64_t tot = 0;
-      for (uint64_t i = 0; i < nb; ++i) {
-        blk[i].coded_off = tot;
-        tot += words[i];
-      }
+      for (uint8_t w : words) tot += w;
       coded = dev_alloc(ctx, std::max<size_t>(4, tot * 4));
-      if (nb)
-        hip_check(ctx, hipMemcpyAsync(dblk.p, blk.data(), nb * sizeof(EcBlock), hipMemcpyHostToDevice,
-                                      ctx->stream), "upload");
-      hip_check(ctx, launch_ec_gather(static_cast<const EcBlock *>(dblk.p), nb,
-                                      static_cast<const uint8_t *>(dwords.p),
-                                      static_cast<const uint32_t *>(scratch.p),
+      hip_check(ctx, launch_ec_gather(blk, nb, words_d, static_cast<const uint32_t *>(scratch.p),
                                       static_cast<uint32_t *>(coded.p), ctx->stream),
                 "entropy gather launch");
       hip_check(ctx, hipStreamSynchronize(ctx->stream), "entropy gather");
@@ -1543,6 +1540,7 @@ ipc_status ipc_stream_entropy_code(ipc_ctx *ctx, ipc_stream *s) {
       coded = DevBuf();
       s->tables = plan_tables(m);
     } catch (...) {
+      (void)hipStreamSynchronize(ctx->stream);
       release();
       dev_free(ctx, coded);
       throw;
@@ -1587,34 +1585,37 @@ ipc_status ipc_stream_from_host(ipc_ctx *ctx, const void *src, uint64_t bytes, i
     s->chunk_off = dev_alloc(ctx, off.size() * 8);
     if (m.coding) {
       // stored blocks to the device, decoded there into the packed placement
-      std::vector<EcBlock> blk = stream_blocks(m);
-      const uint64_t nb = blk.size();
+      const uint64_t nb = m.block_words.size();
       s->coded = dev_alloc(ctx, std::max<size_t>(4, m.coded_words * 4));
-      DevBuf dblk = dev_alloc(ctx, std::max<size_t>(sizeof(EcBlock), nb * sizeof(EcBlock)));
-      DevBuf dwords = dev_alloc(ctx, std::max<size_t>(1, nb));
+      DevBuf dblk, tabs, dwords, dtot;
+      auto release = [&] {
+        for (DevBuf *b : {&dblk, &tabs, &dwords, &dtot}) dev_free(ctx, *b);
+      };
       try {
         if (m.coded_words)
           hip_check(ctx, hipMemcpyAsync(s->coded.p, payload, m.coded_words * 4, hipMemcpyHostToDevice,
                                         ctx->stream), "upload");
-        if (nb) {
-          hip_check(ctx, hipMemcpyAsync(dblk.p, blk.data(), nb * sizeof(EcBlock), hipMemcpyHostToDevice,
-                                        ctx->stream), "upload");
+        device_blocks(ctx, m, dblk, tabs);
+        dwords = dev_alloc(ctx, std::max<size_t>(1, nb));
+        dtot = dev_alloc(ctx, std::max<size_t>(8, (nb + 1023) / 1024 * 8));
+        if (nb)
           hip_check(ctx, hipMemcpyAsync(dwords.p, m.block_words.data(), nb, hipMemcpyHostToDevice,
                                         ctx->stream), "upload");
-        }
-        hip_check(ctx, launch_ec_decode(static_cast<const EcBlock *>(dblk.p), nb,
-                                        static_cast<const uint8_t *>(dwords.p),
+        EcBlock *blk = static_cast<EcBlock *>(dblk.p);
+        hip_check(ctx, launch_ec_offsets(static_cast<const uint8_t *>(dwords.p), nb, blk,
+                                         static_cast<uint64_t *>(dtot.p), ctx->stream),
+                  "entropy offsets launch");
+        hip_check(ctx, launch_ec_decode(blk, nb, static_cast<const uint8_t *>(dwords.p),
                                         static_cast<const uint32_t *>(s->coded.p),
                                         static_cast<uint32_t *>(s->payload.p), ctx->stream),
                   "entropy decode launch");
         hip_check(ctx, hipStreamSynchronize(ctx->stream), "entropy decode");
       } catch (...) {
-        dev_free(ctx, dblk);
-        dev_free(ctx, dwords);
+        (void)hipStreamSynchronize(ctx->stream);
+        release();
         throw;
       }
-      dev_free(ctx, dblk);
-      dev_free(ctx, dwords);
+      release();
     } else if (m.payload_words) {
       hip_check(ctx, hipMemcpyAsync(s->payload.p, payload, m.payload_words * 4, hipMemcpyHostToDevice,
                                     ctx->stream), "upload");

@@ -208,7 +208,83 @@ __global__ __launch_bounds__(EC_WG) void k_ec_decode(const EcBlock *__restrict__
   }
 }
 
+// one thread per chunk: the descriptors of its stored blocks (planes from
+// 31 down, each W = ceil(count / 32) words in the packed placement)
+__global__ __launch_bounds__(256) void k_ec_blocks(const uint32_t *__restrict__ cblk,
+                                                   const uint64_t *__restrict__ craw,
+                                                   const uint32_t *__restrict__ ccount,
+                                                   uint64_t n_chunks, EcBlock *__restrict__ blk) {
+  const uint64_t c = uint64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (c >= n_chunks) return;
+  const uint32_t b0 = cblk[c], b1 = cblk[c + 1];
+  const uint32_t count = ccount[c];
+  const uint64_t W = (count + 31) >> 5;
+  for (uint32_t r = 0; r < b1 - b0; ++r) {
+    EcBlock e;
+    e.raw_off = craw[c] + uint64_t(r) * W;
+    e.coded_off = 0;
+    e.count = count;
+    e.pad = 0;
+    blk[b0 + r] = e;
+  }
+}
+
+// exclusive scan of the stored word counts into the blocks' coded offsets:
+// tiles of 1024 blocks scanned in LDS, tile totals to `tot`
+__global__ __launch_bounds__(1024) void k_ec_scan_tiles(const uint8_t *__restrict__ words, uint64_t n,
+                                                        EcBlock *__restrict__ blk,
+                                                        uint64_t *__restrict__ tot) {
+  __shared__ uint32_t s[1024];
+  const uint64_t i = uint64_t(blockIdx.x) * 1024 + threadIdx.x;
+  const uint32_t x = i < n ? words[i] : 0u;
+  s[threadIdx.x] = x;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint32_t t = threadIdx.x >= unsigned(o) ? s[threadIdx.x - o] : 0u;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  if (i < n) blk[i].coded_off = s[threadIdx.x] - x;
+  if (threadIdx.x == 1023) tot[blockIdx.x] = s[1023];
+}
+
+// adds to every tile the totals of the tiles before it (each workgroup sums
+// them itself)
+__global__ __launch_bounds__(1024) void k_ec_scan_add(uint64_t n, EcBlock *__restrict__ blk,
+                                                      const uint64_t *__restrict__ tot) {
+  __shared__ uint64_t s[1024];
+  uint64_t t = 0;
+  for (uint32_t j = threadIdx.x; j < blockIdx.x; j += 1024) t += tot[j];
+  s[threadIdx.x] = t;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < unsigned(o)) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  const uint64_t i = uint64_t(blockIdx.x) * 1024 + threadIdx.x;
+  if (i < n) blk[i].coded_off += s[0];
+}
+
 }  // namespace
+
+hipError_t launch_ec_blocks(const uint32_t *cblk, const uint64_t *craw, const uint32_t *ccount,
+                            uint64_t n_chunks, EcBlock *blk, hipStream_t s) {
+  if (n_chunks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ec_blocks, dim3(uint32_t((n_chunks + 255) / 256)), dim3(256), 0, s, cblk, craw,
+                     ccount, n_chunks, blk);
+  return hipGetLastError();
+}
+
+hipError_t launch_ec_offsets(const uint8_t *words, uint64_t n, EcBlock *blk, uint64_t *tot,
+                             hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint32_t tiles = uint32_t((n + 1023) / 1024);
+  hipLaunchKernelGGL(k_ec_scan_tiles, dim3(tiles), dim3(1024), 0, s, words, n, blk, tot);
+  hipLaunchKernelGGL(k_ec_scan_add, dim3(tiles), dim3(1024), 0, s, n, blk,
+                     static_cast<const uint64_t *>(tot));
+  return hipGetLastError();
+}
 
 hipError_t launch_ec_encode(const EcBlock *blk, uint64_t n, const uint32_t *raw, uint32_t *scratch,
                             uint8_t *words, hipStream_t s) {

@@ -213,6 +213,15 @@ struct EcBlock {
 // count into words[i]
 hipError_t launch_ec_encode(const EcBlock *blk, uint64_t n, const uint32_t *raw, uint32_t *scratch,
                             uint8_t *words, hipStream_t s);
+// the blocks of n_chunks chunks: chunk c holds blocks cblk[c] .. cblk[c+1]
+// (its stored planes from 31 down), raw planes from word craw[c], ccount[c]
+// codes each
+hipError_t launch_ec_blocks(const uint32_t *cblk, const uint64_t *craw, const uint32_t *ccount,
+                            uint64_t n_chunks, EcBlock *blk, hipStream_t s);
+// coded_off of every block: exclusive prefix sum of words[] (tot: one u64 per
+// 1024 blocks of scratch)
+hipError_t launch_ec_offsets(const uint8_t *words, uint64_t n, EcBlock *blk, uint64_t *tot,
+                             hipStream_t s);
 // words[i] stored words of every block from its scratch slot to coded_off
 hipError_t launch_ec_gather(const EcBlock *blk, uint64_t n, const uint8_t *words,
                             const uint32_t *scratch, uint32_t *coded, hipStream_t s);
