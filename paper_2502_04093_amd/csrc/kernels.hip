@@ -21,6 +21,7 @@
 #include "kernels.h"
 
 #include <algorithm>
+#include <type_traits>
 
 #include "ipc_internal.h"
 
@@ -186,26 +187,50 @@ __device__ __forceinline__ T predict(const T *w, int64_t idx, int64_t st, int64_
   return F::mul(F::add(b, c), T(0.5));
 }
 
+// Reductions over a full wave (every lane active) in registers: lane swaps
+// within each row of 16 by DPP (quad permutes, half-row and row mirrors; order
+// is irrelevant for OR and max), then the four row results read out.  The
+// result is uniform.
+template <int CTRL>
+__device__ __forceinline__ uint32_t lane_swap(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, 0xF, 0xF, false));
+}
+template <typename Op>
+__device__ __forceinline__ uint32_t wave_fold(uint32_t v, Op op) {
+  v = op(v, lane_swap<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+  v = op(v, lane_swap<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+  v = op(v, lane_swap<0x141>(v));  // row_half_mirror
+  v = op(v, lane_swap<0x140>(v));  // row_mirror
+  const uint32_t r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+  const uint32_t r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+  return op(op(r0, r1), op(r2, r3));
+}
 __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
-  return v;
+  return wave_fold(v, [](uint32_t a, uint32_t b) { return a | b; });
 }
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    uint32_t u = __shfl_xor(v, o, 64);
-    v = u > v ? u : v;
-  }
-  return v;
+  return wave_fold(v, [](uint32_t a, uint32_t b) { return a > b ? a : b; });
 }
 __device__ __forceinline__ unsigned long long wave_max64(unsigned long long v) {
+  auto mx = [](unsigned long long a, unsigned long long b) { return a > b ? a : b; };
+  auto sw = [](unsigned long long x, auto ctrl) {
+    constexpr int C = decltype(ctrl)::value;
+    return (unsigned long long)lane_swap<C>(uint32_t(x)) |
+           ((unsigned long long)lane_swap<C>(uint32_t(x >> 32)) << 32);
+  };
+  v = mx(v, sw(v, std::integral_constant<int, 0xB1>{}));
+  v = mx(v, sw(v, std::integral_constant<int, 0x4E>{}));
+  v = mx(v, sw(v, std::integral_constant<int, 0x141>{}));
+  v = mx(v, sw(v, std::integral_constant<int, 0x140>{}));
+  unsigned long long r = 0;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    unsigned long long u = __shfl_xor(v, o, 64);
-    v = u > v ? u : v;
+  for (int l = 0; l < 64; l += 16) {
+    const unsigned long long x =
+        (unsigned long long)uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v)), l)) |
+        ((unsigned long long)uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v >> 32)), l)) << 32);
+    r = mx(r, x);
   }
-  return v;
+  return r;
 }
 
 // Chunk c of one pass (the workgroup's share of a k_compress launch).
