@@ -408,7 +408,6 @@ __device__ __forceinline__ void retrieve_chunk(const PassArgs &a, const int64_t 
                                                int discard_old) {
   using F = FP<T>;
   __shared__ uint32_t s_v[LDS_WORDS];
-  __shared__ uint64_t s_lo, s_hi;
   const int tid = threadIdx.x;
   const ChunkGeo g = chunk_geo(a, c);
   const int count = g.count;
@@ -436,26 +435,11 @@ __device__ __forceinline__ void retrieve_chunk(const PassArgs &a, const int64_t 
       if (jj < count) s_v[lds_idx(jj)] = xor_decode(r[j]) & keep;
     }
   }
-  if (tid == 0) {
-    uint64_t lo = 0, hi = in.n_out;
-    // first outlier with chunk >= gc
-    uint64_t a0 = 0, a1 = in.n_out;
-    while (a0 < a1) {
-      uint64_t m = (a0 + a1) >> 1;
-      if (in.out_gchunk[m] < uint64_t(gc)) a0 = m + 1; else a1 = m;
-    }
-    lo = a0;
-    a1 = in.n_out;
-    while (a0 < a1) {
-      uint64_t m = (a0 + a1) >> 1;
-      if (in.out_gchunk[m] <= uint64_t(gc)) a0 = m + 1; else a1 = m;
-    }
-    hi = a0;
-    s_lo = lo;
-    s_hi = hi;
-  }
   __syncthreads();
-  const uint64_t olo = s_lo, ohi = s_hi;
+  // the chunk's outliers: records out_start[gc] .. out_start[gc + 1] (a
+  // stream without outliers has no table)
+  const bool any_out = in.n_out > 0;
+  const uint64_t olo = any_out ? in.out_start[gc] : 0, ohi = any_out ? in.out_start[gc + 1] : 0;
   const int64_t st = pass_stride(a);
   const int pd = a.dim3;
   const bool additive = discard_old >= 0;
