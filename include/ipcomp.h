@@ -128,9 +128,13 @@ void ipc_stream_free(ipc_stream *s);
  *   - retrieval and refinement read the resident raw planes, unchanged.
  * A stream already coded is left as it is.  ipc_stream_from_host accepts both
  * forms and decodes a coded one on the device.  The coded payload stays on the
- * device beside the raw planes (at most the size of the raw payload). */
+ * device beside the raw planes (at most the size of the raw payload), owned
+ * by the stream and freed with it.
+ * Errors: IPC_EINVAL (null argument), IPC_ESTATE (stream of another
+ * context), IPC_ENOMEM / IPC_EHIP (device memory or a HIP failure: the stream
+ * is left raw and usable).  Returns when the coded form is complete. */
 ipc_status ipc_stream_entropy_code(ipc_ctx *ctx, ipc_stream *s);
-/* 0 raw blocks, 1 entropy-coded blocks */
+/* *coding = 0 (raw blocks) or 1 (entropy-coded blocks); IPC_EINVAL on null. */
 ipc_status ipc_stream_coding(const ipc_stream *s, int *coding);
 
 /* Per-pass description of a stream (the planner's inputs, Sec. 5). */
@@ -181,7 +185,9 @@ void ipc_state_free(ipc_state *st);
  * adds a rounding allowance to the plan's bound (the old reconstruction's
  * rounding terms, the difference field's, and u M for the addition).  Runs
  * the one-pass-per-launch kernels for every shape.  Uses a context working
- * buffer of the field's size. */
+ * buffer of the field's size.  Arguments, no-op cases and errors as for
+ * ipc_refine; on an error the state keeps its plan and bound (its field may
+ * be partly updated if the failure came from the device). */
 ipc_status ipc_refine_additive(ipc_ctx *ctx, ipc_state *st, ipc_target target, ipc_info *info);
 
 /* Batches (beyond the paper, which compresses one field at a time): n fields
