@@ -42,15 +42,15 @@ def parse_args():
                     help="edge of the cubic sub-block the oracle compresses and retrieves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", choices=["c2", "c3-batch", "c4-batch", "c5-serve", "entropy",
+    ap.add_argument("--workload", choices=["field512", "climate-batch", "lognormal-batch", "serve", "entropy",
                                            "variants"],
-                    default="c2",
-                    help="c2: the headline line (one field); c3-batch: 20 (--fields) "
+                    default="field512",
+                    help="field512: the headline line (one field); climate-batch: 20 (--fields) "
                          "1800x3600 float32 climate fields, batched compress and batched "
                          "retrievals at 1, 2 and 4 bits per value, beside one field per call; "
-                         "c4-batch: --fields float64 "
+                         "lognormal-batch: --fields float64 "
                          "256x384x384 log-normal fields through the batched calls, beside "
-                         "the same fields one call at a time; c5-serve: a Poisson request "
+                         "the same fields one call at a time; serve: a Poisson request "
                          "mix over --fields resident fields through the serving loop, beside "
                          "the same trace served one request at a time; entropy: the entropy "
                          "stage on the 512^3 field (compression ratio, coder times) and on "
@@ -59,8 +59,8 @@ def parse_args():
                          "plane groups against per-pass groups, and its additive refinement "
                          "against the recompute form, on the 512^3 field")
     ap.add_argument("--requests", type=int, default=600)
-    ap.add_argument("--rate", type=float, default=2000.0, help="c5-serve arrivals per second")
-    ap.add_argument("--budget-gib", type=float, default=32.0, help="c5-serve device-memory budget")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
+    ap.add_argument("--budget-gib", type=float, default=32.0, help="serve: device-memory budget")
     ap.add_argument("--fields", type=int, default=8)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default column lengths (no ipc_autotune before timing)")
@@ -86,11 +86,11 @@ def main():
     import fieldgen
     import paper_2502_04093_amd as pkg
 
-    if args.workload == "c4-batch":
+    if args.workload == "lognormal-batch":
         return batch_main(args)
-    if args.workload == "c3-batch":
+    if args.workload == "climate-batch":
         return climate_batch_main(args)
-    if args.workload == "c5-serve":
+    if args.workload == "serve":
         return serve_main(args)
     if args.workload == "entropy":
         return entropy_main(args)
@@ -690,7 +690,7 @@ def serve_main(args):
     plain = {"requests_per_s": round(R / (T1 - T0), 2), "p50_ms": round(pct(plat, 0.5), 4),
              "p99_ms": round(pct(plat, 0.99), 4)}
     out = {
-        "metric": "serving requests/s and p50/p99 latency (C5-like mix)",
+        "metric": "serving requests/s and p50/p99 latency (resident-field request mix)",
         "value": served["requests_per_s"], "unit": "requests/s", "n_gpus": 1, "steps": R,
         "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
