@@ -77,7 +77,7 @@ def main():
     args = parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "independent fields would shard across GPUs with no exchange, see DESIGN.md",
+              "independent fields would shard across GPUs with no exchange",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
