@@ -76,7 +76,7 @@ def parse_args():
 def main():
     args = parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: measures one GPU (asked for --gpus {args.gpus}); "
               "independent fields would shard across GPUs with no exchange",
               file=sys.stderr)
         sys.exit(2)
