@@ -40,7 +40,7 @@ typedef enum {
   IPC_ECORRUPT = -3,     /* serialized stream fails validation */
   IPC_EHIP = -4,         /* HIP runtime error */
   IPC_ESTATE = -5,       /* object used with the wrong context or stream */
-  IPC_EUNSUPPORTED = -6  /* valid request outside what this build supports */
+  IPC_EUNSUPPORTED = -6  /* valid request outside what the library supports */
 } ipc_status;
 
 typedef enum { IPC_F32 = 0, IPC_F64 = 1 } ipc_dtype;
