@@ -98,6 +98,9 @@ static PlanResult plan_eb(const PlanTables &t, double E, const int *limit, bool 
     res.flags = IPC_FLAG_CLAMPED_TO_EB;
     return res;
   }
+  // E == eb: every discarded plane costs a positive term (at least T_s r), so
+  // the program can only keep every plane; that plan without running it
+  if (R == 0.0) return res;
   double r = rounding_step(t, t.maxabs + E);
   double u = R / G_UNITS;
   const int64_t NEG = std::numeric_limits<int64_t>::min() / 4;

@@ -84,8 +84,7 @@ def test_planner_matches_oracle():
     for buf in _streams():
         _, _, t = codec.open_stream(buf)
         scale = max(t.maxabs, 1e-12)
-        for rel in (1e-7, 1e-5, 1e-4, 1e-3, 1e-2, 0.1, 1.0, 10.0):
-            E = rel * scale
+        for E in [t.eb] + [rel * scale for rel in (1e-7, 1e-5, 1e-4, 1e-3, 1e-2, 0.1, 1.0, 10.0)]:
             plan, bound, flags, loaded, _ = _oracle_plan(buf, "eb", E)
             cplan, cb, cf, cl = pkg.plan_host(buf, eb=E)
             assert cplan[:t.n_passes] == plan
