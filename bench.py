@@ -165,6 +165,7 @@ def main():
     tc = tr = 0.0
     dom_c = []
     dom_r = []
+    step_c, step_r = [], []
     T0 = time.perf_counter()
     for _ in range(args.steps):
         t0 = time.perf_counter()
@@ -176,6 +177,8 @@ def main():
         t2 = time.perf_counter()
         tc += t1 - t0
         tr += t2 - t1
+        step_c.append((t1 - t0) * 1e3)
+        step_r.append((t2 - t1) * 1e3)
         st.free()
         s.free()
     torch.cuda.synchronize()
@@ -187,11 +190,13 @@ def main():
     # retrieval latency
     s = ctx.compress(x, eb, interp=args.interp)
     lat = []
+    plan_ms = []
     L = args.latency_calls
     for _ in range(L):
         t0 = time.perf_counter()
         st = s.retrieve(eb=eb)
         lat.append((time.perf_counter() - t0) * 1e3)
+        plan_ms.append(st.info.t_plan_ms)
         st.free()
     s.free()
     # quality of the full retrieval (outside the timed region)
@@ -236,7 +241,12 @@ def main():
                    "n_passes": P},
         "compress_GBps": round(gb / (tc / args.steps), 3),
         "retrieve_GBps": round(gb / (tr / args.steps), 3),
-        "retrieve_latency_ms": {"p50": p50 and round(p50, 4), "p99": p99 and round(p99, 4), "calls": L},
+        "retrieve_latency_ms": {"p50": p50 and round(p50, 4), "p99": p99 and round(p99, 4), "calls": L,
+                                "planner_median": round(sorted(plan_ms)[len(plan_ms) // 2], 4) if plan_ms else None},
+        "step_ms": {"compress_median": round(sorted(step_c)[len(step_c) // 2], 4),
+                    "compress_min": round(min(step_c), 4),
+                    "retrieve_median": round(sorted(step_r)[len(step_r) // 2], 4),
+                    "retrieve_min": round(min(step_r), 4)},
         "quality": {"max_abs_err": max_err, "within_eb": max_err <= eb, "psnr_db": round(psnr, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
