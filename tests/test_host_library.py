@@ -205,3 +205,28 @@ def test_target_flags_validated():
         st = L.ipc_plan_host(buf, len(buf), pkg.ipc_target(kind, 1.0), None, out, pkg.IPC_MAX_PASSES,
                              None, None, None)
         assert st == -1
+
+
+def test_parser_survives_random_corruption():
+    """Random byte flips, truncations and extensions of raw and entropy-coded
+    streams: the host parser either rejects them (IPC_ECORRUPT) or plans on a
+    consistent stream; it never crashes."""
+    _lib_or_skip()
+    rng = np.random.default_rng(123)
+    bases = [_streams()[0], _streams()[4], _streams()[1], _streams()[5]]
+    for base in bases:
+        for trial in range(150):
+            b = bytearray(base)
+            kind = trial % 3
+            if kind == 0:
+                for _ in range(int(rng.integers(1, 6))):
+                    i = int(rng.integers(0, len(b)))
+                    b[i] = int(rng.integers(0, 256))
+            elif kind == 1:
+                b = b[:int(rng.integers(0, len(b)))]
+            else:
+                b = b + bytes(rng.integers(0, 256, int(rng.integers(1, 64)), dtype=np.uint8))
+            try:
+                pkg.plan_host(bytes(b), bitrate=2.0)
+            except pkg.IpcError as e:
+                assert e.status in (-1, -3, -6)
