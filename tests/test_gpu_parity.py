@@ -206,6 +206,10 @@ def test_errors_are_reported(ctx):
     with pytest.raises(pkg.IpcError):
         s.retrieve_plan([0] * (s.n_passes + 1))
     s.free()
+    # an empty field is refused before anything runs on the device
+    with pytest.raises(pkg.IpcError) as ei:
+        ctx.compress(_dev(np.zeros((0, 4), dtype=np.float32)), 1e-3)
+    assert ei.value.status == -1
 
 
 def test_deterministic(ctx):
