@@ -29,7 +29,9 @@ def build(verbose: bool = False) -> str:
            "-ffp-contract=off", "-fno-fast-math",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wall", "-Wno-unused-function",
-           "-o", out_tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+           "-o", out_tmp] + [os.path.join(CSRC, s) for s in SOURCES] + [
+           # ROCTx ranges around the library calls (rocprofv3 --marker-trace)
+           "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

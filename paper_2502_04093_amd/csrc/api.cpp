@@ -17,6 +17,8 @@
 #include <thread>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "ipc_internal.h"
 #include "kernels.h"
 
@@ -112,6 +114,15 @@ namespace {
 
 struct Fail {
   ipc_status st;
+};
+
+// A named range on the ROCTx marker stream for the span of a library call
+// (seen by rocprofv3 --marker-trace; nearly free when no tool listens)
+struct TraceRange {
+  explicit TraceRange(const char *name) { roctxRangePush(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange &) = delete;
+  TraceRange &operator=(const TraceRange &) = delete;
 };
 
 // fn(i) for i in [0, n) on up to 16 host threads (planning several requests:
@@ -1272,6 +1283,7 @@ void ipc_ctx_destroy(ipc_ctx *ctx) {
 
 ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dims, int ndim,
                         int dtype, double abs_eb, const ipc_options *opts, ipc_stream **out) {
+  TraceRange trace_range("ipc_compress");
   if (!out) return IPC_EINVAL;
   *out = nullptr;
   if (!ctx) return IPC_EINVAL;
@@ -1457,6 +1469,7 @@ ipc_status ipc_stream_size(const ipc_stream *s, uint64_t *bytes) {
 }
 
 ipc_status ipc_stream_to_host(ipc_ctx *ctx, const ipc_stream *sc, void *dst, uint64_t capacity) {
+  TraceRange trace_range("ipc_stream_to_host");
   if (!ctx || !sc || !dst) return IPC_EINVAL;
   if (sc->ctx != ctx) {
     set_err(ctx, "stream belongs to another context");
@@ -1494,6 +1507,7 @@ ipc_status ipc_stream_to_host(ipc_ctx *ctx, const ipc_stream *sc, void *dst, uin
 }
 
 ipc_status ipc_stream_entropy_code(ipc_ctx *ctx, ipc_stream *s) {
+  TraceRange trace_range("ipc_stream_entropy_code");
   if (!ctx || !s) return IPC_EINVAL;
   if (s->ctx != ctx) {
     set_err(ctx, "stream belongs to another context");
@@ -1556,6 +1570,7 @@ ipc_status ipc_stream_coding(const ipc_stream *s, int *coding) {
 }
 
 ipc_status ipc_stream_from_host(ipc_ctx *ctx, const void *src, uint64_t bytes, ipc_stream **out) {
+  TraceRange trace_range("ipc_stream_from_host");
   if (!out) return IPC_EINVAL;
   *out = nullptr;
   if (!ctx || !src) return IPC_EINVAL;
@@ -1682,6 +1697,7 @@ static bool valid_target(ipc_target t) {
 
 ipc_status ipc_retrieve(ipc_ctx *ctx, const ipc_stream *s, ipc_target target, ipc_state **out,
                         ipc_info *info) {
+  TraceRange trace_range("ipc_retrieve");
   if (!out) return IPC_EINVAL;
   *out = nullptr;
   if (!ctx || !s) return IPC_EINVAL;
@@ -1701,6 +1717,7 @@ ipc_status ipc_retrieve(ipc_ctx *ctx, const ipc_stream *s, ipc_target target, ip
 
 ipc_status ipc_retrieve_plan(ipc_ctx *ctx, const ipc_stream *s, const uint8_t *plan,
                              uint32_t n_passes, ipc_state **out, ipc_info *info) {
+  TraceRange trace_range("ipc_retrieve_plan");
   if (!out) return IPC_EINVAL;
   *out = nullptr;
   if (!ctx || !s || !plan) return IPC_EINVAL;
@@ -1775,6 +1792,7 @@ ipc_status ipc_stream_passes(const ipc_stream *s, uint32_t *n_passes) {
 }
 
 ipc_status ipc_refine(ipc_ctx *ctx, ipc_state *st, ipc_target target, ipc_info *info) {
+  TraceRange trace_range("ipc_refine");
   if (!ctx || !st) return IPC_EINVAL;
   if (st->ctx != ctx) {
     set_err(ctx, "state belongs to another context");
@@ -1819,6 +1837,7 @@ ipc_status ipc_refine(ipc_ctx *ctx, ipc_state *st, ipc_target target, ipc_info *
 }
 
 ipc_status ipc_refine_additive(ipc_ctx *ctx, ipc_state *st, ipc_target target, ipc_info *info) {
+  TraceRange trace_range("ipc_refine_additive");
   if (!ctx || !st) return IPC_EINVAL;
   if (st->ctx != ctx) {
     set_err(ctx, "state belongs to another context");
@@ -1915,6 +1934,7 @@ ipc_status ipc_plan_host(const void *stream_bytes, uint64_t nbytes, ipc_target t
 ipc_status ipc_compress_batch(ipc_ctx *ctx, uint32_t n, const void *const *fields_dev,
                               const uint64_t *dims, int ndim, int dtype, const double *abs_eb,
                               const ipc_options *opts, ipc_stream **out) {
+  TraceRange trace_range("ipc_compress_batch");
   if (!out) return IPC_EINVAL;
   for (uint32_t i = 0; i < n; ++i) out[i] = nullptr;
   if (!ctx || n == 0 || !fields_dev || !dims || !abs_eb) return IPC_EINVAL;
@@ -2000,6 +2020,7 @@ ipc_status ipc_compress_batch(ipc_ctx *ctx, uint32_t n, const void *const *field
 
 ipc_status ipc_retrieve_batch(ipc_ctx *ctx, uint32_t n, const ipc_stream *const *streams,
                               const ipc_target *targets, ipc_state **out, ipc_info *info) {
+  TraceRange trace_range("ipc_retrieve_batch");
   if (!out) return IPC_EINVAL;
   for (uint32_t i = 0; i < n; ++i) out[i] = nullptr;
   if (!ctx || n == 0 || !streams || !targets) return IPC_EINVAL;
@@ -2194,6 +2215,7 @@ ipc_status ipc_autotune_clear(ipc_ctx *ctx) {
 }
 
 ipc_status ipc_serve_batch(ipc_ctx *ctx, uint32_t n, ipc_request *req) {
+  TraceRange trace_range("ipc_serve_batch");
   if (!ctx || (n && !req)) return IPC_EINVAL;
   // plan every request; refinements that need nothing finish here
   struct Job {
