@@ -25,6 +25,9 @@ What it computes (IPComp, arXiv 2502.04093):
 * ``codec``     -- compress, retrieve (Alg. 1) and refine (Alg. 2, recompute
   form).
 * ``brute``     -- scalar per-point versions for tiny grids.
+* ``pointwise`` -- single outputs of full-size fields through their dependency
+  cones (memoised recursion), for sampled checks at sizes the codec would take
+  minutes on.
 
 Arithmetic runs in the field's own dtype (float32 or float64) with one IEEE
 operation per step and no fused multiply-add, because the GPU path must agree
@@ -36,4 +39,4 @@ Parity pins (what ties this oracle to something other than itself) live in
 own numbers are unpinned (the paper's zstd stage and datasets are absent).
 """
 
-from . import schedule, predict, coding, entropy, stream, planner, codec  # noqa: F401
+from . import schedule, predict, coding, entropy, stream, planner, codec, pointwise  # noqa: F401

@@ -3,10 +3,11 @@ columns (several chunk rows per workgroup, the coarse-plane ring, prefetch of
 the next step), and on streams the oracle wrote (packed payload placement)
 (gpu).
 
-Byte-exact against the oracle up to 33.5 M points; the 512^3 benchmark field
-itself is checked through properties that hold at any size (the oracle needs
-minutes there): the error bound of every retrieval, refinement equal to a fresh
-retrieval, determinism.
+Byte-exact against the oracle up to 33.5 M points.  The 512^3 benchmark field
+and the full-shape float64 batch are checked on sampled outputs, each
+evaluated by the pointwise oracle through its dependency cone, and through
+properties that hold at any size: the error bound of every retrieval,
+refinement equal to a fresh retrieval, determinism.
 """
 
 import numpy as np
@@ -180,4 +181,86 @@ def test_lognormal_f64_full_shape_batched(ctx):
         assert err <= e
         st.free()
         one.free()
+        b.free()
+
+
+def _samples(shape, n, seed):
+    """n random points plus the corners and points next to the upper faces
+    (boundary stencil forms), as an int64 array [m, 3]."""
+    rng = np.random.default_rng(seed)
+    pts = [tuple(int(rng.integers(0, d)) for d in shape) for _ in range(n)]
+    hi = [d - 1 for d in shape]
+    pts += [(0, 0, 0), tuple(hi), (hi[0], 0, hi[2]), (1, 1, 1), (hi[0] - 1, hi[1] - 2, hi[2] - 3),
+            (hi[0] // 2, hi[1], hi[2] // 2), (2, hi[1] - 1, 5)]
+    return np.array(pts, dtype=np.int64)
+
+
+def _at(t, pts):
+    idx = torch.from_numpy(pts).to(t.device)
+    return t[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+
+
+def _check_samples(st, cone, pts, plan, what):
+    got = _at(st.tensor(), pts)
+    ref = np.array([cone.retrieved(tuple(p), plan) for p in pts], dtype=got.dtype)
+    bad = [i for i in range(len(pts)) if got[i].tobytes() != ref[i].tobytes()]
+    assert not bad, (what, pts[bad[:5]].tolist(), got[bad[:5]], ref[bad[:5]])
+
+
+def test_benchmark_field_sampled_parity(ctx):
+    """The 512^3 float32 benchmark field at 1e-4 * range in the benchmark's
+    launch configuration (column lengths autotuned as the benchmark does):
+    sampled outputs of the full retrieval, of bitrate and error-bound
+    retrievals and of a refinement, bit-exact against the pointwise oracle
+    (each sample evaluated through its dependency cone)."""
+    from oracle.pointwise import Cone
+
+    x = fieldgen.grf_torch((512, 512, 512), -5.0 / 6.0, 0)
+    r = float(x.max().double() - x.min().double())
+    eb = 1e-4 * r
+    ctx.autotune(x, eb)
+    try:
+        s = ctx.compress(x, eb)
+        cone = Cone(x.cpu().numpy(), eb)
+        pts = _samples(x.shape, 160, 1)
+        print(f"sampled parity 512^3 f32: {len(pts)} points", flush=True)
+        st = s.retrieve(eb=eb)
+        assert all(b == 0 for b in st.plan)
+        got = _at(st.tensor(), pts)
+        ref = np.array([cone.xhat(tuple(p)) for p in pts], dtype=np.float32)
+        assert got.tobytes() == ref.tobytes()
+        st.free()
+        for kind, v in (("bitrate", 1.0), ("bitrate", 4.0), ("eb", 1e-2 * r)):
+            st = s.retrieve(**{kind: v})
+            _check_samples(st, cone, pts, st.plan, (kind, v))
+            st.free()
+        st = s.retrieve(eb=1e-2 * r)
+        st.refine(eb=1e-3 * r)
+        _check_samples(st, cone, pts, st.plan, "refine")
+        st.free()
+        print(f"cone points evaluated: {cone.cone_size()}", flush=True)
+        s.free()
+    finally:
+        ctx.autotune_clear()
+
+
+def test_lognormal_f64_full_shape_sampled_parity(ctx):
+    """The float64 log-normal fields at their full 256 x 384 x 384 shape,
+    compressed and retrieved as one batch: sampled outputs bit-exact against
+    the pointwise oracle."""
+    from oracle.pointwise import Cone
+
+    xs = [fieldgen.lognormal_torch((256, 384, 384), seed=i) for i in range(2)]
+    ebs = [1e-5 * float(x.max() - x.min()) for x in xs]
+    bs = ctx.compress_batch(xs, ebs)
+    sts = ctx.retrieve_batch(bs, bitrate=2.0)
+    for k, (x, e, b, st) in enumerate(zip(xs, ebs, bs, sts)):
+        cone = Cone(x.cpu().numpy(), e)
+        pts = _samples(x.shape, 96, 10 + k)
+        print(f"sampled parity 256x384x384 f64 field {k}: {len(pts)} points", flush=True)
+        _check_samples(st, cone, pts, st.plan, ("batch bitrate", k))
+        st.free()
+        full = b.retrieve(eb=e)
+        _check_samples(full, cone, pts, full.plan, ("full", k))
+        full.free()
         b.free()
