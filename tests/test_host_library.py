@@ -230,3 +230,24 @@ def test_parser_survives_random_corruption():
                 pkg.plan_host(bytes(b), bitrate=2.0)
             except pkg.IpcError as e:
                 assert e.status in (-1, -3, -6)
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """With no built library the binding raises on first use; there is no
+    fallback path (run in a child process: this one keeps its loaded library)."""
+    import subprocess
+    import sys
+    code = ("import paper_2502_04093_amd as p\n"
+            "p.LIB_PATH = p.LIB_PATH + '.absent'\n"
+            "p._lib = None\n"
+            "try:\n"
+            "    p.lib()\n"
+            "except ImportError as e:\n"
+            "    print('raised:', e)\n"
+            "else:\n"
+            "    raise SystemExit('no error')\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "not built" in r.stdout
