@@ -62,6 +62,8 @@ def parse_args():
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
     ap.add_argument("--budget-gib", type=float, default=32.0, help="serve: device-memory budget")
     ap.add_argument("--fields", type=int, default=8)
+    ap.add_argument("--batch-graphs", action="store_true",
+                    help="serve: batched retrievals as queue launches replayed from HIP graphs")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default column lengths (no ipc_autotune before timing)")
     ap.add_argument("--column-rows", default=None,
@@ -366,6 +368,19 @@ def batch_main(args):
 
     tb = timed(batched)
     tp = timed(plain)
+    # the batched retrieval alone, direct level launches and graph replays
+    ss = ctx.compress_batch(xs, ebs)
+
+    def retrieve_only():
+        for st in ctx.retrieve_batch(ss, eb=ebs):
+            st.free()
+
+    tr_direct = timed(retrieve_only)
+    ctx.set_batch_graphs(True)
+    tr_graph = timed(retrieve_only)
+    ctx.set_batch_graphs(False)
+    for s in ss:
+        s.free()
     gb = n * xs[0].numel() * 8 / 1e9
     out = {
         "metric": "batched compress & retrieve GB/s (fp64 in), 8 fields, eb=1e-5*range",
@@ -376,6 +391,9 @@ def batch_main(args):
                                "eb=1e-5*range each, batched compress + full retrieve"},
         "plain_GBps": round(gb / tp, 3), "plain_ms_per_step": round(tp * 1e3, 4),
         "batch_speedup": round(tp / tb, 4),
+        "batched_retrieve_ms": {"direct_launches": round(tr_direct * 1e3, 4),
+                                "graph_replay": round(tr_graph * 1e3, 4),
+                                "graphs": ctx.graph_stats()},
     }
     print(json.dumps(out), flush=True)
     ctx.close()
@@ -631,6 +649,7 @@ def serve_main(args):
         return v[min(len(v) - 1, int(np.ceil(q * len(v))) - 1)]
 
     # served
+    ctx.set_batch_graphs(args.batch_graphs)
     srv = pkg.Server(ctx, budget_bytes=int(args.budget_gib * (1 << 30)), max_batch=64)
     tickets = [None] * R
     states = [None] * R
@@ -673,7 +692,9 @@ def serve_main(args):
     srv.close()
     served = {"requests_per_s": round(R / (T1 - T0), 2), "p50_ms": round(pct(lat, 0.5), 4),
               "p99_ms": round(pct(lat, 0.99), 4), "batches": stats["batches"],
-              "peak_budget_GiB": round(stats["peak"] / (1 << 30), 3)}
+              "peak_budget_GiB": round(stats["peak"] / (1 << 30), 3),
+              "batch_graphs": bool(args.batch_graphs), "graphs": ctx.graph_stats()}
+    ctx.set_batch_graphs(False)
     # plain: one request at a time, in arrival order
     pstates = [None] * R
     plat = []
@@ -806,7 +827,29 @@ def cpu_baseline(x, eb, args, ctx):
               "stream_sha256": hashlib.sha256(got).hexdigest()[:16],
               "stream_equal_oracle": got == buf,
               "retrieval_equal_oracle": fld == ref.field.tobytes()}
+    if x.dim() == 3:
+        parity["full_size_sampled"] = sampled_parity(x, eb, args, ctx)
     return base, parity
+
+
+def sampled_parity(x, eb, args, ctx, n=64):
+    """The whole field in the timed launch configuration: n random outputs of
+    its full retrieval against the pointwise oracle (each evaluated through
+    its dependency cone)."""
+    import numpy as np
+    import torch
+    from oracle.pointwise import Cone
+    rng = np.random.default_rng(12345)
+    pts = np.stack([rng.integers(0, d, size=n) for d in x.shape], axis=1)
+    cone = Cone(x.cpu().numpy(), eb, 1 if args.interp == "cubic" else 0)
+    s = ctx.compress(x, eb, interp=args.interp)
+    st = s.retrieve(eb=eb)
+    idx = torch.from_numpy(pts).to(x.device)
+    got = st.tensor()[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+    st.free()
+    s.free()
+    ref = np.array([cone.xhat(tuple(int(v) for v in p)) for p in pts], dtype=got.dtype)
+    return {"points": n, "cone_points": cone.cone_size(), "equal_oracle": got.tobytes() == ref.tobytes()}
 
 
 if __name__ == "__main__":

@@ -304,6 +304,23 @@ ipc_status ipc_plan_host(const void *stream_bytes, uint64_t nbytes, ipc_target t
 ipc_status ipc_ctx_set_profiling(ipc_ctx *ctx, int on, int only_pass);
 ipc_status ipc_ctx_pass_times(const ipc_ctx *ctx, float *ms, uint32_t capacity, uint32_t *n_out);
 
+/* Batched retrievals as graph replays (the batching of many uneven fields by
+ * one persistent launch per level that the problem statement asks for).
+ * When on, ipc_retrieve_batch and the retrievals and refinements of
+ * ipc_serve_batch over fused 3-D streams (3-D fields with the default chunk
+ * shape; at most 2048 of them and 16384 level work lists per call) run as
+ * queue launches: the per-field head jobs, then for each level one
+ * persistent grid whose workgroups claim column segments of every field at
+ * that level from a device counter.  Everything that varies from batch to
+ * batch is uploaded as one table, so the launch sequence is captured once
+ * per launch shape (dtype, interpolation, number of levels, grid class of
+ * each level) into a HIP graph and replayed after.  Results are identical to
+ * the direct launches (the same kernels' bodies).  Graphs, the device table
+ * (about 10 MB) and its pinned staging copy live until ipc_ctx_destroy.
+ * Off by default.  ipc_ctx_graph_stats counts captured graphs and replays. */
+ipc_status ipc_ctx_set_batch_graphs(ipc_ctx *ctx, int on);
+ipc_status ipc_ctx_graph_stats(const ipc_ctx *ctx, uint64_t *captured, uint64_t *replays);
+
 const char *ipc_status_string(ipc_status st);
 const char *ipc_last_error(const ipc_ctx *ctx);
 

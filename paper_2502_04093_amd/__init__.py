@@ -110,6 +110,8 @@ SIGNATURES = {
     "ipc_server_destroy": (None, [c_void_p]),
     "ipc_ctx_set_profiling": (c_int, [c_void_p, c_int, c_int]),
     "ipc_ctx_pass_times": (c_int, [c_void_p, P(c_float), c_uint32, P(c_uint32)]),
+    "ipc_ctx_set_batch_graphs": (c_int, [c_void_p, c_int]),
+    "ipc_ctx_graph_stats": (c_int, [c_void_p, P(c_uint64), P(c_uint64)]),
     "ipc_status_string": (ctypes.c_char_p, [c_int]),
     "ipc_last_error": (ctypes.c_char_p, [c_void_p]),
 }
@@ -209,6 +211,17 @@ class Context:
 
     def set_profiling(self, on: bool = True, only_pass: int = -1):
         _check(lib().ipc_ctx_set_profiling(self._p, int(bool(on)), int(only_pass)), self._p)
+
+    def set_batch_graphs(self, on: bool = True):
+        """Batched retrievals as queue launches replayed from captured HIP
+        graphs (see ipc_ctx_set_batch_graphs)."""
+        _check(lib().ipc_ctx_set_batch_graphs(self._p, int(bool(on))), self._p)
+
+    def graph_stats(self):
+        """(graphs captured, graph replays) so far."""
+        c, r = c_uint64(), c_uint64()
+        _check(lib().ipc_ctx_graph_stats(self._p, ctypes.byref(c), ctypes.byref(r)), self._p)
+        return int(c.value), int(r.value)
 
     def pass_times(self):
         """Per-pass kernel milliseconds of the last call (profiling on)."""

@@ -78,6 +78,13 @@ struct ipc_ctx {
   std::vector<float> pass_ms;     // per pass (0 = not run)
   size_t prof_np = 0;
   int prof_only = -1;
+  // batched retrievals as queue launches replayed from captured HIP graphs
+  bool batch_graphs = false;
+  std::map<std::vector<int>, hipGraphExec_t> graphs;  // by launch shape
+  void *ws_q = nullptr;       // claim counters, then the queue table (fixed address)
+  size_t ws_q_bytes = 0;
+  void *host_q = nullptr;     // pinned staging of the queue table
+  uint64_t graphs_captured = 0, graph_replays = 0;
 };
 
 struct DevBuf {
@@ -942,6 +949,180 @@ void retrieve_batch_fused(ipc_ctx *ctx, const std::vector<const ipc_stream *> &s
   for (DevBuf &b : g) dev_free(ctx, b);
 }
 
+// ------------------------------------------------------- graph-replayed batches
+//
+// A batched retrieval of fused 3-D streams as queue launches: the head jobs
+// (anchors, or coarse grids gathered for refinements) and one persistent
+// launch per level slot, reading everything batch-specific from a table in
+// device memory.  The launch sequence then depends only on the launch shape
+// (dtype, interpolation, number of level slots and the grid class of each),
+// so it is captured once into a HIP graph and replayed for every later batch
+// of the same shape: a replay is one table upload and one graph launch.
+
+constexpr size_t Q_HEADS = 2048;    // fields per queue batch
+constexpr size_t Q_ENTRIES = 16384; // level work-list entries per queue batch
+constexpr size_t Q_CLAIMS = 256;    // bytes of claim counters before the table
+constexpr size_t Q_GRAPHS = 64;     // cached graphs (the cache is cleared beyond)
+
+size_t queue_table_bytes() {
+  const size_t h = std::max(sizeof(HeadR<float>), sizeof(HeadR<double>));
+  const size_t e = std::max(sizeof(BatchR<float>), sizeof(BatchR<double>));
+  // + 256: the entries start at the next 256-byte boundary after the heads
+  return ((sizeof(QueueTable) + 255) & ~size_t(255)) + Q_HEADS * h + 256 + Q_ENTRIES * e;
+}
+
+// persistent grid of a level slot: a class of its item count
+uint32_t queue_grid(const ipc_ctx *ctx, uint32_t items, size_t isz) {
+  const uint32_t full = uint32_t(ctx->n_cu) * (isz == 4 ? 5u : 4u);
+  if (items <= 16) return 16;
+  if (items <= 128) return 128;
+  return full;
+}
+
+bool queue_fits(const std::vector<const ipc_stream *> &ss) {
+  if (ss.size() > Q_HEADS) return false;
+  size_t ent = 0;
+  int Kmax = 0;
+  for (const ipc_stream *s : ss) {
+    ent += size_t(s->meta.sched.K);
+    Kmax = std::max(Kmax, s->meta.sched.K);
+  }
+  return ent <= Q_ENTRIES && Kmax <= QUEUE_LEVELS;
+}
+
+template <typename T>
+void retrieve_batch_queue(ipc_ctx *ctx, const std::vector<const ipc_stream *> &ss,
+                          const std::vector<std::vector<int>> &plans, const std::vector<void *> &out,
+                          const std::vector<int> &l_start) {
+  const int n = int(ss.size());
+  const int dtype = ss[0]->meta.dtype, interp = ss[0]->meta.interp;
+  const size_t isz = sizeof(T);
+  if (!ctx->ws_q) {
+    ctx->ws_q_bytes = Q_CLAIMS + queue_table_bytes();
+    hip_check(ctx, hipMalloc(&ctx->ws_q, ctx->ws_q_bytes), "queue table allocation");
+    hip_check(ctx, hipHostMalloc(&ctx->host_q, queue_table_bytes(), hipHostMallocDefault),
+              "pinned allocation");
+  }
+  uint32_t *claims = static_cast<uint32_t *>(ctx->ws_q);
+  QueueTable *tab_dev = reinterpret_cast<QueueTable *>(static_cast<char *>(ctx->ws_q) + Q_CLAIMS);
+  char *host = static_cast<char *>(ctx->host_q);
+  QueueTable &tab = *reinterpret_cast<QueueTable *>(host);
+  std::memset(&tab, 0, sizeof(tab));
+  tab.n_heads = uint32_t(n);
+  tab.heads_off = uint32_t((sizeof(QueueTable) + 255) & ~size_t(255));
+  HeadR<T> *heads = reinterpret_cast<HeadR<T> *>(host + tab.heads_off);
+  tab.ent_off = uint32_t(tab.heads_off + ((size_t(n) * sizeof(HeadR<T>) + 255) & ~size_t(255)));
+  BatchR<T> *ent = reinterpret_cast<BatchR<T> *>(host + tab.ent_off);
+
+  std::vector<DevBuf> g(2 * n);
+  // the coarse grids go back to the cache once the stream has drained (also
+  // when a step below fails after work was queued)
+  struct Release {
+    ipc_ctx *ctx;
+    std::vector<DevBuf> &g;
+    ~Release() {
+      (void)hipStreamSynchronize(ctx->stream);
+      for (DevBuf &b : g) dev_free(ctx, b);
+    }
+  } release{ctx, g};
+  int Kmax = 0;
+  for (int i = 0; i < n; ++i) {
+    const ipc_stream *s = ss[i];
+    const Schedule &sc = s->meta.sched;
+    Kmax = std::max(Kmax, sc.K);
+    size_t need[2] = {8, 8};
+    for (int j = 1; j <= sc.K; ++j)
+      need[j & 1] = std::max(need[j & 1], size_t(coarse_points(sc, j)) * isz);
+    g[2 * i] = dev_alloc(ctx, need[0]);
+    g[2 * i + 1] = dev_alloc(ctx, need[1]);
+    HeadR<T> &h = heads[i];
+    std::memset(&h, 0, sizeof(h));
+    h.in = retrieve_in(ctx, s);
+    h.two_eb = T(2.0 * s->meta.eb);
+    const int ls = l_start[i];
+    h.g = static_cast<T *>(g[2 * i + (ls & 1)].p);
+    if (ls >= sc.K) {
+      h.mode = 0;
+      h.A = anchor3_args(sc);
+    } else {
+      h.mode = 1;
+      h.field = static_cast<const T *>(out[i]);
+      for (int j = 0; j < 3; ++j) {
+        h.fd[j] = sc.dims3[j];
+        h.gd[j] = ((sc.dims3[j] - 1) >> ls) + 1;
+      }
+      h.step = int64_t(1) << ls;
+    }
+  }
+  std::vector<int> key = {dtype, interp, Kmax};
+  size_t m = 0;
+  for (int slot = 0; slot < Kmax; ++slot) {
+    const int l = Kmax - slot;
+    QueueLevel &q = tab.lev[slot];
+    q.off = uint32_t(m);
+    for (int i = 0; i < n; ++i) {
+      if (l > l_start[i]) continue;
+      Level3Args La = level_args(ctx, ss[i]->meta, l, false);
+      BatchR<T> &e = ent[m++];
+      std::memset(&e, 0, sizeof(e));
+      e.L = La;
+      e.gin = static_cast<const T *>(g[2 * i + (l & 1)].p);
+      e.gout = l > 1 ? static_cast<T *>(g[2 * i + ((l - 1) & 1)].p) : static_cast<T *>(out[i]);
+      e.in = heads[i].in;
+      for (int p = 0; p < 3; ++p) e.disc[p] = plans[i][La.pass_index[p]];
+      e.two_eb = heads[i].two_eb;
+      e.item0 = q.items;
+      ++q.nf;
+      q.items += uint32_t(level3_wgs(La));
+    }
+    key.push_back(int(queue_grid(ctx, q.items, isz)));
+  }
+  const size_t bytes = tab.ent_off + m * sizeof(BatchR<T>);
+  hip_check(ctx, hipMemcpyAsync(tab_dev, host, bytes, hipMemcpyHostToDevice, ctx->stream), "upload");
+
+  auto it = ctx->graphs.find(key);
+  if (it == ctx->graphs.end()) {
+    if (ctx->graphs.size() >= Q_GRAPHS) {
+      for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+      ctx->graphs.clear();
+    }
+    hip_check(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipError_t e = launch_queue_reset(claims, ctx->stream);
+    if (e == hipSuccess) e = launch_heads_retrieve(dtype, tab_dev, ctx->stream);
+    for (int slot = 0; slot < Kmax && e == hipSuccess; ++slot)
+      e = launch_level3_retrieve_queue(dtype, interp, tab_dev, slot, claims, uint32_t(key[3 + slot]),
+                                       ctx->stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->stream, &graph);
+    if ((e != hipSuccess || ec != hipSuccess) && graph) (void)hipGraphDestroy(graph);
+    hip_check(ctx, e, "queue launch capture");
+    hip_check(ctx, ec, "end capture");
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    hip_check(ctx, ei, "graph instantiate");
+    it = ctx->graphs.emplace(key, exec).first;
+    ++ctx->graphs_captured;
+  }
+  hip_check(ctx, hipGraphLaunch(it->second, ctx->stream), "graph launch");
+  ++ctx->graph_replays;
+  // the coarse grids and the staged table are reused by the next call
+  hip_check(ctx, hipStreamSynchronize(ctx->stream), "retrieve");
+}
+
+// batched retrieval of fused 3-D streams: queue launches from a captured
+// graph when the context asks for them and the batch fits the table, else one
+// direct launch per level
+template <typename T>
+void retrieve_batch_levels(ipc_ctx *ctx, const std::vector<const ipc_stream *> &ss,
+                           const std::vector<std::vector<int>> &plans, const std::vector<void *> &out,
+                           const std::vector<int> &l_start) {
+  if (ctx->batch_graphs && queue_fits(ss))
+    retrieve_batch_queue<T>(ctx, ss, plans, out, l_start);
+  else
+    retrieve_batch_fused<T>(ctx, ss, plans, out, l_start);
+}
+
 // Compression of n fields on the one-pass-per-launch path (2-D, 1-D, other
 // chunk shapes) with one launch per pass index over all of them: step i
 // holds pass i of every field that has one.  Each field keeps its own
@@ -1194,6 +1375,19 @@ ipc_status ipc_ctx_set_profiling(ipc_ctx *ctx, int on, int only_pass) {
   return IPC_OK;
 }
 
+ipc_status ipc_ctx_set_batch_graphs(ipc_ctx *ctx, int on) {
+  if (!ctx) return IPC_EINVAL;
+  ctx->batch_graphs = on != 0;
+  return IPC_OK;
+}
+
+ipc_status ipc_ctx_graph_stats(const ipc_ctx *ctx, uint64_t *captured, uint64_t *replays) {
+  if (!ctx || !captured || !replays) return IPC_EINVAL;
+  *captured = ctx->graphs_captured;
+  *replays = ctx->graph_replays;
+  return IPC_OK;
+}
+
 ipc_status ipc_ctx_pass_times(const ipc_ctx *ctx, float *ms, uint32_t capacity, uint32_t *n_out) {
   if (!ctx || !n_out) return IPC_EINVAL;
   *n_out = uint32_t(ctx->pass_ms.size());
@@ -1273,6 +1467,10 @@ void ipc_ctx_destroy(ipc_ctx *ctx) {
   for (int i = 0; i < 2; ++i)
     if (ctx->ws_g[i]) (void)hipFree(ctx->ws_g[i]);
   if (ctx->ws_args) (void)hipFree(ctx->ws_args);
+  for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+  ctx->graphs.clear();
+  if (ctx->ws_q) (void)hipFree(ctx->ws_q);
+  if (ctx->host_q) (void)hipHostFree(ctx->host_q);
   if (ctx->host_summary) (void)hipHostFree(ctx->host_summary);
   for (hipEvent_t e : ctx->pev) (void)hipEventDestroy(e);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -2085,9 +2283,9 @@ ipc_status ipc_retrieve_batch(ipc_ctx *ctx, uint32_t n, const ipc_stream *const 
       std::vector<int> ls(n);
       for (uint32_t i = 0; i < n; ++i) ls[i] = ss[i]->meta.sched.K;
       if (ss[0]->meta.dtype == IPC_F32)
-        retrieve_batch_fused<float>(ctx, ss, plans, fields, ls);
+        retrieve_batch_levels<float>(ctx, ss, plans, fields, ls);
       else
-        retrieve_batch_fused<double>(ctx, ss, plans, fields, ls);
+        retrieve_batch_levels<double>(ctx, ss, plans, fields, ls);
     } else {
       std::vector<int> start(n, 0);
       if (ss[0]->meta.dtype == IPC_F32)
@@ -2377,9 +2575,9 @@ ipc_status ipc_serve_batch(ipc_ctx *ctx, uint32_t n, ipc_request *req) {
     hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
     if (!ss.empty()) {
       if (ss[0]->meta.dtype == IPC_F32)
-        retrieve_batch_fused<float>(ctx, ss, plans, fields, ls);
+        retrieve_batch_levels<float>(ctx, ss, plans, fields, ls);
       else
-        retrieve_batch_fused<double>(ctx, ss, plans, fields, ls);
+        retrieve_batch_levels<double>(ctx, ss, plans, fields, ls);
     }
     if (!ps.empty()) {
       if (ps[0]->meta.dtype == IPC_F32)

@@ -124,6 +124,51 @@ hipError_t launch_level3_compress_batch(int dtype, int interp, const void *batch
 hipError_t launch_level3_retrieve_batch(int dtype, int interp, const void *batch_dev, int nf,
                                         uint32_t n_items, hipStream_t s);
 
+// Queue launches of a batched retrieval, replayable from one captured HIP
+// graph whatever the batch holds: everything that varies from batch to batch
+// sits in a device-resident table, and each level launch is a persistent grid
+// whose workgroups claim work items from a device counter until its work list
+// is exhausted.  The table (QueueTable, then the head jobs, then the level
+// work lists, at the byte offsets the table gives) is uploaded before the
+// graph runs.
+constexpr int QUEUE_LEVELS = 32;
+struct QueueLevel {
+  uint32_t off;    // first BatchR entry of the level's work list
+  uint32_t nf;     // its fields
+  uint32_t items;  // its work items (0: the slot is empty)
+  uint32_t pad;
+};
+struct QueueTable {
+  uint32_t n_heads;
+  uint32_t heads_off;  // byte offset of the HeadR array from the table
+  uint32_t ent_off;    // byte offset of the BatchR array from the table
+  uint32_t pad;
+  QueueLevel lev[QUEUE_LEVELS];
+};
+// The job that fills a field's first coarse grid before its level launches:
+// its anchors (mode 0) or, for a refinement, a strided gather of the
+// resident reconstruction (mode 1).
+template <typename T>
+struct HeadR {
+  Level3Args A;
+  RetrieveIn in;
+  T *g;
+  const T *field;
+  int64_t fd[3];
+  int64_t step;
+  int64_t gd[3];
+  T two_eb;
+  int32_t mode;
+};
+// claim counters (QUEUE_LEVELS words) set to zero
+hipError_t launch_queue_reset(uint32_t *claims, hipStream_t s);
+// every head job of the table (grid of QUEUE_HEAD_WGS workgroups)
+constexpr int QUEUE_HEAD_WGS = 256;
+hipError_t launch_heads_retrieve(int dtype, const QueueTable *tab, hipStream_t s);
+// level slot `slot` of the table: `grid` persistent workgroups
+hipError_t launch_level3_retrieve_queue(int dtype, int interp, const QueueTable *tab, int slot,
+                                        uint32_t *claims, uint32_t grid, hipStream_t s);
+
 hipError_t launch_level3_compress(int dtype, int interp, const Level3Args &L, const void *x,
                                   const void *gin, void *gout, double eb, const CompressOut &o,
                                   hipStream_t s);

@@ -1553,13 +1553,12 @@ __global__ void k_anchor3_compress(Level3Args L, const T *__restrict__ x, T *gou
   if (mb) atomicMax(o.maxabs_bits, mb);
 }
 
-// anchors of a fused retrieval
+// anchors of a fused retrieval: anchor `tid` of the anchor grid (the caller
+// keeps tid below its size)
 template <typename T>
-__global__ void k_anchor3_retrieve(Level3Args L, T *gout, RetrieveIn in, T two_eb) {
+__device__ __forceinline__ void anchor3_retrieve_one(const Level3Args &L, T *gout, const RetrieveIn &in,
+                                                     T two_eb, int tid) {
   using F = F3<T>;
-  const int tid = threadIdx.x;
-  const int n = L.L[0] * L.L[1] * L.L[2];
-  if (tid >= n) return;
   const uint32_t mask = in.masks[L.chunk_base[0]];
   const bool packed = in.chunk_off != nullptr;
   const uint64_t base = packed ? in.chunk_off[L.chunk_base[0]] : L.slot_base[0];
@@ -1580,6 +1579,12 @@ __global__ void k_anchor3_retrieve(Level3Args L, T *gout, RetrieveIn in, T two_e
 }
 
 template <typename T>
+__global__ void k_anchor3_retrieve(Level3Args L, T *gout, RetrieveIn in, T two_eb) {
+  const int tid = threadIdx.x;
+  if (tid < L.L[0] * L.L[1] * L.L[2]) anchor3_retrieve_one<T>(L, gout, in, two_eb, tid);
+}
+
+template <typename T>
 __global__ void k_gather_coarse(const T *__restrict__ field, int64_t fd1, int64_t fd2, int64_t s,
                                 T *g, int64_t g0, int64_t g1, int64_t g2) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1587,6 +1592,64 @@ __global__ void k_gather_coarse(const T *__restrict__ field, int64_t fd1, int64_
   if (i >= n) return;
   int64_t c2 = i % g2, r = i / g2, c1 = r % g1, c0 = r / g1;
   g[i] = field[((s * c0) * fd1 + s * c1) * fd2 + s * c2];
+}
+
+// ------------------------------------------------------------ queue launches
+
+__global__ void k_queue_reset(uint32_t *claims) {
+  if (threadIdx.x < QUEUE_LEVELS) claims[threadIdx.x] = 0u;
+}
+
+// Every head job of the table: the anchors of a field by workgroup
+// (field mod grid), a gather spread over the whole grid.
+template <typename T>
+__global__ __launch_bounds__(256) void k_heads_retrieve(const QueueTable *__restrict__ tab) {
+  const uint32_t n = tab->n_heads;
+  const HeadR<T> *h = reinterpret_cast<const HeadR<T> *>(reinterpret_cast<const char *>(tab) + tab->heads_off);
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (uint32_t f = 0; f < n; ++f) {
+    const HeadR<T> &hd = h[f];
+    if (hd.mode == 0) {
+      const int na = hd.A.L[0] * hd.A.L[1] * hd.A.L[2];
+      if (blockIdx.x == f % gridDim.x && int(threadIdx.x) < na)
+        anchor3_retrieve_one<T>(hd.A, hd.g, hd.in, hd.two_eb, int(threadIdx.x));
+    } else {
+      const int64_t g1 = hd.gd[1], g2 = hd.gd[2], total = hd.gd[0] * g1 * g2;
+      for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const int64_t c2 = i % g2, r = i / g2, c1 = r % g1, c0 = r / g1;
+        hd.g[i] = hd.field[((hd.step * c0) * hd.fd[1] + hd.step * c1) * hd.fd[2] + hd.step * c2];
+      }
+    }
+  }
+}
+
+// One level slot of a queue launch: a persistent grid whose workgroups take
+// work items (column segments of the slot's fields, in work-list order) from
+// the slot's claim counter until the list is exhausted.  Every workgroup
+// leaves once a claim passes the item count, so the grid always drains.
+template <typename T, int INTERP>
+__global__ __launch_bounds__(WG3, sizeof(T) == 4 ? 5 : 4) void k_level3_retrieve_queue(
+    const QueueTable *__restrict__ tab, int slot, uint32_t *claims) {
+  __shared__ Shared3<T> S;
+  __shared__ uint32_t s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(claims + slot, 1u);
+    __syncthreads();
+    const uint32_t it = s_item;
+    // every thread has read the claim before the next one overwrites it
+    __syncthreads();
+    // the slot's description is re-read per item rather than held across
+    // the body (it would take registers the body needs)
+    const QueueLevel &q = tab->lev[slot];
+    if (it >= q.items) break;
+    const BatchR<T> *bf =
+        reinterpret_cast<const BatchR<T> *>(reinterpret_cast<const char *>(tab) + tab->ent_off) + q.off;
+    const BatchR<T> &b = bf[item_field(bf, int(q.nf), it)];
+    int tx, ty, zs;
+    item_tile(b.L, it - b.item0, tx, ty, zs);
+    level3_retrieve_body<T, INTERP>(b.L, b.gin, b.gout, b.disc[0], b.disc[1], b.disc[2], b.in,
+                                    b.two_eb, tx, ty, zs, S);
+  }
 }
 
 // errq, max |x^| and plane sizes of a compression from the fused-level rows:
@@ -1778,6 +1841,37 @@ hipError_t launch_anchor3_retrieve(int dtype, const Level3Args &A, void *gout, c
   else
     hipLaunchKernelGGL(k_anchor3_retrieve<double>, dim3(1), dim3(64), 0, s, A, (double *)gout, in,
                        2.0 * eb);
+  return hipGetLastError();
+}
+
+hipError_t launch_queue_reset(uint32_t *claims, hipStream_t s) {
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, s, claims);
+  return hipGetLastError();
+}
+
+hipError_t launch_heads_retrieve(int dtype, const QueueTable *tab, hipStream_t s) {
+  if (dtype == IPC_F32)
+    hipLaunchKernelGGL(k_heads_retrieve<float>, dim3(QUEUE_HEAD_WGS), dim3(256), 0, s, tab);
+  else
+    hipLaunchKernelGGL(k_heads_retrieve<double>, dim3(QUEUE_HEAD_WGS), dim3(256), 0, s, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_level3_retrieve_queue(int dtype, int interp, const QueueTable *tab, int slot,
+                                        uint32_t *claims, uint32_t grid, hipStream_t s) {
+  if (grid == 0 || slot < 0 || slot >= QUEUE_LEVELS) return hipErrorInvalidValue;
+  const dim3 g(grid);
+  if (dtype == IPC_F32) {
+    if (interp == IPC_LINEAR)
+      hipLaunchKernelGGL((k_level3_retrieve_queue<float, IPC_LINEAR>), g, dim3(WG3), 0, s, tab, slot, claims);
+    else
+      hipLaunchKernelGGL((k_level3_retrieve_queue<float, IPC_CUBIC>), g, dim3(WG3), 0, s, tab, slot, claims);
+  } else {
+    if (interp == IPC_LINEAR)
+      hipLaunchKernelGGL((k_level3_retrieve_queue<double, IPC_LINEAR>), g, dim3(WG3), 0, s, tab, slot, claims);
+    else
+      hipLaunchKernelGGL((k_level3_retrieve_queue<double, IPC_CUBIC>), g, dim3(WG3), 0, s, tab, slot, claims);
+  }
   return hipGetLastError();
 }
 

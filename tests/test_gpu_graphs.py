@@ -1,0 +1,119 @@
+"""Batched retrievals as queue launches replayed from captured HIP graphs
+(gpu).  Every result must equal, byte for byte, the same retrieval made by the
+direct launches (which the other GPU tests tie to the oracle); a graph is
+captured once per launch shape and replayed for later batches of that shape,
+with other work and synchronizations between the replays, and every replay is
+checked."""
+
+import numpy as np
+import pytest
+
+import fieldgen
+
+torch = pytest.importorskip("torch")
+pkg = pytest.importorskip("paper_2502_04093_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pkg.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def _bytes(t):
+    return t.detach().cpu().numpy().tobytes()
+
+
+def _direct(ctx, stream, kind, value):
+    ctx.set_batch_graphs(False)
+    st = stream.retrieve(**{kind: value})
+    out = (st.plan, st.bound, _bytes(st.tensor()))
+    st.free()
+    return out
+
+
+def _check_batch(ctx, streams, kind, values, label):
+    ctx.set_batch_graphs(True)
+    sts = ctx.retrieve_batch(streams, **{kind: values})
+    ctx.set_batch_graphs(False)
+    for i, (s, v, st) in enumerate(zip(streams, values, sts)):
+        plan, bound, field = _direct(ctx, s, kind, v)
+        assert st.plan == plan, (label, i)
+        assert st.bound == bound, (label, i)
+        assert _bytes(st.tensor()) == field, (label, i)
+        st.free()
+
+
+@pytest.mark.parametrize("dtype,interp,rel", [(np.float32, "cubic", 1e-4), (np.float64, "linear", 1e-6)])
+def test_graph_batches_equal_direct_launches(ctx, dtype, interp, rel):
+    # uneven shapes: level counts 3 .. 8, ragged tiles, multi-step columns,
+    # small levels (grid class 16), middle ones (128) and the full class
+    shapes = [(33, 40, 70), (9, 17, 130), (64, 96, 200), (2, 3, 5), (130, 70, 66)]
+    xs = [fieldgen.grf(sh, -5.0 / 6.0, seed=60 + i, dtype=dtype) for i, sh in enumerate(shapes)]
+    ebs = [rel * fieldgen.value_range(x) for x in xs]
+    ss = [ctx.compress(_dev(x), e, interp=interp) for x, e in zip(xs, ebs)]
+    c0, r0 = ctx.graph_stats()
+    # first batch: captured
+    _check_batch(ctx, ss, "eb", ebs, "full")
+    c1, r1 = ctx.graph_stats()
+    assert (c1, r1) == (c0 + 1, r0 + 1)
+    # same fields, other targets: the same launch shape, replayed; eager
+    # work and synchronizations between the replays
+    for trial, (kind, vals) in enumerate([("eb", [10 * e for e in ebs]),
+                                          ("bitrate", [1.0, 2.0, 4.0, 8.0, 0.5]),
+                                          ("eb", [1e3 * e for e in ebs])]):
+        y = torch.randn(1 << 20, device="cuda:0")
+        _ = float((y * y).sum())
+        torch.cuda.synchronize()
+        _check_batch(ctx, ss, kind, vals, ("replay", trial))
+    c2, r2 = ctx.graph_stats()
+    assert c2 == c1 and r2 == r1 + 3
+    # another mix (a field fewer, one repeated): its own shape
+    mix = [ss[2], ss[0], ss[0], ss[4]]
+    _check_batch(ctx, mix, "eb", [ebs[2], ebs[0], 5 * ebs[0], ebs[4]], "mix")
+    # one field alone
+    _check_batch(ctx, [ss[3]], "eb", [ebs[3]], "alone")
+    for s in ss:
+        s.free()
+
+
+def test_graph_serve_batch_refinements(ctx):
+    """Refinements in a served batch start from a coarse grid gathered out of
+    the resident reconstruction (the head jobs' gather mode)."""
+    shapes = [(65, 65, 65), (40, 100, 90), (17, 33, 200)]
+    xs = [fieldgen.grf(sh, -5.0 / 6.0, seed=80 + i, dtype=np.float32) for i, sh in enumerate(shapes)]
+    rs = [fieldgen.value_range(x) for x in xs]
+    ss = [ctx.compress(_dev(x), 1e-5 * r) for x, r in zip(xs, rs)]
+    ctx.set_batch_graphs(True)
+    try:
+        for rnd in range(3):
+            sts = [s.retrieve(eb=1e-2 * r) for s, r in zip(ss, rs)]
+            reqs = [(None, st, {"eb": (1e-3 if rnd % 2 == 0 else 1e-4) * r}) for st, r in zip(sts, rs)]
+            reqs.append((ss[0], None, {"bitrate": 2.0}))
+            out = ctx.serve_batch(reqs)
+            ctx.set_batch_graphs(False)
+            for k, (st, info, status) in enumerate(out):
+                assert status == 0, (rnd, k)
+                tg = reqs[k][2]
+                src = ss[k] if k < len(ss) else ss[0]
+                fresh = src.retrieve(**tg)
+                assert st.plan == fresh.plan, (rnd, k)
+                assert _bytes(st.tensor()) == _bytes(fresh.tensor()), (rnd, k)
+                fresh.free()
+                st.free()
+            ctx.set_batch_graphs(True)
+    finally:
+        ctx.set_batch_graphs(False)
+    captured, replays = ctx.graph_stats()
+    assert replays >= 3
+    for s in ss:
+        s.free()
