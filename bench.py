@@ -62,8 +62,8 @@ def parse_args():
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: arrivals per second")
     ap.add_argument("--budget-gib", type=float, default=32.0, help="serve: device-memory budget")
     ap.add_argument("--fields", type=int, default=8)
-    ap.add_argument("--batch-graphs", action="store_true",
-                    help="serve: batched retrievals as queue launches replayed from HIP graphs")
+    ap.add_argument("--direct-batches", action="store_true",
+                    help="serve: batched retrievals as direct launches instead of graph replays")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default column lengths (no ipc_autotune before timing)")
     ap.add_argument("--column-rows", default=None,
@@ -649,8 +649,8 @@ def serve_main(args):
         return v[min(len(v) - 1, int(np.ceil(q * len(v))) - 1)]
 
     # served
-    ctx.set_batch_graphs(args.batch_graphs)
-    srv = pkg.Server(ctx, budget_bytes=int(args.budget_gib * (1 << 30)), max_batch=64)
+    srv = pkg.Server(ctx, budget_bytes=int(args.budget_gib * (1 << 30)), max_batch=64,
+                     batch_graphs=not args.direct_batches)
     tickets = [None] * R
     states = [None] * R
     done_ev = [threading.Event() for _ in range(R)]
@@ -693,7 +693,7 @@ def serve_main(args):
     served = {"requests_per_s": round(R / (T1 - T0), 2), "p50_ms": round(pct(lat, 0.5), 4),
               "p99_ms": round(pct(lat, 0.99), 4), "batches": stats["batches"],
               "peak_budget_GiB": round(stats["peak"] / (1 << 30), 3),
-              "batch_graphs": bool(args.batch_graphs), "graphs": ctx.graph_stats()}
+              "batch_graphs": not args.direct_batches, "graphs": ctx.graph_stats()}
     ctx.set_batch_graphs(False)
     # plain: one request at a time, in arrival order
     pstates = [None] * R

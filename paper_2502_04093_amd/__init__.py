@@ -513,7 +513,10 @@ class Server:
     While a server exists, use its context only through it (``locked()``
     around any other call on the context)."""
 
-    def __init__(self, ctx: Context, budget_bytes: int, max_batch: int = 64):
+    def __init__(self, ctx: Context, budget_bytes: int, max_batch: int = 64, batch_graphs: bool = True):
+        # batched retrievals replayed from captured HIP graphs (the faster
+        # configuration for serving mixes; see Context.set_batch_graphs)
+        ctx.set_batch_graphs(batch_graphs)
         p = c_void_p()
         _check(lib().ipc_server_create(ctx.handle, int(budget_bytes), int(max_batch), ctypes.byref(p)),
                ctx.handle)

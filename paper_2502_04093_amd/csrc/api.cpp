@@ -990,8 +990,10 @@ bool queue_fits(const std::vector<const ipc_stream *> &ss) {
   return ent <= Q_ENTRIES && Kmax <= QUEUE_LEVELS;
 }
 
+// false when the context's stream cannot be captured into a graph (nothing
+// has run then but the table upload)
 template <typename T>
-void retrieve_batch_queue(ipc_ctx *ctx, const std::vector<const ipc_stream *> &ss,
+bool retrieve_batch_queue(ipc_ctx *ctx, const std::vector<const ipc_stream *> &ss,
                           const std::vector<std::vector<int>> &plans, const std::vector<void *> &out,
                           const std::vector<int> &l_start) {
   const int n = int(ss.size());
@@ -1086,7 +1088,10 @@ void retrieve_batch_queue(ipc_ctx *ctx, const std::vector<const ipc_stream *> &s
       for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
       ctx->graphs.clear();
     }
-    hip_check(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
     hipError_t e = launch_queue_reset(claims, ctx->stream);
     if (e == hipSuccess) e = launch_heads_retrieve(dtype, tab_dev, ctx->stream);
     for (int slot = 0; slot < Kmax && e == hipSuccess; ++slot)
@@ -1108,6 +1113,7 @@ void retrieve_batch_queue(ipc_ctx *ctx, const std::vector<const ipc_stream *> &s
   ++ctx->graph_replays;
   // the coarse grids and the staged table are reused by the next call
   hip_check(ctx, hipStreamSynchronize(ctx->stream), "retrieve");
+  return true;
 }
 
 // batched retrieval of fused 3-D streams: queue launches from a captured
@@ -1117,10 +1123,11 @@ template <typename T>
 void retrieve_batch_levels(ipc_ctx *ctx, const std::vector<const ipc_stream *> &ss,
                            const std::vector<std::vector<int>> &plans, const std::vector<void *> &out,
                            const std::vector<int> &l_start) {
-  if (ctx->batch_graphs && queue_fits(ss))
-    retrieve_batch_queue<T>(ctx, ss, plans, out, l_start);
-  else
-    retrieve_batch_fused<T>(ctx, ss, plans, out, l_start);
+  if (ctx->batch_graphs && queue_fits(ss)) {
+    if (retrieve_batch_queue<T>(ctx, ss, plans, out, l_start)) return;
+    ctx->batch_graphs = false;  // this stream cannot be captured: direct launches from now on
+  }
+  retrieve_batch_fused<T>(ctx, ss, plans, out, l_start);
 }
 
 // Compression of n fields on the one-pass-per-launch path (2-D, 1-D, other

@@ -45,9 +45,10 @@ def _streams(ctx):
     return out
 
 
-def test_mixed_requests_match_single_service(ctx):
+@pytest.mark.parametrize("graphs", [True, False], ids=["graph_replays", "direct_launches"])
+def test_mixed_requests_match_single_service(ctx, graphs):
     streams = _streams(ctx)
-    srv = pkg.Server(ctx, budget_bytes=64 << 20, max_batch=16)
+    srv = pkg.Server(ctx, budget_bytes=64 << 20, max_batch=16, batch_graphs=graphs)
     rng = np.random.default_rng(0)
 
     def submit_retrieve(i):
