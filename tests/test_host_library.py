@@ -251,3 +251,15 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
                        timeout=120)
     assert r.returncode == 0, r.stderr
     assert "not built" in r.stdout
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits with a message before any
+    device work."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=root, capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "measures one GPU" in r.stdout + r.stderr
