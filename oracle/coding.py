@@ -9,7 +9,7 @@ decoder that loads planes from the top.
 Sec. 4.3 / Fig. "overwrite": the 32 bits of the codes of one group form 32
 bitplanes that are stored independently, most significant first.
 Thm. 1: delta-y, the information lost by not loading the low planes, is
-"pre-computed during compression"; here it is the exact max over the pass of
+computed once at compression time; here it is the exact max over the pass of
 |q - q'_b|, q'_b being the code rebuilt from planes b..31, in code units.
 
 Readings used:
