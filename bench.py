@@ -200,6 +200,23 @@ def main():
         lat.append((time.perf_counter() - t0) * 1e3)
         plan_ms.append(st.info.t_plan_ms)
         st.free()
+    # a partial target (1e-3 * range): the planner's program runs
+    part = {}
+    for rel_t in (1e-3,):
+        e_t = rel_t * rng
+        lp, pp = [], []
+        for _ in range(L):
+            t0 = time.perf_counter()
+            st = s.retrieve(eb=e_t)
+            lp.append((time.perf_counter() - t0) * 1e3)
+            pp.append(st.info.t_plan_ms)
+            bl = st.info.bytes_loaded
+            st.free()
+        lp.sort()
+        part[f"eb={rel_t:g}*range"] = {
+            "p50": round(lp[len(lp) // 2], 4),
+            "p99": round(lp[min(len(lp) - 1, int(math.ceil(0.99 * len(lp))) - 1)], 4),
+            "planner_median": round(sorted(pp)[len(pp) // 2], 4), "bytes_loaded": int(bl)}
     s.free()
     # quality of the full retrieval (outside the timed region)
     s = ctx.compress(x, eb, interp=args.interp)
@@ -216,11 +233,23 @@ def main():
     p99 = lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)] if lat else None
 
     # roofline of the dominant kernel: algorithmic bytes per launch
-    alg_bytes, kname = launch_bytes(dom_op, dom_pass, pinfo, shape, itemsize, args.interp)
+    alg_bytes, alg_targets, kname = launch_bytes(dom_op, dom_pass, pinfo, shape, itemsize, args.interp)
     traffic = counted_traffic(dom_op, pinfo[dom_pass]["level"], shape, itemsize, args.interp)
     dom_list = dom_c if dom_op == "compress" else dom_r
     dom_avg_ms = sum(dom_list) / len(dom_list)
     achieved = alg_bytes / (dom_avg_ms * 1e-3) / 1e9
+    # whole calls: compression moves n s + C (field in, stream out), a full
+    # retrieval L_E + n s (every stream byte in, field out); median call time
+    c_med = sorted(step_c)[len(step_c) // 2]
+    r_med = sorted(step_r)[len(step_r) // 2]
+    call_c = n * itemsize + stream_bytes
+    call_r = stream_bytes + n * itemsize
+    whole = {"compress": {"alg_bytes": call_c, "ms": round(c_med, 4),
+                          "GBps": round(call_c / (c_med * 1e-3) / 1e9, 2),
+                          "frac": round(call_c / (c_med * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
+             "retrieve": {"alg_bytes": call_r, "ms": round(r_med, 4),
+                          "GBps": round(call_r / (r_med * 1e-3) / 1e9, 2),
+                          "frac": round(call_r / (r_med * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}}
 
     out = {
         "metric": "compress & retrieve GB/s (fp32 in) at eb=1e-4*range; p50/p99 retrieval latency",
@@ -244,7 +273,8 @@ def main():
         "compress_GBps": round(gb / (tc / args.steps), 3),
         "retrieve_GBps": round(gb / (tr / args.steps), 3),
         "retrieve_latency_ms": {"p50": p50 and round(p50, 4), "p99": p99 and round(p99, 4), "calls": L,
-                                "planner_median": round(sorted(plan_ms)[len(plan_ms) // 2], 4) if plan_ms else None},
+                                "planner_median": round(sorted(plan_ms)[len(plan_ms) // 2], 4) if plan_ms else None,
+                                "partial": part},
         "step_ms": {"compress_median": round(sorted(step_c)[len(step_c) // 2], 4),
                     "compress_min": round(min(step_c), 4),
                     "retrieve_median": round(sorted(step_r)[len(step_r) // 2], 4),
@@ -253,7 +283,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "kernel": kname, "alg_bytes_per_launch": int(alg_bytes),
-                     "avg_launch_ms": round(dom_avg_ms, 5)},
+                     "alg_bytes_per_target": round(alg_bytes / max(1, alg_targets), 4),
+                     "targets_per_launch": int(alg_targets),
+                     "avg_launch_ms": round(dom_avg_ms, 5), "whole_call": whole},
         "pass_ms": {"compress": [round(v, 4) for v in c_ms], "retrieve": [round(v, 4) for v in r_ms]},
         "launch": {"column_rows_by_level": tuned, "autotuned": tuned is not None and not args.column_rows},
     }
@@ -738,35 +770,26 @@ def serve_main(args):
 
 
 def launch_bytes(op, launch, pinfo, shape, itemsize, interp):
-    """Algorithmic HBM bytes of one launch (each byte the launch must move once).
+    """Algorithmic HBM bytes of one launch: what the method must move for the
+    targets the launch predicts, nothing for the work of the layout.
 
-    A launch that runs a whole level l of a 3-D field (passes along z, y, x)
-    reads the coarse grid G_l (points at stride 2^l), the planes of its three
-    passes and, for compression, the inputs at its targets; it writes the
-    level grid G_(l-1) (compression: only when a finer level follows) and, for
-    compression, the planes.  A single-pass launch moves its targets' values
-    once and its planes once.
+    Per target that is its value (compression reads it from the input field,
+    retrieval writes it to the output) plus its share of the stream (the
+    planes of the launch's passes, written by compression, read by a full
+    retrieval).  Summed over the launches of a call this is the call's n * s
+    plus its plane bytes, the whole-call figure less the fixed part of the
+    stream (header, tables, anchors, outliers).  Coarse-grid reads, halo
+    re-reads and the rewrite of coarse points are the kernel's overhead, seen
+    in the counted traffic, not algorithmic bytes.
     """
     group = [i for i, p in enumerate(pinfo) if p["launch_pass"] == launch]
     planes = sum(sum(pinfo[i]["plane_bytes"]) for i in group)
     targets = sum(pinfo[i]["n_targets"] for i in group)
     tname = "float" if itemsize == 4 else "double"
     if len(group) == 1:
-        return targets * itemsize + planes, f"k_{op}_pass<{tname},{interp}> pass {launch}"
+        return targets * itemsize + planes, targets, f"k_{op}_pass<{tname},{interp}> pass {launch}"
     lev = pinfo[launch]["level"]
-
-    def grid(j):
-        n = 1
-        for d in shape:
-            n *= ((d - 1) >> j) + 1
-        return n
-
-    coarse, fine = grid(lev), grid(lev - 1)
-    if op == "compress":
-        b = targets * itemsize + coarse * itemsize + planes + (fine * itemsize if lev > 1 else 0)
-    else:
-        b = coarse * itemsize + planes + fine * itemsize
-    return b, f"k_level3_{op}<{tname},{interp}> level {lev}"
+    return targets * itemsize + planes, targets, f"k_level3_{op}<{tname},{interp}> level {lev}"
 
 
 def counted_traffic(op, level, shape, itemsize, interp):
@@ -794,6 +817,17 @@ def counted_traffic(op, level, shape, itemsize, interp):
     return None
 
 
+def cpu_model():
+    """The host CPU's model name (first processor of /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(x, eb, args, ctx):
     """The oracle (plain NumPy, one core) on a cubic corner of the same field,
     and the parity of the GPU path on that corner: its stream and full
@@ -814,6 +848,7 @@ def cpu_baseline(x, eb, args, ctx):
     t2 = time.perf_counter()
     gb = xs.nbytes / 1e9
     base = {"value": round(gb / (t2 - t0), 5), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "host_cpus": os.cpu_count(), "host_cpu_model": cpu_model(),
             "sample": f"{'x'.join(map(str, xs.shape))} corner of the same field, same eb; "
                       f"compress {t1 - t0:.2f} s + full retrieve {t2 - t1:.2f} s",
             "compress_GBps": round(gb / (t1 - t0), 5), "retrieve_GBps": round(gb / (t2 - t1), 5)}

@@ -174,7 +174,13 @@ def plan_host(stream_bytes: bytes, eb=None, bitrate=None, limit: Optional[Sequen
 
 
 class Context:
-    """ipc_ctx on a device, ordered on torch's current HIP stream by default."""
+    """ipc_ctx on a device.
+
+    With no stream given, calls are ordered after torch's current stream: a
+    non-default torch stream is handed to the library as is; for torch's
+    default stream (the null stream, handle 0) the library issues work on a
+    stream of its own that waits, at every call, for the work queued on the
+    null stream so far (ipc_ctx_create with a NULL stream)."""
 
     def __init__(self, device: int = 0, stream=None):
         import torch

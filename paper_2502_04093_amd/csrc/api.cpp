@@ -48,6 +48,11 @@ struct ipc_ctx {
   int n_cu = 256;                       // compute units of the device
   hipStream_t stream = nullptr;
   hipStream_t owned = nullptr;
+  // no stream was given: the owned stream (which does not synchronize with
+  // the null stream) waits at every call for what the caller queued on the
+  // null stream, so inputs written there are complete before they are read
+  bool follow_null = false;
+  hipEvent_t ev_null = nullptr;
   std::string err;
   std::multimap<size_t, void *> cache;  // freed device blocks by size
   size_t cached_bytes = 0;
@@ -180,6 +185,18 @@ void hip_check(ipc_ctx *ctx, hipError_t e, const char *what) {
   if (e != hipSuccess) {
     set_err(ctx, std::string(what) + ": " + hipGetErrorString(e));
     throw Fail{e == hipErrorOutOfMemory ? IPC_ENOMEM : IPC_EHIP};
+  }
+}
+
+// Start of a call that issues device work: the context's device becomes
+// current, and a context on its own stream orders the call after the work
+// queued on the null stream so far (an event recorded there, waited for on
+// the context's stream; both outside any graph capture).
+void enter_device(ipc_ctx *ctx) {
+  hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  if (ctx->follow_null) {
+    hip_check(ctx, hipEventRecord(ctx->ev_null, nullptr), "null-stream event");
+    hip_check(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_null, 0), "null-stream wait");
   }
 }
 
@@ -1432,12 +1449,15 @@ ipc_status ipc_ctx_create(int device, void *hip_stream, ipc_ctx **out) {
       return IPC_EHIP;
     }
     c->stream = c->owned;
+    c->follow_null = true;
   }
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_null, hipEventDisableTiming) != hipSuccess ||
       hipMalloc(&c->dev_zero, 256) != hipSuccess || hipMemset(c->dev_zero, 0, 256) != hipSuccess) {
     (void)hipGetLastError();
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->ev_null) (void)hipEventDestroy(c->ev_null);
     if (c->dev_zero) (void)hipFree(c->dev_zero);
     if (c->owned) (void)hipStreamDestroy(c->owned);
     delete c;
@@ -1452,10 +1472,12 @@ ipc_status ipc_ctx_set_stream(ipc_ctx *ctx, void *hip_stream) {
   (void)hipStreamSynchronize(ctx->stream);
   if (hip_stream) {
     ctx->stream = static_cast<hipStream_t>(hip_stream);
+    ctx->follow_null = false;
   } else {
     if (!ctx->owned && hipStreamCreateWithFlags(&ctx->owned, hipStreamNonBlocking) != hipSuccess)
       return IPC_EHIP;
     ctx->stream = ctx->owned;
+    ctx->follow_null = true;
   }
   return IPC_OK;
 }
@@ -1482,6 +1504,7 @@ void ipc_ctx_destroy(ipc_ctx *ctx) {
   for (hipEvent_t e : ctx->pev) (void)hipEventDestroy(e);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->ev_null) (void)hipEventDestroy(ctx->ev_null);
   if (ctx->owned) (void)hipStreamDestroy(ctx->owned);
   delete ctx;
 }
@@ -1506,7 +1529,7 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
   if (!s) return IPC_ENOMEM;
   s->ctx = ctx;
   ipc_status st = guarded(ctx, [&] {
-    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    enter_device(ctx);
     setup_stream(ctx, s, dims, ndim, dtype, interp, abs_eb, opts);
     StreamMeta &m = s->meta;
     const Schedule &sc = m.sched;
@@ -1686,7 +1709,7 @@ ipc_status ipc_stream_to_host(ipc_ctx *ctx, const ipc_stream *sc, void *dst, uin
     return IPC_EINVAL;
   }
   return guarded(ctx, [&] {
-    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    enter_device(ctx);
     StreamMeta &m = s->meta;
     ensure_host_masks(ctx, s);
     if (!s->host_outliers_valid) fetch_outliers(ctx, s);
@@ -1720,7 +1743,7 @@ ipc_status ipc_stream_entropy_code(ipc_ctx *ctx, ipc_stream *s) {
   }
   if (s->meta.coding) return IPC_OK;
   return guarded(ctx, [&] {
-    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    enter_device(ctx);
     StreamMeta &m = s->meta;
     ensure_host_masks(ctx, s);
     const uint64_t nb = n_blocks(m);
@@ -1783,7 +1806,7 @@ ipc_status ipc_stream_from_host(ipc_ctx *ctx, const void *src, uint64_t bytes, i
   if (!s) return IPC_ENOMEM;
   s->ctx = ctx;
   ipc_status st = guarded(ctx, [&] {
-    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    enter_device(ctx);
     const uint32_t *payload = nullptr;
     std::string e;
     if (!parse_serialized(static_cast<const uint8_t *>(src), bytes, s->meta, &payload, e)) {
@@ -1872,7 +1895,7 @@ static ipc_status retrieve_common(ipc_ctx *ctx, const ipc_stream *s, const std::
   stt->plan = plan;
   stt->bound = bound;
   ipc_status st = guarded(ctx, [&] {
-    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    enter_device(ctx);
     size_t isz = s->meta.dtype == IPC_F32 ? 4 : 8;
     stt->field = dev_alloc(ctx, size_t(s->meta.sched.n_points) * isz);
     hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
@@ -1967,7 +1990,7 @@ ipc_status ipc_state_copy_field(ipc_ctx *ctx, const ipc_state *st, void *dst_dev
     return IPC_EINVAL;
   }
   return guarded(ctx, [&] {
-    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    enter_device(ctx);
     hip_check(ctx, hipMemcpyAsync(dst_dev, st->field.p, n, hipMemcpyDeviceToDevice, ctx->stream), "copy");
     hip_check(ctx, hipStreamSynchronize(ctx->stream), "copy");
   });
@@ -2026,7 +2049,7 @@ ipc_status ipc_refine(ipc_ctx *ctx, ipc_state *st, ipc_target target, ipc_info *
       break;
     }
   return guarded(ctx, [&] {
-    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    enter_device(ctx);
     hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
     run_retrieve(ctx, s, pr.plan, s_min, st->field.p);
     hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
@@ -2071,7 +2094,7 @@ ipc_status ipc_refine_additive(ipc_ctx *ctx, ipc_state *st, ipc_target target, i
       break;
     }
   return guarded(ctx, [&] {
-    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    enter_device(ctx);
     const size_t isz = s->meta.dtype == IPC_F32 ? 4 : 8;
     const uint64_t n = uint64_t(s->meta.sched.n_points);
     // the difference field lives in the per-pass working buffer
@@ -2181,7 +2204,7 @@ ipc_status ipc_compress_batch(ipc_ctx *ctx, uint32_t n, const void *const *field
   std::vector<ipc_stream *> ss(n, nullptr);
   std::vector<char> redo(n, 0);
   ipc_status st = guarded(ctx, [&] {
-    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    enter_device(ctx);
     for (uint32_t i = 0; i < n; ++i) {
       ss[i] = new ipc_stream();
       ss[i]->ctx = ctx;
@@ -2273,7 +2296,7 @@ ipc_status ipc_retrieve_batch(ipc_ctx *ctx, uint32_t n, const ipc_stream *const 
   });
   std::vector<ipc_state *> sts(n, nullptr);
   ipc_status st = guarded(ctx, [&] {
-    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    enter_device(ctx);
     std::vector<void *> fields(n);
     for (uint32_t i = 0; i < n; ++i) {
       sts[i] = new ipc_state();
@@ -2522,7 +2545,7 @@ ipc_status ipc_serve_batch(ipc_ctx *ctx, uint32_t n, ipc_request *req) {
   }
   std::vector<ipc_state *> fresh(jobs.size(), nullptr);  // new states of this call
   ipc_status st = guarded(ctx, [&] {
-    hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+    enter_device(ctx);
     std::vector<const ipc_stream *> ss;
     std::vector<std::vector<int>> plans;
     std::vector<void *> fields;

@@ -1,14 +1,15 @@
 """Batched retrievals as queue launches replayed from captured HIP graphs
-(gpu).  Every result must equal, byte for byte, the same retrieval made by the
-direct launches (which the other GPU tests tie to the oracle); a graph is
-captured once per launch shape and replayed for later batches of that shape,
-with other work and synchronizations between the replays, and every replay is
-checked."""
+(gpu).  Every result must equal, byte for byte, the oracle's retrieval for
+the same target (plan, bound and reconstruction) and the same retrieval made
+by the direct launches; a graph is captured once per launch shape and
+replayed for later batches of that shape, with other work and
+synchronizations between the replays, and every replay is checked."""
 
 import numpy as np
 import pytest
 
 import fieldgen
+from oracle import codec
 
 torch = pytest.importorskip("torch")
 pkg = pytest.importorskip("paper_2502_04093_amd")
@@ -41,15 +42,19 @@ def _direct(ctx, stream, kind, value):
     return out
 
 
-def _check_batch(ctx, streams, kind, values, label):
+def _check_batch(ctx, streams, kind, values, label, refs):
+    """refs[i]: the oracle's stream for streams[i]"""
     ctx.set_batch_graphs(True)
     sts = ctx.retrieve_batch(streams, **{kind: values})
     ctx.set_batch_graphs(False)
-    for i, (s, v, st) in enumerate(zip(streams, values, sts)):
+    for i, (s, v, st, ref) in enumerate(zip(streams, values, sts, refs)):
+        o = codec.retrieve(ref, kind, v)
+        got = _bytes(st.tensor())
+        assert st.plan == list(o.plan), (label, i)
+        assert st.bound == o.bound, (label, i)
+        assert got == o.field.tobytes(), (label, i)
         plan, bound, field = _direct(ctx, s, kind, v)
-        assert st.plan == plan, (label, i)
-        assert st.bound == bound, (label, i)
-        assert _bytes(st.tensor()) == field, (label, i)
+        assert (st.plan, st.bound, got) == (plan, bound, field), (label, i)
         st.free()
 
 
@@ -61,9 +66,12 @@ def test_graph_batches_equal_direct_launches(ctx, dtype, interp, rel):
     xs = [fieldgen.grf(sh, -5.0 / 6.0, seed=60 + i, dtype=dtype) for i, sh in enumerate(shapes)]
     ebs = [rel * fieldgen.value_range(x) for x in xs]
     ss = [ctx.compress(_dev(x), e, interp=interp) for x, e in zip(xs, ebs)]
+    it = 1 if interp == "cubic" else 0
+    refs = [codec.compress(x, e, interp=it) for x, e in zip(xs, ebs)]
+    assert [s.to_bytes() for s in ss] == refs
     c0, r0 = ctx.graph_stats()
     # first batch: captured
-    _check_batch(ctx, ss, "eb", ebs, "full")
+    _check_batch(ctx, ss, "eb", ebs, "full", refs)
     c1, r1 = ctx.graph_stats()
     assert (c1, r1) == (c0 + 1, r0 + 1)
     # same fields, other targets: the same launch shape, replayed; eager
@@ -74,14 +82,15 @@ def test_graph_batches_equal_direct_launches(ctx, dtype, interp, rel):
         y = torch.randn(1 << 20, device="cuda:0")
         _ = float((y * y).sum())
         torch.cuda.synchronize()
-        _check_batch(ctx, ss, kind, vals, ("replay", trial))
+        _check_batch(ctx, ss, kind, vals, ("replay", trial), refs)
     c2, r2 = ctx.graph_stats()
     assert c2 == c1 and r2 == r1 + 3
     # another mix (a field fewer, one repeated): its own shape
     mix = [ss[2], ss[0], ss[0], ss[4]]
-    _check_batch(ctx, mix, "eb", [ebs[2], ebs[0], 5 * ebs[0], ebs[4]], "mix")
+    _check_batch(ctx, mix, "eb", [ebs[2], ebs[0], 5 * ebs[0], ebs[4]], "mix",
+                 [refs[2], refs[0], refs[0], refs[4]])
     # one field alone
-    _check_batch(ctx, [ss[3]], "eb", [ebs[3]], "alone")
+    _check_batch(ctx, [ss[3]], "eb", [ebs[3]], "alone", [refs[3]])
     for s in ss:
         s.free()
 
@@ -93,10 +102,13 @@ def test_graph_serve_batch_refinements(ctx):
     xs = [fieldgen.grf(sh, -5.0 / 6.0, seed=80 + i, dtype=np.float32) for i, sh in enumerate(shapes)]
     rs = [fieldgen.value_range(x) for x in xs]
     ss = [ctx.compress(_dev(x), 1e-5 * r) for x, r in zip(xs, rs)]
+    refs = [codec.compress(x, 1e-5 * r) for x, r in zip(xs, rs)]
+    assert [s.to_bytes() for s in ss] == refs
     ctx.set_batch_graphs(True)
     try:
         for rnd in range(3):
             sts = [s.retrieve(eb=1e-2 * r) for s, r in zip(ss, rs)]
+            olds = [codec.retrieve(ref, "eb", 1e-2 * r) for ref, r in zip(refs, rs)]
             reqs = [(None, st, {"eb": (1e-3 if rnd % 2 == 0 else 1e-4) * r}) for st, r in zip(sts, rs)]
             reqs.append((ss[0], None, {"bitrate": 2.0}))
             out = ctx.serve_batch(reqs)
@@ -104,6 +116,11 @@ def test_graph_serve_batch_refinements(ctx):
             for k, (st, info, status) in enumerate(out):
                 assert status == 0, (rnd, k)
                 tg = reqs[k][2]
+                kind, v = next(iter(tg.items()))
+                # the oracle: a refinement of its own retrieval, or a fresh retrieval
+                o = codec.refine(olds[k], kind, v) if k < len(ss) else codec.retrieve(refs[0], kind, v)
+                assert st.plan == list(o.plan), (rnd, k)
+                assert _bytes(st.tensor()) == o.field.tobytes(), (rnd, k)
                 src = ss[k] if k < len(ss) else ss[0]
                 fresh = src.retrieve(**tg)
                 assert st.plan == fresh.plan, (rnd, k)

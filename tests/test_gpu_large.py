@@ -43,15 +43,18 @@ def _bytes(t):
 # (512 x 256 x 256), 8 with a ragged last segment (300 x 200 x 260) and 4 in
 # float64 (200 x 130 x 260)
 MULTI = [
-    ((512, 256, 256), np.float32, 3, 1e-4, False),
-    ((300, 200, 260), np.float32, 4, 1e-4, True),
-    ((200, 130, 260), np.float64, 5, 1e-6, True),
+    ((512, 256, 256), np.float32, 3, 1e-4, False, "cubic"),
+    ((300, 200, 260), np.float32, 4, 1e-4, True, "cubic"),
+    ((200, 130, 260), np.float64, 5, 1e-6, True, "cubic"),
+    # linear interpolation with multi-step columns (coarse-plane ring, prefetch)
+    ((512, 256, 256), np.float32, 6, 1e-4, False, "linear"),
+    ((300, 200, 260), np.float32, 7, 1e-5, True, "linear"),
 ]
 
 
-@pytest.mark.parametrize("case", MULTI, ids=lambda c: f"{'x'.join(map(str, c[0]))}-{np.dtype(c[1]).name}")
+@pytest.mark.parametrize("case", MULTI, ids=lambda c: f"{'x'.join(map(str, c[0]))}-{np.dtype(c[1]).name}-{c[5]}")
 def test_multistep_columns_match_oracle(ctx, case):
-    shape, dt, seed, rel, special = case
+    shape, dt, seed, rel, special, interp = case
     x = fieldgen.grf(shape, -5.0 / 6.0, seed=seed, dtype=dt)
     if special:
         f = x.reshape(-1)
@@ -60,9 +63,9 @@ def test_multistep_columns_match_oracle(ctx, case):
         f[f.size // 2 + 7] = dt(3e37) if dt == np.float32 else 3e300
     r = fieldgen.value_range(np.nan_to_num(x, posinf=0, neginf=0))
     eb = rel * r
-    print(f"case {shape} {np.dtype(dt).name} eb={eb}", flush=True)
-    ref, dbg = codec.compress(x, eb, debug=True)
-    s = ctx.compress(_dev(x), eb)
+    print(f"case {shape} {np.dtype(dt).name} {interp} eb={eb}", flush=True)
+    ref, dbg = codec.compress(x, eb, interp=1 if interp == "cubic" else 0, debug=True)
+    s = ctx.compress(_dev(x), eb, interp=interp)
     assert s.to_bytes() == ref
     st = s.retrieve(eb=eb)
     assert _bytes(st.tensor()) == dbg.xhat.tobytes()
@@ -222,6 +225,10 @@ def test_benchmark_field_sampled_parity(ctx):
     try:
         s = ctx.compress(x, eb)
         cone = Cone(x.cpu().numpy(), eb)
+        # the plans are chosen independently by the oracle's planner from the
+        # stream's serialized tables (its sampled bytes are pinned by the
+        # cone: every pass's codes and delta-y are what the samples decode)
+        _, _, tables = codec.open_stream(s.to_bytes())
         pts = _samples(x.shape, 160, 1)
         print(f"sampled parity 512^3 f32: {len(pts)} points", flush=True)
         st = s.retrieve(eb=eb)
@@ -232,11 +239,16 @@ def test_benchmark_field_sampled_parity(ctx):
         st.free()
         for kind, v in (("bitrate", 1.0), ("bitrate", 4.0), ("eb", 1e-2 * r)):
             st = s.retrieve(**{kind: v})
-            _check_samples(st, cone, pts, st.plan, (kind, v))
+            oplan, _ = codec.make_plan(tables, kind, v)
+            assert st.plan == [int(b) for b in oplan], (kind, v)
+            _check_samples(st, cone, pts, oplan, (kind, v))
             st.free()
         st = s.retrieve(eb=1e-2 * r)
+        old = list(st.plan)
         st.refine(eb=1e-3 * r)
-        _check_samples(st, cone, pts, st.plan, "refine")
+        oplan, _ = codec.make_plan(tables, "eb", 1e-3 * r, limit=old)
+        assert st.plan == [int(b) for b in oplan]
+        _check_samples(st, cone, pts, oplan, "refine")
         st.free()
         print(f"cone points evaluated: {cone.cone_size()}", flush=True)
         s.free()

@@ -220,3 +220,63 @@ def test_deterministic(ctx):
     assert a.to_bytes() == b.to_bytes()
     a.free()
     b.free()
+
+
+def _edge_fields():
+    """Fields of edge values (SURVEY T5 style): subnormal magnitudes, signed
+    zeros, tiny bounds whose quantizer constants leave the normal range."""
+    rng = np.random.default_rng(77)
+    base = fieldgen.random_field((20, 33, 70), seed=31, dtype=np.float32)
+    out = []
+    # subnormal magnitudes throughout (float32 normals start at 1.18e-38):
+    # 2 eb is subnormal and 1 / (2 eb) overflows, so every point is an outlier
+    x = (base * np.float32(1e-40)).astype(np.float32)
+    out.append(("f32 subnormal field", x, 1e-4 * fieldgen.value_range(x)))
+    # a normal field with subnormals and signed zeros sprinkled in
+    x = base.copy()
+    f = x.reshape(-1)
+    idx = rng.choice(f.size, size=600, replace=False)
+    f[idx[:200]] = np.float32(1e-42)
+    f[idx[200:300]] = np.float32(-3e-41)
+    f[idx[300:450]] = np.float32(-0.0)
+    f[idx[450:]] = np.float32(0.0)
+    out.append(("f32 with subnormals and signed zeros", x, 1e-3 * fieldgen.value_range(x)))
+    # only signed zeros
+    z = np.zeros((9, 17, 70), dtype=np.float32)
+    z.reshape(-1)[::3] = np.float32(-0.0)
+    out.append(("f32 signed zeros", z, 1e-3))
+    # small normals with a subnormal error bound: 2 eb subnormal, 1 / (2 eb) finite
+    x = (base * np.float32(1e-36)).astype(np.float32)
+    out.append(("f32 subnormal bound", x, 5e-39))
+    # float64 subnormal magnitudes (normals start at 2.2e-308)
+    x = fieldgen.random_field((17, 33, 65), seed=32, dtype=np.float64) * 1e-310
+    out.append(("f64 subnormal field", x, 1e-4 * fieldgen.value_range(x)))
+    x = fieldgen.random_field((17, 33, 65), seed=34, dtype=np.float64) * 1e-306
+    out.append(("f64 subnormal bound", x, 5e-309))
+    x = fieldgen.random_field((130, 257), seed=33, dtype=np.float64)
+    f = x.reshape(-1)
+    f[::97] = -0.0
+    f[5::101] = 4e-320
+    out.append(("f64 2-D with subnormals and signed zeros", x, 1e-6 * fieldgen.value_range(x)))
+    return out
+
+
+@pytest.mark.parametrize("k", range(7))
+def test_edge_values_match_oracle(ctx, k):
+    what, x, eb = _edge_fields()[k]
+    print(f"edge values: {what}, eb={eb}", flush=True)
+    ref, dbg = codec.compress(x, eb, debug=True)
+    s = ctx.compress(_dev(x), eb)
+    assert s.to_bytes() == ref
+    st = s.retrieve(eb=eb)
+    assert _bytes(st.tensor()) == dbg.xhat.tobytes()
+    st.free()
+    for tg in ({"eb": 100 * eb}, {"bitrate": 1.0}):
+        kind, v = next(iter(tg.items()))
+        st = s.retrieve(**tg)
+        o = codec.retrieve(ref, kind, v)
+        assert st.plan == list(o.plan)
+        assert st.bound == o.bound
+        assert _bytes(st.tensor()) == o.field.tobytes()
+        st.free()
+    s.free()
