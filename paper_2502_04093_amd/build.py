@@ -11,8 +11,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libipcomp.so")
-SOURCES = ["api.cpp", "server.cpp", "schedule.cpp", "planner.cpp", "stream_format.cpp", "kernels.hip",
-           "level3.hip", "entropy.hip"]
+# host-only C++ (no HIP API, no device code): compiled as plain C++
+HOST_SOURCES = ["server.cpp", "schedule.cpp", "planner.cpp", "stream_format.cpp"]
+# HIP: the runtime calls and the kernels
+HIP_SOURCES = ["api.cpp", "kernels.hip", "level3.hip", "entropy.hip"]
+SOURCES = HOST_SOURCES + HIP_SOURCES
 ARCH = "gfx950"
 
 
@@ -29,7 +32,8 @@ def build(verbose: bool = False) -> str:
            "-ffp-contract=off", "-fno-fast-math",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wall", "-Wno-unused-function",
-           "-o", out_tmp] + [os.path.join(CSRC, s) for s in SOURCES] + [
+           "-o", out_tmp, "-x", "c++"] + [os.path.join(CSRC, s) for s in HOST_SOURCES] + [
+           "-x", "hip"] + [os.path.join(CSRC, s) for s in HIP_SOURCES] + [
            # ROCTx ranges around the library calls (rocprofv3 --marker-trace)
            "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:

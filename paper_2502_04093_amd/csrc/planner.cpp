@@ -89,6 +89,33 @@ static int64_t group_bytes(const PlanTables &t, const std::vector<int> &g, int l
   return v;
 }
 
+// The programs' inner steps: one choice (cost c, value v) applied to every
+// budget cell, best[r] = max (error bound mode) or min (bitrate mode) of
+// itself and prev[r - c] + v.  Branch-free, so the compiler vectorizes them;
+// built for AVX2 as well as the baseline, picked by the CPU at load time.
+__attribute__((target_clones("avx2", "default"))) static void max_shift_add(double *best,
+                                                                           const double *prev,
+                                                                           int n, int c, double v) {
+  for (int r = c; r < n; ++r) {
+    const double x = prev[r - c] + v;
+    best[r] = x > best[r] ? x : best[r];
+  }
+}
+__attribute__((target_clones("avx2", "default"))) static void min_shift_add(double *best,
+                                                                           const double *prev,
+                                                                           int n, int c, double v) {
+  for (int r = c; r < n; ++r) {
+    const double x = prev[r - c] + v;
+    best[r] = x < best[r] ? x : best[r];
+  }
+}
+
+// Every group's table is kept (NG x cells doubles); the backtrack recovers a
+// group's choice at a cell as the smallest b whose candidate equals the
+// table's value there, which is the choice the tie rule keeps (choices are
+// applied in increasing b and replace only on strict improvement).  Choices
+// that can never be kept are not applied: those with the cost (bytes) and the
+// value of an earlier choice no better (a smaller b always wins or ties).
 static PlanResult plan_eb(const PlanTables &t, double E, const int *limit, bool per_level) {
   PlanResult res;
   const int P = t.P;
@@ -103,21 +130,30 @@ static PlanResult plan_eb(const PlanTables &t, double E, const int *limit, bool 
   if (R == 0.0) return res;
   double r = rounding_step(t, t.maxabs + E);
   double u = R / G_UNITS;
-  const int64_t NEG = std::numeric_limits<int64_t>::min() / 4;
+  const int N = G_UNITS + 1;
   const std::vector<std::vector<int>> groups = plan_groups(t, per_level);
   const int NG = int(groups.size());
-  std::vector<int64_t> F(G_UNITS + 1, 0), nF(G_UNITS + 1);
-  std::vector<uint8_t> choice(size_t(NG) * (G_UNITS + 1), 0);
+  // tables F_0 .. F_NG: F_0 = 0 (nothing chosen); saved bytes are integers
+  // below 2^53, exact in doubles
+  std::vector<double> F(size_t(NG + 1) * N, 0.0);
   std::vector<int> cost(size_t(NG) * 33, 0);
+  std::vector<double> saved_of(size_t(NG) * 33, 0.0);
+  std::vector<uint8_t> used(size_t(NG) * 33, 0);
   for (int gi = 0; gi < NG; ++gi) {
     const std::vector<int> &g = groups[gi];
-    std::fill(nF.begin(), nF.end(), NEG);
-    uint8_t *ch = &choice[size_t(gi) * (G_UNITS + 1)];
+    const double *prev = &F[size_t(gi) * N];
+    double *cur = &F[size_t(gi + 1) * N];
+    // b = 0 discards nothing: term 0, cost 0, nothing saved
+    std::copy(prev, prev + N, cur);
+    used[size_t(gi) * 33] = 1;
     int hi = allowed_hi(t, g, limit);
-    int64_t saved = 0, prev_saved = -1;
-    int prev_c = -1;
-    for (int b = 0; b <= hi; ++b) {
-      if (b > 0) saved += group_bytes(t, g, b - 1, b);
+    int64_t saved = 0;
+    // cheapest cost so far among choices saving exactly `plateau` bytes (saved
+    // bytes never decrease with b)
+    int64_t plateau = 0;
+    int plateau_cost = 0;
+    for (int b = 1; b <= hi; ++b) {
+      saved += group_bytes(t, g, b - 1, b);
       double tv = group_term(t, g, b, r);
       int c;
       if (tv == 0.0) {
@@ -127,29 +163,35 @@ static PlanResult plan_eb(const PlanTables &t, double E, const int *limit, bool 
         c = (qv < double(G_UNITS)) ? int(std::floor(qv)) + 1 : G_UNITS + 1;
       }
       cost[size_t(gi) * 33 + b] = c;
+      saved_of[size_t(gi) * 33 + b] = double(saved);
       if (c > G_UNITS) continue;
-      // the same (cost, saved bytes) as the choice before: it can only tie
-      // with it, and ties go to the smaller b
-      if (c == prev_c && saved == prev_saved) continue;
-      prev_c = c;
-      prev_saved = saved;
-      for (int rr = c; rr <= G_UNITS; ++rr) {
-        int64_t prev = F[rr - c];
-        if (prev == NEG) continue;
-        int64_t cand = prev + saved;
-        if (cand > nF[rr]) {
-          nF[rr] = cand;
-          ch[rr] = uint8_t(b);
-        }
+      if (saved == plateau) {
+        // an earlier (smaller) b saves as much for no more cost
+        if (c >= plateau_cost) continue;
+        plateau_cost = c;
+      } else {
+        plateau = saved;
+        plateau_cost = c;
       }
+      used[size_t(gi) * 33 + b] = 1;
+      max_shift_add(cur, prev, N, c, double(saved));
     }
-    F.swap(nF);
   }
   int rr = G_UNITS;
   for (int gi = NG - 1; gi >= 0; --gi) {
-    int b = choice[size_t(gi) * (G_UNITS + 1) + rr];
-    for (int s : groups[gi]) res.plan[s] = b;
-    rr -= cost[size_t(gi) * 33 + b];
+    const double *prev = &F[size_t(gi) * N];
+    const double want = F[size_t(gi + 1) * N + rr];
+    int pick = 0;
+    for (int b = 0; b <= 32; ++b) {
+      if (!used[size_t(gi) * 33 + b]) continue;
+      const int c = cost[size_t(gi) * 33 + b];
+      if (c <= rr && prev[rr - c] + saved_of[size_t(gi) * 33 + b] == want) {
+        pick = b;
+        break;
+      }
+    }
+    for (int s2 : groups[gi]) res.plan[s2] = pick;
+    rr -= cost[size_t(gi) * 33 + pick];
   }
   return res;
 }
@@ -177,50 +219,65 @@ static PlanResult plan_br(const PlanTables &t, double bitrate, const int *limit,
   }
   int64_t ub = std::max<int64_t>(1, (budget + G_UNITS - 1) / G_UNITS);
   int64_t cap = budget / ub;
+  const int N = int(cap + 1);
   double r = rounding_step(t, t.maxabs);
   const double INF = std::numeric_limits<double>::infinity();
   const std::vector<std::vector<int>> groups = plan_groups(t, per_level);
   const int NG = int(groups.size());
-  std::vector<double> F(cap + 1, 0.0), nF(cap + 1);
-  std::vector<uint8_t> choice(size_t(NG) * (cap + 1), 0);
+  // tables F_0 .. F_NG: F_0 = 0, unreachable cells infinite
+  std::vector<double> F(size_t(NG + 1) * N, INF);
+  std::fill(F.begin(), F.begin() + N, 0.0);
   std::vector<int64_t> lcs(size_t(NG) * 33, 0);
+  std::vector<double> tvs(size_t(NG) * 33, 0.0);
+  std::vector<uint8_t> used(size_t(NG) * 33, 0);
   for (int gi = 0; gi < NG; ++gi) {
     const std::vector<int> &g = groups[gi];
-    std::fill(nF.begin(), nF.end(), INF);
-    uint8_t *ch = &choice[size_t(gi) * (cap + 1)];
+    const double *prev = &F[size_t(gi) * N];
+    double *cur = &F[size_t(gi + 1) * N];
     int hi = allowed_hi(t, g, limit);
-    int64_t prev_lc = -1;
-    double prev_tv = -1.0;
+    // least term so far among choices loading exactly `plateau` byte units
+    // (loaded units never increase with b)
+    int64_t plateau = -1;
+    double plateau_tv = 0.0;
     for (int b = 0; b <= hi; ++b) {
       const int64_t lc = (group_bytes(t, g, b, 32) + ub - 1) / ub;
       const double tv = group_term(t, g, b, r);
       lcs[size_t(gi) * 33 + b] = lc;
+      tvs[size_t(gi) * 33 + b] = tv;
       if (lc > cap) continue;
-      // the same (bytes, term) as the choice before: it can only tie with
-      // it, and ties go to the smaller b
-      if (lc == prev_lc && tv == prev_tv) continue;
-      prev_lc = lc;
-      prev_tv = tv;
-      for (int64_t rr = lc; rr <= cap; ++rr) {
-        double cand = F[rr - lc] + tv;
-        if (cand < nF[rr]) {
-          nF[rr] = cand;
-          ch[rr] = uint8_t(b);
-        }
+      if (lc == plateau) {
+        // an earlier (smaller) b loads as little for no larger term
+        if (tv >= plateau_tv) continue;
+        plateau_tv = tv;
+      } else {
+        plateau = lc;
+        plateau_tv = tv;
       }
+      used[size_t(gi) * 33 + b] = 1;
+      min_shift_add(cur, prev, N, int(lc), tv);
     }
-    F.swap(nF);
   }
-  if (!std::isfinite(F[cap])) {
+  if (!std::isfinite(F[size_t(NG) * N + cap])) {
     res.plan.assign(limit, limit + P);
     res.flags = IPC_FLAG_NOOP;
     return res;
   }
   int64_t rr = cap;
   for (int gi = NG - 1; gi >= 0; --gi) {
-    int b = choice[size_t(gi) * (cap + 1) + rr];
-    for (int s : groups[gi]) res.plan[s] = b;
-    rr -= lcs[size_t(gi) * 33 + b];
+    const double *prev = &F[size_t(gi) * N];
+    const double want = F[size_t(gi + 1) * N + rr];
+    int pick = -1;
+    for (int b = 0; b <= 32; ++b) {
+      if (!used[size_t(gi) * 33 + b]) continue;
+      const int64_t lc = lcs[size_t(gi) * 33 + b];
+      if (lc <= rr && prev[rr - lc] + tvs[size_t(gi) * 33 + b] == want) {
+        pick = b;
+        break;
+      }
+    }
+    if (pick < 0) pick = 0;  // not reached: the table's value came from some choice
+    for (int s2 : groups[gi]) res.plan[s2] = pick;
+    rr -= lcs[size_t(gi) * 33 + pick];
   }
   return res;
 }

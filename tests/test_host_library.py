@@ -116,6 +116,41 @@ def test_refine_planner_matches_oracle():
             assert (cb, cf, cl) == (bound, flags, loaded)
 
 
+def test_planner_matches_oracle_on_tie_heavy_streams():
+    """Streams whose tables hold many equal costs and byte counts (blocky,
+    piecewise-constant fields; a smooth ramp), where the programs' tie rule
+    decides the plan."""
+    _lib_or_skip()
+    rng = np.random.default_rng(3)
+    coarse = rng.integers(-4, 5, size=(5, 6, 7)).astype(np.float64)
+    blocky = np.repeat(np.repeat(np.repeat(coarse, 4, 0), 4, 1), 4, 2)[:17, :21, :25].copy()
+    ramp = np.add.outer(np.arange(33.0), np.arange(40.0)) * 0.25
+    steps = np.floor(fieldgen.random_field((200,), seed=4, dtype=np.float64) * 3.0)
+    bufs = [codec.compress(blocky, 0.05, interp=predict.CUBIC),
+            codec.compress(blocky.astype(np.float32), 1e-3, interp=predict.LINEAR),
+            codec.compress(ramp, 1e-4, interp=predict.CUBIC),
+            codec.compress(steps, 1e-2, interp=predict.CUBIC)]
+    for buf in bufs:
+        _, _, t = codec.open_stream(buf)
+        scale = max(t.maxabs, 1e-12)
+        for E in [t.eb * f for f in (1.0, 1.01, 1.5, 2.0, 3.0, 10.0, 100.0)] + [scale * 2.0]:
+            for lim in (None, [int(v) for v in rng.integers(0, 33, t.n_passes)]):
+                if lim is not None:
+                    lim = [v if t.progressive[i] else 0 for i, v in enumerate(lim)]
+                plan, bound, flags, loaded, _ = _oracle_plan(buf, "eb", E, lim)
+                cplan, cb, cf, cl = pkg.plan_host(buf, eb=E, limit=lim)
+                assert cplan[:t.n_passes] == plan, (E, lim)
+                assert (cb, cf, cl) == (bound, flags, loaded)
+        for br in (0.05, 0.2, 0.5, 1.0, 2.0, 3.0, 6.0, 12.0):
+            for lim in (None, [int(v) for v in rng.integers(0, 33, t.n_passes)]):
+                if lim is not None:
+                    lim = [v if t.progressive[i] else 0 for i, v in enumerate(lim)]
+                plan, bound, flags, loaded, _ = _oracle_plan(buf, "bitrate", br, lim)
+                cplan, cb, cf, cl = pkg.plan_host(buf, bitrate=br, limit=lim)
+                assert cplan[:t.n_passes] == plan, (br, lim)
+                assert (cb, cf, cl) == (bound, flags, loaded)
+
+
 def test_parser_rejects_corruption():
     _lib_or_skip()
     buf = _streams()[0]
