@@ -166,6 +166,23 @@ ipc_status ipc_retrieve(ipc_ctx *ctx, const ipc_stream *s, ipc_target target, ip
 /* Same, with an explicit plan (planes discarded per pass, n_passes entries). */
 ipc_status ipc_retrieve_plan(ipc_ctx *ctx, const ipc_stream *s, const uint8_t *plan,
                              uint32_t n_passes, ipc_state **out, ipc_info *info);
+/* Retrieval for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * reconstruction of ipc_retrieve (same plan, same bytes) written into the
+ * caller's `field_dev` (capacity bytes, at least n * itemsize, C order, the
+ * stream's dtype), with no state created and no device allocation of any
+ * kind.  The fused 3-D path keeps its compact coarse grids in a library
+ * scratch array of IPC_NOALLOC_SCRATCH_BYTES bytes per device, held from the
+ * first context on that device until the process ends; a stream whose coarse
+ * grids need more (about n * itemsize / 7, so 3-D fields above roughly
+ * 2^25 float32 or 2^24 float64 points) is refused with IPC_EINVAL before any
+ * device work.  Other shapes need no scratch.  Every call on a device shares
+ * its scratch: calls that overlap on one device (several contexts or host
+ * threads) race and must be serialized by the caller.  `info` may be NULL;
+ * on an error `field_dev` may be partly written. */
+#define IPC_NOALLOC_SCRATCH_BYTES (16u << 20)
+ipc_status ipc_retrieve_noalloc(ipc_ctx *ctx, const ipc_stream *s, ipc_target target,
+                                void *field_dev, uint64_t capacity, ipc_info *info);
 /* Device pointer to the state's reconstructed field (C order, the stream's
  * dtype); valid until the next ipc_refine on the state or ipc_state_free. */
 const void *ipc_state_field(const ipc_state *st);

@@ -81,6 +81,8 @@ SIGNATURES = {
     "ipc_retrieve": (c_int, [c_void_p, c_void_p, ipc_target, P(c_void_p), P(ipc_info)]),
     "ipc_retrieve_plan": (c_int, [c_void_p, c_void_p, P(c_uint8), c_uint32, P(c_void_p),
                                   P(ipc_info)]),
+    "ipc_retrieve_noalloc": (c_int, [c_void_p, c_void_p, ipc_target, c_void_p, c_uint64,
+                                     P(ipc_info)]),
     "ipc_state_field": (c_void_p, [c_void_p]),
     "ipc_state_copy_field": (c_int, [c_void_p, c_void_p, c_void_p, c_uint64]),
     "ipc_refine": (c_int, [c_void_p, c_void_p, ipc_target, P(ipc_info)]),
@@ -438,6 +440,18 @@ class Stream:
         _check(lib().ipc_retrieve(self.ctx.handle, self._p, _target(eb, bitrate, level_groups),
                                   ctypes.byref(out), ctypes.byref(info)), self.ctx.handle)
         return State(self, out, info)
+
+    def retrieve_noalloc(self, out, eb=None, bitrate=None) -> ipc_info:
+        """ipc_retrieve_noalloc: the reconstruction written into `out` (a
+        contiguous device tensor of the stream's shape and dtype), with no
+        device allocation; returns the call's ipc_info."""
+        if not out.is_contiguous() or out.dtype != self.dtype or tuple(out.shape) != tuple(self.shape):
+            raise ValueError("out must be a contiguous tensor of the stream's shape and dtype")
+        info = ipc_info()
+        _check(lib().ipc_retrieve_noalloc(self.ctx.handle, self._p, _target(eb, bitrate),
+                                          c_void_p(out.data_ptr()), out.numel() * out.element_size(),
+                                          ctypes.byref(info)), self.ctx.handle)
+        return info
 
     def retrieve_plan(self, plan: Sequence[int]) -> "State":
         out = c_void_p()

@@ -76,6 +76,9 @@ struct ipc_ctx {
   void *host_summary = nullptr;         // pinned copy of the compression summary
   size_t host_summary_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // this device's copy of the no-allocation scratch (null if it could not be
+  // resolved; ipc_retrieve_noalloc then fails with IPC_EHIP)
+  void *scratch = nullptr;
   // per-pass timing
   bool profiling = false;
   std::vector<hipEvent_t> pev;   // 2 per pass
@@ -122,11 +125,36 @@ struct ipc_state {
 
 // ------------------------------------------------------------------ helpers
 
+// Scratch of ipc_retrieve_noalloc: the compact coarse grids of a fused 3-D
+// retrieval.  Every device the library runs on holds its own copy until the
+// process ends.  In host code the array's name is not a device address: the
+// device's copy is resolved once per device (device_scratch) and only that
+// pointer is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[IPC_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 struct Fail {
   ipc_status st;
 };
+
+// The address of `scratch` on `device`, which must be the current device;
+// resolved on the first call per device and kept.  Null if it cannot be
+// resolved.
+void *device_scratch(int device) {
+  static std::mutex mu;
+  static std::map<int, void *> ptrs;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = ptrs.find(device);
+  if (it != ptrs.end()) return it->second;
+  void *p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;  // not kept: a later context tries again
+  }
+  ptrs[device] = p;
+  return p;
+}
 
 // A named range on the ROCTx marker stream for the span of a library call
 // (seen by rocprofv3 --marker-trace; nearly free when no tool listens)
@@ -568,11 +596,18 @@ Level3Args level_args(const ipc_ctx *ctx, const StreamMeta &m, int l, bool compr
   return La;
 }
 
-// compact coarse-grid buffers: G_j lives in ws_g[j & 1]
-void ensure_coarse(ipc_ctx *ctx, const Schedule &s, size_t isz) {
-  size_t need[2] = {0, 0};
+// Bytes of the compact coarse grids G_j of a fused retrieval by level parity
+// (G_j lives in buffer j & 1)
+void coarse_need(const Schedule &s, size_t isz, size_t need[2]) {
+  need[0] = need[1] = 0;
   for (int j = 1; j <= s.K; ++j)
     need[j & 1] = std::max(need[j & 1], size_t(coarse_points(s, j)) * isz);
+}
+
+// compact coarse-grid buffers: G_j lives in ws_g[j & 1]
+void ensure_coarse(ipc_ctx *ctx, const Schedule &s, size_t isz) {
+  size_t need[2];
+  coarse_need(s, isz, need);
   for (int i = 0; i < 2; ++i)
     ensure_ws(ctx, ctx->ws_g[i], ctx->ws_g_bytes[i], std::max<size_t>(need[i], 8));
 }
@@ -592,20 +627,30 @@ RetrieveIn retrieve_in(ipc_ctx *ctx, const ipc_stream *s) {
   return in;
 }
 
-// run passes [s0, P) of a retrieval into `field`
+// run passes [s0, P) of a retrieval into `field`; the fused path keeps its
+// coarse grids in `ws` (two buffers by level parity) when given, else in the
+// context's workspace
 void run_retrieve(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &plan, int s0,
-                  void *field) {
+                  void *field, void *const *ws = nullptr) {
   const RetrieveIn in = retrieve_in(ctx, s);
   prof_begin(ctx, s->args.size());
   const Schedule &sc = s->meta.sched;
   if (fused3(sc)) {
     const size_t isz = s->meta.dtype == IPC_F32 ? 4 : 8;
-    ensure_coarse(ctx, sc, isz);
+    void *g[2];
+    if (ws) {
+      g[0] = ws[0];
+      g[1] = ws[1];
+    } else {
+      ensure_coarse(ctx, sc, isz);
+      g[0] = ctx->ws_g[0];
+      g[1] = ctx->ws_g[1];
+    }
     int l_start = sc.K;
     if (s0 <= 0) {
       Level3Args A = anchor3_args(sc);
       prof_mark(ctx, 0, true);
-      hip_check(ctx, launch_anchor3_retrieve(s->meta.dtype, A, ctx->ws_g[sc.K & 1], in, s->meta.eb,
+      hip_check(ctx, launch_anchor3_retrieve(s->meta.dtype, A, g[sc.K & 1], in, s->meta.eb,
                                              ctx->stream),
                 "anchor kernel launch");
       prof_mark(ctx, 0, false);
@@ -615,7 +660,7 @@ void run_retrieve(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &pla
       int64_t gd[3];
       for (int j = 0; j < 3; ++j) gd[j] = ((sc.dims3[j] - 1) >> l_start) + 1;
       hip_check(ctx, launch_gather_coarse(s->meta.dtype, field, sc.dims3, int64_t(1) << l_start,
-                                          ctx->ws_g[l_start & 1], gd, ctx->stream),
+                                          g[l_start & 1], gd, ctx->stream),
                 "gather kernel launch");
     }
     for (int l = l_start; l >= 1; --l) {
@@ -624,8 +669,8 @@ void run_retrieve(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &pla
       for (int p = 0; p < 3; ++p) disc[p] = plan[La.pass_index[p]];
       int pc = int(La.pass_index[2]);
       prof_mark(ctx, pc, true);
-      hip_check(ctx, launch_level3_retrieve(s->meta.dtype, s->meta.interp, La, ctx->ws_g[l & 1],
-                                            l > 1 ? ctx->ws_g[(l - 1) & 1] : field, disc, in,
+      hip_check(ctx, launch_level3_retrieve(s->meta.dtype, s->meta.interp, La, g[l & 1],
+                                            l > 1 ? g[(l - 1) & 1] : field, disc, in,
                                             s->meta.eb, ctx->stream),
                 "level kernel launch");
       prof_mark(ctx, pc, false);
@@ -1463,6 +1508,8 @@ ipc_status ipc_ctx_create(int device, void *hip_stream, ipc_ctx **out) {
     delete c;
     return IPC_EHIP;
   }
+  // with the device current: its copy of the no-allocation scratch
+  c->scratch = device_scratch(device);
   *out = c;
   return IPC_OK;
 }
@@ -1965,6 +2012,66 @@ ipc_status ipc_retrieve_plan(ipc_ctx *ctx, const ipc_stream *s, const uint8_t *p
   double b0 = plan_bound(s->tables, p, s->tables.maxabs);
   double bound = plan_bound(s->tables, p, 2.0 * (s->tables.maxabs + b0));
   return retrieve_common(ctx, s, p, bound, 0, 0.0f, out, info);
+}
+
+ipc_status ipc_retrieve_noalloc(ipc_ctx *ctx, const ipc_stream *s, ipc_target target,
+                                void *field_dev, uint64_t capacity, ipc_info *info) {
+  TraceRange trace_range("ipc_retrieve_noalloc");
+  if (!ctx || !s || !field_dev) return IPC_EINVAL;
+  if (s->ctx != ctx) {
+    set_err(ctx, "stream belongs to another context");
+    return IPC_ESTATE;
+  }
+  if (!valid_target(target)) {
+    set_err(ctx, "target value must be finite and > 0");
+    return IPC_EINVAL;
+  }
+  const Schedule &sc = s->meta.sched;
+  const size_t isz = s->meta.dtype == IPC_F32 ? 4 : 8;
+  if (capacity < uint64_t(sc.n_points) * isz) {
+    set_err(ctx, "output capacity below the field's size");
+    return IPC_EINVAL;
+  }
+  void *ws[2] = {nullptr, nullptr};
+  if (fused3(sc)) {
+    if (!ctx->scratch) {
+      set_err(ctx, "the device's scratch array could not be resolved");
+      return IPC_EHIP;
+    }
+    size_t need[2];
+    coarse_need(sc, isz, need);
+    const size_t off1 = (need[0] + 255) & ~size_t(255);
+    if (off1 + need[1] > size_t(IPC_NOALLOC_SCRATCH_BYTES)) {
+      set_err(ctx, "coarse grids need " + std::to_string(off1 + need[1]) +
+                       " bytes, above the scratch of " +
+                       std::to_string(size_t(IPC_NOALLOC_SCRATCH_BYTES)) + " bytes");
+      return IPC_EINVAL;
+    }
+    ws[0] = ctx->scratch;
+    ws[1] = static_cast<char *>(ctx->scratch) + off1;
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  PlanResult pr = plan_request(s->tables, target.kind, target.value, nullptr);
+  float tplan = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  // per-pass timing would create events: off for this call
+  struct ProfilingOff {
+    ipc_ctx *c;
+    bool was;
+    ~ProfilingOff() { c->profiling = was; }
+  } prof_off{ctx, ctx->profiling};
+  ctx->profiling = false;
+  return guarded(ctx, [&] {
+    enter_device(ctx);
+    hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
+    run_retrieve(ctx, s, pr.plan, 0, field_dev, ws);
+    hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
+    hip_check(ctx, hipStreamSynchronize(ctx->stream), "retrieve");
+    prof_end(ctx);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    std::vector<int> none(pr.plan.size(), 32);
+    fill_info(s, pr.plan, pr.bound, pr.flags, plane_bytes_between(s, pr.plan, none), tplan, ms, info);
+  });
 }
 
 const void *ipc_state_field(const ipc_state *st) { return st ? st->field.p : nullptr; }
