@@ -202,7 +202,7 @@ def main():
         st.free()
     # a partial target (1e-3 * range): the planner's program runs
     part = {}
-    for rel_t in (1e-3,):
+    for rel_t in ((1e-3,) if L > 0 else ()):
         e_t = rel_t * rng
         lp, pp = [], []
         for _ in range(L):

@@ -110,13 +110,38 @@ ipc_status ipc_ctx_set_stream(ipc_ctx *ctx, void *hip_stream);
 ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dims, int ndim,
                         int dtype, double abs_eb, const ipc_options *opts, ipc_stream **out);
 
+/* What a stream reconstructs (the field of the problem statement, Sec.
+ * 3.1.2) and how it was compressed. */
+typedef struct {
+  int32_t ndim;            /* 1..3 */
+  int32_t dtype;           /* ipc_dtype */
+  uint64_t dims[3];        /* C order, dims[0] slowest; the first ndim used */
+  int32_t interp;          /* ipc_interp */
+  int32_t nonprog_levels;  /* top levels always fully loaded (L_p of Alg. 1) */
+  double abs_eb;           /* compression bound (Sec. 4.2.2) */
+  uint32_t n_passes;       /* anchors + one per level and dimension */
+  int32_t coding;          /* 0 raw blocks, 1 entropy-coded blocks */
+} ipc_stream_desc;
+/* Fill `out` from the stream's header; IPC_EINVAL on a null argument. */
+ipc_status ipc_stream_describe(const ipc_stream *s, ipc_stream_desc *out);
+
 /* Serialized size of a stream in bytes (the compressed size). */
 ipc_status ipc_stream_size(const ipc_stream *s, uint64_t *bytes);
-/* Write the serialized stream to host memory `dst` of `capacity` bytes. */
+/* Write the serialized stream -- the independent blocks of Fig.
+ * overall-design, one per bitplane of each chunk, after the fixed tables -- to
+ * host memory `dst` of `capacity` bytes (at least ipc_stream_size).
+ * IPC_EINVAL when it is smaller. */
 ipc_status ipc_stream_to_host(ipc_ctx *ctx, const ipc_stream *s, void *dst, uint64_t capacity);
-/* Make a device-resident stream from serialized bytes (validated:
- * IPC_ECORRUPT on any inconsistency). */
-ipc_status ipc_stream_from_host(ipc_ctx *ctx, const void *src, uint64_t bytes, ipc_stream **out);
+/* Make a stream from serialized bytes (validated: IPC_ECORRUPT on any
+ * inconsistency, IPC_EUNSUPPORTED for a chunk shape the kernels do not take;
+ * `src` is only read during the call).  Tables, masks and outliers always go
+ * to the device.  device_resident = 1: the bitplanes too.  device_resident =
+ * 0: the bitplanes stay in pinned host memory that the kernels read in place,
+ * so a retrieval or refinement moves only the planes its plan loads across
+ * the host link (the progressive retrieval of Sec. 3.1.2 from a store that
+ * keeps the whole stream; slower than device-resident planes). */
+ipc_status ipc_stream_from_host(ipc_ctx *ctx, const void *src, uint64_t bytes, int device_resident,
+                                ipc_stream **out);
 void ipc_stream_free(ipc_stream *s);
 
 /* Entropy stage for the stored bitplane blocks (stands in for the paper's
@@ -183,8 +208,9 @@ ipc_status ipc_retrieve_plan(ipc_ctx *ctx, const ipc_stream *s, const uint8_t *p
 #define IPC_NOALLOC_SCRATCH_BYTES (16u << 20)
 ipc_status ipc_retrieve_noalloc(ipc_ctx *ctx, const ipc_stream *s, ipc_target target,
                                 void *field_dev, uint64_t capacity, ipc_info *info);
-/* Device pointer to the state's reconstructed field (C order, the stream's
- * dtype); valid until the next ipc_refine on the state or ipc_state_free. */
+/* Device pointer to the state's reconstructed field x~ of Alg. 1 (C order,
+ * the stream's dtype), owned by the state; valid until ipc_state_free, and
+ * updated in place by ipc_refine (Alg. 2). */
 const void *ipc_state_field(const ipc_state *st);
 /* Stream-ordered device-to-device copy of the state's field into `dst_dev`
  * (capacity bytes, at least n * itemsize). */

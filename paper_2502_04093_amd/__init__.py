@@ -57,6 +57,13 @@ class ipc_pass_info(ctypes.Structure):
                 ("launch_pass", c_uint32)]
 
 
+class ipc_stream_desc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("dims", ctypes.c_uint64 * 3), ("interp", ctypes.c_int32),
+                ("nonprog_levels", ctypes.c_int32), ("abs_eb", ctypes.c_double),
+                ("n_passes", ctypes.c_uint32), ("coding", ctypes.c_int32)]
+
+
 class ipc_request(ctypes.Structure):
     _fields_ = [("stream", c_void_p), ("state", c_void_p), ("target", ipc_target),
                 ("refine", ctypes.c_int32), ("status", ctypes.c_int32), ("info", ipc_info)]
@@ -70,8 +77,9 @@ SIGNATURES = {
     "ipc_compress": (c_int, [c_void_p, c_void_p, P(c_uint64), c_int, c_int, c_double,
                              P(ipc_options), P(c_void_p)]),
     "ipc_stream_size": (c_int, [c_void_p, P(c_uint64)]),
+    "ipc_stream_describe": (c_int, [c_void_p, P(ipc_stream_desc)]),
     "ipc_stream_to_host": (c_int, [c_void_p, c_void_p, c_void_p, c_uint64]),
-    "ipc_stream_from_host": (c_int, [c_void_p, c_void_p, c_uint64, P(c_void_p)]),
+    "ipc_stream_from_host": (c_int, [c_void_p, c_void_p, c_uint64, c_int, P(c_void_p)]),
     "ipc_stream_free": (None, [c_void_p]),
     "ipc_stream_entropy_code": (c_int, [c_void_p, c_void_p]),
     "ipc_refine_additive": (c_int, [c_void_p, c_void_p, ipc_target, P(ipc_info)]),
@@ -359,20 +367,14 @@ class Context:
                 out.append((st, r.info, r.status))
         return out
 
-    def stream_from_bytes(self, data: bytes, shape=None, dtype=None) -> "Stream":
-        import numpy as np
-        import torch
+    def stream_from_bytes(self, data: bytes, device_resident: bool = True) -> "Stream":
+        """ipc_stream_from_host; device_resident=False keeps the bitplanes in
+        pinned host memory that retrievals read in place."""
         out = c_void_p()
         buf = ctypes.create_string_buffer(bytes(data), len(data))
-        _check(lib().ipc_stream_from_host(self._p, buf, len(data), ctypes.byref(out)), self._p)
-        if shape is None or dtype is None:
-            import struct
-            dcode, nd = data[8], data[9]
-            dims = struct.unpack("<3Q", data[16:40])[:nd]
-            shape = tuple(int(d) for d in dims)
-            dtype = torch.float32 if dcode == 0 else torch.float64
-        _ = np
-        return Stream(self, out, shape, dtype)
+        _check(lib().ipc_stream_from_host(self._p, buf, len(data), int(bool(device_resident)),
+                                          ctypes.byref(out)), self._p)
+        return Stream.from_handle(self, out)
 
 
 class Stream:
@@ -381,6 +383,26 @@ class Stream:
     def __init__(self, ctx: Context, p, shape, dtype):
         self.ctx, self._p, self.shape, self.dtype = ctx, p, shape, dtype
         ctx._streams.add(self)
+
+    @classmethod
+    def from_handle(cls, ctx: Context, p) -> "Stream":
+        """A Stream for a library handle, its shape and dtype from
+        ipc_stream_describe."""
+        import torch
+        d = ipc_stream_desc()
+        _check(lib().ipc_stream_describe(p, ctypes.byref(d)))
+        shape = tuple(int(d.dims[j]) for j in range(d.ndim))
+        return cls(ctx, p, shape, torch.float32 if d.dtype == IPC_F32 else torch.float64)
+
+    def describe(self) -> dict:
+        """ipc_stream_describe as a dict."""
+        d = ipc_stream_desc()
+        _check(lib().ipc_stream_describe(self._p, ctypes.byref(d)))
+        return {"shape": tuple(int(d.dims[j]) for j in range(d.ndim)),
+                "dtype": "f32" if d.dtype == IPC_F32 else "f64",
+                "interp": "cubic" if d.interp == IPC_CUBIC else "linear",
+                "nonprog_levels": int(d.nonprog_levels), "abs_eb": float(d.abs_eb),
+                "n_passes": int(d.n_passes), "coding": int(d.coding)}
 
     def free(self):
         if getattr(self, "_p", None):
@@ -490,6 +512,27 @@ class State:
 
     def field_ptr(self) -> int:
         return lib().ipc_state_field(self._p)
+
+    def view(self):
+        """The reconstruction as a torch tensor that aliases the state's own
+        device memory (no copy, through __cuda_array_interface__).  It is
+        valid until the next refine of this state or its free, and refine
+        updates it in place; the tensor keeps this State object alive."""
+        import torch
+
+        state = self
+
+        class _Field:
+            @property
+            def __cuda_array_interface__(self):
+                return {"shape": tuple(state.stream.shape),
+                        "typestr": "<f4" if state.stream.dtype == torch.float32 else "<f8",
+                        "data": (int(state.field_ptr()), False), "version": 3, "strides": None}
+
+        holder = _Field()
+        t = torch.as_tensor(holder, device=f"cuda:{self.stream.ctx.device}")
+        t._ipc_state = self  # the state outlives the view
+        return t
 
     def tensor(self):
         """A copy of the reconstruction as a torch tensor on the device."""

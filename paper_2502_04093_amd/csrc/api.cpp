@@ -105,6 +105,7 @@ struct ipc_stream {
   StreamMeta meta;
   PlanTables tables;
   bool packed = false;         // payload placement
+  bool host_payload = false;   // payload in pinned host memory the device reads
   DevBuf payload;              // u32 words
   DevBuf masks;                // u32 per chunk
   DevBuf chunk_off;            // u64 per chunk (packed placement only)
@@ -373,6 +374,11 @@ ipc_status guarded(ipc_ctx *ctx, F &&f) {
 
 void free_stream_bufs(ipc_stream *s) {
   ipc_ctx *c = s->ctx;
+  if (s->host_payload) {
+    if (s->payload.p) (void)hipHostFree(s->payload.p);
+    s->payload = DevBuf();
+    s->host_payload = false;
+  }
   dev_free(c, s->payload);
   dev_free(c, s->masks);
   dev_free(c, s->chunk_off);
@@ -1768,7 +1774,8 @@ ipc_status ipc_stream_to_host(ipc_ctx *ctx, const ipc_stream *sc, void *dst, uin
     try {
       const void *src = m.coding ? s->coded.p : packed_payload(ctx, s, tmp, tmp_off);
       if (pbytes)
-        hip_check(ctx, hipMemcpyAsync(d + poff, src, pbytes, hipMemcpyDeviceToHost, ctx->stream), "copy");
+        // (the raw planes may sit in pinned host memory: the direction is inferred)
+        hip_check(ctx, hipMemcpyAsync(d + poff, src, pbytes, hipMemcpyDefault, ctx->stream), "copy");
       hip_check(ctx, hipStreamSynchronize(ctx->stream), "copy");
     } catch (...) {
       dev_free(ctx, tmp);
@@ -1844,7 +1851,8 @@ ipc_status ipc_stream_coding(const ipc_stream *s, int *coding) {
   return IPC_OK;
 }
 
-ipc_status ipc_stream_from_host(ipc_ctx *ctx, const void *src, uint64_t bytes, ipc_stream **out) {
+ipc_status ipc_stream_from_host(ipc_ctx *ctx, const void *src, uint64_t bytes, int device_resident,
+                                ipc_stream **out) {
   TraceRange trace_range("ipc_stream_from_host");
   if (!out) return IPC_EINVAL;
   *out = nullptr;
@@ -1870,7 +1878,8 @@ ipc_status ipc_stream_from_host(ipc_ctx *ctx, const void *src, uint64_t bytes, i
     for (const PassGeom &p : m.sched.passes) s->args.push_back(make_args(m.sched, p));
     std::vector<uint64_t> off;
     packed_chunk_offsets(m, off);
-    s->payload = dev_alloc(ctx, std::max<size_t>(4, m.payload_words * 4));
+    const size_t pbytes = std::max<size_t>(4, m.payload_words * 4);
+    s->payload = dev_alloc(ctx, pbytes);
     s->masks = dev_alloc(ctx, std::max<size_t>(4, m.masks.size() * 4));
     s->chunk_off = dev_alloc(ctx, off.size() * 8);
     if (m.coding) {
@@ -1913,6 +1922,25 @@ ipc_status ipc_stream_from_host(ipc_ctx *ctx, const void *src, uint64_t bytes, i
     hip_check(ctx, hipMemcpyAsync(s->masks.p, m.masks.data(), m.masks.size() * 4, hipMemcpyHostToDevice, ctx->stream), "upload");
     hip_check(ctx, hipMemcpyAsync(s->chunk_off.p, off.data(), off.size() * 8, hipMemcpyHostToDevice, ctx->stream), "upload");
     hip_check(ctx, hipStreamSynchronize(ctx->stream), "upload");
+    if (!device_resident) {
+      // the raw planes move to pinned host memory that the kernels read in
+      // place: a retrieval moves only the planes its plan loads over the bus
+      void *hp = nullptr;
+      if (hipHostMalloc(&hp, pbytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(ctx, "pinned host allocation of " + std::to_string(pbytes) + " bytes failed");
+        throw Fail{IPC_ENOMEM};
+      }
+      hipError_t ce = hipMemcpy(hp, s->payload.p, pbytes, hipMemcpyDeviceToHost);
+      if (ce != hipSuccess) {
+        (void)hipHostFree(hp);
+        hip_check(ctx, ce, "payload to host");
+      }
+      dev_free(ctx, s->payload);
+      s->payload.p = hp;
+      s->payload.bytes = pbytes;
+      s->host_payload = true;
+    }
     s->tables = plan_tables(m);
     upload_outliers(ctx, s);
   });
@@ -2117,6 +2145,21 @@ ipc_status ipc_stream_pass_info(const ipc_stream *s, uint32_t pass, ipc_pass_inf
   out->launch_pass = pass;
   if (fused3(s->meta.sched) && g.level >= 1)
     out->launch_pass = uint32_t(1 + (s->meta.sched.K - g.level) * 3 + 2);
+  return IPC_OK;
+}
+
+ipc_status ipc_stream_describe(const ipc_stream *s, ipc_stream_desc *out) {
+  if (!s || !out) return IPC_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  const StreamMeta &m = s->meta;
+  out->ndim = m.sched.D;
+  out->dtype = m.dtype;
+  for (int j = 0; j < m.sched.D && j < 3; ++j) out->dims[j] = uint64_t(m.sched.dims[j]);
+  out->interp = m.interp;
+  out->nonprog_levels = m.nonprog_levels;
+  out->abs_eb = m.eb;
+  out->n_passes = uint32_t(s->args.size());
+  out->coding = m.coding;
   return IPC_OK;
 }
 

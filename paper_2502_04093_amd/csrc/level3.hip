@@ -14,10 +14,18 @@
 // Passes A and B are also evaluated on a halo (even rows y0-2, y0+16, y0+18
 // and even columns x0-2, x0+64, x0+66) that neighbouring columns own; those
 // values are recomputed from the same inputs, so workgroups never wait on each
-// other.  Codes of the workgroup's own targets are buffered in LDS for two
-// steps; 112 threads then turn rows of 32 codes into plane words (or back)
-// with an in-register 32x32 bit transpose (Sec. 4.3).  Compression also
-// accumulates the delta-y maxima of Thm. 1 from the buffered codes.
+// other.  Codes of the workgroup's own targets are buffered in LDS; one wave
+// turns rows of 32 codes into plane words with an in-register bit transpose
+// (Sec. 4.3), and in retrieval two waves turn the step's own and halo plane
+// words back into codes.  Compression also accumulates the delta-y maxima of
+// Thm. 1 from the buffered codes.
+//
+// Retrieval keeps its register count within five waves per SIMD: everything
+// that follows from the thread index is worked out per step rather than held,
+// a plane word's chunk advances by a fixed stride per step, passes B and C take
+// two targets per thread from five neighbours, and pass C writes four finished
+// points of the level grid per thread straight from its registers.  Code and
+// outlier buffers alternate by step parity, so a step ends without a barrier.
 //
 // Tile-local arithmetic is 32-bit (the host limits extents to 2^24);
 // only offsets into global arrays are 64-bit.  Per target the arithmetic is
@@ -307,19 +315,20 @@ __device__ __forceinline__ uint32_t fetch_code(const Level3Args &L, const Retrie
 // outliers of one chunk kept in LDS for a step (more are looked up in HBM)
 constexpr int OCAP = 8;
 
-// LDS of a retrieval workgroup
+// LDS of a retrieval workgroup.  Codes and outlier slots alternate between
+// two buffers by step parity, so the next step's fetch never waits for this
+// step's last pass.
 template <typename T>
 struct Shared3 {
   T ring[4][NYE][NXP];      // coarse planes m-1 .. m+2 (even rows x even columns, halo'd)
   T wa[NYE][NXP];           // pass A values of the step's odd plane (halo'd)
   T wb[2][8][NXP];          // pass B values of both planes (odd rows, halo'd columns)
-  T wc[2][16][32];          // pass C values (odd columns)
   uint32_t hva[NYE][NXP];   // codes of pass-A halo targets
   uint32_t hvb[2][8][4];    // codes of pass-B halo targets
-  uint32_t codes[PADA + PADB + PADC];
-  uint32_t orng[13][2];     // outlier ranges of the step's chunks
-  uint32_t oloc[13][OCAP];  // their entries, when a chunk holds at most OCAP
-  uint64_t obits[13][OCAP];
+  uint32_t codes[2][PADA + PADB + PADC];
+  uint32_t orng[2][13][2];     // outlier ranges of the step's chunks
+  uint32_t oloc[2][13][OCAP];  // their entries, when a chunk holds at most OCAP
+  uint64_t obits[2][13][OCAP];
 };
 
 // inputs of a compression step: the tile (both planes), then the halo targets
@@ -349,6 +358,16 @@ struct SharedC {
 // code buffers of one step (retrieval): pass A, B, C
 __device__ __forceinline__ int code_off1(int p) { return p == 0 ? 0 : (p == 1 ? PADA : PADA + PADB); }
 
+
+// The thread's role index.  Waves of a workgroup do different amounts of
+// work (wave 0 carries the plane coding, the halo targets fall on the first
+// waves), and every workgroup's wave i tends to land on the same SIMD of its
+// compute unit; rotating the roles by the workgroup index spreads the heavy
+// waves over the SIMDs.  The rotation is by whole waves, so lane numbers and
+// wave-wide operations are unchanged.
+__device__ __forceinline__ int role_thread() {
+  return int((threadIdx.x + 64u * (blockIdx.x & 3u)) & 255u);
+}
 
 // Tile (tx, ty) and column segment zs of this workgroup.  Consecutive
 // workgroup ids are dealt round-robin to the 8 XCDs; renumbering them so that
@@ -622,7 +641,7 @@ __device__ __forceinline__ void level3_compress_body(const Level3Args &L, const 
   double eb = eb_arg;
   T two_eb = two_eb_arg, inv = inv_arg, qmax = qmax_arg;
   asm volatile("" : "+v"(eb), "+v"(two_eb), "+v"(inv), "+v"(qmax));
-  const int tid0 = threadIdx.x;
+  const int tid0 = role_thread();
   const int x0 = tx * TX, y0 = ty * TY;
   const int m0 = zs * L.zseg;
   const int m1 = m0 + L.zseg < L.tiles_z ? m0 + L.zseg : L.tiles_z;
@@ -1071,22 +1090,113 @@ __device__ __forceinline__ void planes_to_codes16(uint32_t p[32], uint32_t keep)
   }
 }
 
-// the NP lowest plane words of word `w` of a chunk (its stored planes that
-// `keep` selects; planes not loaded read the zero word).  Plane offsets are
-// below 2^10 words: 24-bit multiplies.
-template <int NP>
-__device__ __forceinline__ void load_planes(const RetrieveIn &in, uint64_t first_word, uint32_t mask,
-                                            uint32_t keep, uint32_t W, uint32_t w, uint32_t p[32]) {
-  const bool packed = in.chunk_off != nullptr;
-  uint32_t load = mask & keep;
-  // keeps the compiler from precomputing keep & (1 << k) for every plane
-  asm volatile("" : "+v"(load));
-  const uint32_t *base = in.payload + first_word + w;
-#pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    const bool on = (load >> k) & 1u;
-    p[k] = *(on ? base + __umul24(plane_rank(packed, mask, k), W) : in.zero);
+// The plane word a retrieval thread fetches each step.  Roles are fixed for
+// the workgroup (thread index):
+//   t < 56:        word of the workgroup's own chunks (A: 8, B: 16, C: 32)
+//   64 <= t < 121: a halo word (when every chunk column involved is 32
+//                  targets wide, so that a chunk row is one word)
+//     u 0 .. 8:   pass A rows y0-2, y0+16, y0+18 in chunk columns tx-1, tx, tx+1
+//     u 9 .. 24:  pass A own rows, chunk columns tx-1 (code 31) and tx+1 (codes 0, 1)
+//     u 25 .. 56: pass B rows (zz, k), chunk columns tx-1 and tx+1
+// Everything that does not change along the column is worked out once: the
+// chunk's global index and slot at chunk row 0 advance by a fixed stride per
+// row.
+struct WordRole {
+  uint32_t bits;  // pass + 1 (0: no word) | sel << 2 | zlim << 4 | wd << 5 | dst << 10 | eyx << 20
+  uint32_t g0;    // global chunk index at chunk row 0
+  __device__ __forceinline__ int p() const { return int(bits & 3u) - 1; }
+  __device__ __forceinline__ int sel() const { return int((bits >> 2) & 3u); }
+  __device__ __forceinline__ int zlim() const { return int((bits >> 4) & 1u); }
+  __device__ __forceinline__ uint32_t wd() const { return (bits >> 5) & 31u; }
+  __device__ __forceinline__ int dst() const { return int((bits >> 10) & 1023u); }
+  __device__ __forceinline__ uint32_t eyx() const { return bits >> 20; }
+};
+
+__device__ __forceinline__ WordRole word_role(const Level3Args &L, int t, int tx, int ty, int y0,
+                                              bool wordhalo) {
+  WordRole r{0u, 0u};
+  int p = -1, sel = 3, dst = 0, dy = 0, dx = 0, row = 0, y = y0, zz = 0;
+  if (t < 56) {
+    p = t < 8 ? 0 : (t < 24 ? 1 : 2);
+    row = t < 8 ? t : (t < 24 ? t - 8 : t - 24);
+  } else if (wordhalo && t >= 64 && t < 121) {
+    const int u = t - 64;
+    if (u < 9) {
+      const int q = u / 3, c = u - (u / 3) * 3;
+      p = 0;
+      dy = q == 0 ? -1 : 1;
+      dx = c - 1;
+      row = q == 0 ? 7 : q - 1;
+      y = q == 0 ? y0 - 2 : y0 + 14 + 2 * q;
+      sel = c;
+      dst = (q == 0 ? 0 : 8 + q) * NXP;
+    } else if (u < 25) {
+      const int v = u - 9, yj = 1 + (v >> 1), side = v & 1;
+      p = 0;
+      dx = side ? 1 : -1;
+      row = yj - 1;
+      y = y0 - 2 + 2 * yj;
+      sel = side ? 2 : 0;
+      dst = yj * NXP;
+    } else {
+      const int v = u - 25, k = (v >> 1) & 7, side = v & 1;
+      zz = v >> 4;
+      p = 1;
+      dx = side ? 1 : -1;
+      row = k;
+      y = y0 + 1 + 2 * k;
+      sel = side ? 2 : 0;
+      dst = (zz * 8 + k) * 4;
+    }
   }
+  const int tyn = ty + dy, txn = tx + dx;
+  if (p < 0 || unsigned(tyn) >= unsigned(L.tiles_y) || unsigned(txn) >= unsigned(L.tiles_x) ||
+      (sel != 3 && unsigned(y) >= unsigned(L.L[1])))
+    return r;
+  const int ey = clampi(LSEL2(tdims, p, 1) - tyn * LSEL2(ct, p, 1), LSEL2(ct, p, 1));
+  const int ex = clampi(LSEL2(tdims, p, 2) - txn * LSEL2(ct, p, 2), LSEL2(ct, p, 2));
+  const uint32_t wd = uint32_t(sel == 3 || p == 0 ? row : zz * ey + row);
+  const uint32_t zlim = p == 0 ? 1u : uint32_t(zz);
+  r.bits = uint32_t(p + 1) | uint32_t(sel) << 2 | zlim << 4 | wd << 5 | uint32_t(dst) << 10 |
+           uint32_t(ey * ex) << 20;
+  r.g0 = uint32_t(LSEL(chunk_base, p)) + uint32_t(tyn) * uint32_t(L.tiles_x) + uint32_t(txn);
+  return r;
+}
+
+// the NP lowest plane words of word `w` of a chunk whose stored planes start
+// at payload word `first` (its stored planes that `keep` selects; planes not
+// loaded are 0, and planes from `top` up, which no lane of the wave loads,
+// are not looked at).  Slot placement keeps plane k at (31 - k) W words;
+// packed placement at the rank of k among the stored planes.
+template <int NP>
+__device__ __forceinline__ void load_planes_top(const RetrieveIn &in, bool packed, uint64_t first,
+                                                uint32_t mask, uint32_t keep, uint32_t W, uint32_t w,
+                                                int top, uint32_t p[32]) {
+  uint32_t load = mask & keep;
+  asm volatile("" : "+v"(load));
+  const uint32_t *base = in.payload + first + w;
+  if (!packed) {
+    const uint32_t *q = base + 31u * W;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      uint32_t v = 0u;
+      if (k < top && ((load >> k) & 1u)) v = *q;
+      p[k] = v;
+      q -= W;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      uint32_t v = 0u;
+      if (k < top && ((load >> k) & 1u)) v = base[__umul24(uint32_t(__popc((mask >> k) >> 1)), W)];
+      p[k] = v;
+    }
+  }
+}
+
+// OR of v over a full wave (every lane active), uniform
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+  return wave_reduce(v, [](uint32_t a, uint32_t b) { return a | b; });
 }
 
 template <typename T, int INTERP>
@@ -1097,7 +1207,7 @@ __device__ __forceinline__ void level3_retrieve_body(const Level3Args &L, const 
   using F = F3<T>;
   T two_eb = two_eb_arg;  // in a vector register (see level3_compress_body)
   asm volatile("" : "+v"(two_eb));
-  const int tid0 = threadIdx.x;
+  const int tid0 = role_thread();
   const int x0 = tx * TX, y0 = ty * TY;
   const int m0 = zs * L.zseg;
   const int m1 = m0 + L.zseg < L.tiles_z ? m0 + L.zseg : L.tiles_z;
@@ -1107,6 +1217,7 @@ __device__ __forceinline__ void level3_retrieve_body(const Level3Args &L, const 
   const uint32_t keepC = discC >= 32 ? 0u : (0xFFFFFFFFu << discC);
   const bool has_out = in.n_out > 0;
   const bool packed = in.chunk_off != nullptr;
+  const uint32_t tyx = uint32_t(L.tiles_y) * uint32_t(L.tiles_x);
   // halo codes by plane words when every chunk column involved is 32 targets
   // wide (one chunk row = one word)
   const int txr = tx + 1 < L.tiles_x ? tx + 1 : L.tiles_x - 1;
@@ -1123,12 +1234,12 @@ __device__ __forceinline__ void level3_retrieve_body(const Level3Args &L, const 
   };
 
   // exact value of an outlier among the step's chunk oi, if `local` is one
-  auto lookup = [&](int oi, uint32_t local, T &val) {
-    const uint32_t a0 = S.orng[oi][0], a1 = S.orng[oi][1];
+  auto lookup = [&](int mb, int oi, uint32_t local, T &val) {
+    const uint32_t a0 = S.orng[mb][oi][0], a1 = S.orng[mb][oi][1];
     if (a1 > a0) {
       if (a1 - a0 <= uint32_t(OCAP)) {
         for (uint32_t j = 0; j < a1 - a0; ++j)
-          if (S.oloc[oi][j] == local) val = F::from_bits(S.obits[oi][j]);
+          if (S.oloc[mb][oi][j] == local) val = F::from_bits(S.obits[mb][oi][j]);
       } else {
         uint64_t ob;
         if (find_outlier(in, a0, a1, local, ob)) val = F::from_bits(ob);
@@ -1136,109 +1247,57 @@ __device__ __forceinline__ void level3_retrieve_body(const Level3Args &L, const 
     }
   };
 
-  // The plane word this thread fetches each step (role from its thread index):
-  //   tid < 56:        word of the workgroup's own chunks (A: 8, B: 16, C: 32)
-  //   64 <= tid < 121: a halo word (plane-word halo only)
-  //     u 0 .. 8:   pass A rows y0-2, y0+16, y0+18 in chunk columns tx-1, tx, tx+1
-  //     u 9 .. 24:  pass A own rows, chunk columns tx-1 (code 31) and tx+1 (codes 0, 1)
-  //     u 25 .. 56: pass B rows (zz, k), chunk columns tx-1 and tx+1
-  struct Role {
-    int p, dy, dx, zz, row, y, sel, dst;  // sel: 0 code 31, 1 all 32, 2 codes 0 and 1, 3 own words
-  };
-  auto role_of = [&](int t) {
-    Role r{-1, 0, 0, 0, 0, 0, 0, 0};
-    if (t < 56) {
-      r.p = t < 8 ? 0 : (t < 24 ? 1 : 2);
-      r.row = t < 8 ? t : (t < 24 ? t - 8 : t - 24);
-      r.y = y0;
-      r.sel = 3;
-    } else if (wordhalo && t >= 64 && t < 121) {
-      const int u = t - 64;
-      if (u < 9) {
-        const int q = u / 3, c = u - (u / 3) * 3;
-        r.p = 0;
-        r.dy = q == 0 ? -1 : 1;
-        r.dx = c - 1;
-        r.row = q == 0 ? 7 : q - 1;
-        r.y = q == 0 ? y0 - 2 : y0 + 14 + 2 * q;
-        r.sel = c;
-        r.dst = (q == 0 ? 0 : 8 + q) * NXP;
-      } else if (u < 25) {
-        const int v = u - 9, yj = 1 + (v >> 1), side = v & 1;
-        r.p = 0;
-        r.dx = side ? 1 : -1;
-        r.row = yj - 1;
-        r.y = y0 - 2 + 2 * yj;
-        r.sel = side ? 2 : 0;
-        r.dst = yj * NXP;
-      } else {
-        const int v = u - 25, zz = v >> 4, k = (v >> 1) & 7, side = v & 1;
-        r.p = 1;
-        r.dx = side ? 1 : -1;
-        r.zz = zz;
-        r.row = k;
-        r.y = y0 + 1 + 2 * k;
-        r.sel = side ? 2 : 0;
-        r.dst = (zz * 8 + k) * 4;
-      }
-    }
-    return r;
-  };
-  // whether the role's word exists at chunk row m, its chunk id and word index
-  auto role_word = [&](const Role &r, int m, int64_t &cid, int &wd, Ext &e) -> bool {
-    if (r.p < 0 || m >= m1) return false;
-    const int tyn = ty + r.dy, txn = tx + r.dx;
-    if (unsigned(tyn) >= unsigned(L.tiles_y) || unsigned(txn) >= unsigned(L.tiles_x)) return false;
-    e = chunk_ext(L, r.p, m, tyn, txn);
-    cid = chunk_id(L, m, tyn, txn);
-    if (r.sel == 3) {
-      wd = r.row;
-      return wd < ((e.count + 31) >> 5);
-    }
-    if (r.y < 0 || r.y >= Ly) return false;
-    if (r.p == 0 && 2 * m + 1 >= Lz) return false;
-    if (r.p == 1 && 2 * m + r.zz >= Lz) return false;
-    wd = r.p == 0 ? r.row : r.zz * e.ey + r.row;
-    return true;
-  };
-  // prefetched mask and first payload word of the next step's chunk
+  const WordRole R = word_role(L, tid0, tx, ty, y0, wordhalo);
+  const uint32_t rkeep = R.p() < 0 ? 0u : sel3(R.p(), keepA, keepB, keepC);
+  // mask and (packed placement) first payload word of the role's chunk,
+  // fetched one step ahead
   uint32_t pmask = 0;
   uint64_t pword = 0;
-  auto prefetch_word = [&](const Role &r, int m) {
-    int64_t cid;
-    int wd;
-    Ext e;
-    if (role_word(r, m, cid, wd, e)) {
-      const uint64_t g = uint64_t(LSEL(chunk_base, r.p) + cid);
+  auto prefetch_word = [&](int m) {
+    if (R.p() >= 0) {
+      const uint32_t g = R.g0 + uint32_t(m) * tyx;
       pmask = in.masks[g];
-      pword = packed ? in.chunk_off[g] : LSEL(slot_base, r.p) + uint64_t(cid) * 32u * LSEL(wmax, r.p);
+      if (packed) pword = in.chunk_off[g];
     }
   };
 
-  // coarse-plane entries tid, tid + 256 (< 385) of the ring, prefetched a step ahead
+  // coarse-plane entries t, t + 256 (< 385) of the ring, prefetched a step
+  // ahead: entry i of thread t sits at li in its ring slot and at ro in its
+  // coarse plane (worked out when needed rather than held in registers)
   T rv[2];
-  int li[2];
-  uint32_t ro[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int e = tid0 + i * WG3;
+  auto ring_entry = [&](int t, int i, int &li, uint32_t &ro) {
+    const int e = t + i * WG3;
     const int yj = e / NXE, xi = e - (e / NXE) * NXE;
     const int cy = (y0 >> 1) - 1 + yj, cx = (x0 >> 1) - 1 + xi;
     const bool ok = e < NYE * NXE && unsigned(cy) < unsigned(L.G[1]) && unsigned(cx) < unsigned(L.G[2]);
-    li[i] = e < NYE * NXE ? yj * NXP + xi : -1;
-    ro[i] = ok ? uint32_t(cy * L.G[2] + cx) : 0u;
-  }
-  auto issue_ring = [&](int cz) {
+    li = e < NYE * NXE ? yj * NXP + xi : -1;
+    ro = ok ? uint32_t(cy * L.G[2] + cx) : 0u;
+  };
+  auto issue_ring = [&](int t, int cz) {
     if (cz < L.G[0]) {
       const T *gp = gin + int64_t(cz) * L.G[1] * L.G[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) rv[i] = gp[ro[i]];
+      for (int i = 0; i < 2; ++i) {
+        int li;
+        uint32_t ro;
+        ring_entry(t, i, li, ro);
+        rv[i] = gp[ro];
+      }
     }
   };
 
-  load_ring(L, gin, S, m0, li, ro);
-  issue_ring(m0 + 2);
-  prefetch_word(role_of(tid0), m0);
+  const bool vec = (Lx & 3) == 0 && (reinterpret_cast<uintptr_t>(gout) & 15) == 0;
+  const uint32_t plane = uint32_t(Ly) * uint32_t(Lx);
+
+  {
+    int li[2];
+    uint32_t ro[2];
+    ring_entry(tid0, 0, li[0], ro[0]);
+    ring_entry(tid0, 1, li[1], ro[1]);
+    load_ring(L, gin, S, m0, li, ro);
+  }
+  issue_ring(tid0, m0 + 2);
+  prefetch_word(m0);
 
   for (int m = m0; m < m1; ++m) {
     // a fresh copy of the thread index each step: values derived from it are
@@ -1246,57 +1305,65 @@ __device__ __forceinline__ void level3_retrieve_body(const Level3Args &L, const 
     int tid = tid0;
     asm volatile("" : "+v"(tid));
     const int ze = 2 * m, zo = 2 * m + 1;
+    const int mb = m & 1;
+    uint32_t *codes = S.codes[mb];
     // ---- stash the coarse plane m + 2
     if (m + 2 < L.G[0]) {
       T *rs = &S.ring[(m + 2) & 3][0][0];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-        if (li[i] >= 0) rs[li[i]] = rv[i];
+      for (int i = 0; i < 2; ++i) {
+        int li;
+        uint32_t ro;
+        ring_entry(tid, i, li, ro);
+        if (li >= 0) rs[li] = rv[i];
+      }
     }
-    // ---- this step's plane words: own chunks and halo
-    {
-      const Role r = role_of(tid);
-      int64_t cid;
-      int wd;
-      Ext e;
-      const bool ok = role_word(r, m, cid, wd, e);
+    // ---- this step's plane words: own chunks and halo (waves 0 and 1)
+    if (tid < 128) {
       const uint32_t mask = pmask;
-      const uint64_t first = pword;
-      if (m + 1 < m1) prefetch_word(r, m + 1);
+      const int rp = R.p();
+      // slot placement: chunk c of pass p at slot_base + c * 32 wmax words
+      const uint64_t first =
+          packed ? pword
+                 : LSEL(slot_base, rp) + uint64_t(R.g0 + uint32_t(m) * tyx - uint32_t(LSEL(chunk_base, rp))) *
+                                             (32u * LSEL(wmax, rp));
+      const int ez = rp == 0 ? int(zo < Lz) : (Lz - ze < 2 ? Lz - ze : 2);
+      const uint32_t W = (uint32_t(ez) * R.eyx() + 31u) >> 5;
+      const bool ok = rp >= 0 && (R.sel() == 3 ? R.wd() < W : ze + R.zlim() < Lz);
+      if (m + 1 < m1) prefetch_word(m + 1);
+      // highest plane any lane of the wave loads
+      const uint32_t ld = ok ? (mask & rkeep) : 0u;
+      const int top = 32 - __clz(wave_or(ld));
       if (ok) {
-        const uint32_t keep = sel3(r.p, keepA, keepB, keepC);
         uint32_t p[32];
-        // every loaded plane of the wave below 16: half the planes, half
-        // the transposes
-        const bool narrow = __builtin_amdgcn_ballot_w64(((mask & keep) >> 16) != 0u) == 0;
-        if (narrow) {
-          load_planes<16>(in, first, mask, keep, uint32_t((e.count + 31) >> 5), uint32_t(wd), p);
-          planes_to_codes16(p, keep);
+        if (top <= 16) {
+          load_planes_top<16>(in, packed, first, mask, rkeep, W, R.wd(), top, p);
+          planes_to_codes16(p, rkeep);
         } else {
-          load_planes<32>(in, first, mask, keep, uint32_t((e.count + 31) >> 5), uint32_t(wd), p);
-          planes_to_codes(p, keep);
+          load_planes_top<32>(in, packed, first, mask, rkeep, W, R.wd(), top, p);
+          planes_to_codes(p, rkeep);
         }
-        if (r.sel == 3) {
+        if (R.sel() == 3) {
           // all 32 slots of the word, also past the chunk's last code: the
           // pass's buffer holds 33 slots per word of a full chunk, and only
           // slots of real targets are read
-          uint32_t *cb = S.codes + code_off1(r.p) + 33 * wd;
+          uint32_t *cb = codes + code_off1(rp) + 33 * int(R.wd());
 #pragma unroll
           for (int j = 0; j < 32; ++j) cb[j] = p[j];
-        } else if (r.p == 0) {
-          uint32_t *d = &S.hva[0][0] + r.dst;
-          if (r.sel == 1) {
+        } else if (rp == 0) {
+          uint32_t *d = &S.hva[0][0] + R.dst();
+          if (R.sel() == 1) {
 #pragma unroll
             for (int j = 0; j < 32; ++j) d[1 + j] = p[j];
-          } else if (r.sel == 0) {
+          } else if (R.sel() == 0) {
             d[0] = p[31];
           } else {
             d[33] = p[0];
             d[34] = p[1];
           }
         } else {
-          uint32_t *d = &S.hvb[0][0][0] + r.dst;
-          if (r.sel == 0) {
+          uint32_t *d = &S.hvb[0][0][0] + R.dst();
+          if (R.sel() == 0) {
             d[0] = p[31];
           } else {
             d[1] = p[0];
@@ -1340,17 +1407,17 @@ __device__ __forceinline__ void level3_retrieve_body(const Level3Args &L, const 
         a = in.out_start[g];
         b = in.out_start[g + 1];
       }
-      S.orng[u][0] = a;
-      S.orng[u][1] = b;
+      S.orng[mb][u][0] = a;
+      S.orng[mb][u][1] = b;
       if (b - a <= uint32_t(OCAP))
         for (uint32_t j = 0; j < b - a; ++j) {
-          S.oloc[u][j] = in.out_local[a + j];
-          S.obits[u][j] = in.out_bits[a + j];
+          S.oloc[mb][u][j] = in.out_local[a + j];
+          S.obits[mb][u][j] = in.out_bits[a + j];
         }
       any_out = b > a;
     }
     any_out = __builtin_amdgcn_readfirstlane(__syncthreads_or(any_out));
-    if (m + 1 < m1) issue_ring(m + 3);
+    if (m + 1 < m1) issue_ring(tid, m + 3);
     // ---- pass A at plane zo: the 8 x 32 own targets (one per thread), then
     // the 129 halo targets of the 11 x 35 even grid
     if (zo < Lz) {
@@ -1366,8 +1433,8 @@ __device__ __forceinline__ void level3_retrieve_body(const Level3Args &L, const 
           const int ex = clampi(L.tdims[0][2] - tx * L.ct[0][2], L.ct[0][2]);
           const uint32_t local = uint32_t(mad24(r, ex, c));
           const T pred = stencil<T, INTERP>(ra[ri], rb[ri], rc[ri], re[ri], hc, ha, he);
-          T val = value(pred, S.codes[code_off1(0) + pidx(int(local))]);
-          if (any_out) lookup(4, local, val);
+          T val = value(pred, codes[code_off1(0) + pidx(int(local))]);
+          if (any_out) lookup(mb, 4, local, val);
           (&S.wa[0][0])[ri] = val;
         }
       }
@@ -1381,12 +1448,12 @@ __device__ __forceinline__ void level3_retrieve_body(const Level3Args &L, const 
           T val = value(pred, (&S.hva[0][0])[ri]);
           if (any_out) {
             const int oi = (yj == 0 ? 0 : (yj <= 8 ? 3 : 6)) + (xi == 0 ? 0 : (xi <= 32 ? 1 : 2));
-            if (S.orng[oi][1] > S.orng[oi][0]) {
+            if (S.orng[mb][oi][1] > S.orng[mb][oi][0]) {
               int tyn, oy, txn, ox;
               halo_tile(ty, yj, 8, tyn, oy);
               halo_tile(tx, xi, 32, txn, ox);
               const Ext e = chunk_ext(L, 0, m, tyn, txn);
-              lookup(oi, uint32_t(oy * e.ex + ox), val);
+              lookup(mb, oi, uint32_t(oy * e.ex + ox), val);
             }
           }
           (&S.wa[0][0])[ri] = val;
@@ -1394,73 +1461,101 @@ __device__ __forceinline__ void level3_retrieve_body(const Level3Args &L, const 
       }
     }
     __syncthreads();
-    // ---- pass B at planes ze, zo: 2 x 8 x 32 own targets (two per thread),
-    // then the 48 halo targets at columns x0-2, x0+64, x0+66
+    // ---- pass B at planes ze, zo: thread t takes plane t / 128, column
+    // x0 + 2 (t % 32) and the odd rows y0 + 1 + 2 k of k = 2 s, 2 s + 1
+    // (s = t / 32 % 4), from the five even rows around them; then the 48
+    // halo targets at columns x0-2, x0+64, x0+66
     {
+      const int zz = tid >> 7, s = (tid >> 5) & 3, c = tid & 31;
       const int ey = clampi(L.tdims[1][1] - ty * L.ct[1][1], L.ct[1][1]);
       const int ex = clampi(L.tdims[1][2] - tx * L.ct[1][2], L.ct[1][2]);
-      const int k = tid >> 5, c = tid & 31;
-      const int y = y0 + 1 + 2 * k;
-      const bool hc = y + 1 < Ly, ha = y >= 3, he = y + 3 < Ly;
+      if (ze + zz < Lz && x0 + 2 * c < Lx) {
+        const T *src = (zz == 0 ? S.ring[m & 3][0] : S.wa[0]) + 2 * s * NXP + c + 1;
+        const T v0 = src[0], v1 = src[NXP], v2 = src[2 * NXP], v3 = src[3 * NXP], v4 = src[4 * NXP];
 #pragma unroll
-      for (int zz = 0; zz < 2; ++zz) {
-        if (ze + zz >= Lz || y >= Ly || x0 + 2 * c >= Lx) continue;
-        const T *src = zz == 0 ? S.ring[m & 3][0] : S.wa[0];
-        const int ri = k * NXP + c + 1;
-        const uint32_t local = uint32_t(mad24(mad24(zz, ey, k), ex, c));
-        const T pred = stencil<T, INTERP>(src[ri], src[ri + NXP], src[ri + 2 * NXP], src[ri + 3 * NXP], hc, ha, he);
-        T val = value(pred, S.codes[code_off1(1) + pidx(int(local))]);
-        if (any_out) lookup(10, local, val);
-        S.wb[zz][k][c + 1] = val;
+        for (int h = 0; h < 2; ++h) {
+          const int k = 2 * s + h;
+          const int y = y0 + 1 + 2 * k;
+          if (y >= Ly) continue;
+          const bool hc = y + 1 < Ly, ha = y >= 3, he = y + 3 < Ly;
+          const T pred = h == 0 ? stencil<T, INTERP>(v0, v1, v2, v3, hc, ha, he)
+                                : stencil<T, INTERP>(v1, v2, v3, v4, hc, ha, he);
+          const uint32_t local = uint32_t(mad24(mad24(zz, ey, k), ex, c));
+          T val = value(pred, codes[code_off1(1) + pidx(int(local))]);
+          if (any_out) lookup(mb, 10, local, val);
+          S.wb[zz][k][c + 1] = val;
+        }
       }
       if (tid < NHB) {
-        int zz, kh, xi;
-        halo_b(tid, zz, kh, xi);
+        int zh, kh, xi;
+        halo_b(tid, zh, kh, xi);
         const int yh = y0 + 1 + 2 * kh, xg = x0 - 2 + 2 * xi;
-        if (ze + zz < Lz && yh < Ly && unsigned(xg) < unsigned(Lx)) {
-          const T *src = zz == 0 ? S.ring[m & 3][0] : S.wa[0];
+        if (ze + zh < Lz && yh < Ly && unsigned(xg) < unsigned(Lx)) {
+          const T *src = zh == 0 ? S.ring[m & 3][0] : S.wa[0];
           const int ri = kh * NXP + xi;
           const bool hch = yh + 1 < Ly, hah = yh >= 3, heh = yh + 3 < Ly;
           const T pred = stencil<T, INTERP>(src[ri], src[ri + NXP], src[ri + 2 * NXP], src[ri + 3 * NXP], hch, hah, heh);
-          T val = value(pred, S.hvb[zz][kh][xi & 3]);
+          T val = value(pred, S.hvb[zh][kh][xi & 3]);
           if (any_out) {
             const int oi = 9 + (xi == 0 ? 0 : 2);
-            if (S.orng[oi][1] > S.orng[oi][0]) {
+            if (S.orng[mb][oi][1] > S.orng[mb][oi][0]) {
               int txn, ox;
               halo_tile(tx, xi, 32, txn, ox);
               const Ext e = chunk_ext(L, 1, m, ty, txn);
-              lookup(oi, uint32_t((zz * e.ey + kh) * e.ex + ox), val);
+              lookup(mb, oi, uint32_t((zh * e.ey + kh) * e.ex + ox), val);
             }
           }
-          S.wb[zz][kh][xi] = val;
+          S.wb[zh][kh][xi] = val;
         }
       }
     }
     __syncthreads();
-    // ---- pass C: 2 planes x 16 rows x 32 odd columns
-    {
-      const uint32_t *cb = S.codes + code_off1(2);
-      const int ci = tid & 31, cr = (tid >> 5) & 7;
-      const int cxg = x0 + 1 + 2 * ci;
-      const bool chc = cxg + 1 < Lx, cha = cxg >= 3, che = cxg + 3 < Lx;
-      const int cey = clampi(L.tdims[2][1] - ty * L.ct[2][1], L.ct[2][1]);
-      const int cex = clampi(L.tdims[2][2] - tx * L.ct[2][2], L.ct[2][2]);
+    // ---- pass C and the level grid's points (see above).  The next step
+    // writes the other code buffer and outlier slots, and rewrites wa, wb
+    // only after its first barrier, so no barrier closes the step.
+    // pass C: thread t reconstructs row yy = t / 16 of both planes at the odd
+    // columns x0 + 4 k + 1 and x0 + 4 k + 3 (k = t % 16), and writes the four
+    // points x0 + 4 k .. + 3 of the row (two of them even columns it read)
+    const int cyy = tid >> 4, ck = tid & 15;
+    const int cx1 = x0 + 4 * ck + 1;
+    if (y0 + cyy < Ly) {
+      const int cexC = clampi(L.tdims[2][2] - tx * L.ct[2][2], L.ct[2][2]);
+      const int ceyC = clampi(L.tdims[2][1] - ty * L.ct[2][1], L.ct[2][1]);
+      const bool chc0 = cx1 + 1 < Lx, cha0 = cx1 >= 3, che0 = cx1 + 3 < Lx;
+      const bool chc1 = cx1 + 3 < Lx, cha1 = cx1 + 2 >= 3, che1 = cx1 + 5 < Lx;
+      const bool interior = vec && zo < Lz && x0 + TX <= Lx;
+      const int y = y0 + cyy;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int zz = j >> 1, yy = cr + 8 * (j & 1);
-        if (cxg >= Lx || y0 + yy >= Ly || ze + zz >= Lz) continue;
-        const T *row = even_row<T>(S, m, zz, yy);
-        const T pred = stencil<T, INTERP>(row[ci], row[ci + 1], row[ci + 2], row[ci + 3], chc, cha, che);
-        const uint32_t local = uint32_t(mad24(mad24(zz, cey, yy), cex, ci));
-        T val = value(pred, cb[pidx(int(local))]);
-        if (any_out) lookup(12, local, val);
-        S.wc[zz][yy][ci] = val;
+      for (int zz = 0; zz < 2; ++zz) {
+        if (ze + zz >= Lz) continue;
+        const T *row = even_row<T>(S, m, zz, cyy) + 2 * ck;
+        const T e0 = row[0], e1 = row[1], e2 = row[2], e3 = row[3], e4 = row[4];
+        const uint32_t lrow = uint32_t(mad24(mad24(zz, ceyC, cyy), cexC, 2 * ck));
+        T v0 = e0, v1 = e0;
+        if (cx1 < Lx) {
+          v0 = value(stencil<T, INTERP>(e0, e1, e2, e3, chc0, cha0, che0), codes[code_off1(2) + pidx(int(lrow))]);
+          if (any_out) lookup(mb, 12, lrow, v0);
+        }
+        if (cx1 + 2 < Lx) {
+          v1 = value(stencil<T, INTERP>(e1, e2, e3, e4, chc1, cha1, che1), codes[code_off1(2) + pidx(int(lrow) + 1)]);
+          if (any_out) lookup(mb, 12, lrow + 1u, v1);
+        }
+        T *dst = gout + (uint32_t(ze + zz) * plane + uint32_t(mad24(y, Lx, cx1 - 1)));
+        if (interior) {
+          if constexpr (sizeof(T) == 4) {
+            *reinterpret_cast<float4 *>(dst) = make_float4(e1, v0, e2, v1);
+          } else {
+            reinterpret_cast<double2 *>(dst)[0] = make_double2(e1, v0);
+            reinterpret_cast<double2 *>(dst)[1] = make_double2(e2, v1);
+          }
+        } else if (cx1 - 1 < Lx) {
+          dst[0] = e1;
+          if (cx1 < Lx) dst[1] = v0;
+          if (cx1 + 1 < Lx) dst[2] = e2;
+          if (cx1 + 2 < Lx) dst[3] = v1;
+        }
       }
     }
-    __syncthreads();
-    write_rows(L, S, gout, m, y0, x0);
-    // the next step's word fetch rewrites the code buffers pass C read above
-    __syncthreads();
   }
 }
 
