@@ -59,13 +59,40 @@ typedef struct {
   double value;  /* > 0 */
 } ipc_target;
 
-/* Compression options; pass NULL for the defaults
- * {IPC_CUBIC, nonprog_levels 0, default chunk shape}. */
+/* Delta-y table of Thm. 1 (ipc_options.errq_mode):
+ *   IPC_ERRQ_EXACT: per pass, the largest |q - q'_b| over the pass's codes
+ *     (measured during compression);
+ *   IPC_ERRQ_BOUND: the same for every pass, fixed before compression: the
+ *     largest change discarding b negabinary digits can make to any code, the
+ *     truncation uncertainty of Sec. 4.4.2 (floor((2^(b+1) - 1) / 3)).  Plans
+ *     then load at least as much as with the exact table. */
+#define IPC_ERRQ_EXACT 0
+#define IPC_ERRQ_BOUND 1
+/* Lossless stage of the stored planes (ipc_options.lossless; Sec. 6 runs a
+ * general-purpose compressor there): IPC_LOSSLESS_ZWE keeps the blocks raw
+ * (all-zero planes of a chunk are not stored), IPC_LOSSLESS_CODED also
+ * entropy-codes them at the end of compression (ipc_stream_entropy_code). */
+#define IPC_LOSSLESS_ZWE 0
+#define IPC_LOSSLESS_CODED 1
+/* ipc_options.debug_flags: IPC_DEBUG_PER_PASS compresses with the
+ * one-pass-per-launch kernels where the fused level kernels would run (same
+ * stream, a cross-check); IPC_DEBUG_VERIFY retrieves the new stream at full
+ * precision and checks |x - x^| <= abs_eb at every point (exact bits for
+ * values that are not finite), failing with IPC_ECORRUPT otherwise. */
+#define IPC_DEBUG_PER_PASS 1u
+#define IPC_DEBUG_VERIFY 2u
+
+/* Compression options; pass NULL for the defaults {IPC_CUBIC,
+ * nonprog_levels 0, default chunk shape, IPC_ERRQ_EXACT, IPC_LOSSLESS_ZWE,
+ * no debug flags}.  Unknown modes or flags are rejected with IPC_EINVAL. */
 typedef struct {
   int32_t interp;          /* ipc_interp */
   int32_t nonprog_levels;  /* top levels always fully loaded (L_p of Alg. 1) */
   uint8_t chunk_log2[3];   /* chunk extents (log2) per dimension; all 0 = default */
-  uint8_t reserved[5];
+  uint8_t errq_mode;       /* IPC_ERRQ_* */
+  uint8_t lossless;        /* IPC_LOSSLESS_* */
+  uint8_t reserved[3];     /* 0 */
+  uint32_t debug_flags;    /* IPC_DEBUG_* */
 } ipc_options;
 
 #define IPC_FLAG_CLAMPED_TO_EB 1u      /* E below the compression bound: full load */

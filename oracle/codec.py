@@ -128,8 +128,13 @@ class CompressDebug:
 
 
 def compress(x: np.ndarray, eb: float, interp: int = predict.CUBIC, chunk_log2=None,
-             nonprog_levels: int = 0, debug: bool = False):
-    """Compress a float32/float64 field with absolute error bound eb."""
+             nonprog_levels: int = 0, debug: bool = False, errq_mode: str = "exact"):
+    """Compress a float32/float64 field with absolute error bound eb.
+
+    errq_mode "exact" stores each pass's measured delta-y (Thm. 1); "bound"
+    stores the fixed table of coding.errq_bound_table for every pass."""
+    if errq_mode not in ("exact", "bound"):
+        raise ValueError("errq_mode is 'exact' or 'bound'")
     x = np.ascontiguousarray(x)
     if x.dtype not in (np.float32, np.float64):
         raise TypeError("only float32 and float64 fields")
@@ -160,7 +165,7 @@ def compress(x: np.ndarray, eb: float, interp: int = predict.CUBIC, chunk_log2=N
             xt = _pass_inputs(x, p)
             q, xh, out = predict.quantize(xt, pred, eb)
             _store_pass(work, p, xh)
-        errq[p.index] = coding.errq_table(q)
+        errq[p.index] = coding.errq_table(q) if errq_mode == "exact" else coding.errq_bound_table()
         e = coding.xor_encode(coding.to_negabinary(q))
         masks, payload = _encode_pass_chunks(p, e)
         all_masks.append(masks)

@@ -87,6 +87,21 @@ def errq_table(q) -> np.ndarray:
     return out
 
 
+def errq_bound_table() -> np.ndarray:
+    """delta-y fixed before compression (the bound reading of Thm. 1): for
+    b = 0..32 discarded digits, the largest |value| the b low negabinary
+    digits can take, which Sec. 4.4.2's Eq. uncertainty gives as
+    2/3 2^b - 1/3 (b odd) and 2/3 2^b - 2/3 (b even).  Written here as the
+    larger of the two digit sums (even positions carry +2^k, odd ones -2^k),
+    so the formula is checked against it rather than restated."""
+    out = np.zeros(33, dtype=np.uint32)
+    for b in range(33):
+        pos = sum(1 << k for k in range(0, b, 2))
+        neg = sum(1 << k for k in range(1, b, 2))
+        out[b] = np.uint32(max(pos, neg))
+    return out
+
+
 def pack_planes(e_chunk: np.ndarray) -> np.ndarray:
     """Bitplanes of one chunk: array [32, W] of uint32, W = ceil(n / 32).
 

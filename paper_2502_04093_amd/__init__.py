@@ -37,7 +37,29 @@ class ipc_target(ctypes.Structure):
 
 class ipc_options(ctypes.Structure):
     _fields_ = [("interp", ctypes.c_int32), ("nonprog_levels", ctypes.c_int32),
-                ("chunk_log2", c_uint8 * 3), ("reserved", c_uint8 * 5)]
+                ("chunk_log2", c_uint8 * 3), ("errq_mode", c_uint8), ("lossless", c_uint8),
+                ("reserved", c_uint8 * 3), ("debug_flags", c_uint32)]
+
+
+IPC_ERRQ_EXACT, IPC_ERRQ_BOUND = 0, 1
+IPC_LOSSLESS_ZWE, IPC_LOSSLESS_CODED = 0, 1
+IPC_DEBUG_PER_PASS, IPC_DEBUG_VERIFY = 1, 2
+
+
+def _options(interp: str, nonprog_levels: int, chunk_log2=None, errq_mode: str = "exact",
+             lossless: str = "zwe", debug_flags: int = 0) -> ipc_options:
+    if errq_mode not in ("exact", "bound") or lossless not in ("zwe", "coded"):
+        raise ValueError("errq_mode is 'exact' or 'bound', lossless is 'zwe' or 'coded'")
+    opts = ipc_options()
+    opts.interp = IPC_CUBIC if interp == "cubic" else IPC_LINEAR
+    opts.nonprog_levels = nonprog_levels
+    if chunk_log2 is not None:
+        for j, c in enumerate(chunk_log2):
+            opts.chunk_log2[j] = c
+    opts.errq_mode = IPC_ERRQ_BOUND if errq_mode == "bound" else IPC_ERRQ_EXACT
+    opts.lossless = IPC_LOSSLESS_CODED if lossless == "coded" else IPC_LOSSLESS_ZWE
+    opts.debug_flags = int(debug_flags)
+    return opts
 
 
 class ipc_info(ctypes.Structure):
@@ -248,19 +270,17 @@ class Context:
         return [float(arr[i]) for i in range(n.value)]
 
     def compress(self, field, eb: float, interp: str = "cubic", nonprog_levels: int = 0,
-                 chunk_log2: Optional[Sequence[int]] = None) -> "Stream":
+                 chunk_log2: Optional[Sequence[int]] = None, errq_mode: str = "exact",
+                 lossless: str = "zwe", debug_flags: int = 0) -> "Stream":
+        """ipc_compress; errq_mode 'exact' or 'bound' (IPC_ERRQ_*), lossless
+        'zwe' or 'coded' (IPC_LOSSLESS_*), debug_flags IPC_DEBUG_*."""
         import torch
         if not (field.is_cuda and field.is_contiguous()):
             raise ValueError("field must be a contiguous device tensor")
         if field.dtype not in (torch.float32, torch.float64):
             raise TypeError("field must be float32 or float64")
         dims = (c_uint64 * field.dim())(*field.shape)
-        opts = ipc_options()
-        opts.interp = IPC_CUBIC if interp == "cubic" else IPC_LINEAR
-        opts.nonprog_levels = nonprog_levels
-        if chunk_log2 is not None:
-            for j, c in enumerate(chunk_log2):
-                opts.chunk_log2[j] = c
+        opts = _options(interp, nonprog_levels, chunk_log2, errq_mode, lossless, debug_flags)
         out = c_void_p()
         dt = IPC_F32 if field.dtype == torch.float32 else IPC_F64
         _check(lib().ipc_compress(self._p, c_void_p(field.data_ptr()), dims, field.dim(), dt,
@@ -300,7 +320,8 @@ class Context:
     def autotune_clear(self):
         _check(lib().ipc_autotune_clear(self._p), self._p)
 
-    def compress_batch(self, fields, ebs, interp: str = "cubic", nonprog_levels: int = 0):
+    def compress_batch(self, fields, ebs, interp: str = "cubic", nonprog_levels: int = 0,
+                       errq_mode: str = "exact", lossless: str = "zwe", debug_flags: int = 0):
         """Compress several device tensors of one dtype and rank in one call
         (3-D fields share one launch per level); returns a list of Streams."""
         import torch
@@ -319,9 +340,7 @@ class Context:
         ptrs = (c_void_p * n)(*[f.data_ptr() for f in fields])
         dims = (c_uint64 * (n * nd))(*[d for f in fields for d in f.shape])
         eba = (c_double * n)(*[float(e) for e in ebs])
-        opts = ipc_options()
-        opts.interp = IPC_CUBIC if interp == "cubic" else IPC_LINEAR
-        opts.nonprog_levels = nonprog_levels
+        opts = _options(interp, nonprog_levels, None, errq_mode, lossless, debug_flags)
         out = (c_void_p * n)()
         _check(lib().ipc_compress_batch(self._p, n, ptrs, dims, nd,
                                         IPC_F32 if dt == torch.float32 else IPC_F64, eba,

@@ -692,6 +692,56 @@ void run_retrieve(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &pla
   }
 }
 
+uint64_t verify_stream(ipc_ctx *ctx, const ipc_stream *s, const void *field_dev) {
+  const size_t isz = s->meta.dtype == IPC_F32 ? 4 : 8;
+  const uint64_t n = uint64_t(s->meta.sched.n_points);
+  DevBuf rec = dev_alloc(ctx, std::max<size_t>(8, size_t(n) * isz));
+  DevBuf cnt = dev_alloc(ctx, 8);
+  uint64_t bad = 0;
+  try {
+    std::vector<int> full(s->args.size(), 0);
+    run_retrieve(ctx, s, full, 0, rec.p);
+    hip_check(ctx, hipMemsetAsync(cnt.p, 0, 8, ctx->stream), "memset");
+    hip_check(ctx, launch_verify_bound(s->meta.dtype, field_dev, rec.p, n, s->meta.eb,
+                                       static_cast<unsigned long long *>(cnt.p), ctx->stream),
+              "verify launch");
+    hip_check(ctx, hipMemcpyAsync(&bad, cnt.p, 8, hipMemcpyDeviceToHost, ctx->stream), "copy");
+    hip_check(ctx, hipStreamSynchronize(ctx->stream), "verify");
+  } catch (...) {
+    (void)hipStreamSynchronize(ctx->stream);
+    dev_free(ctx, rec);
+    dev_free(ctx, cnt);
+    throw;
+  }
+  dev_free(ctx, rec);
+  dev_free(ctx, cnt);
+  return bad;
+}
+
+void errq_to_bound(ipc_stream *s);
+
+// What ipc_options asks for once a stream's planes and tables exist: the
+// bound form of the delta-y table, the entropy-coded lossless stage, the
+// full-precision check
+ipc_status finish_options(ipc_ctx *ctx, ipc_stream *s, const void *field_dev, const ipc_options *opts) {
+  if (!opts) return IPC_OK;
+  if (opts->errq_mode == IPC_ERRQ_BOUND) errq_to_bound(s);
+  if (opts->debug_flags & IPC_DEBUG_VERIFY) {
+    uint64_t bad = 0;
+    ipc_status st = guarded(ctx, [&] {
+      enter_device(ctx);
+      bad = verify_stream(ctx, s, field_dev);
+    });
+    if (st != IPC_OK) return st;
+    if (bad) {
+      set_err(ctx, "verification: " + std::to_string(bad) + " points miss the error bound");
+      return IPC_ECORRUPT;
+    }
+  }
+  if (opts->lossless == IPC_LOSSLESS_CODED) return ipc_stream_entropy_code(ctx, s);
+  return IPC_OK;
+}
+
 uint64_t plane_bytes_between(const ipc_stream *s, const std::vector<int> &lo,
                              const std::vector<int> &hi) {
   uint64_t tot = 0;
@@ -721,6 +771,11 @@ void setup_stream(ipc_ctx *ctx, ipc_stream *s, const uint64_t *dims, int ndim, i
   int np = opts ? opts->nonprog_levels : 0;
   if (np < 0 || np > m.sched.K) {
     set_err(ctx, "nonprog_levels out of range");
+    throw Fail{IPC_EINVAL};
+  }
+  if (opts && (opts->errq_mode > IPC_ERRQ_BOUND || opts->lossless > IPC_LOSSLESS_CODED ||
+               (opts->debug_flags & ~(IPC_DEBUG_PER_PASS | IPC_DEBUG_VERIFY)) != 0)) {
+    set_err(ctx, "unknown errq_mode, lossless mode or debug flag");
     throw Fail{IPC_EINVAL};
   }
   m.dtype = dtype;
@@ -759,12 +814,28 @@ void finish_stream(ipc_stream *s, const char *hostp, uint64_t nout) {
 
 size_t summary_bytes(int P) { return 16 + size_t(P) * 32 * 8 + size_t(P) * 33 * 4; }
 
+// Thm. 1's delta-y as a table fixed before compression: the largest change
+// that discarding b negabinary digits can make to any code, which is Sec.
+// 4.4.2's truncation uncertainty floor((2^(b+1) - 1) / 3), for every pass
+void errq_to_bound(ipc_stream *s) {
+  StreamMeta &m = s->meta;
+  const size_t P = m.sched.passes.size();
+  m.errq.assign(P * 33, 0u);
+  for (size_t p = 0; p < P; ++p)
+    for (int b = 0; b <= 32; ++b) m.errq[p * 33 + size_t(b)] = uint32_t(((uint64_t(1) << (b + 1)) - 1) / 3);
+  s->tables.errq = m.errq;
+}
+
+// points of a full-precision reconstruction of `s` that miss the bound
+uint64_t verify_stream(ipc_ctx *ctx, const ipc_stream *s, const void *field_dev);
+
 
 // ---------------------------------------------------------------- batches
 
 // Whether a field of these dims would take the fused 3-D path
 bool fused_dims(const uint64_t *dims, int ndim, const ipc_options *opts) {
   if (ndim != 3) return false;
+  if (opts && (opts->debug_flags & IPC_DEBUG_PER_PASS)) return false;
   if (opts)
     for (int j = 0; j < 3; ++j)
       if (opts->chunk_log2[j] != 0) return false;
@@ -1589,7 +1660,7 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
     const int P = int(sc.passes.size());
     const size_t isz = dtype == IPC_F32 ? 4 : 8;
     const size_t nbytes = size_t(sc.n_points) * isz;
-    const bool fused = fused3(sc);
+    const bool fused = fused3(sc) && !(opts && (opts->debug_flags & IPC_DEBUG_PER_PASS));
     void *xh = nullptr;
     if (fused)
       ensure_coarse(ctx, sc, isz);
@@ -1734,6 +1805,7 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
       break;
     }
   });
+  if (st == IPC_OK) st = finish_options(ctx, s, field_dev, opts);
   if (st != IPC_OK) {
     free_stream_bufs(s);
     delete s;
@@ -2382,12 +2454,16 @@ ipc_status ipc_compress_batch(ipc_ctx *ctx, uint32_t n, const void *const *field
   }
   for (uint32_t i = 0; i < n; ++i) out[i] = ss[i];
   // fields whose outliers overflowed the batch's record capacity: again alone
+  // (ipc_compress applies the options to them)
   for (uint32_t i = 0; i < n; ++i) {
-    if (!redo[i]) continue;
-    ipc_stream_free(out[i]);
-    out[i] = nullptr;
-    ipc_status st2 = ipc_compress(ctx, fields_dev[i], dims + size_t(i) * ndim, ndim, dtype, abs_eb[i],
-                                  opts, &out[i]);
+    ipc_status st2 = IPC_OK;
+    if (redo[i]) {
+      ipc_stream_free(out[i]);
+      out[i] = nullptr;
+      st2 = ipc_compress(ctx, fields_dev[i], dims + size_t(i) * ndim, ndim, dtype, abs_eb[i], opts, &out[i]);
+    } else {
+      st2 = finish_options(ctx, out[i], fields_dev[i], opts);
+    }
     if (st2 != IPC_OK) {
       undo(n);
       return st2;

@@ -221,6 +221,9 @@ hipError_t launch_compress_pass_batch(int dtype, int interp, const void *batch_d
 hipError_t launch_retrieve_pass_batch(int dtype, int interp, const void *batch_dev, int nf,
                                       uint32_t n_items, hipStream_t stream);
 // field[i] += delta[i] wherever delta[i] != 0
+// *bad += points where |x - xt| > eb (float64) and the bits differ
+hipError_t launch_verify_bound(int dtype, const void *x, const void *xt, uint64_t n, double eb,
+                               unsigned long long *bad, hipStream_t stream);
 hipError_t launch_add_delta(int dtype, void *field, const void *delta, uint64_t n,
                             hipStream_t stream);
 // Outlier index built on the device from the compression kernels' records

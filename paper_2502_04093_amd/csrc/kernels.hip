@@ -533,6 +533,26 @@ __global__ __launch_bounds__(WG) void k_add_delta(T *f, const T *__restrict__ d,
   }
 }
 
+// Points where a reconstruction misses the error bound: |x - x~| > eb
+// (computed in float64) unless both hold the same bits (values that are not
+// finite are stored exactly).  One atomic per workgroup with misses.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_verify_bound(const T *__restrict__ x, const T *__restrict__ xt,
+                                                      uint64_t n, double eb, unsigned long long *bad) {
+  __shared__ unsigned int s_bad;
+  if (threadIdx.x == 0) s_bad = 0u;
+  __syncthreads();
+  unsigned int mine = 0;
+  for (uint64_t i = uint64_t(blockIdx.x) * WG + threadIdx.x; i < n; i += uint64_t(gridDim.x) * WG) {
+    const T a = x[i], b = xt[i];
+    const bool same = FP<T>::bits(a) == FP<T>::bits(b);
+    if (!same && !(fabs(__dsub_rn(double(b), double(a))) <= eb)) ++mine;
+  }
+  if (mine) atomicAdd(&s_bad, mine);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_bad) atomicAdd(bad, (unsigned long long)s_bad);
+}
+
 // ---- device-side outlier index: records (pass, chunk, local, bits) in any
 // order -> arrays sorted by (global chunk, local) and the first record of
 // every chunk.  Counting sort by chunk, then an insertion sort of each
@@ -803,6 +823,19 @@ hipError_t launch_add_delta(int dtype, void *field, const void *delta, uint64_t 
   else
     hipLaunchKernelGGL(k_add_delta<double>, dim3(grid), dim3(WG), 0, stream,
                        static_cast<double *>(field), static_cast<const double *>(delta), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_verify_bound(int dtype, const void *x, const void *xt, uint64_t n, double eb,
+                               unsigned long long *bad, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  const uint32_t grid = uint32_t(std::min<uint64_t>((n + WG - 1) / WG, 4096));
+  if (dtype == IPC_F32)
+    hipLaunchKernelGGL(k_verify_bound<float>, dim3(grid), dim3(WG), 0, stream,
+                       static_cast<const float *>(x), static_cast<const float *>(xt), n, eb, bad);
+  else
+    hipLaunchKernelGGL(k_verify_bound<double>, dim3(grid), dim3(WG), 0, stream,
+                       static_cast<const double *>(x), static_cast<const double *>(xt), n, eb, bad);
   return hipGetLastError();
 }
 

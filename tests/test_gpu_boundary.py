@@ -84,3 +84,40 @@ def test_host_resident_planes_match_oracle(ctx, coded):
     assert st.tensor().cpu().numpy().tobytes() == o.field.tobytes()
     full = s.retrieve(eb=1e-5 * r)
     assert full.tensor().cpu().numpy().tobytes() == codec.retrieve(ref, "eb", 1e-5 * r).field.tobytes()
+
+
+@pytest.mark.parametrize("shape,dtype", [((33, 47, 129), np.float32), ((96, 70), np.float64)])
+def test_compression_options_match_oracle(ctx, shape, dtype):
+    """ipc_options: errq_mode bound (the fixed delta-y table), lossless coded
+    (entropy-coded blocks), the per-pass debug path and the verification
+    check, each compared with the oracle byte for byte."""
+    from oracle.stream import entropy_code_stream
+    x = fieldgen.random_field(shape, seed=14, dtype=dtype)
+    x.reshape(-1)[7] = np.nan
+    r = fieldgen.value_range(np.nan_to_num(x))
+    eb = 1e-4 * r
+    xd = torch.from_numpy(x).to("cuda:0")
+    exact = codec.compress(x, eb)
+    bound = codec.compress(x, eb, errq_mode="bound")
+    s = ctx.compress(xd, eb, errq_mode="bound")
+    assert s.to_bytes() == bound
+    st = s.retrieve(eb=1e-2 * r)
+    assert st.tensor().cpu().numpy().tobytes() == codec.retrieve(bound, "eb", 1e-2 * r).field.tobytes()
+    s = ctx.compress(xd, eb, lossless="coded")
+    assert s.coding == 1 and s.to_bytes() == entropy_code_stream(exact)
+    s = ctx.compress(xd, eb, debug_flags=pkg.IPC_DEBUG_PER_PASS | pkg.IPC_DEBUG_VERIFY)
+    assert s.to_bytes() == exact
+    s = ctx.compress(xd, eb, errq_mode="bound", lossless="coded", debug_flags=pkg.IPC_DEBUG_VERIFY)
+    assert s.to_bytes() == entropy_code_stream(bound)
+    with pytest.raises(pkg.IpcError) as e:
+        ctx.compress(xd, eb, debug_flags=8)
+    assert e.value.status == -1
+
+
+def test_batch_compression_options(ctx):
+    xs = [fieldgen.random_field((40, 36, 70), seed=20 + i, dtype=np.float32) for i in range(3)]
+    ebs = [1e-4 * fieldgen.value_range(x) for x in xs]
+    ss = ctx.compress_batch([torch.from_numpy(x).to("cuda:0") for x in xs], ebs, errq_mode="bound",
+                            debug_flags=pkg.IPC_DEBUG_VERIFY)
+    for s, x, eb in zip(ss, xs, ebs):
+        assert s.to_bytes() == codec.compress(x, eb, errq_mode="bound")

@@ -66,6 +66,8 @@ def _streams():
         x.reshape(-1)[5] = np.nan
         eb = rel * fieldgen.value_range(np.nan_to_num(x))
         STREAMS.append(codec.compress(x, eb, interp=interp, nonprog_levels=npl))
+        # the bound form of the delta-y table (IPC_ERRQ_BOUND)
+        STREAMS.append(codec.compress(x, eb, interp=interp, nonprog_levels=npl, errq_mode="bound"))
     # the same streams with entropy-coded blocks (plane sizes = coded words)
     STREAMS.extend([entropy_code_stream(b) for b in STREAMS])
     return STREAMS

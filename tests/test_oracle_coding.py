@@ -119,3 +119,27 @@ def test_errq_brute_and_invariants():
         for b in range(33):
             assert int(t[b]) <= ((1 << (b + 1)) - 1) // 3
     assert np.array_equal(coding.errq_table(np.zeros(0, dtype=np.int64)), np.zeros(33))
+
+
+def test_errq_bound_table_is_the_paper_uncertainty():
+    """The bound form of delta-y (IPC_ERRQ_BOUND) is Sec. 4.4.2's Eq.
+    uncertainty for every number of discarded digits, and a code set holding
+    every b-digit pattern attains it (so it is the least bound)."""
+    g = GOLDEN["truncation_uncertainty"]
+    t = coding.errq_bound_table()
+    assert t[0] == 0
+    for b in range(1, 33):
+        form = g["negabinary_odd"] if b % 2 else g["negabinary_even"]
+        assert int(t[b]) == round(form["a"] * 2 ** b + form["b"]), b
+    for b in range(1, 12):
+        qs = np.array([sum(((p >> k) & 1) * (-2) ** k for k in range(b)) for p in range(1 << b)])
+        assert int(coding.errq_table(qs)[b]) == int(t[b])
+
+
+def test_errq_bound_table_dominates_measured_tables():
+    rng = np.random.default_rng(5)
+    t = coding.errq_bound_table().astype(np.int64)
+    for hi in (3, 100, 5000, 1 << 20, (1 << 30) - 1):
+        q = rng.integers(-hi, hi + 1, 2000)
+        m = coding.errq_table(q).astype(np.int64)
+        assert np.all(m <= t), hi

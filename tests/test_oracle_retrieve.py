@@ -288,3 +288,26 @@ def test_stream_validation():
         parse_stream(b"XXXX" + buf[4:])
     with pytest.raises(StreamError):
         parse_stream(buf[:100])
+
+
+@pytest.mark.parametrize("shape,dtype", [((40, 33), np.float32), ((9, 17, 33), np.float64)])
+def test_errq_bound_mode_changes_only_the_table_and_keeps_targets(shape, dtype):
+    """errq_mode="bound": the stream equals the exact one except for its
+    delta-y rows, which are the fixed table; plans built on it meet their
+    targets and load at least as much as plans on the measured table."""
+    x = _field(shape, dtype, seed=9)
+    r = fieldgen.value_range(x)
+    eb = 1e-5 * r
+    a = parse_stream(codec.compress(x, eb))
+    bbuf = codec.compress(x, eb, errq_mode="bound")
+    b = parse_stream(bbuf)
+    assert np.array_equal(a.masks, b.masks) and np.array_equal(a.payload, b.payload)
+    assert np.array_equal(a.out_keys, b.out_keys) and a.out_vals.tobytes() == b.out_vals.tobytes()
+    assert all(np.array_equal(row, coding.errq_bound_table()) for row in b.errq)
+    exact = codec.compress(x, eb)
+    for rel in (1e-1, 1e-2, 1e-3, 1e-4):
+        E = rel * r
+        st = codec.retrieve(bbuf, "eb", E)
+        err = np.max(np.abs(st.field.astype(np.float64) - x.astype(np.float64)))
+        assert err <= st.bound <= E
+        assert st.bytes_read >= codec.retrieve(exact, "eb", E).bytes_read
