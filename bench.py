@@ -407,9 +407,15 @@ def batch_main(args):
         for st in ctx.retrieve_batch(ss, eb=ebs):
             st.free()
 
+    def compress_only():
+        for s in ctx.compress_batch(xs, ebs):
+            s.free()
+
     tr_direct = timed(retrieve_only)
+    tc_direct = timed(compress_only)
     ctx.set_batch_graphs(True)
     tr_graph = timed(retrieve_only)
+    tc_graph = timed(compress_only)
     ctx.set_batch_graphs(False)
     for s in ss:
         s.free()
@@ -426,6 +432,8 @@ def batch_main(args):
         "batched_retrieve_ms": {"direct_launches": round(tr_direct * 1e3, 4),
                                 "graph_replay": round(tr_graph * 1e3, 4),
                                 "graphs": ctx.graph_stats()},
+        "batched_compress_ms": {"direct_launches": round(tc_direct * 1e3, 4),
+                                "graph_replay": round(tc_graph * 1e3, 4)},
     }
     print(json.dumps(out), flush=True)
     ctx.close()
@@ -544,7 +552,10 @@ def variants_main(args):
     per-pass groups and with the paper's per-level groups.  (2) The
     progressive run 1e-2 -> 1e-3 -> 1e-4 -> 1e-5 -> 1e-6 * range refined in
     the recompute form and in the additive form: device time per step, bound,
-    max error and the largest difference between the two reconstructions."""
+    max error and the largest difference between the two reconstructions,
+    beside a fresh retrieval to the same target.  (3) The non-progressive head
+    L_p = 0..4 (the top levels always loaded): stream size, bytes loaded and
+    bound at 1e-2 and 1e-4 * range, bound and error at 1 bit per value."""
     import numpy as np
     import torch
 
@@ -584,9 +595,15 @@ def variants_main(args):
     for rel in (1e-3, 1e-4, 1e-5, 1e-6):
         ia = a.refine(eb=rel * r)
         ib = b.refine_additive(eb=rel * r)
+        # a fresh retrieval to the same target (the same plan) for comparison
+        fr = s.retrieve(eb=rel * r)
+        fresh_ms = fr.info.t_device_ms
+        same_plan = fr.plan == a.plan
+        fr.free()
         ta, tb = a.tensor().double(), b.tensor().double()
         row = {"target": f"eb={rel:g}*range",
                "recompute_ms": round(ia.t_device_ms, 3), "additive_ms": round(ib.t_device_ms, 3),
+               "fresh_retrieve_ms": round(fresh_ms, 3), "fresh_same_plan": bool(same_plan),
                "recompute_bound": ia.bound, "additive_bound": ib.bound,
                "recompute_maxerr": float((ta - xd).abs().max()),
                "additive_maxerr": float((tb - xd).abs().max()),
@@ -598,6 +615,28 @@ def variants_main(args):
     a.free()
     b.free()
     s.free()
+    # the non-progressive head (L_p of Alg. 1): the top levels always loaded
+    head = []
+    for npl in (0, 1, 2, 3, 4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sh = ctx.compress(x, 1e-6 * r, nonprog_levels=npl)
+        torch.cuda.synchronize()
+        row = {"nonprog_levels": npl, "stream_bytes": int(sh.nbytes),
+               "compress_ms": round((time.perf_counter() - t0) * 1e3, 3)}
+        for rel in (1e-2, 1e-4):
+            st = sh.retrieve(eb=rel * r)
+            row[f"eb={rel:g}*range"] = {"bytes_loaded": int(st.info.bytes_loaded), "bound": st.info.bound,
+                                        "device_ms": round(st.info.t_device_ms, 3)}
+            st.free()
+        for br in (1.0,):
+            st = sh.retrieve(bitrate=br)
+            row[f"bitrate={br:g}"] = {"bound": st.info.bound,
+                                     "maxerr": float((st.tensor().double() - xd).abs().max())}
+            st.free()
+        sh.free()
+        head.append(row)
+        print(f"[bench] nonprog {row}", file=sys.stderr, flush=True)
     out = {
         "metric": "paper variants on 512^3 f32 GRF compressed at eb=1e-6*range",
         "value": round(sum(r_["additive_ms"] for r_ in refine), 3), "unit": "ms (additive refine steps)",
@@ -607,7 +646,7 @@ def variants_main(args):
         "data": "synthetic",
         "config": {"workload": "per-pass vs per-level plane groups; recompute vs additive "
                                "refinement 1e-2 -> 1e-6 * range"},
-        "plane_groups": groups, "refinement": refine,
+        "plane_groups": groups, "refinement": refine, "nonprog_head": head,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

@@ -653,7 +653,10 @@ void run_retrieve(ipc_ctx *ctx, const ipc_stream *s, const std::vector<int> &pla
       g[1] = ctx->ws_g[1];
     }
     int l_start = sc.K;
-    if (s0 <= 0) {
+    // a refinement that starts in the top level rebuilds the top coarse grid
+    // from the anchors (always fully loaded, so the same values) instead of
+    // gathering it from the resident field
+    if (s0 <= 0 || sc.passes[size_t(s0)].level == sc.K) {
       Level3Args A = anchor3_args(sc);
       prof_mark(ctx, 0, true);
       hip_check(ctx, launch_anchor3_retrieve(s->meta.dtype, A, g[sc.K & 1], in, s->meta.eb,
@@ -1104,8 +1107,10 @@ constexpr size_t Q_CLAIMS = 256;    // bytes of claim counters before the table
 constexpr size_t Q_GRAPHS = 64;     // cached graphs (the cache is cleared beyond)
 
 size_t queue_table_bytes() {
-  const size_t h = std::max(sizeof(HeadR<float>), sizeof(HeadR<double>));
-  const size_t e = std::max(sizeof(BatchR<float>), sizeof(BatchR<double>));
+  const size_t h = std::max({sizeof(HeadR<float>), sizeof(HeadR<double>), sizeof(HeadC<float>),
+                             sizeof(HeadC<double>)});
+  const size_t e = std::max({sizeof(BatchR<float>), sizeof(BatchR<double>), sizeof(BatchC<float>),
+                             sizeof(BatchC<double>)});
   // + 256: the entries start at the next 256-byte boundary after the heads
   return ((sizeof(QueueTable) + 255) & ~size_t(255)) + Q_HEADS * h + 256 + Q_ENTRIES * e;
 }
@@ -1116,6 +1121,14 @@ uint32_t queue_grid(const ipc_ctx *ctx, uint32_t items, size_t isz) {
   if (items <= 16) return 16;
   if (items <= 128) return 128;
   return full;
+}
+
+// ... and of a compression slot (its kernel runs 4 workgroups per CU in
+// float32, 2 in float64)
+uint32_t queue_grid_c(const ipc_ctx *ctx, uint32_t items, size_t isz) {
+  if (items <= 16) return 16;
+  if (items <= 128) return 128;
+  return uint32_t(ctx->n_cu) * (isz == 4 ? 4u : 2u);
 }
 
 bool queue_fits(const std::vector<const ipc_stream *> &ss) {
@@ -1267,6 +1280,226 @@ void retrieve_batch_levels(ipc_ctx *ctx, const std::vector<const ipc_stream *> &
     ctx->batch_graphs = false;  // this stream cannot be captured: direct launches from now on
   }
   retrieve_batch_fused<T>(ctx, ss, plans, out, l_start);
+}
+
+// Batched compression of fused 3-D fields as queue launches replayed from a
+// captured graph: one persistent launch per level slot whose workgroups claim
+// (field, column segment) items from a device counter, the anchors of every
+// field in one launch before them.  Everything a batch varies in (fields,
+// outputs, bounds, work lists) sits in the device table, so the graph depends
+// only on dtype, interpolation, level count and the grid classes.  The
+// per-field row reductions, outlier indexes and the summary copy follow as
+// direct launches.  Returns false (nothing launched but the table upload)
+// when the context's stream cannot be captured.
+template <typename T>
+bool compress_batch_queue(ipc_ctx *ctx, std::vector<ipc_stream *> &ss, const void *const *fields,
+                          const double *ebs, std::vector<char> &redo) {
+  const int n = int(ss.size());
+  const int dtype = ss[0]->meta.dtype, interp = ss[0]->meta.interp;
+  const size_t isz = sizeof(T);
+  if (!ctx->ws_q) {
+    ctx->ws_q_bytes = Q_CLAIMS + queue_table_bytes();
+    hip_check(ctx, hipMalloc(&ctx->ws_q, ctx->ws_q_bytes), "queue table allocation");
+    hip_check(ctx, hipHostMalloc(&ctx->host_q, queue_table_bytes(), hipHostMallocDefault),
+              "pinned allocation");
+  }
+  uint32_t *claims = static_cast<uint32_t *>(ctx->ws_q);
+  QueueTable *tab_dev = reinterpret_cast<QueueTable *>(static_cast<char *>(ctx->ws_q) + Q_CLAIMS);
+  char *host = static_cast<char *>(ctx->host_q);
+  // the previous call's table upload has completed (its call synchronized)
+  QueueTable &tab = *reinterpret_cast<QueueTable *>(host);
+  std::memset(&tab, 0, sizeof(tab));
+  tab.n_heads = uint32_t(n);
+  tab.heads_off = uint32_t((sizeof(QueueTable) + 255) & ~size_t(255));
+  HeadC<T> *heads = reinterpret_cast<HeadC<T> *>(host + tab.heads_off);
+  tab.ent_off = uint32_t(tab.heads_off + ((size_t(n) * sizeof(HeadC<T>) + 255) & ~size_t(255)));
+  BatchC<T> *ent = reinterpret_cast<BatchC<T> *>(host + tab.ent_off);
+
+  // per-field summary blocks and record ranges (as compress_batch_fused)
+  std::vector<size_t> sum_off(n + 1, 0), rec_off(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    const Schedule &sc = ss[i]->meta.sched;
+    sum_off[i + 1] = sum_off[i] + ((summary_bytes(int(sc.passes.size())) + 255) & ~size_t(255));
+    rec_off[i + 1] = rec_off[i] + std::max<size_t>(4096, size_t(sc.n_points / 1024));
+  }
+  char *summary = static_cast<char *>(ensure_ws(ctx, ctx->ws_summary, ctx->ws_summary_bytes, sum_off[n]));
+  ensure_ws(ctx, ctx->ws_out, ctx->ws_out_cap, rec_off[n] * sizeof(OutlierRec));
+  std::vector<PassArgs> args;
+  std::vector<size_t> args_off(n);
+  for (int i = 0; i < n; ++i) {
+    args_off[i] = args.size();
+    args.insert(args.end(), ss[i]->args.begin(), ss[i]->args.end());
+  }
+  DevBuf args_dev = dev_alloc(ctx, args.size() * sizeof(PassArgs));
+  std::vector<DevBuf> g(2 * n);
+  struct Release {
+    ipc_ctx *ctx;
+    std::vector<DevBuf> &g;
+    DevBuf &args_dev;
+    ~Release() {
+      (void)hipStreamSynchronize(ctx->stream);
+      for (DevBuf &b : g) dev_free(ctx, b);
+      dev_free(ctx, args_dev);
+    }
+  } release{ctx, g, args_dev};
+  hip_check(ctx, hipMemcpyAsync(args_dev.p, args.data(), args.size() * sizeof(PassArgs),
+                                hipMemcpyHostToDevice, ctx->stream), "upload");
+  hip_check(ctx, hipMemsetAsync(summary, 0, sum_off[n], ctx->stream), "memset");
+  std::vector<CompressOut> o(n);
+  int Kmax = 0;
+  for (int i = 0; i < n; ++i) {
+    const Schedule &sc = ss[i]->meta.sched;
+    Kmax = std::max(Kmax, sc.K);
+    size_t need[2] = {8, 8};
+    for (int j = 1; j <= sc.K; ++j)
+      need[j & 1] = std::max(need[j & 1], size_t(coarse_points(sc, j)) * isz);
+    g[2 * i] = dev_alloc(ctx, need[0]);
+    g[2 * i + 1] = dev_alloc(ctx, need[1]);
+    char *sm = summary + sum_off[i];
+    const int P = int(sc.passes.size());
+    o[i].payload = static_cast<uint32_t *>(ss[i]->payload.p);
+    o[i].masks = static_cast<uint32_t *>(ss[i]->masks.p);
+    o[i].n_out = reinterpret_cast<unsigned long long *>(sm);
+    o[i].maxabs_bits = reinterpret_cast<unsigned long long *>(sm + 8);
+    o[i].sizes = reinterpret_cast<unsigned long long *>(sm + 16);
+    o[i].errq = reinterpret_cast<uint32_t *>(sm + 16 + size_t(P) * 32 * 8);
+    o[i].out_recs = static_cast<OutlierRec *>(ctx->ws_out) + rec_off[i];
+    o[i].out_cap = rec_off[i + 1] - rec_off[i];
+  }
+  // level slots (level Kmax - slot) and every field's rows
+  std::vector<LevelRows> lr(n);
+  for (LevelRows &r : lr) std::memset(&r, 0, sizeof(r));
+  uint32_t rows = 0;
+  size_t m = 0;
+  std::vector<int> key = {dtype + 16, interp, Kmax};  // 16 + dtype: compression graphs
+  for (int slot = 0; slot < Kmax; ++slot) {
+    const int l = Kmax - slot;
+    QueueLevel &q = tab.lev[slot];
+    q.off = uint32_t(m);
+    for (int i = 0; i < n; ++i) {
+      const Schedule &sc = ss[i]->meta.sched;
+      if (l > sc.K) continue;
+      Level3Args La = level_args(ctx, ss[i]->meta, l, true);
+      La.row_base = rows;
+      const uint32_t items = uint32_t(level3_wgs(La));
+      LevelRows &r = lr[i];
+      if (r.n >= MAX_LEVEL_LAUNCHES) {
+        set_err(ctx, "too many levels for the fused kernels");
+        throw Fail{IPC_EUNSUPPORTED};
+      }
+      r.row_base[r.n] = rows;
+      r.n_rows[r.n] = items;
+      for (int p = 0; p < 3; ++p) r.pass_index[r.n][p] = La.pass_index[p];
+      ++r.n;
+      rows += items;
+      BatchC<T> &e = ent[m++];
+      std::memset(&e, 0, sizeof(e));
+      e.L = La;
+      e.x = static_cast<const T *>(fields[i]);
+      e.gin = static_cast<const T *>(g[2 * i + (l & 1)].p);
+      e.gout = l > 1 ? static_cast<T *>(g[2 * i + ((l - 1) & 1)].p) : nullptr;
+      e.o = o[i];
+      e.eb = ebs[i];
+      e.two_eb = T(2.0 * ebs[i]);
+      e.inv = T(1.0 / (2.0 * ebs[i]));
+      e.qmax = T(sizeof(T) == 4 ? QMAX_F32 : QMAX_F64);
+      e.item0 = q.items;
+      ++q.nf;
+      q.items += items;
+    }
+    key.push_back(int(queue_grid_c(ctx, q.items, isz)));
+  }
+  uint32_t *rows_p = static_cast<uint32_t *>(
+      ensure_ws(ctx, ctx->ws_rows, ctx->ws_rows_bytes, size_t(rows) * WG_ROW * 4));
+  for (size_t k = 0; k < m; ++k) ent[k].o.wg_rows = rows_p;
+  for (int i = 0; i < n; ++i) {
+    o[i].wg_rows = rows_p;
+    HeadC<T> &h = heads[i];
+    std::memset(&h, 0, sizeof(h));
+    const Schedule &sc = ss[i]->meta.sched;
+    h.A = anchor3_args(sc);
+    h.x = static_cast<const T *>(fields[i]);
+    h.g = static_cast<T *>(g[2 * i + (sc.K & 1)].p);
+    h.o = o[i];
+    h.eb = ebs[i];
+    h.two_eb = T(2.0 * ebs[i]);
+    h.inv = T(1.0 / (2.0 * ebs[i]));
+    h.qmax = T(sizeof(T) == 4 ? QMAX_F32 : QMAX_F64);
+  }
+  const size_t bytes = tab.ent_off + m * sizeof(BatchC<T>);
+  hip_check(ctx, hipMemcpyAsync(tab_dev, host, bytes, hipMemcpyHostToDevice, ctx->stream), "upload");
+
+  auto it = ctx->graphs.find(key);
+  if (it == ctx->graphs.end()) {
+    if (ctx->graphs.size() >= Q_GRAPHS) {
+      for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+      ctx->graphs.clear();
+    }
+    if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    hipError_t e = launch_queue_reset(claims, ctx->stream);
+    if (e == hipSuccess) e = launch_heads_compress(dtype, tab_dev, ctx->stream);
+    for (int slot = 0; slot < Kmax && e == hipSuccess; ++slot)
+      e = launch_level3_compress_queue(dtype, interp, tab_dev, slot, claims, uint32_t(key[3 + slot]),
+                                       ctx->stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->stream, &graph);
+    if ((e != hipSuccess || ec != hipSuccess) && graph) (void)hipGraphDestroy(graph);
+    hip_check(ctx, e, "queue launch capture");
+    hip_check(ctx, ec, "end capture");
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    hip_check(ctx, ei, "graph instantiate");
+    it = ctx->graphs.emplace(key, exec).first;
+    ++ctx->graphs_captured;
+  }
+  hip_check(ctx, hipGraphLaunch(it->second, ctx->stream), "graph launch");
+  ++ctx->graph_replays;
+  // per field: rows -> errq, max |x^|, plane sizes; the outlier index
+  for (int i = 0; i < n; ++i) {
+    ipc_stream *s = ss[i];
+    hip_check(ctx, launch_rows_reduce(lr[i], rows_p, o[i].errq, o[i].maxabs_bits, o[i].sizes, ctx->stream),
+              "row reduction launch");
+    const uint64_t nc = uint64_t(s->meta.sched.n_chunks);
+    const size_t cap = size_t(o[i].out_cap);
+    s->out_gchunk = dev_alloc(ctx, 8 * cap);
+    s->out_local = dev_alloc(ctx, 4 * cap);
+    s->out_bits = dev_alloc(ctx, 8 * cap);
+    s->out_start = dev_alloc(ctx, 4 * (nc + 1));
+    const size_t nb = (nc + 1 + 1023) / 1024;
+    uint32_t *cnt = static_cast<uint32_t *>(
+        ensure_ws(ctx, ctx->ws_cnt, ctx->ws_cnt_bytes, 4 * (nc + 1) + 4 * (nb + 1)));
+    hip_check(ctx, launch_outlier_index(static_cast<const OutlierRec *>(o[i].out_recs), o[i].n_out, cap,
+                                        static_cast<const PassArgs *>(args_dev.p) + args_off[i], nc,
+                                        static_cast<uint32_t *>(s->out_start.p), cnt, cnt + (nc + 1),
+                                        static_cast<uint64_t *>(s->out_gchunk.p),
+                                        static_cast<uint32_t *>(s->out_local.p),
+                                        static_cast<uint64_t *>(s->out_bits.p), ctx->stream),
+              "outlier index launch");
+  }
+  if (ctx->host_summary_bytes < sum_off[n]) {
+    if (ctx->host_summary) (void)hipHostFree(ctx->host_summary);
+    ctx->host_summary = nullptr;
+    ctx->host_summary_bytes = 0;
+    hip_check(ctx, hipHostMalloc(&ctx->host_summary, sum_off[n], hipHostMallocDefault), "pinned alloc");
+    ctx->host_summary_bytes = sum_off[n];
+  }
+  char *hostp = static_cast<char *>(ctx->host_summary);
+  hip_check(ctx, hipMemcpyAsync(hostp, summary, sum_off[n], hipMemcpyDeviceToHost, ctx->stream), "copy");
+  hip_check(ctx, hipStreamSynchronize(ctx->stream), "compress");
+  for (int i = 0; i < n; ++i) {
+    uint64_t nout;
+    std::memcpy(&nout, hostp + sum_off[i], 8);
+    if (nout > o[i].out_cap) {
+      redo[i] = 1;
+      continue;
+    }
+    finish_stream(ss[i], hostp + sum_off[i], nout);
+  }
+  return true;
 }
 
 // Compression of n fields on the one-pass-per-launch path (2-D, 1-D, other
@@ -2433,10 +2666,21 @@ ipc_status ipc_compress_batch(ipc_ctx *ctx, uint32_t n, const void *const *field
       setup_stream(ctx, ss[i], dims + size_t(i) * ndim, ndim, dtype, interp, abs_eb[i], opts);
     }
     if (fused) {
-      if (dtype == IPC_F32)
-        compress_batch_fused<float>(ctx, ss, fields_dev, abs_eb, redo);
-      else
-        compress_batch_fused<double>(ctx, ss, fields_dev, abs_eb, redo);
+      // queue launches from a captured graph when the context asks for them
+      // and the batch fits the table; otherwise one direct launch per level
+      std::vector<const ipc_stream *> cs(ss.begin(), ss.end());
+      bool done = false;
+      if (ctx->batch_graphs && queue_fits(cs)) {
+        done = dtype == IPC_F32 ? compress_batch_queue<float>(ctx, ss, fields_dev, abs_eb, redo)
+                                : compress_batch_queue<double>(ctx, ss, fields_dev, abs_eb, redo);
+        if (!done) ctx->batch_graphs = false;  // this stream cannot be captured
+      }
+      if (!done) {
+        if (dtype == IPC_F32)
+          compress_batch_fused<float>(ctx, ss, fields_dev, abs_eb, redo);
+        else
+          compress_batch_fused<double>(ctx, ss, fields_dev, abs_eb, redo);
+      }
     } else {
       if (dtype == IPC_F32)
         compress_batch_passes<float>(ctx, ss, fields_dev, abs_eb, redo);

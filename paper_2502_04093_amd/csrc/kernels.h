@@ -160,6 +160,21 @@ struct HeadR {
   T two_eb;
   int32_t mode;
 };
+// Anchor job of a queued compression batch (one per field)
+template <typename T>
+struct HeadC {
+  Level3Args A;
+  const T *x;
+  T *g;
+  CompressOut o;
+  double eb;
+  T two_eb, inv, qmax;
+};
+// every anchor job of a compression table (grid of QUEUE_HEAD_WGS workgroups)
+hipError_t launch_heads_compress(int dtype, const QueueTable *tab, hipStream_t s);
+// one level slot of a compression table (its work list holds BatchC<T>)
+hipError_t launch_level3_compress_queue(int dtype, int interp, const QueueTable *tab, int slot,
+                                        uint32_t *claims, uint32_t grid, hipStream_t s);
 // claim counters (QUEUE_LEVELS words) set to zero
 hipError_t launch_queue_reset(uint32_t *claims, hipStream_t s);
 // every head job of the table (grid of QUEUE_HEAD_WGS workgroups)

@@ -1584,12 +1584,12 @@ __global__ __launch_bounds__(WG3, sizeof(T) == 4 ? 5 : 4) void k_level3_retrieve
 }
 
 // anchors of a fused compression: quantize against 0 into the compact coarse grid
+// (every thread of the workgroup calls it: it synchronizes the workgroup)
 template <typename T>
-__global__ void k_anchor3_compress(Level3Args L, const T *__restrict__ x, T *gout, double eb,
-                                   T two_eb, T inv, T qmax, CompressOut o) {
+__device__ __forceinline__ void anchor3_compress_body(const Level3Args &L, const T *__restrict__ x, T *gout,
+                                                      double eb, T two_eb, T inv, T qmax,
+                                                      const CompressOut &o, uint32_t *sv, uint32_t &sor) {
   using F = F3<T>;
-  __shared__ uint32_t sv[64];
-  __shared__ uint32_t sor;
   const int tid = threadIdx.x;
   const int n = L.L[0] * L.L[1] * L.L[2];  // anchor grid (<= 2 per dimension)
   if (tid == 0) sor = 0;
@@ -1646,6 +1646,14 @@ __global__ void k_anchor3_compress(Level3Args L, const T *__restrict__ x, T *gou
     atomicMax(o.errq + b, mxv);
   }
   if (mb) atomicMax(o.maxabs_bits, mb);
+}
+
+template <typename T>
+__global__ void k_anchor3_compress(Level3Args L, const T *__restrict__ x, T *gout, double eb,
+                                   T two_eb, T inv, T qmax, CompressOut o) {
+  __shared__ uint32_t sv[64];
+  __shared__ uint32_t sor;
+  anchor3_compress_body<T>(L, x, gout, eb, two_eb, inv, qmax, o, sv, sor);
 }
 
 // anchors of a fused retrieval: anchor `tid` of the anchor grid (the caller
@@ -1744,6 +1752,52 @@ __global__ __launch_bounds__(WG3, sizeof(T) == 4 ? 5 : 4) void k_level3_retrieve
     item_tile(b.L, it - b.item0, tx, ty, zs);
     level3_retrieve_body<T, INTERP>(b.L, b.gin, b.gout, b.disc[0], b.disc[1], b.disc[2], b.in,
                                     b.two_eb, tx, ty, zs, S);
+  }
+}
+
+// The anchor jobs of a queued compression batch: field f by workgroup
+// f mod grid (the first 64 threads; the anchor grid has at most 8 points)
+template <typename T>
+__global__ __launch_bounds__(256) void k_heads_compress(const QueueTable *__restrict__ tab) {
+  __shared__ uint32_t sv[64];
+  __shared__ uint32_t sor;
+  const uint32_t n = tab->n_heads;
+  const HeadC<T> *h = reinterpret_cast<const HeadC<T> *>(reinterpret_cast<const char *>(tab) + tab->heads_off);
+  for (uint32_t f = blockIdx.x; f < n; f += gridDim.x) {
+    const HeadC<T> &hd = h[f];
+    anchor3_compress_body<T>(hd.A, hd.x, hd.g, hd.eb, hd.two_eb, hd.inv, hd.qmax, hd.o, sv, sor);
+    __syncthreads();
+  }
+}
+
+// One level slot of a queued compression batch: a persistent grid whose
+// workgroups claim work items (column segments of the slot's fields, in
+// work-list order) from the slot's counter until the list is exhausted, as
+// k_level3_retrieve_queue does; every workgroup leaves once a claim passes
+// the item count.
+template <typename T, int INTERP>
+__global__ __launch_bounds__(WG3, sizeof(T) == 4 ? 4 : 2) void k_level3_compress_queue(
+    const QueueTable *__restrict__ tab, int slot, uint32_t *claims) {
+  __shared__ SharedC<T> S;
+  __shared__ uint32_t s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(claims + slot, 1u);
+    __syncthreads();
+    const uint32_t it = s_item;
+    // every thread has read the claim before the next one overwrites it
+    __syncthreads();
+    const QueueLevel &q = tab->lev[slot];
+    if (it >= q.items) break;
+    const BatchC<T> *bf =
+        reinterpret_cast<const BatchC<T> *>(reinterpret_cast<const char *>(tab) + tab->ent_off) + q.off;
+    const BatchC<T> &b = bf[item_field(bf, int(q.nf), it)];
+    const uint32_t li = it - b.item0;
+    int tx, ty, zs;
+    item_tile(b.L, li, tx, ty, zs);
+    level3_compress_body<T, INTERP>(b.L, b.x, b.gin, b.gout, b.eb, b.two_eb, b.inv, b.qmax, b.o, tx,
+                                    ty, zs, b.L.row_base + li, S);
+    // the body's last LDS reads are done before the next item clears it
+    __syncthreads();
   }
 }
 
@@ -1966,6 +2020,32 @@ hipError_t launch_level3_retrieve_queue(int dtype, int interp, const QueueTable 
       hipLaunchKernelGGL((k_level3_retrieve_queue<double, IPC_LINEAR>), g, dim3(WG3), 0, s, tab, slot, claims);
     else
       hipLaunchKernelGGL((k_level3_retrieve_queue<double, IPC_CUBIC>), g, dim3(WG3), 0, s, tab, slot, claims);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_heads_compress(int dtype, const QueueTable *tab, hipStream_t s) {
+  if (dtype == IPC_F32)
+    hipLaunchKernelGGL(k_heads_compress<float>, dim3(QUEUE_HEAD_WGS), dim3(256), 0, s, tab);
+  else
+    hipLaunchKernelGGL(k_heads_compress<double>, dim3(QUEUE_HEAD_WGS), dim3(256), 0, s, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_level3_compress_queue(int dtype, int interp, const QueueTable *tab, int slot,
+                                        uint32_t *claims, uint32_t grid, hipStream_t s) {
+  if (grid == 0 || slot < 0 || slot >= QUEUE_LEVELS) return hipErrorInvalidValue;
+  const dim3 g(grid);
+  if (dtype == IPC_F32) {
+    if (interp == IPC_LINEAR)
+      hipLaunchKernelGGL((k_level3_compress_queue<float, IPC_LINEAR>), g, dim3(WG3), 0, s, tab, slot, claims);
+    else
+      hipLaunchKernelGGL((k_level3_compress_queue<float, IPC_CUBIC>), g, dim3(WG3), 0, s, tab, slot, claims);
+  } else {
+    if (interp == IPC_LINEAR)
+      hipLaunchKernelGGL((k_level3_compress_queue<double, IPC_LINEAR>), g, dim3(WG3), 0, s, tab, slot, claims);
+    else
+      hipLaunchKernelGGL((k_level3_compress_queue<double, IPC_CUBIC>), g, dim3(WG3), 0, s, tab, slot, claims);
   }
   return hipGetLastError();
 }

@@ -134,3 +134,38 @@ def test_graph_serve_batch_refinements(ctx):
     assert replays >= 3
     for s in ss:
         s.free()
+
+
+def _compress_graphs(ctx, xs, ebs, interp):
+    ctx.set_batch_graphs(True)
+    try:
+        return ctx.compress_batch([_dev(x) for x in xs], ebs, interp=interp)
+    finally:
+        ctx.set_batch_graphs(False)
+
+
+@pytest.mark.parametrize("dtype,interp", [(np.float32, "cubic"), (np.float64, "linear")])
+def test_batched_compression_from_graph_replays_equals_oracle(ctx, dtype, interp):
+    """Batched compression as persistent queue launches replayed from a
+    captured graph: every stream equals the oracle's byte for byte, over a
+    capture and two replays with new fields, with eager device work and
+    synchronizations between them; uneven fields share the launches."""
+    from oracle import predict
+    it = predict.CUBIC if interp == "cubic" else predict.LINEAR
+    c0, _ = ctx.graph_stats()
+    shapes = [(40, 70, 130), (17, 33, 65), (64, 64, 64)]
+    for rep in range(3):
+        print(f"compress graphs: {dtype.__name__} {interp} replay {rep}", flush=True)
+        xs = [fieldgen.grf(sh, -5.0 / 6.0, seed=100 + 10 * rep + i, dtype=dtype) for i, sh in enumerate(shapes)]
+        if rep == 1:
+            xs[0].reshape(-1)[11] = np.nan  # an outlier record through the queue path
+        ebs = [1e-4 * fieldgen.value_range(np.nan_to_num(x)) for x in xs]
+        ss = _compress_graphs(ctx, xs, ebs, interp)
+        junk = torch.randn(1 << 20, device="cuda:0") * 2.0  # other work between replays
+        torch.cuda.synchronize()
+        del junk
+        for x, e, s in zip(xs, ebs, ss):
+            assert s.to_bytes() == codec.compress(x, e, interp=it)
+            s.free()
+    c1, r1 = ctx.graph_stats()
+    assert c1 - c0 == 1  # one launch shape: captured once, replayed
