@@ -223,7 +223,8 @@ ipc_status ipc_retrieve_plan(ipc_ctx *ctx, const ipc_stream *s, const uint8_t *p
  * reconstruction of ipc_retrieve (same plan, same bytes) written into the
  * caller's `field_dev` (capacity bytes, at least n * itemsize, C order, the
  * stream's dtype), with no state created and no device allocation of any
- * kind.  The fused 3-D path keeps its compact coarse grids in a library
+ * kind.  The fused level path (3-D and 2-D fields with the default chunk
+ * shape) keeps its compact coarse grids in a library
  * scratch array of IPC_NOALLOC_SCRATCH_BYTES bytes per device, held from the
  * first context on that device until the process ends; a stream whose coarse
  * grids need more (about n * itemsize / 7, so 3-D fields above roughly
@@ -266,8 +267,8 @@ void ipc_state_free(ipc_state *st);
 ipc_status ipc_refine_additive(ipc_ctx *ctx, ipc_state *st, ipc_target target, ipc_info *info);
 
 /* Batches (beyond the paper, which compresses one field at a time): n fields
- * or streams in one call.  Fields of 3-D shape with the default chunk shape
- * share one kernel launch per level (a work list of every field's column
+ * or streams in one call.  Fields of 3-D or 2-D shape with the default chunk
+ * shape share one kernel launch per level (a work list of every field's column
  * segments; a field with fewer levels joins from its top level on), which
  * keeps the device full where single small levels would not.  Results are
  * bit-identical to n separate calls, which is also what other shapes get.
@@ -352,7 +353,8 @@ void ipc_server_destroy(ipc_server *srv);
  * shape, batched ones included, use the choices.  Outputs never depend on
  * the column length.  zseg_c / zseg_r (NULL, or `capacity` entries indexed
  * by level; 0 = no fused launch) receive the choices.  IPC_EUNSUPPORTED for
- * shapes without fused launches.  ipc_autotune_clear forgets every choice. */
+ * shapes without fused 3-D launches (2-D fields have one chunk row per
+ * column, so nothing to choose).  ipc_autotune_clear forgets every choice. */
 ipc_status ipc_autotune(ipc_ctx *ctx, const void *field_dev, const uint64_t *dims, int ndim,
                         int dtype, double abs_eb, const ipc_options *opts, int32_t *zseg_c,
                         int32_t *zseg_r, uint32_t capacity);
@@ -382,8 +384,8 @@ ipc_status ipc_ctx_pass_times(const ipc_ctx *ctx, float *ms, uint32_t capacity, 
 /* Batched retrievals as graph replays (the batching of many uneven fields by
  * one persistent launch per level that the problem statement asks for).
  * When on, ipc_retrieve_batch and the retrievals and refinements of
- * ipc_serve_batch over fused 3-D streams (3-D fields with the default chunk
- * shape; at most 2048 of them and 16384 level work lists per call) run as
+ * ipc_serve_batch over fused streams (3-D and 2-D fields with the default
+ * chunk shape; at most 2048 of them and 16384 level work lists per call) run as
  * queue launches: the per-field head jobs, then for each level one
  * persistent grid whose workgroups claim column segments of every field at
  * that level from a device counter.  Everything that varies from batch to

@@ -30,7 +30,7 @@ from typing import List, Tuple
 
 import numpy as np
 
-DEFAULT_CHUNK_LOG2 = {1: (12,), 2: (5, 6), 3: (1, 4, 6)}
+DEFAULT_CHUNK_LOG2 = {1: (12,), 2: (4, 6), 3: (1, 4, 6)}
 
 ANY, ODD, EVEN = 0, 1, 2
 

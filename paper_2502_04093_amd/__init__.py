@@ -321,9 +321,11 @@ class Context:
         _check(lib().ipc_autotune_clear(self._p), self._p)
 
     def compress_batch(self, fields, ebs, interp: str = "cubic", nonprog_levels: int = 0,
-                       errq_mode: str = "exact", lossless: str = "zwe", debug_flags: int = 0):
+                       errq_mode: str = "exact", lossless: str = "zwe", debug_flags: int = 0,
+                       chunk_log2: Optional[Sequence[int]] = None):
         """Compress several device tensors of one dtype and rank in one call
-        (3-D fields share one launch per level); returns a list of Streams."""
+        (3-D and 2-D fields with the default chunks share one launch per
+        level, other fields one launch per pass); returns a list of Streams."""
         import torch
         n = len(fields)
         if n == 0 or len(ebs) != n:
@@ -340,7 +342,7 @@ class Context:
         ptrs = (c_void_p * n)(*[f.data_ptr() for f in fields])
         dims = (c_uint64 * (n * nd))(*[d for f in fields for d in f.shape])
         eba = (c_double * n)(*[float(e) for e in ebs])
-        opts = _options(interp, nonprog_levels, None, errq_mode, lossless, debug_flags)
+        opts = _options(interp, nonprog_levels, chunk_log2, errq_mode, lossless, debug_flags)
         out = (c_void_p * n)()
         _check(lib().ipc_compress_batch(self._p, n, ptrs, dims, nd,
                                         IPC_F32 if dt == torch.float32 else IPC_F64, eba,

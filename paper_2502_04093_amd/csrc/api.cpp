@@ -497,12 +497,14 @@ void fill_info(const ipc_stream *s, const std::vector<int> &plan, double bound, 
 
 Level3Args level3_args(const Schedule &s, int l, int64_t fill = 1024);
 
-// The fused level kernels cover 3-D fields with the default chunk shape whose
-// level-1 launch fits the grid limits (their tile arithmetic is 32-bit).
+// The fused level kernels cover 3-D fields with the default chunk shape and
+// 2-D fields with chunks of 16 x 64 (the 3-D tile with a z extent of one
+// plane, pass A absent), whose level-1 launch fits the grid limits (their tile
+// arithmetic is 32-bit).
 bool fused3(const Schedule &s) {
-  if (!(s.D == 3 && s.K >= 1 && s.chunk_log2[0] == 1 && s.chunk_log2[1] == 4 &&
-        s.chunk_log2[2] == 6))
-    return false;
+  const bool c3 = s.D == 3 && s.chunk_log2[0] == 1 && s.chunk_log2[1] == 4 && s.chunk_log2[2] == 6;
+  const bool c2 = s.D == 2 && s.chunk_log2[0] == 4 && s.chunk_log2[1] == 6;
+  if (!(s.K >= 1 && (c3 || c2))) return false;
   // 32-bit element offsets inside the kernels' two-plane slabs
   if (s.n_points >= (int64_t(1) << 31)) return false;
   for (int j = 0; j < 3; ++j)
@@ -560,8 +562,13 @@ Level3Args level3_args(const Schedule &s, int l, int64_t fill) {
   const int64_t nxy = int64_t(A.tiles_y) * A.tiles_x;
   A.zseg = 16;
   while (A.zseg > 1 && nxy * ((A.tiles_z + A.zseg - 1) / A.zseg) < fill) A.zseg >>= 1;
-  for (int p = 0; p < 3; ++p) {
-    const PassGeom &g = s.passes[size_t(1 + (s.K - l) * 3 + p)];
+  // passes A, B, C are the level's passes along z, y, x; a 2-D field has no
+  // pass along z: its slot A gets no targets (tdims 0), wmax 0 (which the
+  // compression kernel reads as "no pass A": no chunk masks written) and pass
+  // B's chunk table, so reads through it stay in bounds
+  const int D = s.D;
+  for (int p = 3 - D; p < 3; ++p) {
+    const PassGeom &g = s.passes[size_t(1 + (s.K - l) * D + p - (3 - D))];
     for (int j = 0; j < 3; ++j) {
       A.tdims[p][j] = int32_t(g.tdims[j]);
       A.ct[p][j] = int32_t(g.ct[j]);
@@ -571,8 +578,22 @@ Level3Args level3_args(const Schedule &s, int l, int64_t fill) {
     A.wmax[p] = uint32_t(g.wmax);
     A.pass_index[p] = uint32_t(g.index);
   }
+  if (D == 2) {
+    for (int j = 0; j < 3; ++j) {
+      A.tdims[0][j] = 0;
+      A.ct[0][j] = A.ct[1][j];
+    }
+    A.chunk_base[0] = A.chunk_base[1];
+    A.slot_base[0] = A.slot_base[1];
+    A.wmax[0] = 0;
+    A.pass_index[0] = A.pass_index[1];
+  }
   return A;
 }
+
+// stream index of the last pass of level l (the pass its fused launch is
+// timed and reported under)
+int level_last_pass(const Schedule &s, int l) { return 1 + (s.K - l) * s.D + s.D - 1; }
 
 // resident workgroups per compute unit assumed when sizing the fused level
 // launches (occupancy of the compression and retrieval kernels)
@@ -835,18 +856,19 @@ uint64_t verify_stream(ipc_ctx *ctx, const ipc_stream *s, const void *field_dev)
 
 // ---------------------------------------------------------------- batches
 
-// Whether a field of these dims would take the fused 3-D path
+// Whether a field of these dims (and options) would take the fused level path
 bool fused_dims(const uint64_t *dims, int ndim, const ipc_options *opts) {
-  if (ndim != 3) return false;
+  if (ndim != 2 && ndim != 3) return false;
   if (opts && (opts->debug_flags & IPC_DEBUG_PER_PASS)) return false;
-  if (opts)
-    for (int j = 0; j < 3; ++j)
-      if (opts->chunk_log2[j] != 0) return false;
-  int64_t d64[3] = {int64_t(dims[0]), int64_t(dims[1]), int64_t(dims[2])};
+  int64_t d64[3] = {0, 0, 0};
   int cl[3] = {0, 0, 0};
+  for (int j = 0; j < ndim; ++j) {
+    d64[j] = int64_t(dims[j]);
+    if (opts) cl[j] = int(opts->chunk_log2[j]);
+  }
   Schedule sc;
   std::string e;
-  return make_schedule(d64, 3, cl, sc, e) && fused3(sc);
+  return make_schedule(d64, ndim, cl, sc, e) && fused3(sc);
 }
 
 // Compression of n fused 3-D fields with one launch per level over all of
@@ -2449,7 +2471,7 @@ ipc_status ipc_stream_pass_info(const ipc_stream *s, uint32_t pass, ipc_pass_inf
   out->progressive = s->tables.progressive[pass];
   out->launch_pass = pass;
   if (fused3(s->meta.sched) && g.level >= 1)
-    out->launch_pass = uint32_t(1 + (s->meta.sched.K - g.level) * 3 + 2);
+    out->launch_pass = uint32_t(level_last_pass(s->meta.sched, g.level));
   return IPC_OK;
 }
 
@@ -2820,7 +2842,8 @@ ipc_status ipc_autotune(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
                         int dtype, double abs_eb, const ipc_options *opts, int32_t *zseg_c,
                         int32_t *zseg_r, uint32_t capacity) {
   if (!ctx || !field_dev || !dims) return IPC_EINVAL;
-  if (!fused_dims(dims, ndim, opts)) {
+  // a 2-D field's columns are one chunk row long: no column length to choose
+  if (ndim != 3 || !fused_dims(dims, ndim, opts)) {
     set_err(ctx, "no tunable launches for this shape (3-D fields with the default chunks only)");
     return IPC_EUNSUPPORTED;
   }
@@ -2859,7 +2882,7 @@ ipc_status ipc_autotune(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
       }
       std::vector<float> tr = ctx->pass_ms;
       for (int l = 1; l <= sc.K && l < 32; ++l) {
-        const size_t slot = size_t(1 + (sc.K - l) * 3 + 2);
+        const size_t slot = size_t(level_last_pass(sc, l));
         if (slot < tc.size() && tc[slot] > 0 && tc[slot] < best_c[l]) {
           best_c[l] = tc[slot];
           zc[l] = c;

@@ -956,7 +956,8 @@ __device__ __forceinline__ void level3_compress_body(const Level3Args &L, const 
         finish(std::integral_constant<int, 32>{});
       }
       const uint32_t rowor = rp == 2 ? mC : (rp == 1 ? mB : mA);
-      if (lane < 56 && rw == 0) o.masks[LSEL(chunk_base, rp) + cid] = rowor;
+      // (a 2-D field has no pass A: wmax 0 in its slot)
+      if (lane < 56 && rw == 0 && (rp != 0 || L.wmax[0] != 0u)) o.masks[LSEL(chunk_base, rp) + cid] = rowor;
       {
         const int k = lane & 31;
         const uint32_t wA = uint32_t(cA + 31) >> 5, wB = uint32_t(cB + 31) >> 5, wC = uint32_t(cC + 31) >> 5;

@@ -15,7 +15,7 @@
 
 namespace ipc {
 
-static const int kDefaultChunk[4][3] = {{0, 0, 0}, {12, 0, 0}, {5, 6, 0}, {1, 4, 6}};
+static const int kDefaultChunk[4][3] = {{0, 0, 0}, {12, 0, 0}, {4, 6, 0}, {1, 4, 6}};
 
 int ceil_log2_u64(uint64_t v) {
   int e = 0;

@@ -83,6 +83,33 @@ def test_batch_equals_single_calls(ctx, dtype, rel):
         s.free()
 
 
+def test_batch_2d_fields_and_mixed_rank_retrieval(ctx):
+    """2-D fields batched on the fused level kernels (one plane, no pass A),
+    uneven in size and level count; their streams retrieved in one batch with
+    3-D streams; every result equal to the oracle's."""
+    shapes2 = [(90, 300), (17, 1000), (257, 129)]
+    xs = _fields(shapes2, np.float32, 70)
+    ebs = [1e-4 * fieldgen.value_range(x) for x in xs]
+    batch = ctx.compress_batch([_dev(x) for x in xs], ebs)
+    refs = [codec.compress(x, e) for x, e in zip(xs, ebs)]
+    assert [s.to_bytes() for s in batch] == refs
+    x3 = fieldgen.grf((33, 40, 70), -5.0 / 6.0, seed=77, dtype=np.float32)
+    e3 = 1e-4 * fieldgen.value_range(x3)
+    s3 = ctx.compress(_dev(x3), e3)
+    ref3 = codec.compress(x3, e3)
+    ss = batch + [s3]
+    refs = refs + [ref3]
+    for kind, vals in (("eb", [10 * e for e in ebs] + [100 * e3]), ("bitrate", [1.0, 2.0, 4.0, 3.0])):
+        sts = ctx.retrieve_batch(ss, **{kind: vals})
+        for i, (st, ref, v) in enumerate(zip(sts, refs, vals)):
+            o = codec.retrieve(ref, kind, v)
+            assert st.plan == list(o.plan), (kind, i)
+            assert _bytes(st.tensor()) == o.field.tobytes(), (kind, i)
+            st.free()
+    for s in ss:
+        s.free()
+
+
 def test_batch_outlier_overflow_and_fallback(ctx):
     """A field whose outliers exceed the batch's record share is compressed
     again alone; a batch of 2-D fields shares the pass launches."""
@@ -153,22 +180,26 @@ def test_autotune_keeps_results(ctx):
         ctx.autotune(_dev(np.zeros((40, 50), dtype=np.float32)), 1e-3)
 
 
-@pytest.mark.parametrize("dtype,rel", [(np.float32, 1e-4), (np.float64, 1e-7)])
-def test_pass_batch_equals_single_calls(ctx, dtype, rel):
-    """2-D fields of uneven shapes (different pass counts, ragged chunks) and
-    1-D fields through the one-pass-per-launch batch: streams, retrievals
-    and refinements equal the same field alone and the oracle."""
+@pytest.mark.parametrize("dtype,rel,cl2", [(np.float32, 1e-4, None), (np.float64, 1e-7, None),
+                                          (np.float32, 1e-4, (5, 6))])
+def test_pass_batch_equals_single_calls(ctx, dtype, rel, cl2):
+    """2-D fields of uneven shapes (different pass counts, ragged chunks:
+    the fused level launches with the default chunks, the
+    one-pass-per-launch batch with 32 x 64 chunks) and 1-D fields (one pass
+    per launch): streams, retrievals and refinements equal the same field
+    alone and the oracle."""
     for shapes in ([(300, 500), (47, 1000), (9, 17), (1800, 700)], [(20000,), (333,), (5,)]):
+        cl = cl2 if len(shapes[0]) == 2 else None
         xs = [fieldgen.random_field(sh, seed=60 + i, dtype=dtype) for i, sh in enumerate(shapes)]
         ebs = [rel * fieldgen.value_range(x) for x in xs]
         devs = [_dev(x) for x in xs]
-        batch = ctx.compress_batch(devs, ebs)
-        singles = [ctx.compress(d, e) for d, e in zip(devs, ebs)]
+        batch = ctx.compress_batch(devs, ebs, chunk_log2=cl)
+        singles = [ctx.compress(d, e, chunk_log2=cl) for d, e in zip(devs, ebs)]
         for i, (b, one) in enumerate(zip(batch, singles)):
             bb = b.to_bytes()
             assert bb == one.to_bytes(), f"field {i} {shapes[i]}"
             if xs[i].size < 200_000:
-                assert bb == codec.compress(xs[i], ebs[i]), f"field {i} vs oracle"
+                assert bb == codec.compress(xs[i], ebs[i], chunk_log2=cl), f"field {i} vs oracle"
         for kind, vals in (("eb", [30 * e for e in ebs]), ("bitrate", [1.0, 3.0, 6.0, 9.0][:len(xs)])):
             got = ctx.retrieve_batch(batch, **{kind: vals})
             for i, st in enumerate(got):

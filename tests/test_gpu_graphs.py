@@ -61,8 +61,9 @@ def _check_batch(ctx, streams, kind, values, label, refs):
 @pytest.mark.parametrize("dtype,interp,rel", [(np.float32, "cubic", 1e-4), (np.float64, "linear", 1e-6)])
 def test_graph_batches_equal_direct_launches(ctx, dtype, interp, rel):
     # uneven shapes: level counts 3 .. 8, ragged tiles, multi-step columns,
-    # small levels (grid class 16), middle ones (128) and the full class
-    shapes = [(33, 40, 70), (9, 17, 130), (64, 96, 200), (2, 3, 5), (130, 70, 66)]
+    # small levels (grid class 16), middle ones (128) and the full class, a
+    # 2-D field among them
+    shapes = [(33, 40, 70), (9, 17, 130), (64, 96, 200), (2, 3, 5), (130, 70, 66), (90, 300)]
     xs = [fieldgen.grf(sh, -5.0 / 6.0, seed=60 + i, dtype=dtype) for i, sh in enumerate(shapes)]
     ebs = [rel * fieldgen.value_range(x) for x in xs]
     ss = [ctx.compress(_dev(x), e, interp=interp) for x, e in zip(xs, ebs)]
@@ -77,7 +78,7 @@ def test_graph_batches_equal_direct_launches(ctx, dtype, interp, rel):
     # same fields, other targets: the same launch shape, replayed; eager
     # work and synchronizations between the replays
     for trial, (kind, vals) in enumerate([("eb", [10 * e for e in ebs]),
-                                          ("bitrate", [1.0, 2.0, 4.0, 8.0, 0.5]),
+                                          ("bitrate", [1.0, 2.0, 4.0, 8.0, 0.5, 3.0]),
                                           ("eb", [1e3 * e for e in ebs])]):
         y = torch.randn(1 << 20, device="cuda:0")
         _ = float((y * y).sum())
@@ -86,9 +87,9 @@ def test_graph_batches_equal_direct_launches(ctx, dtype, interp, rel):
     c2, r2 = ctx.graph_stats()
     assert c2 == c1 and r2 == r1 + 3
     # another mix (a field fewer, one repeated): its own shape
-    mix = [ss[2], ss[0], ss[0], ss[4]]
-    _check_batch(ctx, mix, "eb", [ebs[2], ebs[0], 5 * ebs[0], ebs[4]], "mix",
-                 [refs[2], refs[0], refs[0], refs[4]])
+    mix = [ss[2], ss[0], ss[0], ss[4], ss[5]]
+    _check_batch(ctx, mix, "eb", [ebs[2], ebs[0], 5 * ebs[0], ebs[4], 30 * ebs[5]], "mix",
+                 [refs[2], refs[0], refs[0], refs[4], refs[5]])
     # one field alone
     _check_batch(ctx, [ss[3]], "eb", [ebs[3]], "alone", [refs[3]])
     for s in ss:
@@ -153,19 +154,23 @@ def test_batched_compression_from_graph_replays_equals_oracle(ctx, dtype, interp
     from oracle import predict
     it = predict.CUBIC if interp == "cubic" else predict.LINEAR
     c0, _ = ctx.graph_stats()
-    shapes = [(40, 70, 130), (17, 33, 65), (64, 64, 64)]
+    # a batch of 3-D fields and one of 2-D fields (one plane on the fused
+    # kernels), each its own launch shape
+    batches = [[(40, 70, 130), (17, 33, 65), (64, 64, 64)], [(100, 260), (33, 700)]]
     for rep in range(3):
-        print(f"compress graphs: {dtype.__name__} {interp} replay {rep}", flush=True)
-        xs = [fieldgen.grf(sh, -5.0 / 6.0, seed=100 + 10 * rep + i, dtype=dtype) for i, sh in enumerate(shapes)]
-        if rep == 1:
-            xs[0].reshape(-1)[11] = np.nan  # an outlier record through the queue path
-        ebs = [1e-4 * fieldgen.value_range(np.nan_to_num(x)) for x in xs]
-        ss = _compress_graphs(ctx, xs, ebs, interp)
-        junk = torch.randn(1 << 20, device="cuda:0") * 2.0  # other work between replays
-        torch.cuda.synchronize()
-        del junk
-        for x, e, s in zip(xs, ebs, ss):
-            assert s.to_bytes() == codec.compress(x, e, interp=it)
-            s.free()
+        for bi, shapes in enumerate(batches):
+            print(f"compress graphs: {dtype.__name__} {interp} batch {bi} replay {rep}", flush=True)
+            xs = [fieldgen.grf(sh, -5.0 / 6.0, seed=100 + 10 * rep + i, dtype=dtype)
+                  for i, sh in enumerate(shapes)]
+            if rep == 1:
+                xs[0].reshape(-1)[11] = np.nan  # an outlier record through the queue path
+            ebs = [1e-4 * fieldgen.value_range(np.nan_to_num(x)) for x in xs]
+            ss = _compress_graphs(ctx, xs, ebs, interp)
+            junk = torch.randn(1 << 20, device="cuda:0") * 2.0  # other work between replays
+            torch.cuda.synchronize()
+            del junk
+            for x, e, s in zip(xs, ebs, ss):
+                assert s.to_bytes() == codec.compress(x, e, interp=it)
+                s.free()
     c1, r1 = ctx.graph_stats()
-    assert c1 - c0 == 1  # one launch shape: captured once, replayed
+    assert c1 - c0 == 2  # two launch shapes: each captured once, then replayed

@@ -67,6 +67,16 @@ CASES = [
     ((33, 17, 65), np.float64, predict.CUBIC, 1e-6, None, 0, True),
     ((64, 96, 200), np.float32, predict.LINEAR, 1e-5, None, 0, False),
     ((65, 33, 129), np.float32, predict.CUBIC, 1e-3, None, 1, True),
+    # 2-D fields on the fused level kernels (one plane, pass A absent):
+    # ragged multi-tile grids, degenerate rows and columns, an exact tile, and
+    # the former 32 x 64 chunk on the per-pass kernels
+    ((77, 300), np.float32, predict.LINEAR, 1e-4, None, 0, True),
+    ((257, 1025), np.float32, predict.CUBIC, 1e-5, None, 1, False),
+    ((130, 515), np.float64, predict.CUBIC, 1e-6, None, 0, True),
+    ((1, 700), np.float64, predict.CUBIC, 1e-4, None, 0, False),
+    ((700, 1), np.float32, predict.LINEAR, 1e-4, None, 0, False),
+    ((16, 64), np.float32, predict.CUBIC, 1e-3, None, 0, False),
+    ((100, 130), np.float32, predict.CUBIC, 1e-4, (5, 6), 0, True),
 ]
 
 
@@ -88,9 +98,10 @@ def test_compress_stream_bytes_and_full_retrieve(ctx, case):
     s.free()
 
 
-@pytest.mark.parametrize("dtype", [np.float32, np.float64])
-def test_partial_retrieve_and_refine_match_oracle(ctx, dtype):
-    x = fieldgen.grf((40, 48, 72), -5.0 / 6.0, seed=2, dtype=dtype)
+@pytest.mark.parametrize("dtype,shape", [(np.float32, (40, 48, 72)), (np.float64, (40, 48, 72)),
+                                         (np.float32, (150, 333))])
+def test_partial_retrieve_and_refine_match_oracle(ctx, dtype, shape):
+    x = fieldgen.grf(shape, -5.0 / 6.0, seed=2, dtype=dtype)
     r = fieldgen.value_range(x)
     eb = 1e-5 * r
     ref = codec.compress(x, eb)
