@@ -341,6 +341,8 @@ constexpr int RB = 13;
 constexpr int RW = (1 << RB) / 32;            // words of one pass's residue set
 
 // LDS of a compression workgroup
+constexpr int REC_CAP = 128;  // outlier records a compression step stages in LDS
+
 template <typename T>
 struct SharedC {
   T ring[4][NYE][NXP];
@@ -353,6 +355,11 @@ struct SharedC {
   uint32_t eq[3][33];       // per workgroup delta-y of each pass
   uint32_t qa[3];           // largest |q| among 14-digit codes, per pass
   unsigned long long mxab;  // bits of the workgroup's largest finite |x^| (as a double)
+  // the step's outlier records (pass << 16 | local, value bits), written out
+  // with one slot reservation per step
+  uint32_t rec_n;
+  uint32_t rec_key[REC_CAP];
+  unsigned long long rec_bits[REC_CAP];
 };
 
 // code buffers of one step (retrieval): pass A, B, C
@@ -506,17 +513,30 @@ __device__ __forceinline__ uint64_t wave_max_bits(uint64_t v) {
 }
 __device__ __forceinline__ uint32_t wave_max_bits(uint32_t v) { return uint32_t(wave_max(int(v))); }
 
-// Delta-y for b >= 14 over one chunk of `count` buffered codes with at most nb
-// digits, nb > 14 (see k_level3_compress), by one wave: exact |q - q'_b| per
-// code while b < nb, the chunk's largest |q| from there on; into the maxima
-// eq[14..32].  One b at a time keeps the register footprint small.
-__device__ __forceinline__ void errq_hi(uint32_t *eq, const uint32_t *v, int count, int nb, int lane) {
-  uint32_t qa = 0;
-  for (int j = lane; j < count; j += 64) {
-    const int32_t q = int32_t((v[pidx(j)] ^ NB_A) - NB_A);
+// OR of v over a full wave (every lane active), uniform
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+  return wave_reduce(v, [](uint32_t a, uint32_t b) { return a | b; });
+}
+
+
+// Delta-y for b >= 14 over the buffered codes lo .. hi - 1 of one chunk (see
+// k_level3_compress), by one wave: nothing to do when none has more than 14
+// digits; else, with nb the longest code's digit count, exact |q - q'_b| per
+// code while b < nb and the range's largest |q| from there on, into the
+// maxima eq[14..32].  One b at a time keeps the register footprint small.
+__device__ __forceinline__ void errq_hi(uint32_t *eq, const uint32_t *v, int lo, int hi, int lane) {
+  uint32_t qa = 0, orv = 0;
+  for (int j = lo + lane; j < hi; j += 64) {
+    const uint32_t c = v[pidx(j)];
+    orv |= c;
+    const int32_t q = int32_t((c ^ NB_A) - NB_A);
     const uint32_t aq = uint32_t(q < 0 ? -q : q);
     qa = aq > qa ? aq : qa;
   }
+  // every code within 14 digits: the |q| tracked per code covers b >= 14
+  const uint32_t o = wave_or(orv);
+  const int nb = o ? 32 - __clz(o) : 0;
+  if (nb <= 14) return;
   qa = uint32_t(wave_max(int(qa)));
 #pragma unroll 1
   for (int b = 14; b < 33; ++b) {
@@ -524,7 +544,7 @@ __device__ __forceinline__ void errq_hi(uint32_t *eq, const uint32_t *v, int cou
     if (b < nb) {
       const uint32_t mb = (1u << b) - 1u, ab = NB_A & mb;
       d = 0;
-      for (int j = lane; j < count; j += 64) {
+      for (int j = lo + lane; j < hi; j += 64) {
         const uint32_t t = absdiff((v[pidx(j)] ^ NB_A) & mb, ab);
         d = t > d ? t : d;
       }
@@ -651,6 +671,7 @@ __device__ __forceinline__ void level3_compress_body(const Level3Args &L, const 
   if (tid0 < 3 * 33) (&S.eq[0][0])[tid0] = 0u;
   if (tid0 < 3) S.qa[tid0] = 0u;
   if (tid0 == 0) S.mxab = 0ull;
+  if (tid0 == 0) S.rec_n = 0u;
 
   uint32_t qaA = 0, qaB = 0, qaC = 0;
   U mxb = 0;
@@ -660,8 +681,12 @@ __device__ __forceinline__ void level3_compress_body(const Level3Args &L, const 
   uint32_t szCB = 0, szA = 0;
 
   auto record = [&](int p, int m, int local, T xv) {
-    unsigned long long slot = atomicAdd(o.n_out, 1ull);
-    if (slot < o.out_cap) {
+    const uint32_t k = atomicAdd(&S.rec_n, 1u);
+    if (k < uint32_t(REC_CAP)) {
+      S.rec_key[k] = uint32_t(p) << 16 | uint32_t(local);
+      S.rec_bits[k] = (unsigned long long)F::bits(xv);
+    } else if (unsigned long long slot = atomicAdd(o.n_out, 1ull); slot < o.out_cap) {
+      // past the step's staging: a slot of its own
       OutlierRec *rr = reinterpret_cast<OutlierRec *>(o.out_recs) + slot;
       rr->pass = LSEL(pass_index, p);
       rr->chunk = uint32_t(chunk_id(L, m, ty, tx));
@@ -956,6 +981,16 @@ __device__ __forceinline__ void level3_compress_body(const Level3Args &L, const 
         finish(std::integral_constant<int, 32>{});
       }
       const uint32_t rowor = rp == 2 ? mC : (rp == 1 ? mB : mA);
+      // delta-y for b >= 14 of chunks holding codes longer than 14 digits
+      {
+        const uint32_t mk[3] = {mA, mB, mC};
+        const int ck[3] = {cA, cB, cC};
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          const int nb = mk[p] ? 32 - __clz(mk[p]) : 0;
+          if (nb > 14) errq_hi(S.eq[p], S.codes + code_off1(p), 0, ck[p], lane);
+        }
+      }
       // (a 2-D field has no pass A: wmax 0 in its slot)
       if (lane < 56 && rw == 0 && (rp != 0 || L.wmax[0] != 0u)) o.masks[LSEL(chunk_base, rp) + cid] = rowor;
       {
@@ -965,13 +1000,31 @@ __device__ __forceinline__ void level3_compress_body(const Level3Args &L, const 
         szCB += ((mcb >> k) & 1u) ? (lane < 32 ? wC : wB) : 0u;
         szA += ((mA >> k) & 1u) ? wA : 0u;
       }
-      // delta-y for b >= 14 of chunks holding codes longer than 14 digits
-      const uint32_t mk[3] = {mA, mB, mC};
-      const int ck[3] = {cA, cB, cC};
-#pragma unroll
-      for (int p = 0; p < 3; ++p) {
-        const int nb = mk[p] ? 32 - __clz(mk[p]) : 0;
-        if (nb > 14) errq_hi(S.eq[p], S.codes + code_off1(p), ck[p], nb, lane);
+    } else if ((tid >> 6) == 3) {
+      {
+        // meanwhile another wave writes the step's staged outlier records out
+        // with one reservation of output slots; the count starts again from
+        // zero for the next step (whose records come after its first barrier)
+        const uint32_t nr = S.rec_n < uint32_t(REC_CAP) ? S.rec_n : uint32_t(REC_CAP);
+        if (nr) {
+          unsigned long long base = 0;
+          if (lane == 0) base = atomicAdd(o.n_out, (unsigned long long)nr);
+          base = (unsigned long long)uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(base)))) |
+                 (unsigned long long)uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(base >> 32)))) << 32;
+          const uint32_t cid = uint32_t(chunk_id(L, m, ty, tx));
+          for (uint32_t i = uint32_t(lane); i < nr; i += 64u) {
+            if (base + i < o.out_cap) {
+              OutlierRec *rr = reinterpret_cast<OutlierRec *>(o.out_recs) + (base + i);
+              const uint32_t key = S.rec_key[i];
+              rr->pass = LSEL(pass_index, int(key >> 16));
+              rr->chunk = cid;
+              rr->local = key & 0xFFFFu;
+              rr->pad = 0;
+              rr->bits = S.rec_bits[i];
+            }
+          }
+        }
+        if (lane == 0) S.rec_n = 0u;
       }
     }
   }
@@ -1195,10 +1248,6 @@ __device__ __forceinline__ void load_planes_top(const RetrieveIn &in, bool packe
   }
 }
 
-// OR of v over a full wave (every lane active), uniform
-__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
-  return wave_reduce(v, [](uint32_t a, uint32_t b) { return a | b; });
-}
 
 template <typename T, int INTERP>
 __device__ __forceinline__ void level3_retrieve_body(const Level3Args &L, const T *__restrict__ gin,
