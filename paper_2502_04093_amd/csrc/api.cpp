@@ -971,40 +971,57 @@ void compress_batch_fused(ipc_ctx *ctx, std::vector<ipc_stream *> &ss,
       ensure_ws(ctx, ctx->ws_rows, ctx->ws_rows_bytes, size_t(rows) * WG_ROW * 4));
   for (BatchC<T> &e : ent) e.o.wg_rows = rows_p;
   for (int i = 0; i < n; ++i) o[i].wg_rows = rows_p;
-  DevBuf ent_dev = dev_alloc(ctx, ent.size() * sizeof(BatchC<T>));
-  hip_check(ctx, hipMemcpyAsync(ent_dev.p, ent.data(), ent.size() * sizeof(BatchC<T>),
-                                hipMemcpyHostToDevice, ctx->stream), "upload");
+  // one upload: the anchor jobs as a head table, the level work lists, and
+  // the row-reduction jobs of every field's level launches
+  std::vector<RowsJob> jobs;
+  uint32_t most_rows = 0;
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < lr[i].n; ++k) {
+      RowsJob j;
+      std::memset(&j, 0, sizeof(j));
+      j.row_base = lr[i].row_base[k];
+      j.n_rows = lr[i].n_rows[k];
+      for (int p = 0; p < 3; ++p) j.pass_index[p] = lr[i].pass_index[k][p];
+      j.errq = o[i].errq;
+      j.maxabs_bits = o[i].maxabs_bits;
+      j.sizes = o[i].sizes;
+      most_rows = std::max(most_rows, j.n_rows);
+      jobs.push_back(j);
+    }
+  const size_t heads_off = (sizeof(QueueTable) + 255) & ~size_t(255);
+  const size_t ent_off = heads_off + ((size_t(n) * sizeof(HeadC<T>) + 255) & ~size_t(255));
+  const size_t jobs_off = ent_off + ((ent.size() * sizeof(BatchC<T>) + 255) & ~size_t(255));
+  std::vector<char> up(jobs_off + jobs.size() * sizeof(RowsJob), 0);
+  QueueTable &tab = *reinterpret_cast<QueueTable *>(up.data());
+  tab.n_heads = uint32_t(n);
+  tab.heads_off = uint32_t(heads_off);
+  tab.ent_off = uint32_t(ent_off);
   for (int i = 0; i < n; ++i) {
+    HeadC<T> &h = reinterpret_cast<HeadC<T> *>(up.data() + heads_off)[i];
     const Schedule &sc = ss[i]->meta.sched;
-    hip_check(ctx, launch_anchor3_compress(dtype, anchor3_args(sc), fields[i], g[2 * i + (sc.K & 1)].p,
-                                           ebs[i], o[i], ctx->stream),
-              "anchor kernel launch");
+    h.A = anchor3_args(sc);
+    h.x = static_cast<const T *>(fields[i]);
+    h.g = static_cast<T *>(g[2 * i + (sc.K & 1)].p);
+    h.o = o[i];
+    h.eb = ebs[i];
+    h.two_eb = T(2.0 * ebs[i]);
+    h.inv = T(1.0 / (2.0 * ebs[i]));
+    h.qmax = T(sizeof(T) == 4 ? QMAX_F32 : QMAX_F64);
   }
+  std::memcpy(up.data() + ent_off, ent.data(), ent.size() * sizeof(BatchC<T>));
+  std::memcpy(up.data() + jobs_off, jobs.data(), jobs.size() * sizeof(RowsJob));
+  DevBuf up_dev = dev_alloc(ctx, up.size());
+  hip_check(ctx, hipMemcpyAsync(up_dev.p, up.data(), up.size(), hipMemcpyHostToDevice, ctx->stream), "upload");
+  const QueueTable *tab_dev = static_cast<const QueueTable *>(up_dev.p);
+  const BatchC<T> *ent_dev = reinterpret_cast<const BatchC<T> *>(static_cast<const char *>(up_dev.p) + ent_off);
+  hip_check(ctx, launch_heads_compress(dtype, tab_dev, ctx->stream), "anchor kernel launch");
   for (const Launch &ln : launches)
-    hip_check(ctx, launch_level3_compress_batch(dtype, interp, static_cast<BatchC<T> *>(ent_dev.p) + ln.off,
-                                                ln.nf, ln.items, ctx->stream),
+    hip_check(ctx, launch_level3_compress_batch(dtype, interp, ent_dev + ln.off, ln.nf, ln.items, ctx->stream),
               "level kernel launch");
-  for (int i = 0; i < n; ++i) {
-    ipc_stream *s = ss[i];
-    hip_check(ctx, launch_rows_reduce(lr[i], rows_p, o[i].errq, o[i].maxabs_bits, o[i].sizes, ctx->stream),
-              "row reduction launch");
-    const uint64_t nc = uint64_t(s->meta.sched.n_chunks);
-    const size_t cap = size_t(o[i].out_cap);
-    s->out_gchunk = dev_alloc(ctx, 8 * cap);
-    s->out_local = dev_alloc(ctx, 4 * cap);
-    s->out_bits = dev_alloc(ctx, 8 * cap);
-    s->out_start = dev_alloc(ctx, 4 * (nc + 1));
-    const size_t nb = (nc + 1 + 1023) / 1024;
-    uint32_t *cnt = static_cast<uint32_t *>(
-        ensure_ws(ctx, ctx->ws_cnt, ctx->ws_cnt_bytes, 4 * (nc + 1) + 4 * (nb + 1)));
-    hip_check(ctx, launch_outlier_index(static_cast<const OutlierRec *>(o[i].out_recs), o[i].n_out, cap,
-                                        static_cast<const PassArgs *>(args_dev.p) + args_off[i], nc,
-                                        static_cast<uint32_t *>(s->out_start.p), cnt, cnt + (nc + 1),
-                                        static_cast<uint64_t *>(s->out_gchunk.p),
-                                        static_cast<uint32_t *>(s->out_local.p),
-                                        static_cast<uint64_t *>(s->out_bits.p), ctx->stream),
-              "outlier index launch");
-  }
+  hip_check(ctx, launch_rows_reduce_batch(
+                     reinterpret_cast<const RowsJob *>(static_cast<const char *>(up_dev.p) + jobs_off),
+                     uint32_t(jobs.size()), most_rows, rows_p, ctx->stream),
+            "row reduction launch");
   if (ctx->host_summary_bytes < sum_off[n]) {
     if (ctx->host_summary) (void)hipHostFree(ctx->host_summary);
     ctx->host_summary = nullptr;
@@ -1023,8 +1040,28 @@ void compress_batch_fused(ipc_ctx *ctx, std::vector<ipc_stream *> &ss,
       continue;
     }
     finish_stream(ss[i], hostp + sum_off[i], nout);
+    // the outlier index, sorted on the device, for the fields that have
+    // outliers (a stream without any has no table); queued behind the
+    // call's work and read only by later work on the same stream
+    if (nout == 0) continue;
+    ipc_stream *s = ss[i];
+    const uint64_t nc = uint64_t(s->meta.sched.n_chunks);
+    s->out_gchunk = dev_alloc(ctx, 8 * nout);
+    s->out_local = dev_alloc(ctx, 4 * nout);
+    s->out_bits = dev_alloc(ctx, 8 * nout);
+    s->out_start = dev_alloc(ctx, 4 * (nc + 1));
+    const size_t nb = (nc + 1 + 1023) / 1024;
+    uint32_t *cnt = static_cast<uint32_t *>(
+        ensure_ws(ctx, ctx->ws_cnt, ctx->ws_cnt_bytes, 4 * (nc + 1) + 4 * (nb + 1)));
+    hip_check(ctx, launch_outlier_index(static_cast<const OutlierRec *>(o[i].out_recs), o[i].n_out, nout,
+                                        static_cast<const PassArgs *>(args_dev.p) + args_off[i], nc,
+                                        static_cast<uint32_t *>(s->out_start.p), cnt, cnt + (nc + 1),
+                                        static_cast<uint64_t *>(s->out_gchunk.p),
+                                        static_cast<uint32_t *>(s->out_local.p),
+                                        static_cast<uint64_t *>(s->out_bits.p), ctx->stream),
+              "outlier index launch");
   }
-  dev_free(ctx, ent_dev);
+  dev_free(ctx, up_dev);
   dev_free(ctx, args_dev);
   for (DevBuf &b : g) dev_free(ctx, b);
 }
@@ -1085,31 +1122,47 @@ void retrieve_batch_fused(ipc_ctx *ctx, const std::vector<const ipc_stream *> &s
     }
     launches.push_back(ln);
   }
-  DevBuf ent_dev = dev_alloc(ctx, ent.size() * sizeof(BatchR<T>));
-  hip_check(ctx, hipMemcpyAsync(ent_dev.p, ent.data(), ent.size() * sizeof(BatchR<T>),
-                                hipMemcpyHostToDevice, ctx->stream), "upload");
+  // one upload: the head jobs (anchors, or a refinement's coarse grid
+  // gathered from the resident field) as a head table, then the work lists;
+  // one launch runs every head job
+  const size_t heads_off = (sizeof(QueueTable) + 255) & ~size_t(255);
+  const size_t ent_off = heads_off + ((size_t(n) * sizeof(HeadR<T>) + 255) & ~size_t(255));
+  std::vector<char> up(ent_off + ent.size() * sizeof(BatchR<T>), 0);
+  QueueTable &tab = *reinterpret_cast<QueueTable *>(up.data());
+  tab.n_heads = uint32_t(n);
+  tab.heads_off = uint32_t(heads_off);
+  tab.ent_off = uint32_t(ent_off);
   for (int i = 0; i < n; ++i) {
+    HeadR<T> &h = reinterpret_cast<HeadR<T> *>(up.data() + heads_off)[i];
     const Schedule &sc = ss[i]->meta.sched;
     const int ls = l_start[i];
+    h.in = in[i];
+    h.two_eb = T(2.0 * ss[i]->meta.eb);
+    h.g = static_cast<T *>(g[2 * i + (ls & 1)].p);
     if (ls >= sc.K) {
-      hip_check(ctx, launch_anchor3_retrieve(dtype, anchor3_args(sc), g[2 * i + (sc.K & 1)].p, in[i],
-                                             ss[i]->meta.eb, ctx->stream),
-                "anchor kernel launch");
+      h.mode = 0;
+      h.A = anchor3_args(sc);
     } else {
-      // refinement: the coarse grid of its first level from the resident field
-      int64_t gd[3];
-      for (int j = 0; j < 3; ++j) gd[j] = ((sc.dims3[j] - 1) >> ls) + 1;
-      hip_check(ctx, launch_gather_coarse(ss[i]->meta.dtype, out[i], sc.dims3, int64_t(1) << ls,
-                                          g[2 * i + (ls & 1)].p, gd, ctx->stream),
-                "gather kernel launch");
+      h.mode = 1;
+      h.field = static_cast<const T *>(out[i]);
+      for (int j = 0; j < 3; ++j) {
+        h.fd[j] = sc.dims3[j];
+        h.gd[j] = ((sc.dims3[j] - 1) >> ls) + 1;
+      }
+      h.step = int64_t(1) << ls;
     }
   }
+  std::memcpy(up.data() + ent_off, ent.data(), ent.size() * sizeof(BatchR<T>));
+  DevBuf up_dev = dev_alloc(ctx, up.size());
+  hip_check(ctx, hipMemcpyAsync(up_dev.p, up.data(), up.size(), hipMemcpyHostToDevice, ctx->stream), "upload");
+  const BatchR<T> *ent_dev = reinterpret_cast<const BatchR<T> *>(static_cast<const char *>(up_dev.p) + ent_off);
+  hip_check(ctx, launch_heads_retrieve(dtype, static_cast<const QueueTable *>(up_dev.p), ctx->stream),
+            "head launch");
   for (const Launch &ln : launches)
-    hip_check(ctx, launch_level3_retrieve_batch(dtype, interp, static_cast<BatchR<T> *>(ent_dev.p) + ln.off,
-                                                ln.nf, ln.items, ctx->stream),
+    hip_check(ctx, launch_level3_retrieve_batch(dtype, interp, ent_dev + ln.off, ln.nf, ln.items, ctx->stream),
               "level kernel launch");
   hip_check(ctx, hipStreamSynchronize(ctx->stream), "retrieve");
-  dev_free(ctx, ent_dev);
+  dev_free(ctx, up_dev);
   for (DevBuf &b : g) dev_free(ctx, b);
 }
 
@@ -1480,28 +1533,33 @@ bool compress_batch_queue(ipc_ctx *ctx, std::vector<ipc_stream *> &ss, const voi
   }
   hip_check(ctx, hipGraphLaunch(it->second, ctx->stream), "graph launch");
   ++ctx->graph_replays;
-  // per field: rows -> errq, max |x^|, plane sizes; the outlier index
-  for (int i = 0; i < n; ++i) {
-    ipc_stream *s = ss[i];
-    hip_check(ctx, launch_rows_reduce(lr[i], rows_p, o[i].errq, o[i].maxabs_bits, o[i].sizes, ctx->stream),
-              "row reduction launch");
-    const uint64_t nc = uint64_t(s->meta.sched.n_chunks);
-    const size_t cap = size_t(o[i].out_cap);
-    s->out_gchunk = dev_alloc(ctx, 8 * cap);
-    s->out_local = dev_alloc(ctx, 4 * cap);
-    s->out_bits = dev_alloc(ctx, 8 * cap);
-    s->out_start = dev_alloc(ctx, 4 * (nc + 1));
-    const size_t nb = (nc + 1 + 1023) / 1024;
-    uint32_t *cnt = static_cast<uint32_t *>(
-        ensure_ws(ctx, ctx->ws_cnt, ctx->ws_cnt_bytes, 4 * (nc + 1) + 4 * (nb + 1)));
-    hip_check(ctx, launch_outlier_index(static_cast<const OutlierRec *>(o[i].out_recs), o[i].n_out, cap,
-                                        static_cast<const PassArgs *>(args_dev.p) + args_off[i], nc,
-                                        static_cast<uint32_t *>(s->out_start.p), cnt, cnt + (nc + 1),
-                                        static_cast<uint64_t *>(s->out_gchunk.p),
-                                        static_cast<uint32_t *>(s->out_local.p),
-                                        static_cast<uint64_t *>(s->out_bits.p), ctx->stream),
-              "outlier index launch");
-  }
+  // every field's rows -> errq, max |x^|, plane sizes in one launch
+  std::vector<RowsJob> jobs;
+  uint32_t most_rows = 0;
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < lr[i].n; ++k) {
+      RowsJob j;
+      std::memset(&j, 0, sizeof(j));
+      j.row_base = lr[i].row_base[k];
+      j.n_rows = lr[i].n_rows[k];
+      for (int p = 0; p < 3; ++p) j.pass_index[p] = lr[i].pass_index[k][p];
+      j.errq = o[i].errq;
+      j.maxabs_bits = o[i].maxabs_bits;
+      j.sizes = o[i].sizes;
+      most_rows = std::max(most_rows, j.n_rows);
+      jobs.push_back(j);
+    }
+  DevBuf jobs_dev = dev_alloc(ctx, jobs.size() * sizeof(RowsJob));
+  struct FreeJobs {
+    ipc_ctx *ctx;
+    DevBuf &b;
+    ~FreeJobs() { dev_free(ctx, b); }
+  } free_jobs{ctx, jobs_dev};
+  hip_check(ctx, hipMemcpyAsync(jobs_dev.p, jobs.data(), jobs.size() * sizeof(RowsJob), hipMemcpyHostToDevice,
+                                ctx->stream), "upload");
+  hip_check(ctx, launch_rows_reduce_batch(static_cast<const RowsJob *>(jobs_dev.p), uint32_t(jobs.size()),
+                                          most_rows, rows_p, ctx->stream),
+            "row reduction launch");
   if (ctx->host_summary_bytes < sum_off[n]) {
     if (ctx->host_summary) (void)hipHostFree(ctx->host_summary);
     ctx->host_summary = nullptr;
@@ -1520,6 +1578,25 @@ bool compress_batch_queue(ipc_ctx *ctx, std::vector<ipc_stream *> &ss, const voi
       continue;
     }
     finish_stream(ss[i], hostp + sum_off[i], nout);
+    // the outlier index of the fields that have outliers (as
+    // compress_batch_fused)
+    if (nout == 0) continue;
+    ipc_stream *s = ss[i];
+    const uint64_t nc = uint64_t(s->meta.sched.n_chunks);
+    s->out_gchunk = dev_alloc(ctx, 8 * nout);
+    s->out_local = dev_alloc(ctx, 4 * nout);
+    s->out_bits = dev_alloc(ctx, 8 * nout);
+    s->out_start = dev_alloc(ctx, 4 * (nc + 1));
+    const size_t nb = (nc + 1 + 1023) / 1024;
+    uint32_t *cnt = static_cast<uint32_t *>(
+        ensure_ws(ctx, ctx->ws_cnt, ctx->ws_cnt_bytes, 4 * (nc + 1) + 4 * (nb + 1)));
+    hip_check(ctx, launch_outlier_index(static_cast<const OutlierRec *>(o[i].out_recs), o[i].n_out, nout,
+                                        static_cast<const PassArgs *>(args_dev.p) + args_off[i], nc,
+                                        static_cast<uint32_t *>(s->out_start.p), cnt, cnt + (nc + 1),
+                                        static_cast<uint64_t *>(s->out_gchunk.p),
+                                        static_cast<uint32_t *>(s->out_local.p),
+                                        static_cast<uint64_t *>(s->out_bits.p), ctx->stream),
+              "outlier index launch");
   }
   return true;
 }

@@ -55,6 +55,21 @@ struct LevelRows {
   uint32_t n_rows[MAX_LEVEL_LAUNCHES];        // its workgroups
   uint32_t pass_index[MAX_LEVEL_LAUNCHES][3]; // its passes A, B, C
 };
+// One level launch of one field of a compression batch, for the batched row
+// reduction: its rows and passes, and the field's outputs
+struct RowsJob {
+  uint32_t row_base;
+  uint32_t n_rows;
+  uint32_t pass_index[3];
+  uint32_t pad;
+  uint32_t *errq;
+  unsigned long long *maxabs_bits;
+  unsigned long long *sizes;
+};
+// the same reduction for every job of `jobs_dev` (n_jobs entries; most_rows
+// is the largest n_rows among them) in one launch
+hipError_t launch_rows_reduce_batch(const RowsJob *jobs_dev, uint32_t n_jobs, uint32_t most_rows,
+                                    const uint32_t *rows, hipStream_t stream);
 // errq[pass][b] and maxabs_bits <- max over the rows of every launch;
 // sizes[pass][k] += 4 x the rows' plane words
 hipError_t launch_rows_reduce(const LevelRows &lr, const uint32_t *rows, uint32_t *errq,

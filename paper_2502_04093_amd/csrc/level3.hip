@@ -1851,27 +1851,24 @@ __global__ __launch_bounds__(WG3, sizeof(T) == 4 ? 4 : 2) void k_level3_compress
   }
 }
 
-// errq, max |x^| and plane sizes of a compression from the fused-level rows:
-// grid (launch, pass, split), each workgroup reduces RR_ROWS rows of one
-// launch for one pass with every load of a thread issued together, then one
-// atomic per value.
+// workgroup rows reduced by one workgroup of a row reduction
 constexpr int RR_ROWS = 64;
-__global__ __launch_bounds__(256) void k_rows_reduce(LevelRows lr, const uint32_t *rows, uint32_t *errq,
-                                                     unsigned long long *maxabs_bits,
-                                                     unsigned long long *sizes) {
+// rows r0 .. r0 + RR_ROWS - 1 of one launch (its rows from row_base), pass p
+__device__ __forceinline__ void rows_reduce_part(uint32_t row_base, uint32_t n, const uint32_t pass_index[3],
+                                                 const uint32_t *rows, uint32_t *errq,
+                                                 unsigned long long *maxabs_bits,
+                                                 unsigned long long *sizes, int p, uint32_t r0) {
   __shared__ uint32_t s_max[33];
   __shared__ uint32_t s_sz[32];
   __shared__ unsigned long long s_mx;
-  const int li = blockIdx.x, p = blockIdx.y, tid = threadIdx.x;
-  const uint32_t r0 = blockIdx.z * RR_ROWS;
-  const uint32_t n = lr.n_rows[li];
+  const int tid = threadIdx.x;
   if (r0 >= n) return;  // uniform: before any barrier
   const uint32_t nr = n - r0 < uint32_t(RR_ROWS) ? n - r0 : uint32_t(RR_ROWS);
   if (tid < 33) s_max[tid] = 0u;
   if (tid < 32) s_sz[tid] = 0u;
   if (tid == 0) s_mx = 0ull;
   __syncthreads();
-  const uint32_t *base = rows + (size_t(lr.row_base[li]) + r0) * WG_ROW;
+  const uint32_t *base = rows + (size_t(row_base) + r0) * WG_ROW;
   // delta-y: thread t takes b = t % 33 of rows t / 33, + 7, ...
   if (tid < 7 * 33) {
     const int b = tid % 33, r = tid / 33;
@@ -1906,10 +1903,31 @@ __global__ __launch_bounds__(256) void k_rows_reduce(LevelRows lr, const uint32_
     if (v) atomicMax(&s_mx, v);
   }
   __syncthreads();
-  const size_t pi = lr.pass_index[li][p];
+  const size_t pi = pass_index[p];
   if (tid > 0 && tid < 33 && s_max[tid]) atomicMax(errq + pi * 33 + tid, s_max[tid]);
   if (tid < 32 && s_sz[tid]) atomicAdd(sizes + pi * 32 + tid, 4ull * s_sz[tid]);
   if (p == 0 && tid == 0 && s_mx) atomicMax(maxabs_bits, s_mx);
+}
+
+// errq, max |x^| and plane sizes of a compression from the fused-level rows:
+// grid (launch, pass, split), each workgroup reduces RR_ROWS rows of one
+// launch for one pass with every load of a thread issued together, then one
+// atomic per value.
+__global__ __launch_bounds__(256) void k_rows_reduce(LevelRows lr, const uint32_t *rows, uint32_t *errq,
+                                                     unsigned long long *maxabs_bits,
+                                                     unsigned long long *sizes) {
+  const int li = blockIdx.x;
+  rows_reduce_part(lr.row_base[li], lr.n_rows[li], lr.pass_index[li], rows, errq, maxabs_bits, sizes,
+                   int(blockIdx.y), blockIdx.z * RR_ROWS);
+}
+
+// ... of every field of a batch in one launch: grid (job, pass, split), a
+// job being one level launch of one field with that field's outputs
+__global__ __launch_bounds__(256) void k_rows_reduce_batch(const RowsJob *__restrict__ jobs,
+                                                           const uint32_t *rows) {
+  const RowsJob &j = jobs[blockIdx.x];
+  rows_reduce_part(j.row_base, j.n_rows, j.pass_index, rows, j.errq, j.maxabs_bits, j.sizes,
+                   int(blockIdx.y), blockIdx.z * RR_ROWS);
 }
 
 }  // namespace
@@ -1922,6 +1940,14 @@ hipError_t launch_rows_reduce(const LevelRows &lr, const uint32_t *rows, uint32_
   if (lr.n == 0 || most == 0) return hipSuccess;
   dim3 grid(uint32_t(lr.n), 3, (most + RR_ROWS - 1) / RR_ROWS);
   hipLaunchKernelGGL(k_rows_reduce, grid, dim3(256), 0, stream, lr, rows, errq, maxabs_bits, sizes);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_reduce_batch(const RowsJob *jobs_dev, uint32_t n_jobs, uint32_t most_rows,
+                                    const uint32_t *rows, hipStream_t stream) {
+  if (n_jobs == 0 || most_rows == 0) return hipSuccess;
+  dim3 grid(n_jobs, 3, (most_rows + RR_ROWS - 1) / RR_ROWS);
+  hipLaunchKernelGGL(k_rows_reduce_batch, grid, dim3(256), 0, stream, jobs_dev, rows);
   return hipGetLastError();
 }
 
