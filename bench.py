@@ -408,6 +408,12 @@ def climate_batch_main(args):
     xs = [torch.from_numpy(fieldgen.climate_2d(i)).to("cuda:0") for i in range(n)]
     ebs = [1e-3 * float(x.max().double() - x.min().double()) for x in xs]
     ctx = pkg.Context(0)
+    schedule = None
+    if not args.no_autotune:
+        # the batch schedule for this shape (direct launches or graph
+        # replays), used by the batched calls (automatic mode)
+        schedule = ctx.autotune_batch(xs[0], ebs[0], copies=n)
+        ctx.set_batch_graphs("auto")
 
     def batched():
         ss = ctx.compress_batch(xs, ebs)
@@ -446,7 +452,7 @@ def climate_batch_main(args):
                                "fields 30 % masked), cubic, eb=1e-3*range, batched compress + "
                                "retrievals at 1/2/4 bits per value"},
         "plain_GBps": round(gb / tp, 3), "plain_ms_per_step": round(tp * 1e3, 4),
-        "batch_speedup": round(tp / tb, 4),
+        "batch_speedup": round(tp / tb, 4), "batch_schedule": schedule,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
@@ -467,8 +473,13 @@ def batch_main(args):
     xs = [fieldgen.lognormal_torch(shape, seed=i) for i in range(n)]
     ebs = [1e-5 * float(x.max() - x.min()) for x in xs]
     ctx = pkg.Context(0)
+    schedule = None
     if not args.no_autotune:
         ctx.autotune(xs[0], ebs[0])
+        # the batch schedule (direct or graph replays, persistent grid) for
+        # this shape, used by the batched calls below (automatic mode)
+        schedule = ctx.autotune_batch(xs[0], ebs[0], copies=n)
+        ctx.set_batch_graphs("auto")
 
     def batched():
         ss = ctx.compress_batch(xs, ebs)
@@ -508,6 +519,7 @@ def batch_main(args):
         for s in ctx.compress_batch(xs, ebs):
             s.free()
 
+    ctx.set_batch_graphs(False)
     tr_direct = timed(retrieve_only)
     tc_direct = timed(compress_only)
     ctx.set_batch_graphs(True)
@@ -531,6 +543,7 @@ def batch_main(args):
                                 "graphs": ctx.graph_stats()},
         "batched_compress_ms": {"direct_launches": round(tc_direct * 1e3, 4),
                                 "graph_replay": round(tc_graph * 1e3, 4)},
+        "batch_schedule": schedule,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

@@ -359,6 +359,20 @@ ipc_status ipc_autotune(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
                         int dtype, double abs_eb, const ipc_options *opts, int32_t *zseg_c,
                         int32_t *zseg_r, uint32_t capacity);
 ipc_status ipc_autotune_clear(ipc_ctx *ctx);
+/* Batch autotuner (beyond the paper): the schedule of batches of `copies`
+ * (1..64) copies of a representative field of this (shape, dtype,
+ * interpolation), for the automatic batch mode of ipc_ctx_set_batch_graphs.
+ * Each candidate is timed three times, in turns, on one compression batch and
+ * one full-precision retrieval batch: direct launches, and graph replays whose
+ * full queue slots run 3, 4 or 5 (float64: 2, 3 or 4) workgroups per CU for
+ * retrieval and 2, 3 or 4 (float64: 1 or 2) for compression.  The choice is
+ * kept in the context (ipc_autotune_clear forgets it); `choice` (NULL, or 4
+ * entries) receives compression's (graphs 0/1, workgroups per CU), then
+ * retrieval's.  Results never depend on the schedule.  IPC_EUNSUPPORTED for
+ * shapes without fused launches. */
+ipc_status ipc_autotune_batch(ipc_ctx *ctx, const void *field_dev, const uint64_t *dims, int ndim,
+                              int dtype, double abs_eb, const ipc_options *opts, uint32_t copies,
+                              int32_t choice[4]);
 /* Install column lengths chosen earlier (e.g. by ipc_autotune in another
  * process): n entries per direction indexed by level, 0 = default rule. */
 ipc_status ipc_autotune_set(ipc_ctx *ctx, const uint64_t *dims, int ndim, int dtype, int interp,
@@ -394,10 +408,15 @@ ipc_status ipc_ctx_pass_times(const ipc_ctx *ctx, float *ms, uint32_t capacity, 
  * each level) into a HIP graph and replayed after.  Results are identical to
  * the direct launches (the same kernels' bodies).  Graphs, the device table
  * (about 10 MB) and its pinned staging copy live until ipc_ctx_destroy.
- * Off by default (the Python Server turns it on: serving mixes ran 22-26 %
- * more requests per second with it).  If the context's stream cannot be
- * captured, the call runs the direct launches and the setting turns itself
- * off.  ipc_ctx_graph_stats counts captured graphs and replays. */
+ * `on`: 0 = direct launches (the default), 2 = automatic (the schedule
+ * ipc_autotune_batch chose when every field of the batch has that tuned
+ * shape, else graph replays only when no field exceeds 2^22 points: on large
+ * fields the launch overhead a replay saves is small against the work), any
+ * other value = always graph replays (the Python Server's setting: serving
+ * mixes ran 22-26 % more requests per second with it).  Compression batches
+ * follow the same setting.  If the context's stream cannot be captured, the
+ * call runs the direct launches and the setting turns itself off.
+ * ipc_ctx_graph_stats counts captured graphs and replays. */
 ipc_status ipc_ctx_set_batch_graphs(ipc_ctx *ctx, int on);
 ipc_status ipc_ctx_graph_stats(const ipc_ctx *ctx, uint64_t *captured, uint64_t *replays);
 

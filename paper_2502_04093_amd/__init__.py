@@ -143,6 +143,8 @@ SIGNATURES = {
     "ipc_ctx_set_profiling": (c_int, [c_void_p, c_int, c_int]),
     "ipc_ctx_pass_times": (c_int, [c_void_p, P(c_float), c_uint32, P(c_uint32)]),
     "ipc_ctx_set_batch_graphs": (c_int, [c_void_p, c_int]),
+    "ipc_autotune_batch": (c_int, [c_void_p, c_void_p, P(c_uint64), c_int, c_int, c_double, c_void_p,
+                                   c_uint32, P(ctypes.c_int32)]),
     "ipc_ctx_graph_stats": (c_int, [c_void_p, P(c_uint64), P(c_uint64)]),
     "ipc_status_string": (ctypes.c_char_p, [c_int]),
     "ipc_last_error": (ctypes.c_char_p, [c_void_p]),
@@ -250,10 +252,12 @@ class Context:
     def set_profiling(self, on: bool = True, only_pass: int = -1):
         _check(lib().ipc_ctx_set_profiling(self._p, int(bool(on)), int(only_pass)), self._p)
 
-    def set_batch_graphs(self, on: bool = True):
-        """Batched retrievals as queue launches replayed from captured HIP
-        graphs (see ipc_ctx_set_batch_graphs)."""
-        _check(lib().ipc_ctx_set_batch_graphs(self._p, int(bool(on))), self._p)
+    def set_batch_graphs(self, on=True):
+        """Batches as queue launches replayed from captured HIP graphs: True
+        (always), False (direct launches) or "auto" (the batch autotuner's
+        choice, else by field size); see ipc_ctx_set_batch_graphs."""
+        mode = 2 if on == "auto" else int(bool(on))
+        _check(lib().ipc_ctx_set_batch_graphs(self._p, mode), self._p)
 
     def graph_stats(self):
         """(graphs captured, graph replays) so far."""
@@ -303,6 +307,22 @@ class Context:
         _check(lib().ipc_autotune(self._p, c_void_p(field.data_ptr()), dims, field.dim(), dt,
                                   float(eb), ctypes.byref(opts), zc, zr, 32), self._p)
         return list(zc), list(zr)
+
+    def autotune_batch(self, field, eb: float, copies: int = 2, interp: str = "cubic"):
+        """Choose the batch schedule for this field's shape, dtype and
+        interpolation (ipc_autotune_batch); returns {"compress": (graphs,
+        workgroups per CU), "retrieve": (...)}."""
+        import torch
+        if not (field.is_cuda and field.is_contiguous()):
+            raise ValueError("field must be a contiguous device tensor")
+        dims = (c_uint64 * field.dim())(*field.shape)
+        opts = ipc_options()
+        opts.interp = IPC_CUBIC if interp == "cubic" else IPC_LINEAR
+        ch = (ctypes.c_int32 * 4)()
+        dt = IPC_F32 if field.dtype == torch.float32 else IPC_F64
+        _check(lib().ipc_autotune_batch(self._p, c_void_p(field.data_ptr()), dims, field.dim(), dt,
+                                        float(eb), ctypes.byref(opts), int(copies), ch), self._p)
+        return {"compress": (bool(ch[0]), int(ch[1])), "retrieve": (bool(ch[2]), int(ch[3]))}
 
     def autotune_set(self, shape, dtype, zseg_c, zseg_r, interp: str = "cubic"):
         """Install column lengths (lists indexed by level, 0 = default) for a

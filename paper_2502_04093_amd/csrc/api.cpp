@@ -39,6 +39,12 @@ struct TuneVal {
   int32_t zseg_c[32];  // compression, by level
   int32_t zseg_r[32];  // retrieval, by level
 };
+// the batch schedule chosen for a shape: graph replays or direct launches,
+// and the persistent grid of a full queue slot (workgroups per CU)
+struct BatchTune {
+  int graphs_r = 0, graphs_c = 0;
+  uint32_t per_cu_r = 0, per_cu_c = 0;
+};
 
 struct ipc_ctx {
   int device = 0;
@@ -86,8 +92,13 @@ struct ipc_ctx {
   std::vector<float> pass_ms;     // per pass (0 = not run)
   size_t prof_np = 0;
   int prof_only = -1;
-  // batched retrievals as queue launches replayed from captured HIP graphs
-  bool batch_graphs = false;
+  // batches as queue launches replayed from captured HIP graphs: 0 never
+  // (direct launches), 1 always, 2 as the batch autotuner chose for the
+  // batch's shape, else by field size
+  int batch_graphs = 0;
+  std::map<TuneKey, BatchTune> tuned_batch;
+  // workgroups per CU of a full queue slot while a batch runs (0 = default)
+  uint32_t per_cu_r = 0, per_cu_c = 0;
   std::map<std::vector<int>, hipGraphExec_t> graphs;  // by launch shape
   void *ws_q = nullptr;       // claim counters, then the queue table (fixed address)
   size_t ws_q_bytes = 0;
@@ -1192,7 +1203,7 @@ size_t queue_table_bytes() {
 
 // persistent grid of a level slot: a class of its item count
 uint32_t queue_grid(const ipc_ctx *ctx, uint32_t items, size_t isz) {
-  const uint32_t full = uint32_t(ctx->n_cu) * (isz == 4 ? 5u : 4u);
+  const uint32_t full = uint32_t(ctx->n_cu) * (ctx->per_cu_r ? ctx->per_cu_r : (isz == 4 ? 5u : 4u));
   if (items <= 16) return 16;
   if (items <= 128) return 128;
   return full;
@@ -1203,7 +1214,40 @@ uint32_t queue_grid(const ipc_ctx *ctx, uint32_t items, size_t isz) {
 uint32_t queue_grid_c(const ipc_ctx *ctx, uint32_t items, size_t isz) {
   if (items <= 16) return 16;
   if (items <= 128) return 128;
-  return uint32_t(ctx->n_cu) * (isz == 4 ? 4u : 2u);
+  return uint32_t(ctx->n_cu) * (ctx->per_cu_c ? ctx->per_cu_c : (isz == 4 ? 4u : 2u));
+}
+
+// Fields above this many points make a batch run as direct launches in the
+// automatic mode when the autotuner has no choice for it: there the launch
+// overhead a replay saves is small against the work, and the persistent grid's
+// claiming costs more (two 512^3 fields: 0.59 ms per field replayed, 0.52 ms
+// direct; eight 256x384x384 float64 fields: 1.93 against 1.85 ms).
+constexpr int64_t AUTO_GRAPH_POINTS = int64_t(1) << 22;
+
+TuneKey tune_key(const StreamMeta &m) {
+  return TuneKey{{m.sched.dims3[0], m.sched.dims3[1], m.sched.dims3[2]}, m.dtype, m.interp};
+}
+
+// whether a batch runs as graph replays, and the full-slot grid it uses
+// (set in ctx->per_cu_* for the call)
+bool batch_wants_graphs(ipc_ctx *ctx, const std::vector<const ipc_stream *> &ss, bool compress) {
+  ctx->per_cu_r = ctx->per_cu_c = 0;
+  if (ctx->batch_graphs == 0) return false;
+  if (ctx->batch_graphs == 1) return true;
+  // automatic: the autotuner's choice when every field of the batch has the
+  // same tuned shape, else by the largest field
+  const auto it = ctx->tuned_batch.find(tune_key(ss[0]->meta));
+  bool same = it != ctx->tuned_batch.end();
+  for (const ipc_stream *s : ss) same = same && !(tune_key(s->meta) < it->first) && !(it->first < tune_key(s->meta));
+  if (same) {
+    const BatchTune &b = it->second;
+    ctx->per_cu_r = b.per_cu_r;
+    ctx->per_cu_c = b.per_cu_c;
+    return compress ? b.graphs_c != 0 : b.graphs_r != 0;
+  }
+  int64_t most = 0;
+  for (const ipc_stream *s : ss) most = std::max(most, s->meta.sched.n_points);
+  return most <= AUTO_GRAPH_POINTS;
 }
 
 bool queue_fits(const std::vector<const ipc_stream *> &ss) {
@@ -1350,9 +1394,9 @@ template <typename T>
 void retrieve_batch_levels(ipc_ctx *ctx, const std::vector<const ipc_stream *> &ss,
                            const std::vector<std::vector<int>> &plans, const std::vector<void *> &out,
                            const std::vector<int> &l_start) {
-  if (ctx->batch_graphs && queue_fits(ss)) {
+  if (batch_wants_graphs(ctx, ss, false) && queue_fits(ss)) {
     if (retrieve_batch_queue<T>(ctx, ss, plans, out, l_start)) return;
-    ctx->batch_graphs = false;  // this stream cannot be captured: direct launches from now on
+    ctx->batch_graphs = 0;  // this stream cannot be captured: direct launches from now on
   }
   retrieve_batch_fused<T>(ctx, ss, plans, out, l_start);
 }
@@ -1855,7 +1899,7 @@ ipc_status ipc_ctx_set_profiling(ipc_ctx *ctx, int on, int only_pass) {
 
 ipc_status ipc_ctx_set_batch_graphs(ipc_ctx *ctx, int on) {
   if (!ctx) return IPC_EINVAL;
-  ctx->batch_graphs = on != 0;
+  ctx->batch_graphs = on == 0 ? 0 : (on == 2 ? 2 : 1);
   return IPC_OK;
 }
 
@@ -2769,10 +2813,10 @@ ipc_status ipc_compress_batch(ipc_ctx *ctx, uint32_t n, const void *const *field
       // and the batch fits the table; otherwise one direct launch per level
       std::vector<const ipc_stream *> cs(ss.begin(), ss.end());
       bool done = false;
-      if (ctx->batch_graphs && queue_fits(cs)) {
+      if (batch_wants_graphs(ctx, cs, true) && queue_fits(cs)) {
         done = dtype == IPC_F32 ? compress_batch_queue<float>(ctx, ss, fields_dev, abs_eb, redo)
                                 : compress_batch_queue<double>(ctx, ss, fields_dev, abs_eb, redo);
-        if (!done) ctx->batch_graphs = false;  // this stream cannot be captured
+        if (!done) ctx->batch_graphs = 0;  // this stream cannot be captured
       }
       if (!done) {
         if (dtype == IPC_F32)
@@ -2990,6 +3034,100 @@ ipc_status ipc_autotune(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
   return IPC_OK;
 }
 
+ipc_status ipc_autotune_batch(ipc_ctx *ctx, const void *field_dev, const uint64_t *dims, int ndim,
+                              int dtype, double abs_eb, const ipc_options *opts, uint32_t copies,
+                              int32_t choice[4]) {
+  if (!ctx || !field_dev || !dims || copies < 1 || copies > 64) return IPC_EINVAL;
+  if (!fused_dims(dims, ndim, opts)) {
+    set_err(ctx, "no batch schedule to choose for this shape (fused 3-D and 2-D fields only)");
+    return IPC_EUNSUPPORTED;
+  }
+  const int saved = ctx->batch_graphs;
+  // candidate schedules: direct launches (0), then graph replays with a full
+  // queue slot of that many workgroups per CU
+  const bool f32 = dtype == IPC_F32;
+  const std::vector<int> cand_r = f32 ? std::vector<int>{0, 3, 4, 5} : std::vector<int>{0, 2, 3, 4};
+  const std::vector<int> cand_c = f32 ? std::vector<int>{0, 2, 3, 4} : std::vector<int>{0, 1, 2};
+  std::vector<const void *> fields(copies, field_dev);
+  std::vector<uint64_t> dd(size_t(copies) * size_t(ndim));
+  std::vector<double> ebs(copies, abs_eb);
+  for (uint32_t i = 0; i < copies; ++i)
+    for (int j = 0; j < ndim; ++j) dd[size_t(i) * ndim + j] = dims[j];
+  int64_t d64[3] = {1, 1, 1};
+  for (int j = 0; j < ndim; ++j) d64[3 - ndim + j] = int64_t(dims[j]);
+  const TuneKey k{{d64[0], d64[1], d64[2]}, dtype, opts ? opts->interp : IPC_CUBIC};
+  double best_r = 1e30, best_c = 1e30;
+  int pick_r = 0, pick_c = 0;
+  ipc_status st = IPC_OK;
+  std::vector<ipc_stream *> ss(copies, nullptr);
+  std::vector<ipc_state *> sts(copies, nullptr);
+  std::vector<ipc_target> tg(copies);
+  for (ipc_target &t : tg) {
+    t.kind = IPC_TARGET_EB;
+    t.value = abs_eb;
+  }
+  auto free_all = [&] {
+    for (ipc_state *&x : sts) {
+      if (x) ipc_state_free(x);
+      x = nullptr;
+    }
+    for (ipc_stream *&x : ss) {
+      if (x) ipc_stream_free(x);
+      x = nullptr;
+    }
+  };
+  // every candidate three times, in turns; a schedule is tried on the shape
+  // as the automatic mode would run it (a forced entry in the table)
+  for (int rep = 0; rep < 3 && st == IPC_OK; ++rep) {
+    for (size_t ci = 0; ci < std::max(cand_r.size(), cand_c.size()) && st == IPC_OK; ++ci) {
+      BatchTune bt;
+      bt.graphs_c = ci < cand_c.size() && cand_c[ci] != 0;
+      bt.per_cu_c = ci < cand_c.size() ? uint32_t(cand_c[ci]) : 0u;
+      bt.graphs_r = ci < cand_r.size() && cand_r[ci] != 0;
+      bt.per_cu_r = ci < cand_r.size() ? uint32_t(cand_r[ci]) : 0u;
+      ctx->tuned_batch[k] = bt;
+      ctx->batch_graphs = 2;
+      auto t0 = std::chrono::steady_clock::now();
+      st = ipc_compress_batch(ctx, copies, fields.data(), dd.data(), ndim, dtype, ebs.data(), opts, ss.data());
+      auto t1 = std::chrono::steady_clock::now();
+      if (st != IPC_OK) break;
+      st = ipc_retrieve_batch(ctx, copies, ss.data(), tg.data(), sts.data(), nullptr);
+      auto t2 = std::chrono::steady_clock::now();
+      if (st != IPC_OK) break;
+      const double tc = std::chrono::duration<double>(t1 - t0).count();
+      const double tr = std::chrono::duration<double>(t2 - t1).count();
+      if (ci < cand_c.size() && tc < best_c) {
+        best_c = tc;
+        pick_c = cand_c[ci];
+      }
+      if (ci < cand_r.size() && tr < best_r) {
+        best_r = tr;
+        pick_r = cand_r[ci];
+      }
+      free_all();
+    }
+  }
+  free_all();
+  ctx->batch_graphs = saved;
+  if (st != IPC_OK) {
+    ctx->tuned_batch.erase(k);
+    return st;
+  }
+  BatchTune bt;
+  bt.graphs_r = pick_r != 0;
+  bt.per_cu_r = uint32_t(pick_r);
+  bt.graphs_c = pick_c != 0;
+  bt.per_cu_c = uint32_t(pick_c);
+  ctx->tuned_batch[k] = bt;
+  if (choice) {
+    choice[0] = bt.graphs_c;
+    choice[1] = int32_t(bt.per_cu_c);
+    choice[2] = bt.graphs_r;
+    choice[3] = int32_t(bt.per_cu_r);
+  }
+  return IPC_OK;
+}
+
 ipc_status ipc_autotune_set(ipc_ctx *ctx, const uint64_t *dims, int ndim, int dtype, int interp,
                             const int32_t *zseg_c, const int32_t *zseg_r, uint32_t n) {
   if (!ctx || !dims || ndim < 1 || ndim > 3 || !zseg_c || !zseg_r) return IPC_EINVAL;
@@ -3009,6 +3147,7 @@ ipc_status ipc_autotune_set(ipc_ctx *ctx, const uint64_t *dims, int ndim, int dt
 ipc_status ipc_autotune_clear(ipc_ctx *ctx) {
   if (!ctx) return IPC_EINVAL;
   ctx->tuned.clear();
+  ctx->tuned_batch.clear();
   return IPC_OK;
 }
 

@@ -174,3 +174,34 @@ def test_batched_compression_from_graph_replays_equals_oracle(ctx, dtype, interp
                 s.free()
     c1, r1 = ctx.graph_stats()
     assert c1 - c0 == 2  # two launch shapes: each captured once, then replayed
+
+
+def test_batch_autotuner_and_automatic_mode(ctx):
+    """ipc_autotune_batch picks a batch schedule for a shape; batches in the
+    automatic mode (the tuned shape, and an untuned mix decided by field
+    size) equal the oracle byte for byte."""
+    x = fieldgen.grf((64, 96, 200), -5.0 / 6.0, seed=90, dtype=np.float32)
+    eb0 = 1e-4 * fieldgen.value_range(x)
+    ch = ctx.autotune_batch(_dev(x), eb0, copies=3)
+    assert ch["compress"][0] == (ch["compress"][1] != 0) and ch["compress"][1] in (0, 2, 3, 4)
+    assert ch["retrieve"][0] == (ch["retrieve"][1] != 0) and ch["retrieve"][1] in (0, 3, 4, 5)
+    ctx.set_batch_graphs("auto")
+    try:
+        for shapes in ([(64, 96, 200)] * 3, [(33, 40, 70), (9, 17, 130), (40, 200, 16)]):
+            print(f"automatic batches: {shapes}", flush=True)
+            xs = [fieldgen.grf(sh, -5.0 / 6.0, seed=91 + i, dtype=np.float32) for i, sh in enumerate(shapes)]
+            ebs = [1e-4 * fieldgen.value_range(v) for v in xs]
+            ss = ctx.compress_batch([_dev(v) for v in xs], ebs)
+            refs = [codec.compress(v, e) for v, e in zip(xs, ebs)]
+            assert [s.to_bytes() for s in ss] == refs
+            sts = ctx.retrieve_batch(ss, eb=[10 * e for e in ebs])
+            for i, (st, ref, e) in enumerate(zip(sts, refs, ebs)):
+                o = codec.retrieve(ref, "eb", 10 * e)
+                assert st.plan == list(o.plan), (shapes, i)
+                assert _bytes(st.tensor()) == o.field.tobytes(), (shapes, i)
+                st.free()
+            for s in ss:
+                s.free()
+    finally:
+        ctx.set_batch_graphs(False)
+        ctx.autotune_clear()
