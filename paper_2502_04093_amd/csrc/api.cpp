@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -18,6 +21,7 @@
 #include <vector>
 
 #include <rocprofiler-sdk-roctx/roctx.h>
+#include <unistd.h>
 
 #include "ipc_internal.h"
 #include "kernels.h"
@@ -177,43 +181,102 @@ struct TraceRange {
   TraceRange &operator=(const TraceRange &) = delete;
 };
 
+// Host worker threads for parallel_for, started once per process and kept:
+// starting threads per call had cost about as much as the planning they
+// shared out.  One job at a time; a caller that finds the pool busy (another
+// host thread's call) runs its job alone.
+class WorkerPool {
+ public:
+  static WorkerPool &get() {
+    static WorkerPool pool;
+    return pool;
+  }
+  size_t helpers() const { return th_.size(); }
+  // fn(i) for i in [0, n) on the helpers and the calling thread; false (and
+  // nothing run) when the pool is busy
+  bool run(size_t n, const std::function<void(size_t)> &fn) {
+    // a forked child has none of the helpers
+    if (getpid() != pid_) return false;
+    std::unique_lock<std::mutex> busy(job_mu_, std::try_to_lock);
+    if (!busy.owns_lock() || th_.empty()) return false;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      fn_ = &fn;
+      n_ = n;
+      next_.store(0);
+      working_ = th_.size();
+      ++gen_;
+    }
+    cv_.notify_all();
+    work();
+    std::unique_lock<std::mutex> lk(mu_);
+    done_cv_.wait(lk, [&] { return working_ == 0; });
+    fn_ = nullptr;
+    return true;
+  }
+
+ private:
+  WorkerPool() : pid_(getpid()) {
+    const size_t hw = std::max<size_t>(1, std::min<size_t>(16, std::thread::hardware_concurrency()));
+    try {
+      for (size_t t = 1; t < hw; ++t) th_.emplace_back([this] { loop(); });
+    } catch (...) {
+    }
+  }
+  ~WorkerPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (std::thread &t : th_) t.join();
+  }
+  void work() {
+    for (size_t i = next_.fetch_add(1); i < n_; i = next_.fetch_add(1)) (*fn_)(i);
+  }
+  void loop() {
+    uint64_t seen = 0;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+      }
+      work();
+      std::lock_guard<std::mutex> lk(mu_);
+      if (--working_ == 0) done_cv_.notify_one();
+    }
+  }
+  pid_t pid_;
+  std::vector<std::thread> th_;
+  std::mutex job_mu_, mu_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(size_t)> *fn_ = nullptr;
+  size_t n_ = 0;
+  std::atomic<size_t> next_{0};
+  size_t working_ = 0;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+
 // fn(i) for i in [0, n) on up to 16 host threads (planning several requests:
 // each plan reads only its stream's tables).  The first exception any call
-// throws is rethrown after all threads have joined.
+// throws is rethrown once every call has returned.
 template <typename Fn>
 void parallel_for(size_t n, Fn fn) {
-  const size_t hw = std::max<size_t>(1, std::min<size_t>(16, std::thread::hardware_concurrency()));
-  const size_t nt = std::min(n, hw);
-  if (nt <= 1 || n < 4) {
-    for (size_t i = 0; i < n; ++i) fn(i);
-    return;
-  }
   std::exception_ptr err;
   std::mutex err_mu;
-  std::vector<std::thread> th;
-  th.reserve(nt - 1);
-  auto work = [&](size_t t, size_t stride) {
-    for (size_t i = t; i < n; i += stride) {
-      try {
-        fn(i);
-      } catch (...) {
-        std::lock_guard<std::mutex> lk(err_mu);
-        if (!err) err = std::current_exception();
-      }
+  const std::function<void(size_t)> job = [&](size_t i) {
+    try {
+      fn(i);
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(err_mu);
+      if (!err) err = std::current_exception();
     }
   };
-  size_t started = 0;  // threads 1 .. started run their share
-  try {
-    for (size_t t = 1; t < nt; ++t) {
-      th.emplace_back(work, t, nt);
-      started = t;
-    }
-  } catch (...) {
-  }
-  // this thread: share 0 and the shares of threads that could not start
-  for (size_t t = 0; t < nt; ++t)
-    if (t == 0 || t > started) work(t, nt);
-  for (std::thread &x : th) x.join();
+  if (n < 4 || !WorkerPool::get().run(n, job))
+    for (size_t i = 0; i < n; ++i) job(i);
   if (err) std::rethrow_exception(err);
 }
 
