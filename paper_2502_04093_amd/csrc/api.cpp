@@ -63,6 +63,7 @@ struct ipc_ctx {
   // null stream, so inputs written there are complete before they are read
   bool follow_null = false;
   hipEvent_t ev_null = nullptr;
+  hipEvent_t ev_copy = nullptr;  // a compression's summary copy (the host waits on it alone)
   std::string err;
   std::multimap<size_t, void *> cache;  // freed device blocks by size
   size_t cached_bytes = 0;
@@ -2014,11 +2015,13 @@ ipc_status ipc_ctx_create(int device, void *hip_stream, ipc_ctx **out) {
   }
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_null, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_copy, hipEventDisableTiming) != hipSuccess ||
       hipMalloc(&c->dev_zero, 256) != hipSuccess || hipMemset(c->dev_zero, 0, 256) != hipSuccess) {
     (void)hipGetLastError();
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->ev_null) (void)hipEventDestroy(c->ev_null);
+    if (c->ev_copy) (void)hipEventDestroy(c->ev_copy);
     if (c->dev_zero) (void)hipFree(c->dev_zero);
     if (c->owned) (void)hipStreamDestroy(c->owned);
     delete c;
@@ -2068,6 +2071,7 @@ void ipc_ctx_destroy(ipc_ctx *ctx) {
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   if (ctx->ev_null) (void)hipEventDestroy(ctx->ev_null);
+  if (ctx->ev_copy) (void)hipEventDestroy(ctx->ev_copy);
   if (ctx->owned) (void)hipStreamDestroy(ctx->owned);
   delete ctx;
 }
@@ -2128,7 +2132,8 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
     for (int attempt = 0; attempt < 2; ++attempt) {
       ensure_ws(ctx, ctx->ws_out, ctx->ws_out_cap, cap * sizeof(OutlierRec));
       size_t cap_recs = ctx->ws_out_cap / sizeof(OutlierRec);
-      hip_check(ctx, hipMemsetAsync(summary, 0, sum_bytes, ctx->stream), "memset");
+      // (the fused path's anchor launch clears the summary itself)
+      if (!fused) hip_check(ctx, hipMemsetAsync(summary, 0, sum_bytes, ctx->stream), "memset");
       unsigned long long *sizes = reinterpret_cast<unsigned long long *>(summary + 16);
       CompressOut o;
       o.payload = static_cast<uint32_t *>(s->payload.p);
@@ -2168,7 +2173,8 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
         Level3Args A = anchor3_args(sc);
         prof_mark(ctx, 0, true);
         hip_check(ctx, launch_anchor3_compress(dtype, A, field_dev, ctx->ws_g[K & 1], abs_eb, o,
-                                               ctx->stream),
+                                               reinterpret_cast<uint32_t *>(summary),
+                                               uint32_t(sum_bytes / 4), ctx->stream),
                   "anchor kernel launch");
         prof_mark(ctx, 0, false);
         for (const Level3Args &La : las) {
@@ -2197,8 +2203,21 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
         hip_check(ctx, launch_all_sizes(static_cast<const PassArgs *>(ctx->ws_args), P, max_chunks,
                                         o.masks, sizes, ctx->stream),
                   "sizes kernel launch");
+      hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
+      if (ctx->host_summary_bytes < sum_bytes) {
+        if (ctx->host_summary) (void)hipHostFree(ctx->host_summary);
+        ctx->host_summary = nullptr;
+        ctx->host_summary_bytes = 0;
+        hip_check(ctx, hipHostMalloc(&ctx->host_summary, sum_bytes, hipHostMallocDefault), "pinned alloc");
+        ctx->host_summary_bytes = sum_bytes;
+      }
+      char *hostp = static_cast<char *>(ctx->host_summary);
+      hip_check(ctx, hipMemcpyAsync(hostp, summary, sum_bytes, hipMemcpyDeviceToHost, ctx->stream), "copy");
+      hip_check(ctx, hipEventRecord(ctx->ev_copy, ctx->stream), "event");
       // the outlier index, sorted on the device (records stay there until a
-      // serialization asks for them), enqueued behind the level launches
+      // serialization asks for them), queued behind the summary copy: it runs
+      // while the host reads the summary, and only later work on the same
+      // stream reads it
       {
         const uint64_t nc = uint64_t(sc.n_chunks);
         dev_free(ctx, s->out_gchunk);
@@ -2220,17 +2239,7 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
                                             static_cast<uint64_t *>(s->out_bits.p), ctx->stream),
                   "outlier index launch");
       }
-      hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
-      if (ctx->host_summary_bytes < sum_bytes) {
-        if (ctx->host_summary) (void)hipHostFree(ctx->host_summary);
-        ctx->host_summary = nullptr;
-        ctx->host_summary_bytes = 0;
-        hip_check(ctx, hipHostMalloc(&ctx->host_summary, sum_bytes, hipHostMallocDefault), "pinned alloc");
-        ctx->host_summary_bytes = sum_bytes;
-      }
-      char *hostp = static_cast<char *>(ctx->host_summary);
-      hip_check(ctx, hipMemcpyAsync(hostp, summary, sum_bytes, hipMemcpyDeviceToHost, ctx->stream), "copy");
-      hip_check(ctx, hipStreamSynchronize(ctx->stream), "compress");
+      hip_check(ctx, hipEventSynchronize(ctx->ev_copy), "compress");
       prof_end(ctx);
       uint64_t nout;
       std::memcpy(&nout, hostp, 8);

@@ -205,8 +205,11 @@ hipError_t launch_level3_compress(int dtype, int interp, const Level3Args &L, co
 hipError_t launch_level3_retrieve(int dtype, int interp, const Level3Args &L, const void *gin,
                                   void *gout, const int disc[3], const RetrieveIn &in, double eb,
                                   hipStream_t s);
+// `clear`: clear_words words zeroed before the anchors write anything (the
+// call's summary block, which the anchors are the first to update)
 hipError_t launch_anchor3_compress(int dtype, const Level3Args &A, const void *x, void *gout,
-                                   double eb, const CompressOut &o, hipStream_t s);
+                                   double eb, const CompressOut &o, uint32_t *clear,
+                                   uint32_t clear_words, hipStream_t s);
 hipError_t launch_anchor3_retrieve(int dtype, const Level3Args &A, void *gout, const RetrieveIn &in,
                                    double eb, hipStream_t s);
 // g[c] = field[step * c] over the coarse grid gd

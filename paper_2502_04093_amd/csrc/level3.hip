@@ -1698,11 +1698,20 @@ __device__ __forceinline__ void anchor3_compress_body(const Level3Args &L, const
   if (mb) atomicMax(o.maxabs_bits, mb);
 }
 
+// One wave (64 threads).  The cleared words are updated again by this wave's
+// anchors (after the fence, which waits until the clearing stores have
+// reached memory) and by later launches.
 template <typename T>
-__global__ void k_anchor3_compress(Level3Args L, const T *__restrict__ x, T *gout, double eb,
-                                   T two_eb, T inv, T qmax, CompressOut o) {
+__global__ __launch_bounds__(64) void k_anchor3_compress(Level3Args L, const T *__restrict__ x, T *gout,
+                                                         double eb, T two_eb, T inv, T qmax,
+                                                         CompressOut o, uint32_t *clear,
+                                                         uint32_t clear_words) {
   __shared__ uint32_t sv[64];
   __shared__ uint32_t sor;
+  if (clear_words) {
+    for (uint32_t i = threadIdx.x; i < clear_words; i += 64) clear[i] = 0u;
+    __threadfence();
+  }
   anchor3_compress_body<T>(L, x, gout, eb, two_eb, inv, qmax, o, sv, sor);
 }
 
@@ -2048,13 +2057,16 @@ hipError_t launch_level3_retrieve(int dtype, int interp, const Level3Args &L, co
 }
 
 hipError_t launch_anchor3_compress(int dtype, const Level3Args &A, const void *x, void *gout,
-                                   double eb, const CompressOut &o, hipStream_t s) {
+                                   double eb, const CompressOut &o, uint32_t *clear,
+                                   uint32_t clear_words, hipStream_t s) {
   if (dtype == IPC_F32)
     hipLaunchKernelGGL(k_anchor3_compress<float>, dim3(1), dim3(64), 0, s, A, (const float *)x,
-                       (float *)gout, eb, float(2.0 * eb), float(1.0 / (2.0 * eb)), float(QMAX_F32), o);
+                       (float *)gout, eb, float(2.0 * eb), float(1.0 / (2.0 * eb)), float(QMAX_F32), o,
+                       clear, clear_words);
   else
     hipLaunchKernelGGL(k_anchor3_compress<double>, dim3(1), dim3(64), 0, s, A, (const double *)x,
-                       (double *)gout, eb, 2.0 * eb, 1.0 / (2.0 * eb), double(QMAX_F64), o);
+                       (double *)gout, eb, 2.0 * eb, 1.0 / (2.0 * eb), double(QMAX_F64), o, clear,
+                       clear_words);
   return hipGetLastError();
 }
 
