@@ -133,7 +133,9 @@ ipc_status ipc_ctx_set_stream(ipc_ctx *ctx, void *hip_stream);
  * float32 or float64 on the device with absolute error bound abs_eb > 0
  * (finite).  The field is read only and must stay valid for the call.
  * Every reconstructed value satisfies |x - x^| <= abs_eb (Sec. 4.2.2).
- * The returned stream is device resident. */
+ * The returned stream is device resident.  On return every read of the field
+ * is done; the stream's outlier index may still be building on the context's
+ * stream, behind which every later call on the context is ordered. */
 ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dims, int ndim,
                         int dtype, double abs_eb, const ipc_options *opts, ipc_stream **out);
 
