@@ -783,8 +783,9 @@ __device__ __forceinline__ void level3_compress_body(const Level3Args &L, const 
     }
   };
 
-  load_ring(L, gin, S, m0, li, ro);
+  // the first step's inputs requested before the ring's loads are waited for
   issue(m0);
+  load_ring(L, gin, S, m0, li, ro);
 
   for (int m = m0; m < m1; ++m) {
     // a fresh copy of the thread index each step: values derived from it are
@@ -1339,6 +1340,10 @@ __device__ __forceinline__ void level3_retrieve_body(const Level3Args &L, const 
   const bool vec = (Lx & 3) == 0 && (reinterpret_cast<uintptr_t>(gout) & 15) == 0;
   const uint32_t plane = uint32_t(Ly) * uint32_t(Lx);
 
+  // the first step's chunk words and coarse plane requested before the
+  // ring's loads are waited for
+  prefetch_word(m0);
+  issue_ring(tid0, m0 + 2);
   {
     int li[2];
     uint32_t ro[2];
@@ -1346,8 +1351,6 @@ __device__ __forceinline__ void level3_retrieve_body(const Level3Args &L, const 
     ring_entry(tid0, 1, li[1], ro[1]);
     load_ring(L, gin, S, m0, li, ro);
   }
-  issue_ring(tid0, m0 + 2);
-  prefetch_word(m0);
 
   for (int m = m0; m < m1; ++m) {
     // a fresh copy of the thread index each step: values derived from it are
