@@ -503,13 +503,16 @@ void device_blocks(ipc_ctx *ctx, const StreamMeta &m, DevBuf &blk, DevBuf &tabs)
   packed_chunk_offsets(m, craw);  // nc + 1 entries
   std::vector<uint32_t> cblk(nc + 1), ccount(nc + 1, 0);
   uint32_t nb = 0;
-  for (const PassGeom &p : m.sched.passes)
+  std::vector<uint32_t> cnt;
+  for (const PassGeom &p : m.sched.passes) {
+    chunk_counts(p, cnt);
     for (int64_t c = 0; c < p.n_chunks; ++c) {
       const size_t g = size_t(p.chunk_base + c);
       cblk[g] = nb;
-      ccount[g] = uint32_t(chunk_count(p, c));
+      ccount[g] = cnt[size_t(c)];
       nb += uint32_t(__builtin_popcount(m.masks[g]));
     }
+  }
   cblk[nc] = nb;
   const size_t b_raw = craw.size() * 8, b_blk = cblk.size() * 4, b_cnt = ccount.size() * 4;
   tabs = dev_alloc(ctx, b_raw + b_blk + b_cnt);

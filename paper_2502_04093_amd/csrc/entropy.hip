@@ -121,8 +121,11 @@ __global__ __launch_bounds__(EC_WG) void k_ec_encode(const EcBlock *__restrict__
   ByteSink out(dst, W);
   Encoder enc;
   uint32_t p0 = PROB_ONE / 2;
+  // each word loaded one word ahead, while the one before it is coded
+  uint32_t next = W ? src[0] : 0u;
   for (uint32_t w = 0; w < W; ++w) {
-    const uint32_t word = src[w];
+    const uint32_t word = next;
+    if (w + 1 < W) next = src[w + 1];
     const uint32_t nb = count - 32 * w < 32 ? count - 32 * w : 32;
     for (uint32_t j = 0; j < nb; ++j) enc.bit((word >> j) & 1u, p0, out);
   }
@@ -137,18 +140,20 @@ __global__ __launch_bounds__(EC_WG) void k_ec_encode(const EcBlock *__restrict__
   }
 }
 
-// one wave per block: stored words from the scratch slot to their place in
-// the coded payload
+// 16 lanes per block (a stored block holds at most 64 words, most far
+// fewer): stored words from the scratch slot to their place in the coded
+// payload
+constexpr int EC_GATHER_LANES = 16;
 __global__ __launch_bounds__(256) void k_ec_gather(const EcBlock *__restrict__ blk, uint64_t n,
                                                    const uint8_t *__restrict__ words,
                                                    const uint32_t *__restrict__ scratch,
                                                    uint32_t *__restrict__ coded) {
-  const uint64_t i = uint64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const uint64_t i = uint64_t(blockIdx.x) * (256 / EC_GATHER_LANES) + threadIdx.x / EC_GATHER_LANES;
   if (i >= n) return;
-  const int lane = threadIdx.x & 63;
+  const uint32_t lane = threadIdx.x % EC_GATHER_LANES;
   const EcBlock b = blk[i];
   const uint32_t nw = words[i];
-  for (uint32_t w = lane; w < nw; w += 64) coded[b.coded_off + w] = scratch[b.raw_off + w];
+  for (uint32_t w = lane; w < nw; w += EC_GATHER_LANES) coded[b.coded_off + w] = scratch[b.raw_off + w];
 }
 
 // one thread per block: the raw plane (W words) back at raw_off
@@ -169,14 +174,19 @@ __global__ __launch_bounds__(EC_WG) void k_ec_decode(const EcBlock *__restrict__
     return;
   }
   const uint32_t nbytes = 4 * nw;
-  uint32_t pos = 0;      // next byte to read
-  uint32_t cur = 0;      // the word holding byte pos
+  uint32_t pos = 0;                         // next byte to read
+  uint32_t cur = nw ? src[0] : 0u;          // the word holding byte pos
+  uint32_t nxt = nw > 1 ? src[1] : 0u;      // the word after it, loaded ahead
   auto next_byte = [&]() -> uint32_t {
     if (pos >= nbytes) {
       ++pos;
       return 0u;
     }
-    if ((pos & 3) == 0) cur = src[pos >> 2];
+    if ((pos & 3) == 0 && pos) {
+      cur = nxt;
+      const uint32_t k = (pos >> 2) + 1;
+      nxt = k < nw ? src[k] : 0u;
+    }
     const uint32_t v = (cur >> (8 * (pos & 3))) & 0xFFu;
     ++pos;
     return v;
@@ -297,8 +307,9 @@ hipError_t launch_ec_encode(const EcBlock *blk, uint64_t n, const uint32_t *raw,
 hipError_t launch_ec_gather(const EcBlock *blk, uint64_t n, const uint8_t *words,
                             const uint32_t *scratch, uint32_t *coded, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ec_gather, dim3(uint32_t((n + 3) / 4)), dim3(256), 0, s, blk, n, words,
-                     scratch, coded);
+  constexpr uint64_t per_wg = 256 / EC_GATHER_LANES;
+  hipLaunchKernelGGL(k_ec_gather, dim3(uint32_t((n + per_wg - 1) / per_wg)), dim3(256), 0, s, blk, n,
+                     words, scratch, coded);
   return hipGetLastError();
 }
 

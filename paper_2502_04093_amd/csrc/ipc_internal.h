@@ -56,6 +56,9 @@ bool make_schedule(const int64_t *dims, int D, const int *chunk_log2, Schedule &
                    std::string &err);
 // codes in chunk c of pass p
 int64_t chunk_count(const PassGeom &p, int64_t c);
+// the same for every chunk of pass p, in chunk order (out[c], no division per
+// chunk: host loops over every chunk of a stream use it)
+void chunk_counts(const PassGeom &p, std::vector<uint32_t> &out);
 int ceil_log2_u64(uint64_t v);
 
 // ---------------------------------------------------------------- planner

@@ -346,11 +346,13 @@ PlanTables plan_tables(const StreamMeta &m) {
   const Schedule &s = m.sched;
   std::vector<uint64_t> sizes(s.passes.size() * 32, 0);
   size_t blk = 0;
+  std::vector<uint32_t> cnt;
   for (const PassGeom &p : s.passes) {
+    chunk_counts(p, cnt);
     for (int64_t c = 0; c < p.n_chunks; ++c) {
       uint32_t mk = m.masks[size_t(p.chunk_base + c)];
       if (!mk) continue;
-      uint64_t W = uint64_t((chunk_count(p, c) + 31) / 32);
+      uint64_t W = uint64_t((cnt[size_t(c)] + 31) / 32);
       for (int k = 31; k >= 0; --k)
         if ((mk >> k) & 1u) {
           sizes[size_t(p.index) * 32 + k] += 4 * (m.coding ? uint64_t(m.block_words[blk]) : W);

@@ -43,6 +43,24 @@ int64_t chunk_count(const PassGeom &p, int64_t c) {
   return n;
 }
 
+void chunk_counts(const PassGeom &p, std::vector<uint32_t> &out) {
+  out.assign(size_t(p.n_chunks), 0u);
+  // extent of tile t along dimension j (0 past the lattice)
+  auto ext = [&](int j, int64_t t) {
+    const int64_t e = std::min(p.ct[j], p.tdims[j] - t * p.ct[j]);
+    return e > 0 ? e : int64_t(0);
+  };
+  size_t c = 0;
+  for (int64_t t0 = 0; t0 < p.tiles[0]; ++t0) {
+    const int64_t e0 = ext(0, t0);
+    for (int64_t t1 = 0; t1 < p.tiles[1]; ++t1) {
+      const int64_t e01 = e0 * ext(1, t1);
+      for (int64_t t2 = 0; t2 < p.tiles[2] && c < out.size(); ++t2, ++c)
+        out[c] = uint32_t(e01 * ext(2, t2));
+    }
+  }
+}
+
 bool make_schedule(const int64_t *dims, int D, const int *chunk_log2, Schedule &s,
                    std::string &err) {
   if (D < 1 || D > 3) {

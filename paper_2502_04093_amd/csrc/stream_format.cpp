@@ -72,12 +72,14 @@ uint64_t n_blocks(const StreamMeta &m) {
 void packed_chunk_offsets(const StreamMeta &m, std::vector<uint64_t> &off) {
   off.assign(size_t(m.sched.n_chunks) + 1, 0);
   uint64_t w = 0;
+  std::vector<uint32_t> cnt;
   for (const PassGeom &p : m.sched.passes) {
+    chunk_counts(p, cnt);
     for (int64_t c = 0; c < p.n_chunks; ++c) {
       size_t g = size_t(p.chunk_base + c);
       off[g] = w;
       uint32_t mk = m.masks[g];
-      if (mk) w += uint64_t(__builtin_popcount(mk)) * uint64_t((chunk_count(p, c) + 31) / 32);
+      if (mk) w += uint64_t(__builtin_popcount(mk)) * uint64_t((cnt[size_t(c)] + 31) / 32);
     }
   }
   off[size_t(m.sched.n_chunks)] = w;
@@ -252,10 +254,12 @@ bool parse_serialized(const uint8_t *buf, uint64_t n, StreamMeta &m, const uint3
   // masks and payload size; a coded block stores at most its raw words
   uint64_t words = 0, stored = 0;
   size_t blk = 0;
+  std::vector<uint32_t> counts;
   for (const PassGeom &g : m.sched.passes) {
+    chunk_counts(g, counts);
     for (int64_t c = 0; c < g.n_chunks; ++c) {
       uint32_t mk = m.masks[size_t(g.chunk_base + c)];
-      int64_t cnt = chunk_count(g, c);
+      int64_t cnt = int64_t(counts[size_t(c)]);
       if (cnt == 0 && mk) {
         err = "empty chunk with stored planes";
         return false;
