@@ -196,11 +196,12 @@ def plan_host(stream_bytes: bytes, eb=None, bitrate=None, limit: Optional[Sequen
               level_groups: bool = False):
     """Host-only planner: (plan, bound, flags, loaded_bytes) for a serialized stream."""
     L = lib()
-    buf = ctypes.create_string_buffer(bytes(stream_bytes), len(stream_bytes))
+    data = stream_bytes if isinstance(stream_bytes, bytes) else bytes(stream_bytes)
+    buf = ctypes.cast(ctypes.c_char_p(data), c_void_p)  # read in place during the call
     out = (c_uint8 * IPC_MAX_PASSES)()
     lim = (c_uint8 * IPC_MAX_PASSES)(*limit) if limit is not None else None
     bound, flags, loaded = c_double(), c_uint32(), c_uint64()
-    st = L.ipc_plan_host(buf, len(stream_bytes), _target(eb, bitrate, level_groups), lim, out,
+    st = L.ipc_plan_host(buf, len(data), _target(eb, bitrate, level_groups), lim, out,
                          IPC_MAX_PASSES,
                          ctypes.byref(bound), ctypes.byref(flags), ctypes.byref(loaded))
     _check(st)
@@ -412,8 +413,12 @@ class Context:
         """ipc_stream_from_host; device_resident=False keeps the bitplanes in
         pinned host memory that retrievals read in place."""
         out = c_void_p()
-        buf = ctypes.create_string_buffer(bytes(data), len(data))
-        _check(lib().ipc_stream_from_host(self._p, buf, len(data), int(bool(device_resident)),
+        if not isinstance(data, bytes):
+            data = bytes(data)
+        # the library only reads the bytes during the call: their own buffer,
+        # not a copy
+        src = ctypes.cast(ctypes.c_char_p(data), c_void_p)
+        _check(lib().ipc_stream_from_host(self._p, src, len(data), int(bool(device_resident)),
                                           ctypes.byref(out)), self._p)
         return Stream.from_handle(self, out)
 
