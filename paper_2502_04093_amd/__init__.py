@@ -192,6 +192,12 @@ def _target(eb: Optional[float], bitrate: Optional[float], level_groups: bool = 
     return ipc_target(IPC_TARGET_BITRATE | flag, float(bitrate))
 
 
+# PyBytes_FromStringAndSize(NULL, n): an uninitialized bytes object of n bytes
+_new_bytes = ctypes.pythonapi.PyBytes_FromStringAndSize
+_new_bytes.restype = ctypes.py_object
+_new_bytes.argtypes = [c_void_p, ctypes.c_ssize_t]
+
+
 def plan_host(stream_bytes: bytes, eb=None, bitrate=None, limit: Optional[Sequence[int]] = None,
               level_groups: bool = False):
     """Host-only planner: (plan, bound, flags, loaded_bytes) for a serialized stream."""
@@ -498,9 +504,13 @@ class Stream:
 
     def to_bytes(self) -> bytes:
         n = self.nbytes
-        buf = ctypes.create_string_buffer(n)
-        _check(lib().ipc_stream_to_host(self.ctx.handle, self._p, buf, n), self.ctx.handle)
-        return buf.raw
+        # a new bytes object, not yet shared, filled in place by the library
+        # (no zero fill and no second copy)
+        out = _new_bytes(None, n)
+        _check(lib().ipc_stream_to_host(self.ctx.handle, self._p,
+                                        ctypes.cast(ctypes.c_char_p(out), c_void_p), n),
+               self.ctx.handle)
+        return out
 
     def retrieve(self, eb=None, bitrate=None, level_groups: bool = False) -> "State":
         out = c_void_p()

@@ -295,10 +295,14 @@ void hip_check(ipc_ctx *ctx, hipError_t e, const char *what) {
 // Start of a call that issues device work: the context's device becomes
 // current, and a context on its own stream orders the call after the work
 // queued on the null stream so far (an event recorded there, waited for on
-// the context's stream; both outside any graph capture).
+// the context's stream; both outside any graph capture).  When the null
+// stream has nothing left to run, there is nothing to wait for.
 void enter_device(ipc_ctx *ctx) {
   hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
   if (ctx->follow_null) {
+    const hipError_t q = hipStreamQuery(nullptr);
+    if (q == hipSuccess) return;
+    if (q != hipErrorNotReady) hip_check(ctx, q, "null-stream query");
     hip_check(ctx, hipEventRecord(ctx->ev_null, nullptr), "null-stream event");
     hip_check(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_null, 0), "null-stream wait");
   }
