@@ -118,12 +118,12 @@ typedef struct ipc_stream ipc_stream;
 typedef struct ipc_state ipc_state;
 
 /* Context on HIP device `device`, issuing work on `hip_stream` (a
- * hipStream_t; NULL = a stream the context creates and owns).  An owned
- * stream does not synchronize with the null stream by itself, so every call
- * that issues device work first makes it wait for the work queued on the null
- * stream up to that moment: a field written by a pending null-stream kernel
- * is complete before the call reads it, and an output buffer is not written
- * while earlier null-stream work still uses it. */
+ * hipStream_t; NULL = a stream the context creates and owns).  The owned
+ * stream is a blocking stream, so HIP orders each of its operations after the
+ * work queued on the null stream before it (and later null-stream work after
+ * it): a field written by a pending null-stream kernel is complete before a
+ * call reads it, and an output buffer is not written while earlier
+ * null-stream work still uses it. */
 ipc_status ipc_ctx_create(int device, void *hip_stream, ipc_ctx **out);
 void ipc_ctx_destroy(ipc_ctx *ctx);
 /* Switch the hipStream later calls are ordered on (NULL = the owned one). */

@@ -220,8 +220,8 @@ class Context:
     With no stream given, calls are ordered after torch's current stream: a
     non-default torch stream is handed to the library as is; for torch's
     default stream (the null stream, handle 0) the library issues work on a
-    stream of its own that waits, at every call, for the work queued on the
-    null stream so far (ipc_ctx_create with a NULL stream)."""
+    blocking stream of its own, which HIP orders after the work queued on the
+    null stream (ipc_ctx_create with a NULL stream)."""
 
     def __init__(self, device: int = 0, stream=None):
         import torch

@@ -1,9 +1,9 @@
 """Ordering of library calls after work the caller queued on the null stream
 (gpu).
 
-A context made without a stream issues its kernels on a stream of its own;
-every call first waits for what is pending on the null stream (torch's
-default stream).  Each test queues a long spin kernel on the null stream and,
+A context made without a stream issues its kernels on a blocking stream of
+its own, which waits for what is pending on the null stream (torch's default
+stream).  Each test queues a long spin kernel on the null stream and,
 behind it, the kernel that writes the call's input (or last uses its output
 buffer), then calls the library at once: without the wait the call would read
 the input before it is written.  Results are compared with the oracle.
