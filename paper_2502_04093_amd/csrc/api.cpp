@@ -2487,7 +2487,9 @@ static ipc_status retrieve_common(ipc_ctx *ctx, const ipc_stream *s, const std::
     hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
     run_retrieve(ctx, s, plan, 0, stt->field.p);
     hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
-    hip_check(ctx, hipStreamSynchronize(ctx->stream), "retrieve");
+    // the call's last operation: waiting for its event wakes the host sooner
+    // than a stream synchronization
+    hip_check(ctx, hipEventSynchronize(ctx->ev1), "retrieve");
     prof_end(ctx);
     float ms = 0;
     (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
