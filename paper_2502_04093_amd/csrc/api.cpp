@@ -1126,7 +1126,7 @@ void compress_batch_fused(ipc_ctx *ctx, std::vector<ipc_stream *> &ss,
     const size_t nb = (nc + 1 + 1023) / 1024;
     uint32_t *cnt = static_cast<uint32_t *>(
         ensure_ws(ctx, ctx->ws_cnt, ctx->ws_cnt_bytes, 4 * (nc + 1) + 4 * (nb + 1)));
-    hip_check(ctx, launch_outlier_index(static_cast<const OutlierRec *>(o[i].out_recs), o[i].n_out, nout,
+    hip_check(ctx, launch_outlier_index_n(static_cast<const OutlierRec *>(o[i].out_recs), nout, o[i].n_out,
                                         static_cast<const PassArgs *>(args_dev.p) + args_off[i], nc,
                                         static_cast<uint32_t *>(s->out_start.p), cnt, cnt + (nc + 1),
                                         static_cast<uint64_t *>(s->out_gchunk.p),
@@ -1696,7 +1696,7 @@ bool compress_batch_queue(ipc_ctx *ctx, std::vector<ipc_stream *> &ss, const voi
     const size_t nb = (nc + 1 + 1023) / 1024;
     uint32_t *cnt = static_cast<uint32_t *>(
         ensure_ws(ctx, ctx->ws_cnt, ctx->ws_cnt_bytes, 4 * (nc + 1) + 4 * (nb + 1)));
-    hip_check(ctx, launch_outlier_index(static_cast<const OutlierRec *>(o[i].out_recs), o[i].n_out, nout,
+    hip_check(ctx, launch_outlier_index_n(static_cast<const OutlierRec *>(o[i].out_recs), nout, o[i].n_out,
                                         static_cast<const PassArgs *>(args_dev.p) + args_off[i], nc,
                                         static_cast<uint32_t *>(s->out_start.p), cnt, cnt + (nc + 1),
                                         static_cast<uint64_t *>(s->out_gchunk.p),
@@ -2208,7 +2208,8 @@ ipc_status ipc_compress(ipc_ctx *ctx, const void *field_dev, const uint64_t *dim
       // the outlier index, sorted on the device (records stay there until a
       // serialization asks for them), queued behind the summary copy: it runs
       // while the host reads the summary, and only later work on the same
-      // stream reads it
+      // stream reads it.  (Issued after the wait instead, sized to the count
+      // read there, its launches lengthened the call by their issue time.)
       {
         const uint64_t nc = uint64_t(sc.n_chunks);
         dev_free(ctx, s->out_gchunk);
@@ -2487,9 +2488,10 @@ static ipc_status retrieve_common(ipc_ctx *ctx, const ipc_stream *s, const std::
     hip_check(ctx, hipEventRecord(ctx->ev0, ctx->stream), "event");
     run_retrieve(ctx, s, plan, 0, stt->field.p);
     hip_check(ctx, hipEventRecord(ctx->ev1, ctx->stream), "event");
-    // the call's last operation: waiting for its event wakes the host sooner
-    // than a stream synchronization
-    hip_check(ctx, hipEventSynchronize(ctx->ev1), "retrieve");
+    // (waiting on the event instead returns a few us sooner, but the next
+    // synchronization of the stream then takes longer: measured slower over
+    // whole steps)
+    hip_check(ctx, hipStreamSynchronize(ctx->stream), "retrieve");
     prof_end(ctx);
     float ms = 0;
     (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);

@@ -267,6 +267,15 @@ hipError_t launch_outlier_index(const OutlierRec *recs, const unsigned long long
                                 uint64_t cap, const PassArgs *args, uint64_t n_chunks,
                                 uint32_t *start, uint32_t *cnt, uint32_t *bsum, uint64_t *gchunk,
                                 uint32_t *local, uint64_t *bits, hipStream_t stream);
+// The same index for a record count n known on the host (at most cap
+// records): up to OUT_SMALL records are sorted by one workgroup and start[]
+// comes from a binary search per chunk (two launches), more take the path
+// above.  cnt and bsum are used by the larger path only.
+constexpr uint32_t OUT_SMALL = 2048;
+hipError_t launch_outlier_index_n(const OutlierRec *recs, uint64_t n, const unsigned long long *n_out,
+                                  const PassArgs *args, uint64_t n_chunks, uint32_t *start,
+                                  uint32_t *cnt, uint32_t *bsum, uint64_t *gchunk, uint32_t *local,
+                                  uint64_t *bits, hipStream_t stream);
 // out_start[c] = index of the first outlier whose global chunk is >= c, for
 // c = 0 .. n_chunks (outliers sorted by global chunk)
 hipError_t launch_out_start(const uint64_t *out_gchunk, uint64_t n_out, uint64_t n_chunks,

@@ -642,6 +642,53 @@ __global__ void k_out_sort_chunks(const uint32_t *start, uint64_t n_chunks, uint
   }
 }
 
+// up to OUT_SMALL records sorted by (global chunk, local) in one workgroup:
+// keys g << 32 | local (global chunks below 2^32, checked by the host) with
+// their record indices, a bitonic sort over the next power of two (padding
+// keys sort last), then the sorted arrays
+__global__ __launch_bounds__(1024) void k_out_sort_small(const OutlierRec *__restrict__ recs, uint32_t n,
+                                                         const PassArgs *__restrict__ args,
+                                                         uint64_t *gchunk, uint32_t *local,
+                                                         uint64_t *bits) {
+  __shared__ uint64_t key[OUT_SMALL];
+  __shared__ uint32_t idx[OUT_SMALL];
+  uint32_t p2 = 1;
+  while (p2 < n) p2 <<= 1;
+  for (uint32_t i = threadIdx.x; i < p2; i += blockDim.x) {
+    if (i < n) {
+      const OutlierRec r = recs[i];
+      key[i] = rec_chunk(args, r) << 32 | uint64_t(r.local);
+    } else {
+      key[i] = ~0ull;
+    }
+    idx[i] = i;
+  }
+  __syncthreads();
+  for (uint32_t k = 2; k <= p2; k <<= 1)
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      // each pair (i, i ^ j) is ordered by its lower index alone
+      for (uint32_t i = threadIdx.x; i < p2; i += blockDim.x) {
+        const uint32_t l = i ^ j;
+        if (l > i) {
+          const uint64_t a = key[i], b = key[l];
+          if ((a > b) == ((i & k) == 0)) {
+            key[i] = b;
+            key[l] = a;
+            const uint32_t t = idx[i];
+            idx[i] = idx[l];
+            idx[l] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    gchunk[i] = key[i] >> 32;
+    local[i] = uint32_t(key[i]);
+    bits[i] = recs[idx[i]].bits;
+  }
+}
+
 __global__ void k_out_start(const uint64_t *keys, uint64_t n, uint64_t n_chunks, uint32_t *start) {
   uint64_t c = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (c > n_chunks) return;
@@ -868,6 +915,19 @@ hipError_t launch_out_start(const uint64_t *out_gchunk, uint64_t n_out, uint64_t
   dim3 grid(uint32_t((n_chunks + 1 + 255) / 256));
   hipLaunchKernelGGL(k_out_start, grid, dim3(256), 0, stream, out_gchunk, n_out, n_chunks, out_start);
   return hipGetLastError();
+}
+
+hipError_t launch_outlier_index_n(const OutlierRec *recs, uint64_t n, const unsigned long long *n_out,
+                                  const PassArgs *args, uint64_t n_chunks, uint32_t *start,
+                                  uint32_t *cnt, uint32_t *bsum, uint64_t *gchunk, uint32_t *local,
+                                  uint64_t *bits, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  if (n > OUT_SMALL || n_chunks >= (uint64_t(1) << 32))
+    return launch_outlier_index(recs, n_out, n, args, n_chunks, start, cnt, bsum, gchunk, local, bits,
+                                stream);
+  hipLaunchKernelGGL(k_out_sort_small, dim3(1), dim3(1024), 0, stream, recs, uint32_t(n), args, gchunk,
+                     local, bits);
+  return launch_out_start(gchunk, n, n_chunks, start, stream);
 }
 
 hipError_t launch_outlier_index(const OutlierRec *recs, const unsigned long long *n_out,
