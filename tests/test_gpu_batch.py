@@ -135,6 +135,31 @@ def test_batch_outlier_overflow_and_fallback(ctx):
         s.free()
 
 
+def test_batch_outlier_index_paths(ctx):
+    """Outlier indexes of a batch: a field with more than 2048 outliers (the
+    general sort), one with a few (one-workgroup sort), one with none; the
+    streams and retrievals through the indexes equal the oracle's."""
+    rng = np.random.default_rng(5)
+    a = fieldgen.random_field((40, 64, 128), seed=21, dtype=np.float32)
+    a.reshape(-1)[rng.choice(a.size, size=600, replace=False)] = np.nan
+    b = fieldgen.random_field((40, 64, 128), seed=22, dtype=np.float32)
+    b.reshape(-1)[rng.choice(b.size, size=97, replace=False)] = np.inf
+    c = np.zeros((40, 64, 128), dtype=np.float32)
+    xs = [a, b, c]
+    print("batch outlier index paths", flush=True)
+    batch = ctx.compress_batch([_dev(x) for x in xs], [1e-3] * 3)
+    counts = []
+    for x, s in zip(xs, batch):
+        ref = codec.compress(x, 1e-3)
+        assert s.to_bytes() == ref
+        counts.append(codec.open_stream(ref)[0].header.n_outliers)
+        st = s.retrieve(eb=1e-3)
+        assert _bytes(st.tensor()) == codec.retrieve(ref, "eb", 1e-3).field.tobytes()
+        st.free()
+        s.free()
+    assert counts[0] > 2048 and 0 < counts[1] <= 2048 and counts[2] == 0, counts
+
+
 def test_batch_argument_errors(ctx):
     x = _dev(np.zeros((4, 4, 4), dtype=np.float32))
     with pytest.raises(ValueError):
